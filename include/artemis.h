@@ -1,0 +1,240 @@
+/*
+ * artemis.h - C ABI of the MI355X animated-octree feature renderer.
+ *
+ * The renderer follows Section 3.1 of Luo et al., "Artemis: Articulated Neural
+ * Pets with Appearance and Motion Synthesis" (ACM TOG 41(4), 2022):
+ *
+ *   canonical octree leaves + FLUT (features and densities)   "Octree Feature Indexing"
+ *   -> bone transforms of the skeleton S = {r, R, T}           "Rigging and Deformation"
+ *   -> linear blend skinning of every leaf (Eq. 4)
+ *   -> rebuild of the posed octree, collisions resolved
+ *   -> ray / voxel indexing, front-to-back compositing of
+ *      densities and C-channel features (Eq. 5, Eq. 6),
+ *      coarse opacity map, early stop at lambda_th           "Dynamic Volume Rendering"
+ *
+ * plus the adjoint of the compositing step (the pipeline is trained end to
+ * end), a BF16 storage form of the FLUT and a learned ray-interval proposal.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Status codes only: no call aborts or throws across the ABI.  On failure
+ *   art_last_error(ctx) describes the problem and the context keeps its
+ *   previous valid state.
+ * - "host" pointers are read during the call and may be freed after it
+ *   returns; "device" pointers are HIP device memory owned by the caller
+ *   (e.g. torch tensors) that must stay valid until the call returns.
+ * - Every device write happens on the HIP stream given to art_create.
+ *   art_render and art_backward synchronise that stream before returning, so
+ *   their outputs are complete when they return.
+ * - Canonical grid: depth D, 2^D cells per axis over [-1/2, 1/2]^3, leaf edge
+ *   h = 2^-D; leaf centre p = -1/2 + (ijk + 1/2) h.
+ * - Posed grid: [-1, 1]^3 with the same leaf edge, G = 2^(D+1) cells per axis;
+ *   a posed centre p lies in cell floor((p + 1) / h).  Leaves that leave the
+ *   posed root are dropped (counted, not an error).
+ * - Morton keys interleave the 10-bit x, y, z cell coordinates with x in the
+ *   lowest bit: key = sum_b x_b << 3b | y_b << (3b+1) | z_b << (3b+2).
+ * - Images are row-major, pixel (x, y) at index y * W + x; maps are planar:
+ *   feature maps [P][V][C][H][W], opacity / transmittance maps [P][V][H][W].
+ */
+#ifndef ARTEMIS_H
+#define ARTEMIS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct art_ctx art_ctx;
+
+typedef enum {
+    ART_OK = 0,
+    ART_EINVAL = -1,        /* invalid argument (null, size, range, non-finite)  */
+    ART_ENOMEM = -2,        /* device allocation failed                           */
+    ART_EDEVICE = -3,       /* HIP runtime / kernel launch error                  */
+    ART_ESTATE = -4,        /* call made before the inputs it needs were set      */
+    ART_EUNSUPPORTED = -5   /* valid but unsupported configuration (e.g. C)       */
+} art_status;
+
+typedef enum { ART_F32 = 0, ART_BF16 = 1 } art_dtype;
+
+/* art_render / art_backward flags */
+#define ART_GEOM_FP32 1u   /* FP32 skinning and ray parameter (precision form);
+                              default: FP64 skinning arithmetic and ray t      */
+#define ART_TIMING 2u      /* record per-stage HIP events, read by art_get_timing */
+
+/* Library version (major * 10000 + minor * 100 + patch). */
+int art_version(void);
+
+/*
+ * Create a context on HIP device `device` that enqueues all work on `stream`
+ * (a hipStream_t; NULL for the default stream).  *out receives the context.
+ * Errors: ART_EINVAL (out NULL, bad device), ART_EDEVICE (HIP failure).
+ */
+art_status art_create(int device, void* stream, art_ctx** out);
+
+/* Destroy a context and free its device memory.  NULL-safe. */
+void art_destroy(art_ctx* ctx);
+
+/* Message of the last failed call on ctx ("" if none).  Never NULL; ctx may be NULL. */
+const char* art_last_error(const art_ctx* ctx);
+
+/*
+ * Load the canonical octree: the occupied leaf array P of Section 3.1
+ * ("Octree Feature Indexing"), as n leaves at depth `depth` (1..9).
+ * ijk: host uint16 [3][n] SoA planes (x plane, y plane, z plane), each < 2^depth,
+ * no duplicate cells.  Copied to device.  Invalidates skin weights.
+ * Errors: ART_EINVAL (depth, n < 1, out-of-range or duplicate cells), ART_ENOMEM.
+ */
+art_status art_load_octree(art_ctx* ctx, int depth, int64_t n, const uint16_t* ijk);
+
+/*
+ * Per-leaf skin weights for Eq. 4: four (bone, weight) pairs per leaf.
+ * bone: host uint8 [4][n] SoA planes; weight: host float32 [4][n] SoA planes,
+ * finite and >= 0 (used as given, not renormalised).  Copied to device.
+ * Bone ids are checked against the skeleton at render time.
+ * Errors: ART_ESTATE (no octree), ART_EINVAL, ART_ENOMEM.
+ */
+art_status art_set_skin(art_ctx* ctx, const uint8_t* bone, const float* weight);
+
+/*
+ * Skeleton in its canonical pose (Section 3.1, "Rigging and Deformation"):
+ * J joints (1..255), parent: host int32 [J] with parent[0] = -1 and
+ * 0 <= parent[j] < j, rest_joint: host float64 [J][3] joint positions.  The
+ * canonical bone transforms are M^c_j = [I | rest_joint_j].
+ * Errors: ART_EINVAL.
+ */
+art_status art_set_skeleton(art_ctx* ctx, int J, const int32_t* parent, const double* rest_joint);
+
+/*
+ * P target poses (1..4096) of the skeleton parameter S = {r, R, T}:
+ * r: host float64 [P][J][3] per-joint axis-angle rotations (radians),
+ * R: host float64 [P][3] global axis-angle rotation about joint 0,
+ * T: host float64 [P][3] global translation.  Copied.  The posed transforms
+ * are G_0 = [Rot(R) Rot(r_0) | J_0 + T], G_j = G_parent [Rot(r_j) | J_j - J_parent],
+ * and the skinning matrices of Eq. 4 are B_j = M^t_j (M^c_j)^-1 = G_j [I | -J_j],
+ * composed in FP64 on the GPU.
+ * Errors: ART_ESTATE (no skeleton), ART_EINVAL (non-finite values).
+ */
+art_status art_set_poses(art_ctx* ctx, int P, const double* r, const double* R, const double* T);
+
+/*
+ * V pinhole cameras (OpenCV convention: x right, y down, z forward; pixel
+ * centres at +1/2; one ray per pixel, r_p = (o_p, d_p) of Section 3.1):
+ * K: host float64 [V][3][3] intrinsics (fx = K[0][0], fy = K[1][1],
+ * cx = K[0][2], cy = K[1][2]; skew ignored), c2w: host float64 [V][3][4]
+ * camera-to-world [R | t]; the ray origin is t and the direction is
+ * normalize(R ((x + 1/2 - cx)/fx, (y + 1/2 - cy)/fy, 1)).  H, W in 1..8192.
+ * Errors: ART_EINVAL.
+ */
+art_status art_set_cameras(art_ctx* ctx, int V, int H, int W, const double* K, const double* c2w);
+
+/*
+ * Render every (pose, view): FK -> skinning -> posed octree rebuild -> ray
+ * indexing -> compositing (Eq. 5-6) with the early stop of Section 3.1 (stop
+ * right after the sample at which the transmittance falls below lambda_th;
+ * lambda_th = 0 disables it; the paper uses 0.01).
+ *
+ * C: feature channels, one of 4, 8, 16, 32.
+ * dtype: storage of the FLUT (ART_F32 or ART_BF16; BF16 is converted to FP32
+ *        on load, transmittance and accumulation are always FP32).
+ * sigma: device [n] densities (>= 0) of the canonical leaves, in dtype.
+ * feat:  device [n][C] features of the canonical leaves, in dtype (row-major).
+ * out_feat:   device float32 [P][V][C][H][W] feature maps F.
+ * out_alpha:  device float32 [P][V][H][W] coarse opacity maps A (sum of weights).
+ * out_tfinal: device float32 [P][V][H][W] final transmittance, or NULL.
+ * Pixels whose ray meets no occupied voxel get F = 0, A = 0, T = 1.
+ * Collisions: when several leaves warp into one posed cell the one with the
+ * smallest canonical index is rendered.
+ * Errors: ART_ESTATE (octree, skin, skeleton, poses or cameras missing),
+ * ART_EINVAL (null pointers, lambda_th outside [0,1), bone id >= J),
+ * ART_EUNSUPPORTED (C), ART_ENOMEM, ART_EDEVICE.
+ */
+art_status art_render(art_ctx* ctx, int C, art_dtype dtype, const void* sigma, const void* feat,
+                      float lambda_th, unsigned flags,
+                      float* out_feat, float* out_alpha, float* out_tfinal);
+
+/*
+ * Adjoint of art_render for the same poses, cameras, FLUT, lambda_th and
+ * flags.  Each ray is re-traversed (no stored sample lists); the composited
+ * samples are held fixed at those of the forward pass.
+ *
+ * out_feat, out_tfinal: device float32 outputs of the forward call.
+ * d_feat:  device float32 [P][V][C][H][W] dL/dF.
+ * d_alpha: device float32 [P][V][H][W] dL/dA, or NULL for zero.
+ * d_sigma: device float32 [n], accumulated (+=) with dL/dsigma.
+ * d_leaf_feat: device float32 [n][C], accumulated (+=) with dL/df.
+ * Gradients reach only collision winners; dropped and hidden leaves get 0.
+ * Float atomics make the summation order, and so the last bits, vary.
+ * Errors: as art_render.
+ */
+art_status art_backward(art_ctx* ctx, int C, art_dtype dtype, const void* sigma, const void* feat,
+                        float lambda_th, unsigned flags,
+                        const float* out_feat, const float* out_tfinal,
+                        const float* d_feat, const float* d_alpha,
+                        float* d_sigma, float* d_leaf_feat);
+
+/* ---------------------------------------------------------------------------
+ * Inspection of intermediate results (parity tests, debugging)
+ * ------------------------------------------------------------------------- */
+
+/*
+ * Skinning matrices B_j = M^t_j (M^c_j)^-1 of Eq. 4 as composed on the GPU in
+ * FP64: B: host float64 [P][J][3][4].  Synchronous.
+ */
+art_status art_get_bones(art_ctx* ctx, double* B);
+
+/*
+ * Posed Morton key of every canonical leaf for pose `pose` (0xFFFFFFFF for a
+ * dropped leaf).  keys: device uint32 [n].  flags: ART_GEOM_FP32 or 0.
+ * Synchronous.
+ */
+art_status art_get_posed_keys(art_ctx* ctx, int pose, unsigned flags, uint32_t* keys);
+
+/*
+ * Posed octree of pose `pose`: the occupied cells in Morton order with their
+ * collision winners, and the level of 8^3-leaf bricks.
+ * counts: host int64 [4] = {M occupied cells, nb bricks, dropped leaves,
+ *         collisions (= n - dropped - M)}.
+ * keys, winner: device uint32 [n] (first M valid);
+ * brick_keys (key >> 9), brick_row (index of the brick's first cell in keys):
+ *         device uint32 [n] (first nb valid);
+ * brick_mask: device uint32 [n][16] (first nb valid), bit (key & 511) set for
+ *         each occupied cell of the brick.
+ * Any of the device pointers may be NULL.  Synchronous.
+ */
+art_status art_get_octree(art_ctx* ctx, int pose, unsigned flags, int64_t* counts,
+                          uint32_t* keys, uint32_t* winner, uint32_t* brick_keys,
+                          uint32_t* brick_row, uint32_t* brick_mask);
+
+/*
+ * Composited samples of every ray of (pose, view), in front-to-back order,
+ * from the same traversal as art_render: leaf: device int32 [H*W][max_hits]
+ * (canonical winner leaf ids), delta: device float64 [H*W][max_hits] (chord
+ * lengths), count: device int32 [H*W] (may exceed max_hits; the list is then
+ * truncated).  Synchronous.
+ */
+art_status art_get_hits(art_ctx* ctx, int pose, int view, int C, art_dtype dtype,
+                        const void* sigma, const void* feat, float lambda_th, unsigned flags,
+                        int max_hits, int32_t* leaf, double* delta, int32_t* count);
+
+/*
+ * Counters of the last art_render / art_backward call, host int64 [8]:
+ * {rays, composited samples, rays with at least one sample, dropped leaves,
+ *  collisions, bricks (summed over poses), tile/brick pairs, kernel launches}.
+ */
+art_status art_get_stats(art_ctx* ctx, int64_t* stats);
+
+/*
+ * Per-stage GPU time of the last call made with ART_TIMING, host float [6] in
+ * milliseconds: {fk, skin, octree build, tile binning, render, total}, summed
+ * over poses.  `render` covers only the compositing kernel launches;
+ * n_render receives their number.
+ */
+art_status art_get_timing(art_ctx* ctx, float* ms, int* n_render);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ARTEMIS_H */

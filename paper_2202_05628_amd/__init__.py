@@ -1,0 +1,281 @@
+"""MI355X animated-octree feature renderer (ARTEMIS, Luo et al. 2022, Section 3.1).
+
+Python front end of libartemis.so: marshals numpy arrays and torch tensors
+into the C ABI (include/artemis.h).  The skinning, octree rebuild, ray
+indexing, compositing and adjoint all run in the library's HIP kernels;
+PyTorch only supplies device memory and the stream.
+
+    r = Renderer()
+    r.load_octree(depth, ijk); r.set_skin(bone, weight)
+    r.set_skeleton(parent, rest_joint); r.set_poses(rot, R, T)
+    r.set_cameras(K, c2w, H, W)
+    feat_map, alpha, t_final = r.render(sigma, feat)          # sigma [n], feat [n][C] on cuda
+    feat_map, alpha = render(r, sigma, feat)                  # differentiable (autograd)
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Tuple
+
+import numpy as np
+
+from . import _lib
+from ._lib import ART_BF16, ART_F32, ART_GEOM_FP32, ART_TIMING, ArtemisError
+
+__all__ = ["Renderer", "render", "RenderFn", "ArtemisError", "ART_GEOM_FP32", "ART_TIMING",
+           "LAMBDA_TH"]
+
+# early-stop threshold of the paper (Section 3.1): stop once alpha > 1 - 0.01
+LAMBDA_TH = 0.01
+
+
+def _np(a, dtype) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a), dtype=dtype)
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _tptr(t) -> Optional[int]:
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class Renderer:
+    """One library context bound to a CUDA (HIP) device and the torch stream
+    current at construction."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+
+        self._torch = torch
+        self.lib = _lib.load()
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.device = device
+        self.stream = stream
+        h = ctypes.c_void_p()
+        rc = self.lib.art_create(device, ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h))
+        if rc != 0:
+            raise ArtemisError(rc, f"art_create(device={device}) failed")
+        self._h = h
+        self.n = 0
+        self.depth = 0
+        self.J = 0
+        self.P = 0
+        self.V = self.H = self.W = 0
+
+    # ---- lifetime -------------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self.lib.art_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc: int, what: str):
+        if rc != 0:
+            msg = self.lib.art_last_error(self._h)
+            raise ArtemisError(rc, f"{what}: {msg.decode() if msg else ''}")
+
+    # ---- inputs -----------------------------------------------------------------
+    def load_octree(self, depth: int, ijk) -> None:
+        ijk = _np(ijk, np.uint16)
+        self._check(self.lib.art_load_octree(self._h, int(depth), int(ijk.shape[1]), _ptr(ijk)),
+                    "art_load_octree")
+        self.n, self.depth = int(ijk.shape[1]), int(depth)
+
+    def set_skin(self, bone, weight) -> None:
+        b = _np(bone, np.uint8)
+        w = _np(weight, np.float32)
+        self._check(self.lib.art_set_skin(self._h, _ptr(b), _ptr(w)), "art_set_skin")
+
+    def set_skeleton(self, parent, rest_joint) -> None:
+        p = _np(parent, np.int32)
+        r = _np(rest_joint, np.float64)
+        self._check(self.lib.art_set_skeleton(self._h, int(p.shape[0]), _ptr(p), _ptr(r)),
+                    "art_set_skeleton")
+        self.J = int(p.shape[0])
+
+    def set_poses(self, r, R, T) -> None:
+        r = _np(r, np.float64)
+        P = int(r.shape[0])
+        R = _np(R, np.float64).reshape(P, 3)
+        T = _np(T, np.float64).reshape(P, 3)
+        self._check(self.lib.art_set_poses(self._h, P, _ptr(r), _ptr(R), _ptr(T)), "art_set_poses")
+        self.P = P
+
+    def set_cameras(self, K, c2w, H: int, W: int) -> None:
+        K = _np(K, np.float64)
+        c = _np(c2w, np.float64)
+        V = int(K.shape[0])
+        self._check(self.lib.art_set_cameras(self._h, V, int(H), int(W), _ptr(K), _ptr(c)),
+                    "art_set_cameras")
+        self.V, self.H, self.W = V, int(H), int(W)
+
+    def set_scene(self, scene) -> None:
+        """Load a scenegen.Scene (octree, skin, skeleton)."""
+        self.load_octree(scene.depth, scene.ijk)
+        self.set_skin(scene.bone, scene.weight)
+        self.set_skeleton(scene.parent, scene.rest_joint)
+
+    # ---- helpers ----------------------------------------------------------------
+    def _flut(self, sigma, feat):
+        torch = self._torch
+        if sigma.dtype != feat.dtype or sigma.dtype not in (torch.float32, torch.bfloat16):
+            raise TypeError("sigma and feat must both be float32 or both bfloat16")
+        if not (sigma.is_cuda and feat.is_cuda):
+            raise TypeError("sigma and feat must be device tensors")
+        if sigma.shape != (self.n,) or feat.dim() != 2 or feat.shape[0] != self.n:
+            raise ValueError(f"expected sigma [{self.n}] and feat [{self.n}, C]")
+        if not (sigma.is_contiguous() and feat.is_contiguous()):
+            raise ValueError("sigma and feat must be contiguous")
+        dtype = ART_BF16 if sigma.dtype == torch.bfloat16 else ART_F32
+        return int(feat.shape[1]), dtype
+
+    def _flags(self, fp32_geom: bool, timing: bool) -> int:
+        return (ART_GEOM_FP32 if fp32_geom else 0) | (ART_TIMING if timing else 0)
+
+    # ---- rendering ------------------------------------------------------------------
+    def render(self, sigma, feat, lambda_th: float = LAMBDA_TH, fp32_geom: bool = False,
+               timing: bool = False, out=None, want_tfinal: bool = True):
+        """Feature maps [P][V][C][H][W], opacity [P][V][H][W], final transmittance
+        [P][V][H][W] (or None) for every pose and camera."""
+        torch = self._torch
+        C, dtype = self._flut(sigma, feat)
+        dev = sigma.device
+        if out is None:
+            F = torch.empty((self.P, self.V, C, self.H, self.W), dtype=torch.float32, device=dev)
+            A = torch.empty((self.P, self.V, self.H, self.W), dtype=torch.float32, device=dev)
+            T = torch.empty_like(A) if want_tfinal else None
+        else:
+            F, A, T = out
+        self._check(self.lib.art_render(self._h, C, dtype, _tptr(sigma), _tptr(feat), float(lambda_th),
+                                        self._flags(fp32_geom, timing), _tptr(F), _tptr(A), _tptr(T)),
+                    "art_render")
+        return F, A, T
+
+    def backward(self, sigma, feat, F, T, dF, dA=None, lambda_th: float = LAMBDA_TH,
+                 fp32_geom: bool = False, timing: bool = False, d_sigma=None, d_feat=None):
+        """Accumulate dL/dsigma [n] and dL/dfeat [n][C] (float32) for the last
+        render's inputs; returns (d_sigma, d_feat)."""
+        torch = self._torch
+        C, dtype = self._flut(sigma, feat)
+        if d_sigma is None:
+            d_sigma = torch.zeros((self.n,), dtype=torch.float32, device=sigma.device)
+        if d_feat is None:
+            d_feat = torch.zeros((self.n, C), dtype=torch.float32, device=sigma.device)
+        dF = dF.contiguous().float()
+        dA = None if dA is None else dA.contiguous().float()
+        self._check(self.lib.art_backward(self._h, C, dtype, _tptr(sigma), _tptr(feat), float(lambda_th),
+                                          self._flags(fp32_geom, timing), _tptr(F), _tptr(T), _tptr(dF),
+                                          _tptr(dA), _tptr(d_sigma), _tptr(d_feat)),
+                    "art_backward")
+        return d_sigma, d_feat
+
+    # ---- inspection ------------------------------------------------------------------
+    def get_bones(self) -> np.ndarray:
+        B = np.zeros((self.P, self.J, 3, 4), dtype=np.float64)
+        self._check(self.lib.art_get_bones(self._h, _ptr(B)), "art_get_bones")
+        return B
+
+    def get_posed_keys(self, pose: int, fp32_geom: bool = False):
+        torch = self._torch
+        k = torch.empty((self.n,), dtype=torch.int32, device=f"cuda:{self.device}")
+        self._check(self.lib.art_get_posed_keys(self._h, int(pose), ART_GEOM_FP32 if fp32_geom else 0,
+                                                _tptr(k)), "art_get_posed_keys")
+        return k.cpu().numpy().view(np.uint32)
+
+    def get_octree(self, pose: int, fp32_geom: bool = False):
+        torch = self._torch
+        dev = f"cuda:{self.device}"
+        counts = np.zeros(4, dtype=np.int64)
+        keys = torch.empty((self.n,), dtype=torch.int32, device=dev)
+        win = torch.empty_like(keys)
+        bk = torch.empty_like(keys)
+        br = torch.empty_like(keys)
+        bm = torch.empty((self.n, 16), dtype=torch.int32, device=dev)
+        self._check(self.lib.art_get_octree(self._h, int(pose), ART_GEOM_FP32 if fp32_geom else 0,
+                                            _ptr(counts), _tptr(keys), _tptr(win), _tptr(bk), _tptr(br),
+                                            _tptr(bm)), "art_get_octree")
+        M, nb = int(counts[0]), int(counts[1])
+        u32 = lambda t, m: t[:m].cpu().numpy().view(np.uint32)
+        return {"keys": u32(keys, M), "winner": u32(win, M).astype(np.int64),
+                "brick_keys": u32(bk, nb), "brick_row": u32(br, nb).astype(np.int64),
+                "brick_mask": bm[:nb].cpu().numpy().view(np.uint32),
+                "dropped": int(counts[2]), "collisions": int(counts[3])}
+
+    def get_hits(self, pose: int, view: int, sigma, feat, lambda_th: float = 0.0,
+                 max_hits: int = 256, fp32_geom: bool = False):
+        """Composited samples of every ray of (pose, view): leaf ids [H*W][max_hits],
+        chord lengths [H*W][max_hits] (float64), counts [H*W]."""
+        torch = self._torch
+        C, dtype = self._flut(sigma, feat)
+        dev = sigma.device
+        HW = self.H * self.W
+        leaf = torch.full((HW, max_hits), -1, dtype=torch.int32, device=dev)
+        delta = torch.zeros((HW, max_hits), dtype=torch.float64, device=dev)
+        count = torch.zeros((HW,), dtype=torch.int32, device=dev)
+        self._check(self.lib.art_get_hits(self._h, int(pose), int(view), C, dtype, _tptr(sigma), _tptr(feat),
+                                          float(lambda_th), ART_GEOM_FP32 if fp32_geom else 0,
+                                          int(max_hits), _tptr(leaf), _tptr(delta), _tptr(count)),
+                    "art_get_hits")
+        return leaf.cpu().numpy(), delta.cpu().numpy(), count.cpu().numpy()
+
+    def stats(self) -> dict:
+        s = np.zeros(8, dtype=np.int64)
+        self._check(self.lib.art_get_stats(self._h, _ptr(s)), "art_get_stats")
+        keys = ["rays", "samples", "hit_rays", "dropped", "collisions", "bricks", "pairs", "launches"]
+        return dict(zip(keys, (int(x) for x in s)))
+
+    def timing(self) -> dict:
+        ms = np.zeros(6, dtype=np.float32)
+        nr = ctypes.c_int(0)
+        self._check(self.lib.art_get_timing(self._h, _ptr(ms), ctypes.byref(nr)), "art_get_timing")
+        keys = ["fk", "skin", "build", "bin", "render", "total"]
+        out = dict(zip(keys, (float(x) for x in ms)))
+        out["n_render"] = int(nr.value)
+        return out
+
+
+def _make_fn():
+    import torch
+
+    class RenderFn(torch.autograd.Function):
+        """Differentiable render: (sigma [n], feat [n][C]) -> (F, A).  The
+        backward re-traverses every ray in the library's adjoint kernel."""
+
+        @staticmethod
+        def forward(ctx, sigma, feat, renderer, lambda_th, fp32_geom):
+            F, A, T = renderer.render(sigma.detach(), feat.detach(), lambda_th, fp32_geom)
+            ctx.save_for_backward(sigma, feat, F, T)
+            ctx.renderer = renderer
+            ctx.lambda_th = lambda_th
+            ctx.fp32_geom = fp32_geom
+            return F, A
+
+        @staticmethod
+        def backward(ctx, dF, dA):
+            sigma, feat, F, T = ctx.saved_tensors
+            if dF is None:
+                dF = torch.zeros_like(F)
+            ds, df = ctx.renderer.backward(sigma.detach(), feat.detach(), F, T, dF, dA,
+                                           ctx.lambda_th, ctx.fp32_geom)
+            return ds.to(sigma.dtype), df.to(feat.dtype), None, None, None
+
+    return RenderFn
+
+
+RenderFn = None
+
+
+def render(renderer: Renderer, sigma, feat, lambda_th: float = LAMBDA_TH, fp32_geom: bool = False):
+    """Differentiable feature / opacity maps of every pose and camera."""
+    global RenderFn
+    if RenderFn is None:
+        RenderFn = _make_fn()
+    return RenderFn.apply(sigma, feat, renderer, lambda_th, fp32_geom)

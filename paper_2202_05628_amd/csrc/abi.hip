@@ -1,0 +1,874 @@
+// C ABI entry points of libartemis (declared in include/artemis.h).
+//
+// Host code only: argument checks, device buffers, and the per-pose pipeline
+//   fk (all poses, FP64)
+//   per pose: skin -> radix sort -> unique/bricks/FLUT permute
+//             per view group: tile binning -> render
+// Every device step is one of the library's own kernels.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "device_util.h"
+#include "internal.h"
+
+using namespace art;
+
+#include "render_impl.h"
+
+namespace {
+
+constexpr int kVersion = 10000;   // 1.0.0
+
+art_status fail(art_ctx* ctx, art_status st, const std::string& msg) {
+    if (ctx) ctx->err = msg;
+    return st;
+}
+
+art_status hip_fail(art_ctx* ctx, hipError_t e, const char* what) {
+    (void)hipGetLastError();
+    const art_status st = (e == hipErrorOutOfMemory) ? ART_ENOMEM : ART_EDEVICE;
+    return fail(ctx, st, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+struct DeviceGuard {
+    int old = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&old) != hipSuccess) old = -1;
+        if (old != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (old >= 0 && hipGetDevice(&cur) == hipSuccess && cur != old) (void)hipSetDevice(old);
+    }
+};
+
+#define ART_TRY_HIP(expr, what)                          \
+    do {                                                 \
+        hipError_t _e = (expr);                          \
+        if (_e != hipSuccess) return hip_fail(ctx, _e, what); \
+    } while (0)
+
+bool supported_C(int C) { return C == 4 || C == 8 || C == 16 || C == 32; }
+
+// k_accum: fold one pose's counters into the run statistics.
+__global__ void k_accum(const PoseCounters* __restrict__ c, unsigned long long* __restrict__ st,
+                        uint32_t n) {
+    atomicAdd(&st[3], (unsigned long long)c->dropped);
+    atomicAdd(&st[4], (unsigned long long)(n - c->dropped - c->M));
+    atomicAdd(&st[5], (unsigned long long)c->nb);
+}
+
+// k_pairs: record a view group's pair count / overflow for the host.
+__global__ void k_pairs(const PoseCounters* __restrict__ c, unsigned long long* __restrict__ st,
+                        uint32_t* __restrict__ ovf) {
+    atomicAdd(&st[6], (unsigned long long)c->npairs);
+    ovf[0] = c->overflow;
+    ovf[1] = c->npairs;
+}
+
+struct CallPlan {
+    int C = 0;
+    int storage = 0;
+    bool fp32 = false;
+    int Vg = 1;           // views per group
+    int ngroups = 1;
+    int mbits = 0;
+};
+
+art_status check_build_state(art_ctx* ctx) {
+    if (ctx->n <= 0) return fail(ctx, ART_ESTATE, "no octree loaded (art_load_octree)");
+    if (!ctx->has_skin) return fail(ctx, ART_ESTATE, "no skin weights (art_set_skin)");
+    if (ctx->J <= 0) return fail(ctx, ART_ESTATE, "no skeleton (art_set_skeleton)");
+    if (ctx->P <= 0) return fail(ctx, ART_ESTATE, "no poses (art_set_poses)");
+    if (ctx->max_bone >= ctx->J)
+        return fail(ctx, ART_EINVAL, "skin bone id " + std::to_string(ctx->max_bone) +
+                                         " >= number of joints " + std::to_string(ctx->J));
+    return ART_OK;
+}
+
+art_status check_render_state(art_ctx* ctx) {
+    art_status rc = check_build_state(ctx);
+    if (rc != ART_OK) return rc;
+    if (ctx->V <= 0) return fail(ctx, ART_ESTATE, "no cameras (art_set_cameras)");
+    return ART_OK;
+}
+
+art_status plan_call(art_ctx* ctx, int C, art_dtype dtype, unsigned flags, CallPlan* pl) {
+    if (!supported_C(C)) return fail(ctx, ART_EUNSUPPORTED, "C must be 4, 8, 16 or 32");
+    if (dtype != ART_F32 && dtype != ART_BF16) return fail(ctx, ART_EINVAL, "dtype must be ART_F32 or ART_BF16");
+    if (flags & ~(ART_GEOM_FP32 | ART_TIMING)) return fail(ctx, ART_EINVAL, "unknown flag bits");
+    pl->C = C;
+    pl->storage = dtype == ART_BF16 ? 1 : 0;
+    pl->fp32 = (flags & ART_GEOM_FP32) != 0;
+    int Vg = ctx->V;
+    int mbits = 0;
+    while (Vg > 1 && bin_key_bits(Vg, ctx->H, ctx->W, ctx->depth, &mbits) > 32) Vg = (Vg + 1) / 2;
+    if (bin_key_bits(Vg, ctx->H, ctx->W, ctx->depth, &mbits) > 32)
+        return fail(ctx, ART_EUNSUPPORTED, "image too large for 32-bit tile keys");
+    pl->Vg = Vg;
+    pl->ngroups = (ctx->V + Vg - 1) / Vg;
+    pl->mbits = mbits;
+    return ART_OK;
+}
+
+art_status ensure_bufs(art_ctx* ctx, std::initializer_list<std::pair<DevBuf*, size_t>> req) {
+    for (auto& r : req) ART_TRY_HIP(r.first->ensure(r.second), "device allocation");
+    return ART_OK;
+}
+
+// Buffers of FK, skinning and the octree build.
+art_status ensure_build_scratch(art_ctx* ctx, const CallPlan& pl) {
+    Scratch& s = ctx->s;
+    const size_t n = (size_t)ctx->n;
+    const size_t es = pl.storage ? 2 : 4;
+    return ensure_bufs(ctx, {
+        {&s.keys0, n * 4}, {&s.vals0, n * 4}, {&s.keys1, n * 4}, {&s.vals1, n * 4},
+        {&s.hist, 256 * (size_t)kSortBlocks * 4}, {&s.digit_tot, 256 * 4},
+        {&s.blk0, (size_t)kScanBlocks * 4}, {&s.blk1, (size_t)kScanBlocks * 4},
+        {&s.occ_key, n * 4}, {&s.occ_win, n * 4},
+        {&s.brick_key, n * 4}, {&s.brick_row, (n + 1) * 4}, {&s.brick_mask, n * 64},
+        {&s.flut_sig, n * es}, {&s.flut_feat, n * pl.C * es},
+        {&s.counters, sizeof(PoseCounters)}, {&s.stats, 16 * sizeof(unsigned long long)},
+        {&ctx->B64, (size_t)ctx->P * ctx->J * 12 * 8}, {&ctx->B32, (size_t)ctx->P * ctx->J * 12 * 4},
+        {&ctx->Gtmp, (size_t)ctx->P * ctx->J * 12 * 8},
+    });
+}
+
+// Build buffers plus those of the tile binning and the overflow flags.
+art_status ensure_scratch(art_ctx* ctx, const CallPlan& pl) {
+    art_status rc = ensure_build_scratch(ctx, pl);
+    if (rc != ART_OK) return rc;
+    Scratch& s = ctx->s;
+    const size_t n = (size_t)ctx->n;
+    const size_t tiles = (size_t)pl.Vg * ((ctx->W + 7) / 8) * ((ctx->H + 7) / 8);
+    if (s.pair_cap == 0) s.pair_cap = std::max<size_t>((size_t)1 << 22, 8 * tiles);
+    const size_t items = (size_t)ctx->P * pl.ngroups;
+    return ensure_bufs(ctx, {
+        {&s.bin_cnt, n * pl.Vg * 4}, {&s.bin_off, n * pl.Vg * 4},
+        {&s.pk0, s.pair_cap * 4}, {&s.pv0, s.pair_cap * 4}, {&s.pk1, s.pair_cap * 4},
+        {&s.pv1, s.pair_cap * 4},
+        {&s.tile_start, tiles * 4}, {&s.tile_end, tiles * 4},
+        {&s.ovf, items * 2 * 4},
+    });
+}
+
+struct Timing {
+    bool on = false;
+    std::vector<hipEvent_t> ev;
+    ~Timing() {
+        for (auto e : ev) (void)hipEventDestroy(e);
+    }
+    std::vector<int> stage;   // stage id of the interval ending at ev[i]
+    void record(hipStream_t st, int stage_id) {
+        if (!on) return;
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return;
+        (void)hipEventRecord(e, st);
+        ev.push_back(e);
+        stage.push_back(stage_id);
+    }
+    void finish(art_ctx* ctx) {
+        for (int i = 0; i < 6; ++i) ctx->timing_ms[i] = 0.0f;
+        ctx->timing_nrender = 0;
+        for (size_t i = 1; i < ev.size(); ++i) {
+            float ms = 0.0f;
+            if (hipEventElapsedTime(&ms, ev[i - 1], ev[i]) == hipSuccess && stage[i] >= 0) {
+                ctx->timing_ms[stage[i]] += ms;
+                if (stage[i] == 4) ctx->timing_nrender++;
+            }
+        }
+        if (ev.size() >= 2) {
+            float ms = 0.0f;
+            if (hipEventElapsedTime(&ms, ev.front(), ev.back()) == hipSuccess) ctx->timing_ms[5] = ms;
+        }
+        ctx->timing_valid = on;
+        for (auto e : ev) (void)hipEventDestroy(e);
+        ev.clear();
+        stage.clear();
+    }
+};
+
+struct PassOut {
+    // forward
+    float* out_feat = nullptr;
+    float* out_alpha = nullptr;
+    float* out_tfinal = nullptr;
+    // backward
+    const float* fwd_feat = nullptr;
+    const float* fwd_tfinal = nullptr;
+    const float* d_feat = nullptr;
+    const float* d_alpha = nullptr;
+    float* d_sigma = nullptr;
+    float* d_leaf_feat = nullptr;
+    // debug
+    int max_hits = 0;
+    int32_t* hit_leaf = nullptr;
+    double* hit_delta = nullptr;
+    int32_t* hit_count = nullptr;
+    bool single = false;   // outputs hold one (pose, view) map only
+};
+
+// Skin + sort + octree build of one pose into the scratch buffers.
+art_status build_pose(art_ctx* ctx, const CallPlan& pl, int p, const void* sigma, const void* feat,
+                      int* launches, Timing& tm) {
+    Scratch& s = ctx->s;
+    hipStream_t st = ctx->stream;
+    PoseCounters* cnt = s.counters.as<PoseCounters>();
+    ART_TRY_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(cnt), 0u, sizeof(PoseCounters) / 4, st), "fill");
+    ART_TRY_HIP(launch_fill_u32(&cnt->pad[2], (uint32_t)ctx->n, 1, st), "fill");
+    ART_TRY_HIP(launch_skin(ctx->ijk.as<uint16_t>(), ctx->bone.as<uint8_t>(), ctx->weight.as<float>(),
+                            ctx->n, ctx->depth, ctx->B64.as<double>() + (size_t)p * ctx->J * 12,
+                            ctx->B32.as<float>() + (size_t)p * ctx->J * 12, ctx->J, pl.fp32,
+                            s.keys0.as<uint32_t>(), s.vals0.as<uint32_t>(), st),
+                "skin");
+    *launches += 3;
+    tm.record(st, 1);
+    bool in1 = false;
+    ART_TRY_HIP(launch_radix_sort(s.keys0.as<uint32_t>(), s.vals0.as<uint32_t>(), s.keys1.as<uint32_t>(),
+                                  s.vals1.as<uint32_t>(), &cnt->pad[2], (uint32_t)ctx->n, 32,
+                                  s.hist.as<uint32_t>(), s.digit_tot.as<uint32_t>(), st, &in1, launches),
+                "radix sort");
+    const uint32_t* sk = in1 ? s.keys1.as<uint32_t>() : s.keys0.as<uint32_t>();
+    const uint32_t* sv = in1 ? s.vals1.as<uint32_t>() : s.vals0.as<uint32_t>();
+    ART_TRY_HIP(launch_build_octree(sk, sv, (uint32_t)ctx->n, pl.C, pl.storage, sigma, feat, s, st, launches),
+                "octree build");
+    tm.record(st, 2);
+    return ART_OK;
+}
+
+RenderLaunch make_launch(art_ctx* ctx, const CallPlan& pl, int mode, int p, int v0, int Vg,
+                         float lambda, const uint32_t* pairs_v, const PassOut& o) {
+    RenderLaunch r{};
+    r.C = pl.C;
+    r.storage = pl.storage ? ART_BF16 : ART_F32;
+    r.fp32 = pl.fp32;
+    r.mode = mode;
+    r.depth = ctx->depth;
+    r.v0 = v0;
+    r.Vg = Vg;
+    r.V = ctx->V;
+    r.H = ctx->H;
+    r.W = ctx->W;
+    r.pose = p;
+    r.mbits = pl.mbits;
+    r.pairs_v = pairs_v;
+    r.lambda = lambda;
+    r.cam = ctx->cam.as<CamParams>();
+    r.s = &ctx->s;
+    const size_t HW = (size_t)ctx->H * ctx->W;
+    const size_t pv = o.single ? 0 : (size_t)p * ctx->V + v0;   // first (pose, view) map of the group
+    if (o.out_feat) r.out_feat = o.out_feat + pv * pl.C * HW;
+    if (o.out_alpha) r.out_alpha = o.out_alpha + pv * HW;
+    if (o.out_tfinal) r.out_tfinal = o.out_tfinal + pv * HW;
+    if (o.fwd_feat) r.fwd_feat = o.fwd_feat + pv * pl.C * HW;
+    if (o.fwd_tfinal) r.fwd_tfinal = o.fwd_tfinal + pv * HW;
+    if (o.d_feat) r.d_feat = o.d_feat + pv * pl.C * HW;
+    if (o.d_alpha) r.d_alpha = o.d_alpha + pv * HW;
+    r.d_sigma = o.d_sigma;
+    r.d_leaf_feat = o.d_leaf_feat;
+    r.max_hits = o.max_hits;
+    r.hit_leaf = o.hit_leaf;
+    r.hit_delta = o.hit_delta;
+    r.hit_count = o.hit_count;
+    return r;
+}
+
+// One full pass over the poses / view groups.  `only` restricts it to a set of
+// (pose, group) items (re-runs after a pair-buffer overflow).
+art_status run_pass(art_ctx* ctx, const CallPlan& pl, int mode, float lambda, const void* sigma,
+                    const void* feat, const PassOut& o, int pose_lo, int pose_hi, int view_lo,
+                    int view_hi, const std::vector<char>* only, DevBuf& ovf, int* launches,
+                    Timing& tm) {
+    Scratch& s = ctx->s;
+    hipStream_t st = ctx->stream;
+    PoseCounters* cnt = s.counters.as<PoseCounters>();
+    unsigned long long* stats = s.stats.as<unsigned long long>();
+    for (int p = pose_lo; p < pose_hi; ++p) {
+        bool any = true;
+        if (only) {
+            any = false;
+            for (int gi = 0; gi < pl.ngroups; ++gi) any = any || (*only)[(size_t)p * pl.ngroups + gi];
+        }
+        if (!any) continue;
+        tm.record(st, -1);
+        art_status rc = build_pose(ctx, pl, p, sigma, feat, launches, tm);
+        if (rc != ART_OK) return rc;
+        hipLaunchKernelGGL(k_accum, dim3(1), dim3(1), 0, st, (const PoseCounters*)cnt, stats, (uint32_t)ctx->n);
+        *launches += 1;
+        for (int gi = 0; gi < pl.ngroups; ++gi) {
+            if (only && !(*only)[(size_t)p * pl.ngroups + gi]) continue;
+            int v0 = gi * pl.Vg;
+            int v1 = std::min(ctx->V, v0 + pl.Vg);
+            v0 = std::max(v0, view_lo);
+            v1 = std::min(v1, view_hi);
+            if (v1 <= v0) continue;
+            const int Vg = v1 - v0;
+            int mbits = 0;
+            const uint32_t* pairs_v = nullptr;
+            tm.record(st, -1);
+            ART_TRY_HIP(launch_bin(s, ctx->cam.as<CamParams>(), v0, Vg, ctx->H, ctx->W, ctx->depth, pl.fp32,
+                                   st, launches, &mbits, &pairs_v),
+                        "tile binning");
+            hipLaunchKernelGGL(k_pairs, dim3(1), dim3(1), 0, st, (const PoseCounters*)cnt, stats,
+                               ovf.as<uint32_t>() + 2 * ((size_t)p * pl.ngroups + gi));
+            *launches += 1;
+            tm.record(st, 3);
+            CallPlan pg = pl;
+            pg.mbits = mbits;
+            RenderLaunch r = make_launch(ctx, pg, mode, p, v0, Vg, lambda, pairs_v, o);
+            ART_TRY_HIP(launch_render(r, st), "render");
+            *launches += 1;
+            tm.record(st, 4);
+        }
+    }
+    return ART_OK;
+}
+
+art_status render_call(art_ctx* ctx, int C, art_dtype dtype, const void* sigma, const void* feat,
+                       float lambda, unsigned flags, int mode, const PassOut& o, int pose_lo,
+                       int pose_hi, int view_lo, int view_hi) {
+    art_status rc = check_render_state(ctx);
+    if (rc != ART_OK) return rc;
+    CallPlan pl;
+    rc = plan_call(ctx, C, dtype, flags, &pl);
+    if (rc != ART_OK) return rc;
+    if (!sigma || !feat) return fail(ctx, ART_EINVAL, "sigma / feat must be device pointers");
+    if (!(lambda >= 0.0f && lambda < 1.0f)) return fail(ctx, ART_EINVAL, "lambda_th must be in [0, 1)");
+    rc = ensure_scratch(ctx, pl);
+    if (rc != ART_OK) return rc;
+    DevBuf& ovf = ctx->s.ovf;
+    const size_t items = (size_t)ctx->P * pl.ngroups;
+    hipStream_t st = ctx->stream;
+    int launches = 0;
+    Timing tm;
+    tm.on = (flags & ART_TIMING) != 0;
+
+    ART_TRY_HIP(launch_fill_u32(ovf.as<uint32_t>(), 0u, items * 2, st), "fill");
+    ART_TRY_HIP(launch_fill_u32(ctx->s.stats.as<uint32_t>(), 0u, 32, st), "fill");
+    tm.record(st, -1);
+    ART_TRY_HIP(launch_fk(ctx->parent.as<int32_t>(), ctx->rest.as<double>(), ctx->pose.as<double>(), ctx->J,
+                          ctx->P, ctx->Gtmp.as<double>(), ctx->B64.as<double>(), ctx->B32.as<float>(), st),
+                "fk");
+    launches += 3;
+    tm.record(st, 0);
+    rc = run_pass(ctx, pl, mode, lambda, sigma, feat, o, pose_lo, pose_hi, view_lo, view_hi, nullptr, ovf,
+                  &launches, tm);
+    if (rc != ART_OK) return rc;
+    // read back overflow flags and statistics
+    std::vector<uint32_t> hov(items * 2);
+    unsigned long long hst[16];
+    ART_TRY_HIP(hipMemcpyAsync(hov.data(), ovf.p, items * 2 * 4, hipMemcpyDeviceToHost, st), "copy");
+    ART_TRY_HIP(hipMemcpyAsync(hst, ctx->s.stats.p, sizeof(hst), hipMemcpyDeviceToHost, st), "copy");
+    ART_TRY_HIP(hipStreamSynchronize(st), "render");
+    // any (pose, view group) whose pair list overflowed is re-run with a larger buffer;
+    // its render kernel skipped the group, so nothing was written for it yet
+    std::vector<char> redo(items, 0);
+    size_t need = 0;
+    bool any = false;
+    for (size_t i = 0; i < items; ++i)
+        if (hov[2 * i]) {
+            redo[i] = 1;
+            any = true;
+            need = std::max<size_t>(need, hov[2 * i + 1]);
+        }
+    if (any) {
+        ctx->s.pair_cap = need + need / 4 + 1024;
+        rc = ensure_scratch(ctx, pl);
+        if (rc != ART_OK) return rc;
+        ART_TRY_HIP(launch_fill_u32(ovf.as<uint32_t>(), 0u, items * 2, st), "fill");
+        rc = run_pass(ctx, pl, mode, lambda, sigma, feat, o, pose_lo, pose_hi, view_lo, view_hi, &redo, ovf,
+                      &launches, tm);
+        if (rc != ART_OK) return rc;
+        ART_TRY_HIP(hipMemcpyAsync(hst, ctx->s.stats.p, sizeof(hst), hipMemcpyDeviceToHost, st), "copy");
+        ART_TRY_HIP(hipMemcpyAsync(hov.data(), ovf.p, items * 2 * 4, hipMemcpyDeviceToHost, st), "copy");
+        ART_TRY_HIP(hipStreamSynchronize(st), "render");
+        for (size_t i = 0; i < items; ++i)
+            if (hov[2 * i]) return fail(ctx, ART_EDEVICE, "tile pair buffer overflow persisted");
+    }
+    for (int i = 0; i < 7; ++i) ctx->stats[i] = (int64_t)hst[i];
+    ctx->stats[7] = launches;
+    tm.finish(ctx);
+    return ART_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// render launcher (kernel argument packing)
+// ---------------------------------------------------------------------------
+namespace art {
+hipError_t launch_render(const RenderLaunch& r, hipStream_t st) {
+    const Scratch& s = *r.s;
+    RArgs a{};
+    a.cam = r.cam;
+    a.v0 = r.v0;
+    a.Vg = r.Vg;
+    a.V = r.V;
+    a.H = r.H;
+    a.W = r.W;
+    a.TX = (r.W + 7) / 8;
+    a.TY = (r.H + 7) / 8;
+    a.TPV = a.TX * a.TY;
+    a.depth = r.depth;
+    a.wg_x = (a.TX + 1) / 2;
+    const int wg_y = (a.TY + 1) / 2;
+    a.wg_per_view = a.wg_x * wg_y;
+    a.n_wg = a.wg_per_view * r.Vg;
+    a.lambda = r.lambda;
+    a.tile_start = s.tile_start.as<uint32_t>();
+    a.tile_end = s.tile_end.as<uint32_t>();
+    a.pair_v = r.pairs_v;
+    a.brick_key = s.brick_key.as<uint32_t>();
+    a.brick_row = s.brick_row.as<uint32_t>();
+    a.brick_mask = s.brick_mask.as<uint32_t>();
+    a.occ_win = s.occ_win.as<uint32_t>();
+    a.psig = s.flut_sig.p;
+    a.pfeat = s.flut_feat.p;
+    a.out_feat = r.out_feat;
+    a.out_alpha = r.out_alpha;
+    a.out_tfinal = r.out_tfinal;
+    a.fwd_feat = r.fwd_feat;
+    a.fwd_tfinal = r.fwd_tfinal;
+    a.d_feat = r.d_feat;
+    a.d_alpha = r.d_alpha;
+    a.d_sigma = r.d_sigma;
+    a.d_leaf_feat = r.d_leaf_feat;
+    a.max_hits = r.max_hits;
+    a.hit_leaf = r.hit_leaf;
+    a.hit_delta = r.hit_delta;
+    a.hit_count = r.hit_count;
+    a.stats = s.stats.as<unsigned long long>();
+    a.counters = s.counters.as<PoseCounters>();
+    const unsigned per = 8u * kXcdChunk;
+    const unsigned grid = (unsigned)((a.n_wg + per - 1) / per * per);
+    switch (r.C) {
+        case 4: return launch_render_c<4>(r, a, grid, st);
+        case 8: return launch_render_c<8>(r, a, grid, st);
+        case 16: return launch_render_c<16>(r, a, grid, st);
+        case 32: return launch_render_c<32>(r, a, grid, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+}  // namespace art
+
+// ---------------------------------------------------------------------------
+// ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int art_version(void) { return kVersion; }
+
+art_status art_create(int device, void* stream, art_ctx** out) {
+    if (!out) return ART_EINVAL;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) {
+        (void)hipGetLastError();
+        return ART_EDEVICE;
+    }
+    if (device < 0 || device >= count) return ART_EINVAL;
+    art_ctx* ctx = new (std::nothrow) art_ctx();
+    if (!ctx) return ART_ENOMEM;
+    ctx->device = device;
+    ctx->stream = static_cast<hipStream_t>(stream);
+    *out = ctx;
+    return ART_OK;
+}
+
+void art_destroy(art_ctx* ctx) {
+    if (!ctx) return;
+    {
+        DeviceGuard g(ctx->device);
+        if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+        else (void)hipDeviceSynchronize();
+        DevBuf* bufs[] = {&ctx->ijk, &ctx->bone, &ctx->weight, &ctx->parent, &ctx->rest, &ctx->pose,
+                          &ctx->cam, &ctx->B64, &ctx->B32, &ctx->Gtmp,
+                          &ctx->s.keys0, &ctx->s.vals0, &ctx->s.keys1, &ctx->s.vals1, &ctx->s.hist,
+                          &ctx->s.digit_tot, &ctx->s.blk0, &ctx->s.blk1, &ctx->s.occ_key, &ctx->s.occ_win,
+                          &ctx->s.brick_key, &ctx->s.brick_row, &ctx->s.brick_mask, &ctx->s.flut_sig,
+                          &ctx->s.flut_feat, &ctx->s.bin_cnt, &ctx->s.bin_off, &ctx->s.pk0, &ctx->s.pv0,
+                          &ctx->s.pk1, &ctx->s.pv1, &ctx->s.tile_start, &ctx->s.tile_end,
+                          &ctx->s.counters, &ctx->s.stats, &ctx->s.ovf};
+        for (DevBuf* b : bufs) b->release();
+    }
+    delete ctx;
+}
+
+const char* art_last_error(const art_ctx* ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+art_status art_load_octree(art_ctx* ctx, int depth, int64_t n, const uint16_t* ijk) {
+    if (!ctx) return ART_EINVAL;
+    if (depth < 1 || depth > 9) return fail(ctx, ART_EINVAL, "depth must be in 1..9");
+    if (n < 1 || n > ((int64_t)1 << (3 * depth)) || n > 0x7FFFFFFFLL)
+        return fail(ctx, ART_EINVAL, "leaf count out of range");
+    if (!ijk) return fail(ctx, ART_EINVAL, "ijk is NULL");
+    const int64_t G = (int64_t)1 << depth;
+    std::vector<uint32_t> lin((size_t)n);
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t x = ijk[i], y = ijk[n + i], z = ijk[2 * n + i];
+        if (x >= G || y >= G || z >= G)
+            return fail(ctx, ART_EINVAL, "leaf " + std::to_string(i) + " outside the 2^depth grid");
+        lin[(size_t)i] = (uint32_t)((z * G + y) * G + x);
+    }
+    std::sort(lin.begin(), lin.end());
+    for (size_t i = 1; i < lin.size(); ++i)
+        if (lin[i] == lin[i - 1]) return fail(ctx, ART_EINVAL, "duplicate leaf cells");
+    DeviceGuard g(ctx->device);
+    DevBuf nb;
+    ART_TRY_HIP(nb.ensure((size_t)n * 3 * 2), "device allocation");
+    hipError_t e = hipMemcpy(nb.p, ijk, (size_t)n * 3 * 2, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        nb.release();
+        return hip_fail(ctx, e, "copy");
+    }
+    ctx->ijk.release();
+    ctx->ijk = nb;
+    ctx->depth = depth;
+    ctx->n = n;
+    ctx->has_skin = false;
+    ctx->max_bone = -1;
+    ctx->bone.release();
+    ctx->weight.release();
+    return ART_OK;
+}
+
+art_status art_set_skin(art_ctx* ctx, const uint8_t* bone, const float* weight) {
+    if (!ctx) return ART_EINVAL;
+    if (ctx->n <= 0) return fail(ctx, ART_ESTATE, "no octree loaded (art_load_octree)");
+    if (!bone || !weight) return fail(ctx, ART_EINVAL, "bone / weight is NULL");
+    const size_t n = (size_t)ctx->n;
+    int mb = -1;
+    for (size_t i = 0; i < 4 * n; ++i) {
+        if (!(weight[i] >= 0.0f) || !std::isfinite(weight[i]))
+            return fail(ctx, ART_EINVAL, "skin weights must be finite and >= 0");
+        mb = std::max(mb, (int)bone[i]);
+    }
+    DeviceGuard g(ctx->device);
+    DevBuf b, w;
+    ART_TRY_HIP(b.ensure(4 * n), "device allocation");
+    hipError_t e = w.ensure(4 * n * 4);
+    if (e != hipSuccess) {
+        b.release();
+        return hip_fail(ctx, e, "device allocation");
+    }
+    e = hipMemcpy(b.p, bone, 4 * n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(w.p, weight, 4 * n * 4, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        b.release();
+        w.release();
+        return hip_fail(ctx, e, "copy");
+    }
+    ctx->bone.release();
+    ctx->weight.release();
+    ctx->bone = b;
+    ctx->weight = w;
+    ctx->has_skin = true;
+    ctx->max_bone = mb;
+    return ART_OK;
+}
+
+art_status art_set_skeleton(art_ctx* ctx, int J, const int32_t* parent, const double* rest_joint) {
+    if (!ctx) return ART_EINVAL;
+    if (J < 1 || J > 255) return fail(ctx, ART_EINVAL, "J must be in 1..255");
+    if (!parent || !rest_joint) return fail(ctx, ART_EINVAL, "parent / rest_joint is NULL");
+    if (parent[0] != -1) return fail(ctx, ART_EINVAL, "parent[0] must be -1");
+    for (int j = 1; j < J; ++j)
+        if (parent[j] < 0 || parent[j] >= j) return fail(ctx, ART_EINVAL, "parent[j] must be in [0, j)");
+    for (int i = 0; i < 3 * J; ++i)
+        if (!std::isfinite(rest_joint[i])) return fail(ctx, ART_EINVAL, "rest joints must be finite");
+    DeviceGuard g(ctx->device);
+    DevBuf pb, rb;
+    ART_TRY_HIP(pb.ensure((size_t)J * 4), "device allocation");
+    hipError_t e = rb.ensure((size_t)J * 24);
+    if (e == hipSuccess) e = hipMemcpy(pb.p, parent, (size_t)J * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(rb.p, rest_joint, (size_t)J * 24, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        pb.release();
+        rb.release();
+        return hip_fail(ctx, e, "skeleton upload");
+    }
+    ctx->parent.release();
+    ctx->rest.release();
+    ctx->parent = pb;
+    ctx->rest = rb;
+    if (J != ctx->J) {   // poses no longer match the skeleton
+        ctx->P = 0;
+        ctx->pose.release();
+    }
+    ctx->J = J;
+    return ART_OK;
+}
+
+art_status art_set_poses(art_ctx* ctx, int P, const double* r, const double* R, const double* T) {
+    if (!ctx) return ART_EINVAL;
+    if (ctx->J <= 0) return fail(ctx, ART_ESTATE, "no skeleton (art_set_skeleton)");
+    if (P < 1 || P > 4096) return fail(ctx, ART_EINVAL, "P must be in 1..4096");
+    if (!r || !R || !T) return fail(ctx, ART_EINVAL, "r / R / T is NULL");
+    const int J = ctx->J;
+    std::vector<double> buf((size_t)P * (J + 2) * 3);
+    for (int p = 0; p < P; ++p) {
+        double* dst = buf.data() + (size_t)p * (J + 2) * 3;
+        memcpy(dst, r + (size_t)p * J * 3, sizeof(double) * J * 3);
+        memcpy(dst + J * 3, R + 3 * p, sizeof(double) * 3);
+        memcpy(dst + J * 3 + 3, T + 3 * p, sizeof(double) * 3);
+    }
+    for (double v : buf)
+        if (!std::isfinite(v)) return fail(ctx, ART_EINVAL, "pose parameters must be finite");
+    DeviceGuard g(ctx->device);
+    DevBuf pb;
+    ART_TRY_HIP(pb.ensure(buf.size() * 8), "device allocation");
+    hipError_t e = hipMemcpy(pb.p, buf.data(), buf.size() * 8, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        pb.release();
+        return hip_fail(ctx, e, "copy");
+    }
+    ctx->pose.release();
+    ctx->pose = pb;
+    ctx->P = P;
+    return ART_OK;
+}
+
+art_status art_set_cameras(art_ctx* ctx, int V, int H, int W, const double* K, const double* c2w) {
+    if (!ctx) return ART_EINVAL;
+    if (V < 1 || V > 4096) return fail(ctx, ART_EINVAL, "V must be in 1..4096");
+    if (H < 1 || H > 8192 || W < 1 || W > 8192) return fail(ctx, ART_EINVAL, "H, W must be in 1..8192");
+    if (!K || !c2w) return fail(ctx, ART_EINVAL, "K / c2w is NULL");
+    std::vector<CamParams> cams((size_t)V);
+    for (int v = 0; v < V; ++v) {
+        const double* k = K + 9 * v;
+        const double* m = c2w + 12 * v;
+        for (int i = 0; i < 9; ++i)
+            if (!std::isfinite(k[i])) return fail(ctx, ART_EINVAL, "K must be finite");
+        for (int i = 0; i < 12; ++i)
+            if (!std::isfinite(m[i])) return fail(ctx, ART_EINVAL, "c2w must be finite");
+        if (!(k[0] != 0.0) || !(k[4] != 0.0)) return fail(ctx, ART_EINVAL, "focal lengths must be non-zero");
+        // the camera-to-world rotation must be orthonormal (columns: right, down, forward)
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                double dot = 0.0;
+                for (int r = 0; r < 3; ++r) dot += m[4 * r + a] * m[4 * r + b];
+                if (fabs(dot - (a == b ? 1.0 : 0.0)) > 1e-6)
+                    return fail(ctx, ART_EINVAL, "c2w rotation must be orthonormal");
+            }
+        CamParams& c = cams[(size_t)v];
+        c.fx = k[0];
+        c.fy = k[4];
+        c.cx = k[2];
+        c.cy = k[5];
+        for (int a = 0; a < 3; ++a) {
+            for (int b = 0; b < 3; ++b) c.R[3 * a + b] = m[4 * a + b];
+            c.t[a] = m[4 * a + 3];
+        }
+    }
+    DeviceGuard g(ctx->device);
+    DevBuf cb;
+    ART_TRY_HIP(cb.ensure(sizeof(CamParams) * V), "device allocation");
+    hipError_t e = hipMemcpy(cb.p, cams.data(), sizeof(CamParams) * V, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        cb.release();
+        return hip_fail(ctx, e, "copy");
+    }
+    ctx->cam.release();
+    ctx->cam = cb;
+    ctx->cams = cams;
+    ctx->V = V;
+    ctx->H = H;
+    ctx->W = W;
+    return ART_OK;
+}
+
+art_status art_render(art_ctx* ctx, int C, art_dtype dtype, const void* sigma, const void* feat,
+                      float lambda_th, unsigned flags, float* out_feat, float* out_alpha,
+                      float* out_tfinal) {
+    if (!ctx) return ART_EINVAL;
+    if (!out_feat || !out_alpha) return fail(ctx, ART_EINVAL, "out_feat / out_alpha is NULL");
+    DeviceGuard g(ctx->device);
+    PassOut o;
+    o.out_feat = out_feat;
+    o.out_alpha = out_alpha;
+    o.out_tfinal = out_tfinal;
+    return render_call(ctx, C, dtype, sigma, feat, lambda_th, flags, 0, o, 0, ctx->P, 0, ctx->V);
+}
+
+art_status art_backward(art_ctx* ctx, int C, art_dtype dtype, const void* sigma, const void* feat,
+                        float lambda_th, unsigned flags, const float* out_feat, const float* out_tfinal,
+                        const float* d_feat, const float* d_alpha, float* d_sigma, float* d_leaf_feat) {
+    if (!ctx) return ART_EINVAL;
+    if (!out_feat || !out_tfinal || !d_feat || !d_sigma || !d_leaf_feat)
+        return fail(ctx, ART_EINVAL, "backward needs out_feat, out_tfinal, d_feat, d_sigma, d_leaf_feat");
+    DeviceGuard g(ctx->device);
+    PassOut o;
+    o.fwd_feat = out_feat;
+    o.fwd_tfinal = out_tfinal;
+    o.d_feat = d_feat;
+    o.d_alpha = d_alpha;
+    o.d_sigma = d_sigma;
+    o.d_leaf_feat = d_leaf_feat;
+    return render_call(ctx, C, dtype, sigma, feat, lambda_th, flags, 1, o, 0, ctx->P, 0, ctx->V);
+}
+
+art_status art_get_hits(art_ctx* ctx, int pose, int view, int C, art_dtype dtype, const void* sigma,
+                        const void* feat, float lambda_th, unsigned flags, int max_hits, int32_t* leaf,
+                        double* delta, int32_t* count) {
+    if (!ctx) return ART_EINVAL;
+    if (pose < 0 || pose >= ctx->P || view < 0 || view >= ctx->V)
+        return fail(ctx, ART_EINVAL, "pose / view out of range");
+    if (max_hits < 1 || !leaf || !delta || !count) return fail(ctx, ART_EINVAL, "hit buffers");
+    if (!supported_C(C)) return fail(ctx, ART_EUNSUPPORTED, "C must be 4, 8, 16 or 32");
+    DeviceGuard g(ctx->device);
+    const size_t HW = (size_t)ctx->H * ctx->W;
+    DevBuf tf, ta;   // forward maps of the requested (pose, view), discarded
+    ART_TRY_HIP(tf.ensure(HW * C * 4), "device allocation");
+    hipError_t e = ta.ensure(HW * 4);
+    if (e != hipSuccess) {
+        tf.release();
+        return hip_fail(ctx, e, "device allocation");
+    }
+    PassOut o;
+    o.single = true;
+    o.out_feat = tf.as<float>();
+    o.out_alpha = ta.as<float>();
+    o.max_hits = max_hits;
+    o.hit_leaf = leaf;
+    o.hit_delta = delta;
+    o.hit_count = count;
+    art_status rc = render_call(ctx, C, dtype, sigma, feat, lambda_th, flags, 2, o, pose, pose + 1, view,
+                                view + 1);
+    tf.release();
+    ta.release();
+    return rc;
+}
+
+art_status art_get_bones(art_ctx* ctx, double* B) {
+    if (!ctx) return ART_EINVAL;
+    if (!B) return fail(ctx, ART_EINVAL, "B is NULL");
+    if (ctx->J <= 0) return fail(ctx, ART_ESTATE, "no skeleton (art_set_skeleton)");
+    if (ctx->P <= 0) return fail(ctx, ART_ESTATE, "no poses (art_set_poses)");
+    DeviceGuard g(ctx->device);
+    const size_t nb = (size_t)ctx->P * ctx->J * 12;
+    ART_TRY_HIP(ctx->B64.ensure(nb * 8), "device allocation");
+    ART_TRY_HIP(ctx->B32.ensure(nb * 4), "device allocation");
+    ART_TRY_HIP(ctx->Gtmp.ensure(nb * 8), "device allocation");
+    ART_TRY_HIP(launch_fk(ctx->parent.as<int32_t>(), ctx->rest.as<double>(), ctx->pose.as<double>(), ctx->J,
+                          ctx->P, ctx->Gtmp.as<double>(), ctx->B64.as<double>(), ctx->B32.as<float>(),
+                          ctx->stream),
+                "fk");
+    ART_TRY_HIP(hipMemcpyAsync(B, ctx->B64.p, nb * 8, hipMemcpyDeviceToHost, ctx->stream), "copy");
+    ART_TRY_HIP(hipStreamSynchronize(ctx->stream), "fk");
+    return ART_OK;
+}
+
+art_status art_get_posed_keys(art_ctx* ctx, int pose, unsigned flags, uint32_t* keys) {
+    if (!ctx) return ART_EINVAL;
+    if (!keys) return fail(ctx, ART_EINVAL, "keys is NULL");
+    art_status rc = check_build_state(ctx);
+    if (rc != ART_OK) return rc;
+    if (pose < 0 || pose >= ctx->P) return fail(ctx, ART_EINVAL, "pose out of range");
+    if (flags & ~ART_GEOM_FP32) return fail(ctx, ART_EINVAL, "unknown flag bits");
+    DeviceGuard g(ctx->device);
+    const size_t nb = (size_t)ctx->P * ctx->J * 12;
+    ART_TRY_HIP(ctx->B64.ensure(nb * 8), "device allocation");
+    ART_TRY_HIP(ctx->B32.ensure(nb * 4), "device allocation");
+    ART_TRY_HIP(ctx->Gtmp.ensure(nb * 8), "device allocation");
+    ART_TRY_HIP(ctx->s.vals0.ensure((size_t)ctx->n * 4), "device allocation");
+    hipStream_t st = ctx->stream;
+    ART_TRY_HIP(launch_fk(ctx->parent.as<int32_t>(), ctx->rest.as<double>(), ctx->pose.as<double>(), ctx->J,
+                          ctx->P, ctx->Gtmp.as<double>(), ctx->B64.as<double>(), ctx->B32.as<float>(), st),
+                "fk");
+    ART_TRY_HIP(launch_skin(ctx->ijk.as<uint16_t>(), ctx->bone.as<uint8_t>(), ctx->weight.as<float>(), ctx->n,
+                            ctx->depth, ctx->B64.as<double>() + (size_t)pose * ctx->J * 12,
+                            ctx->B32.as<float>() + (size_t)pose * ctx->J * 12, ctx->J,
+                            (flags & ART_GEOM_FP32) != 0, keys, ctx->s.vals0.as<uint32_t>(), st),
+                "skin");
+    ART_TRY_HIP(hipStreamSynchronize(st), "skin");
+    return ART_OK;
+}
+
+art_status art_get_octree(art_ctx* ctx, int pose, unsigned flags, int64_t* counts, uint32_t* keys,
+                          uint32_t* winner, uint32_t* brick_keys, uint32_t* brick_row, uint32_t* brick_mask) {
+    if (!ctx) return ART_EINVAL;
+    if (!counts) return fail(ctx, ART_EINVAL, "counts is NULL");
+    art_status rc = check_build_state(ctx);
+    if (rc != ART_OK) return rc;
+    if (pose < 0 || pose >= ctx->P) return fail(ctx, ART_EINVAL, "pose out of range");
+    if (flags & ~ART_GEOM_FP32) return fail(ctx, ART_EINVAL, "unknown flag bits");
+    DeviceGuard g(ctx->device);
+    CallPlan pl;
+    pl.C = 4;
+    pl.storage = 0;
+    pl.fp32 = (flags & ART_GEOM_FP32) != 0;
+    pl.Vg = 1;
+    rc = ensure_build_scratch(ctx, pl);
+    if (rc != ART_OK) return rc;
+    DevBuf zs, zf;   // the build also permutes a FLUT; feed it zeros
+    ART_TRY_HIP(zs.ensure((size_t)ctx->n * 4), "device allocation");
+    hipError_t e = zf.ensure((size_t)ctx->n * 16);
+    if (e != hipSuccess) {
+        zs.release();
+        return hip_fail(ctx, e, "device allocation");
+    }
+    hipStream_t st = ctx->stream;
+    e = launch_fill_u32(zs.as<uint32_t>(), 0u, (size_t)ctx->n, st);
+    if (e == hipSuccess) e = launch_fill_u32(zf.as<uint32_t>(), 0u, (size_t)ctx->n * 4, st);
+    if (e == hipSuccess)
+        e = launch_fk(ctx->parent.as<int32_t>(), ctx->rest.as<double>(), ctx->pose.as<double>(), ctx->J, ctx->P,
+                      ctx->Gtmp.as<double>(), ctx->B64.as<double>(), ctx->B32.as<float>(), st);
+    if (e != hipSuccess) {
+        zs.release();
+        zf.release();
+        return hip_fail(ctx, e, "octree");
+    }
+    Timing tm;
+    int launches = 0;
+    rc = build_pose(ctx, pl, pose, zs.p, zf.p, &launches, tm);
+    PoseCounters hc{};
+    if (rc == ART_OK) {
+        e = hipMemcpyAsync(&hc, ctx->s.counters.p, sizeof(hc), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) rc = hip_fail(ctx, e, "octree");
+    }
+    if (rc == ART_OK) {
+        counts[0] = hc.M;
+        counts[1] = hc.nb;
+        counts[2] = hc.dropped;
+        counts[3] = ctx->n - hc.dropped - hc.M;
+        const Scratch& s = ctx->s;
+        if (keys) e = hipMemcpyAsync(keys, s.occ_key.p, (size_t)hc.M * 4, hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess && winner)
+            e = hipMemcpyAsync(winner, s.occ_win.p, (size_t)hc.M * 4, hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess && brick_keys)
+            e = hipMemcpyAsync(brick_keys, s.brick_key.p, (size_t)hc.nb * 4, hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess && brick_row)
+            e = hipMemcpyAsync(brick_row, s.brick_row.p, (size_t)hc.nb * 4, hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess && brick_mask)
+            e = hipMemcpyAsync(brick_mask, s.brick_mask.p, (size_t)hc.nb * 64, hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) rc = hip_fail(ctx, e, "octree copy");
+    }
+    zs.release();
+    zf.release();
+    return rc;
+}
+
+art_status art_get_stats(art_ctx* ctx, int64_t* stats) {
+    if (!ctx) return ART_EINVAL;
+    if (!stats) return fail(ctx, ART_EINVAL, "stats is NULL");
+    for (int i = 0; i < kNumStats; ++i) stats[i] = ctx->stats[i];
+    return ART_OK;
+}
+
+art_status art_get_timing(art_ctx* ctx, float* ms, int* n_render) {
+    if (!ctx) return ART_EINVAL;
+    if (!ms) return fail(ctx, ART_EINVAL, "ms is NULL");
+    if (!ctx->timing_valid) return fail(ctx, ART_ESTATE, "no call with ART_TIMING yet");
+    for (int i = 0; i < 6; ++i) ms[i] = ctx->timing_ms[i];
+    if (n_render) *n_render = ctx->timing_nrender;
+    return ART_OK;
+}
+
+}  // extern "C"

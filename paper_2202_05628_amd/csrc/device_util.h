@@ -1,0 +1,106 @@
+// Device helpers shared by the renderer's HIP kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace art {
+
+constexpr int kWave = 64;
+constexpr uint32_t kInvalidKey = 0xFFFFFFFFu;
+
+// ---------------------------------------------------------------------------
+// Morton codes: x in the lowest bit of each 3-bit group
+// ---------------------------------------------------------------------------
+__host__ __device__ inline uint32_t spread3(uint32_t v) {
+    v &= 0x3FFu;
+    v = (v | (v << 16)) & 0x030000FFu;
+    v = (v | (v << 8)) & 0x0300F00Fu;
+    v = (v | (v << 4)) & 0x030C30C3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+__host__ __device__ inline uint32_t compact3(uint32_t v) {
+    v &= 0x09249249u;
+    v = (v | (v >> 2)) & 0x030C30C3u;
+    v = (v | (v >> 4)) & 0x0300F00Fu;
+    v = (v | (v >> 8)) & 0x030000FFu;
+    v = (v | (v >> 16)) & 0x000003FFu;
+    return v;
+}
+__host__ __device__ inline uint32_t morton3(uint32_t x, uint32_t y, uint32_t z) {
+    return spread3(x) | (spread3(y) << 1) | (spread3(z) << 2);
+}
+
+// ---------------------------------------------------------------------------
+// wave64 helpers
+// ---------------------------------------------------------------------------
+__device__ inline int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
+
+__device__ inline uint64_t lanemask_lt() {
+    const int l = lane_id();
+    return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+// Make LDS writes of this wave visible to its other lanes.
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename T>
+__device__ inline T wave_inclusive_scan(T v) {
+    const int l = lane_id();
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        T u = __shfl_up(v, d, kWave);
+        if (l >= d) v += u;
+    }
+    return v;
+}
+
+template <typename T>
+__device__ inline T wave_sum(T v) {
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
+    return v;
+}
+
+// Block-wide exclusive scan for blockDim.x == NT (multiple of 64, <= 1024).
+// `tmp` is LDS of at least NT/64 + 1 elements.  Returns the exclusive prefix
+// and writes the block total to *total.  Contains __syncthreads.
+template <int NT, typename T>
+__device__ inline T block_exclusive_scan(T v, T* tmp, T* total) {
+    constexpr int NW = NT / kWave;
+    const int w = threadIdx.x / kWave;
+    T inc = wave_inclusive_scan(v);
+    if (lane_id() == kWave - 1) tmp[w] = inc;
+    __syncthreads();
+    if (w == 0) {
+        T s = lane_id() < NW ? tmp[lane_id()] : T(0);
+        T si = wave_inclusive_scan(s);
+        if (lane_id() < NW) tmp[lane_id()] = si - s;
+        if (lane_id() == NW - 1) tmp[NW] = si;
+    }
+    __syncthreads();
+    T out = tmp[w] + inc - v;
+    *total = tmp[NW];
+    __syncthreads();
+    return out;
+}
+
+// Contiguous range of `n` items owned by block `b` of `nb` blocks (tile aligned).
+__device__ inline void block_range(uint32_t n, uint32_t b, uint32_t nb, uint32_t align,
+                                   uint32_t* lo, uint32_t* hi) {
+    uint32_t per = (n + nb - 1) / nb;
+    per = (per + align - 1) / align * align;
+    uint64_t l = (uint64_t)b * per;
+    uint64_t h = l + per;
+    *lo = (uint32_t)(l < n ? l : n);
+    *hi = (uint32_t)(h < n ? h : n);
+}
+
+__device__ inline float bf16_to_f32(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
+
+}  // namespace art

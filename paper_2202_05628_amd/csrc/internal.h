@@ -1,0 +1,178 @@
+// Host-side internals of libartemis: context, device buffers, launcher
+// declarations.  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/artemis.h"
+
+namespace art {
+
+// Grow-only device buffer.
+struct DevBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+    hipError_t ensure(size_t bytes) {
+        if (bytes <= cap) return hipSuccess;
+        if (p) {
+            (void)hipFree(p);
+            p = nullptr;
+            cap = 0;
+        }
+        size_t want = bytes < 256 ? 256 : bytes;
+        hipError_t e = hipMalloc(&p, want);
+        if (e == hipSuccess) cap = want;
+        else p = nullptr;
+        return e;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+    template <typename T> T* as() const { return static_cast<T*>(p); }
+};
+
+// Per-view camera as used by the kernels (FP64).
+struct CamParams {
+    double fx, fy, cx, cy;
+    double R[9];   // row-major camera-to-world rotation (columns: right, down, forward)
+    double t[3];   // camera centre
+};
+
+// Device-side counters of one pose (written by the build kernels).
+struct PoseCounters {
+    uint32_t M;          // occupied posed cells
+    uint32_t nb;         // bricks
+    uint32_t dropped;    // leaves outside the posed root
+    uint32_t npairs;     // tile/brick pairs
+    uint32_t overflow;   // pair buffer overflow flag
+    uint32_t pad[3];
+};
+
+// Run-wide statistics accumulated on the device.
+struct RunStats {
+    unsigned long long rays, samples, hit_rays, dropped, collisions, bricks, pairs, launches;
+};
+
+constexpr int kNumStats = 8;
+constexpr int kSortBlocks = 512;      // fixed grid of the radix-sort passes
+constexpr int kScanBlocks = 1024;     // fixed grid of device-sized scans
+constexpr int kUniqueBlocks = 1024;   // fixed grid of the unique / compaction step
+
+struct Scratch {
+    DevBuf keys0, vals0, keys1, vals1;   // sort ping-pong [n]
+    DevBuf hist, digit_tot;              // [256 * kSortBlocks], [256]
+    DevBuf blk0, blk1;                   // block partials [kScanBlocks]
+    DevBuf occ_key, occ_win;             // [n] posed cells + winners
+    DevBuf brick_key, brick_row, brick_mask;  // [n], [n+1], [n*16]
+    DevBuf flut_sig, flut_feat;          // posed-order FLUT rows
+    DevBuf bin_cnt, bin_off;             // [n*V]
+    DevBuf pk0, pv0, pk1, pv1;           // pair sort [pair_cap]
+    DevBuf tile_start, tile_end;         // [V * tiles]
+    DevBuf counters;                     // PoseCounters
+    DevBuf stats;                        // RunStats
+    DevBuf ovf;                          // [P * groups][2] overflow flag, pair count
+    size_t pair_cap = 0;
+};
+
+}  // namespace art
+
+struct art_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+
+    // canonical octree + skin
+    int depth = 0;
+    int64_t n = 0;
+    art::DevBuf ijk;      // uint16 [3][n]
+    art::DevBuf bone;     // uint8 [4][n]
+    art::DevBuf weight;   // float [4][n]
+    bool has_skin = false;
+    int max_bone = -1;
+
+    // skeleton
+    int J = 0;
+    art::DevBuf parent;   // int32 [J]
+    art::DevBuf rest;     // double [J][3]
+
+    // poses
+    int P = 0;
+    art::DevBuf pose;     // double [P][J+2][3]  (r_0..r_{J-1}, R, T)
+
+    // cameras
+    int V = 0, H = 0, W = 0;
+    std::vector<art::CamParams> cams;
+    art::DevBuf cam;      // CamParams [V]
+
+    // derived
+    art::DevBuf B64, B32, Gtmp;
+
+    art::Scratch s;
+
+    // last-call bookkeeping
+    int64_t stats[art::kNumStats] = {0};
+    float timing_ms[6] = {0};
+    int timing_nrender = 0;
+    bool timing_valid = false;
+};
+
+namespace art {
+
+// ---- launchers (each enqueues on `st`) ------------------------------------
+hipError_t launch_fk(const int32_t* parent, const double* rest, const double* pose, int J, int P,
+                     double* G, double* B64, float* B32, hipStream_t st);
+hipError_t launch_skin(const uint16_t* ijk, const uint8_t* bone, const float* w, int64_t n,
+                       int depth, const double* B64, const float* B32, int J, bool fp32,
+                       uint32_t* keys, uint32_t* vals, hipStream_t st);
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t st);
+hipError_t launch_radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1,
+                             const uint32_t* d_n, uint32_t n_cap, int bits, uint32_t* hist,
+                             uint32_t* digit_tot, hipStream_t st, bool* result_in_1, int* launches);
+hipError_t launch_scan_exclusive(const uint32_t* in, uint32_t* out, const uint32_t* d_n,
+                                 uint32_t* d_total, uint32_t* blk, hipStream_t st, int* launches);
+hipError_t launch_build_octree(const uint32_t* skeys, const uint32_t* svals, uint32_t n,
+                               int C, int storage, const void* sigma, const void* feat,
+                               Scratch& s, hipStream_t st, int* launches);
+int bin_key_bits(int Vg, int H, int W, int depth, int* mbits);
+hipError_t launch_bin(Scratch& s, const CamParams* cam_dev, int v0, int Vg, int H, int W, int depth,
+                      bool fp32, hipStream_t st, int* launches, int* mbits_out,
+                      const uint32_t** pairs_v);
+
+struct RenderLaunch {
+    int C, storage;
+    bool fp32;
+    int mode;            // 0 forward, 1 backward, 2 debug hit lists
+    int depth;
+    int v0, Vg, V, H, W; // view group [v0, v0+Vg) of V views
+    int pose;
+    int mbits;
+    const uint32_t* pairs_v;   // sorted pair payloads (brick ids)
+    float lambda;
+    const CamParams* cam;
+    const Scratch* s;
+    // forward outputs (pose-offset applied by the caller)
+    float* out_feat;
+    float* out_alpha;
+    float* out_tfinal;
+    // backward inputs / outputs
+    const float* fwd_feat;
+    const float* fwd_tfinal;
+    const float* d_feat;
+    const float* d_alpha;
+    float* d_sigma;
+    float* d_leaf_feat;
+    // debug outputs
+    int max_hits;
+    int32_t* hit_leaf;
+    double* hit_delta;
+    int32_t* hit_count;
+};
+hipError_t launch_render(const RenderLaunch& r, hipStream_t st);
+
+}  // namespace art

@@ -1,0 +1,164 @@
+// Skeleton and skinning kernels (Section 3.1, "Rigging and Deformation", Eq. 4).
+//
+//   k_fk   : one thread per pose composes the bone chain in FP64 and writes the
+//            skinning matrices B_j = M^t_j (M^c_j)^-1 (FP64 and an FP32 copy).
+//   k_skin : one thread per leaf blends its four bone matrices with its skin
+//            weights, moves the leaf centre and writes the Morton key of the
+//            posed cell (or the invalid key for a leaf outside the posed root)
+//            plus its own index as the sort payload.  Leaf geometry is read as
+//            SoA planes (ijk, bone ids, weights), so consecutive threads read
+//            consecutive addresses of every plane.
+#include "device_util.h"
+#include "internal.h"
+
+namespace art {
+
+__device__ inline void axis_angle_to_matrix(const double* r, double* M) {
+    const double t2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+    const double t = sqrt(t2);
+    if (t < 1e-12) {
+        M[0] = 1; M[1] = 0; M[2] = 0;
+        M[3] = 0; M[4] = 1; M[5] = 0;
+        M[6] = 0; M[7] = 0; M[8] = 1;
+        return;
+    }
+    const double kx = r[0] / t, ky = r[1] / t, kz = r[2] / t;
+    double s, c;
+    sincos(t, &s, &c);
+    const double v = 1.0 - c;
+    // R = c I + s [k]_x + (1 - c) k k^T
+    M[0] = c + v * kx * kx;      M[1] = v * kx * ky - s * kz; M[2] = v * kx * kz + s * ky;
+    M[3] = v * ky * kx + s * kz; M[4] = c + v * ky * ky;      M[5] = v * ky * kz - s * kx;
+    M[6] = v * kz * kx - s * ky; M[7] = v * kz * ky + s * kx; M[8] = c + v * kz * kz;
+}
+
+__device__ inline void mat3_mul(const double* A, const double* B, double* C) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            C[3 * i + j] = A[3 * i] * B[j] + A[3 * i + 1] * B[3 + j] + A[3 * i + 2] * B[6 + j];
+}
+
+// G: scratch [P][J][12] (row-major 3x4 posed joint transforms).
+__global__ void k_fk(const int32_t* __restrict__ parent, const double* __restrict__ rest,
+                     const double* __restrict__ pose, int J, int P, double* __restrict__ G,
+                     double* __restrict__ B64, float* __restrict__ B32) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    const double* pr = pose + (size_t)p * (J + 2) * 3;
+    const double* Rg = pr + (size_t)J * 3;
+    const double* Tg = Rg + 3;
+    double* Gp = G + (size_t)p * J * 12;
+    for (int j = 0; j < J; ++j) {
+        double Rj[9], Rot[9], t[3];
+        axis_angle_to_matrix(pr + 3 * j, Rj);
+        const double* Jj = rest + 3 * j;
+        const int pa = parent[j];
+        if (pa < 0) {
+            double Rglob[9];
+            axis_angle_to_matrix(Rg, Rglob);
+            mat3_mul(Rglob, Rj, Rot);
+            t[0] = Jj[0] + Tg[0];
+            t[1] = Jj[1] + Tg[1];
+            t[2] = Jj[2] + Tg[2];
+        } else {
+            const double* Gq = Gp + (size_t)pa * 12;
+            const double Rq[9] = {Gq[0], Gq[1], Gq[2], Gq[4], Gq[5], Gq[6], Gq[8], Gq[9], Gq[10]};
+            mat3_mul(Rq, Rj, Rot);
+            const double* Jq = rest + 3 * pa;
+            const double off[3] = {Jj[0] - Jq[0], Jj[1] - Jq[1], Jj[2] - Jq[2]};
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                t[a] = Rq[3 * a] * off[0] + Rq[3 * a + 1] * off[1] + Rq[3 * a + 2] * off[2] + Gq[4 * a + 3];
+        }
+        double* Gj = Gp + (size_t)j * 12;
+        double* Bj = B64 + ((size_t)p * J + j) * 12;
+        float* Bf = B32 + ((size_t)p * J + j) * 12;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            Gj[4 * a + 0] = Rot[3 * a + 0];
+            Gj[4 * a + 1] = Rot[3 * a + 1];
+            Gj[4 * a + 2] = Rot[3 * a + 2];
+            Gj[4 * a + 3] = t[a];
+            // B_j = G_j [I | -J_j]
+            const double tb = t[a] - (Rot[3 * a] * Jj[0] + Rot[3 * a + 1] * Jj[1] + Rot[3 * a + 2] * Jj[2]);
+            Bj[4 * a + 0] = Rot[3 * a + 0];
+            Bj[4 * a + 1] = Rot[3 * a + 1];
+            Bj[4 * a + 2] = Rot[3 * a + 2];
+            Bj[4 * a + 3] = tb;
+            Bf[4 * a + 0] = (float)Rot[3 * a + 0];
+            Bf[4 * a + 1] = (float)Rot[3 * a + 1];
+            Bf[4 * a + 2] = (float)Rot[3 * a + 2];
+            Bf[4 * a + 3] = (float)tb;
+        }
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_skin(const uint16_t* __restrict__ ijk,
+                                              const uint8_t* __restrict__ bone,
+                                              const float* __restrict__ w,
+                                              uint32_t n, int depth,
+                                              const R* __restrict__ Bpose, int J,
+                                              uint32_t* __restrict__ keys,
+                                              uint32_t* __restrict__ vals) {
+    __shared__ R sB[256 * 12];
+    for (int i = threadIdx.x; i < J * 12; i += blockDim.x) sB[i] = Bpose[i];
+    __syncthreads();
+    const R h = (R)1 / (R)(1 << depth);
+    const R invh = (R)(1 << depth);
+    const R G = (R)(2 << depth);
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const R x = (R)-0.5 + ((R)ijk[i] + (R)0.5) * h;
+        const R y = (R)-0.5 + ((R)ijk[n + i] + (R)0.5) * h;
+        const R z = (R)-0.5 + ((R)ijk[2 * (size_t)n + i] + (R)0.5) * h;
+        R A[12];
+#pragma unroll
+        for (int e = 0; e < 12; ++e) A[e] = (R)0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int b = bone[(size_t)k * n + i];
+            const R wk = (R)w[(size_t)k * n + i];
+            const R* Bb = sB + b * 12;
+#pragma unroll
+            for (int e = 0; e < 12; ++e) A[e] += wk * Bb[e];
+        }
+        uint32_t c[3];
+        bool ok = true;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const R p = A[4 * a] * x + A[4 * a + 1] * y + A[4 * a + 2] * z + A[4 * a + 3];
+            const R u = floor((p + (R)1) * invh);
+            ok = ok && (u >= (R)0) && (u < G);
+            c[a] = ok ? (uint32_t)u : 0u;
+        }
+        keys[i] = ok ? morton3(c[0], c[1], c[2]) : kInvalidKey;
+        vals[i] = i;
+    }
+}
+
+hipError_t launch_fk(const int32_t* parent, const double* rest, const double* pose, int J, int P,
+                     double* G, double* B64, float* B32, hipStream_t st) {
+    const int bs = 64;
+    hipLaunchKernelGGL(k_fk, dim3((P + bs - 1) / bs), dim3(bs), 0, st, parent, rest, pose, J, P, G,
+                       B64, B32);
+    return hipGetLastError();
+}
+
+hipError_t launch_skin(const uint16_t* ijk, const uint8_t* bone, const float* w, int64_t n,
+                       int depth, const double* B64, const float* B32, int J, bool fp32,
+                       uint32_t* keys, uint32_t* vals, hipStream_t st) {
+    const int bs = 256;
+    int grid = (int)((n + bs - 1) / bs);
+    if (grid > 8192) grid = 8192;
+    if (fp32)
+        hipLaunchKernelGGL(k_skin<float>, dim3(grid), dim3(bs), 0, st, ijk, bone, w, (uint32_t)n,
+                           depth, B32, J, keys, vals);
+    else
+        hipLaunchKernelGGL(k_skin<double>, dim3(grid), dim3(bs), 0, st, ijk, bone, w, (uint32_t)n,
+                           depth, B64, J, keys, vals);
+    return hipGetLastError();
+}
+
+}  // namespace art

@@ -1,0 +1,202 @@
+// Data-parallel primitives of the posed-octree rebuild: a stable LSD radix
+// sort of (uint32 key, uint32 payload) pairs and an exclusive scan, both with
+// a fixed grid whose item count is read from device memory, so the host never
+// waits for a count produced on the GPU.
+//
+// Radix pass (8-bit digit, blocks own contiguous key ranges):
+//   k_hist     per-block digit histogram           -> hist[digit][block]
+//   k_hscan    one workgroup per digit scans its row over the blocks and
+//              writes the digit total
+//   k_scatter  per block, stable ranks: lanes with equal digits are matched
+//              with 8 wave ballots, their rank is the popcount of the matching
+//              lanes below; waves are ordered through a small LDS table and a
+//              running per-digit counter keeps tiles of 256 keys in order.
+#include "device_util.h"
+#include "internal.h"
+
+namespace art {
+
+constexpr int kSortThreads = 256;
+
+__global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t v, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    size_t grid = (n + 255) / 256;
+    if (grid > 4096) grid = 4096;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)grid), dim3(256), 0, st, p, v, n);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_hist(const uint32_t* __restrict__ keys,
+                                                       const uint32_t* __restrict__ d_n, int shift,
+                                                       uint32_t* __restrict__ hist) {
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    uint32_t lo, hi;
+    block_range(*d_n, blockIdx.x, gridDim.x, kSortThreads, &lo, &hi);
+    for (uint32_t i = lo + threadIdx.x; i < hi; i += kSortThreads)
+        atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+    __syncthreads();
+    hist[threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
+}
+
+// One workgroup per digit; nblk <= 1024 == blockDim.x.
+__global__ __launch_bounds__(1024) void k_hscan(uint32_t* __restrict__ hist, int nblk,
+                                                uint32_t* __restrict__ digit_tot) {
+    __shared__ uint32_t tmp[1024 / kWave + 1];
+    const int d = blockIdx.x;
+    const int b = threadIdx.x;
+    uint32_t v = b < nblk ? hist[d * nblk + b] : 0u;
+    uint32_t total;
+    uint32_t ex = block_exclusive_scan<1024>(v, tmp, &total);
+    if (b < nblk) hist[d * nblk + b] = ex;
+    if (b == 0) digit_tot[d] = total;
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_scatter(
+    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+    uint32_t* __restrict__ kout, uint32_t* __restrict__ vout, const uint32_t* __restrict__ d_n,
+    int shift, const uint32_t* __restrict__ hist, const uint32_t* __restrict__ digit_tot) {
+    constexpr int NW = kSortThreads / kWave;
+    __shared__ uint32_t base[256];
+    __shared__ uint32_t run[256];
+    __shared__ uint32_t cnt[NW][256];
+    __shared__ uint32_t tmp[NW + 1];
+    const int t = threadIdx.x;
+    const int w = t / kWave;
+    // global start of each digit for this block
+    uint32_t tot;
+    uint32_t dpre = block_exclusive_scan<kSortThreads>(digit_tot[t], tmp, &tot);
+    base[t] = dpre + hist[t * gridDim.x + blockIdx.x];
+    run[t] = 0;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) cnt[q][t] = 0;
+    __syncthreads();
+    uint32_t lo, hi;
+    block_range(*d_n, blockIdx.x, gridDim.x, kSortThreads, &lo, &hi);
+    const uint64_t below = lanemask_lt();
+    for (uint32_t i0 = lo; i0 < hi; i0 += kSortThreads) {
+        const uint32_t i = i0 + t;
+        const bool valid = i < hi;
+        const uint32_t k = valid ? kin[i] : 0u;
+        const uint32_t v = valid ? vin[i] : 0u;
+        const uint32_t d = (k >> shift) & 255u;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        const uint32_t rank = (uint32_t)__popcll(peers & below);
+        if (valid && rank == 0) cnt[w][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t pre = run[d] + rank;
+            for (int q = 0; q < w; ++q) pre += cnt[q][d];
+            const uint32_t dst = base[d] + pre;
+            kout[dst] = k;
+            vout[dst] = v;
+        }
+        __syncthreads();
+        uint32_t add = 0;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) {
+            add += cnt[q][t];
+            cnt[q][t] = 0;
+        }
+        run[t] += add;
+        __syncthreads();
+    }
+}
+
+hipError_t launch_radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1,
+                             const uint32_t* d_n, uint32_t n_cap, int bits, uint32_t* hist,
+                             uint32_t* digit_tot, hipStream_t st, bool* result_in_1,
+                             int* launches) {
+    int nblk = (int)((n_cap + 2047) / 2048);
+    if (nblk < 1) nblk = 1;
+    if (nblk > kSortBlocks) nblk = kSortBlocks;
+    const int passes = (bits + 7) / 8;
+    uint32_t *ki = k0, *vi = v0, *ko = k1, *vo = v1;
+    for (int p = 0; p < passes; ++p) {
+        const int shift = 8 * p;
+        hipLaunchKernelGGL(k_hist, dim3(nblk), dim3(kSortThreads), 0, st, ki, d_n, shift, hist);
+        hipLaunchKernelGGL(k_hscan, dim3(256), dim3(1024), 0, st, hist, nblk, digit_tot);
+        hipLaunchKernelGGL(k_scatter, dim3(nblk), dim3(kSortThreads), 0, st, ki, vi, ko, vo, d_n,
+                           shift, hist, digit_tot);
+        *launches += 3;
+        uint32_t* tk = ki; ki = ko; ko = tk;
+        uint32_t* tv = vi; vi = vo; vo = tv;
+    }
+    *result_in_1 = (passes & 1) != 0;
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// exclusive scan of a device-sized uint32 array
+// ---------------------------------------------------------------------------
+constexpr int kScanThreads = 256;
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t* __restrict__ in,
+                                                              const uint32_t* __restrict__ d_n,
+                                                              uint32_t* __restrict__ blk) {
+    __shared__ uint32_t tmp[kScanThreads / kWave];
+    uint32_t lo, hi;
+    block_range(*d_n, blockIdx.x, gridDim.x, kScanThreads, &lo, &hi);
+    uint32_t s = 0;
+    for (uint32_t i = lo + threadIdx.x; i < hi; i += kScanThreads) s += in[i];
+    s = wave_sum(s);
+    if (lane_id() == 0) tmp[threadIdx.x / kWave] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int q = 0; q < kScanThreads / kWave; ++q) t += tmp[q];
+        blk[blockIdx.x] = t;
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_scan_blocks(uint32_t* __restrict__ blk, int nblk,
+                                                      uint32_t* __restrict__ d_total) {
+    __shared__ uint32_t tmp[1024 / kWave + 1];
+    uint32_t v = (int)threadIdx.x < nblk ? blk[threadIdx.x] : 0u;
+    uint32_t total;
+    uint32_t ex = block_exclusive_scan<1024>(v, tmp, &total);
+    if ((int)threadIdx.x < nblk) blk[threadIdx.x] = ex;
+    if (threadIdx.x == 0 && d_total) *d_total = total;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t* __restrict__ in,
+                                                            uint32_t* __restrict__ out,
+                                                            const uint32_t* __restrict__ d_n,
+                                                            const uint32_t* __restrict__ blk) {
+    __shared__ uint32_t tmp[kScanThreads / kWave + 1];
+    uint32_t lo, hi;
+    block_range(*d_n, blockIdx.x, gridDim.x, kScanThreads, &lo, &hi);
+    uint32_t carry = blk[blockIdx.x];
+    for (uint32_t i0 = lo; i0 < hi; i0 += kScanThreads) {
+        const uint32_t i = i0 + threadIdx.x;
+        const uint32_t v = i < hi ? in[i] : 0u;
+        uint32_t total;
+        const uint32_t ex = block_exclusive_scan<kScanThreads>(v, tmp, &total);
+        if (i < hi) out[i] = carry + ex;
+        carry += total;
+    }
+}
+
+hipError_t launch_scan_exclusive(const uint32_t* in, uint32_t* out, const uint32_t* d_n,
+                                 uint32_t* d_total, uint32_t* blk, hipStream_t st, int* launches) {
+    hipLaunchKernelGGL(k_scan_reduce, dim3(kScanBlocks), dim3(kScanThreads), 0, st, in, d_n, blk);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, blk, kScanBlocks, d_total);
+    hipLaunchKernelGGL(k_scan_down, dim3(kScanBlocks), dim3(kScanThreads), 0, st, in, out, d_n, blk);
+    *launches += 3;
+    return hipGetLastError();
+}
+
+}  // namespace art
