@@ -121,49 +121,70 @@ art_status ensure_bufs(art_ctx* ctx, std::initializer_list<std::pair<DevBuf*, si
     return ART_OK;
 }
 
-// Buffers of FK, skinning and the octree build.
-art_status ensure_build_scratch(art_ctx* ctx, const CallPlan& pl) {
+// Device memory held for the posed octrees of one batch of poses; the poses of
+// a call are processed in batches of at most this many.
+constexpr size_t kSlotBudgetBytes = (size_t)48 << 30;
+
+size_t slot_bytes(const art_ctx* ctx, const CallPlan& pl, size_t pair_cap) {
+    const size_t n = (size_t)ctx->n;
+    const size_t es = pl.storage ? 2 : 4;
+    const size_t tiles = (size_t)ctx->V * ((ctx->W + 7) / 8) * ((ctx->H + 7) / 8);
+    return n * (4 + 4 + 4 + 4 + 64 + es * (pl.C + 1)) + (size_t)pl.ngroups * pair_cap * 4 + tiles * 8 +
+           (size_t)pl.ngroups * 8;
+}
+
+// Sort / scan scratch and the per-slot arrays of `slots` poses.
+art_status ensure_scratch(art_ctx* ctx, const CallPlan& pl, int slots) {
     Scratch& s = ctx->s;
     const size_t n = (size_t)ctx->n;
     const size_t es = pl.storage ? 2 : 4;
-    return ensure_bufs(ctx, {
+    const size_t V = (size_t)std::max(ctx->V, 1);
+    const size_t tiles = V * ((ctx->W + 7) / 8) * ((ctx->H + 7) / 8);
+    const size_t tiles_g = (size_t)pl.Vg * ((ctx->W + 7) / 8) * ((ctx->H + 7) / 8);
+    if (s.pair_cap == 0) s.pair_cap = std::max<size_t>((size_t)1 << 20, 16 * tiles_g);
+    const size_t S = (size_t)slots;
+    art_status rc = ensure_bufs(ctx, {
         {&s.keys0, n * 4}, {&s.vals0, n * 4}, {&s.keys1, n * 4}, {&s.vals1, n * 4},
         {&s.hist, 256 * (size_t)kSortBlocks * 4}, {&s.digit_tot, 256 * 4},
         {&s.blk0, (size_t)kScanBlocks * 4}, {&s.blk1, (size_t)kScanBlocks * 4},
-        {&s.occ_key, n * 4}, {&s.occ_win, n * 4},
-        {&s.brick_key, n * 4}, {&s.brick_row, (n + 1) * 4}, {&s.brick_mask, n * 64},
-        {&s.flut_sig, n * es}, {&s.flut_feat, n * pl.C * es},
         {&s.counters, sizeof(PoseCounters)}, {&s.stats, 16 * sizeof(unsigned long long)},
         {&ctx->B64, (size_t)ctx->P * ctx->J * 12 * 8}, {&ctx->B32, (size_t)ctx->P * ctx->J * 12 * 4},
         {&ctx->Gtmp, (size_t)ctx->P * ctx->J * 12 * 8},
-    });
-}
-
-// Build buffers plus those of the tile binning and the overflow flags.
-art_status ensure_scratch(art_ctx* ctx, const CallPlan& pl) {
-    art_status rc = ensure_build_scratch(ctx, pl);
-    if (rc != ART_OK) return rc;
-    Scratch& s = ctx->s;
-    const size_t n = (size_t)ctx->n;
-    const size_t tiles = (size_t)pl.Vg * ((ctx->W + 7) / 8) * ((ctx->H + 7) / 8);
-    if (s.pair_cap == 0) s.pair_cap = std::max<size_t>((size_t)1 << 22, 8 * tiles);
-    const size_t items = (size_t)ctx->P * pl.ngroups;
-    return ensure_bufs(ctx, {
+        {&s.occ_key, S * n * 4}, {&s.occ_win, S * n * 4},
+        {&s.brick_key, S * n * 4}, {&s.brick_row, S * (n + 1) * 4}, {&s.brick_mask, S * n * 64},
+        {&s.flut_sig, S * n * es}, {&s.flut_feat, S * n * pl.C * es},
         {&s.bin_cnt, n * pl.Vg * 4}, {&s.bin_off, n * pl.Vg * 4},
         {&s.pk0, s.pair_cap * 4}, {&s.pv0, s.pair_cap * 4}, {&s.pk1, s.pair_cap * 4},
-        {&s.pv1, s.pair_cap * 4},
-        {&s.tile_start, tiles * 4}, {&s.tile_end, tiles * 4},
-        {&s.ovf, items * 2 * 4},
+        {&s.pair_v, S * pl.ngroups * s.pair_cap * 4},
+        {&s.tile_start, S * tiles * 4}, {&s.tile_end, S * tiles * 4},
+        {&s.ovf, S * pl.ngroups * 2 * 4},
     });
+    if (rc == ART_OK) s.slots = std::max(s.slots, slots);
+    return rc;
+}
+
+OctreeSlot octree_slot(art_ctx* ctx, const CallPlan& pl, int slot) {
+    Scratch& s = ctx->s;
+    const size_t n = (size_t)ctx->n;
+    const size_t es = pl.storage ? 2 : 4;
+    OctreeSlot o;
+    o.occ_key = s.occ_key.as<uint32_t>() + (size_t)slot * n;
+    o.occ_win = s.occ_win.as<uint32_t>() + (size_t)slot * n;
+    o.brick_key = s.brick_key.as<uint32_t>() + (size_t)slot * n;
+    o.brick_row = s.brick_row.as<uint32_t>() + (size_t)slot * (n + 1);
+    o.brick_mask = s.brick_mask.as<uint32_t>() + (size_t)slot * n * 16;
+    o.psig = s.flut_sig.as<char>() + (size_t)slot * n * es;
+    o.pfeat = s.flut_feat.as<char>() + (size_t)slot * n * pl.C * es;
+    return o;
 }
 
 struct Timing {
     bool on = false;
     std::vector<hipEvent_t> ev;
+    std::vector<int> stage;   // stage id of the interval ending at ev[i]
     ~Timing() {
         for (auto e : ev) (void)hipEventDestroy(e);
     }
-    std::vector<int> stage;   // stage id of the interval ending at ev[i]
     void record(hipStream_t st, int stage_id) {
         if (!on) return;
         hipEvent_t e;
@@ -207,18 +228,20 @@ struct PassOut {
     float* d_leaf_feat = nullptr;
     // debug
     int max_hits = 0;
+    int debug_view = 0;
     int32_t* hit_leaf = nullptr;
     double* hit_delta = nullptr;
     int32_t* hit_count = nullptr;
-    bool single = false;   // outputs hold one (pose, view) map only
+    bool single_pose = false;   // maps hold one pose only
 };
 
-// Skin + sort + octree build of one pose into the scratch buffers.
-art_status build_pose(art_ctx* ctx, const CallPlan& pl, int p, const void* sigma, const void* feat,
-                      int* launches, Timing& tm) {
+// Skin + sort + octree build of pose p into slot `slot`.
+art_status build_pose(art_ctx* ctx, const CallPlan& pl, int p, int slot, const void* sigma,
+                      const void* feat, int* launches, Timing& tm) {
     Scratch& s = ctx->s;
     hipStream_t st = ctx->stream;
     PoseCounters* cnt = s.counters.as<PoseCounters>();
+    tm.record(st, -1);
     ART_TRY_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(cnt), 0u, sizeof(PoseCounters) / 4, st), "fill");
     ART_TRY_HIP(launch_fill_u32(&cnt->pad[2], (uint32_t)ctx->n, 1, st), "fill");
     ART_TRY_HIP(launch_skin(ctx->ijk.as<uint16_t>(), ctx->bone.as<uint8_t>(), ctx->weight.as<float>(),
@@ -235,103 +258,101 @@ art_status build_pose(art_ctx* ctx, const CallPlan& pl, int p, const void* sigma
                 "radix sort");
     const uint32_t* sk = in1 ? s.keys1.as<uint32_t>() : s.keys0.as<uint32_t>();
     const uint32_t* sv = in1 ? s.vals1.as<uint32_t>() : s.vals0.as<uint32_t>();
-    ART_TRY_HIP(launch_build_octree(sk, sv, (uint32_t)ctx->n, pl.C, pl.storage, sigma, feat, s, st, launches),
+    ART_TRY_HIP(launch_build_octree(sk, sv, (uint32_t)ctx->n, pl.C, pl.storage, sigma, feat, s,
+                                    octree_slot(ctx, pl, slot), st, launches),
                 "octree build");
     tm.record(st, 2);
     return ART_OK;
 }
 
-RenderLaunch make_launch(art_ctx* ctx, const CallPlan& pl, int mode, int p, int v0, int Vg,
-                         float lambda, const uint32_t* pairs_v, const PassOut& o) {
+// One batch of poses [p0, p1): build every pose into its slot, bin its view
+// groups, then render all (pose, view) maps of the batch in one launch.
+// `redo` (indexed by slot * ngroups + group) restricts the batch to the
+// (pose, group) items whose tile lists overflowed in an earlier attempt.
+art_status run_batch(art_ctx* ctx, const CallPlan& pl, int mode, float lambda, const void* sigma,
+                     const void* feat, const PassOut& o, int p0, int p1,
+                     const std::vector<char>* redo, int* launches, Timing& tm) {
+    Scratch& s = ctx->s;
+    hipStream_t st = ctx->stream;
+    PoseCounters* cnt = s.counters.as<PoseCounters>();
+    unsigned long long* stats = s.stats.as<unsigned long long>();
+    const int Pb = p1 - p0;
+    const size_t TPV = (size_t)((ctx->W + 7) / 8) * ((ctx->H + 7) / 8);
+    // slots not (re)built in this attempt are skipped by the render kernel
+    ART_TRY_HIP(launch_fill_u32(s.ovf.as<uint32_t>(), redo ? 1u : 0u, (size_t)Pb * pl.ngroups * 2, st), "fill");
+    *launches += 1;
+    for (int p = p0; p < p1; ++p) {
+        const int slot = p - p0;
+        bool any = true;
+        if (redo) {
+            any = false;
+            for (int gi = 0; gi < pl.ngroups; ++gi) any = any || (*redo)[(size_t)slot * pl.ngroups + gi];
+        }
+        if (!any) continue;
+        art_status rc = build_pose(ctx, pl, p, slot, sigma, feat, launches, tm);
+        if (rc != ART_OK) return rc;
+        hipLaunchKernelGGL(k_accum, dim3(1), dim3(1), 0, st, (const PoseCounters*)cnt, stats, (uint32_t)ctx->n);
+        *launches += 1;
+        const OctreeSlot os = octree_slot(ctx, pl, slot);
+        for (int gi = 0; gi < pl.ngroups; ++gi) {
+            const size_t sg = (size_t)slot * pl.ngroups + gi;
+            if (redo && !(*redo)[sg]) continue;
+            const int v0 = gi * pl.Vg;
+            const int Vg = std::min(ctx->V, v0 + pl.Vg) - v0;
+            tm.record(st, -1);
+            uint32_t* ts = s.tile_start.as<uint32_t>() + ((size_t)slot * ctx->V + v0) * TPV;
+            uint32_t* te = s.tile_end.as<uint32_t>() + ((size_t)slot * ctx->V + v0) * TPV;
+            ART_TRY_HIP(launch_bin(s, ctx->cam.as<CamParams>(), os.brick_key, v0, Vg, ctx->H, ctx->W, ctx->depth,
+                                   pl.fp32, s.pair_v.as<uint32_t>() + sg * s.pair_cap, ts, te, st, launches),
+                        "tile binning");
+            hipLaunchKernelGGL(k_pairs, dim3(1), dim3(1), 0, st, (const PoseCounters*)cnt, stats,
+                               s.ovf.as<uint32_t>() + 2 * sg);
+            *launches += 1;
+            tm.record(st, 3);
+        }
+    }
+    tm.record(st, -1);
     RenderLaunch r{};
     r.C = pl.C;
     r.storage = pl.storage ? ART_BF16 : ART_F32;
     r.fp32 = pl.fp32;
     r.mode = mode;
     r.depth = ctx->depth;
-    r.v0 = v0;
-    r.Vg = Vg;
+    r.Pb = Pb;
     r.V = ctx->V;
     r.H = ctx->H;
     r.W = ctx->W;
-    r.pose = p;
-    r.mbits = pl.mbits;
-    r.pairs_v = pairs_v;
+    r.Vg = pl.Vg;
+    r.ngroups = pl.ngroups;
+    r.ncap = (uint32_t)ctx->n;
     r.lambda = lambda;
     r.cam = ctx->cam.as<CamParams>();
     r.s = &ctx->s;
     const size_t HW = (size_t)ctx->H * ctx->W;
-    const size_t pv = o.single ? 0 : (size_t)p * ctx->V + v0;   // first (pose, view) map of the group
-    if (o.out_feat) r.out_feat = o.out_feat + pv * pl.C * HW;
-    if (o.out_alpha) r.out_alpha = o.out_alpha + pv * HW;
-    if (o.out_tfinal) r.out_tfinal = o.out_tfinal + pv * HW;
-    if (o.fwd_feat) r.fwd_feat = o.fwd_feat + pv * pl.C * HW;
-    if (o.fwd_tfinal) r.fwd_tfinal = o.fwd_tfinal + pv * HW;
-    if (o.d_feat) r.d_feat = o.d_feat + pv * pl.C * HW;
-    if (o.d_alpha) r.d_alpha = o.d_alpha + pv * HW;
+    const size_t m0 = o.single_pose ? 0 : (size_t)p0 * ctx->V;   // first map of the batch
+    if (o.out_feat) r.out_feat = o.out_feat + m0 * pl.C * HW;
+    if (o.out_alpha) r.out_alpha = o.out_alpha + m0 * HW;
+    if (o.out_tfinal) r.out_tfinal = o.out_tfinal + m0 * HW;
+    if (o.fwd_feat) r.fwd_feat = o.fwd_feat + m0 * pl.C * HW;
+    if (o.fwd_tfinal) r.fwd_tfinal = o.fwd_tfinal + m0 * HW;
+    if (o.d_feat) r.d_feat = o.d_feat + m0 * pl.C * HW;
+    if (o.d_alpha) r.d_alpha = o.d_alpha + m0 * HW;
     r.d_sigma = o.d_sigma;
     r.d_leaf_feat = o.d_leaf_feat;
     r.max_hits = o.max_hits;
+    r.debug_view = o.debug_view;
     r.hit_leaf = o.hit_leaf;
     r.hit_delta = o.hit_delta;
     r.hit_count = o.hit_count;
-    return r;
-}
-
-// One full pass over the poses / view groups.  `only` restricts it to a set of
-// (pose, group) items (re-runs after a pair-buffer overflow).
-art_status run_pass(art_ctx* ctx, const CallPlan& pl, int mode, float lambda, const void* sigma,
-                    const void* feat, const PassOut& o, int pose_lo, int pose_hi, int view_lo,
-                    int view_hi, const std::vector<char>* only, DevBuf& ovf, int* launches,
-                    Timing& tm) {
-    Scratch& s = ctx->s;
-    hipStream_t st = ctx->stream;
-    PoseCounters* cnt = s.counters.as<PoseCounters>();
-    unsigned long long* stats = s.stats.as<unsigned long long>();
-    for (int p = pose_lo; p < pose_hi; ++p) {
-        bool any = true;
-        if (only) {
-            any = false;
-            for (int gi = 0; gi < pl.ngroups; ++gi) any = any || (*only)[(size_t)p * pl.ngroups + gi];
-        }
-        if (!any) continue;
-        tm.record(st, -1);
-        art_status rc = build_pose(ctx, pl, p, sigma, feat, launches, tm);
-        if (rc != ART_OK) return rc;
-        hipLaunchKernelGGL(k_accum, dim3(1), dim3(1), 0, st, (const PoseCounters*)cnt, stats, (uint32_t)ctx->n);
-        *launches += 1;
-        for (int gi = 0; gi < pl.ngroups; ++gi) {
-            if (only && !(*only)[(size_t)p * pl.ngroups + gi]) continue;
-            int v0 = gi * pl.Vg;
-            int v1 = std::min(ctx->V, v0 + pl.Vg);
-            v0 = std::max(v0, view_lo);
-            v1 = std::min(v1, view_hi);
-            if (v1 <= v0) continue;
-            const int Vg = v1 - v0;
-            int mbits = 0;
-            const uint32_t* pairs_v = nullptr;
-            tm.record(st, -1);
-            ART_TRY_HIP(launch_bin(s, ctx->cam.as<CamParams>(), v0, Vg, ctx->H, ctx->W, ctx->depth, pl.fp32,
-                                   st, launches, &mbits, &pairs_v),
-                        "tile binning");
-            hipLaunchKernelGGL(k_pairs, dim3(1), dim3(1), 0, st, (const PoseCounters*)cnt, stats,
-                               ovf.as<uint32_t>() + 2 * ((size_t)p * pl.ngroups + gi));
-            *launches += 1;
-            tm.record(st, 3);
-            CallPlan pg = pl;
-            pg.mbits = mbits;
-            RenderLaunch r = make_launch(ctx, pg, mode, p, v0, Vg, lambda, pairs_v, o);
-            ART_TRY_HIP(launch_render(r, st), "render");
-            *launches += 1;
-            tm.record(st, 4);
-        }
-    }
+    ART_TRY_HIP(launch_render(r, st), "render");
+    *launches += 1;
+    tm.record(st, 4);
     return ART_OK;
 }
 
 art_status render_call(art_ctx* ctx, int C, art_dtype dtype, const void* sigma, const void* feat,
                        float lambda, unsigned flags, int mode, const PassOut& o, int pose_lo,
-                       int pose_hi, int view_lo, int view_hi) {
+                       int pose_hi) {
     art_status rc = check_render_state(ctx);
     if (rc != ART_OK) return rc;
     CallPlan pl;
@@ -339,59 +360,62 @@ art_status render_call(art_ctx* ctx, int C, art_dtype dtype, const void* sigma, 
     if (rc != ART_OK) return rc;
     if (!sigma || !feat) return fail(ctx, ART_EINVAL, "sigma / feat must be device pointers");
     if (!(lambda >= 0.0f && lambda < 1.0f)) return fail(ctx, ART_EINVAL, "lambda_th must be in [0, 1)");
-    rc = ensure_scratch(ctx, pl);
+    const int P = pose_hi - pose_lo;
+    if (ctx->s.pair_cap == 0) {
+        const size_t tiles_g = (size_t)pl.Vg * ((ctx->W + 7) / 8) * ((ctx->H + 7) / 8);
+        ctx->s.pair_cap = std::max<size_t>((size_t)1 << 20, 16 * tiles_g);
+    }
+    int slots = (int)std::min<size_t>((size_t)P, std::max<size_t>(1, kSlotBudgetBytes / slot_bytes(ctx, pl, ctx->s.pair_cap)));
+    rc = ensure_scratch(ctx, pl, slots);
     if (rc != ART_OK) return rc;
-    DevBuf& ovf = ctx->s.ovf;
-    const size_t items = (size_t)ctx->P * pl.ngroups;
     hipStream_t st = ctx->stream;
     int launches = 0;
     Timing tm;
     tm.on = (flags & ART_TIMING) != 0;
 
-    ART_TRY_HIP(launch_fill_u32(ovf.as<uint32_t>(), 0u, items * 2, st), "fill");
     ART_TRY_HIP(launch_fill_u32(ctx->s.stats.as<uint32_t>(), 0u, 32, st), "fill");
     tm.record(st, -1);
     ART_TRY_HIP(launch_fk(ctx->parent.as<int32_t>(), ctx->rest.as<double>(), ctx->pose.as<double>(), ctx->J,
                           ctx->P, ctx->Gtmp.as<double>(), ctx->B64.as<double>(), ctx->B32.as<float>(), st),
                 "fk");
-    launches += 3;
+    launches += 2;
     tm.record(st, 0);
-    rc = run_pass(ctx, pl, mode, lambda, sigma, feat, o, pose_lo, pose_hi, view_lo, view_hi, nullptr, ovf,
-                  &launches, tm);
-    if (rc != ART_OK) return rc;
-    // read back overflow flags and statistics
-    std::vector<uint32_t> hov(items * 2);
+    for (int p0 = pose_lo; p0 < pose_hi; p0 += slots) {
+        const int p1 = std::min(pose_hi, p0 + slots);
+        const size_t items = (size_t)(p1 - p0) * pl.ngroups;
+        rc = run_batch(ctx, pl, mode, lambda, sigma, feat, o, p0, p1, nullptr, &launches, tm);
+        if (rc != ART_OK) return rc;
+        // a (pose, view group) whose tile lists overflowed was skipped by the
+        // render kernel: grow the list buffers and run those items again
+        for (int attempt = 0; attempt < 3; ++attempt) {
+            std::vector<uint32_t> hov(items * 2);
+            ART_TRY_HIP(hipMemcpyAsync(hov.data(), ctx->s.ovf.p, items * 2 * 4, hipMemcpyDeviceToHost, st), "copy");
+            ART_TRY_HIP(hipStreamSynchronize(st), "render");
+            std::vector<char> redo(items, 0);
+            size_t need = 0;
+            bool any = false;
+            for (size_t i = 0; i < items; ++i)
+                if (hov[2 * i] != 0u && hov[2 * i + 1] > ctx->s.pair_cap) {
+                    redo[i] = 1;
+                    any = true;
+                    need = std::max<size_t>(need, hov[2 * i + 1]);
+                }
+            if (!any) break;
+            if (attempt == 2) return fail(ctx, ART_EDEVICE, "tile list buffer overflow persisted");
+            ctx->s.pair_cap = need + need / 4 + 1024;
+            rc = ensure_scratch(ctx, pl, slots);
+            if (rc != ART_OK) return rc;
+            rc = run_batch(ctx, pl, mode, lambda, sigma, feat, o, p0, p1, &redo, &launches, tm);
+            if (rc != ART_OK) return rc;
+        }
+    }
     unsigned long long hst[16];
-    ART_TRY_HIP(hipMemcpyAsync(hov.data(), ovf.p, items * 2 * 4, hipMemcpyDeviceToHost, st), "copy");
     ART_TRY_HIP(hipMemcpyAsync(hst, ctx->s.stats.p, sizeof(hst), hipMemcpyDeviceToHost, st), "copy");
     ART_TRY_HIP(hipStreamSynchronize(st), "render");
-    // any (pose, view group) whose pair list overflowed is re-run with a larger buffer;
-    // its render kernel skipped the group, so nothing was written for it yet
-    std::vector<char> redo(items, 0);
-    size_t need = 0;
-    bool any = false;
-    for (size_t i = 0; i < items; ++i)
-        if (hov[2 * i]) {
-            redo[i] = 1;
-            any = true;
-            need = std::max<size_t>(need, hov[2 * i + 1]);
-        }
-    if (any) {
-        ctx->s.pair_cap = need + need / 4 + 1024;
-        rc = ensure_scratch(ctx, pl);
-        if (rc != ART_OK) return rc;
-        ART_TRY_HIP(launch_fill_u32(ovf.as<uint32_t>(), 0u, items * 2, st), "fill");
-        rc = run_pass(ctx, pl, mode, lambda, sigma, feat, o, pose_lo, pose_hi, view_lo, view_hi, &redo, ovf,
-                      &launches, tm);
-        if (rc != ART_OK) return rc;
-        ART_TRY_HIP(hipMemcpyAsync(hst, ctx->s.stats.p, sizeof(hst), hipMemcpyDeviceToHost, st), "copy");
-        ART_TRY_HIP(hipMemcpyAsync(hov.data(), ovf.p, items * 2 * 4, hipMemcpyDeviceToHost, st), "copy");
-        ART_TRY_HIP(hipStreamSynchronize(st), "render");
-        for (size_t i = 0; i < items; ++i)
-            if (hov[2 * i]) return fail(ctx, ART_EDEVICE, "tile pair buffer overflow persisted");
-    }
     for (int i = 0; i < 7; ++i) ctx->stats[i] = (int64_t)hst[i];
     ctx->stats[7] = launches;
+    ctx->stats[8] = (int64_t)hst[7];
+    ctx->stats[9] = (int64_t)hst[8];
     tm.finish(ctx);
     return ART_OK;
 }
@@ -406,8 +430,7 @@ hipError_t launch_render(const RenderLaunch& r, hipStream_t st) {
     const Scratch& s = *r.s;
     RArgs a{};
     a.cam = r.cam;
-    a.v0 = r.v0;
-    a.Vg = r.Vg;
+    a.Pb = r.Pb;
     a.V = r.V;
     a.H = r.H;
     a.W = r.W;
@@ -415,14 +438,19 @@ hipError_t launch_render(const RenderLaunch& r, hipStream_t st) {
     a.TY = (r.H + 7) / 8;
     a.TPV = a.TX * a.TY;
     a.depth = r.depth;
+    a.Vg = r.Vg;
+    a.ngroups = r.ngroups;
     a.wg_x = (a.TX + 1) / 2;
     const int wg_y = (a.TY + 1) / 2;
     a.wg_per_view = a.wg_x * wg_y;
-    a.n_wg = a.wg_per_view * r.Vg;
+    a.n_wg = a.wg_per_view * r.V * r.Pb;
+    a.ncap = r.ncap;
+    a.pair_cap = (uint32_t)s.pair_cap;
     a.lambda = r.lambda;
     a.tile_start = s.tile_start.as<uint32_t>();
     a.tile_end = s.tile_end.as<uint32_t>();
-    a.pair_v = r.pairs_v;
+    a.pair_v = s.pair_v.as<uint32_t>();
+    a.ovf = s.ovf.as<uint32_t>();
     a.brick_key = s.brick_key.as<uint32_t>();
     a.brick_row = s.brick_row.as<uint32_t>();
     a.brick_mask = s.brick_mask.as<uint32_t>();
@@ -439,11 +467,11 @@ hipError_t launch_render(const RenderLaunch& r, hipStream_t st) {
     a.d_sigma = r.d_sigma;
     a.d_leaf_feat = r.d_leaf_feat;
     a.max_hits = r.max_hits;
+    a.debug_view = r.debug_view;
     a.hit_leaf = r.hit_leaf;
     a.hit_delta = r.hit_delta;
     a.hit_count = r.hit_count;
     a.stats = s.stats.as<unsigned long long>();
-    a.counters = s.counters.as<PoseCounters>();
     const unsigned per = 8u * kXcdChunk;
     const unsigned grid = (unsigned)((a.n_wg + per - 1) / per * per);
     switch (r.C) {
@@ -692,7 +720,7 @@ art_status art_render(art_ctx* ctx, int C, art_dtype dtype, const void* sigma, c
     o.out_feat = out_feat;
     o.out_alpha = out_alpha;
     o.out_tfinal = out_tfinal;
-    return render_call(ctx, C, dtype, sigma, feat, lambda_th, flags, 0, o, 0, ctx->P, 0, ctx->V);
+    return render_call(ctx, C, dtype, sigma, feat, lambda_th, flags, 0, o, 0, ctx->P);
 }
 
 art_status art_backward(art_ctx* ctx, int C, art_dtype dtype, const void* sigma, const void* feat,
@@ -709,7 +737,7 @@ art_status art_backward(art_ctx* ctx, int C, art_dtype dtype, const void* sigma,
     o.d_alpha = d_alpha;
     o.d_sigma = d_sigma;
     o.d_leaf_feat = d_leaf_feat;
-    return render_call(ctx, C, dtype, sigma, feat, lambda_th, flags, 1, o, 0, ctx->P, 0, ctx->V);
+    return render_call(ctx, C, dtype, sigma, feat, lambda_th, flags, 1, o, 0, ctx->P);
 }
 
 art_status art_get_hits(art_ctx* ctx, int pose, int view, int C, art_dtype dtype, const void* sigma,
@@ -722,23 +750,23 @@ art_status art_get_hits(art_ctx* ctx, int pose, int view, int C, art_dtype dtype
     if (!supported_C(C)) return fail(ctx, ART_EUNSUPPORTED, "C must be 4, 8, 16 or 32");
     DeviceGuard g(ctx->device);
     const size_t HW = (size_t)ctx->H * ctx->W;
-    DevBuf tf, ta;   // forward maps of the requested (pose, view), discarded
-    ART_TRY_HIP(tf.ensure(HW * C * 4), "device allocation");
-    hipError_t e = ta.ensure(HW * 4);
+    DevBuf tf, ta;   // forward maps of the pose's views, discarded
+    ART_TRY_HIP(tf.ensure(HW * C * 4 * ctx->V), "device allocation");
+    hipError_t e = ta.ensure(HW * 4 * ctx->V);
     if (e != hipSuccess) {
         tf.release();
         return hip_fail(ctx, e, "device allocation");
     }
     PassOut o;
-    o.single = true;
+    o.single_pose = true;
     o.out_feat = tf.as<float>();
     o.out_alpha = ta.as<float>();
     o.max_hits = max_hits;
+    o.debug_view = view;
     o.hit_leaf = leaf;
     o.hit_delta = delta;
     o.hit_count = count;
-    art_status rc = render_call(ctx, C, dtype, sigma, feat, lambda_th, flags, 2, o, pose, pose + 1, view,
-                                view + 1);
+    art_status rc = render_call(ctx, C, dtype, sigma, feat, lambda_th, flags, 2, o, pose, pose + 1);
     tf.release();
     ta.release();
     return rc;
@@ -803,7 +831,8 @@ art_status art_get_octree(art_ctx* ctx, int pose, unsigned flags, int64_t* count
     pl.storage = 0;
     pl.fp32 = (flags & ART_GEOM_FP32) != 0;
     pl.Vg = 1;
-    rc = ensure_build_scratch(ctx, pl);
+    pl.ngroups = 1;
+    rc = ensure_scratch(ctx, pl, 1);
     if (rc != ART_OK) return rc;
     DevBuf zs, zf;   // the build also permutes a FLUT; feed it zeros
     ART_TRY_HIP(zs.ensure((size_t)ctx->n * 4), "device allocation");
@@ -825,7 +854,7 @@ art_status art_get_octree(art_ctx* ctx, int pose, unsigned flags, int64_t* count
     }
     Timing tm;
     int launches = 0;
-    rc = build_pose(ctx, pl, pose, zs.p, zf.p, &launches, tm);
+    rc = build_pose(ctx, pl, pose, 0, zs.p, zf.p, &launches, tm);
     PoseCounters hc{};
     if (rc == ART_OK) {
         e = hipMemcpyAsync(&hc, ctx->s.counters.p, sizeof(hc), hipMemcpyDeviceToHost, st);

@@ -56,10 +56,10 @@ struct PoseCounters {
 
 // Run-wide statistics accumulated on the device.
 struct RunStats {
-    unsigned long long rays, samples, hit_rays, dropped, collisions, bricks, pairs, launches;
+    unsigned long long rays, samples, hit_rays, dropped, collisions, bricks, pairs, list_entries, rounds;
 };
 
-constexpr int kNumStats = 8;
+constexpr int kNumStats = 10;
 constexpr int kSortBlocks = 512;      // fixed grid of the radix-sort passes
 constexpr int kScanBlocks = 1024;     // fixed grid of device-sized scans
 constexpr int kUniqueBlocks = 1024;   // fixed grid of the unique / compaction step
@@ -68,16 +68,18 @@ struct Scratch {
     DevBuf keys0, vals0, keys1, vals1;   // sort ping-pong [n]
     DevBuf hist, digit_tot;              // [256 * kSortBlocks], [256]
     DevBuf blk0, blk1;                   // block partials [kScanBlocks]
-    DevBuf occ_key, occ_win;             // [n] posed cells + winners
-    DevBuf brick_key, brick_row, brick_mask;  // [n], [n+1], [n*16]
-    DevBuf flut_sig, flut_feat;          // posed-order FLUT rows
+    DevBuf occ_key, occ_win;             // [slots][n] posed cells + winners
+    DevBuf brick_key, brick_row, brick_mask;  // [slots][n], [slots][n+1], [slots][n*16]
+    DevBuf flut_sig, flut_feat;          // [slots][n] posed-order FLUT rows
     DevBuf bin_cnt, bin_off;             // [n*V]
-    DevBuf pk0, pv0, pk1, pv1;           // pair sort [pair_cap]
-    DevBuf tile_start, tile_end;         // [V * tiles]
+    DevBuf pk0, pv0, pk1, pv1;           // pair sort scratch [pair_cap]
+    DevBuf pair_v;                       // [slots][groups][pair_cap] sorted brick ids
+    DevBuf tile_start, tile_end;         // [slots][V][tiles]
     DevBuf counters;                     // PoseCounters
     DevBuf stats;                        // RunStats
-    DevBuf ovf;                          // [P * groups][2] overflow flag, pair count
+    DevBuf ovf;                          // [slots][groups][2] overflow flag, pair count
     size_t pair_cap = 0;
+    int slots = 0;                       // poses whose octrees are held at once
 };
 
 }  // namespace art
@@ -136,39 +138,49 @@ hipError_t launch_radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t*
                              uint32_t* digit_tot, hipStream_t st, bool* result_in_1, int* launches);
 hipError_t launch_scan_exclusive(const uint32_t* in, uint32_t* out, const uint32_t* d_n,
                                  uint32_t* d_total, uint32_t* blk, hipStream_t st, int* launches);
+// Posed octree of one pose (one slot of the per-pose arrays).
+struct OctreeSlot {
+    uint32_t* occ_key;      // [n]
+    uint32_t* occ_win;      // [n]
+    uint32_t* brick_key;    // [n]
+    uint32_t* brick_row;    // [n + 1]
+    uint32_t* brick_mask;   // [n][16]
+    void* psig;             // [n] posed-order densities
+    void* pfeat;            // [n][C] posed-order features
+};
 hipError_t launch_build_octree(const uint32_t* skeys, const uint32_t* svals, uint32_t n,
                                int C, int storage, const void* sigma, const void* feat,
-                               Scratch& s, hipStream_t st, int* launches);
+                               Scratch& s, const OctreeSlot& o, hipStream_t st, int* launches);
 int bin_key_bits(int Vg, int H, int W, int depth, int* mbits);
-hipError_t launch_bin(Scratch& s, const CamParams* cam_dev, int v0, int Vg, int H, int W, int depth,
-                      bool fp32, hipStream_t st, int* launches, int* mbits_out,
-                      const uint32_t** pairs_v);
+// Tile lists of views [v0, v0 + Vg) of one pose: sorted brick ids into pair_out
+// (capacity s.pair_cap) and per-tile ranges into tile_start / tile_end [Vg][TPV].
+hipError_t launch_bin(Scratch& s, const CamParams* cam_dev, const uint32_t* brick_key, int v0, int Vg,
+                      int H, int W, int depth, bool fp32, uint32_t* pair_out, uint32_t* tile_start,
+                      uint32_t* tile_end, hipStream_t st, int* launches);
 
 struct RenderLaunch {
     int C, storage;
     bool fp32;
     int mode;            // 0 forward, 1 backward, 2 debug hit lists
     int depth;
-    int v0, Vg, V, H, W; // view group [v0, v0+Vg) of V views
-    int pose;
-    int mbits;
-    const uint32_t* pairs_v;   // sorted pair payloads (brick ids)
+    int Pb, V, H, W;     // poses in the launch (slots 0..Pb-1), views, image
+    int Vg, ngroups;     // view groups of the tile lists
+    uint32_t ncap;       // leaves per slot
     float lambda;
     const CamParams* cam;
     const Scratch* s;
-    // forward outputs (pose-offset applied by the caller)
+    // maps of the launch's first pose (pose offset applied by the caller)
     float* out_feat;
     float* out_alpha;
     float* out_tfinal;
-    // backward inputs / outputs
     const float* fwd_feat;
     const float* fwd_tfinal;
     const float* d_feat;
     const float* d_alpha;
     float* d_sigma;
     float* d_leaf_feat;
-    // debug outputs
     int max_hits;
+    int debug_view;
     int32_t* hit_leaf;
     double* hit_delta;
     int32_t* hit_count;

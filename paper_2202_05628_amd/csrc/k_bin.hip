@@ -185,46 +185,47 @@ __global__ void k_bin_items(PoseCounters* __restrict__ cnt, uint32_t Vg) {
     cnt->pad[1] = cnt->nb * Vg;
 }
 
-// count -> scan -> emit -> stable sort -> per-tile ranges.  On return
-// *pairs_k / *pairs_v point at the sorted pairs.
-hipError_t launch_bin(Scratch& s, const CamParams* cam_dev, int v0, int Vg, int H, int W, int depth,
-                      bool fp32, hipStream_t st, int* launches, int* mbits_out,
-                      const uint32_t** pairs_v) {
+// count -> scan -> emit -> stable sort -> per-tile ranges.  The sorted brick
+// ids end in pair_out; the sort ping-pongs between the scratch buffer and
+// pair_out so that its last pass writes pair_out.
+hipError_t launch_bin(Scratch& s, const CamParams* cam_dev, const uint32_t* brick_key, int v0, int Vg,
+                      int H, int W, int depth, bool fp32, uint32_t* pair_out, uint32_t* tile_start,
+                      uint32_t* tile_end, hipStream_t st, int* launches) {
     BinGeom g = make_geom(s, v0, Vg, H, W, depth);
     const int key_bits = bits_for((uint64_t)Vg * g.TPV - 1) + g.mbits;
-    *mbits_out = g.mbits;
+    const int passes = (key_bits + 7) / 8;
     PoseCounters* cnt = s.counters.as<PoseCounters>();
     hipLaunchKernelGGL(k_bin_items, dim3(1), dim3(1), 0, st, cnt, (uint32_t)Vg);
-    hipLaunchKernelGGL(k_bin_count, dim3(2048), dim3(256), 0, st, cam_dev, s.brick_key.as<uint32_t>(),
+    hipLaunchKernelGGL(k_bin_count, dim3(2048), dim3(256), 0, st, cam_dev, brick_key,
                        (const PoseCounters*)cnt, g, s.bin_cnt.as<uint32_t>());
     *launches += 2;
     hipError_t e = launch_scan_exclusive(s.bin_cnt.as<uint32_t>(), s.bin_off.as<uint32_t>(),
                                          &cnt->pad[1], &cnt->npairs, s.blk0.as<uint32_t>(), st,
                                          launches);
     if (e != hipSuccess) return e;
+    // an even number of passes ends where it starts
+    uint32_t* v_first = (passes & 1) ? s.pv0.as<uint32_t>() : pair_out;
+    uint32_t* v_second = (passes & 1) ? pair_out : s.pv0.as<uint32_t>();
     if (fp32)
-        hipLaunchKernelGGL(k_bin_emit<float>, dim3(2048), dim3(256), 0, st, cam_dev,
-                           s.brick_key.as<uint32_t>(), cnt, g, s.bin_off.as<uint32_t>(),
-                           s.pk0.as<uint32_t>(), s.pv0.as<uint32_t>());
+        hipLaunchKernelGGL(k_bin_emit<float>, dim3(2048), dim3(256), 0, st, cam_dev, brick_key, cnt, g,
+                           s.bin_off.as<uint32_t>(), s.pk0.as<uint32_t>(), v_first);
     else
-        hipLaunchKernelGGL(k_bin_emit<double>, dim3(2048), dim3(256), 0, st, cam_dev,
-                           s.brick_key.as<uint32_t>(), cnt, g, s.bin_off.as<uint32_t>(),
-                           s.pk0.as<uint32_t>(), s.pv0.as<uint32_t>());
+        hipLaunchKernelGGL(k_bin_emit<double>, dim3(2048), dim3(256), 0, st, cam_dev, brick_key, cnt, g,
+                           s.bin_off.as<uint32_t>(), s.pk0.as<uint32_t>(), v_first);
     *launches += 1;
     bool in1 = false;
-    e = launch_radix_sort(s.pk0.as<uint32_t>(), s.pv0.as<uint32_t>(), s.pk1.as<uint32_t>(),
-                          s.pv1.as<uint32_t>(), &cnt->pad[0], (uint32_t)s.pair_cap, key_bits,
-                          s.hist.as<uint32_t>(), s.digit_tot.as<uint32_t>(), st, &in1, launches);
+    e = launch_radix_sort(s.pk0.as<uint32_t>(), v_first, s.pk1.as<uint32_t>(), v_second, &cnt->pad[0],
+                          (uint32_t)s.pair_cap, key_bits, s.hist.as<uint32_t>(),
+                          s.digit_tot.as<uint32_t>(), st, &in1, launches);
     if (e != hipSuccess) return e;
     const uint32_t* pk = in1 ? s.pk1.as<uint32_t>() : s.pk0.as<uint32_t>();
-    *pairs_v = in1 ? s.pv1.as<uint32_t>() : s.pv0.as<uint32_t>();
     const size_t tiles = (size_t)Vg * g.TPV;
-    e = launch_fill_u32(s.tile_start.as<uint32_t>(), 0u, tiles, st);
+    e = launch_fill_u32(tile_start, 0u, tiles, st);
     if (e != hipSuccess) return e;
-    e = launch_fill_u32(s.tile_end.as<uint32_t>(), 0u, tiles, st);
+    e = launch_fill_u32(tile_end, 0u, tiles, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_tile_mark, dim3(2048), dim3(256), 0, st, pk, (const PoseCounters*)cnt,
-                       g.mbits, s.tile_start.as<uint32_t>(), s.tile_end.as<uint32_t>());
+    hipLaunchKernelGGL(k_tile_mark, dim3(2048), dim3(256), 0, st, pk, (const PoseCounters*)cnt, g.mbits,
+                       tile_start, tile_end);
     *launches += 3;
     return hipGetLastError();
 }

@@ -155,45 +155,44 @@ __global__ __launch_bounds__(kUThreads) void k_unique_write(
 
 template <int ROW_BYTES, int SIG_BYTES>
 static void launch_write(const uint32_t* skeys, const uint32_t* svals, uint32_t n, Scratch& s,
-                         const void* sigma, const void* feat, hipStream_t st) {
+                         const OctreeSlot& o, const void* sigma, const void* feat, hipStream_t st) {
     hipLaunchKernelGGL((k_unique_write<ROW_BYTES, SIG_BYTES>), dim3(kUniqueBlocks), dim3(kUThreads),
-                       0, st, skeys, svals, n, s.blk0.as<uint32_t>(), s.blk1.as<uint32_t>(),
-                       s.occ_key.as<uint32_t>(), s.occ_win.as<uint32_t>(),
-                       s.brick_key.as<uint32_t>(), s.brick_row.as<uint32_t>(),
-                       s.brick_mask.as<uint32_t>(), static_cast<const uint8_t*>(sigma),
-                       static_cast<const uint8_t*>(feat), s.flut_sig.as<uint8_t>(),
-                       s.flut_feat.as<uint8_t>());
+                       0, st, skeys, svals, n, s.blk0.as<uint32_t>(), s.blk1.as<uint32_t>(), o.occ_key,
+                       o.occ_win, o.brick_key, o.brick_row, o.brick_mask,
+                       static_cast<const uint8_t*>(sigma), static_cast<const uint8_t*>(feat),
+                       static_cast<uint8_t*>(o.psig), static_cast<uint8_t*>(o.pfeat));
 }
 
 hipError_t launch_build_octree(const uint32_t* skeys, const uint32_t* svals, uint32_t n, int C,
                                int storage, const void* sigma, const void* feat, Scratch& s,
-                               hipStream_t st, int* launches) {
+                               const OctreeSlot& o, hipStream_t st, int* launches) {
     PoseCounters* cnt = s.counters.as<PoseCounters>();
     hipLaunchKernelGGL(k_unique_count, dim3(kUniqueBlocks), dim3(kUThreads), 0, st, skeys, n,
                        s.blk0.as<uint32_t>(), s.blk1.as<uint32_t>(), cnt);
     hipLaunchKernelGGL(k_unique_scan, dim3(1), dim3(1024), 0, st, s.blk0.as<uint32_t>(),
-                       s.blk1.as<uint32_t>(), kUniqueBlocks, cnt, s.brick_row.as<uint32_t>());
-    hipLaunchKernelGGL(k_zero_masks, dim3(1024), dim3(256), 0, st, s.brick_mask.as<uint32_t>(),
+                       s.blk1.as<uint32_t>(), kUniqueBlocks, cnt, o.brick_row);
+    hipLaunchKernelGGL(k_zero_masks, dim3(1024), dim3(256), 0, st, o.brick_mask,
                        (const PoseCounters*)cnt);
     *launches += 4;
     const int es = storage == ART_BF16 ? 2 : 4;
     switch (C * es) {
-        case 8: launch_write<8, 2>(skeys, svals, n, s, sigma, feat, st); break;     // C=4 bf16
+        case 8: launch_write<8, 2>(skeys, svals, n, s, o, sigma, feat, st); break;     // C=4 bf16
         case 16:
-            if (es == 4) launch_write<16, 4>(skeys, svals, n, s, sigma, feat, st);  // C=4 f32
-            else launch_write<16, 2>(skeys, svals, n, s, sigma, feat, st);          // C=8 bf16
+            if (es == 4) launch_write<16, 4>(skeys, svals, n, s, o, sigma, feat, st);  // C=4 f32
+            else launch_write<16, 2>(skeys, svals, n, s, o, sigma, feat, st);          // C=8 bf16
             break;
         case 32:
-            if (es == 4) launch_write<32, 4>(skeys, svals, n, s, sigma, feat, st);
-            else launch_write<32, 2>(skeys, svals, n, s, sigma, feat, st);
+            if (es == 4) launch_write<32, 4>(skeys, svals, n, s, o, sigma, feat, st);
+            else launch_write<32, 2>(skeys, svals, n, s, o, sigma, feat, st);
             break;
         case 64:
-            if (es == 4) launch_write<64, 4>(skeys, svals, n, s, sigma, feat, st);
-            else launch_write<64, 2>(skeys, svals, n, s, sigma, feat, st);
+            if (es == 4) launch_write<64, 4>(skeys, svals, n, s, o, sigma, feat, st);
+            else launch_write<64, 2>(skeys, svals, n, s, o, sigma, feat, st);
             break;
-        case 128: launch_write<128, 4>(skeys, svals, n, s, sigma, feat, st); break;  // C=32 f32
+        case 128: launch_write<128, 4>(skeys, svals, n, s, o, sigma, feat, st); break;  // C=32 f32
         default: return hipErrorInvalidValue;
     }
+    *launches += 1;
     return hipGetLastError();
 }
 

@@ -33,22 +33,26 @@ constexpr int kStage = 64;
 
 struct RArgs {
     const CamParams* cam;
-    int v0, Vg, V, H, W, TX, TY, TPV, depth;
+    int Pb, V, H, W, TX, TY, TPV, depth;   // poses in this launch, views, image, tiles
+    int Vg, ngroups;                       // view groups of the tile lists
     int n_wg, wg_x, wg_per_view;
+    uint32_t ncap;                         // per-pose capacity of the octree arrays (leaves)
+    uint32_t pair_cap;                     // per (pose, group) capacity of the tile lists
     float lambda;
-    const uint32_t* tile_start;
+    const uint32_t* tile_start;            // [Pb][V][TPV], relative to the (pose, group) list
     const uint32_t* tile_end;
-    const uint32_t* pair_v;
-    const uint32_t* brick_key;
-    const uint32_t* brick_row;
-    const uint32_t* brick_mask;
-    const uint32_t* occ_win;
-    const void* psig;
-    const void* pfeat;
-    // every per-view array below starts at the group's first view v0
-    float* out_feat;      // [Vg][C][H][W]
-    float* out_alpha;     // [Vg][H][W]
-    float* out_tfinal;    // [Vg][H][W] or null
+    const uint32_t* pair_v;                // [Pb][ngroups][pair_cap] brick ids
+    const uint32_t* ovf;                   // [Pb][ngroups][2] overflow flag, pair count
+    const uint32_t* brick_key;             // [Pb][ncap]
+    const uint32_t* brick_row;             // [Pb][ncap + 1]
+    const uint32_t* brick_mask;            // [Pb][ncap][16]
+    const uint32_t* occ_win;               // [Pb][ncap]
+    const void* psig;                      // [Pb][ncap] posed-order densities
+    const void* pfeat;                     // [Pb][ncap][C] posed-order features
+    // maps of the launch's poses: [Pb][V][C][H][W] / [Pb][V][H][W]
+    float* out_feat;
+    float* out_alpha;
+    float* out_tfinal;
     const float* fwd_feat;
     const float* fwd_tfinal;
     const float* d_feat;
@@ -56,11 +60,11 @@ struct RArgs {
     float* d_sigma;
     float* d_leaf_feat;
     int max_hits;
-    int32_t* hit_leaf;
+    int debug_view;                        // view whose hit lists are recorded (MODE 2)
+    int32_t* hit_leaf;                     // [H*W][max_hits] (single pose / view)
     double* hit_delta;
     int32_t* hit_count;
-    unsigned long long* stats;   // RunStats
-    const PoseCounters* counters;
+    unsigned long long* stats;             // RunStats
 };
 
 template <int C, int ST>
@@ -107,14 +111,37 @@ __device__ inline uint32_t spread3_small(uint32_t v) {   // 3-bit x -> bits 0, 3
     return (v & 1u) | ((v & 2u) << 2) | ((v & 4u) << 4);
 }
 
+// Ray parameter of lattice plane k on one axis: (-1 + k h - o) / d, written with
+// q = 1 + o and the reciprocal of d.
 template <typename R>
 __device__ inline R tplane(int k, R h, R q, R inv) {
     return ((R)k * h - q) * inv;
 }
 
+// Positive-length overlap [t0, t1] of the clipped ray with brick b3.
+template <typename R>
+__device__ inline bool brick_overlap(const int* b3, const R* d, const R* q, const R* inv,
+                                     const int* c0, R h, R ta, R tb, R& t0, R& t1) {
+    t0 = ta;
+    t1 = tb;
+    bool ok = true;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        if (d[i] == (R)0) {
+            ok = ok && ((c0[i] >> 3) == b3[i]);
+        } else {
+            const R u0 = tplane<R>(8 * b3[i], h, q[i], inv[i]);
+            const R u1 = tplane<R>(8 * b3[i] + 8, h, q[i], inv[i]);
+            t0 = fmax(t0, fmin(u0, u1));
+            t1 = fmin(t1, fmax(u0, u1));
+        }
+    }
+    return ok && (t1 > t0);
+}
+
 // MODE: 0 forward, 1 adjoint, 2 forward recording hit lists
 template <int C, int ST, typename R, int MODE>
-__global__ __launch_bounds__(256) void k_render(RArgs a) {
+__global__ __launch_bounds__(256, MODE == 1 ? 3 : 4) void k_render(RArgs a) {
     __shared__ uint32_t s_mask[4][16][kStage];
     __shared__ uint16_t s_pref[4][16][kStage];
     __shared__ uint32_t s_row[4][kStage];
@@ -123,16 +150,21 @@ __global__ __launch_bounds__(256) void k_render(RArgs a) {
     const int wv = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
 
-    // XCD-aware workgroup remap
+    // XCD-aware workgroup remap: runs of kXcdChunk consecutive workgroups share an XCD
     const uint32_t hw = blockIdx.x;
     const uint32_t xcd = hw & 7u;
     const uint32_t kk = hw >> 3;
     const uint32_t wg = ((kk / kXcdChunk) * 8u + xcd) * kXcdChunk + (kk % kXcdChunk);
     if (wg >= (uint32_t)a.n_wg) return;
-    // the tile lists of this group overflowed their buffer: the host re-runs it
-    if (a.counters->overflow) return;
 
-    const int vv = (int)(wg / (uint32_t)a.wg_per_view);
+    const int pvi = (int)(wg / (uint32_t)a.wg_per_view);   // pose-in-launch * V + view
+    const int pb = pvi / a.V;
+    const int v = pvi % a.V;
+    if (MODE == 2 && v != a.debug_view) return;
+    const int grp = v / a.Vg;
+    const size_t slot_pg = (size_t)pb * a.ngroups + grp;
+    // the tile lists of this (pose, view group) overflowed their buffer: re-run by the host
+    if (a.ovf[2 * slot_pg]) return;
     const int rem = (int)(wg % (uint32_t)a.wg_per_view);
     const int ty = 2 * (rem / a.wg_x) + (wv >> 1);
     const int tx = 2 * (rem % a.wg_x) + (wv & 1);
@@ -140,21 +172,28 @@ __global__ __launch_bounds__(256) void k_render(RArgs a) {
     const int px = tx * 8 + (lane & 7);
     const int py = ty * 8 + (lane >> 3);
     const bool pix_ok = tile_ok && px < a.W && py < a.H;
-    const int v = a.v0 + vv;
 
     uint32_t ls = 0, le = 0;
     if (tile_ok) {
-        const int tile = vv * a.TPV + ty * a.TX + tx;
+        const size_t tile = (size_t)pvi * a.TPV + (size_t)ty * a.TX + tx;
         ls = a.tile_start[tile];
         le = a.tile_end[tile];
     }
+    const uint32_t* pair_v = a.pair_v + slot_pg * a.pair_cap;
+    const uint32_t* brick_key = a.brick_key + (size_t)pb * a.ncap;
+    const uint32_t* brick_row = a.brick_row + (size_t)pb * (a.ncap + 1);
+    const uint32_t* brick_mask = a.brick_mask + (size_t)pb * a.ncap * 16;
+    const uint32_t* occ_win = a.occ_win + (size_t)pb * a.ncap;
+    const size_t es = ST == 0 ? 4 : 2;
+    const void* psig = static_cast<const char*>(a.psig) + (size_t)pb * a.ncap * es;
+    const void* pfeat = static_cast<const char*>(a.pfeat) + (size_t)pb * a.ncap * C * es;
 
     // ---- ray r_p = (o, d) of pixel (px, py) -----------------------------------
     const CamParams& cam = a.cam[v];
     const R h = (R)1 / (R)(1 << a.depth);
     const R invh = (R)(1 << a.depth);
     const int G = 2 << a.depth;
-    R o[3], d[3], q[3], inv[3];
+    R d[3], q[3], inv[3];
     {
         const R dcx = ((R)px + (R)0.5 - (R)cam.cx) / (R)cam.fx;
         const R dcy = ((R)py + (R)0.5 - (R)cam.cy) / (R)cam.fy;
@@ -168,8 +207,7 @@ __global__ __launch_bounds__(256) void k_render(RArgs a) {
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
             d[i] = d[i] / nrm;
-            o[i] = (R)cam.t[i];
-            q[i] = (R)1 + o[i];
+            q[i] = (R)1 + (R)cam.t[i];
             inv[i] = d[i] != (R)0 ? (R)1 / d[i] : (R)0;
         }
     }
@@ -201,6 +239,7 @@ __global__ __launch_bounds__(256) void k_render(RArgs a) {
     int nsamp = 0;
     const size_t pix = (size_t)py * a.W + px;
     const size_t HW = (size_t)a.H * a.W;
+    const size_t map = (size_t)pvi;   // (pose-in-launch, view) map index
     // adjoint state
     float g[C], Ff[C], P[C];
     float gA = 0.0f, Tfin = 0.0f;
@@ -214,35 +253,37 @@ __global__ __launch_bounds__(256) void k_render(RArgs a) {
         if (active) {
 #pragma unroll
             for (int c = 0; c < C; ++c) {
-                g[c] = a.d_feat[((size_t)vv * C + c) * HW + pix];
-                Ff[c] = a.fwd_feat[((size_t)vv * C + c) * HW + pix];
+                g[c] = a.d_feat[(map * C + c) * HW + pix];
+                Ff[c] = a.fwd_feat[(map * C + c) * HW + pix];
             }
-            gA = a.d_alpha ? a.d_alpha[(size_t)vv * HW + pix] : 0.0f;
-            Tfin = a.fwd_tfinal[(size_t)vv * HW + pix];
+            gA = a.d_alpha ? a.d_alpha[map * HW + pix] : 0.0f;
+            Tfin = a.fwd_tfinal[map * HW + pix];
         }
     }
-    const size_t hit_base = (size_t)((size_t)vv * HW + pix) * (size_t)(MODE == 2 ? a.max_hits : 0);
+    const size_t hit_base = pix * (size_t)(MODE == 2 ? a.max_hits : 0);
 
-    // ---- traversal state --------------------------------------------------------
+    // ---- traversal state (current brick) ----------------------------------------
     bool inb = false;
     R s = 0, t1 = 0;
     R tc[3];
-    int kp[3];
-    int bxyz[3] = {0, 0, 0};
+    int kp[3];          // index of the next lattice plane crossed on each axis
+    int cl[3];          // lattice coordinate of the current cell (brick local after entry)
     int slot = 0;
-    int steps = 0;
+    int bsteps = 0;
+    uint32_t row_base = 0;
 
+    uint32_t rounds = 0;   // wave-uniform traversal rounds (diagnostic)
     for (uint32_t base = ls; base < le; base += kStage) {
         if (__ballot(active) == 0ull) break;
-        // stage up to 64 bricks of the tile's list
+        // stage up to 64 bricks of the tile's front-to-back list
         {
             const uint32_t e = base + (uint32_t)lane;
             if (e < le) {
-                const uint32_t b = a.pair_v[e];
-                const uint32_t bk = a.brick_key[b];
+                const uint32_t b = pair_v[e];
+                const uint32_t bk = brick_key[b];
                 s_coord[wv][lane] = compact3(bk) | (compact3(bk >> 1) << 10) | (compact3(bk >> 2) << 20);
-                s_row[wv][lane] = a.brick_row[b];
-                const uint4* mp = reinterpret_cast<const uint4*>(a.brick_mask + (size_t)b * 16);
+                s_row[wv][lane] = brick_row[b];
+                const uint4* mp = reinterpret_cast<const uint4*>(brick_mask + (size_t)b * 16);
                 uint32_t run = 0;
 #pragma unroll
                 for (int qd = 0; qd < 4; ++qd) {
@@ -259,131 +300,151 @@ __global__ __launch_bounds__(256) void k_render(RArgs a) {
         }
         wave_sync();
         const int nchunk = (int)((le - base) < (uint32_t)kStage ? (le - base) : (uint32_t)kStage);
-        int cur = 0;
-        while (true) {
-            // a lane outside a brick slab-tests its next staged brick
-            if (active && !inb && cur < nchunk) {
-                const uint32_t cc = s_coord[wv][cur];
+        // phase 1: which staged bricks does this lane's ray cross (positive length)?
+        uint64_t todo = 0;
+        if (active) {
+            for (int j = 0; j < nchunk; ++j) {
+                const uint32_t cc = s_coord[wv][j];
                 const int b3[3] = {(int)(cc & 1023u), (int)((cc >> 10) & 1023u), (int)(cc >> 20)};
-                R t0 = ta, tt1 = tb;
-                bool ok = true;
+                R u0, u1;
+                if (brick_overlap<R>(b3, d, q, inv, c0, h, ta, tb, u0, u1)) todo |= 1ull << j;
+            }
+        }
+        // phase 2: walk the crossed bricks in list order.  Software pipeline of
+        // depth one: each round advances the ray to its next occupied segment
+        // while the current sample's gather is in flight, composites the current
+        // sample, then issues the next sample's gather into the same registers.
+        bool hasA = false;
+        uint32_t rowA = 0;
+        float dlA = 0.0f;
+        double dxA = 0.0;
+        float sgA = 0.0f;
+        float fA[C];
 #pragma unroll
-                for (int i = 0; i < 3; ++i) {
-                    if (d[i] == (R)0) {
-                        ok = ok && ((c0[i] >> 3) == b3[i]);
-                    } else {
-                        const R u0 = tplane<R>(8 * b3[i], h, q[i], inv[i]);
-                        const R u1 = tplane<R>(8 * b3[i] + 8, h, q[i], inv[i]);
-                        t0 = fmax(t0, fmin(u0, u1));
-                        tt1 = fmin(tt1, fmax(u0, u1));
-                    }
-                }
-                if (ok && tt1 > t0) {
+        for (int c = 0; c < C; ++c) fA[c] = 0.0f;
+        while (true) {
+            const bool more = active && (inb || todo != 0ull);
+            if (__ballot(more || hasA) == 0ull) break;
+            ++rounds;
+            // (1) next occupied segment of this lane's ray (overlaps the gather of A)
+            bool hasB = false;
+            uint32_t rowB = 0;
+            float dlB = 0.0f;
+            double dxB = 0.0;
+            int guard = 0;
+            while (active && !hasB && (inb || todo != 0ull) && guard < 64) {
+                ++guard;
+                if (!inb) {
+                    slot = __ffsll((unsigned long long)todo) - 1;
+                    todo &= todo - 1ull;
+                    const uint32_t cc = s_coord[wv][slot];
+                    const int b3[3] = {(int)(cc & 1023u), (int)((cc >> 10) & 1023u), (int)(cc >> 20)};
+                    R t0;
+                    if (!brick_overlap<R>(b3, d, q, inv, c0, h, ta, tb, t0, t1)) continue;
                     inb = true;
-                    slot = cur;
+                    bsteps = 0;
                     s = t0;
-                    t1 = tt1;
-                    steps = 0;
+                    row_base = s_row[wv][slot];
 #pragma unroll
                     for (int i = 0; i < 3; ++i) {
-                        bxyz[i] = b3[i];
+                        const int lo = 8 * b3[i];
                         if (d[i] == (R)0) {
                             tc[i] = (R)INFINITY;
                             kp[i] = 0;
+                            cl[i] = c0[i] - lo;
                             continue;
                         }
-                        const int lo = 8 * b3[i];
                         const R u = (q[i] + t0 * d[i]) * invh;
                         int k;
                         if (d[i] > (R)0) {
                             k = (int)floor(u) + 1;
                             k = k < lo + 1 ? lo + 1 : (k > lo + 8 ? lo + 8 : k);
-                            while (k > lo + 1 && tplane<R>(k - 1, h, q[i], inv[i]) > t0) --k;
-                            while (k < lo + 8 && tplane<R>(k, h, q[i], inv[i]) <= t0) ++k;
+                            // u carries rounding far below one cell: one correction each way
+                            if (k > lo + 1 && tplane<R>(k - 1, h, q[i], inv[i]) > t0) --k;
+                            if (k < lo + 8 && tplane<R>(k, h, q[i], inv[i]) <= t0) ++k;
+                            cl[i] = k - 1 - lo;
                         } else {
                             k = (int)ceil(u) - 1;
                             k = k < lo ? lo : (k > lo + 7 ? lo + 7 : k);
-                            while (k < lo + 7 && tplane<R>(k + 1, h, q[i], inv[i]) > t0) ++k;
-                            while (k > lo && tplane<R>(k, h, q[i], inv[i]) <= t0) --k;
+                            if (k < lo + 7 && tplane<R>(k + 1, h, q[i], inv[i]) > t0) ++k;
+                            if (k > lo && tplane<R>(k, h, q[i], inv[i]) <= t0) --k;
+                            cl[i] = k - lo;
                         }
                         kp[i] = k;
                         tc[i] = tplane<R>(k, h, q[i], inv[i]);
                     }
                 }
-                ++cur;
-            }
-            const bool busy = active && (inb || cur < nchunk);
-            if (__ballot(busy) == 0ull) break;
-            if (active && inb) {
-                // one segment of the exact partition
+                // one segment of the exact partition: (s, s1) in cell cl
                 R s1 = fmin(fmin(tc[0], tc[1]), fmin(tc[2], t1));
                 s1 = fmax(s1, s);
-                if (s1 > s) {
-                    const R mid = (s + s1) * (R)0.5;
-                    int l[3];
-#pragma unroll
-                    for (int i = 0; i < 3; ++i) {
-                        const int c = d[i] == (R)0 ? c0[i] : (int)floor((q[i] + mid * d[i]) * invh);
-                        l[i] = c - 8 * bxyz[i];
-                    }
-                    if ((unsigned)l[0] < 8u && (unsigned)l[1] < 8u && (unsigned)l[2] < 8u) {
-                        const uint32_t m9 = spread3_small((uint32_t)l[0]) |
-                                            (spread3_small((uint32_t)l[1]) << 1) |
-                                            (spread3_small((uint32_t)l[2]) << 2);
-                        const uint32_t wd = m9 >> 5, bit = m9 & 31u;
-                        const uint32_t mw = s_mask[wv][wd][slot];
-                        if ((mw >> bit) & 1u) {
-                            const uint32_t row = s_row[wv][slot] + s_pref[wv][wd][slot] +
-                                                 (uint32_t)__popc(mw & ((1u << bit) - 1u));
-                            const float dl = (float)(s1 - s);
-                            float sg;
-                            float f[C];
-                            load_sample<C, ST>(a.psig, a.pfeat, row, sg, f);
-                            const float tau = sg * dl;
-                            const float al = -expm1f(-tau);
-                            const float w = T * al;
-                            const float Tn = __fmaf_rn(-T, al, T);
-                            if constexpr (MODE == 1) {
-#pragma unroll
-                                for (int c = 0; c < C; ++c) P[c] = __fmaf_rn(w, f[c], P[c]);
-                                float acc = 0.0f;
-#pragma unroll
-                                for (int c = 0; c < C; ++c) acc += g[c] * (Tn * f[c] - (Ff[c] - P[c]));
-                                const float ds = dl * (acc + gA * Tfin);
-                                const uint32_t leaf = a.occ_win[row];
-                                unsafeAtomicAdd(&a.d_sigma[leaf], ds);
-#pragma unroll
-                                for (int c = 0; c < C; ++c)
-                                    unsafeAtomicAdd(&a.d_leaf_feat[(size_t)leaf * C + c], w * g[c]);
-                            } else {
-#pragma unroll
-                                for (int c = 0; c < C; ++c) F[c] = __fmaf_rn(w, f[c], F[c]);
-                                Aacc += w;
-                                if constexpr (MODE == 2) {
-                                    if (nsamp < a.max_hits) {
-                                        a.hit_leaf[hit_base + nsamp] = (int32_t)a.occ_win[row];
-                                        a.hit_delta[hit_base + nsamp] = (double)(s1 - s);
-                                    }
-                                }
-                            }
-                            T = Tn;
-                            ++nsamp;
-                            if (T < a.lambda) {
-                                active = false;
-                                inb = false;
-                            }
-                        }
+                if (s1 > s && (unsigned)cl[0] < 8u && (unsigned)cl[1] < 8u && (unsigned)cl[2] < 8u) {
+                    const uint32_t m9 = spread3_small((uint32_t)cl[0]) | (spread3_small((uint32_t)cl[1]) << 1) |
+                                        (spread3_small((uint32_t)cl[2]) << 2);
+                    const uint32_t wd = m9 >> 5, bit = m9 & 31u;
+                    const uint32_t mw = s_mask[wv][wd][slot];
+                    if ((mw >> bit) & 1u) {
+                        rowB = row_base + s_pref[wv][wd][slot] + (uint32_t)__popc(mw & ((1u << bit) - 1u));
+                        dlB = (float)(s1 - s);
+                        if constexpr (MODE == 2) dxB = (double)(s1 - s);
+                        hasB = true;
                     }
                 }
 #pragma unroll
                 for (int i = 0; i < 3; ++i) {
                     if (tc[i] <= s1) {
-                        kp[i] += d[i] > (R)0 ? 1 : -1;
+                        const int st = d[i] > (R)0 ? 1 : -1;
+                        kp[i] += st;
+                        cl[i] += st;
                         tc[i] = tplane<R>(kp[i], h, q[i], inv[i]);
                     }
                 }
                 s = s1;
-                if (s >= t1 || ++steps > 40) inb = false;
+                // a brick holds at most 3 * 8 plane crossings; the cap only guards
+                // against non-finite input
+                if (s >= t1 || ++bsteps > 32) inb = false;
+            }
+            // (2) composite the current sample (Eq. 5-6, exclusive transmittance)
+            if (hasA && active) {
+                const float tau = sgA * dlA;
+                const float al = -expm1f(-tau);
+                const float w = T * al;
+                const float Tn = __fmaf_rn(-T, al, T);
+                if constexpr (MODE == 1) {
+#pragma unroll
+                    for (int c = 0; c < C; ++c) P[c] = __fmaf_rn(w, fA[c], P[c]);
+                    float acc = 0.0f;
+#pragma unroll
+                    for (int c = 0; c < C; ++c) acc += g[c] * (Tn * fA[c] - (Ff[c] - P[c]));
+                    const float ds = dlA * (acc + gA * Tfin);
+                    const uint32_t leaf = occ_win[rowA];
+                    unsafeAtomicAdd(&a.d_sigma[leaf], ds);
+#pragma unroll
+                    for (int c = 0; c < C; ++c) unsafeAtomicAdd(&a.d_leaf_feat[(size_t)leaf * C + c], w * g[c]);
+                } else {
+#pragma unroll
+                    for (int c = 0; c < C; ++c) F[c] = __fmaf_rn(w, fA[c], F[c]);
+                    Aacc += w;
+                    if constexpr (MODE == 2) {
+                        if (nsamp < a.max_hits) {
+                            a.hit_leaf[hit_base + nsamp] = (int32_t)occ_win[rowA];
+                            a.hit_delta[hit_base + nsamp] = dxA;
+                        }
+                    }
+                }
+                T = Tn;
+                ++nsamp;
+                if (T < a.lambda) {
+                    active = false;
+                    inb = false;
+                }
+            }
+            // (3) issue the next sample's gather into the freed registers
+            hasA = hasB && active;
+            if (hasA) {
+                rowA = rowB;
+                dlA = dlB;
+                dxA = dxB;
+                load_sample<C, ST>(psig, pfeat, rowA, sgA, fA);
             }
         }
         wave_sync();
@@ -393,10 +454,10 @@ __global__ __launch_bounds__(256) void k_render(RArgs a) {
     if constexpr (MODE != 1) {
         if (pix_ok) {
 #pragma unroll
-            for (int c = 0; c < C; ++c) a.out_feat[((size_t)vv * C + c) * HW + pix] = F[c];
-            a.out_alpha[(size_t)vv * HW + pix] = Aacc;
-            if (a.out_tfinal) a.out_tfinal[(size_t)vv * HW + pix] = T;
-            if constexpr (MODE == 2) a.hit_count[(size_t)vv * HW + pix] = nsamp;
+            for (int c = 0; c < C; ++c) a.out_feat[(map * C + c) * HW + pix] = F[c];
+            a.out_alpha[map * HW + pix] = Aacc;
+            if (a.out_tfinal) a.out_tfinal[map * HW + pix] = T;
+            if constexpr (MODE == 2) a.hit_count[pix] = nsamp;
         }
     }
     if (a.stats) {
@@ -407,6 +468,8 @@ __global__ __launch_bounds__(256) void k_render(RArgs a) {
             atomicAdd(&a.stats[0], (unsigned long long)__popcll(rays));
             atomicAdd(&a.stats[1], ns);
             atomicAdd(&a.stats[2], (unsigned long long)__popcll(hits));
+            atomicAdd(&a.stats[7], (unsigned long long)(le - ls));
+            atomicAdd(&a.stats[8], (unsigned long long)rounds);
         }
     }
 }
