@@ -190,6 +190,7 @@ def main():
         "bricks_per_pose": st["bricks"] // P,
         "tile_list_entries_per_pose": st["list_entries"] // P,
         "traversal_rounds_per_pose": st["rounds"] // P,
+        "partition_steps_per_pose": st["steps"] // P,
         "launches_per_step": st["launches"],
     }
     if not args.no_cpu_baseline:

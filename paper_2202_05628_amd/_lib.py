@@ -9,7 +9,8 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libartemis.so")
+# ARTEMIS_LIB selects another build of the library (e.g. a tuning variant)
+LIB_PATH = os.environ.get("ARTEMIS_LIB") or os.path.join(HERE, "libartemis.so")
 
 ART_OK, ART_EINVAL, ART_ENOMEM, ART_EDEVICE, ART_ESTATE, ART_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 ART_F32, ART_BF16 = 0, 1

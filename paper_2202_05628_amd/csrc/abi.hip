@@ -328,6 +328,8 @@ art_status run_batch(art_ctx* ctx, const CallPlan& pl, int mode, float lambda, c
     r.lambda = lambda;
     r.cam = ctx->cam.as<CamParams>();
     r.s = &ctx->s;
+    r.sigma = sigma;
+    r.feat = feat;
     const size_t HW = (size_t)ctx->H * ctx->W;
     const size_t m0 = o.single_pose ? 0 : (size_t)p0 * ctx->V;   // first map of the batch
     if (o.out_feat) r.out_feat = o.out_feat + m0 * pl.C * HW;
@@ -416,6 +418,7 @@ art_status render_call(art_ctx* ctx, int C, art_dtype dtype, const void* sigma, 
     ctx->stats[7] = launches;
     ctx->stats[8] = (int64_t)hst[7];
     ctx->stats[9] = (int64_t)hst[8];
+    ctx->stats[10] = (int64_t)hst[9];
     tm.finish(ctx);
     return ART_OK;
 }
@@ -440,10 +443,10 @@ hipError_t launch_render(const RenderLaunch& r, hipStream_t st) {
     a.depth = r.depth;
     a.Vg = r.Vg;
     a.ngroups = r.ngroups;
-    a.wg_x = (a.TX + 1) / 2;
-    const int wg_y = (a.TY + 1) / 2;
-    a.wg_per_view = a.wg_x * wg_y;
-    a.n_wg = a.wg_per_view * r.V * r.Pb;
+    int side = 1;
+    while (side < a.TX || side < a.TY) side <<= 1;
+    a.tiles_pow4 = side * side;   // Morton tile slots per view (slots outside the image exit)
+    a.n_wg = a.tiles_pow4 * r.V * r.Pb;
     a.ncap = r.ncap;
     a.pair_cap = (uint32_t)s.pair_cap;
     a.lambda = r.lambda;
@@ -457,6 +460,8 @@ hipError_t launch_render(const RenderLaunch& r, hipStream_t st) {
     a.occ_win = s.occ_win.as<uint32_t>();
     a.psig = s.flut_sig.p;
     a.pfeat = s.flut_feat.p;
+    a.csig = r.sigma;
+    a.cfeat = r.feat;
     a.out_feat = r.out_feat;
     a.out_alpha = r.out_alpha;
     a.out_tfinal = r.out_tfinal;

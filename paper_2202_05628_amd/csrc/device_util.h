@@ -28,6 +28,14 @@ __host__ __device__ inline uint32_t compact3(uint32_t v) {
     v = (v | (v >> 16)) & 0x000003FFu;
     return v;
 }
+__host__ __device__ inline uint32_t compact2(uint32_t v) {   // even bits -> low half
+    v &= 0x55555555u;
+    v = (v | (v >> 1)) & 0x33333333u;
+    v = (v | (v >> 2)) & 0x0F0F0F0Fu;
+    v = (v | (v >> 4)) & 0x00FF00FFu;
+    v = (v | (v >> 8)) & 0x0000FFFFu;
+    return v;
+}
 __host__ __device__ inline uint32_t morton3(uint32_t x, uint32_t y, uint32_t z) {
     return spread3(x) | (spread3(y) << 1) | (spread3(z) << 2);
 }

@@ -56,10 +56,11 @@ struct PoseCounters {
 
 // Run-wide statistics accumulated on the device.
 struct RunStats {
-    unsigned long long rays, samples, hit_rays, dropped, collisions, bricks, pairs, list_entries, rounds;
+    unsigned long long rays, samples, hit_rays, dropped, collisions, bricks, pairs, list_entries, rounds,
+        steps;
 };
 
-constexpr int kNumStats = 10;
+constexpr int kNumStats = 11;
 constexpr int kSortBlocks = 512;      // fixed grid of the radix-sort passes
 constexpr int kScanBlocks = 1024;     // fixed grid of device-sized scans
 constexpr int kUniqueBlocks = 1024;   // fixed grid of the unique / compaction step
@@ -169,6 +170,8 @@ struct RenderLaunch {
     float lambda;
     const CamParams* cam;
     const Scratch* s;
+    const void* sigma;   // canonical FLUT (device)
+    const void* feat;
     // maps of the launch's first pose (pose offset applied by the caller)
     float* out_feat;
     float* out_alpha;

@@ -6,7 +6,7 @@ namespace art {
 template <>
 hipError_t launch_render_c<4>(const RenderLaunch& r, const RArgs& a, unsigned grid, hipStream_t st) {
 #define ART_LAUNCH(ST, R, MODE) \
-    hipLaunchKernelGGL((k_render<4, ST, R, MODE>), dim3(grid), dim3(256), 0, st, a)
+    hipLaunchKernelGGL((k_render<4, ST, R, MODE>), dim3(grid), dim3(64), 0, st, a)
     const int st_ = r.storage == ART_BF16 ? 1 : 0;
     if (r.fp32) {
         if (st_ == 0) {

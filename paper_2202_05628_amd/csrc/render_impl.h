@@ -1,7 +1,8 @@
 // Ray indexing + front-to-back compositing (Section 3.1, "Dynamic Volume
 // Rendering", Eq. 5 and Eq. 6) and its adjoint.
 //
-// One wave64 owns one 8x8-pixel tile; a workgroup holds 2x2 tiles.  The
+// One wave64 owns one 8x8-pixel tile and is its own workgroup, so the LDS of
+// a finished tile is released at once whatever its neighbours still do.  The
 // tile's front-to-back brick list (see k_bin.hip) is streamed through LDS in
 // chunks of 64 bricks: each lane stages one brick (its 512-bit occupancy mask,
 // per-word prefix popcounts, first row and coordinates), then every lane walks
@@ -17,10 +18,11 @@
 // Geometry (ray parameter t, plane crossings, midpoint cells) runs in R =
 // double (default) or float (precision form); compositing is always FP32.
 //
-// Workgroups are remapped so that each XCD (workgroups are dispatched round
-// robin over the 8 XCDs) receives runs of kXcdChunk neighbouring workgroups,
-// keeping neighbouring tiles - which read the same bricks and FLUT rows - in
-// one XCD's L2.
+// Tiles are numbered in Morton order within a view, and workgroups are
+// remapped so that each XCD (workgroups are dispatched round robin over the 8
+// XCDs) receives runs of kXcdChunk consecutive tiles - a 4x4-tile block -
+// keeping neighbouring tiles, which read the same bricks and FLUT rows, in one
+// XCD's L2.
 #pragma once
 
 #include "device_util.h"
@@ -28,14 +30,26 @@
 
 namespace art {
 
-constexpr int kXcdChunk = 8;
+constexpr int kXcdChunk = 16;
 constexpr int kStage = 64;
+// Partition steps a lane may take per round while looking for its next
+// occupied segment.  Bounding it keeps one lane that crosses empty cells from
+// stalling the whole wave for many steps per composited sample.
+#ifndef ART_STEPS_PER_ROUND
+#define ART_STEPS_PER_ROUND 1
+#endif
+// 1: gather FLUT rows from the canonical arrays through the winner id instead
+// of the per-pose posed-order copies
+#ifndef ART_GATHER_CANONICAL
+#define ART_GATHER_CANONICAL 0
+#endif
+constexpr int kStepsPerRound = ART_STEPS_PER_ROUND;
 
 struct RArgs {
     const CamParams* cam;
     int Pb, V, H, W, TX, TY, TPV, depth;   // poses in this launch, views, image, tiles
     int Vg, ngroups;                       // view groups of the tile lists
-    int n_wg, wg_x, wg_per_view;
+    int n_wg, tiles_pow4;                  // workgroups, Morton tile slots per view
     uint32_t ncap;                         // per-pose capacity of the octree arrays (leaves)
     uint32_t pair_cap;                     // per (pose, group) capacity of the tile lists
     float lambda;
@@ -49,6 +63,8 @@ struct RArgs {
     const uint32_t* occ_win;               // [Pb][ncap]
     const void* psig;                      // [Pb][ncap] posed-order densities
     const void* pfeat;                     // [Pb][ncap][C] posed-order features
+    const void* csig;                      // [n] canonical densities
+    const void* cfeat;                     // [n][C] canonical features
     // maps of the launch's poses: [Pb][V][C][H][W] / [Pb][V][H][W]
     float* out_feat;
     float* out_alpha;
@@ -140,14 +156,18 @@ __device__ inline bool brick_overlap(const int* b3, const R* d, const R* q, cons
 }
 
 // MODE: 0 forward, 1 adjoint, 2 forward recording hit lists
+#ifndef ART_RENDER_WAVES_PER_EU
+#define ART_RENDER_WAVES_PER_EU 1
+#endif
 template <int C, int ST, typename R, int MODE>
-__global__ __launch_bounds__(256, MODE == 1 ? 3 : 4) void k_render(RArgs a) {
-    __shared__ uint32_t s_mask[4][16][kStage];
-    __shared__ uint16_t s_pref[4][16][kStage];
-    __shared__ uint32_t s_row[4][kStage];
-    __shared__ uint32_t s_coord[4][kStage];
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MODE == 1 ? 1 : ART_RENDER_WAVES_PER_EU)))
+void k_render(RArgs a) {
+    __shared__ uint32_t s_mask[1][16][kStage];
+    __shared__ uint16_t s_pref[1][16][kStage];
+    __shared__ uint32_t s_row[1][kStage];
+    __shared__ uint32_t s_coord[1][kStage];
 
-    const int wv = threadIdx.x >> 6;
+    constexpr int wv = 0;
     const int lane = threadIdx.x & 63;
 
     // XCD-aware workgroup remap: runs of kXcdChunk consecutive workgroups share an XCD
@@ -157,7 +177,7 @@ __global__ __launch_bounds__(256, MODE == 1 ? 3 : 4) void k_render(RArgs a) {
     const uint32_t wg = ((kk / kXcdChunk) * 8u + xcd) * kXcdChunk + (kk % kXcdChunk);
     if (wg >= (uint32_t)a.n_wg) return;
 
-    const int pvi = (int)(wg / (uint32_t)a.wg_per_view);   // pose-in-launch * V + view
+    const int pvi = (int)(wg / (uint32_t)a.tiles_pow4);   // pose-in-launch * V + view
     const int pb = pvi / a.V;
     const int v = pvi % a.V;
     if (MODE == 2 && v != a.debug_view) return;
@@ -165,10 +185,11 @@ __global__ __launch_bounds__(256, MODE == 1 ? 3 : 4) void k_render(RArgs a) {
     const size_t slot_pg = (size_t)pb * a.ngroups + grp;
     // the tile lists of this (pose, view group) overflowed their buffer: re-run by the host
     if (a.ovf[2 * slot_pg]) return;
-    const int rem = (int)(wg % (uint32_t)a.wg_per_view);
-    const int ty = 2 * (rem / a.wg_x) + (wv >> 1);
-    const int tx = 2 * (rem % a.wg_x) + (wv & 1);
-    const bool tile_ok = tx < a.TX && ty < a.TY;
+    const uint32_t mt = wg % (uint32_t)a.tiles_pow4;        // Morton index of the tile
+    const int tx = (int)compact2(mt);
+    const int ty = (int)compact2(mt >> 1);
+    if (tx >= a.TX || ty >= a.TY) return;   // Morton slot outside the image (whole wave)
+    const bool tile_ok = true;
     const int px = tx * 8 + (lane & 7);
     const int py = ty * 8 + (lane >> 3);
     const bool pix_ok = tile_ok && px < a.W && py < a.H;
@@ -185,8 +206,13 @@ __global__ __launch_bounds__(256, MODE == 1 ? 3 : 4) void k_render(RArgs a) {
     const uint32_t* brick_mask = a.brick_mask + (size_t)pb * a.ncap * 16;
     const uint32_t* occ_win = a.occ_win + (size_t)pb * a.ncap;
     const size_t es = ST == 0 ? 4 : 2;
+#if ART_GATHER_CANONICAL
+    const void* psig = a.csig;
+    const void* pfeat = a.cfeat;
+#else
     const void* psig = static_cast<const char*>(a.psig) + (size_t)pb * a.ncap * es;
     const void* pfeat = static_cast<const char*>(a.pfeat) + (size_t)pb * a.ncap * C * es;
+#endif
 
     // ---- ray r_p = (o, d) of pixel (px, py) -----------------------------------
     const CamParams& cam = a.cam[v];
@@ -273,6 +299,7 @@ __global__ __launch_bounds__(256, MODE == 1 ? 3 : 4) void k_render(RArgs a) {
     uint32_t row_base = 0;
 
     uint32_t rounds = 0;   // wave-uniform traversal rounds (diagnostic)
+    uint32_t nsteps = 0;   // partition steps of this lane (diagnostic)
     for (uint32_t base = ls; base < le; base += kStage) {
         if (__ballot(active) == 0ull) break;
         // stage up to 64 bricks of the tile's front-to-back list
@@ -332,8 +359,9 @@ __global__ __launch_bounds__(256, MODE == 1 ? 3 : 4) void k_render(RArgs a) {
             float dlB = 0.0f;
             double dxB = 0.0;
             int guard = 0;
-            while (active && !hasB && (inb || todo != 0ull) && guard < 64) {
+            while (active && !hasB && (inb || todo != 0ull) && guard < kStepsPerRound) {
                 ++guard;
+                ++nsteps;
                 if (!inb) {
                     slot = __ffsll((unsigned long long)todo) - 1;
                     todo &= todo - 1ull;
@@ -444,7 +472,11 @@ __global__ __launch_bounds__(256, MODE == 1 ? 3 : 4) void k_render(RArgs a) {
                 rowA = rowB;
                 dlA = dlB;
                 dxA = dxB;
+#if ART_GATHER_CANONICAL
+                load_sample<C, ST>(psig, pfeat, occ_win[rowA], sgA, fA);
+#else
                 load_sample<C, ST>(psig, pfeat, rowA, sgA, fA);
+#endif
             }
         }
         wave_sync();
@@ -470,6 +502,10 @@ __global__ __launch_bounds__(256, MODE == 1 ? 3 : 4) void k_render(RArgs a) {
             atomicAdd(&a.stats[2], (unsigned long long)__popcll(hits));
             atomicAdd(&a.stats[7], (unsigned long long)(le - ls));
             atomicAdd(&a.stats[8], (unsigned long long)rounds);
+        }
+        const unsigned long long steps = (unsigned long long)wave_sum(nsteps);
+        if (lane == 0 && rays) {
+            atomicAdd(&a.stats[9], steps);
         }
     }
 }
