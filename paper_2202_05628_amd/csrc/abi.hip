@@ -6,6 +6,7 @@
 //             per view group: tile binning -> render
 // Every device step is one of the library's own kernels.
 #include <math.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -121,9 +122,28 @@ art_status ensure_bufs(art_ctx* ctx, std::initializer_list<std::pair<DevBuf*, si
     return ART_OK;
 }
 
-// Device memory held for the posed octrees of one batch of poses; the poses of
-// a call are processed in batches of at most this many.
-constexpr size_t kSlotBudgetBytes = (size_t)48 << 30;
+// Device memory held for the posed octrees of one batch of poses (48 GiB by
+// default, ARTEMIS_SLOT_BUDGET_MB overrides); the poses of a call are processed
+// in batches that fit it.
+size_t slot_budget_bytes() {
+    const char* e = getenv("ARTEMIS_SLOT_BUDGET_MB");
+    if (e && *e) {
+        const long long mb = atoll(e);
+        if (mb > 0) return (size_t)mb << 20;
+    }
+    return (size_t)48 << 30;
+}
+
+// Initial capacity of one (pose, view group) tile list (ARTEMIS_PAIR_CAP
+// overrides; the capacity grows when a list overflows).
+size_t initial_pair_cap(size_t tiles_g) {
+    const char* e = getenv("ARTEMIS_PAIR_CAP");
+    if (e && *e) {
+        const long long v = atoll(e);
+        if (v > 0) return (size_t)v;
+    }
+    return std::max<size_t>((size_t)1 << 20, 16 * tiles_g);
+}
 
 size_t slot_bytes(const art_ctx* ctx, const CallPlan& pl, size_t pair_cap) {
     const size_t n = (size_t)ctx->n;
@@ -141,7 +161,7 @@ art_status ensure_scratch(art_ctx* ctx, const CallPlan& pl, int slots) {
     const size_t V = (size_t)std::max(ctx->V, 1);
     const size_t tiles = V * ((ctx->W + 7) / 8) * ((ctx->H + 7) / 8);
     const size_t tiles_g = (size_t)pl.Vg * ((ctx->W + 7) / 8) * ((ctx->H + 7) / 8);
-    if (s.pair_cap == 0) s.pair_cap = std::max<size_t>((size_t)1 << 20, 16 * tiles_g);
+    if (s.pair_cap == 0) s.pair_cap = initial_pair_cap(tiles_g);
     const size_t S = (size_t)slots;
     art_status rc = ensure_bufs(ctx, {
         {&s.keys0, n * 4}, {&s.vals0, n * 4}, {&s.keys1, n * 4}, {&s.vals1, n * 4},
@@ -365,9 +385,9 @@ art_status render_call(art_ctx* ctx, int C, art_dtype dtype, const void* sigma, 
     const int P = pose_hi - pose_lo;
     if (ctx->s.pair_cap == 0) {
         const size_t tiles_g = (size_t)pl.Vg * ((ctx->W + 7) / 8) * ((ctx->H + 7) / 8);
-        ctx->s.pair_cap = std::max<size_t>((size_t)1 << 20, 16 * tiles_g);
+        ctx->s.pair_cap = initial_pair_cap(tiles_g);
     }
-    int slots = (int)std::min<size_t>((size_t)P, std::max<size_t>(1, kSlotBudgetBytes / slot_bytes(ctx, pl, ctx->s.pair_cap)));
+    int slots = (int)std::min<size_t>((size_t)P, std::max<size_t>(1, slot_budget_bytes() / slot_bytes(ctx, pl, ctx->s.pair_cap)));
     rc = ensure_scratch(ctx, pl, slots);
     if (rc != ART_OK) return rc;
     hipStream_t st = ctx->stream;

@@ -1,0 +1,106 @@
+"""Precision form: BF16 storage of leaf densities and features, FP32
+transmittance and accumulation, FP32 skinning and ray parameter, FP64 bone
+chain - against the FP64 oracle, at the precision form's launch shape (full
+scene, 16 cameras at 1024x1024).
+
+Reported per (pose, view) map, on sampled pixels: rel_max and rel_mean against
+(a) the oracle on the unrounded FP32 inputs (total error) and (b) the oracle on
+the BF16-rounded inputs (arithmetic and geometry error only).  FP32 geometry
+may place a leaf whose FP64 centre lies within 1e-4 h of a lattice face in the
+neighbouring cell; such leaves, the rays crossing either candidate cell and
+rays with a partition gap below 1e-4 h are counted and excluded from the
+rel_max bound (rel_mean covers every sampled pixel)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import scenegen as sg
+from gpu_common import log, make_renderer
+
+pytestmark = pytest.mark.gpu
+
+TOL_BF16 = 1e-2
+EPS_FLIP = 1e-4
+
+
+def _ambiguous(pt, depth):
+    """Leaves within EPS_FLIP*h of a lattice plane and every cell they may land
+    in: on an axis near the plane k the cell is k - 1 or k, else floor(u)."""
+    import itertools
+    u = (pt + 1.0) * (1 << depth)
+    k = np.round(u)
+    near = np.abs(u - k) < EPS_FLIP
+    leaves = np.flatnonzero(near.any(axis=1))
+    cells = []
+    for i in leaves:
+        opts = [(int(k[i, a]) - 1, int(k[i, a])) if near[i, a] else (int(np.floor(u[i, a])),) for a in range(3)]
+        cells.extend(itertools.product(*opts))
+    return leaves, np.array(cells, dtype=np.int64).reshape(-1, 3)
+
+
+def test_bf16_form_errors():
+    import torch
+
+    cfg = sg.CONFIGS["bf16"]
+    s = sg.make_scene("bf16")
+    r_, R_, T_ = sg.make_poses(s.J, cfg.n_poses, cfg.pose_seed0)
+    sel = (r_[:1], R_[:1], T_[:1])
+    H, W = cfg.height, cfg.width
+    K, c2w = sg.make_cameras(s, cfg.n_views, H, W)
+    rend = make_renderer(s, sel, K, c2w, H, W)
+    sig = torch.from_numpy(s.sigma).cuda().to(torch.bfloat16)
+    f = torch.from_numpy(s.feat).cuda().to(torch.bfloat16)
+    log(f"bf16 form: 1 pose x {cfg.n_views} views at {H}x{W}")
+    F, A, T = rend.render(sig, f, lambda_th=0.01, fp32_geom=True)
+    F = F.cpu().numpy()
+    A = A.cpu().numpy()
+
+    B = oracle.fk(s.parent, s.rest_joint, *sel)[0]
+    pt = oracle.lbs(s.ijk, s.depth, s.bone, s.weight, B)
+    cells, valid = oracle.posed_cells(pt, s.depth)
+    ko = oracle.posed_keys(cells, valid)
+    kg = rend.get_posed_keys(0, fp32_geom=True)
+    amb_leaves, amb_cells = _ambiguous(pt, s.depth)
+    flips = np.flatnonzero(kg != ko)
+    assert set(flips.tolist()) <= set(amb_leaves.tolist()), "a posed cell differs away from a face"
+    ok_, ol_ = oracle.occupancy_from_cells(cells, valid, s.depth)
+    G = 1 << (s.depth + 1)
+    amb_lin = np.unique((amb_cells[:, 2] * G + amb_cells[:, 1]) * G + amb_cells[:, 0]) if len(amb_cells) else \
+        np.zeros(0, dtype=np.int64)
+    sig_r = oracle.bf16_round(s.sigma)
+    feat_r = oracle.bf16_round(s.feat)
+    o, d = oracle.camera_rays(K, c2w, H, W)
+    h = 1.0 / (1 << s.depth)
+    rng = np.random.default_rng(21)
+    report = {"flipped_leaves": int(len(flips)), "ambiguous_leaves": int(len(amb_leaves)), "maps": []}
+    for v in range(cfg.n_views):
+        hitpix = np.flatnonzero(A[0, v].reshape(-1) > 0)
+        pix = np.concatenate([rng.choice(hitpix, 500, replace=False), rng.integers(0, H * W, 100)])
+        ov, dv = o[v].reshape(-1, 3)[pix], d[v].reshape(-1, 3)[pix]
+        ref_a = oracle.render(ov, dv, s.depth, ok_, ol_, s.sigma, s.feat, 0.01)
+        ref_b = oracle.render(ov, dv, s.depth, ok_, ol_, sig_r, feat_r, 0.01)
+        amb = np.zeros(len(pix), dtype=bool)
+        if len(amb_lin):
+            hit_amb = oracle.render(ov, dv, s.depth, amb_lin, np.zeros(len(amb_lin), dtype=np.int64),
+                                    np.zeros(1), np.zeros((1, 1)), 0.0)
+            amb = hit_amb["n_hit"] > 0
+        amb |= ref_a["min_gap"] < EPS_FLIP * h
+        good = ~amb
+        Fg = F[0, v].reshape(s.C, -1)[:, pix]
+        row = {"view": v, "excluded": int(amb.sum())}
+        for name, ref in (("total", ref_a), ("arith", ref_b)):
+            Fr = ref["F"].T
+            rmax = np.abs(Fg - Fr)[:, good].max() / np.abs(Fr[:, good]).max()
+            rmean = np.abs(Fg - Fr).sum() / np.abs(Fr).sum()
+            row[f"{name}_rel_max"] = float(rmax)
+            row[f"{name}_rel_mean"] = float(rmean)
+            assert rmax <= TOL_BF16 and rmean <= TOL_BF16, (name, v, rmax, rmean)
+        log(f"  view {v}: {row}")
+        report["maps"].append(row)
+    out = os.path.join(os.environ.get("GRAFT_REPO_ROOT", "."), "gpurun_out")
+    if os.path.isdir(out):
+        with open(os.path.join(out, "bf16_errors.json"), "w") as fh:
+            json.dump(report, fh, indent=1)
