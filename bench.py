@@ -41,12 +41,13 @@ def parse():
 
 
 def algorithmic_bytes(stats, C, es, with_tfinal=True):
-    """Bytes the compositing must move: per composited sample the density, the C
-    features and the 4-byte leaf-index word; per ray the C + 1 output floats
-    (+ the final transmittance)."""
+    """Bytes the compositing kernel must move: per composited sample the
+    density, the C features and the 4-byte leaf-index word; per ray of the
+    tiles it renders the C + 1 output floats (+ the final transmittance).
+    (Pixels of tiles with no brick are written by the background kernel.)"""
     per_sample = es * (C + 1) + 4
     per_ray = 4 * (C + 1) + (4 if with_tfinal else 0)
-    return stats["samples"] * per_sample + stats["rays"] * per_ray
+    return stats["samples"] * per_sample + stats["tile_rays"] * per_ray
 
 
 def cpu_baseline(scene, poses, K, c2w, H, W, lam, budget_s):

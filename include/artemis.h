@@ -219,11 +219,12 @@ art_status art_get_hits(art_ctx* ctx, int pose, int view, int C, art_dtype dtype
                         int max_hits, int32_t* leaf, double* delta, int32_t* count);
 
 /*
- * Counters of the last art_render / art_backward call, host int64 [11]:
+ * Counters of the last art_render / art_backward call, host int64 [12]:
  * {rays, composited samples, rays with at least one sample, dropped leaves,
  *  collisions, bricks (summed over poses), tile/brick pairs, kernel launches,
  *  tile-list entries summed over the 8x8 tiles, traversal rounds summed over
- *  the compositing kernel's waves, ray/voxel partition steps summed over rays}.
+ *  the compositing kernel's waves, ray/voxel partition steps summed over rays,
+ *  rays of the tiles the compositing kernel rendered (non-empty brick list)}.
  */
 art_status art_get_stats(art_ctx* ctx, int64_t* stats);
 

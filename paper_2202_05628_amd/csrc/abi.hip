@@ -178,6 +178,7 @@ art_status ensure_scratch(art_ctx* ctx, const CallPlan& pl, int slots) {
         {&s.pair_v, S * pl.ngroups * s.pair_cap * 4},
         {&s.tile_start, S * tiles * 4}, {&s.tile_end, S * tiles * 4},
         {&s.ovf, S * pl.ngroups * 2 * 4},
+        {&s.items, S * tiles * 4}, {&s.queue, 64},
     });
     if (rc == ART_OK) s.slots = std::max(s.slots, slots);
     return rc;
@@ -366,6 +367,31 @@ art_status run_batch(art_ctx* ctx, const CallPlan& pl, int mode, float lambda, c
     r.hit_leaf = o.hit_leaf;
     r.hit_delta = o.hit_delta;
     r.hit_count = o.hit_count;
+    int side = 1;
+    while (side < (ctx->W + 7) / 8 || side < (ctx->H + 7) / 8) side <<= 1;
+    TileLaunch tl{};
+    tl.Pb = Pb;
+    tl.V = ctx->V;
+    tl.Vg = pl.Vg;
+    tl.ngroups = pl.ngroups;
+    tl.H = ctx->H;
+    tl.W = ctx->W;
+    tl.C = pl.C;
+    tl.tiles_pow4 = (uint32_t)(side * side);
+    tl.debug_view = mode == 2 ? o.debug_view : -1;
+    tl.ovf = s.ovf.as<uint32_t>();
+    tl.tile_start = s.tile_start.as<uint32_t>();
+    tl.tile_end = s.tile_end.as<uint32_t>();
+    tl.items = s.items.as<uint32_t>();
+    tl.counters = s.queue.as<uint32_t>();
+    tl.out_feat = r.out_feat;
+    tl.out_alpha = r.out_alpha;
+    tl.out_tfinal = r.out_tfinal;
+    tl.hit_count = r.hit_count;
+    tl.stats = s.stats.as<unsigned long long>();
+    ART_TRY_HIP(launch_tiles(tl, st), "tile compaction");
+    *launches += (r.out_feat || r.hit_count) ? 3 : 2;
+    tm.record(st, 3);
     ART_TRY_HIP(launch_render(r, st), "render");
     *launches += 1;
     tm.record(st, 4);
@@ -439,6 +465,7 @@ art_status render_call(art_ctx* ctx, int C, art_dtype dtype, const void* sigma, 
     ctx->stats[8] = (int64_t)hst[7];
     ctx->stats[9] = (int64_t)hst[8];
     ctx->stats[10] = (int64_t)hst[9];
+    ctx->stats[11] = (int64_t)hst[10];
     tm.finish(ctx);
     return ART_OK;
 }
@@ -463,10 +490,9 @@ hipError_t launch_render(const RenderLaunch& r, hipStream_t st) {
     a.depth = r.depth;
     a.Vg = r.Vg;
     a.ngroups = r.ngroups;
-    int side = 1;
-    while (side < a.TX || side < a.TY) side <<= 1;
-    a.tiles_pow4 = side * side;   // Morton tile slots per view (slots outside the image exit)
-    a.n_wg = a.tiles_pow4 * r.V * r.Pb;
+    a.items = s.items.as<uint32_t>();
+    a.n_items = s.queue.as<uint32_t>();
+    a.queue = s.queue.as<uint32_t>() + 1;
     a.ncap = r.ncap;
     a.pair_cap = (uint32_t)s.pair_cap;
     a.lambda = r.lambda;
@@ -497,8 +523,16 @@ hipError_t launch_render(const RenderLaunch& r, hipStream_t st) {
     a.hit_delta = r.hit_delta;
     a.hit_count = r.hit_count;
     a.stats = s.stats.as<unsigned long long>();
-    const unsigned per = 8u * kXcdChunk;
-    const unsigned grid = (unsigned)((a.n_wg + per - 1) / per * per);
+    // persistent single-wave workgroups: about two per resident slot
+    static int n_cu = 0;
+    if (n_cu == 0) {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+            n_cu = prop.multiProcessorCount;
+        if (n_cu <= 0) n_cu = 256;
+    }
+    const unsigned grid = (unsigned)n_cu * 32u;
     switch (r.C) {
         case 4: return launch_render_c<4>(r, a, grid, st);
         case 8: return launch_render_c<8>(r, a, grid, st);

@@ -57,10 +57,10 @@ struct PoseCounters {
 // Run-wide statistics accumulated on the device.
 struct RunStats {
     unsigned long long rays, samples, hit_rays, dropped, collisions, bricks, pairs, list_entries, rounds,
-        steps;
+        steps, tile_rays;
 };
 
-constexpr int kNumStats = 11;
+constexpr int kNumStats = 12;
 constexpr int kSortBlocks = 512;      // fixed grid of the radix-sort passes
 constexpr int kScanBlocks = 1024;     // fixed grid of device-sized scans
 constexpr int kUniqueBlocks = 1024;   // fixed grid of the unique / compaction step
@@ -79,6 +79,8 @@ struct Scratch {
     DevBuf counters;                     // PoseCounters
     DevBuf stats;                        // RunStats
     DevBuf ovf;                          // [slots][groups][2] overflow flag, pair count
+    DevBuf items;                        // [slots][V][tiles] compacted non-empty tiles
+    DevBuf queue;                        // [2] item count, queue head
     size_t pair_cap = 0;
     int slots = 0;                       // poses whose octrees are held at once
 };
@@ -189,5 +191,23 @@ struct RenderLaunch {
     int32_t* hit_count;
 };
 hipError_t launch_render(const RenderLaunch& r, hipStream_t st);
+
+// Tile compaction (non-empty tiles -> work list) and background of empty tiles.
+struct TileLaunch {
+    int Pb, V, Vg, ngroups, H, W, C;
+    uint32_t tiles_pow4;
+    int debug_view;            // -1: all views
+    const uint32_t* ovf;
+    const uint32_t* tile_start;
+    const uint32_t* tile_end;
+    uint32_t* items;           // [Pb * V * TPV]
+    uint32_t* counters;        // [2]: item count, queue head
+    float* out_feat;           // forward maps (null in the adjoint)
+    float* out_alpha;
+    float* out_tfinal;
+    int32_t* hit_count;
+    unsigned long long* stats;
+};
+hipError_t launch_tiles(const TileLaunch& t, hipStream_t st);
 
 }  // namespace art

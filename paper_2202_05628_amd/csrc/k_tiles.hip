@@ -1,0 +1,125 @@
+// Tile work distribution of the compositing pass.
+//
+//   k_tile_compact : one thread per tile slot (Morton order within each view);
+//                    tiles whose brick list is not empty are appended to the work
+//                    list with a wave ballot + popcount of the lanes below (one
+//                    atomic per wave), so the persistent compositing waves only
+//                    ever take tiles with work.
+//   k_background   : one wave per tile slot; an empty tile's pixels get F = 0,
+//                    A = 0, T = 1 (no voxel on their ray).
+#include "device_util.h"
+#include "internal.h"
+
+namespace art {
+
+struct TileGeom {
+    int Pb, V, Vg, ngroups, TX, TY, TPV, H, W, C;
+    uint32_t tiles_pow4;
+    int debug_view;   // -1: all views
+};
+
+__device__ inline bool tile_slot(const TileGeom& g, const uint32_t* ovf, uint64_t i, uint32_t* item,
+                                 int* tx, int* ty, int* pvi) {
+    const uint64_t total = (uint64_t)g.Pb * g.V * g.tiles_pow4;
+    if (i >= total) return false;
+    *pvi = (int)(i / g.tiles_pow4);
+    const uint32_t mt = (uint32_t)(i % g.tiles_pow4);
+    *tx = (int)compact2(mt);
+    *ty = (int)compact2(mt >> 1);
+    if (*tx >= g.TX || *ty >= g.TY) return false;
+    const int pb = *pvi / g.V;
+    const int v = *pvi % g.V;
+    if (g.debug_view >= 0 && v != g.debug_view) return false;
+    if (ovf[2 * ((size_t)pb * g.ngroups + v / g.Vg)]) return false;   // re-run later by the host
+    *item = (uint32_t)((uint64_t)*pvi * g.TPV + (uint64_t)*ty * g.TX + *tx);
+    return true;
+}
+
+__global__ __launch_bounds__(256) void k_tile_compact(TileGeom g, const uint32_t* __restrict__ ovf,
+                                                      const uint32_t* __restrict__ tstart,
+                                                      const uint32_t* __restrict__ tend,
+                                                      uint32_t* __restrict__ items,
+                                                      uint32_t* __restrict__ n_items) {
+    const uint64_t total = (uint64_t)g.Pb * g.V * g.tiles_pow4;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < total; base += stride) {
+        const uint64_t i = base + threadIdx.x;
+        uint32_t item = 0;
+        int tx, ty, pvi;
+        bool work = tile_slot(g, ovf, i, &item, &tx, &ty, &pvi);
+        work = work && tend[item] > tstart[item];
+        const uint64_t m = __ballot(work);
+        if (m == 0ull) continue;
+        uint32_t first = 0;
+        if (lane_id() == 0) first = atomicAdd(n_items, (uint32_t)__popcll(m));
+        first = (uint32_t)__shfl((int)first, 0, kWave);
+        if (work) items[first + (uint32_t)__popcll(m & lanemask_lt())] = item;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_background(TileGeom g, const uint32_t* __restrict__ ovf,
+                                                    const uint32_t* __restrict__ tstart,
+                                                    const uint32_t* __restrict__ tend,
+                                                    float* __restrict__ out_feat, float* __restrict__ out_alpha,
+                                                    float* __restrict__ out_tfinal, int32_t* __restrict__ hit_count,
+                                                    unsigned long long* __restrict__ stats) {
+    const uint64_t total = (uint64_t)g.Pb * g.V * g.tiles_pow4;
+    const int lane = lane_id();
+    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / kWave);
+    for (uint64_t i = (uint64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; i < total; i += waves) {
+        uint32_t item = 0;
+        int tx, ty, pvi;
+        if (!tile_slot(g, ovf, i, &item, &tx, &ty, &pvi)) continue;   // wave-uniform
+        if (tend[item] > tstart[item]) continue;                       // rendered by k_render
+        const int px = tx * 8 + (lane & 7);
+        const int py = ty * 8 + (lane >> 3);
+        const bool pix_ok = px < g.W && py < g.H;
+        if (pix_ok) {
+            const size_t HW = (size_t)g.H * g.W;
+            const size_t pix = (size_t)py * g.W + px;
+            if (out_feat)
+                for (int c = 0; c < g.C; ++c) out_feat[((size_t)pvi * g.C + c) * HW + pix] = 0.0f;
+            if (out_alpha) out_alpha[(size_t)pvi * HW + pix] = 0.0f;
+            if (out_tfinal) out_tfinal[(size_t)pvi * HW + pix] = 1.0f;
+            if (hit_count) hit_count[pix] = 0;
+        }
+        if (stats) {
+            const uint64_t rays = __ballot(pix_ok);
+            if (lane == 0) atomicAdd(&stats[0], (unsigned long long)__popcll(rays));
+        }
+    }
+}
+
+hipError_t launch_tiles(const TileLaunch& t, hipStream_t st) {
+    TileGeom g;
+    g.Pb = t.Pb;
+    g.V = t.V;
+    g.Vg = t.Vg;
+    g.ngroups = t.ngroups;
+    g.TX = (t.W + 7) / 8;
+    g.TY = (t.H + 7) / 8;
+    g.TPV = g.TX * g.TY;
+    g.H = t.H;
+    g.W = t.W;
+    g.C = t.C;
+    g.tiles_pow4 = t.tiles_pow4;
+    g.debug_view = t.debug_view;
+    const uint64_t total = (uint64_t)g.Pb * g.V * g.tiles_pow4;
+    hipError_t e = launch_fill_u32(t.counters, 0u, 2, st);   // n_items, queue
+    if (e != hipSuccess) return e;
+    uint64_t blocks = (total + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_tile_compact, dim3((unsigned)blocks), dim3(256), 0, st, g, t.ovf, t.tile_start, t.tile_end,
+                       t.items, t.counters);
+    if (t.out_feat || t.hit_count) {
+        uint64_t wblocks = (total + 3) / 4;
+        if (wblocks > 65536) wblocks = 65536;
+        if (wblocks < 1) wblocks = 1;
+        hipLaunchKernelGGL(k_background, dim3((unsigned)wblocks), dim3(256), 0, st, g, t.ovf, t.tile_start,
+                           t.tile_end, t.out_feat, t.out_alpha, t.out_tfinal, t.hit_count, t.stats);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace art

@@ -1,8 +1,12 @@
 // Ray indexing + front-to-back compositing (Section 3.1, "Dynamic Volume
 // Rendering", Eq. 5 and Eq. 6) and its adjoint.
 //
-// One wave64 owns one 8x8-pixel tile and is its own workgroup, so the LDS of
-// a finished tile is released at once whatever its neighbours still do.  The
+// Work distribution: k_tile_compact gathers the (pose, view, tile) items whose
+// brick list is not empty with wave ballots (one atomic per wave), and
+// k_background writes F = 0, A = 0, T = 1 for the pixels of the empty tiles.
+// The compositing kernel then runs persistent single-wave workgroups that pull
+// non-empty tiles from an atomic queue, so every resident wave has a tile with
+// work in it; one wave64 renders one 8x8-pixel tile at a time.  The
 // tile's front-to-back brick list (see k_bin.hip) is streamed through LDS in
 // chunks of 64 bricks: each lane stages one brick (its 512-bit occupancy mask,
 // per-word prefix popcounts, first row and coordinates), then every lane walks
@@ -18,11 +22,9 @@
 // Geometry (ray parameter t, plane crossings, midpoint cells) runs in R =
 // double (default) or float (precision form); compositing is always FP32.
 //
-// Tiles are numbered in Morton order within a view, and workgroups are
-// remapped so that each XCD (workgroups are dispatched round robin over the 8
-// XCDs) receives runs of kXcdChunk consecutive tiles - a 4x4-tile block -
-// keeping neighbouring tiles, which read the same bricks and FLUT rows, in one
-// XCD's L2.
+// Items are compacted in Morton tile order within each view, so consecutive
+// queue entries - taken by waves at nearly the same time - are neighbouring
+// tiles that read the same bricks and FLUT rows.
 #pragma once
 
 #include "device_util.h"
@@ -30,7 +32,6 @@
 
 namespace art {
 
-constexpr int kXcdChunk = 16;
 constexpr int kStage = 64;
 // Partition steps a lane may take per round while looking for its next
 // occupied segment.  Bounding it keeps one lane that crosses empty cells from
@@ -49,7 +50,9 @@ struct RArgs {
     const CamParams* cam;
     int Pb, V, H, W, TX, TY, TPV, depth;   // poses in this launch, views, image, tiles
     int Vg, ngroups;                       // view groups of the tile lists
-    int n_wg, tiles_pow4;                  // workgroups, Morton tile slots per view
+    const uint32_t* items;                 // compacted non-empty tiles: pvi * TPV + ty * TX + tx
+    const uint32_t* n_items;               // device count of items
+    uint32_t* queue;                       // next item to take (zeroed before the launch)
     uint32_t ncap;                         // per-pose capacity of the octree arrays (leaves)
     uint32_t pair_cap;                     // per (pose, group) capacity of the tile lists
     float lambda;
@@ -159,47 +162,27 @@ __device__ inline bool brick_overlap(const int* b3, const R* d, const R* q, cons
 #ifndef ART_RENDER_WAVES_PER_EU
 #define ART_RENDER_WAVES_PER_EU 1
 #endif
+// Render one non-empty tile (item = pose-in-launch * V + view, tile index).
 template <int C, int ST, typename R, int MODE>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MODE == 1 ? 1 : ART_RENDER_WAVES_PER_EU)))
-void k_render(RArgs a) {
-    __shared__ uint32_t s_mask[1][16][kStage];
-    __shared__ uint16_t s_pref[1][16][kStage];
-    __shared__ uint32_t s_row[1][kStage];
-    __shared__ uint32_t s_coord[1][kStage];
-
+__device__ inline void render_tile(const RArgs& a, uint32_t item, int lane, uint32_t (*s_mask)[16][kStage],
+                                   uint16_t (*s_pref)[16][kStage], uint32_t (*s_row)[kStage],
+                                   uint32_t (*s_coord)[kStage]) {
     constexpr int wv = 0;
-    const int lane = threadIdx.x & 63;
-
-    // XCD-aware workgroup remap: runs of kXcdChunk consecutive workgroups share an XCD
-    const uint32_t hw = blockIdx.x;
-    const uint32_t xcd = hw & 7u;
-    const uint32_t kk = hw >> 3;
-    const uint32_t wg = ((kk / kXcdChunk) * 8u + xcd) * kXcdChunk + (kk % kXcdChunk);
-    if (wg >= (uint32_t)a.n_wg) return;
-
-    const int pvi = (int)(wg / (uint32_t)a.tiles_pow4);   // pose-in-launch * V + view
+    const int pvi = (int)(item / (uint32_t)a.TPV);   // pose-in-launch * V + view
+    const int tile_in_view = (int)(item % (uint32_t)a.TPV);
     const int pb = pvi / a.V;
     const int v = pvi % a.V;
-    if (MODE == 2 && v != a.debug_view) return;
     const int grp = v / a.Vg;
     const size_t slot_pg = (size_t)pb * a.ngroups + grp;
-    // the tile lists of this (pose, view group) overflowed their buffer: re-run by the host
-    if (a.ovf[2 * slot_pg]) return;
-    const uint32_t mt = wg % (uint32_t)a.tiles_pow4;        // Morton index of the tile
-    const int tx = (int)compact2(mt);
-    const int ty = (int)compact2(mt >> 1);
-    if (tx >= a.TX || ty >= a.TY) return;   // Morton slot outside the image (whole wave)
+    const int ty = tile_in_view / a.TX;
+    const int tx = tile_in_view % a.TX;
     const bool tile_ok = true;
     const int px = tx * 8 + (lane & 7);
     const int py = ty * 8 + (lane >> 3);
-    const bool pix_ok = tile_ok && px < a.W && py < a.H;
+    const bool pix_ok = px < a.W && py < a.H;
 
-    uint32_t ls = 0, le = 0;
-    if (tile_ok) {
-        const size_t tile = (size_t)pvi * a.TPV + (size_t)ty * a.TX + tx;
-        ls = a.tile_start[tile];
-        le = a.tile_end[tile];
-    }
+    const uint32_t ls = a.tile_start[item];
+    const uint32_t le = a.tile_end[item];
     const uint32_t* pair_v = a.pair_v + slot_pg * a.pair_cap;
     const uint32_t* brick_key = a.brick_key + (size_t)pb * a.ncap;
     const uint32_t* brick_row = a.brick_row + (size_t)pb * (a.ncap + 1);
@@ -291,9 +274,11 @@ void k_render(RArgs a) {
     // ---- traversal state (current brick) ----------------------------------------
     bool inb = false;
     R s = 0, t1 = 0;
-    R tc[3];
-    int kp[3];          // index of the next lattice plane crossed on each axis
-    int cl[3];          // lattice coordinate of the current cell (brick local after entry)
+    R tc[3] = {(R)INFINITY, (R)INFINITY, (R)INFINITY};
+    int kp[3] = {0, 0, 0};   // index of the next lattice plane crossed on each axis
+    int cg[3] = {c0[0], c0[1], c0[2]};   // lattice cell of the ray at s
+    int lo3[3] = {0, 0, 0};  // first lattice cell of the current brick
+    bool fresh = false;      // plane state valid (set by the first brick entry)
     int slot = 0;
     int bsteps = 0;
     uint32_t row_base = 0;
@@ -371,43 +356,35 @@ void k_render(RArgs a) {
                     if (!brick_overlap<R>(b3, d, q, inv, c0, h, ta, tb, t0, t1)) continue;
                     inb = true;
                     bsteps = 0;
-                    s = t0;
                     row_base = s_row[wv][slot];
 #pragma unroll
-                    for (int i = 0; i < 3; ++i) {
-                        const int lo = 8 * b3[i];
-                        if (d[i] == (R)0) {
-                            tc[i] = (R)INFINITY;
-                            kp[i] = 0;
-                            cl[i] = c0[i] - lo;
-                            continue;
+                    for (int i = 0; i < 3; ++i) lo3[i] = 8 * b3[i];
+                    // Entering exactly where the ray left the previous brick (its
+                    // neighbour), the plane state carries over unchanged.  Otherwise
+                    // it restarts from the lattice coordinate at t0; rounding there
+                    // can only misplace a segment shorter than the rounding itself
+                    // (a plane index one too small costs one empty step).
+                    if (!(fresh && t0 == s)) {
+#pragma unroll
+                        for (int i = 0; i < 3; ++i) {
+                            if (d[i] == (R)0) continue;
+                            const R u = (q[i] + t0 * d[i]) * invh;
+                            const int k = d[i] > (R)0 ? (int)floor(u) + 1 : (int)ceil(u) - 1;
+                            kp[i] = k;
+                            cg[i] = d[i] > (R)0 ? k - 1 : k;
+                            tc[i] = tplane<R>(k, h, q[i], inv[i]);
                         }
-                        const R u = (q[i] + t0 * d[i]) * invh;
-                        int k;
-                        if (d[i] > (R)0) {
-                            k = (int)floor(u) + 1;
-                            k = k < lo + 1 ? lo + 1 : (k > lo + 8 ? lo + 8 : k);
-                            // u carries rounding far below one cell: one correction each way
-                            if (k > lo + 1 && tplane<R>(k - 1, h, q[i], inv[i]) > t0) --k;
-                            if (k < lo + 8 && tplane<R>(k, h, q[i], inv[i]) <= t0) ++k;
-                            cl[i] = k - 1 - lo;
-                        } else {
-                            k = (int)ceil(u) - 1;
-                            k = k < lo ? lo : (k > lo + 7 ? lo + 7 : k);
-                            if (k < lo + 7 && tplane<R>(k + 1, h, q[i], inv[i]) > t0) ++k;
-                            if (k > lo && tplane<R>(k, h, q[i], inv[i]) <= t0) --k;
-                            cl[i] = k - lo;
-                        }
-                        kp[i] = k;
-                        tc[i] = tplane<R>(k, h, q[i], inv[i]);
+                        fresh = true;
                     }
+                    s = t0;
                 }
-                // one segment of the exact partition: (s, s1) in cell cl
+                // one segment of the exact partition: (s, s1) in cell cg
                 R s1 = fmin(fmin(tc[0], tc[1]), fmin(tc[2], t1));
                 s1 = fmax(s1, s);
-                if (s1 > s && (unsigned)cl[0] < 8u && (unsigned)cl[1] < 8u && (unsigned)cl[2] < 8u) {
-                    const uint32_t m9 = spread3_small((uint32_t)cl[0]) | (spread3_small((uint32_t)cl[1]) << 1) |
-                                        (spread3_small((uint32_t)cl[2]) << 2);
+                const int l0 = cg[0] - lo3[0], l1 = cg[1] - lo3[1], l2 = cg[2] - lo3[2];
+                if (s1 > s && (unsigned)l0 < 8u && (unsigned)l1 < 8u && (unsigned)l2 < 8u) {
+                    const uint32_t m9 = spread3_small((uint32_t)l0) | (spread3_small((uint32_t)l1) << 1) |
+                                        (spread3_small((uint32_t)l2) << 2);
                     const uint32_t wd = m9 >> 5, bit = m9 & 31u;
                     const uint32_t mw = s_mask[wv][wd][slot];
                     if ((mw >> bit) & 1u) {
@@ -422,7 +399,7 @@ void k_render(RArgs a) {
                     if (tc[i] <= s1) {
                         const int st = d[i] > (R)0 ? 1 : -1;
                         kp[i] += st;
-                        cl[i] += st;
+                        cg[i] += st;
                         tc[i] = tplane<R>(kp[i], h, q[i], inv[i]);
                     }
                 }
@@ -501,12 +478,34 @@ void k_render(RArgs a) {
             atomicAdd(&a.stats[1], ns);
             atomicAdd(&a.stats[2], (unsigned long long)__popcll(hits));
             atomicAdd(&a.stats[7], (unsigned long long)(le - ls));
+            atomicAdd(&a.stats[10], (unsigned long long)__popcll(rays));
             atomicAdd(&a.stats[8], (unsigned long long)rounds);
         }
         const unsigned long long steps = (unsigned long long)wave_sum(nsteps);
         if (lane == 0 && rays) {
             atomicAdd(&a.stats[9], steps);
         }
+    }
+}
+
+// Persistent compositing kernel: each single-wave workgroup takes non-empty
+// tiles from the queue until it is exhausted (every wave reaches the exit).
+template <int C, int ST, typename R, int MODE>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MODE == 1 ? 1 : ART_RENDER_WAVES_PER_EU)))
+void k_render(RArgs a) {
+    __shared__ uint32_t s_mask[1][16][kStage];
+    __shared__ uint16_t s_pref[1][16][kStage];
+    __shared__ uint32_t s_row[1][kStage];
+    __shared__ uint32_t s_coord[1][kStage];
+    const int lane = threadIdx.x & 63;
+    const uint32_t n_items = *a.n_items;
+    while (true) {
+        uint32_t idx = 0;
+        if (lane == 0) idx = atomicAdd(a.queue, 1u);
+        idx = (uint32_t)__shfl((int)idx, 0, kWave);
+        if (idx >= n_items) break;
+        render_tile<C, ST, R, MODE>(a, a.items[idx], lane, s_mask, s_pref, s_row, s_coord);
+        wave_sync();
     }
 }
 
