@@ -56,20 +56,14 @@ struct DeviceGuard {
 
 bool supported_C(int C) { return C == 4 || C == 8 || C == 16 || C == 32; }
 
-// k_accum: fold one pose's counters into the run statistics.
-__global__ void k_accum(const PoseCounters* __restrict__ c, unsigned long long* __restrict__ st,
-                        uint32_t n) {
-    atomicAdd(&st[3], (unsigned long long)c->dropped);
-    atomicAdd(&st[4], (unsigned long long)(n - c->dropped - c->M));
-    atomicAdd(&st[5], (unsigned long long)c->nb);
-}
-
-// k_pairs: record a view group's pair count / overflow for the host.
-__global__ void k_pairs(const PoseCounters* __restrict__ c, unsigned long long* __restrict__ st,
-                        uint32_t* __restrict__ ovf) {
-    atomicAdd(&st[6], (unsigned long long)c->npairs);
-    ovf[0] = c->overflow;
-    ovf[1] = c->npairs;
+// k_accum: fold the counters of a batch of poses into the run statistics.
+__global__ void k_accum(const PoseCounters* __restrict__ c, unsigned long long* __restrict__ st, uint32_t n,
+                        int batch) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= batch) return;
+    atomicAdd(&st[3], (unsigned long long)c[p].dropped);
+    atomicAdd(&st[4], (unsigned long long)(n - c[p].dropped - c[p].M));
+    atomicAdd(&st[5], (unsigned long long)c[p].nb);
 }
 
 struct CallPlan {
@@ -149,8 +143,9 @@ size_t slot_bytes(const art_ctx* ctx, const CallPlan& pl, size_t pair_cap) {
     const size_t n = (size_t)ctx->n;
     const size_t es = pl.storage ? 2 : 4;
     const size_t tiles = (size_t)ctx->V * ((ctx->W + 7) / 8) * ((ctx->H + 7) / 8);
-    return n * (4 + 4 + 4 + 4 + 64 + es * (pl.C + 1)) + (size_t)pl.ngroups * pair_cap * 4 + tiles * 8 +
-           (size_t)pl.ngroups * 8;
+    // octree slot + sort scratch + bin counts + tile lists and their sort scratch + tile ranges
+    return n * (4 + 4 + 4 + 4 + 64 + es * (pl.C + 1)) + n * 16 + n * pl.Vg * 8 +
+           (size_t)pl.ngroups * pair_cap * 8 + pair_cap * 8 + tiles * 12 + (size_t)pl.ngroups * 9;
 }
 
 // Sort / scan scratch and the per-slot arrays of `slots` poses.
@@ -163,19 +158,22 @@ art_status ensure_scratch(art_ctx* ctx, const CallPlan& pl, int slots) {
     const size_t tiles_g = (size_t)pl.Vg * ((ctx->W + 7) / 8) * ((ctx->H + 7) / 8);
     if (s.pair_cap == 0) s.pair_cap = initial_pair_cap(tiles_g);
     const size_t S = (size_t)slots;
+    const size_t nblk = (size_t)std::max(kScanBlocks, kUniqueBlocks);
+    s.bin_stride = n * pl.Vg;
     art_status rc = ensure_bufs(ctx, {
-        {&s.keys0, n * 4}, {&s.vals0, n * 4}, {&s.keys1, n * 4}, {&s.vals1, n * 4},
-        {&s.hist, 256 * (size_t)kSortBlocks * 4}, {&s.digit_tot, 256 * 4},
-        {&s.blk0, (size_t)kScanBlocks * 4}, {&s.blk1, (size_t)kScanBlocks * 4},
-        {&s.counters, sizeof(PoseCounters)}, {&s.stats, 16 * sizeof(unsigned long long)},
+        {&s.keys0, S * n * 4}, {&s.vals0, S * n * 4}, {&s.keys1, S * n * 4}, {&s.vals1, S * n * 4},
+        {&s.hist, S * 256 * (size_t)kSortBlocks * 4}, {&s.digit_tot, S * 256 * 4},
+        {&s.blk0, S * nblk * 4}, {&s.blk1, S * nblk * 4},
+        {&s.counters, S * sizeof(PoseCounters)}, {&s.stats, 16 * sizeof(unsigned long long)},
         {&ctx->B64, (size_t)ctx->P * ctx->J * 12 * 8}, {&ctx->B32, (size_t)ctx->P * ctx->J * 12 * 4},
         {&ctx->Gtmp, (size_t)ctx->P * ctx->J * 12 * 8},
         {&s.occ_key, S * n * 4}, {&s.occ_win, S * n * 4},
         {&s.brick_key, S * n * 4}, {&s.brick_row, S * (n + 1) * 4}, {&s.brick_mask, S * n * 64},
         {&s.flut_sig, S * n * es}, {&s.flut_feat, S * n * pl.C * es},
-        {&s.bin_cnt, n * pl.Vg * 4}, {&s.bin_off, n * pl.Vg * 4},
-        {&s.pk0, s.pair_cap * 4}, {&s.pv0, s.pair_cap * 4}, {&s.pk1, s.pair_cap * 4},
+        {&s.bin_cnt, S * n * pl.Vg * 4}, {&s.bin_off, S * n * pl.Vg * 4},
+        {&s.pk0, S * s.pair_cap * 4}, {&s.pk1, S * s.pair_cap * 4}, {&s.pv0, S * pl.ngroups * s.pair_cap * 4},
         {&s.pair_v, S * pl.ngroups * s.pair_cap * 4},
+        {&s.redo, S * pl.ngroups},
         {&s.tile_start, S * tiles * 4}, {&s.tile_end, S * tiles * 4},
         {&s.ovf, S * pl.ngroups * 2 * 4},
         {&s.items, S * tiles * 4}, {&s.queue, 64},
@@ -256,82 +254,88 @@ struct PassOut {
     bool single_pose = false;   // maps hold one pose only
 };
 
-// Skin + sort + octree build of pose p into slot `slot`.
-art_status build_pose(art_ctx* ctx, const CallPlan& pl, int p, int slot, const void* sigma,
-                      const void* feat, int* launches, Timing& tm) {
+// Skin + sort + octree build of poses [p0, p0 + batch) into slots 0..batch-1.
+art_status build_batch(art_ctx* ctx, const CallPlan& pl, int p0, int batch, const void* sigma, const void* feat,
+                       int* launches, Timing& tm) {
     Scratch& s = ctx->s;
     hipStream_t st = ctx->stream;
     PoseCounters* cnt = s.counters.as<PoseCounters>();
+    const size_t n = (size_t)ctx->n;
     tm.record(st, -1);
-    ART_TRY_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(cnt), 0u, sizeof(PoseCounters) / 4, st), "fill");
-    ART_TRY_HIP(launch_fill_u32(&cnt->pad[2], (uint32_t)ctx->n, 1, st), "fill");
-    ART_TRY_HIP(launch_skin(ctx->ijk.as<uint16_t>(), ctx->bone.as<uint8_t>(), ctx->weight.as<float>(),
-                            ctx->n, ctx->depth, ctx->B64.as<double>() + (size_t)p * ctx->J * 12,
-                            ctx->B32.as<float>() + (size_t)p * ctx->J * 12, ctx->J, pl.fp32,
+    ART_TRY_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(cnt), 0u, (size_t)batch * sizeof(PoseCounters) / 4, st),
+                "fill");
+    ART_TRY_HIP(launch_skin(ctx->ijk.as<uint16_t>(), ctx->bone.as<uint8_t>(), ctx->weight.as<float>(), ctx->n,
+                            ctx->depth, ctx->B64.as<double>() + (size_t)p0 * ctx->J * 12,
+                            ctx->B32.as<float>() + (size_t)p0 * ctx->J * 12, ctx->J, pl.fp32, batch,
                             s.keys0.as<uint32_t>(), s.vals0.as<uint32_t>(), st),
                 "skin");
-    *launches += 3;
+    *launches += 2;
     tm.record(st, 1);
+    // every pose sorts n keys: the count word of the first pose serves them all
+    ART_TRY_HIP(launch_fill_u32(&cnt[0].pad[2], (uint32_t)n, 1, st), "fill");
+    SortBatch sb;
+    sb.k0 = s.keys0.as<uint32_t>();
+    sb.k1 = s.keys1.as<uint32_t>();
+    sb.v0 = s.vals0.as<uint32_t>();
+    sb.v1 = s.vals1.as<uint32_t>();
+    sb.kstride = n;
+    sb.vstride = n;
+    sb.d_n = &cnt[0].pad[2];
+    sb.nstride = 0;
+    sb.n_cap = (uint32_t)n;
+    sb.hist = s.hist.as<uint32_t>();
+    sb.digit_tot = s.digit_tot.as<uint32_t>();
+    sb.batch = batch;
     bool in1 = false;
-    ART_TRY_HIP(launch_radix_sort(s.keys0.as<uint32_t>(), s.vals0.as<uint32_t>(), s.keys1.as<uint32_t>(),
-                                  s.vals1.as<uint32_t>(), &cnt->pad[2], (uint32_t)ctx->n, 32,
-                                  s.hist.as<uint32_t>(), s.digit_tot.as<uint32_t>(), st, &in1, launches),
-                "radix sort");
+    ART_TRY_HIP(launch_radix_sort(sb, 32, st, &in1, launches), "radix sort");
     const uint32_t* sk = in1 ? s.keys1.as<uint32_t>() : s.keys0.as<uint32_t>();
     const uint32_t* sv = in1 ? s.vals1.as<uint32_t>() : s.vals0.as<uint32_t>();
-    ART_TRY_HIP(launch_build_octree(sk, sv, (uint32_t)ctx->n, pl.C, pl.storage, sigma, feat, s,
-                                    octree_slot(ctx, pl, slot), st, launches),
+    ART_TRY_HIP(launch_build_octree(sk, sv, (uint32_t)n, pl.C, pl.storage, sigma, feat, s, octree_slot(ctx, pl, 0),
+                                    batch, st, launches),
                 "octree build");
+    hipLaunchKernelGGL(k_accum, dim3((batch + 63) / 64), dim3(64), 0, st, (const PoseCounters*)cnt,
+                       s.stats.as<unsigned long long>(), (uint32_t)n, batch);
+    *launches += 2;
     tm.record(st, 2);
     return ART_OK;
 }
 
 // One batch of poses [p0, p1): build every pose into its slot, bin its view
 // groups, then render all (pose, view) maps of the batch in one launch.
-// `redo` (indexed by slot * ngroups + group) restricts the batch to the
+// `redo` (indexed by slot * ngroups + group) restricts the render to the
 // (pose, group) items whose tile lists overflowed in an earlier attempt.
 art_status run_batch(art_ctx* ctx, const CallPlan& pl, int mode, float lambda, const void* sigma,
                      const void* feat, const PassOut& o, int p0, int p1,
                      const std::vector<char>* redo, int* launches, Timing& tm) {
     Scratch& s = ctx->s;
     hipStream_t st = ctx->stream;
-    PoseCounters* cnt = s.counters.as<PoseCounters>();
-    unsigned long long* stats = s.stats.as<unsigned long long>();
     const int Pb = p1 - p0;
     const size_t TPV = (size_t)((ctx->W + 7) / 8) * ((ctx->H + 7) / 8);
-    // slots not (re)built in this attempt are skipped by the render kernel
-    ART_TRY_HIP(launch_fill_u32(s.ovf.as<uint32_t>(), redo ? 1u : 0u, (size_t)Pb * pl.ngroups * 2, st), "fill");
-    *launches += 1;
-    for (int p = p0; p < p1; ++p) {
-        const int slot = p - p0;
-        bool any = true;
-        if (redo) {
-            any = false;
-            for (int gi = 0; gi < pl.ngroups; ++gi) any = any || (*redo)[(size_t)slot * pl.ngroups + gi];
-        }
-        if (!any) continue;
-        art_status rc = build_pose(ctx, pl, p, slot, sigma, feat, launches, tm);
-        if (rc != ART_OK) return rc;
-        hipLaunchKernelGGL(k_accum, dim3(1), dim3(1), 0, st, (const PoseCounters*)cnt, stats, (uint32_t)ctx->n);
-        *launches += 1;
-        const OctreeSlot os = octree_slot(ctx, pl, slot);
-        for (int gi = 0; gi < pl.ngroups; ++gi) {
-            const size_t sg = (size_t)slot * pl.ngroups + gi;
-            if (redo && !(*redo)[sg]) continue;
-            const int v0 = gi * pl.Vg;
-            const int Vg = std::min(ctx->V, v0 + pl.Vg) - v0;
-            tm.record(st, -1);
-            uint32_t* ts = s.tile_start.as<uint32_t>() + ((size_t)slot * ctx->V + v0) * TPV;
-            uint32_t* te = s.tile_end.as<uint32_t>() + ((size_t)slot * ctx->V + v0) * TPV;
-            ART_TRY_HIP(launch_bin(s, ctx->cam.as<CamParams>(), os.brick_key, v0, Vg, ctx->H, ctx->W, ctx->depth,
-                                   pl.fp32, s.pair_v.as<uint32_t>() + sg * s.pair_cap, ts, te, st, launches),
-                        "tile binning");
-            hipLaunchKernelGGL(k_pairs, dim3(1), dim3(1), 0, st, (const PoseCounters*)cnt, stats,
-                               s.ovf.as<uint32_t>() + 2 * sg);
-            *launches += 1;
-            tm.record(st, 3);
-        }
+    art_status rc = build_batch(ctx, pl, p0, Pb, sigma, feat, launches, tm);
+    if (rc != ART_OK) return rc;
+    const uint8_t* redo_dev = nullptr;
+    if (redo) {
+        std::vector<uint8_t> m(redo->begin(), redo->end());
+        ART_TRY_HIP(hipMemcpyAsync(s.redo.p, m.data(), m.size(), hipMemcpyHostToDevice, st), "copy");
+        ART_TRY_HIP(hipStreamSynchronize(st), "copy");
+        redo_dev = s.redo.as<uint8_t>();
     }
+    tm.record(st, -1);
+    ART_TRY_HIP(launch_fill_u32(s.tile_start.as<uint32_t>(), 0u, (size_t)Pb * ctx->V * TPV, st), "fill");
+    ART_TRY_HIP(launch_fill_u32(s.tile_end.as<uint32_t>(), 0u, (size_t)Pb * ctx->V * TPV, st), "fill");
+    *launches += 2;
+    const OctreeSlot os = octree_slot(ctx, pl, 0);
+    for (int gi = 0; gi < pl.ngroups; ++gi) {
+        const int v0 = gi * pl.Vg;
+        const int Vg = std::min(ctx->V, v0 + pl.Vg) - v0;
+        ART_TRY_HIP(launch_bin(s, ctx->cam.as<CamParams>(), os, (size_t)ctx->n, Pb, ctx->V, v0, Vg, gi, pl.ngroups,
+                               ctx->H, ctx->W, ctx->depth, pl.fp32, st, launches),
+                    "tile binning");
+        hipLaunchKernelGGL(k_pairs, dim3((Pb + 63) / 64), dim3(64), 0, st, (const PoseCounters*)s.counters.as<PoseCounters>(),
+                           s.stats.as<unsigned long long>(), s.ovf.as<uint32_t>(), pl.ngroups, gi, redo_dev, Pb);
+        *launches += 1;
+    }
+    tm.record(st, 3);
     tm.record(st, -1);
     RenderLaunch r{};
     r.C = pl.C;
@@ -579,8 +583,9 @@ void art_destroy(art_ctx* ctx) {
                           &ctx->s.digit_tot, &ctx->s.blk0, &ctx->s.blk1, &ctx->s.occ_key, &ctx->s.occ_win,
                           &ctx->s.brick_key, &ctx->s.brick_row, &ctx->s.brick_mask, &ctx->s.flut_sig,
                           &ctx->s.flut_feat, &ctx->s.bin_cnt, &ctx->s.bin_off, &ctx->s.pk0, &ctx->s.pv0,
-                          &ctx->s.pk1, &ctx->s.pv1, &ctx->s.tile_start, &ctx->s.tile_end,
-                          &ctx->s.counters, &ctx->s.stats, &ctx->s.ovf};
+                          &ctx->s.pk1, &ctx->s.pair_v, &ctx->s.tile_start, &ctx->s.tile_end,
+                          &ctx->s.counters, &ctx->s.stats, &ctx->s.ovf, &ctx->s.items, &ctx->s.queue,
+                          &ctx->s.redo};
         for (DevBuf* b : bufs) b->release();
     }
     delete ctx;
@@ -870,7 +875,7 @@ art_status art_get_posed_keys(art_ctx* ctx, int pose, unsigned flags, uint32_t* 
     ART_TRY_HIP(launch_skin(ctx->ijk.as<uint16_t>(), ctx->bone.as<uint8_t>(), ctx->weight.as<float>(), ctx->n,
                             ctx->depth, ctx->B64.as<double>() + (size_t)pose * ctx->J * 12,
                             ctx->B32.as<float>() + (size_t)pose * ctx->J * 12, ctx->J,
-                            (flags & ART_GEOM_FP32) != 0, keys, ctx->s.vals0.as<uint32_t>(), st),
+                            (flags & ART_GEOM_FP32) != 0, 1, keys, ctx->s.vals0.as<uint32_t>(), st),
                 "skin");
     ART_TRY_HIP(hipStreamSynchronize(st), "skin");
     return ART_OK;
@@ -913,7 +918,7 @@ art_status art_get_octree(art_ctx* ctx, int pose, unsigned flags, int64_t* count
     }
     Timing tm;
     int launches = 0;
-    rc = build_pose(ctx, pl, pose, 0, zs.p, zf.p, &launches, tm);
+    rc = build_batch(ctx, pl, pose, 1, zs.p, zf.p, &launches, tm);
     PoseCounters hc{};
     if (rc == ART_OK) {
         e = hipMemcpyAsync(&hc, ctx->s.counters.p, sizeof(hc), hipMemcpyDeviceToHost, st);

@@ -61,25 +61,28 @@ struct RunStats {
 };
 
 constexpr int kNumStats = 12;
-constexpr int kSortBlocks = 512;      // fixed grid of the radix-sort passes
-constexpr int kScanBlocks = 1024;     // fixed grid of device-sized scans
-constexpr int kUniqueBlocks = 1024;   // fixed grid of the unique / compaction step
+constexpr int kSortBlocks = 512;      // fixed grid (per pose) of the radix-sort passes
+constexpr int kScanBlocks = 256;      // fixed grid (per pose) of device-sized scans
+constexpr int kUniqueBlocks = 512;    // fixed grid (per pose) of the unique / compaction step
 
 struct Scratch {
-    DevBuf keys0, vals0, keys1, vals1;   // sort ping-pong [n]
-    DevBuf hist, digit_tot;              // [256 * kSortBlocks], [256]
-    DevBuf blk0, blk1;                   // block partials [kScanBlocks]
+    DevBuf keys0, vals0, keys1, vals1;   // sort ping-pong [slots][n]
+    DevBuf hist, digit_tot;              // [slots][256 * kSortBlocks], [slots][256]
+    DevBuf blk0, blk1;                   // block partials [slots][max(kScanBlocks, kUniqueBlocks)]
     DevBuf occ_key, occ_win;             // [slots][n] posed cells + winners
     DevBuf brick_key, brick_row, brick_mask;  // [slots][n], [slots][n+1], [slots][n*16]
     DevBuf flut_sig, flut_feat;          // [slots][n] posed-order FLUT rows
-    DevBuf bin_cnt, bin_off;             // [n*V]
-    DevBuf pk0, pv0, pk1, pv1;           // pair sort scratch [pair_cap]
+    DevBuf bin_cnt, bin_off;             // [slots][n * Vg]
+    size_t bin_stride = 0;               // n * Vg
+    DevBuf pk0, pk1;                     // pair sort keys [slots][pair_cap]
+    DevBuf pv0;                          // pair sort payload scratch [slots][groups][pair_cap]
     DevBuf pair_v;                       // [slots][groups][pair_cap] sorted brick ids
     DevBuf tile_start, tile_end;         // [slots][V][tiles]
-    DevBuf counters;                     // PoseCounters
+    DevBuf counters;                     // PoseCounters [slots]
     DevBuf stats;                        // RunStats
     DevBuf ovf;                          // [slots][groups][2] overflow flag, pair count
     DevBuf items;                        // [slots][V][tiles] compacted non-empty tiles
+    DevBuf redo;                         // [slots][groups] items re-run after an overflow
     DevBuf queue;                        // [2] item count, queue head
     size_t pair_cap = 0;
     int slots = 0;                       // poses whose octrees are held at once
@@ -130,18 +133,32 @@ struct art_ctx {
 namespace art {
 
 // ---- launchers (each enqueues on `st`) ------------------------------------
+// Kernels of the octree build run for a batch of poses at once (pose =
+// blockIdx.y); per-pose arrays are addressed as base + pose * stride.
 hipError_t launch_fk(const int32_t* parent, const double* rest, const double* pose, int J, int P,
                      double* G, double* B64, float* B32, hipStream_t st);
 hipError_t launch_skin(const uint16_t* ijk, const uint8_t* bone, const float* w, int64_t n,
-                       int depth, const double* B64, const float* B32, int J, bool fp32,
+                       int depth, const double* B64, const float* B32, int J, bool fp32, int batch,
                        uint32_t* keys, uint32_t* vals, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t st);
-hipError_t launch_radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1,
-                             const uint32_t* d_n, uint32_t n_cap, int bits, uint32_t* hist,
-                             uint32_t* digit_tot, hipStream_t st, bool* result_in_1, int* launches);
-hipError_t launch_scan_exclusive(const uint32_t* in, uint32_t* out, const uint32_t* d_n,
-                                 uint32_t* d_total, uint32_t* blk, hipStream_t st, int* launches);
-// Posed octree of one pose (one slot of the per-pose arrays).
+
+struct SortBatch {
+    uint32_t *k0, *k1;    // keys (ping-pong), pose stride kstride
+    uint32_t *v0, *v1;    // payloads (ping-pong), pose stride vstride
+    size_t kstride, vstride;
+    const uint32_t* d_n;  // item count of pose p at d_n[p * nstride]
+    uint32_t nstride;
+    uint32_t n_cap;       // largest item count (sizes the grid)
+    uint32_t* hist;       // [batch][256 * kSortBlocks]
+    uint32_t* digit_tot;  // [batch][256]
+    int batch;
+};
+hipError_t launch_radix_sort(const SortBatch& b, int bits, hipStream_t st, bool* result_in_1, int* launches);
+hipError_t launch_scan_exclusive(const uint32_t* in, uint32_t* out, size_t stride, const uint32_t* d_n,
+                                 uint32_t nstride, uint32_t* d_total, uint32_t tstride, uint32_t* blk, int batch,
+                                 hipStream_t st, int* launches);
+
+// Posed octrees of a batch of poses (slot p at base + p * stride).
 struct OctreeSlot {
     uint32_t* occ_key;      // [n]
     uint32_t* occ_win;      // [n]
@@ -151,15 +168,19 @@ struct OctreeSlot {
     void* psig;             // [n] posed-order densities
     void* pfeat;            // [n][C] posed-order features
 };
-hipError_t launch_build_octree(const uint32_t* skeys, const uint32_t* svals, uint32_t n,
-                               int C, int storage, const void* sigma, const void* feat,
-                               Scratch& s, const OctreeSlot& o, hipStream_t st, int* launches);
+hipError_t launch_build_octree(const uint32_t* skeys, const uint32_t* svals, uint32_t n, int C, int storage,
+                               const void* sigma, const void* feat, Scratch& s, const OctreeSlot& o, int batch,
+                               hipStream_t st, int* launches);
 int bin_key_bits(int Vg, int H, int W, int depth, int* mbits);
-// Tile lists of views [v0, v0 + Vg) of one pose: sorted brick ids into pair_out
-// (capacity s.pair_cap) and per-tile ranges into tile_start / tile_end [Vg][TPV].
-hipError_t launch_bin(Scratch& s, const CamParams* cam_dev, const uint32_t* brick_key, int v0, int Vg,
-                      int H, int W, int depth, bool fp32, uint32_t* pair_out, uint32_t* tile_start,
-                      uint32_t* tile_end, hipStream_t st, int* launches);
+// Tile lists of views [v0, v0 + Vg) of every pose of the batch: sorted brick
+// ids into pair_v + (p * ngroups + group) * pair_cap, per-tile ranges into
+// tile_start / tile_end + (p * V + v0) * TPV.
+hipError_t launch_bin(Scratch& s, const CamParams* cam_dev, const OctreeSlot& o, size_t n, int batch, int V, int v0,
+                      int Vg, int group, int ngroups, int H, int W, int depth, bool fp32, hipStream_t st,
+                      int* launches);
+__global__ void k_pairs(const PoseCounters* __restrict__ c, unsigned long long* __restrict__ st,
+                        uint32_t* __restrict__ ovf, int ngroups, int group, const uint8_t* __restrict__ redo,
+                        int batch);
 
 struct RenderLaunch {
     int C, storage;

@@ -94,9 +94,11 @@ __device__ inline void eye_brick(const CamParams& c, const BinGeom& g, int* e) {
 }
 
 __global__ void k_bin_count(const CamParams* __restrict__ cam, const uint32_t* __restrict__ brick_key,
-                            const PoseCounters* __restrict__ cnt, BinGeom g,
-                            uint32_t* __restrict__ out) {
-    const uint32_t total = cnt->nb * (uint32_t)g.Vg;
+                            size_t key_stride, const PoseCounters* __restrict__ cnt, BinGeom g,
+                            uint32_t* __restrict__ out, size_t out_stride) {
+    brick_key += blockIdx.y * key_stride;
+    out += blockIdx.y * out_stride;
+    const uint32_t total = cnt[blockIdx.y].nb * (uint32_t)g.Vg;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
         const uint32_t b = i / g.Vg;
         const int v = g.v0 + (int)(i % g.Vg);
@@ -111,9 +113,14 @@ __global__ void k_bin_count(const CamParams* __restrict__ cam, const uint32_t* _
 
 template <typename R>
 __global__ void k_bin_emit(const CamParams* __restrict__ cam, const uint32_t* __restrict__ brick_key,
-                           PoseCounters* __restrict__ cnt, BinGeom g,
-                           const uint32_t* __restrict__ off, uint32_t* __restrict__ pk,
-                           uint32_t* __restrict__ pv) {
+                           size_t key_stride, PoseCounters* __restrict__ cnt, BinGeom g,
+                           const uint32_t* __restrict__ off, size_t off_stride, uint32_t* __restrict__ pk,
+                           size_t pk_stride, uint32_t* __restrict__ pv, size_t pv_stride) {
+    brick_key += blockIdx.y * key_stride;
+    cnt += blockIdx.y;
+    off += blockIdx.y * off_stride;
+    pk += blockIdx.y * pk_stride;
+    pv += blockIdx.y * pv_stride;
     const uint32_t total = cnt->nb * (uint32_t)g.Vg;
     const uint32_t npairs = cnt->npairs;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -141,9 +148,13 @@ __global__ void k_bin_emit(const CamParams* __restrict__ cam, const uint32_t* __
     }
 }
 
-__global__ void k_tile_mark(const uint32_t* __restrict__ pk, const PoseCounters* __restrict__ cnt,
-                            int mbits, uint32_t* __restrict__ tstart, uint32_t* __restrict__ tend) {
-    const uint32_t n = cnt->pad[0];
+__global__ void k_tile_mark(const uint32_t* __restrict__ pk, size_t pk_stride,
+                            const PoseCounters* __restrict__ cnt, int mbits, uint32_t* __restrict__ tstart,
+                            uint32_t* __restrict__ tend, size_t t_stride) {
+    pk += blockIdx.y * pk_stride;
+    tstart += blockIdx.y * t_stride;
+    tend += blockIdx.y * t_stride;
+    const uint32_t n = cnt[blockIdx.y].pad[0];
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         const uint32_t t = pk[i] >> mbits;
         if (i == 0 || (pk[i - 1] >> mbits) != t) tstart[t] = i;
@@ -181,52 +192,83 @@ int bin_key_bits(int Vg, int H, int W, int depth, int* mbits) {
     return bits_for((uint64_t)Vg * g.TPV - 1) + g.mbits;
 }
 
-__global__ void k_bin_items(PoseCounters* __restrict__ cnt, uint32_t Vg) {
-    cnt->pad[1] = cnt->nb * Vg;
+__global__ void k_bin_items(PoseCounters* __restrict__ cnt, uint32_t Vg, int batch) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < batch) cnt[p].pad[1] = cnt[p].nb * Vg;
 }
 
-// count -> scan -> emit -> stable sort -> per-tile ranges.  The sorted brick
-// ids end in pair_out; the sort ping-pongs between the scratch buffer and
-// pair_out so that its last pass writes pair_out.
-hipError_t launch_bin(Scratch& s, const CamParams* cam_dev, const uint32_t* brick_key, int v0, int Vg,
-                      int H, int W, int depth, bool fp32, uint32_t* pair_out, uint32_t* tile_start,
-                      uint32_t* tile_end, hipStream_t st, int* launches) {
+// Pair counts of a view group for the host: overflow flag and pair count per
+// pose (a pose outside `redo`, when given, is marked done so the compositing
+// kernel skips it).
+__global__ void k_pairs(const PoseCounters* __restrict__ c, unsigned long long* __restrict__ st,
+                        uint32_t* __restrict__ ovf, int ngroups, int group, const uint8_t* __restrict__ redo,
+                        int batch) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= batch) return;
+    const size_t slot = (size_t)p * ngroups + group;
+    if (redo && !redo[slot]) {
+        ovf[2 * slot] = 1u;
+        ovf[2 * slot + 1] = 0u;
+        return;
+    }
+    atomicAdd(&st[6], (unsigned long long)c[p].npairs);
+    ovf[2 * slot] = c[p].overflow;
+    ovf[2 * slot + 1] = c[p].npairs;
+}
+
+// count -> scan -> emit -> stable sort -> per-tile ranges for one view group
+// of every pose in the batch.  The sort ping-pongs between the scratch payload
+// buffer and the persistent tile lists so that its last pass writes the lists.
+hipError_t launch_bin(Scratch& s, const CamParams* cam_dev, const OctreeSlot& o, size_t n, int batch, int V, int v0,
+                      int Vg, int group, int ngroups, int H, int W, int depth, bool fp32, hipStream_t st,
+                      int* launches) {
     BinGeom g = make_geom(s, v0, Vg, H, W, depth);
     const int key_bits = bits_for((uint64_t)Vg * g.TPV - 1) + g.mbits;
     const int passes = (key_bits + 7) / 8;
     PoseCounters* cnt = s.counters.as<PoseCounters>();
-    hipLaunchKernelGGL(k_bin_items, dim3(1), dim3(1), 0, st, cnt, (uint32_t)Vg);
-    hipLaunchKernelGGL(k_bin_count, dim3(2048), dim3(256), 0, st, cam_dev, brick_key,
-                       (const PoseCounters*)cnt, g, s.bin_cnt.as<uint32_t>());
+    hipLaunchKernelGGL(k_bin_items, dim3((batch + 63) / 64), dim3(64), 0, st, cnt, (uint32_t)Vg, batch);
+    hipLaunchKernelGGL(k_bin_count, dim3(256, batch), dim3(256), 0, st, cam_dev, o.brick_key, n,
+                       (const PoseCounters*)cnt, g, s.bin_cnt.as<uint32_t>(), s.bin_stride);
     *launches += 2;
-    hipError_t e = launch_scan_exclusive(s.bin_cnt.as<uint32_t>(), s.bin_off.as<uint32_t>(),
-                                         &cnt->pad[1], &cnt->npairs, s.blk0.as<uint32_t>(), st,
-                                         launches);
+    hipError_t e = launch_scan_exclusive(s.bin_cnt.as<uint32_t>(), s.bin_off.as<uint32_t>(), s.bin_stride,
+                                         &cnt[0].pad[1], sizeof(PoseCounters) / 4, &cnt[0].npairs,
+                                         sizeof(PoseCounters) / 4, s.blk0.as<uint32_t>(), batch, st, launches);
     if (e != hipSuccess) return e;
+    const size_t vstride = (size_t)ngroups * s.pair_cap;
+    uint32_t* lists = s.pair_v.as<uint32_t>() + (size_t)group * s.pair_cap;
+    uint32_t* scratch = s.pv0.as<uint32_t>() + (size_t)group * s.pair_cap;
     // an even number of passes ends where it starts
-    uint32_t* v_first = (passes & 1) ? s.pv0.as<uint32_t>() : pair_out;
-    uint32_t* v_second = (passes & 1) ? pair_out : s.pv0.as<uint32_t>();
+    uint32_t* v_first = (passes & 1) ? scratch : lists;
+    uint32_t* v_second = (passes & 1) ? lists : scratch;
     if (fp32)
-        hipLaunchKernelGGL(k_bin_emit<float>, dim3(2048), dim3(256), 0, st, cam_dev, brick_key, cnt, g,
-                           s.bin_off.as<uint32_t>(), s.pk0.as<uint32_t>(), v_first);
+        hipLaunchKernelGGL(k_bin_emit<float>, dim3(256, batch), dim3(256), 0, st, cam_dev, o.brick_key, n, cnt, g,
+                           s.bin_off.as<uint32_t>(), s.bin_stride, s.pk0.as<uint32_t>(), s.pair_cap, v_first, vstride);
     else
-        hipLaunchKernelGGL(k_bin_emit<double>, dim3(2048), dim3(256), 0, st, cam_dev, brick_key, cnt, g,
-                           s.bin_off.as<uint32_t>(), s.pk0.as<uint32_t>(), v_first);
+        hipLaunchKernelGGL(k_bin_emit<double>, dim3(256, batch), dim3(256), 0, st, cam_dev, o.brick_key, n, cnt, g,
+                           s.bin_off.as<uint32_t>(), s.bin_stride, s.pk0.as<uint32_t>(), s.pair_cap, v_first, vstride);
     *launches += 1;
+    SortBatch sb;
+    sb.k0 = s.pk0.as<uint32_t>();
+    sb.k1 = s.pk1.as<uint32_t>();
+    sb.kstride = s.pair_cap;
+    sb.v0 = v_first;
+    sb.v1 = v_second;
+    sb.vstride = vstride;
+    sb.d_n = &cnt[0].pad[0];
+    sb.nstride = sizeof(PoseCounters) / 4;
+    sb.n_cap = (uint32_t)s.pair_cap;
+    sb.hist = s.hist.as<uint32_t>();
+    sb.digit_tot = s.digit_tot.as<uint32_t>();
+    sb.batch = batch;
     bool in1 = false;
-    e = launch_radix_sort(s.pk0.as<uint32_t>(), v_first, s.pk1.as<uint32_t>(), v_second, &cnt->pad[0],
-                          (uint32_t)s.pair_cap, key_bits, s.hist.as<uint32_t>(),
-                          s.digit_tot.as<uint32_t>(), st, &in1, launches);
+    e = launch_radix_sort(sb, key_bits, st, &in1, launches);
     if (e != hipSuccess) return e;
     const uint32_t* pk = in1 ? s.pk1.as<uint32_t>() : s.pk0.as<uint32_t>();
-    const size_t tiles = (size_t)Vg * g.TPV;
-    e = launch_fill_u32(tile_start, 0u, tiles, st);
-    if (e != hipSuccess) return e;
-    e = launch_fill_u32(tile_end, 0u, tiles, st);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_tile_mark, dim3(2048), dim3(256), 0, st, pk, (const PoseCounters*)cnt, g.mbits,
-                       tile_start, tile_end);
-    *launches += 3;
+    const size_t TPVg = (size_t)V * g.TPV;   // tile stride per pose
+    hipLaunchKernelGGL(k_tile_mark, dim3(256, batch), dim3(256), 0, st, pk, s.pair_cap, (const PoseCounters*)cnt,
+                       g.mbits, s.tile_start.as<uint32_t>() + (size_t)v0 * g.TPV,
+                       s.tile_end.as<uint32_t>() + (size_t)v0 * g.TPV, TPVg);
+    *launches += 1;
     return hipGetLastError();
 }
 

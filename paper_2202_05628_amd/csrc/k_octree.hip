@@ -19,6 +19,10 @@
 #include "device_util.h"
 #include "internal.h"
 
+#ifndef ART_GATHER_CANONICAL
+#define ART_GATHER_CANONICAL 0
+#endif
+
 namespace art {
 
 constexpr int kUThreads = 256;
@@ -29,9 +33,14 @@ __global__ __launch_bounds__(kUThreads) void k_unique_count(const uint32_t* __re
                                                             uint32_t* __restrict__ blk_brick,
                                                             PoseCounters* __restrict__ cnt) {
     __shared__ uint32_t sr[kUThreads / kWave], sb[kUThreads / kWave], sd[kUThreads / kWave];
+    const uint32_t p = blockIdx.y;
+    skeys += (size_t)p * n;
+    blk_run += (size_t)p * gridDim.x;
+    blk_brick += (size_t)p * gridDim.x;
+    cnt += p;
     uint32_t lo, hi;
     block_range(n, blockIdx.x, gridDim.x, kUThreads, &lo, &hi);
-    uint32_t nr = 0, nbk = 0, nd = 0;
+    uint32_t nr = 0, nbk = 0, nd = 0;   // (same block ranges as k_unique_write)
     for (uint32_t i = lo + threadIdx.x; i < hi; i += kUThreads) {
         const uint32_t k = skeys[i];
         const uint32_t kp = i > 0 ? skeys[i - 1] : kInvalidKey;
@@ -66,8 +75,13 @@ __global__ __launch_bounds__(kUThreads) void k_unique_count(const uint32_t* __re
 __global__ __launch_bounds__(1024) void k_unique_scan(uint32_t* __restrict__ blk_run,
                                                       uint32_t* __restrict__ blk_brick, int nblk,
                                                       PoseCounters* __restrict__ cnt,
-                                                      uint32_t* __restrict__ brick_row) {
+                                                      uint32_t* __restrict__ brick_row, size_t row_stride) {
     __shared__ uint32_t tmp[1024 / kWave + 1];
+    const uint32_t p = blockIdx.x;
+    blk_run += (size_t)p * nblk;
+    blk_brick += (size_t)p * nblk;
+    cnt += p;
+    brick_row += p * row_stride;
     const int t = threadIdx.x;
     uint32_t a = t < nblk ? blk_run[t] : 0u;
     uint32_t ta;
@@ -86,12 +100,18 @@ __global__ __launch_bounds__(1024) void k_unique_scan(uint32_t* __restrict__ blk
     }
 }
 
-__global__ void k_zero_masks(uint32_t* __restrict__ mask, const PoseCounters* __restrict__ cnt) {
-    const size_t total = (size_t)cnt->nb * 16;
+__global__ void k_zero_masks(uint32_t* __restrict__ mask, size_t mask_stride,
+                             const PoseCounters* __restrict__ cnt) {
+    mask += (size_t)blockIdx.y * mask_stride;
+    const size_t total = (size_t)cnt[blockIdx.y].nb * 16;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
          i += (size_t)gridDim.x * blockDim.x)
         mask[i] = 0u;
 }
+
+// Each thread owns kUItems consecutive sorted keys; one block scan of the
+// packed (cell runs | brick runs << 16) counts per 256 * kUItems keys.
+constexpr int kUItems = 8;
 
 template <int ROW_BYTES, int SIG_BYTES>
 __global__ __launch_bounds__(kUThreads) void k_unique_write(
@@ -102,94 +122,131 @@ __global__ __launch_bounds__(kUThreads) void k_unique_write(
     uint32_t* __restrict__ brick_mask, const uint8_t* __restrict__ sigma,
     const uint8_t* __restrict__ feat, uint8_t* __restrict__ psig, uint8_t* __restrict__ pfeat) {
     __shared__ uint32_t tmp[kUThreads / kWave + 1];
+    const size_t p = blockIdx.y;
+    skeys += p * n;
+    svals += p * n;
+    blk_run += p * gridDim.x;
+    blk_brick += p * gridDim.x;
+    occ_key += p * n;
+    occ_win += p * n;
+    brick_key += p * n;
+    brick_row += p * (n + 1);
+    brick_mask += p * n * 16;
+    if (ROW_BYTES > 0) {
+        psig += p * n * SIG_BYTES;
+        pfeat += p * n * ROW_BYTES;
+    }
     uint32_t lo, hi;
     block_range(n, blockIdx.x, gridDim.x, kUThreads, &lo, &hi);
     uint32_t carry_r = blk_run[blockIdx.x];
     uint32_t carry_b = blk_brick[blockIdx.x];
-    for (uint32_t i0 = lo; i0 < hi; i0 += kUThreads) {
-        const uint32_t i = i0 + threadIdx.x;
-        uint32_t k = kInvalidKey, kp = kInvalidKey;
-        if (i < hi) {
-            k = skeys[i];
-            kp = i > 0 ? skeys[i - 1] : kInvalidKey;
-        }
-        const bool valid = k != kInvalidKey;
-        const bool rs = valid && (i == 0 || kp != k);
-        const bool bs = valid && (i == 0 || (kp >> 9) != (k >> 9));
-        uint32_t tr, tb;
-        const uint32_t er = block_exclusive_scan<kUThreads>(rs ? 1u : 0u, tmp, &tr);
-        const uint32_t eb = block_exclusive_scan<kUThreads>(bs ? 1u : 0u, tmp, &tb);
-        const uint32_t m = carry_r + er;
-        const uint32_t bi = carry_b + eb + (bs ? 1u : 0u) - 1u;   // brick holding element i
-        if (bs) {
-            brick_key[bi] = k >> 9;
-            brick_row[bi] = m;
-        }
-        if (rs) {
-            const uint32_t id = svals[i];
-            occ_key[m] = k;
-            occ_win[m] = id;
-            const uint32_t local = k & 511u;
-            atomicOr(&brick_mask[(size_t)bi * 16 + (local >> 5)], 1u << (local & 31u));
-            // winner's FLUT row in posed order
-            if (SIG_BYTES == 4)
-                reinterpret_cast<uint32_t*>(psig)[m] = reinterpret_cast<const uint32_t*>(sigma)[id];
-            else
-                reinterpret_cast<uint16_t*>(psig)[m] = reinterpret_cast<const uint16_t*>(sigma)[id];
-            if constexpr (ROW_BYTES % 16 == 0) {
-                const uint4* src = reinterpret_cast<const uint4*>(feat + (size_t)id * ROW_BYTES);
-                uint4* dst = reinterpret_cast<uint4*>(pfeat + (size_t)m * ROW_BYTES);
+    for (uint32_t t0 = lo; t0 < hi; t0 += kUThreads * kUItems) {
+        const uint32_t i0 = t0 + threadIdx.x * kUItems;
+        uint32_t k[kUItems];
+        uint32_t prev = (i0 > 0 && i0 - 1 < hi) ? skeys[i0 - 1] : kInvalidKey;
+        uint32_t flags = 0;   // bit j: cell run start, bit 8 + j: brick run start
+        uint32_t nr = 0, nbk = 0;
 #pragma unroll
-                for (int q = 0; q < ROW_BYTES / 16; ++q) dst[q] = src[q];
-            } else {
-                const uint2* src = reinterpret_cast<const uint2*>(feat + (size_t)id * ROW_BYTES);
-                uint2* dst = reinterpret_cast<uint2*>(pfeat + (size_t)m * ROW_BYTES);
+        for (int j = 0; j < kUItems; ++j) {
+            const uint32_t i = i0 + j;
+            k[j] = i < hi ? skeys[i] : kInvalidKey;
+            const bool valid = k[j] != kInvalidKey;
+            const bool rs = valid && (i == 0 || prev != k[j]);
+            const bool bs = valid && (i == 0 || (prev >> 9) != (k[j] >> 9));
+            flags |= (rs ? 1u : 0u) << j;
+            flags |= (bs ? 1u : 0u) << (8 + j);
+            nr += rs ? 1u : 0u;
+            nbk += bs ? 1u : 0u;
+            prev = k[j];
+        }
+        uint32_t tot;
+        const uint32_t ex = block_exclusive_scan<kUThreads>(nr | (nbk << 16), tmp, &tot);
+        uint32_t m = carry_r + (ex & 0xFFFFu);
+        uint32_t bc = carry_b + (ex >> 16);   // bricks started before this thread's items
 #pragma unroll
-                for (int q = 0; q < ROW_BYTES / 8; ++q) dst[q] = src[q];
+        for (int j = 0; j < kUItems; ++j) {
+            const bool rs = (flags >> j) & 1u;
+            const bool bs = (flags >> (8 + j)) & 1u;
+            if (bs) {
+                brick_key[bc] = k[j] >> 9;
+                brick_row[bc] = m;
+                ++bc;
+            }
+            if (rs) {
+                const uint32_t id = svals[i0 + j];
+                occ_key[m] = k[j];
+                occ_win[m] = id;
+                const uint32_t local = k[j] & 511u;
+                atomicOr(&brick_mask[(size_t)(bc - 1) * 16 + (local >> 5)], 1u << (local & 31u));
+                if constexpr (ROW_BYTES > 0) {   // winner's FLUT row in posed order
+                    if (SIG_BYTES == 4)
+                        reinterpret_cast<uint32_t*>(psig)[m] = reinterpret_cast<const uint32_t*>(sigma)[id];
+                    else
+                        reinterpret_cast<uint16_t*>(psig)[m] = reinterpret_cast<const uint16_t*>(sigma)[id];
+                    if constexpr (ROW_BYTES % 16 == 0) {
+                        const uint4* src = reinterpret_cast<const uint4*>(feat + (size_t)id * ROW_BYTES);
+                        uint4* dst = reinterpret_cast<uint4*>(pfeat + (size_t)m * ROW_BYTES);
+#pragma unroll
+                        for (int q = 0; q < ROW_BYTES / 16; ++q) dst[q] = src[q];
+                    } else {
+                        const uint2* src = reinterpret_cast<const uint2*>(feat + (size_t)id * ROW_BYTES);
+                        uint2* dst = reinterpret_cast<uint2*>(pfeat + (size_t)m * ROW_BYTES);
+#pragma unroll
+                        for (int q = 0; q < ROW_BYTES / 8; ++q) dst[q] = src[q];
+                    }
+                }
+                ++m;
             }
         }
-        carry_r += tr;
-        carry_b += tb;
+        carry_r += tot & 0xFFFFu;
+        carry_b += tot >> 16;
     }
 }
 
 template <int ROW_BYTES, int SIG_BYTES>
 static void launch_write(const uint32_t* skeys, const uint32_t* svals, uint32_t n, Scratch& s,
-                         const OctreeSlot& o, const void* sigma, const void* feat, hipStream_t st) {
-    hipLaunchKernelGGL((k_unique_write<ROW_BYTES, SIG_BYTES>), dim3(kUniqueBlocks), dim3(kUThreads),
+                         const OctreeSlot& o, const void* sigma, const void* feat, int batch, hipStream_t st) {
+    hipLaunchKernelGGL((k_unique_write<ROW_BYTES, SIG_BYTES>), dim3(kUniqueBlocks, batch), dim3(kUThreads),
                        0, st, skeys, svals, n, s.blk0.as<uint32_t>(), s.blk1.as<uint32_t>(), o.occ_key,
                        o.occ_win, o.brick_key, o.brick_row, o.brick_mask,
                        static_cast<const uint8_t*>(sigma), static_cast<const uint8_t*>(feat),
                        static_cast<uint8_t*>(o.psig), static_cast<uint8_t*>(o.pfeat));
 }
 
-hipError_t launch_build_octree(const uint32_t* skeys, const uint32_t* svals, uint32_t n, int C,
-                               int storage, const void* sigma, const void* feat, Scratch& s,
-                               const OctreeSlot& o, hipStream_t st, int* launches) {
+hipError_t launch_build_octree(const uint32_t* skeys, const uint32_t* svals, uint32_t n, int C, int storage,
+                               const void* sigma, const void* feat, Scratch& s, const OctreeSlot& o, int batch,
+                               hipStream_t st, int* launches) {
     PoseCounters* cnt = s.counters.as<PoseCounters>();
-    hipLaunchKernelGGL(k_unique_count, dim3(kUniqueBlocks), dim3(kUThreads), 0, st, skeys, n,
+    hipLaunchKernelGGL(k_unique_count, dim3(kUniqueBlocks, batch), dim3(kUThreads), 0, st, skeys, n,
                        s.blk0.as<uint32_t>(), s.blk1.as<uint32_t>(), cnt);
-    hipLaunchKernelGGL(k_unique_scan, dim3(1), dim3(1024), 0, st, s.blk0.as<uint32_t>(),
-                       s.blk1.as<uint32_t>(), kUniqueBlocks, cnt, o.brick_row);
-    hipLaunchKernelGGL(k_zero_masks, dim3(1024), dim3(256), 0, st, o.brick_mask,
+    hipLaunchKernelGGL(k_unique_scan, dim3(batch), dim3(1024), 0, st, s.blk0.as<uint32_t>(), s.blk1.as<uint32_t>(),
+                       kUniqueBlocks, cnt, o.brick_row, (size_t)n + 1);
+    hipLaunchKernelGGL(k_zero_masks, dim3(256, batch), dim3(256), 0, st, o.brick_mask, (size_t)n * 16,
                        (const PoseCounters*)cnt);
-    *launches += 4;
+    *launches += 3;
     const int es = storage == ART_BF16 ? 2 : 4;
+#if ART_GATHER_CANONICAL
+    // the compositing kernel gathers canonical rows through the winner id
+    if (es == 4) launch_write<0, 4>(skeys, svals, n, s, o, sigma, feat, batch, st);
+    else launch_write<0, 2>(skeys, svals, n, s, o, sigma, feat, batch, st);
+    *launches += 1;
+    return hipGetLastError();
+#endif
     switch (C * es) {
-        case 8: launch_write<8, 2>(skeys, svals, n, s, o, sigma, feat, st); break;     // C=4 bf16
+        case 8: launch_write<8, 2>(skeys, svals, n, s, o, sigma, feat, batch, st); break;     // C=4 bf16
         case 16:
-            if (es == 4) launch_write<16, 4>(skeys, svals, n, s, o, sigma, feat, st);  // C=4 f32
-            else launch_write<16, 2>(skeys, svals, n, s, o, sigma, feat, st);          // C=8 bf16
+            if (es == 4) launch_write<16, 4>(skeys, svals, n, s, o, sigma, feat, batch, st);  // C=4 f32
+            else launch_write<16, 2>(skeys, svals, n, s, o, sigma, feat, batch, st);          // C=8 bf16
             break;
         case 32:
-            if (es == 4) launch_write<32, 4>(skeys, svals, n, s, o, sigma, feat, st);
-            else launch_write<32, 2>(skeys, svals, n, s, o, sigma, feat, st);
+            if (es == 4) launch_write<32, 4>(skeys, svals, n, s, o, sigma, feat, batch, st);
+            else launch_write<32, 2>(skeys, svals, n, s, o, sigma, feat, batch, st);
             break;
         case 64:
-            if (es == 4) launch_write<64, 4>(skeys, svals, n, s, o, sigma, feat, st);
-            else launch_write<64, 2>(skeys, svals, n, s, o, sigma, feat, st);
+            if (es == 4) launch_write<64, 4>(skeys, svals, n, s, o, sigma, feat, batch, st);
+            else launch_write<64, 2>(skeys, svals, n, s, o, sigma, feat, batch, st);
             break;
-        case 128: launch_write<128, 4>(skeys, svals, n, s, o, sigma, feat, st); break;  // C=32 f32
+        case 128: launch_write<128, 4>(skeys, svals, n, s, o, sigma, feat, batch, st); break;  // C=32 f32
         default: return hipErrorInvalidValue;
     }
     *launches += 1;

@@ -95,6 +95,7 @@ __global__ void k_fk(const int32_t* __restrict__ parent, const double* __restric
     }
 }
 
+// Batched over poses: pose p = blockIdx.y reads B[p] and writes keys/vals + p * n.
 template <typename R>
 __global__ __launch_bounds__(256) void k_skin(const uint16_t* __restrict__ ijk,
                                               const uint8_t* __restrict__ bone,
@@ -104,6 +105,9 @@ __global__ __launch_bounds__(256) void k_skin(const uint16_t* __restrict__ ijk,
                                               uint32_t* __restrict__ keys,
                                               uint32_t* __restrict__ vals) {
     __shared__ R sB[256 * 12];
+    Bpose += (size_t)blockIdx.y * J * 12;
+    keys += (size_t)blockIdx.y * n;
+    vals += (size_t)blockIdx.y * n;
     for (int i = threadIdx.x; i < J * 12; i += blockDim.x) sB[i] = Bpose[i];
     __syncthreads();
     const R h = (R)1 / (R)(1 << depth);
@@ -147,16 +151,16 @@ hipError_t launch_fk(const int32_t* parent, const double* rest, const double* po
 }
 
 hipError_t launch_skin(const uint16_t* ijk, const uint8_t* bone, const float* w, int64_t n,
-                       int depth, const double* B64, const float* B32, int J, bool fp32,
+                       int depth, const double* B64, const float* B32, int J, bool fp32, int batch,
                        uint32_t* keys, uint32_t* vals, hipStream_t st) {
     const int bs = 256;
     int grid = (int)((n + bs - 1) / bs);
-    if (grid > 8192) grid = 8192;
+    if (grid > 2048) grid = 2048;
     if (fp32)
-        hipLaunchKernelGGL(k_skin<float>, dim3(grid), dim3(bs), 0, st, ijk, bone, w, (uint32_t)n,
+        hipLaunchKernelGGL(k_skin<float>, dim3(grid, batch), dim3(bs), 0, st, ijk, bone, w, (uint32_t)n,
                            depth, B32, J, keys, vals);
     else
-        hipLaunchKernelGGL(k_skin<double>, dim3(grid), dim3(bs), 0, st, ijk, bone, w, (uint32_t)n,
+        hipLaunchKernelGGL(k_skin<double>, dim3(grid, batch), dim3(bs), 0, st, ijk, bone, w, (uint32_t)n,
                            depth, B64, J, keys, vals);
     return hipGetLastError();
 }

@@ -1,12 +1,13 @@
-// Data-parallel primitives of the posed-octree rebuild: a stable LSD radix
-// sort of (uint32 key, uint32 payload) pairs and an exclusive scan, both with
-// a fixed grid whose item count is read from device memory, so the host never
+// Data-parallel primitives of the posed-octree rebuild, batched over the poses
+// of a launch (pose = blockIdx.y): a stable LSD radix sort of (uint32 key,
+// uint32 payload) pairs and an exclusive scan.  Every kernel has a fixed grid;
+// the item count of each pose is read from device memory, so the host never
 // waits for a count produced on the GPU.
 //
-// Radix pass (8-bit digit, blocks own contiguous key ranges):
-//   k_hist     per-block digit histogram           -> hist[digit][block]
-//   k_hscan    one workgroup per digit scans its row over the blocks and
-//              writes the digit total
+// Radix pass (8-bit digit, blocks own contiguous key ranges of their pose):
+//   k_hist     per-block digit histogram           -> hist[pose][digit][block]
+//   k_hscan    one workgroup per (digit, pose) scans its row over the blocks
+//              and writes the digit total
 //   k_scatter  per block, stable ranks: lanes with equal digits are matched
 //              with 8 wave ballots, their rank is the popcount of the matching
 //              lanes below; waves are ordered through a small LDS table and a
@@ -32,25 +33,31 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t st) {
     return hipGetLastError();
 }
 
-__global__ __launch_bounds__(kSortThreads) void k_hist(const uint32_t* __restrict__ keys,
-                                                       const uint32_t* __restrict__ d_n, int shift,
-                                                       uint32_t* __restrict__ hist) {
+__global__ __launch_bounds__(kSortThreads) void k_hist(const uint32_t* __restrict__ keys, size_t kstride,
+                                                       const uint32_t* __restrict__ d_n, uint32_t nstride,
+                                                       int shift, uint32_t* __restrict__ hist) {
     __shared__ uint32_t h[256];
+    const uint32_t p = blockIdx.y;
+    keys += p * kstride;
+    hist += (size_t)p * 256 * gridDim.x;
     h[threadIdx.x] = 0;
     __syncthreads();
     uint32_t lo, hi;
-    block_range(*d_n, blockIdx.x, gridDim.x, kSortThreads, &lo, &hi);
+    block_range(d_n[p * nstride], blockIdx.x, gridDim.x, kSortThreads, &lo, &hi);
     for (uint32_t i = lo + threadIdx.x; i < hi; i += kSortThreads)
         atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
     __syncthreads();
     hist[threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
 }
 
-// One workgroup per digit; nblk <= 1024 == blockDim.x.
+// One workgroup per (digit, pose); nblk <= 1024 == blockDim.x.
 __global__ __launch_bounds__(1024) void k_hscan(uint32_t* __restrict__ hist, int nblk,
                                                 uint32_t* __restrict__ digit_tot) {
     __shared__ uint32_t tmp[1024 / kWave + 1];
     const int d = blockIdx.x;
+    const uint32_t p = blockIdx.y;
+    hist += (size_t)p * 256 * nblk;
+    digit_tot += (size_t)p * 256;
     const int b = threadIdx.x;
     uint32_t v = b < nblk ? hist[d * nblk + b] : 0u;
     uint32_t total;
@@ -60,14 +67,22 @@ __global__ __launch_bounds__(1024) void k_hscan(uint32_t* __restrict__ hist, int
 }
 
 __global__ __launch_bounds__(kSortThreads) void k_scatter(
-    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
-    uint32_t* __restrict__ kout, uint32_t* __restrict__ vout, const uint32_t* __restrict__ d_n,
-    int shift, const uint32_t* __restrict__ hist, const uint32_t* __restrict__ digit_tot) {
+    const uint32_t* __restrict__ kin, uint32_t* __restrict__ kout, size_t kstride,
+    const uint32_t* __restrict__ vin, uint32_t* __restrict__ vout, size_t vstride,
+    const uint32_t* __restrict__ d_n, uint32_t nstride, int shift, const uint32_t* __restrict__ hist,
+    const uint32_t* __restrict__ digit_tot) {
     constexpr int NW = kSortThreads / kWave;
     __shared__ uint32_t base[256];
     __shared__ uint32_t run[256];
     __shared__ uint32_t cnt[NW][256];
     __shared__ uint32_t tmp[NW + 1];
+    const uint32_t p = blockIdx.y;
+    kin += p * kstride;
+    kout += p * kstride;
+    vin += p * vstride;
+    vout += p * vstride;
+    hist += (size_t)p * 256 * gridDim.x;
+    digit_tot += (size_t)p * 256;
     const int t = threadIdx.x;
     const int w = t / kWave;
     // global start of each digit for this block
@@ -79,7 +94,7 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(
     for (int q = 0; q < NW; ++q) cnt[q][t] = 0;
     __syncthreads();
     uint32_t lo, hi;
-    block_range(*d_n, blockIdx.x, gridDim.x, kSortThreads, &lo, &hi);
+    block_range(d_n[p * nstride], blockIdx.x, gridDim.x, kSortThreads, &lo, &hi);
     const uint64_t below = lanemask_lt();
     for (uint32_t i0 = lo; i0 < hi; i0 += kSortThreads) {
         const uint32_t i = i0 + t;
@@ -116,21 +131,19 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(
     }
 }
 
-hipError_t launch_radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1,
-                             const uint32_t* d_n, uint32_t n_cap, int bits, uint32_t* hist,
-                             uint32_t* digit_tot, hipStream_t st, bool* result_in_1,
-                             int* launches) {
-    int nblk = (int)((n_cap + 2047) / 2048);
+hipError_t launch_radix_sort(const SortBatch& b, int bits, hipStream_t st, bool* result_in_1, int* launches) {
+    int nblk = (int)((b.n_cap + 2047) / 2048);
     if (nblk < 1) nblk = 1;
     if (nblk > kSortBlocks) nblk = kSortBlocks;
     const int passes = (bits + 7) / 8;
-    uint32_t *ki = k0, *vi = v0, *ko = k1, *vo = v1;
+    uint32_t *ki = b.k0, *vi = b.v0, *ko = b.k1, *vo = b.v1;
     for (int p = 0; p < passes; ++p) {
         const int shift = 8 * p;
-        hipLaunchKernelGGL(k_hist, dim3(nblk), dim3(kSortThreads), 0, st, ki, d_n, shift, hist);
-        hipLaunchKernelGGL(k_hscan, dim3(256), dim3(1024), 0, st, hist, nblk, digit_tot);
-        hipLaunchKernelGGL(k_scatter, dim3(nblk), dim3(kSortThreads), 0, st, ki, vi, ko, vo, d_n,
-                           shift, hist, digit_tot);
+        hipLaunchKernelGGL(k_hist, dim3(nblk, b.batch), dim3(kSortThreads), 0, st, ki, b.kstride, b.d_n, b.nstride,
+                           shift, b.hist);
+        hipLaunchKernelGGL(k_hscan, dim3(256, b.batch), dim3(1024), 0, st, b.hist, nblk, b.digit_tot);
+        hipLaunchKernelGGL(k_scatter, dim3(nblk, b.batch), dim3(kSortThreads), 0, st, ki, ko, b.kstride, vi, vo,
+                           b.vstride, b.d_n, b.nstride, shift, b.hist, b.digit_tot);
         *launches += 3;
         uint32_t* tk = ki; ki = ko; ko = tk;
         uint32_t* tv = vi; vi = vo; vo = tv;
@@ -140,16 +153,19 @@ hipError_t launch_radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t*
 }
 
 // ---------------------------------------------------------------------------
-// exclusive scan of a device-sized uint32 array
+// exclusive scan of a device-sized uint32 array per pose
 // ---------------------------------------------------------------------------
 constexpr int kScanThreads = 256;
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t* __restrict__ in,
-                                                              const uint32_t* __restrict__ d_n,
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t* __restrict__ in, size_t stride,
+                                                              const uint32_t* __restrict__ d_n, uint32_t nstride,
                                                               uint32_t* __restrict__ blk) {
     __shared__ uint32_t tmp[kScanThreads / kWave];
+    const uint32_t p = blockIdx.y;
+    in += p * stride;
+    blk += (size_t)p * gridDim.x;
     uint32_t lo, hi;
-    block_range(*d_n, blockIdx.x, gridDim.x, kScanThreads, &lo, &hi);
+    block_range(d_n[p * nstride], blockIdx.x, gridDim.x, kScanThreads, &lo, &hi);
     uint32_t s = 0;
     for (uint32_t i = lo + threadIdx.x; i < hi; i += kScanThreads) s += in[i];
     s = wave_sum(s);
@@ -163,23 +179,28 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t* __
 }
 
 __global__ __launch_bounds__(1024) void k_scan_blocks(uint32_t* __restrict__ blk, int nblk,
-                                                      uint32_t* __restrict__ d_total) {
+                                                      uint32_t* __restrict__ d_total, uint32_t tstride) {
     __shared__ uint32_t tmp[1024 / kWave + 1];
+    const uint32_t p = blockIdx.x;
+    blk += (size_t)p * nblk;
     uint32_t v = (int)threadIdx.x < nblk ? blk[threadIdx.x] : 0u;
     uint32_t total;
     uint32_t ex = block_exclusive_scan<1024>(v, tmp, &total);
     if ((int)threadIdx.x < nblk) blk[threadIdx.x] = ex;
-    if (threadIdx.x == 0 && d_total) *d_total = total;
+    if (threadIdx.x == 0 && d_total) d_total[p * tstride] = total;
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t* __restrict__ in,
-                                                            uint32_t* __restrict__ out,
-                                                            const uint32_t* __restrict__ d_n,
+                                                            uint32_t* __restrict__ out, size_t stride,
+                                                            const uint32_t* __restrict__ d_n, uint32_t nstride,
                                                             const uint32_t* __restrict__ blk) {
     __shared__ uint32_t tmp[kScanThreads / kWave + 1];
+    const uint32_t p = blockIdx.y;
+    in += p * stride;
+    out += p * stride;
     uint32_t lo, hi;
-    block_range(*d_n, blockIdx.x, gridDim.x, kScanThreads, &lo, &hi);
-    uint32_t carry = blk[blockIdx.x];
+    block_range(d_n[p * nstride], blockIdx.x, gridDim.x, kScanThreads, &lo, &hi);
+    uint32_t carry = blk[(size_t)p * gridDim.x + blockIdx.x];
     for (uint32_t i0 = lo; i0 < hi; i0 += kScanThreads) {
         const uint32_t i = i0 + threadIdx.x;
         const uint32_t v = i < hi ? in[i] : 0u;
@@ -190,11 +211,14 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t* __re
     }
 }
 
-hipError_t launch_scan_exclusive(const uint32_t* in, uint32_t* out, const uint32_t* d_n,
-                                 uint32_t* d_total, uint32_t* blk, hipStream_t st, int* launches) {
-    hipLaunchKernelGGL(k_scan_reduce, dim3(kScanBlocks), dim3(kScanThreads), 0, st, in, d_n, blk);
-    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, blk, kScanBlocks, d_total);
-    hipLaunchKernelGGL(k_scan_down, dim3(kScanBlocks), dim3(kScanThreads), 0, st, in, out, d_n, blk);
+hipError_t launch_scan_exclusive(const uint32_t* in, uint32_t* out, size_t stride, const uint32_t* d_n,
+                                 uint32_t nstride, uint32_t* d_total, uint32_t tstride, uint32_t* blk, int batch,
+                                 hipStream_t st, int* launches) {
+    const int nblk = kScanBlocks;   // per pose; blk holds batch * nblk partials
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nblk, batch), dim3(kScanThreads), 0, st, in, stride, d_n, nstride, blk);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(batch), dim3(1024), 0, st, blk, nblk, d_total, tstride);
+    hipLaunchKernelGGL(k_scan_down, dim3(nblk, batch), dim3(kScanThreads), 0, st, in, out, stride, d_n, nstride,
+                       blk);
     *launches += 3;
     return hipGetLastError();
 }

@@ -5,8 +5,8 @@
 //                    list with a wave ballot + popcount of the lanes below (one
 //                    atomic per wave), so the persistent compositing waves only
 //                    ever take tiles with work.
-//   k_background   : one wave per tile slot; an empty tile's pixels get F = 0,
-//                    A = 0, T = 1 (no voxel on their ray).
+//   k_background   : one thread per pixel; the pixels of an empty tile get
+//                    F = 0, A = 0, T = 1 (no voxel on their ray).
 #include "device_util.h"
 #include "internal.h"
 
@@ -57,36 +57,38 @@ __global__ __launch_bounds__(256) void k_tile_compact(TileGeom g, const uint32_t
     }
 }
 
+// One thread per pixel of every (pose, view) map, row-major so each output
+// plane is written in full 256-byte runs; pixels of tiles with a brick list are
+// left to the compositing kernel.
 __global__ __launch_bounds__(256) void k_background(TileGeom g, const uint32_t* __restrict__ ovf,
                                                     const uint32_t* __restrict__ tstart,
                                                     const uint32_t* __restrict__ tend,
                                                     float* __restrict__ out_feat, float* __restrict__ out_alpha,
                                                     float* __restrict__ out_tfinal, int32_t* __restrict__ hit_count,
                                                     unsigned long long* __restrict__ stats) {
-    const uint64_t total = (uint64_t)g.Pb * g.V * g.tiles_pow4;
-    const int lane = lane_id();
-    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / kWave);
-    for (uint64_t i = (uint64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; i < total; i += waves) {
-        uint32_t item = 0;
-        int tx, ty, pvi;
-        if (!tile_slot(g, ovf, i, &item, &tx, &ty, &pvi)) continue;   // wave-uniform
-        if (tend[item] > tstart[item]) continue;                       // rendered by k_render
-        const int px = tx * 8 + (lane & 7);
-        const int py = ty * 8 + (lane >> 3);
-        const bool pix_ok = px < g.W && py < g.H;
-        if (pix_ok) {
-            const size_t HW = (size_t)g.H * g.W;
-            const size_t pix = (size_t)py * g.W + px;
-            if (out_feat)
-                for (int c = 0; c < g.C; ++c) out_feat[((size_t)pvi * g.C + c) * HW + pix] = 0.0f;
-            if (out_alpha) out_alpha[(size_t)pvi * HW + pix] = 0.0f;
-            if (out_tfinal) out_tfinal[(size_t)pvi * HW + pix] = 1.0f;
-            if (hit_count) hit_count[pix] = 0;
-        }
-        if (stats) {
-            const uint64_t rays = __ballot(pix_ok);
-            if (lane == 0) atomicAdd(&stats[0], (unsigned long long)__popcll(rays));
-        }
+    const size_t HW = (size_t)g.H * g.W;
+    const uint64_t total = (uint64_t)g.Pb * g.V * HW;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    unsigned long long nrays = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+        const uint32_t pvi = (uint32_t)(i / HW);
+        const size_t pix = (size_t)(i % HW);
+        const int py = (int)(pix / g.W), px = (int)(pix % g.W);
+        const int pb = (int)pvi / g.V, v = (int)pvi % g.V;
+        if (g.debug_view >= 0 && v != g.debug_view) continue;
+        if (ovf[2 * ((size_t)pb * g.ngroups + v / g.Vg)]) continue;   // re-run later by the host
+        const size_t item = (size_t)pvi * g.TPV + (size_t)(py >> 3) * g.TX + (px >> 3);
+        if (tend[item] > tstart[item]) continue;                      // rendered by k_render
+        ++nrays;
+        if (out_feat)
+            for (int c = 0; c < g.C; ++c) out_feat[((size_t)pvi * g.C + c) * HW + pix] = 0.0f;
+        if (out_alpha) out_alpha[(size_t)pvi * HW + pix] = 0.0f;
+        if (out_tfinal) out_tfinal[(size_t)pvi * HW + pix] = 1.0f;
+        if (hit_count) hit_count[pix] = 0;
+    }
+    if (stats) {
+        const unsigned long long w = wave_sum(nrays);
+        if (lane_id() == 0 && w) atomicAdd(&stats[0], w);
     }
 }
 
@@ -113,8 +115,9 @@ hipError_t launch_tiles(const TileLaunch& t, hipStream_t st) {
     hipLaunchKernelGGL(k_tile_compact, dim3((unsigned)blocks), dim3(256), 0, st, g, t.ovf, t.tile_start, t.tile_end,
                        t.items, t.counters);
     if (t.out_feat || t.hit_count) {
-        uint64_t wblocks = (total + 3) / 4;
-        if (wblocks > 65536) wblocks = 65536;
+        const uint64_t pixels = (uint64_t)g.Pb * g.V * g.H * g.W;
+        uint64_t wblocks = (pixels + 255) / 256;
+        if (wblocks > 16384) wblocks = 16384;
         if (wblocks < 1) wblocks = 1;
         hipLaunchKernelGGL(k_background, dim3((unsigned)wblocks), dim3(256), 0, st, g, t.ovf, t.tile_start,
                            t.tile_end, t.out_feat, t.out_alpha, t.out_tfinal, t.hit_count, t.stats);
