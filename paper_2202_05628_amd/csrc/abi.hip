@@ -144,7 +144,7 @@ size_t slot_bytes(const art_ctx* ctx, const CallPlan& pl, size_t pair_cap) {
     const size_t es = pl.storage ? 2 : 4;
     const size_t tiles = (size_t)ctx->V * ((ctx->W + 7) / 8) * ((ctx->H + 7) / 8);
     // octree slot + sort scratch + bin counts + tile lists and their sort scratch + tile ranges
-    return n * (4 + 4 + 4 + 4 + 64 + es * (pl.C + 1)) + n * 16 + n * pl.Vg * 8 +
+    return n * (4 + 4 + 4 + 4 + 64) + n * 16 + n * pl.Vg * 8 +
            (size_t)pl.ngroups * pair_cap * 8 + pair_cap * 8 + tiles * 12 + (size_t)pl.ngroups * 9;
 }
 
@@ -169,7 +169,6 @@ art_status ensure_scratch(art_ctx* ctx, const CallPlan& pl, int slots) {
         {&ctx->Gtmp, (size_t)ctx->P * ctx->J * 12 * 8},
         {&s.occ_key, S * n * 4}, {&s.occ_win, S * n * 4},
         {&s.brick_key, S * n * 4}, {&s.brick_row, S * (n + 1) * 4}, {&s.brick_mask, S * n * 64},
-        {&s.flut_sig, S * n * es}, {&s.flut_feat, S * n * pl.C * es},
         {&s.bin_cnt, S * n * pl.Vg * 4}, {&s.bin_off, S * n * pl.Vg * 4},
         {&s.pk0, S * s.pair_cap * 4}, {&s.pk1, S * s.pair_cap * 4}, {&s.pv0, S * pl.ngroups * s.pair_cap * 4},
         {&s.pair_v, S * pl.ngroups * s.pair_cap * 4},
@@ -192,8 +191,6 @@ OctreeSlot octree_slot(art_ctx* ctx, const CallPlan& pl, int slot) {
     o.brick_key = s.brick_key.as<uint32_t>() + (size_t)slot * n;
     o.brick_row = s.brick_row.as<uint32_t>() + (size_t)slot * (n + 1);
     o.brick_mask = s.brick_mask.as<uint32_t>() + (size_t)slot * n * 16;
-    o.psig = s.flut_sig.as<char>() + (size_t)slot * n * es;
-    o.pfeat = s.flut_feat.as<char>() + (size_t)slot * n * pl.C * es;
     return o;
 }
 
@@ -290,8 +287,7 @@ art_status build_batch(art_ctx* ctx, const CallPlan& pl, int p0, int batch, cons
     ART_TRY_HIP(launch_radix_sort(sb, 32, st, &in1, launches), "radix sort");
     const uint32_t* sk = in1 ? s.keys1.as<uint32_t>() : s.keys0.as<uint32_t>();
     const uint32_t* sv = in1 ? s.vals1.as<uint32_t>() : s.vals0.as<uint32_t>();
-    ART_TRY_HIP(launch_build_octree(sk, sv, (uint32_t)n, pl.C, pl.storage, sigma, feat, s, octree_slot(ctx, pl, 0),
-                                    batch, st, launches),
+    ART_TRY_HIP(launch_build_octree(sk, sv, (uint32_t)n, s, octree_slot(ctx, pl, 0), batch, st, launches),
                 "octree build");
     hipLaunchKernelGGL(k_accum, dim3((batch + 63) / 64), dim3(64), 0, st, (const PoseCounters*)cnt,
                        s.stats.as<unsigned long long>(), (uint32_t)n, batch);
@@ -508,10 +504,8 @@ hipError_t launch_render(const RenderLaunch& r, hipStream_t st) {
     a.brick_row = s.brick_row.as<uint32_t>();
     a.brick_mask = s.brick_mask.as<uint32_t>();
     a.occ_win = s.occ_win.as<uint32_t>();
-    a.psig = s.flut_sig.p;
-    a.pfeat = s.flut_feat.p;
-    a.csig = r.sigma;
-    a.cfeat = r.feat;
+    a.sigma = r.sigma;
+    a.feat = r.feat;
     a.out_feat = r.out_feat;
     a.out_alpha = r.out_alpha;
     a.out_tfinal = r.out_tfinal;
@@ -581,8 +575,7 @@ void art_destroy(art_ctx* ctx) {
                           &ctx->cam, &ctx->B64, &ctx->B32, &ctx->Gtmp,
                           &ctx->s.keys0, &ctx->s.vals0, &ctx->s.keys1, &ctx->s.vals1, &ctx->s.hist,
                           &ctx->s.digit_tot, &ctx->s.blk0, &ctx->s.blk1, &ctx->s.occ_key, &ctx->s.occ_win,
-                          &ctx->s.brick_key, &ctx->s.brick_row, &ctx->s.brick_mask, &ctx->s.flut_sig,
-                          &ctx->s.flut_feat, &ctx->s.bin_cnt, &ctx->s.bin_off, &ctx->s.pk0, &ctx->s.pv0,
+                          &ctx->s.brick_key, &ctx->s.brick_row, &ctx->s.brick_mask, &ctx->s.bin_cnt, &ctx->s.bin_off, &ctx->s.pk0, &ctx->s.pv0,
                           &ctx->s.pk1, &ctx->s.pair_v, &ctx->s.tile_start, &ctx->s.tile_end,
                           &ctx->s.counters, &ctx->s.stats, &ctx->s.ovf, &ctx->s.items, &ctx->s.queue,
                           &ctx->s.redo};

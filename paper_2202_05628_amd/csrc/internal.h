@@ -71,7 +71,6 @@ struct Scratch {
     DevBuf blk0, blk1;                   // block partials [slots][max(kScanBlocks, kUniqueBlocks)]
     DevBuf occ_key, occ_win;             // [slots][n] posed cells + winners
     DevBuf brick_key, brick_row, brick_mask;  // [slots][n], [slots][n+1], [slots][n*16]
-    DevBuf flut_sig, flut_feat;          // [slots][n] posed-order FLUT rows
     DevBuf bin_cnt, bin_off;             // [slots][n * Vg]
     size_t bin_stride = 0;               // n * Vg
     DevBuf pk0, pk1;                     // pair sort keys [slots][pair_cap]
@@ -165,12 +164,9 @@ struct OctreeSlot {
     uint32_t* brick_key;    // [n]
     uint32_t* brick_row;    // [n + 1]
     uint32_t* brick_mask;   // [n][16]
-    void* psig;             // [n] posed-order densities
-    void* pfeat;            // [n][C] posed-order features
 };
-hipError_t launch_build_octree(const uint32_t* skeys, const uint32_t* svals, uint32_t n, int C, int storage,
-                               const void* sigma, const void* feat, Scratch& s, const OctreeSlot& o, int batch,
-                               hipStream_t st, int* launches);
+hipError_t launch_build_octree(const uint32_t* skeys, const uint32_t* svals, uint32_t n, Scratch& s,
+                               const OctreeSlot& o, int batch, hipStream_t st, int* launches);
 int bin_key_bits(int Vg, int H, int W, int depth, int* mbits);
 // Tile lists of views [v0, v0 + Vg) of every pose of the batch: sorted brick
 // ids into pair_v + (p * ngroups + group) * pair_cap, per-tile ranges into

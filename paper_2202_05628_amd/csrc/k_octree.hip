@@ -9,19 +9,14 @@
 //                    (key >> 9 changes) and dropped leaves
 //   k_unique_scan  : one workgroup scans the block counts -> M, nb
 //   k_zero_masks   : clear the 512-bit occupancy masks of the nb bricks
-//   k_unique_write : per cell run: occupied key, winner id, the FLUT row of the
-//                    winner copied into posed (Morton) order, the cell's bit in
-//                    its brick mask; per brick run: brick key and first row.
+//   k_unique_write : per cell run: occupied key, winner id and the cell's bit
+//                    in its brick mask; per brick run: brick key and first row.
 //
 // The result is a two-level octree: bricks (the level 3 above the leaves) with
 // a 512-bit child mask each, and their leaves stored contiguously in Morton
 // order, so a leaf's row is brick_row + popcount(mask bits below its bit).
 #include "device_util.h"
 #include "internal.h"
-
-#ifndef ART_GATHER_CANONICAL
-#define ART_GATHER_CANONICAL 0
-#endif
 
 namespace art {
 
@@ -113,14 +108,12 @@ __global__ void k_zero_masks(uint32_t* __restrict__ mask, size_t mask_stride,
 // packed (cell runs | brick runs << 16) counts per 256 * kUItems keys.
 constexpr int kUItems = 8;
 
-template <int ROW_BYTES, int SIG_BYTES>
 __global__ __launch_bounds__(kUThreads) void k_unique_write(
     const uint32_t* __restrict__ skeys, const uint32_t* __restrict__ svals, uint32_t n,
     const uint32_t* __restrict__ blk_run, const uint32_t* __restrict__ blk_brick,
     uint32_t* __restrict__ occ_key, uint32_t* __restrict__ occ_win,
     uint32_t* __restrict__ brick_key, uint32_t* __restrict__ brick_row,
-    uint32_t* __restrict__ brick_mask, const uint8_t* __restrict__ sigma,
-    const uint8_t* __restrict__ feat, uint8_t* __restrict__ psig, uint8_t* __restrict__ pfeat) {
+    uint32_t* __restrict__ brick_mask) {
     __shared__ uint32_t tmp[kUThreads / kWave + 1];
     const size_t p = blockIdx.y;
     skeys += p * n;
@@ -132,10 +125,6 @@ __global__ __launch_bounds__(kUThreads) void k_unique_write(
     brick_key += p * n;
     brick_row += p * (n + 1);
     brick_mask += p * n * 16;
-    if (ROW_BYTES > 0) {
-        psig += p * n * SIG_BYTES;
-        pfeat += p * n * ROW_BYTES;
-    }
     uint32_t lo, hi;
     block_range(n, blockIdx.x, gridDim.x, kUThreads, &lo, &hi);
     uint32_t carry_r = blk_run[blockIdx.x];
@@ -178,23 +167,6 @@ __global__ __launch_bounds__(kUThreads) void k_unique_write(
                 occ_win[m] = id;
                 const uint32_t local = k[j] & 511u;
                 atomicOr(&brick_mask[(size_t)(bc - 1) * 16 + (local >> 5)], 1u << (local & 31u));
-                if constexpr (ROW_BYTES > 0) {   // winner's FLUT row in posed order
-                    if (SIG_BYTES == 4)
-                        reinterpret_cast<uint32_t*>(psig)[m] = reinterpret_cast<const uint32_t*>(sigma)[id];
-                    else
-                        reinterpret_cast<uint16_t*>(psig)[m] = reinterpret_cast<const uint16_t*>(sigma)[id];
-                    if constexpr (ROW_BYTES % 16 == 0) {
-                        const uint4* src = reinterpret_cast<const uint4*>(feat + (size_t)id * ROW_BYTES);
-                        uint4* dst = reinterpret_cast<uint4*>(pfeat + (size_t)m * ROW_BYTES);
-#pragma unroll
-                        for (int q = 0; q < ROW_BYTES / 16; ++q) dst[q] = src[q];
-                    } else {
-                        const uint2* src = reinterpret_cast<const uint2*>(feat + (size_t)id * ROW_BYTES);
-                        uint2* dst = reinterpret_cast<uint2*>(pfeat + (size_t)m * ROW_BYTES);
-#pragma unroll
-                        for (int q = 0; q < ROW_BYTES / 8; ++q) dst[q] = src[q];
-                    }
-                }
                 ++m;
             }
         }
@@ -203,19 +175,8 @@ __global__ __launch_bounds__(kUThreads) void k_unique_write(
     }
 }
 
-template <int ROW_BYTES, int SIG_BYTES>
-static void launch_write(const uint32_t* skeys, const uint32_t* svals, uint32_t n, Scratch& s,
-                         const OctreeSlot& o, const void* sigma, const void* feat, int batch, hipStream_t st) {
-    hipLaunchKernelGGL((k_unique_write<ROW_BYTES, SIG_BYTES>), dim3(kUniqueBlocks, batch), dim3(kUThreads),
-                       0, st, skeys, svals, n, s.blk0.as<uint32_t>(), s.blk1.as<uint32_t>(), o.occ_key,
-                       o.occ_win, o.brick_key, o.brick_row, o.brick_mask,
-                       static_cast<const uint8_t*>(sigma), static_cast<const uint8_t*>(feat),
-                       static_cast<uint8_t*>(o.psig), static_cast<uint8_t*>(o.pfeat));
-}
-
-hipError_t launch_build_octree(const uint32_t* skeys, const uint32_t* svals, uint32_t n, int C, int storage,
-                               const void* sigma, const void* feat, Scratch& s, const OctreeSlot& o, int batch,
-                               hipStream_t st, int* launches) {
+hipError_t launch_build_octree(const uint32_t* skeys, const uint32_t* svals, uint32_t n, Scratch& s,
+                               const OctreeSlot& o, int batch, hipStream_t st, int* launches) {
     PoseCounters* cnt = s.counters.as<PoseCounters>();
     hipLaunchKernelGGL(k_unique_count, dim3(kUniqueBlocks, batch), dim3(kUThreads), 0, st, skeys, n,
                        s.blk0.as<uint32_t>(), s.blk1.as<uint32_t>(), cnt);
@@ -223,33 +184,10 @@ hipError_t launch_build_octree(const uint32_t* skeys, const uint32_t* svals, uin
                        kUniqueBlocks, cnt, o.brick_row, (size_t)n + 1);
     hipLaunchKernelGGL(k_zero_masks, dim3(256, batch), dim3(256), 0, st, o.brick_mask, (size_t)n * 16,
                        (const PoseCounters*)cnt);
-    *launches += 3;
-    const int es = storage == ART_BF16 ? 2 : 4;
-#if ART_GATHER_CANONICAL
-    // the compositing kernel gathers canonical rows through the winner id
-    if (es == 4) launch_write<0, 4>(skeys, svals, n, s, o, sigma, feat, batch, st);
-    else launch_write<0, 2>(skeys, svals, n, s, o, sigma, feat, batch, st);
-    *launches += 1;
-    return hipGetLastError();
-#endif
-    switch (C * es) {
-        case 8: launch_write<8, 2>(skeys, svals, n, s, o, sigma, feat, batch, st); break;     // C=4 bf16
-        case 16:
-            if (es == 4) launch_write<16, 4>(skeys, svals, n, s, o, sigma, feat, batch, st);  // C=4 f32
-            else launch_write<16, 2>(skeys, svals, n, s, o, sigma, feat, batch, st);          // C=8 bf16
-            break;
-        case 32:
-            if (es == 4) launch_write<32, 4>(skeys, svals, n, s, o, sigma, feat, batch, st);
-            else launch_write<32, 2>(skeys, svals, n, s, o, sigma, feat, batch, st);
-            break;
-        case 64:
-            if (es == 4) launch_write<64, 4>(skeys, svals, n, s, o, sigma, feat, batch, st);
-            else launch_write<64, 2>(skeys, svals, n, s, o, sigma, feat, batch, st);
-            break;
-        case 128: launch_write<128, 4>(skeys, svals, n, s, o, sigma, feat, batch, st); break;  // C=32 f32
-        default: return hipErrorInvalidValue;
-    }
-    *launches += 1;
+    hipLaunchKernelGGL(k_unique_write, dim3(kUniqueBlocks, batch), dim3(kUThreads), 0, st, skeys, svals, n,
+                       s.blk0.as<uint32_t>(), s.blk1.as<uint32_t>(), o.occ_key, o.occ_win, o.brick_key, o.brick_row,
+                       o.brick_mask);
+    *launches += 4;
     return hipGetLastError();
 }
 

@@ -14,8 +14,10 @@
 //   - a lane without a current brick slab-tests the next staged brick;
 //   - a lane inside a brick takes one step of the exact ray/voxel partition:
 //     the segment up to the next lattice-plane crossing, whose midpoint cell
-//     is looked up in the LDS mask; an occupied cell's row in the posed FLUT
-//     is brick_row + prefix + popcount(mask bits below);
+//     is looked up in the LDS mask; an occupied cell's index in the posed
+//     octree is brick_row + prefix + popcount(mask bits below), and its
+//     winner leaf id selects the FLUT row (the canonical FLUT is shared by
+//     every pose, so it stays cache resident);
 //   - the sample is composited in FP32 (w = T alpha, F += w f, A += w,
 //     T -= T alpha) and the lane stops once T < lambda_th.
 // A wave ballot ends the chunk (and the tile) as soon as no lane has work.
@@ -39,11 +41,7 @@ constexpr int kStage = 64;
 #ifndef ART_STEPS_PER_ROUND
 #define ART_STEPS_PER_ROUND 1
 #endif
-// 1: gather FLUT rows from the canonical arrays through the winner id instead
-// of the per-pose posed-order copies
-#ifndef ART_GATHER_CANONICAL
-#define ART_GATHER_CANONICAL 0
-#endif
+
 constexpr int kStepsPerRound = ART_STEPS_PER_ROUND;
 
 struct RArgs {
@@ -64,10 +62,8 @@ struct RArgs {
     const uint32_t* brick_row;             // [Pb][ncap + 1]
     const uint32_t* brick_mask;            // [Pb][ncap][16]
     const uint32_t* occ_win;               // [Pb][ncap]
-    const void* psig;                      // [Pb][ncap] posed-order densities
-    const void* pfeat;                     // [Pb][ncap][C] posed-order features
-    const void* csig;                      // [n] canonical densities
-    const void* cfeat;                     // [n][C] canonical features
+    const void* sigma;                     // [n] canonical densities (FLUT)
+    const void* feat;                      // [n][C] canonical features (FLUT)
     // maps of the launch's poses: [Pb][V][C][H][W] / [Pb][V][H][W]
     float* out_feat;
     float* out_alpha;
@@ -189,13 +185,7 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, int lane, uint
     const uint32_t* brick_mask = a.brick_mask + (size_t)pb * a.ncap * 16;
     const uint32_t* occ_win = a.occ_win + (size_t)pb * a.ncap;
     const size_t es = ST == 0 ? 4 : 2;
-#if ART_GATHER_CANONICAL
-    const void* psig = a.csig;
-    const void* pfeat = a.cfeat;
-#else
-    const void* psig = static_cast<const char*>(a.psig) + (size_t)pb * a.ncap * es;
-    const void* pfeat = static_cast<const char*>(a.pfeat) + (size_t)pb * a.ncap * C * es;
-#endif
+
 
     // ---- ray r_p = (o, d) of pixel (px, py) -----------------------------------
     const CamParams& cam = a.cam[v];
@@ -449,11 +439,8 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, int lane, uint
                 rowA = rowB;
                 dlA = dlB;
                 dxA = dxB;
-#if ART_GATHER_CANONICAL
-                load_sample<C, ST>(psig, pfeat, occ_win[rowA], sgA, fA);
-#else
-                load_sample<C, ST>(psig, pfeat, rowA, sgA, fA);
-#endif
+                // the FLUT row of the cell's collision winner
+                load_sample<C, ST>(a.sigma, a.feat, occ_win[rowA], sgA, fA);
             }
         }
         wave_sync();
