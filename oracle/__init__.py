@@ -73,7 +73,7 @@ def _load():
     lib.oracle_render.restype = ctypes.c_int
     lib.oracle_render.argtypes = [ctypes.c_int64, P, P, ctypes.c_int, ctypes.c_double,
                                   ctypes.c_int64, P, P, ctypes.c_int, P, P, ctypes.c_double,
-                                  P, P, P, P, P, P, P, ctypes.c_int, P, P, ctypes.c_int]
+                                  P, P, P, P, P, P, P, ctypes.c_int, P, P, P, ctypes.c_int]
     lib.oracle_backward.restype = ctypes.c_int
     lib.oracle_backward.argtypes = [ctypes.c_int64, P, P, ctypes.c_int, ctypes.c_double,
                                     ctypes.c_int64, P, P, ctypes.c_int, P, P, ctypes.c_double,
@@ -295,7 +295,9 @@ def render(o: np.ndarray, d: np.ndarray, depth: int, occ_key: np.ndarray, occ_le
 
     o, d: [n][3] float64 rays (|d| = 1).  Returns F [n][C], A [n], T [n],
     n_comp [n], n_hit [n], min_gap [n], min_tgap [n] and, when max_hits > 0,
-    hit_leaf/hit_delta [n][max_hits] of the composited samples."""
+    hit_leaf/hit_delta [n][max_hits] of the composited samples, and seg [n][4]:
+    t_a, t_b of the clipped ray (NaN on a miss) and the entry t of the first /
+    exit t of the last composited sample (NaN without samples)."""
     lib = _load()
     o = np.ascontiguousarray(o, dtype=np.float64).reshape(-1, 3)
     d = np.ascontiguousarray(d, dtype=np.float64).reshape(-1, 3)
@@ -310,7 +312,7 @@ def render(o: np.ndarray, d: np.ndarray, depth: int, occ_key: np.ndarray, occ_le
     out = {
         "F": np.zeros((n, C)), "A": np.zeros(n), "T": np.ones(n),
         "n_comp": np.zeros(n, dtype=np.int32), "n_hit": np.zeros(n, dtype=np.int32),
-        "min_gap": np.zeros(n), "min_tgap": np.zeros(n),
+        "min_gap": np.zeros(n), "min_tgap": np.zeros(n), "seg": np.zeros((n, 4)),
     }
     hl = hd = None
     if max_hits > 0:
@@ -321,9 +323,26 @@ def render(o: np.ndarray, d: np.ndarray, depth: int, occ_key: np.ndarray, occ_le
                            C, _ptr(sigma), _ptr(feat), float(lambda_th),
                            _ptr(out["F"]), _ptr(out["A"]), _ptr(out["T"]), _ptr(out["n_comp"]),
                            _ptr(out["n_hit"]), _ptr(out["min_gap"]), _ptr(out["min_tgap"]),
-                           int(max_hits), _ptr(hl), _ptr(hd), int(n_threads))
+                           int(max_hits), _ptr(hl), _ptr(hd), _ptr(out["seg"]), int(n_threads))
     if rc != 0:
         raise MemoryError("oracle_render failed")
+    return out
+
+
+def interval_labels(seg: np.ndarray) -> np.ndarray:
+    """Training labels of the ray-interval proposal from ``render(...)["seg"]``:
+    u_near / u_far = entry t of the first / exit t of the last composited sample,
+    mapped to [0, 1] over the ray's span [t_a, t_b] inside the posed root.  A ray
+    with no composited sample (including one that misses the root) gets the
+    empty interval (1, 0)."""
+    seg = np.asarray(seg, dtype=np.float64).reshape(-1, 4)
+    out = np.empty((seg.shape[0], 2))
+    out[:, 0] = 1.0
+    out[:, 1] = 0.0
+    hit = np.isfinite(seg[:, 2])
+    span = seg[hit, 1] - seg[hit, 0]
+    out[hit, 0] = (seg[hit, 2] - seg[hit, 0]) / span
+    out[hit, 1] = (seg[hit, 3] - seg[hit, 0]) / span
     return out
 
 

@@ -1,0 +1,168 @@
+"""FP64 reference of the learned ray-interval proposal network.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring): the plain definition the
+GPU network kernels are checked against.  The proposal is an addition to the
+paper's renderer, not part of it; what it predicts is defined by the
+renderer's composited samples (Section 3.1, Eq. 5 and Eq. 6): for a ray with
+span [t_a, t_b] inside the posed root, the entry t of its first and the exit t
+of its last composited sample, mapped to [0, 1] (``interval_labels``).
+
+Network (all FP64 here):
+    x   = [o (3), d (3), code (6 J)]       ray origin, unit direction, pose code
+    z1  = W1 x + b1,   h1 = relu(z1)        W1: [64][6 + 6J]
+    z2  = W2 h1 + b2,  h2 = relu(z2)        W2: [64][64]
+    z3  = W3 h2 + b3,  h3 = relu(z3)        W3: [64][64]
+    z4  = W4 h3 + b4,  y  = sigmoid(z4)     W4: [2][64];  y = (u_near, u_far)
+The pose code of a pose is, for every bone j, the first two columns of its
+local rotation Rot(r_j) (the 6-D rotation representation), column by column.
+Loss: mean over rays and both outputs of SmoothL1 with beta = 1.
+Training: Adam with bias correction.
+
+Flat parameter order (FP32 on the GPU, the same order here):
+    W1 (row-major), b1, W2, b2, W3, b3, W4, b4.
+
+``round_bf16=True`` rounds both operands of every matrix product to bfloat16
+before an FP64 product (the network's precision form: BF16 matrix-core
+operands, wide accumulation); everything else stays FP64.  The one exception
+is the pose-code part of the first layer in the forward pass, W1[:, 6:] code +
+b1, which depends only on the pose and is evaluated once per pose at full
+precision (it enters every ray of the pose as a bias).
+"""
+from __future__ import annotations
+
+from typing import Dict, List, Tuple
+
+import numpy as np
+
+from . import bf16_round, rodrigues
+
+HIDDEN = 64
+
+
+def input_dim(J: int) -> int:
+    return 6 + 6 * J
+
+
+def param_shapes(J: int) -> List[Tuple[str, Tuple[int, ...]]]:
+    n_in = input_dim(J)
+    return [("W1", (HIDDEN, n_in)), ("b1", (HIDDEN,)), ("W2", (HIDDEN, HIDDEN)), ("b2", (HIDDEN,)),
+            ("W3", (HIDDEN, HIDDEN)), ("b3", (HIDDEN,)), ("W4", (2, HIDDEN)), ("b4", (2,))]
+
+
+def param_count(J: int) -> int:
+    return sum(int(np.prod(s)) for _, s in param_shapes(J))
+
+
+def unpack(theta: np.ndarray, J: int) -> Dict[str, np.ndarray]:
+    theta = np.asarray(theta, dtype=np.float64).reshape(-1)
+    assert theta.size == param_count(J)
+    out, k = {}, 0
+    for name, shp in param_shapes(J):
+        m = int(np.prod(shp))
+        out[name] = theta[k:k + m].reshape(shp)
+        k += m
+    return out
+
+
+def pack(p: Dict[str, np.ndarray], J: int) -> np.ndarray:
+    return np.concatenate([np.asarray(p[name], dtype=np.float64).reshape(-1) for name, _ in param_shapes(J)])
+
+
+def pose_code(r: np.ndarray) -> np.ndarray:
+    """[P][J][3] axis-angle local rotations -> [P][6J]: per bone the first and
+    second column of Rot(r_j)."""
+    r = np.asarray(r, dtype=np.float64)
+    P, J, _ = r.shape
+    out = np.zeros((P, 6 * J))
+    for p in range(P):
+        for j in range(J):
+            R = rodrigues(r[p, j])
+            out[p, 6 * j:6 * j + 3] = R[:, 0]
+            out[p, 6 * j + 3:6 * j + 6] = R[:, 1]
+    return out
+
+
+def inputs(o: np.ndarray, d: np.ndarray, code: np.ndarray) -> np.ndarray:
+    """Rows [o, d, code] of the network input for rays (o, d) of one pose."""
+    o = np.asarray(o, dtype=np.float64).reshape(-1, 3)
+    d = np.asarray(d, dtype=np.float64).reshape(-1, 3)
+    code = np.broadcast_to(np.asarray(code, dtype=np.float64), (o.shape[0], code.shape[-1]))
+    return np.concatenate([o, d, code], axis=1)
+
+
+def _mm(a: np.ndarray, b: np.ndarray, bf16: bool) -> np.ndarray:
+    """a @ b, with both operands rounded to bfloat16 first when bf16 is set."""
+    if bf16:
+        a = bf16_round(a).astype(np.float64)
+        b = bf16_round(b).astype(np.float64)
+    return a @ b
+
+
+def sigmoid(z: np.ndarray) -> np.ndarray:
+    return 0.5 * (1.0 + np.tanh(0.5 * z))
+
+
+def forward(theta: np.ndarray, X: np.ndarray, J: int, round_bf16: bool = False):
+    """Outputs y [n][2] and the activations of every layer."""
+    p = unpack(theta, J)
+    X = np.asarray(X, dtype=np.float64)
+    z1 = _mm(X[:, :6], p["W1"][:, :6].T, round_bf16) + (X[:, 6:] @ p["W1"][:, 6:].T + p["b1"])
+    h1 = np.maximum(z1, 0.0)
+    z2 = _mm(h1, p["W2"].T, round_bf16) + p["b2"]
+    h2 = np.maximum(z2, 0.0)
+    z3 = _mm(h2, p["W3"].T, round_bf16) + p["b3"]
+    h3 = np.maximum(z3, 0.0)
+    z4 = _mm(h3, p["W4"].T, round_bf16) + p["b4"]
+    y = sigmoid(z4)
+    return y, {"X": X, "z1": z1, "h1": h1, "z2": z2, "h2": h2, "z3": z3, "h3": h3, "z4": z4, "y": y}
+
+
+def smooth_l1(e: np.ndarray, beta: float = 1.0) -> np.ndarray:
+    """Elementwise SmoothL1: e^2 / (2 beta) where |e| < beta, else |e| - beta / 2."""
+    a = np.abs(e)
+    return np.where(a < beta, 0.5 * e * e / beta, a - 0.5 * beta)
+
+
+def smooth_l1_grad(e: np.ndarray, beta: float = 1.0) -> np.ndarray:
+    return np.where(np.abs(e) < beta, e / beta, np.sign(e))
+
+
+def loss(y: np.ndarray, target: np.ndarray) -> float:
+    """Mean SmoothL1 (beta = 1) over rays and both outputs."""
+    return float(smooth_l1(np.asarray(y) - np.asarray(target, dtype=np.float64)).mean())
+
+
+def grad(theta: np.ndarray, X: np.ndarray, target: np.ndarray, J: int,
+         round_bf16: bool = False) -> Tuple[float, np.ndarray]:
+    """Loss and its gradient with respect to the flat parameters, by the chain
+    rule written out layer by layer (backpropagation)."""
+    p = unpack(theta, J)
+    y, a = forward(theta, X, J, round_bf16)
+    t = np.asarray(target, dtype=np.float64)
+    n = y.shape[0]
+    L = loss(y, t)
+    dy = smooth_l1_grad(y - t) / (2.0 * n)          # dL/dy
+    d4 = dy * y * (1.0 - y)                          # dL/dz4 (sigmoid')
+    g = {"W4": _mm(d4.T, a["h3"], round_bf16), "b4": d4.sum(axis=0)}
+    d3 = _mm(d4, p["W4"], round_bf16) * (a["z3"] > 0)
+    g["W3"] = _mm(d3.T, a["h2"], round_bf16)
+    g["b3"] = d3.sum(axis=0)
+    d2 = _mm(d3, p["W3"], round_bf16) * (a["z2"] > 0)
+    g["W2"] = _mm(d2.T, a["h1"], round_bf16)
+    g["b2"] = d2.sum(axis=0)
+    d1 = _mm(d2, p["W2"], round_bf16) * (a["z1"] > 0)
+    g["W1"] = _mm(d1.T, a["X"], round_bf16)
+    g["b1"] = d1.sum(axis=0)
+    return L, pack(g, J)
+
+
+def adam_step(theta: np.ndarray, m: np.ndarray, v: np.ndarray, g: np.ndarray, step: int,
+              lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+    """One Adam update (step counts from 1): moments, bias correction, update.
+    Returns the new (theta, m, v)."""
+    m = beta1 * m + (1.0 - beta1) * g
+    v = beta2 * v + (1.0 - beta2) * g * g
+    m_hat = m / (1.0 - beta1 ** step)
+    v_hat = v / (1.0 - beta2 ** step)
+    theta = theta - lr * m_hat / (np.sqrt(v_hat) + eps)
+    return theta, m, v

@@ -84,6 +84,7 @@ static int clip_root(const double o[3], const double d[3], double* ta, double* t
 typedef struct {
     int64_t leaf;   /* winner leaf id */
     double delta;   /* chord length */
+    double t0, t1;  /* the segment (t0, t1) of the ray inside the voxel */
 } sample_t;
 
 /* Enumerate the occupied samples of one ray in increasing t.
@@ -92,10 +93,15 @@ typedef struct {
  * (0 if two crossings coincided exactly), a guard band for rounding. */
 static int64_t ray_samples(const double o[3], const double d[3], int G, double h,
                            int64_t M, const int64_t* occ_key, const int64_t* occ_leaf,
-                           sample_t* out, int64_t cap, double* pts, double* min_gap) {
+                           sample_t* out, int64_t cap, double* pts, double* min_gap,
+                           double* ta_out, double* tb_out) {
     double ta, tb;
     *min_gap = INFINITY;
+    *ta_out = NAN;
+    *tb_out = NAN;
     if (!clip_root(o, d, &ta, &tb)) return 0;
+    *ta_out = ta;
+    *tb_out = tb;
     int64_t np = 0;
     pts[np++] = ta;
     for (int a = 0; a < 3; ++a) {
@@ -127,6 +133,8 @@ static int64_t ray_samples(const double o[3], const double d[3], int G, double h
         if (ns < cap) {
             out[ns].leaf = occ_leaf[idx];
             out[ns].delta = s1 - s0;
+            out[ns].t0 = s0;
+            out[ns].t1 = s1;
         }
         ++ns;
     }
@@ -142,7 +150,10 @@ static int64_t max_points(int G) { return 3 * (int64_t)(G + 1) + 2; }
  *   guard band of the partition), min_tgap [n] (smallest |T - lambda| / lambda
  *   over the composited samples; +inf when lambda == 0).
  * Optional hit lists (hit_leaf/hit_delta [n][max_hits], may be NULL) record the
- * composited samples in order.
+ * composited samples in order.  Optional seg [n][4] (may be NULL) receives
+ * t_a, t_b of the clipped ray (NaN on a miss), the entry t of the first
+ * composited sample and the exit t of the last one (NaN without samples): the
+ * interval a ray-interval proposal has to cover.
  * Returns 0, or -1 on allocation failure.
  */
 int oracle_render(int64_t n, const double* o, const double* d, int G, double h,
@@ -150,7 +161,8 @@ int oracle_render(int64_t n, const double* o, const double* d, int G, double h,
                   int C, const double* sigma, const double* feat, double lambda_th,
                   double* F, double* A, double* Tfin, int32_t* n_comp, int32_t* n_hit,
                   double* min_gap, double* min_tgap,
-                  int max_hits, int64_t* hit_leaf, double* hit_delta, int n_threads) {
+                  int max_hits, int64_t* hit_leaf, double* hit_delta, double* seg,
+                  int n_threads) {
     int failed = 0;
     int64_t cap = max_points(G);
 #ifdef _OPENMP
@@ -170,9 +182,9 @@ int oracle_render(int64_t n, const double* o, const double* d, int G, double h,
 #pragma omp for schedule(dynamic, 64)
 #endif
             for (int64_t r = 0; r < n; ++r) {
-                double gap;
+                double gap, ta, tb;
                 int64_t ns = ray_samples(o + 3 * r, d + 3 * r, G, h, M, occ_key, occ_leaf,
-                                         smp, cap, pts, &gap);
+                                         smp, cap, pts, &gap, &ta, &tb);
                 double T = 1.0, acc = 0.0, tg = INFINITY;
                 double* Fr = F + (size_t)r * C;
                 for (int c = 0; c < C; ++c) Fr[c] = 0.0;
@@ -199,6 +211,13 @@ int oracle_render(int64_t n, const double* o, const double* d, int G, double h,
                 }
                 A[r] = acc;
                 Tfin[r] = T;
+                if (seg) {
+                    double* sg = seg + 4 * (size_t)r;
+                    sg[0] = ta;
+                    sg[1] = tb;
+                    sg[2] = used > 0 ? smp[0].t0 : NAN;
+                    sg[3] = used > 0 ? smp[used - 1].t1 : NAN;
+                }
                 n_comp[r] = (int32_t)used;
                 n_hit[r] = (int32_t)ns;
                 min_gap[r] = gap;
@@ -243,9 +262,9 @@ int oracle_backward(int64_t n, const double* o, const double* d, int G, double h
 #pragma omp for schedule(dynamic, 64)
 #endif
             for (int64_t r = 0; r < n; ++r) {
-                double gap;
+                double gap, ta, tb;
                 int64_t ns = ray_samples(o + 3 * r, d + 3 * r, G, h, M, occ_key, occ_leaf,
-                                         smp, cap, pts, &gap);
+                                         smp, cap, pts, &gap, &ta, &tb);
                 /* forward: weights and transmittances of the composited samples */
                 double T = 1.0;
                 int64_t used = 0;

@@ -433,6 +433,21 @@ def make_targets(P: int, V: int, C: int, H: int, W: int, seed: int = 3) -> np.nd
     return rng.normal(size=(P, V, C, H, W)).astype(np.float32)
 
 
+def make_mlp_init(J: int, seed: int = 4, hidden: int = 64) -> np.ndarray:
+    """Initial FP32 parameters of the ray-interval proposal network
+    (6 + 6J -> hidden -> hidden -> hidden -> 2), flat in the order W1, b1, W2,
+    b2, W3, b3, W4, b4 (weights row-major [out][in]): every weight and bias of a
+    layer with fan-in m drawn from U(-1/sqrt(m), 1/sqrt(m))."""
+    rng = np.random.default_rng(seed)
+    dims = [6 + 6 * J, hidden, hidden, hidden, 2]
+    parts = []
+    for a, b in zip(dims[:-1], dims[1:]):
+        k = 1.0 / np.sqrt(a)
+        parts.append(rng.uniform(-k, k, size=(b, a)).reshape(-1))
+        parts.append(rng.uniform(-k, k, size=b))
+    return np.concatenate(parts).astype(np.float32)
+
+
 def sample_training_rays(n: int, P: int, V: int, H: int, W: int, hit_mask: Optional[np.ndarray] = None,
                          hit_fraction: float = 0.5, seed: int = 5) -> np.ndarray:
     """Uniform (pose, view, pixel) draws, about `hit_fraction` from hit pixels when a
