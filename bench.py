@@ -25,6 +25,57 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_render_full_traffic.txt")
+RENDER_SOURCES = ("render_impl.h", "render_c16.hip", "device_util.h", "internal.h")
+
+
+def render_source_hash():
+    """SHA-256 over the sources the compositing kernel is built from."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in RENDER_SOURCES:
+        with open(os.path.join(ROOT, "paper_2202_05628_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload):
+    """HBM bytes per compositing launch from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel factor), or
+    None when the summary is missing, covers another workload or was taken on
+    a different version of the kernel sources."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("render_source_hash") != render_source_hash() or kv.get("workload") != workload:
+        return None
+    try:
+        return int(float(kv["hbm_bytes_per_launch"]))
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_ceiling(torch, nbytes=1 << 30, reps=5):
+    """Device-to-device copy bandwidth (read + write bytes / time) of one
+    torch copy kernel over nbytes, timed with events on the current stream."""
+    x = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    y = torch.empty_like(x)
+    y.copy_(x)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    s = e0.elapsed_time(e1) / 1e3 / reps
+    del x, y
+    return 2 * nbytes / s / 1e9
 
 
 def parse():
@@ -124,6 +175,7 @@ def main():
     out = (Fm, Am, Tm)
     fp32_geom = cfg.storage == "bf16"
 
+    copy_gbs = copy_ceiling(torch)
     for i in range(args.warmup):
         r.render(sig, feat, args.lambda_th, fp32_geom=fp32_geom, out=out)
         print(f"[bench] warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
@@ -151,6 +203,9 @@ def main():
     avg_launch_s = render_ms / n_render / 1e3
     achieved = per_launch_bytes / avg_launch_s / 1e9
     hit = st["hit_rays"] / max(st["rays"], 1)
+    workload = (f"plain renderer {cfg.name}: depth {cfg.depth} octree, {scene.n} leaves, "
+                f"{scene.J} bones, C={cfg.C}, {P} poses x {cfg.n_views} cameras at "
+                f"{cfg.height}x{cfg.width}, lambda_th={args.lambda_th}")
     line = {
         "metric": "feature-map Mrays/s (C=16) learned-proposal vs plain at <=1e-3 rel err; %HBM peak",
         "value": round(value, 2),
@@ -165,9 +220,7 @@ def main():
         "dtype": "bf16-storage/f32" if cfg.storage == "bf16" else "f32",
         "data": "synthetic (seeded animal-shaped octree, ring cameras, random poses)",
         "config": {
-            "workload": (f"plain renderer {cfg.name}: depth {cfg.depth} octree, {scene.n} leaves, "
-                         f"{scene.J} bones, C={cfg.C}, {P} poses x {cfg.n_views} cameras at "
-                         f"{cfg.height}x{cfg.width}, lambda_th={args.lambda_th}"),
+            "workload": workload,
             "poses": P, "views": cfg.n_views, "height": cfg.height, "width": cfg.width,
             "C": cfg.C, "leaves": scene.n, "depth": cfg.depth, "storage": cfg.storage,
             "geometry": "fp32" if fp32_geom else "fp64",
@@ -178,8 +231,11 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": measured_traffic(workload),
             "kernel": "k_render (forward compositing)",
+            "render_source_hash": render_source_hash(),
+            "copy_ceiling_GBps": round(copy_gbs, 1),
+            "frac_of_copy_ceiling": round(achieved / copy_gbs, 4),
             "launches_per_step": launches_per_call,
             "avg_launch_us": round(avg_launch_s * 1e6, 2),
             "algorithmic_bytes_per_launch": int(per_launch_bytes),

@@ -175,6 +175,117 @@ art_status art_backward(art_ctx* ctx, int C, art_dtype dtype, const void* sigma,
                         float* d_sigma, float* d_leaf_feat);
 
 /* ---------------------------------------------------------------------------
+ * Learned ray-interval proposal (an addition to the paper's renderer: a small
+ * network predicts, per ray, the stretch of the ray that holds its composited
+ * samples, so that the traversal can skip the empty part of the ray in front
+ * of the surface)
+ * ------------------------------------------------------------------------- */
+
+/* Default margin m added on both sides of a proposed interval, in leaf edges h. */
+#define ART_PROPOSAL_MARGIN_H 2.0f
+
+/*
+ * Training labels of the proposal from the plain renderer: every ray of the
+ * current poses x cameras is traversed exactly as by art_render (same
+ * arguments and flags) and labels[ray] = (u_near, u_far) receives the entry t
+ * of its first and the exit t of its last composited sample, mapped to [0, 1]
+ * over the ray's span [t_a, t_b] inside the posed root ([-1, 1]^3, t_a >= 0).
+ * Rays with no composited sample (including rays that miss the root) get the
+ * empty interval (1, 0).
+ * labels: device float32 [P][V][H][W][2].
+ * Errors: as art_render.
+ */
+art_status art_proposal_labels(art_ctx* ctx, int C, art_dtype dtype, const void* sigma, const void* feat,
+                               float lambda_th, unsigned flags, float* labels);
+
+/*
+ * Forward render (as art_render) whose traversal starts from a proposed
+ * interval per ray.  intervals: device float32 [P][V][H][W][2] of (u_near,
+ * u_far) in the units of art_proposal_labels, or NULL to take them from the
+ * proposal network (art_proposal_set_weights; evaluated for the rays of every
+ * 8x8 tile that holds a brick).  A ray with u_near <= u_far first traverses
+ * only [t_a + u_near (t_b - t_a) - m, t_a + u_far (t_b - t_a) + m] clipped to
+ * [t_a, t_b], with m = margin_h * h; it falls back to the full traversal of
+ * [t_a, t_b] when that interval held no occupied voxel (F1) or, with
+ * f2_tau >= 0, when its transmittance on leaving the interval before t_b is
+ * still >= f2_tau (F2).  A ray with u_near > u_far (predicted empty) is
+ * traversed in full.  The result equals art_render's whenever every skipped
+ * part of a ray holds no occupied voxel.
+ * Errors: as art_render; ART_EINVAL for a negative or non-finite margin_h or
+ * a NaN f2_tau; ART_ESTATE for NULL intervals without network weights.
+ */
+art_status art_render_proposal(art_ctx* ctx, int C, art_dtype dtype, const void* sigma, const void* feat,
+                               float lambda_th, unsigned flags, const float* intervals, float margin_h,
+                               float f2_tau, float* out_feat, float* out_alpha, float* out_tfinal);
+
+/*
+ * The proposal network: x = [o (3), d (3), pose code (6 J)] -> 64 -> 64 -> 64
+ * (ReLU) -> 2 (sigmoid) = (u_near, u_far), where (o, d) is the ray (origin,
+ * unit direction, FP32) and the pose code holds, per bone j, the first and
+ * second column of the rotation of its axis-angle r_j.  Matrix products use
+ * BF16 operands with FP32 accumulation; the pose-code part of the first layer
+ * is evaluated per pose in FP32.  Weights are FP32, flat in the order W1
+ * [64][6 + 6J], b1 [64], W2 [64][64], b2, W3 [64][64], b3, W4 [2][64], b4 [2]
+ * (row-major [out][in]).
+ * Returns the parameter count for J bones (24258 for J = 40), -1 for J
+ * outside 1..255.
+ */
+int64_t art_proposal_param_count(int J);
+
+/* Copy `count` host FP32 weights in (resets the Adam state) / out.
+ * Errors: ART_ESTATE (no skeleton; get: no weights for the current skeleton),
+ * ART_EINVAL (count mismatch, NULL, non-finite weight). */
+art_status art_proposal_set_weights(art_ctx* ctx, int64_t count, const float* w);
+art_status art_proposal_get_weights(art_ctx* ctx, int64_t count, float* w);
+
+/*
+ * Network inputs and targets of selected rays: ray_id (device int64 [n]) are
+ * indices into [P][V][H][W] of the current poses and cameras; labels is the
+ * device output of art_proposal_labels.  Writes od (device float32 [n][6]: the
+ * ray origin and direction in FP32), pose (device int32 [n]) and target
+ * (device float32 [n][2]).  Synchronous.
+ * Errors: ART_ESTATE (no poses or cameras), ART_EINVAL (NULL, an id out of
+ * range).
+ */
+art_status art_proposal_gather(art_ctx* ctx, int64_t n, const int64_t* ray_id, const float* labels, float* od,
+                               int32_t* pose, float* target);
+
+/*
+ * Network outputs for n rays: od (device float32 [n][6]), pose (device int32
+ * [n], indices of the current poses) -> out (device float32 [n][2]).
+ * Synchronous.  Errors: ART_ESTATE (no weights for the current skeleton, no
+ * poses), ART_EINVAL (NULL, n < 0, a pose id out of range).
+ */
+art_status art_proposal_forward(art_ctx* ctx, int64_t n, const float* od, const int32_t* pose, float* out);
+
+/*
+ * Loss L = mean over the n rays and both outputs of SmoothL1 (beta = 1)
+ * between the network outputs and target (device float32 [n][2]), and its
+ * gradient with respect to the weights: grad (device float32 [count]), loss
+ * (device float32 [1]).  The weight gradients are contractions over rays on
+ * the matrix cores (BF16 operands, the deltas stored in BF16); partial sums
+ * over chunks of rays are added in a fixed order, so the result is
+ * deterministic.  n in 1..2^20.  Synchronous.
+ * Errors: as art_proposal_forward.
+ */
+art_status art_proposal_grad(art_ctx* ctx, int64_t n, const float* od, const int32_t* pose, const float* target,
+                             float* grad, float* loss);
+
+/*
+ * `steps` Adam steps (bias-corrected) on the FP32 weights, step s on the rays
+ * [(s mod (n / batch)) * batch, + batch) of the device arrays od / pose /
+ * target (shuffle them beforehand; n mod batch rays at the end are unused).
+ * The Adam state persists across calls until the weights are set again.
+ * loss_log: host float32 [steps] of the batch losses (before each update), or
+ * NULL.  batch in 1..2^20, n >= batch.  Synchronous.
+ * Errors: as art_proposal_forward; ART_EINVAL for hyper-parameters outside
+ * lr > 0, 0 <= beta < 1, eps > 0.
+ */
+art_status art_proposal_train(art_ctx* ctx, int64_t n, const float* od, const int32_t* pose, const float* target,
+                              int64_t batch, int steps, float lr, float beta1, float beta2, float eps,
+                              float* loss_log);
+
+/* ---------------------------------------------------------------------------
  * Inspection of intermediate results (parity tests, debugging)
  * ------------------------------------------------------------------------- */
 
@@ -219,20 +330,22 @@ art_status art_get_hits(art_ctx* ctx, int pose, int view, int C, art_dtype dtype
                         int max_hits, int32_t* leaf, double* delta, int32_t* count);
 
 /*
- * Counters of the last art_render / art_backward call, host int64 [12]:
+ * Counters of the last render / backward / label call, host int64 [14]:
  * {rays, composited samples, rays with at least one sample, dropped leaves,
  *  collisions, bricks (summed over poses), tile/brick pairs, kernel launches,
  *  tile-list entries summed over the 8x8 tiles, traversal rounds summed over
  *  the compositing kernel's waves, ray/voxel partition steps summed over rays,
- *  rays of the tiles the compositing kernel rendered (non-empty brick list)}.
+ *  rays of the tiles the compositing kernel rendered (non-empty brick list),
+ *  rays that started from a proposed interval, rays of those that fell back
+ *  to the full traversal (art_render_proposal only; 0 otherwise)}.
  */
 art_status art_get_stats(art_ctx* ctx, int64_t* stats);
 
 /*
- * Per-stage GPU time of the last call made with ART_TIMING, host float [6] in
- * milliseconds: {fk, skin, octree build, tile binning, render, total}, summed
- * over poses.  `render` covers only the compositing kernel launches;
- * n_render receives their number.
+ * Per-stage GPU time of the last call made with ART_TIMING, host float [7] in
+ * milliseconds: {fk, skin, octree build, tile binning, render, total,
+ * proposal-network inference}, summed over poses.  `render` covers only the
+ * compositing kernel launches; n_render receives their number.
  */
 art_status art_get_timing(art_ctx* ctx, float* ms, int* n_render);
 

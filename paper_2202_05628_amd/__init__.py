@@ -20,7 +20,7 @@ from typing import Optional, Tuple
 import numpy as np
 
 from . import _lib
-from ._lib import ART_BF16, ART_F32, ART_GEOM_FP32, ART_TIMING, ArtemisError
+from ._lib import ART_BF16, ART_F32, ART_GEOM_FP32, ART_PROPOSAL_MARGIN_H, ART_TIMING, ArtemisError
 
 __all__ = ["Renderer", "render", "RenderFn", "ArtemisError", "ART_GEOM_FP32", "ART_TIMING",
            "LAMBDA_TH"]
@@ -159,6 +159,94 @@ class Renderer:
                     "art_render")
         return F, A, T
 
+    def proposal_labels(self, sigma, feat, lambda_th: float = LAMBDA_TH, fp32_geom: bool = False,
+                        timing: bool = False, out=None):
+        """Interval labels [P][V][H][W][2] = (u_near, u_far) of every ray from the
+        plain traversal ((1, 0) for rays without a composited sample)."""
+        torch = self._torch
+        C, dtype = self._flut(sigma, feat)
+        lab = out if out is not None else torch.empty((self.P, self.V, self.H, self.W, 2), dtype=torch.float32,
+                                                      device=sigma.device)
+        self._check(self.lib.art_proposal_labels(self._h, C, dtype, _tptr(sigma), _tptr(feat), float(lambda_th),
+                                                 self._flags(fp32_geom, timing), _tptr(lab)),
+                    "art_proposal_labels")
+        return lab
+
+    def render_proposal(self, sigma, feat, intervals, lambda_th: float = LAMBDA_TH,
+                        margin_h: float = ART_PROPOSAL_MARGIN_H, f2_tau: float = -1.0, fp32_geom: bool = False,
+                        timing: bool = False, out=None, want_tfinal: bool = True):
+        """Forward render whose traversal starts from the proposed intervals
+        [P][V][H][W][2] (u_near, u_far), with the full traversal as fallback."""
+        torch = self._torch
+        C, dtype = self._flut(sigma, feat)
+        dev = sigma.device
+        if out is None:
+            F = torch.empty((self.P, self.V, C, self.H, self.W), dtype=torch.float32, device=dev)
+            A = torch.empty((self.P, self.V, self.H, self.W), dtype=torch.float32, device=dev)
+            T = torch.empty_like(A) if want_tfinal else None
+        else:
+            F, A, T = out
+        iv = None if intervals is None else intervals.contiguous().float()
+        self._check(self.lib.art_render_proposal(self._h, C, dtype, _tptr(sigma), _tptr(feat), float(lambda_th),
+                                                 self._flags(fp32_geom, timing), _tptr(iv), float(margin_h),
+                                                 float(f2_tau), _tptr(F), _tptr(A), _tptr(T)),
+                    "art_render_proposal")
+        return F, A, T
+
+    # ---- proposal network ----------------------------------------------------------
+    def proposal_param_count(self) -> int:
+        return int(self.lib.art_proposal_param_count(int(self.J)))
+
+    def set_proposal_weights(self, w) -> None:
+        w = np.ascontiguousarray(w, dtype=np.float32).reshape(-1)
+        self._check(self.lib.art_proposal_set_weights(self._h, w.size, _ptr(w)), "art_proposal_set_weights")
+
+    def get_proposal_weights(self) -> np.ndarray:
+        w = np.zeros(self.proposal_param_count(), dtype=np.float32)
+        self._check(self.lib.art_proposal_get_weights(self._h, w.size, _ptr(w)), "art_proposal_get_weights")
+        return w
+
+    def proposal_gather(self, ray_id, labels):
+        """Network inputs (od [n][6], pose [n]) and targets [n][2] of the rays
+        ray_id (int64 indices into [P][V][H][W]) from a label map."""
+        torch = self._torch
+        ray_id = ray_id.contiguous().to(torch.int64)
+        n = ray_id.numel()
+        dev = labels.device
+        od = torch.empty((n, 6), dtype=torch.float32, device=dev)
+        pose = torch.empty((n,), dtype=torch.int32, device=dev)
+        tgt = torch.empty((n, 2), dtype=torch.float32, device=dev)
+        self._check(self.lib.art_proposal_gather(self._h, n, _tptr(ray_id), _tptr(labels.contiguous()), _tptr(od),
+                                                 _tptr(pose), _tptr(tgt)), "art_proposal_gather")
+        return od, pose, tgt
+
+    def proposal_forward(self, od, pose):
+        torch = self._torch
+        out = torch.empty((od.shape[0], 2), dtype=torch.float32, device=od.device)
+        self._check(self.lib.art_proposal_forward(self._h, od.shape[0], _tptr(od.contiguous()),
+                                                  _tptr(pose.contiguous()), _tptr(out)), "art_proposal_forward")
+        return out
+
+    def proposal_grad(self, od, pose, target):
+        """(loss, gradient [count]) of the mean SmoothL1 loss over the rays."""
+        torch = self._torch
+        g = torch.empty((self.proposal_param_count(),), dtype=torch.float32, device=od.device)
+        L = torch.empty((1,), dtype=torch.float32, device=od.device)
+        self._check(self.lib.art_proposal_grad(self._h, od.shape[0], _tptr(od.contiguous()),
+                                               _tptr(pose.contiguous()), _tptr(target.contiguous()), _tptr(g),
+                                               _tptr(L)), "art_proposal_grad")
+        return float(L.item()), g
+
+    def proposal_train(self, od, pose, target, batch: int = 16384, steps: int = 1000, lr: float = 1e-3,
+                       betas=(0.9, 0.999), eps: float = 1e-8) -> np.ndarray:
+        """Adam steps over consecutive batches; returns the batch losses."""
+        log = np.zeros(max(steps, 1), dtype=np.float32)
+        self._check(self.lib.art_proposal_train(self._h, od.shape[0], _tptr(od.contiguous()),
+                                                _tptr(pose.contiguous()), _tptr(target.contiguous()), int(batch),
+                                                int(steps), float(lr), float(betas[0]), float(betas[1]), float(eps),
+                                                _ptr(log)), "art_proposal_train")
+        return log[:steps]
+
     def backward(self, sigma, feat, F, T, dF, dA=None, lambda_th: float = LAMBDA_TH,
                  fp32_geom: bool = False, timing: bool = False, d_sigma=None, d_feat=None):
         """Accumulate dL/dsigma [n] and dL/dfeat [n][C] (float32) for the last
@@ -227,17 +315,17 @@ class Renderer:
         return leaf.cpu().numpy(), delta.cpu().numpy(), count.cpu().numpy()
 
     def stats(self) -> dict:
-        s = np.zeros(12, dtype=np.int64)
+        s = np.zeros(14, dtype=np.int64)
         self._check(self.lib.art_get_stats(self._h, _ptr(s)), "art_get_stats")
         keys = ["rays", "samples", "hit_rays", "dropped", "collisions", "bricks", "pairs", "launches",
-                "list_entries", "rounds", "steps", "tile_rays"]
+                "list_entries", "rounds", "steps", "tile_rays", "proposal_rays", "fallbacks"]
         return dict(zip(keys, (int(x) for x in s)))
 
     def timing(self) -> dict:
-        ms = np.zeros(6, dtype=np.float32)
+        ms = np.zeros(7, dtype=np.float32)
         nr = ctypes.c_int(0)
         self._check(self.lib.art_get_timing(self._h, _ptr(ms), ctypes.byref(nr)), "art_get_timing")
-        keys = ["fk", "skin", "build", "bin", "render", "total"]
+        keys = ["fk", "skin", "build", "bin", "render", "total", "proposal"]
         out = dict(zip(keys, (float(x) for x in ms)))
         out["n_render"] = int(nr.value)
         return out

@@ -16,6 +16,7 @@ ART_OK, ART_EINVAL, ART_ENOMEM, ART_EDEVICE, ART_ESTATE, ART_EUNSUPPORTED = 0, -
 ART_F32, ART_BF16 = 0, 1
 ART_GEOM_FP32 = 1
 ART_TIMING = 2
+ART_PROPOSAL_MARGIN_H = 2.0
 
 STATUS_NAMES = {0: "ART_OK", -1: "ART_EINVAL", -2: "ART_ENOMEM", -3: "ART_EDEVICE",
                 -4: "ART_ESTATE", -5: "ART_EUNSUPPORTED"}
@@ -38,6 +39,15 @@ SIGNATURES = [
     ("art_set_cameras", _I, [_P, _I, _I, _I, _P, _P]),
     ("art_render", _I, [_P, _I, _I, _P, _P, _F, _U, _P, _P, _P]),
     ("art_backward", _I, [_P, _I, _I, _P, _P, _F, _U, _P, _P, _P, _P, _P, _P]),
+    ("art_proposal_labels", _I, [_P, _I, _I, _P, _P, _F, _U, _P]),
+    ("art_render_proposal", _I, [_P, _I, _I, _P, _P, _F, _U, _P, _F, _F, _P, _P, _P]),
+    ("art_proposal_param_count", _L, [_I]),
+    ("art_proposal_set_weights", _I, [_P, _L, _P]),
+    ("art_proposal_get_weights", _I, [_P, _L, _P]),
+    ("art_proposal_gather", _I, [_P, _L, _P, _P, _P, _P, _P]),
+    ("art_proposal_forward", _I, [_P, _L, _P, _P, _P]),
+    ("art_proposal_grad", _I, [_P, _L, _P, _P, _P, _P, _P]),
+    ("art_proposal_train", _I, [_P, _L, _P, _P, _P, _L, _I, _F, _F, _F, _F, _P]),
     ("art_get_bones", _I, [_P, _P]),
     ("art_get_posed_keys", _I, [_P, _I, _U, _P]),
     ("art_get_octree", _I, [_P, _I, _U, _P, _P, _P, _P, _P, _P]),

@@ -10,6 +10,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <string>
 #include <vector>
@@ -73,6 +74,7 @@ struct CallPlan {
     int Vg = 1;           // views per group
     int ngroups = 1;
     int mbits = 0;
+    bool net = false;     // proposal network inference (per-item intervals)
 };
 
 art_status check_build_state(art_ctx* ctx) {
@@ -145,7 +147,8 @@ size_t slot_bytes(const art_ctx* ctx, const CallPlan& pl, size_t pair_cap) {
     const size_t tiles = (size_t)ctx->V * ((ctx->W + 7) / 8) * ((ctx->H + 7) / 8);
     // octree slot + sort scratch + bin counts + tile lists and their sort scratch + tile ranges
     return n * (4 + 4 + 4 + 4 + 64) + n * 16 + n * pl.Vg * 8 +
-           (size_t)pl.ngroups * pair_cap * 8 + pair_cap * 8 + tiles * 12 + (size_t)pl.ngroups * 9;
+           (size_t)pl.ngroups * pair_cap * 8 + pair_cap * 8 + tiles * 12 + (size_t)pl.ngroups * 9 +
+           (pl.net ? tiles * 64 * 8 : 0);
 }
 
 // Sort / scan scratch and the per-slot arrays of `slots` poses.
@@ -176,6 +179,7 @@ art_status ensure_scratch(art_ctx* ctx, const CallPlan& pl, int slots) {
         {&s.tile_start, S * tiles * 4}, {&s.tile_end, S * tiles * 4},
         {&s.ovf, S * pl.ngroups * 2 * 4},
         {&s.items, S * tiles * 4}, {&s.queue, 64},
+        {&s.interval, pl.net ? S * tiles * 64 * 8 : 0},
     });
     if (rc == ART_OK) s.slots = std::max(s.slots, slots);
     return rc;
@@ -210,7 +214,7 @@ struct Timing {
         stage.push_back(stage_id);
     }
     void finish(art_ctx* ctx) {
-        for (int i = 0; i < 6; ++i) ctx->timing_ms[i] = 0.0f;
+        for (int i = 0; i < 7; ++i) ctx->timing_ms[i] = 0.0f;
         ctx->timing_nrender = 0;
         for (size_t i = 1; i < ev.size(); ++i) {
             float ms = 0.0f;
@@ -242,6 +246,11 @@ struct PassOut {
     const float* d_alpha = nullptr;
     float* d_sigma = nullptr;
     float* d_leaf_feat = nullptr;
+    // proposal: labels (mode 3) / intervals, margin and F2 threshold (mode 4)
+    float* labels = nullptr;
+    const float* intervals = nullptr;
+    float margin = 0.0f;
+    float f2_tau = -1.0f;
     // debug
     int max_hits = 0;
     int debug_view = 0;
@@ -362,6 +371,10 @@ art_status run_batch(art_ctx* ctx, const CallPlan& pl, int mode, float lambda, c
     if (o.d_alpha) r.d_alpha = o.d_alpha + m0 * HW;
     r.d_sigma = o.d_sigma;
     r.d_leaf_feat = o.d_leaf_feat;
+    if (o.labels) r.labels = o.labels + m0 * HW * 2;
+    if (o.intervals) r.interval = o.intervals + m0 * HW * 2;
+    r.margin = o.margin;
+    r.f2_tau = o.f2_tau;
     r.max_hits = o.max_hits;
     r.debug_view = o.debug_view;
     r.hit_leaf = o.hit_leaf;
@@ -387,14 +400,57 @@ art_status run_batch(art_ctx* ctx, const CallPlan& pl, int mode, float lambda, c
     tl.out_feat = r.out_feat;
     tl.out_alpha = r.out_alpha;
     tl.out_tfinal = r.out_tfinal;
+    tl.labels = r.labels;
     tl.hit_count = r.hit_count;
     tl.stats = s.stats.as<unsigned long long>();
     ART_TRY_HIP(launch_tiles(tl, st), "tile compaction");
-    *launches += (r.out_feat || r.hit_count) ? 3 : 2;
+    *launches += (r.out_feat || r.hit_count || r.labels) ? 3 : 2;
     tm.record(st, 3);
+    if (mode == 4 && !o.intervals) {   // proposal network: intervals of the rays of every non-empty tile
+        InferLaunch ia{};
+        ia.packed = ctx->mlp_packed.as<uint16_t>();
+        ia.theta = ctx->mlp_theta.as<float>();
+        ia.cbias = ctx->mlp_cbias.as<float>();
+        ia.m = mlp_dims(ctx->J);
+        ia.cam = ctx->cam.as<CamParams>();
+        ia.items = s.items.as<uint32_t>();
+        ia.n_items = s.queue.as<uint32_t>();
+        ia.V = ctx->V;
+        ia.TX = (ctx->W + 7) / 8;
+        ia.TPV = (int)TPV;
+        ia.pose0 = p0;
+        ia.out = s.interval.as<float>();
+        ART_TRY_HIP(launch_mlp_infer_tiles(ia, (unsigned)num_cus() * 8u, st), "proposal inference");
+        *launches += 1;
+        r.interval = s.interval.as<float>();
+        r.interval_by_item = true;
+        tm.record(st, 6);
+    }
     ART_TRY_HIP(launch_render(r, st), "render");
     *launches += 1;
     tm.record(st, 4);
+    return ART_OK;
+}
+
+// Pose codes of the current poses, BF16 operands and per-pose biases of the
+// current proposal weights.
+art_status mlp_prepare(art_ctx* ctx) {
+    if (ctx->mlp_J <= 0 || ctx->mlp_J != ctx->J)
+        return fail(ctx, ART_ESTATE, "no proposal weights for the current skeleton (art_proposal_set_weights)");
+    if (ctx->P <= 0) return fail(ctx, ART_ESTATE, "no poses (art_set_poses)");
+    const MlpDims m = mlp_dims(ctx->J);
+    hipStream_t st = ctx->stream;
+    art_status rc = ensure_bufs(ctx, {{&ctx->mlp_code, (size_t)ctx->P * 6 * ctx->J * 4},
+                                      {&ctx->mlp_packed, (size_t)mlp_packed_elems() * 2},
+                                      {&ctx->mlp_cbias, (size_t)ctx->P * 64 * 4}});
+    if (rc != ART_OK) return rc;
+    if (ctx->code_version != ctx->poses_version) {
+        ART_TRY_HIP(launch_pose_code(ctx->pose.as<double>(), ctx->J, ctx->P, ctx->mlp_code.as<float>(), st), "pose code");
+        ctx->code_version = ctx->poses_version;
+    }
+    ART_TRY_HIP(launch_mlp_prep(ctx->mlp_theta.as<float>(), m, ctx->mlp_code.as<float>(), ctx->P,
+                                ctx->mlp_packed.as<uint16_t>(), ctx->mlp_cbias.as<float>(), st),
+                "proposal prep");
     return ART_OK;
 }
 
@@ -406,6 +462,7 @@ art_status render_call(art_ctx* ctx, int C, art_dtype dtype, const void* sigma, 
     CallPlan pl;
     rc = plan_call(ctx, C, dtype, flags, &pl);
     if (rc != ART_OK) return rc;
+    pl.net = mode == 4 && !o.intervals;
     if (!sigma || !feat) return fail(ctx, ART_EINVAL, "sigma / feat must be device pointers");
     if (!(lambda >= 0.0f && lambda < 1.0f)) return fail(ctx, ART_EINVAL, "lambda_th must be in [0, 1)");
     const int P = pose_hi - pose_lo;
@@ -466,6 +523,8 @@ art_status render_call(art_ctx* ctx, int C, art_dtype dtype, const void* sigma, 
     ctx->stats[9] = (int64_t)hst[8];
     ctx->stats[10] = (int64_t)hst[9];
     ctx->stats[11] = (int64_t)hst[10];
+    ctx->stats[12] = (int64_t)hst[11];
+    ctx->stats[13] = (int64_t)hst[12];
     tm.finish(ctx);
     return ART_OK;
 }
@@ -476,6 +535,18 @@ art_status render_call(art_ctx* ctx, int C, art_dtype dtype, const void* sigma, 
 // render launcher (kernel argument packing)
 // ---------------------------------------------------------------------------
 namespace art {
+int num_cus() {
+    static int n_cu = 0;
+    if (n_cu == 0) {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+            n_cu = prop.multiProcessorCount;
+        if (n_cu <= 0) n_cu = 256;
+    }
+    return n_cu;
+}
+
 hipError_t launch_render(const RenderLaunch& r, hipStream_t st) {
     const Scratch& s = *r.s;
     RArgs a{};
@@ -515,6 +586,11 @@ hipError_t launch_render(const RenderLaunch& r, hipStream_t st) {
     a.d_alpha = r.d_alpha;
     a.d_sigma = r.d_sigma;
     a.d_leaf_feat = r.d_leaf_feat;
+    a.labels = r.labels;
+    a.interval = r.interval;
+    a.interval_by_item = r.interval_by_item ? 1 : 0;
+    a.margin = r.margin;
+    a.f2_tau = r.f2_tau;
     a.max_hits = r.max_hits;
     a.debug_view = r.debug_view;
     a.hit_leaf = r.hit_leaf;
@@ -522,15 +598,7 @@ hipError_t launch_render(const RenderLaunch& r, hipStream_t st) {
     a.hit_count = r.hit_count;
     a.stats = s.stats.as<unsigned long long>();
     // persistent single-wave workgroups: about two per resident slot
-    static int n_cu = 0;
-    if (n_cu == 0) {
-        int dev = 0;
-        hipDeviceProp_t prop;
-        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
-            n_cu = prop.multiProcessorCount;
-        if (n_cu <= 0) n_cu = 256;
-    }
-    const unsigned grid = (unsigned)n_cu * 32u;
+    const unsigned grid = (unsigned)num_cus() * 32u;
     switch (r.C) {
         case 4: return launch_render_c<4>(r, a, grid, st);
         case 8: return launch_render_c<8>(r, a, grid, st);
@@ -578,7 +646,9 @@ void art_destroy(art_ctx* ctx) {
                           &ctx->s.brick_key, &ctx->s.brick_row, &ctx->s.brick_mask, &ctx->s.bin_cnt, &ctx->s.bin_off, &ctx->s.pk0, &ctx->s.pv0,
                           &ctx->s.pk1, &ctx->s.pair_v, &ctx->s.tile_start, &ctx->s.tile_end,
                           &ctx->s.counters, &ctx->s.stats, &ctx->s.ovf, &ctx->s.items, &ctx->s.queue,
-                          &ctx->s.redo};
+                          &ctx->s.redo, &ctx->s.interval, &ctx->mlp_theta, &ctx->mlp_m1, &ctx->mlp_m2,
+                          &ctx->mlp_packed, &ctx->mlp_cbias, &ctx->mlp_code, &ctx->mlp_S, &ctx->mlp_part,
+                          &ctx->mlp_lossp, &ctx->mlp_loss, &ctx->mlp_flag};
         for (DevBuf* b : bufs) b->release();
     }
     delete ctx;
@@ -715,6 +785,7 @@ art_status art_set_poses(art_ctx* ctx, int P, const double* r, const double* R, 
     ctx->pose.release();
     ctx->pose = pb;
     ctx->P = P;
+    ctx->poses_version++;
     return ART_OK;
 }
 
@@ -795,6 +866,217 @@ art_status art_backward(art_ctx* ctx, int C, art_dtype dtype, const void* sigma,
     o.d_sigma = d_sigma;
     o.d_leaf_feat = d_leaf_feat;
     return render_call(ctx, C, dtype, sigma, feat, lambda_th, flags, 1, o, 0, ctx->P);
+}
+
+art_status art_proposal_labels(art_ctx* ctx, int C, art_dtype dtype, const void* sigma, const void* feat,
+                               float lambda_th, unsigned flags, float* labels) {
+    if (!ctx) return ART_EINVAL;
+    if (!labels) return fail(ctx, ART_EINVAL, "labels is NULL");
+    DeviceGuard g(ctx->device);
+    PassOut o;
+    o.labels = labels;
+    return render_call(ctx, C, dtype, sigma, feat, lambda_th, flags, 3, o, 0, ctx->P);
+}
+
+art_status art_render_proposal(art_ctx* ctx, int C, art_dtype dtype, const void* sigma, const void* feat,
+                               float lambda_th, unsigned flags, const float* intervals, float margin_h,
+                               float f2_tau, float* out_feat, float* out_alpha, float* out_tfinal) {
+    if (!ctx) return ART_EINVAL;
+    if (!out_feat || !out_alpha) return fail(ctx, ART_EINVAL, "out_feat / out_alpha is NULL");
+    if (!(margin_h >= 0.0f && margin_h < 1e30f)) return fail(ctx, ART_EINVAL, "margin_h must be finite and >= 0");
+    if (!(f2_tau == f2_tau)) return fail(ctx, ART_EINVAL, "f2_tau is NaN");
+    DeviceGuard g(ctx->device);
+    if (!intervals) {
+        art_status rc = check_render_state(ctx);
+        if (rc != ART_OK) return rc;
+        rc = mlp_prepare(ctx);
+        if (rc != ART_OK) return rc;
+    }
+    PassOut o;
+    o.out_feat = out_feat;
+    o.out_alpha = out_alpha;
+    o.out_tfinal = out_tfinal;
+    o.intervals = intervals;
+    o.margin = (float)(margin_h / (double)(1 << std::max(ctx->depth, 0)));
+    o.f2_tau = f2_tau;
+    return render_call(ctx, C, dtype, sigma, feat, lambda_th, flags, 4, o, 0, ctx->P);
+}
+
+int64_t art_proposal_param_count(int J) {
+    if (J < 1 || J > 255) return -1;
+    return mlp_dims(J).np;
+}
+
+art_status art_proposal_set_weights(art_ctx* ctx, int64_t count, const float* w) {
+    if (!ctx) return ART_EINVAL;
+    if (ctx->J <= 0) return fail(ctx, ART_ESTATE, "no skeleton (art_set_skeleton)");
+    const MlpDims m = mlp_dims(ctx->J);
+    if (!w || count != m.np)
+        return fail(ctx, ART_EINVAL, "expected " + std::to_string(m.np) + " weights for J = " + std::to_string(ctx->J));
+    for (int64_t i = 0; i < count; ++i)
+        if (!std::isfinite(w[i])) return fail(ctx, ART_EINVAL, "weights must be finite");
+    DeviceGuard g(ctx->device);
+    hipStream_t st = ctx->stream;
+    const size_t bytes = (size_t)m.np * 4;
+    art_status rc = ensure_bufs(ctx, {{&ctx->mlp_theta, bytes}, {&ctx->mlp_m1, bytes}, {&ctx->mlp_m2, bytes}});
+    if (rc != ART_OK) return rc;
+    ART_TRY_HIP(hipMemcpyAsync(ctx->mlp_theta.p, w, bytes, hipMemcpyHostToDevice, st), "copy");
+    ART_TRY_HIP(launch_fill_u32(ctx->mlp_m1.as<uint32_t>(), 0u, (size_t)m.np, st), "fill");
+    ART_TRY_HIP(launch_fill_u32(ctx->mlp_m2.as<uint32_t>(), 0u, (size_t)m.np, st), "fill");
+    ART_TRY_HIP(hipStreamSynchronize(st), "copy");
+    ctx->mlp_J = ctx->J;
+    ctx->mlp_step = 0;
+    return ART_OK;
+}
+
+art_status art_proposal_get_weights(art_ctx* ctx, int64_t count, float* w) {
+    if (!ctx) return ART_EINVAL;
+    if (ctx->mlp_J <= 0 || ctx->mlp_J != ctx->J)
+        return fail(ctx, ART_ESTATE, "no proposal weights for the current skeleton (art_proposal_set_weights)");
+    const MlpDims m = mlp_dims(ctx->J);
+    if (!w || count != m.np) return fail(ctx, ART_EINVAL, "expected " + std::to_string(m.np) + " weights");
+    DeviceGuard g(ctx->device);
+    ART_TRY_HIP(hipMemcpyAsync(w, ctx->mlp_theta.p, (size_t)m.np * 4, hipMemcpyDeviceToHost, ctx->stream), "copy");
+    ART_TRY_HIP(hipStreamSynchronize(ctx->stream), "copy");
+    return ART_OK;
+}
+
+art_status art_proposal_gather(art_ctx* ctx, int64_t n, const int64_t* ray_id, const float* labels, float* od,
+                               int32_t* pose, float* target) {
+    if (!ctx) return ART_EINVAL;
+    if (ctx->P <= 0) return fail(ctx, ART_ESTATE, "no poses (art_set_poses)");
+    if (ctx->V <= 0) return fail(ctx, ART_ESTATE, "no cameras (art_set_cameras)");
+    if (n < 0) return fail(ctx, ART_EINVAL, "n must be >= 0");
+    if (n > 0 && (!ray_id || !labels || !od || !pose || !target)) return fail(ctx, ART_EINVAL, "NULL buffer");
+    DeviceGuard g(ctx->device);
+    hipStream_t st = ctx->stream;
+    ART_TRY_HIP(ctx->mlp_flag.ensure(64), "device allocation");
+    ART_TRY_HIP(launch_fill_u32(ctx->mlp_flag.as<uint32_t>(), 0u, 1, st), "fill");
+    ART_TRY_HIP(launch_mlp_gather(ray_id, n, labels, ctx->cam.as<CamParams>(), ctx->P, ctx->V, ctx->H, ctx->W, od,
+                                  pose, target, ctx->mlp_flag.as<uint32_t>(), st),
+                "gather");
+    uint32_t bad = 0;
+    ART_TRY_HIP(hipMemcpyAsync(&bad, ctx->mlp_flag.p, 4, hipMemcpyDeviceToHost, st), "copy");
+    ART_TRY_HIP(hipStreamSynchronize(st), "gather");
+    if (bad) return fail(ctx, ART_EINVAL, "ray id outside [0, P*V*H*W)");
+    return ART_OK;
+}
+
+namespace {
+constexpr int64_t kMaxMlpBatch = (int64_t)1 << 20;
+
+art_status check_bad_pose(art_ctx* ctx) {
+    uint32_t bad = 0;
+    ART_TRY_HIP(hipMemcpyAsync(&bad, ctx->mlp_flag.p, 4, hipMemcpyDeviceToHost, ctx->stream), "copy");
+    ART_TRY_HIP(hipStreamSynchronize(ctx->stream), "proposal network");
+    if (bad) return fail(ctx, ART_EINVAL, "pose id outside [0, P)");
+    return ART_OK;
+}
+
+art_status ensure_mlp_train_bufs(art_ctx* ctx, int64_t n) {
+    const MlpDims m = mlp_dims(ctx->J);
+    const size_t chunks = (size_t)(mlp_pad(n) / 256);
+    return ensure_bufs(ctx, {{&ctx->mlp_S, mlp_scratch_bytes(n)},
+                             {&ctx->mlp_part, chunks * (size_t)m.np * 4},
+                             {&ctx->mlp_lossp, (size_t)mlp_loss_parts(n) * 4},
+                             {&ctx->mlp_flag, 64}});
+}
+}  // namespace
+
+art_status art_proposal_forward(art_ctx* ctx, int64_t n, const float* od, const int32_t* pose, float* out) {
+    if (!ctx) return ART_EINVAL;
+    if (n < 0) return fail(ctx, ART_EINVAL, "n must be >= 0");
+    if (n > 0 && (!od || !pose || !out)) return fail(ctx, ART_EINVAL, "NULL buffer");
+    DeviceGuard g(ctx->device);
+    if (ctx->P <= 0) return fail(ctx, ART_ESTATE, "no poses (art_set_poses)");
+    art_status rc = mlp_prepare(ctx);
+    if (rc != ART_OK) return rc;
+    if (n == 0) return ART_OK;
+    ART_TRY_HIP(ctx->mlp_flag.ensure(64), "device allocation");
+    ART_TRY_HIP(launch_fill_u32(ctx->mlp_flag.as<uint32_t>(), 0u, 1, ctx->stream), "fill");
+    ART_TRY_HIP(launch_mlp_forward(ctx->mlp_packed.as<uint16_t>(), ctx->mlp_theta.as<float>(),
+                                   ctx->mlp_cbias.as<float>(), mlp_dims(ctx->J), od, pose, ctx->P, n, out,
+                                   ctx->mlp_flag.as<uint32_t>(), ctx->stream),
+                "proposal forward");
+    return check_bad_pose(ctx);
+}
+
+art_status art_proposal_grad(art_ctx* ctx, int64_t n, const float* od, const int32_t* pose, const float* target,
+                             float* grad, float* loss) {
+    if (!ctx) return ART_EINVAL;
+    if (n < 1 || n > kMaxMlpBatch) return fail(ctx, ART_EINVAL, "n must be in 1..2^20");
+    if (!od || !pose || !target || !grad || !loss) return fail(ctx, ART_EINVAL, "NULL buffer");
+    DeviceGuard g(ctx->device);
+    if (ctx->P <= 0) return fail(ctx, ART_ESTATE, "no poses (art_set_poses)");
+    art_status rc = mlp_prepare(ctx);
+    if (rc != ART_OK) return rc;
+    rc = ensure_mlp_train_bufs(ctx, n);
+    if (rc != ART_OK) return rc;
+    hipStream_t st = ctx->stream;
+    const MlpDims m = mlp_dims(ctx->J);
+    ART_TRY_HIP(launch_fill_u32(ctx->mlp_flag.as<uint32_t>(), 0u, 1, st), "fill");
+    ART_TRY_HIP(launch_mlp_grad(ctx->mlp_packed.as<uint16_t>(), ctx->mlp_theta.as<float>(), ctx->mlp_cbias.as<float>(),
+                                ctx->mlp_code.as<float>(), m, od, pose, target, ctx->P, n, ctx->mlp_S.as<uint16_t>(),
+                                ctx->mlp_part.as<float>(), ctx->mlp_lossp.as<float>(), ctx->mlp_flag.as<uint32_t>(),
+                                st),
+                "proposal gradient");
+    ART_TRY_HIP(launch_mlp_reduce(ctx->mlp_part.as<float>(), n, m, grad, ctx->mlp_theta.as<float>(), nullptr, nullptr,
+                                  nullptr, ctx->mlp_lossp.as<float>(), loss, st),
+                "proposal gradient");
+    return check_bad_pose(ctx);
+}
+
+art_status art_proposal_train(art_ctx* ctx, int64_t n, const float* od, const int32_t* pose, const float* target,
+                              int64_t batch, int steps, float lr, float beta1, float beta2, float eps,
+                              float* loss_log) {
+    if (!ctx) return ART_EINVAL;
+    if (batch < 1 || batch > kMaxMlpBatch) return fail(ctx, ART_EINVAL, "batch must be in 1..2^20");
+    if (n < batch) return fail(ctx, ART_EINVAL, "n must be >= batch");
+    if (steps < 0) return fail(ctx, ART_EINVAL, "steps must be >= 0");
+    if (!(lr > 0.0f && lr < 1e30f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) ||
+        !(eps > 0.0f && eps < 1e30f))
+        return fail(ctx, ART_EINVAL, "Adam hyper-parameters out of range");
+    if (!od || !pose || !target) return fail(ctx, ART_EINVAL, "NULL buffer");
+    DeviceGuard g(ctx->device);
+    if (ctx->P <= 0) return fail(ctx, ART_ESTATE, "no poses (art_set_poses)");
+    art_status rc = mlp_prepare(ctx);
+    if (rc != ART_OK) return rc;
+    rc = ensure_mlp_train_bufs(ctx, batch);
+    if (rc != ART_OK) return rc;
+    rc = ensure_bufs(ctx, {{&ctx->mlp_loss, (size_t)std::max(steps, 1) * 4}});
+    if (rc != ART_OK) return rc;
+    hipStream_t st = ctx->stream;
+    const MlpDims m = mlp_dims(ctx->J);
+    const int64_t nb = n / batch;
+    ART_TRY_HIP(launch_fill_u32(ctx->mlp_flag.as<uint32_t>(), 0u, 1, st), "fill");
+    for (int s = 0; s < steps; ++s) {
+        const int64_t off = (s % nb) * batch;
+        if (s > 0)   // operands and pose biases of the updated weights
+            ART_TRY_HIP(launch_mlp_prep(ctx->mlp_theta.as<float>(), m, ctx->mlp_code.as<float>(), ctx->P,
+                                        ctx->mlp_packed.as<uint16_t>(), ctx->mlp_cbias.as<float>(), st),
+                        "proposal prep");
+        ART_TRY_HIP(launch_mlp_grad(ctx->mlp_packed.as<uint16_t>(), ctx->mlp_theta.as<float>(),
+                                    ctx->mlp_cbias.as<float>(), ctx->mlp_code.as<float>(), m, od + off * 6,
+                                    pose + off, target + off * 2, ctx->P, batch, ctx->mlp_S.as<uint16_t>(),
+                                    ctx->mlp_part.as<float>(), ctx->mlp_lossp.as<float>(),
+                                    ctx->mlp_flag.as<uint32_t>(), st),
+                    "proposal gradient");
+        const int64_t t = ++ctx->mlp_step;
+        AdamStep ad;
+        ad.lr = lr;
+        ad.beta1 = beta1;
+        ad.beta2 = beta2;
+        ad.eps = eps;
+        ad.bc1 = (float)(1.0 - std::pow((double)beta1, (double)t));
+        ad.bc2 = (float)(1.0 - std::pow((double)beta2, (double)t));
+        ART_TRY_HIP(launch_mlp_reduce(ctx->mlp_part.as<float>(), batch, m, nullptr, ctx->mlp_theta.as<float>(),
+                                      ctx->mlp_m1.as<float>(), ctx->mlp_m2.as<float>(), &ad, ctx->mlp_lossp.as<float>(),
+                                      ctx->mlp_loss.as<float>() + s, st),
+                    "proposal Adam step");
+    }
+    if (loss_log && steps > 0)
+        ART_TRY_HIP(hipMemcpyAsync(loss_log, ctx->mlp_loss.p, (size_t)steps * 4, hipMemcpyDeviceToHost, st), "copy");
+    return check_bad_pose(ctx);
 }
 
 art_status art_get_hits(art_ctx* ctx, int pose, int view, int C, art_dtype dtype, const void* sigma,
@@ -952,7 +1234,7 @@ art_status art_get_timing(art_ctx* ctx, float* ms, int* n_render) {
     if (!ctx) return ART_EINVAL;
     if (!ms) return fail(ctx, ART_EINVAL, "ms is NULL");
     if (!ctx->timing_valid) return fail(ctx, ART_ESTATE, "no call with ART_TIMING yet");
-    for (int i = 0; i < 6; ++i) ms[i] = ctx->timing_ms[i];
+    for (int i = 0; i < 7; ++i) ms[i] = ctx->timing_ms[i];
     if (n_render) *n_render = ctx->timing_nrender;
     return ART_OK;
 }

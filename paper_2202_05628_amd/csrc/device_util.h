@@ -111,4 +111,25 @@ __device__ inline void block_range(uint32_t n, uint32_t b, uint32_t nb, uint32_t
 
 __device__ inline float bf16_to_f32(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
 
+// Rotation matrix (row-major 3x3) of an axis-angle vector r, FP64 (Rodrigues).
+__device__ inline void axis_angle_to_matrix(const double* r, double* M) {
+    const double t2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+    const double t = sqrt(t2);
+    if (t < 1e-12) {
+        M[0] = 1; M[1] = 0; M[2] = 0;
+        M[3] = 0; M[4] = 1; M[5] = 0;
+        M[6] = 0; M[7] = 0; M[8] = 1;
+        return;
+    }
+    const double kx = r[0] / t, ky = r[1] / t, kz = r[2] / t;
+    double s, c;
+    sincos(t, &s, &c);
+    const double v = 1.0 - c;
+    // R = c I + s [k]_x + (1 - c) k k^T
+    M[0] = c + v * kx * kx;      M[1] = v * kx * ky - s * kz; M[2] = v * kx * kz + s * ky;
+    M[3] = v * ky * kx + s * kz; M[4] = c + v * ky * ky;      M[5] = v * ky * kz - s * kx;
+    M[6] = v * kz * kx - s * ky; M[7] = v * kz * ky + s * kx; M[8] = c + v * kz * kz;
+}
+
+
 }  // namespace art

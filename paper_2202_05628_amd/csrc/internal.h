@@ -44,6 +44,28 @@ struct CamParams {
     double t[3];   // camera centre
 };
 
+// Parameter layout of the proposal network for J bones (flat FP32 vector:
+// W1 [64][n_in], b1, W2 [64][64], b2, W3 [64][64], b3, W4 [2][64], b4).
+struct MlpDims {
+    int J, n_in, np;
+    int oW1, ob1, oW2, ob2, oW3, ob3, oW4, ob4;
+};
+inline MlpDims mlp_dims(int J) {
+    MlpDims m;
+    m.J = J;
+    m.n_in = 6 + 6 * J;
+    m.oW1 = 0;
+    m.ob1 = m.oW1 + 64 * m.n_in;
+    m.oW2 = m.ob1 + 64;
+    m.ob2 = m.oW2 + 64 * 64;
+    m.oW3 = m.ob2 + 64;
+    m.ob3 = m.oW3 + 64 * 64;
+    m.oW4 = m.ob3 + 64;
+    m.ob4 = m.oW4 + 2 * 64;
+    m.np = m.ob4 + 2;
+    return m;
+}
+
 // Device-side counters of one pose (written by the build kernels).
 struct PoseCounters {
     uint32_t M;          // occupied posed cells
@@ -60,7 +82,7 @@ struct RunStats {
         steps, tile_rays;
 };
 
-constexpr int kNumStats = 12;
+constexpr int kNumStats = 14;
 constexpr int kSortBlocks = 512;      // fixed grid (per pose) of the radix-sort passes
 constexpr int kScanBlocks = 256;      // fixed grid (per pose) of device-sized scans
 constexpr int kUniqueBlocks = 512;    // fixed grid (per pose) of the unique / compaction step
@@ -83,6 +105,7 @@ struct Scratch {
     DevBuf items;                        // [slots][V][tiles] compacted non-empty tiles
     DevBuf redo;                         // [slots][groups] items re-run after an overflow
     DevBuf queue;                        // [2] item count, queue head
+    DevBuf interval;                     // [slots][V][tiles][64] float2 proposed intervals
     size_t pair_cap = 0;
     int slots = 0;                       // poses whose octrees are held at once
 };
@@ -122,9 +145,20 @@ struct art_ctx {
 
     art::Scratch s;
 
+    // learned ray-interval proposal
+    int mlp_J = 0;                 // skeleton size the weights were set for (0: none)
+    int64_t mlp_step = 0;          // Adam steps taken since the weights were set
+    art::DevBuf mlp_theta, mlp_m1, mlp_m2;   // FP32 master weights and Adam moments
+    art::DevBuf mlp_packed;        // BF16 matrix-core operands
+    art::DevBuf mlp_cbias;         // [P][64] per-pose first-layer bias
+    art::DevBuf mlp_code;          // [P][6J] pose codes
+    art::DevBuf mlp_S, mlp_part, mlp_lossp, mlp_loss, mlp_flag;
+    int64_t poses_version = 0;     // bumped by art_set_poses
+    int64_t code_version = -1;     // poses_version the pose codes were computed for
+
     // last-call bookkeeping
     int64_t stats[art::kNumStats] = {0};
-    float timing_ms[6] = {0};
+    float timing_ms[7] = {0};
     int timing_nrender = 0;
     bool timing_valid = false;
 };
@@ -181,7 +215,7 @@ __global__ void k_pairs(const PoseCounters* __restrict__ c, unsigned long long* 
 struct RenderLaunch {
     int C, storage;
     bool fp32;
-    int mode;            // 0 forward, 1 backward, 2 debug hit lists
+    int mode;            // 0 forward, 1 backward, 2 debug hit lists, 3 labels, 4 proposal
     int depth;
     int Pb, V, H, W;     // poses in the launch (slots 0..Pb-1), views, image
     int Vg, ngroups;     // view groups of the tile lists
@@ -201,6 +235,11 @@ struct RenderLaunch {
     const float* d_alpha;
     float* d_sigma;
     float* d_leaf_feat;
+    float* labels;           // [Pb][V][H][W][2] (mode 3)
+    const float* interval;   // [Pb][V][H][W][2], or [items][64][2] with interval_by_item (mode 4)
+    bool interval_by_item;
+    float margin;            // ray-parameter units
+    float f2_tau;
     int max_hits;
     int debug_view;
     int32_t* hit_leaf;
@@ -208,6 +247,7 @@ struct RenderLaunch {
     int32_t* hit_count;
 };
 hipError_t launch_render(const RenderLaunch& r, hipStream_t st);
+int num_cus();   // compute units of the current device
 
 // Tile compaction (non-empty tiles -> work list) and background of empty tiles.
 struct TileLaunch {
@@ -222,9 +262,46 @@ struct TileLaunch {
     float* out_feat;           // forward maps (null in the adjoint)
     float* out_alpha;
     float* out_tfinal;
+    float* labels;             // interval labels (label pass)
     int32_t* hit_count;
     unsigned long long* stats;
 };
 hipError_t launch_tiles(const TileLaunch& t, hipStream_t st);
+
+// Proposal network (k_mlp.hip).
+struct AdamStep {
+    float lr, beta1, beta2, eps, bc1, bc2;   // bc = 1 - beta^step
+};
+struct InferLaunch {
+    const uint16_t* packed;
+    const float* theta;
+    const float* cbias;
+    MlpDims m;
+    const CamParams* cam;
+    const uint32_t* items;
+    const uint32_t* n_items;
+    int V, TX, TPV, pose0;
+    float* out;            // [items][64] float2
+};
+hipError_t launch_pose_code(const double* pose, int J, int P, float* code, hipStream_t st);
+hipError_t launch_mlp_prep(const float* theta, const MlpDims& m, const float* code, int P, uint16_t* packed,
+                           float* cbias, hipStream_t st);
+int64_t mlp_pad(int64_t n);
+size_t mlp_scratch_bytes(int64_t n);
+int mlp_packed_elems();
+unsigned mlp_loss_parts(int64_t n);
+hipError_t launch_mlp_forward(const uint16_t* packed, const float* theta, const float* cbias, const MlpDims& m,
+                              const float* od, const int32_t* pose, int P, int64_t n, float* out, uint32_t* bad,
+                              hipStream_t st);
+hipError_t launch_mlp_grad(const uint16_t* packed, const float* theta, const float* cbias, const float* code,
+                           const MlpDims& m, const float* od, const int32_t* pose, const float* target, int P,
+                           int64_t n, uint16_t* S, float* part, float* loss_part, uint32_t* bad, hipStream_t st);
+hipError_t launch_mlp_reduce(const float* part, int64_t n, const MlpDims& m, float* grad, float* theta, float* m1,
+                             float* m2, const AdamStep* adam, const float* loss_part, float* loss_out,
+                             hipStream_t st);
+hipError_t launch_mlp_gather(const int64_t* ray_id, int64_t n, const float* labels, const CamParams* cam, int P,
+                             int V, int H, int W, float* od, int32_t* pose, float* target, uint32_t* bad,
+                             hipStream_t st);
+hipError_t launch_mlp_infer_tiles(const InferLaunch& a, unsigned grid, hipStream_t st);
 
 }  // namespace art

@@ -1,0 +1,698 @@
+// Learned ray-interval proposal network on the matrix cores (an addition to
+// the paper's renderer; the quantity it predicts is defined by the renderer's
+// composited samples, Section 3.1, Eq. 5-6).
+//
+// Network: x = [o (3), d (3), pose code (6J)] -> 64 -> 64 -> 64 (ReLU) -> 2
+// (sigmoid) = (u_near, u_far).  The pose-code part of the first layer,
+// c_p = W1[:, 6:] code_p + b1, depends only on the pose and is evaluated once
+// per pose in FP32 (k_mlp_prep); per ray the first layer is the 6-input
+// product plus that bias.  Every other product runs on
+// v_mfma_f32_16x16x32_bf16: BF16 operands, FP32 accumulation, FP32 master
+// weights.
+//
+// Register layout of one wave working on 16 rays (lane l, r = l % 16,
+// g = l / 16):
+//   accumulator tile t (f32x4): lane holds h[ray r][16 t + 4 g + e], e < 4;
+//   B operand of k-step ks (8 x bf16): lane holds h[ray r][phi(ks, g, e)],
+//     phi(ks, g, e) = 16 (2 ks + e / 4) + 4 g + e % 4, e < 8,
+//   i.e. the accumulators of tiles 2 ks and 2 ks + 1 - a layer's output feeds
+//   the next layer without moving data between lanes; the weight operands are
+//   packed with the same feature permutation over K (k_mlp_prep);
+//   A operand (weights): lane holds W[16 m + r][phi(ks, g, e)].
+// The weight gradients are contractions over rays: the training forward /
+// backward kernel stores activations and deltas (BF16) feature-major, and
+// k_mlp_wgrad reads 8 consecutive rays per lane as the K operand.  Partial
+// sums per chunk of 256 rays are reduced in a fixed order (deterministic).
+#include <algorithm>
+
+#include "device_util.h"
+#include "internal.h"
+
+namespace art {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kHid = 64;
+// packed operand blocks (64 lanes x 8 bf16 each)
+constexpr int kB_W1 = 0;     // [mt]      first layer, 6 inputs padded to K = 32
+constexpr int kB_W2 = 4;     // [mt][ks]
+constexpr int kB_W3 = 12;    // [mt][ks]
+constexpr int kB_W4 = 20;    // [ks]      2 outputs padded to 16 rows
+constexpr int kB_W4T = 22;   // [mt]      W4^T, K = 2 outputs padded to 32
+constexpr int kB_W3T = 26;   // [mt][ks]
+constexpr int kB_W2T = 34;   // [mt][ks]
+constexpr int kBlocks = 42;
+constexpr int kPacked = kBlocks * 64 * 8;
+// feature-major training scratch rows
+constexpr int kRowH1 = 0, kRowH2 = 64, kRowH3 = 128, kRowD1 = 192, kRowD2 = 256, kRowD3 = 320, kRowD4 = 384;
+constexpr int kRows = 400;
+constexpr int kChunk = 256;   // rays per weight-gradient partial
+
+__device__ inline uint16_t f2bf(float x) {   // round to nearest even
+    const uint32_t u = __float_as_uint(x);
+    return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+
+__device__ inline bf16x8 pack8(float v0, float v1, float v2, float v3, float v4, float v5, float v6, float v7) {
+    u16x8 u;
+    u[0] = f2bf(v0);
+    u[1] = f2bf(v1);
+    u[2] = f2bf(v2);
+    u[3] = f2bf(v3);
+    u[4] = f2bf(v4);
+    u[5] = f2bf(v5);
+    u[6] = f2bf(v6);
+    u[7] = f2bf(v7);
+    return __builtin_bit_cast(bf16x8, u);
+}
+
+__device__ inline bf16x8 pack_tiles(const f32x4 a, const f32x4 b) {
+    return pack8(a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]);
+}
+
+__device__ inline f32x4 mfma(const bf16x8 a, const bf16x8 b, const f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+__host__ __device__ inline int phi(int ks, int g, int e) { return 16 * (2 * ks + (e >> 2)) + 4 * g + (e & 3); }
+
+__device__ inline float sigmoidf(float z) { return 1.0f / (1.0f + __expf(-z)); }
+
+// Ray of pixel (px, py) of a camera in FP32 (network input only).
+__device__ inline void ray_f32(const CamParams& cam, int px, int py, float* o, float* d) {
+    const float dcx = ((float)px + 0.5f - (float)cam.cx) / (float)cam.fx;
+    const float dcy = ((float)py + 0.5f - (float)cam.cy) / (float)cam.fy;
+    float n2 = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        d[i] = (float)cam.R[3 * i] * dcx + (float)cam.R[3 * i + 1] * dcy + (float)cam.R[3 * i + 2];
+        n2 += d[i] * d[i];
+    }
+    const float inv = 1.0f / sqrtf(n2);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        d[i] *= inv;
+        o[i] = (float)cam.t[i];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// pose code: per pose and bone the first two columns of Rot(r_j)
+// ---------------------------------------------------------------------------
+__global__ void k_pose_code(const double* __restrict__ pose, int J, int P, float* __restrict__ code) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P * J) return;
+    const int p = i / J, j = i % J;
+    double M[9];
+    axis_angle_to_matrix(pose + ((size_t)p * (J + 2) + j) * 3, M);
+    float* c = code + (size_t)p * 6 * J + 6 * j;
+    c[0] = (float)M[0];
+    c[1] = (float)M[3];
+    c[2] = (float)M[6];
+    c[3] = (float)M[1];
+    c[4] = (float)M[4];
+    c[5] = (float)M[7];
+}
+
+// ---------------------------------------------------------------------------
+// operand packing + per-pose first-layer bias
+// ---------------------------------------------------------------------------
+__global__ void k_mlp_prep(const float* __restrict__ theta, MlpDims m, const float* __restrict__ code, int P,
+                           uint16_t* __restrict__ packed, float* __restrict__ cbias) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const float* W1 = theta + m.oW1;
+    const float* W2 = theta + m.oW2;
+    const float* W3 = theta + m.oW3;
+    const float* W4 = theta + m.oW4;
+    if (i < kPacked) {
+        const int blk = i / 512, lane = (i / 8) % 64, e = i % 8;
+        const int r = lane & 15, g = lane >> 4;
+        float v = 0.0f;
+        if (blk < kB_W2) {
+            const int mt = blk - kB_W1, k = 8 * g + e;
+            v = k < 6 ? W1[(16 * mt + r) * m.n_in + k] : 0.0f;
+        } else if (blk < kB_W3) {
+            const int mt = (blk - kB_W2) >> 1, ks = (blk - kB_W2) & 1;
+            v = W2[(16 * mt + r) * kHid + phi(ks, g, e)];
+        } else if (blk < kB_W4) {
+            const int mt = (blk - kB_W3) >> 1, ks = (blk - kB_W3) & 1;
+            v = W3[(16 * mt + r) * kHid + phi(ks, g, e)];
+        } else if (blk < kB_W4T) {
+            const int ks = blk - kB_W4;
+            v = r < 2 ? W4[r * kHid + phi(ks, g, e)] : 0.0f;
+        } else if (blk < kB_W3T) {
+            const int mt = blk - kB_W4T, k = 8 * g + e;
+            v = k < 2 ? W4[k * kHid + 16 * mt + r] : 0.0f;
+        } else if (blk < kB_W2T) {
+            const int mt = (blk - kB_W3T) >> 1, ks = (blk - kB_W3T) & 1;
+            v = W3[phi(ks, g, e) * kHid + 16 * mt + r];
+        } else {
+            const int mt = (blk - kB_W2T) >> 1, ks = (blk - kB_W2T) & 1;
+            v = W2[phi(ks, g, e) * kHid + 16 * mt + r];
+        }
+        packed[i] = f2bf(v);
+        return;
+    }
+    const int j = i - kPacked;
+    if (j >= P * kHid) return;
+    const int p = j / kHid, o = j % kHid;
+    const int nc = m.n_in - 6;
+    const float* w = W1 + (size_t)o * m.n_in + 6;
+    const float* c = code + (size_t)p * nc;
+    float s = theta[m.ob1 + o];
+    for (int k = 0; k < nc; ++k) s = __fmaf_rn(w[k], c[k], s);
+    cbias[j] = s;
+}
+
+// Layer 2..4 forward of one 16-ray group from the layer-1 output h1.
+template <typename WSrc>
+__device__ inline void forward_tail(const WSrc& w, const float* __restrict__ theta, const MlpDims& m, int g,
+                                    const f32x4* h1, f32x4* h2, f32x4* h3, f32x4& z4) {
+    bf16x8 B0 = pack_tiles(h1[0], h1[1]);
+    bf16x8 B1 = pack_tiles(h1[2], h1[3]);
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        acc = mfma(w.get(kB_W2 + 2 * mt), B0, acc);
+        acc = mfma(w.get(kB_W2 + 2 * mt + 1), B1, acc);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[e] = fmaxf(acc[e] + theta[m.ob2 + 16 * mt + 4 * g + e], 0.0f);
+        h2[mt] = acc;
+    }
+    B0 = pack_tiles(h2[0], h2[1]);
+    B1 = pack_tiles(h2[2], h2[3]);
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        acc = mfma(w.get(kB_W3 + 2 * mt), B0, acc);
+        acc = mfma(w.get(kB_W3 + 2 * mt + 1), B1, acc);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[e] = fmaxf(acc[e] + theta[m.ob3 + 16 * mt + 4 * g + e], 0.0f);
+        h3[mt] = acc;
+    }
+    B0 = pack_tiles(h3[0], h3[1]);
+    B1 = pack_tiles(h3[2], h3[3]);
+    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    acc = mfma(w.get(kB_W4), B0, acc);
+    acc = mfma(w.get(kB_W4 + 1), B1, acc);
+    z4 = acc;
+}
+
+// First layer: 6 ray inputs (lanes of group 0 carry them) plus the pose bias.
+template <typename WSrc>
+__device__ inline void forward_head(const WSrc& w, const float* x, const float* __restrict__ cb, int g, f32x4* h1) {
+    const bf16x8 Bx = g == 0 ? pack8(x[0], x[1], x[2], x[3], x[4], x[5], 0.0f, 0.0f)
+                             : pack8(0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f);
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        acc = mfma(w.get(kB_W1 + mt), Bx, acc);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[e] = fmaxf(acc[e] + cb[16 * mt + 4 * g + e], 0.0f);
+        h1[mt] = acc;
+    }
+}
+
+struct WLds {   // operand blocks staged in LDS
+    const bf16x8* s;
+    int lane;
+    __device__ bf16x8 get(int blk) const { return s[blk * 64 + lane]; }
+};
+
+struct WRegs {   // forward operand blocks held in registers
+    bf16x8 b[kB_W4T];
+    __device__ bf16x8 get(int blk) const { return b[blk]; }
+};
+
+// ---------------------------------------------------------------------------
+// forward (mode 0) / forward + loss + backward (mode 1) over n rays
+// ---------------------------------------------------------------------------
+struct FbArgs {
+    const uint16_t* packed;
+    const float* theta;
+    const float* cbias;       // [P][64]
+    MlpDims m;
+    const float* od;          // [n][6]
+    const int32_t* pose;      // [n]
+    const float* target;      // [n][2]
+    float* out;               // [n][2] (mode 0)
+    int64_t n, n_pad;         // n_pad: multiple of kChunk
+    uint16_t* S;              // [kRows][n_pad] (mode 1)
+    float* loss_part;         // [gridDim.x] sums of SmoothL1 over rays and outputs
+    float inv2n;              // 1 / (2 n)
+    int mode;
+    int P;                    // valid pose ids: 0..P-1
+    uint32_t* bad;            // set to 1 when a pose id is out of range
+};
+
+__device__ inline float smooth_l1f(float e) { const float a = fabsf(e); return a < 1.0f ? 0.5f * e * e : a - 0.5f; }
+__device__ inline float smooth_l1_gradf(float e) { return fabsf(e) < 1.0f ? e : (e > 0.0f ? 1.0f : -1.0f); }
+
+__device__ inline void store_tiles(uint16_t* S, int64_t stride, int row0, int64_t ray, int g, const f32x4* t, int nt) {
+    for (int mt = 0; mt < nt; ++mt)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) S[(int64_t)(row0 + 16 * mt + 4 * g + e) * stride + ray] = f2bf(t[mt][e]);
+}
+
+__global__ __launch_bounds__(256) void k_mlp_fb(FbArgs a) {
+    __shared__ bf16x8 sw[kBlocks * 64];
+    __shared__ float sloss[4];
+    {
+        const uint4* src = reinterpret_cast<const uint4*>(a.packed);
+        uint4* dst = reinterpret_cast<uint4*>(sw);
+        for (int i = threadIdx.x; i < kBlocks * 64; i += blockDim.x) dst[i] = src[i];
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int r = lane & 15, g = lane >> 4;
+    WLds W{sw, lane};
+    const MlpDims& m = a.m;
+    float lsum = 0.0f;
+    const int64_t groups = a.n_pad / 16;
+    for (int64_t grp = (int64_t)blockIdx.x * 4 + w; grp < groups; grp += (int64_t)gridDim.x * 4) {
+        const int64_t ray = grp * 16 + r;
+        bool valid = ray < a.n;
+        float x[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+        int p = 0;
+        if (valid) {
+            p = a.pose[ray];
+            if ((unsigned)p >= (unsigned)a.P) {   // a ray with a bad pose id is left out
+                atomicOr(a.bad, 1u);
+                valid = false;
+                p = 0;
+            }
+        }
+        if (valid) {
+#pragma unroll
+            for (int i = 0; i < 6; ++i) x[i] = a.od[ray * 6 + i];
+        }
+        f32x4 h1[4], h2[4], h3[4], z4;
+        forward_head(W, x, a.cbias + (size_t)p * kHid, g, h1);
+        forward_tail(W, a.theta, m, g, h1, h2, h3, z4);
+        const float y0 = sigmoidf(z4[0] + a.theta[m.ob4]);
+        const float y1 = sigmoidf(z4[1] + a.theta[m.ob4 + 1]);
+        if (a.mode == 0) {
+            if (valid && g == 0) reinterpret_cast<float2*>(a.out)[ray] = make_float2(y0, y1);
+            continue;
+        }
+        // loss and dL/dz4 (lanes of group 0 hold the two outputs of ray r)
+        float d40 = 0.0f, d41 = 0.0f;
+        if (valid && g == 0) {
+            const float e0 = y0 - a.target[ray * 2], e1 = y1 - a.target[ray * 2 + 1];
+            lsum += smooth_l1f(e0) + smooth_l1f(e1);
+            d40 = smooth_l1_gradf(e0) * a.inv2n * y0 * (1.0f - y0);
+            d41 = smooth_l1_gradf(e1) * a.inv2n * y1 * (1.0f - y1);
+        }
+        store_tiles(a.S, a.n_pad, kRowH1, ray, g, h1, 4);
+        store_tiles(a.S, a.n_pad, kRowH2, ray, g, h2, 4);
+        store_tiles(a.S, a.n_pad, kRowH3, ray, g, h3, 4);
+        {
+            const f32x4 d4 = {d40, d41, 0.0f, 0.0f};   // zero for g > 0
+            store_tiles(a.S, a.n_pad, kRowD4, ray, g, &d4, 1);
+        }
+        const bf16x8 Bd4 = pack8(d40, d41, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f);
+        f32x4 d3[4], d2[4], d1[4];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+            acc = mfma(W.get(kB_W4T + mt), Bd4, acc);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc[e] = h3[mt][e] > 0.0f ? acc[e] : 0.0f;
+            d3[mt] = acc;
+        }
+        store_tiles(a.S, a.n_pad, kRowD3, ray, g, d3, 4);
+        bf16x8 B0 = pack_tiles(d3[0], d3[1]), B1 = pack_tiles(d3[2], d3[3]);
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+            acc = mfma(W.get(kB_W3T + 2 * mt), B0, acc);
+            acc = mfma(W.get(kB_W3T + 2 * mt + 1), B1, acc);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc[e] = h2[mt][e] > 0.0f ? acc[e] : 0.0f;
+            d2[mt] = acc;
+        }
+        store_tiles(a.S, a.n_pad, kRowD2, ray, g, d2, 4);
+        B0 = pack_tiles(d2[0], d2[1]);
+        B1 = pack_tiles(d2[2], d2[3]);
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+            acc = mfma(W.get(kB_W2T + 2 * mt), B0, acc);
+            acc = mfma(W.get(kB_W2T + 2 * mt + 1), B1, acc);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc[e] = h1[mt][e] > 0.0f ? acc[e] : 0.0f;
+            d1[mt] = acc;
+        }
+        store_tiles(a.S, a.n_pad, kRowD1, ray, g, d1, 4);
+    }
+    if (a.mode == 0) return;
+    lsum = wave_sum(lsum);
+    if (lane == 0) sloss[w] = lsum;
+    __syncthreads();
+    if (threadIdx.x == 0) a.loss_part[blockIdx.x] = ((sloss[0] + sloss[1]) + sloss[2]) + sloss[3];
+}
+
+// ---------------------------------------------------------------------------
+// weight gradients of one chunk of 256 rays: dW = sum_rays delta (x) input
+// ---------------------------------------------------------------------------
+struct WgArgs {
+    const uint16_t* S;
+    int64_t n, n_pad;
+    const float* od;
+    const int32_t* pose;
+    const float* code;     // [P][6J]
+    int P;
+    MlpDims m;
+    float* part;           // [n_pad / kChunk][np]
+};
+
+__device__ inline bf16x8 load8(const uint16_t* p) {
+    return __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(p));
+}
+
+__global__ __launch_bounds__(256) void k_mlp_wgrad(WgArgs a) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int r = lane & 15, g = lane >> 4;
+    const MlpDims& m = a.m;
+    const int64_t R0 = (int64_t)blockIdx.x * kChunk;
+    float* part = a.part + (size_t)blockIdx.x * m.np;
+    const int nt1 = (m.n_in + 15) / 16;
+    const int ntiles = 4 * nt1 + 16 + 16 + 4;
+    const int nc = m.n_in - 6;
+    for (int t = w; t < ntiles; t += 4) {
+        int layer, mt, nt;
+        if (t < 4 * nt1) {
+            layer = 1;
+            mt = t / nt1;
+            nt = t % nt1;
+        } else if (t < 4 * nt1 + 16) {
+            layer = 2;
+            mt = (t - 4 * nt1) / 4;
+            nt = (t - 4 * nt1) % 4;
+        } else if (t < 4 * nt1 + 32) {
+            layer = 3;
+            mt = (t - 4 * nt1 - 16) / 4;
+            nt = (t - 4 * nt1 - 16) % 4;
+        } else {
+            layer = 4;
+            mt = 0;
+            nt = t - 4 * nt1 - 32;
+        }
+        const int arow = layer == 1 ? kRowD1 + 16 * mt + r
+                       : layer == 2 ? kRowD2 + 16 * mt + r
+                       : layer == 3 ? kRowD3 + 16 * mt + r
+                                    : kRowD4 + r;
+        const int brow = layer == 2 ? kRowH1 : layer == 3 ? kRowH2 : kRowH3;
+        const int in = 16 * nt + r;
+        f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        for (int kb = 0; kb < kChunk / 32; ++kb) {
+            const int64_t rb = R0 + kb * 32 + 8 * g;
+            const bf16x8 A = load8(a.S + (int64_t)arow * a.n_pad + rb);
+            bf16x8 B;
+            if (layer == 1) {
+                float v[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int64_t ray = rb + e;
+                    float x = 0.0f;
+                    if (ray < a.n) {
+                        const int p = a.pose[ray];
+                        if ((unsigned)p < (unsigned)a.P) {
+                            if (in < 6) x = a.od[ray * 6 + in];
+                            else if (in < m.n_in) x = a.code[(size_t)p * nc + (in - 6)];
+                        }
+                    }
+                    v[e] = x;
+                }
+                B = pack8(v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7]);
+            } else {
+                B = load8(a.S + (int64_t)(brow + in) * a.n_pad + rb);
+            }
+            acc = mfma(A, B, acc);
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int out = 16 * mt + 4 * g + e;
+            if (layer == 1) {
+                if (in < m.n_in) part[m.oW1 + (size_t)out * m.n_in + in] = acc[e];
+            } else if (layer == 2) {
+                part[m.oW2 + out * kHid + in] = acc[e];
+            } else if (layer == 3) {
+                part[m.oW3 + out * kHid + in] = acc[e];
+            } else if (out < 2) {
+                part[m.oW4 + out * kHid + in] = acc[e];
+            }
+        }
+    }
+    // bias gradients: sums of the stored deltas
+    for (int row = threadIdx.x; row < 3 * kHid + 2; row += blockDim.x) {
+        int srow, dst;
+        if (row < kHid) { srow = kRowD1 + row; dst = m.ob1 + row; }
+        else if (row < 2 * kHid) { srow = kRowD2 + row - kHid; dst = m.ob2 + row - kHid; }
+        else if (row < 3 * kHid) { srow = kRowD3 + row - 2 * kHid; dst = m.ob3 + row - 2 * kHid; }
+        else { srow = kRowD4 + row - 3 * kHid; dst = m.ob4 + row - 3 * kHid; }
+        const uint16_t* s = a.S + (int64_t)srow * a.n_pad + R0;
+        float acc = 0.0f;
+        for (int i = 0; i < kChunk; ++i) acc += bf16_to_f32(s[i]);
+        part[dst] = acc;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// fixed-order reduction of the partials (+ Adam) and of the loss
+// ---------------------------------------------------------------------------
+struct RedArgs {
+    const float* part;
+    int nchunks;
+    int np;
+    float* grad;           // may be null
+    float* theta;
+    float* m1;
+    float* m2;
+    int adam;
+    float lr, beta1, beta2, eps, bc1, bc2;
+    const float* loss_part;
+    int nloss;
+    float inv2n;
+    float* loss_out;       // may be null
+};
+
+__global__ __launch_bounds__(256) void k_mlp_reduce(RedArgs a) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0 && a.loss_out) {
+        float L = 0.0f;
+        for (int k = 0; k < a.nloss; ++k) L += a.loss_part[k];
+        *a.loss_out = L * a.inv2n;
+    }
+    if (i >= a.np) return;
+    float gsum = 0.0f;
+    for (int c = 0; c < a.nchunks; ++c) gsum += a.part[(size_t)c * a.np + i];
+    if (a.grad) a.grad[i] = gsum;
+    if (a.adam) {
+        const float mm = a.beta1 * a.m1[i] + (1.0f - a.beta1) * gsum;
+        const float vv = a.beta2 * a.m2[i] + (1.0f - a.beta2) * gsum * gsum;
+        a.m1[i] = mm;
+        a.m2[i] = vv;
+        a.theta[i] -= a.lr * (mm / a.bc1) / (sqrtf(vv / a.bc2) + a.eps);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// training inputs of selected rays
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_mlp_gather(const int64_t* __restrict__ ray_id, int64_t n,
+                                                    const float* __restrict__ labels, const CamParams* __restrict__ cam,
+                                                    int P, int V, int H, int W, float* __restrict__ od,
+                                                    int32_t* __restrict__ pose, float* __restrict__ target,
+                                                    uint32_t* __restrict__ bad) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t HW = (int64_t)H * W;
+    const int64_t total = (int64_t)P * V * HW;
+    const int64_t id = ray_id[i];
+    if (id < 0 || id >= total) {
+        atomicOr(bad, 1u);
+        for (int k = 0; k < 6; ++k) od[i * 6 + k] = 0.0f;
+        pose[i] = 0;
+        target[i * 2] = 1.0f;
+        target[i * 2 + 1] = 0.0f;
+        return;
+    }
+    const int64_t pv = id / HW, pix = id % HW;
+    const int p = (int)(pv / V), v = (int)(pv % V);
+    float o[3], d[3];
+    ray_f32(cam[v], (int)(pix % W), (int)(pix / W), o, d);
+    for (int k = 0; k < 3; ++k) {
+        od[i * 6 + k] = o[k];
+        od[i * 6 + 3 + k] = d[k];
+    }
+    pose[i] = p;
+    target[i * 2] = labels[id * 2];
+    target[i * 2 + 1] = labels[id * 2 + 1];
+}
+
+// ---------------------------------------------------------------------------
+// inference for the rays of the compacted non-empty tiles of a render launch
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_mlp_infer_tiles(InferLaunch a) {
+    const int lane = threadIdx.x & 63;
+    const int r = lane & 15, g = lane >> 4;
+    WRegs W;
+    {
+        const bf16x8* P = reinterpret_cast<const bf16x8*>(a.packed);
+#pragma unroll
+        for (int b = 0; b < kB_W4T; ++b) W.b[b] = P[b * 64 + lane];
+    }
+    const uint32_t n_items = *a.n_items;
+    const uint32_t nw = gridDim.x * (blockDim.x / 64);
+    for (uint32_t idx = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); idx < n_items; idx += nw) {
+        const uint32_t item = a.items[idx];
+        const int pvi = (int)(item / (uint32_t)a.TPV);
+        const int tile = (int)(item % (uint32_t)a.TPV);
+        const int pb = pvi / a.V, v = pvi % a.V;
+        const int tx = tile % a.TX, ty = tile / a.TX;
+        const float* cb = a.cbias + (size_t)(a.pose0 + pb) * kHid;
+        const CamParams& cam = a.cam[v];
+#pragma unroll 1
+        for (int q = 0; q < 4; ++q) {
+            const int pl = q * 16 + r;   // pixel of the tile (row-major 8x8)
+            const int px = tx * 8 + (pl & 7), py = ty * 8 + (pl >> 3);
+            float x[6];
+            ray_f32(cam, px, py, x, x + 3);
+            f32x4 h1[4], h2[4], h3[4], z4;
+            forward_head(W, x, cb, g, h1);
+            forward_tail(W, a.theta, a.m, g, h1, h2, h3, z4);
+            if (g == 0)
+                reinterpret_cast<float2*>(a.out)[(size_t)idx * 64 + pl] =
+                    make_float2(sigmoidf(z4[0] + a.theta[a.m.ob4]), sigmoidf(z4[1] + a.theta[a.m.ob4 + 1]));
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_pose_code(const double* pose, int J, int P, float* code, hipStream_t st) {
+    const int n = P * J;
+    hipLaunchKernelGGL(k_pose_code, dim3((n + 127) / 128), dim3(128), 0, st, pose, J, P, code);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_prep(const float* theta, const MlpDims& m, const float* code, int P, uint16_t* packed,
+                           float* cbias, hipStream_t st) {
+    const int n = kPacked + P * kHid;
+    hipLaunchKernelGGL(k_mlp_prep, dim3((n + 255) / 256), dim3(256), 0, st, theta, m, code, P, packed, cbias);
+    return hipGetLastError();
+}
+
+int64_t mlp_pad(int64_t n) { return (n + kChunk - 1) / kChunk * kChunk; }
+size_t mlp_scratch_bytes(int64_t n) { return (size_t)kRows * (size_t)mlp_pad(n) * 2; }
+int mlp_packed_elems() { return kPacked; }
+
+static unsigned fb_grid(int64_t n_pad) {
+    const int64_t groups = n_pad / 16;
+    int64_t g = (groups + 3) / 4;
+    if (g > 2048) g = 2048;
+    return (unsigned)std::max<int64_t>(g, 1);
+}
+unsigned mlp_loss_parts(int64_t n) { return fb_grid(mlp_pad(n)); }
+
+hipError_t launch_mlp_forward(const uint16_t* packed, const float* theta, const float* cbias, const MlpDims& m,
+                              const float* od, const int32_t* pose, int P, int64_t n, float* out, uint32_t* bad,
+                              hipStream_t st) {
+    FbArgs a{};
+    a.P = P;
+    a.bad = bad;
+    a.packed = packed;
+    a.theta = theta;
+    a.cbias = cbias;
+    a.m = m;
+    a.od = od;
+    a.pose = pose;
+    a.out = out;
+    a.n = n;
+    a.n_pad = (n + 15) / 16 * 16;
+    a.mode = 0;
+    hipLaunchKernelGGL(k_mlp_fb, dim3(fb_grid(a.n_pad)), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_grad(const uint16_t* packed, const float* theta, const float* cbias, const float* code,
+                           const MlpDims& m, const float* od, const int32_t* pose, const float* target, int P,
+                           int64_t n, uint16_t* S, float* part, float* loss_part, uint32_t* bad, hipStream_t st) {
+    FbArgs a{};
+    a.P = P;
+    a.bad = bad;
+    a.packed = packed;
+    a.theta = theta;
+    a.cbias = cbias;
+    a.m = m;
+    a.od = od;
+    a.pose = pose;
+    a.target = target;
+    a.n = n;
+    a.n_pad = mlp_pad(n);
+    a.S = S;
+    a.loss_part = loss_part;
+    a.inv2n = 1.0f / (2.0f * (float)n);
+    a.mode = 1;
+    hipLaunchKernelGGL(k_mlp_fb, dim3(fb_grid(a.n_pad)), dim3(256), 0, st, a);
+    WgArgs w{};
+    w.S = S;
+    w.n = n;
+    w.n_pad = a.n_pad;
+    w.od = od;
+    w.pose = pose;
+    w.code = code;
+    w.P = P;
+    w.m = m;
+    w.part = part;
+    hipLaunchKernelGGL(k_mlp_wgrad, dim3((unsigned)(a.n_pad / kChunk)), dim3(256), 0, st, w);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_reduce(const float* part, int64_t n, const MlpDims& m, float* grad, float* theta, float* m1,
+                             float* m2, const AdamStep* adam, const float* loss_part, float* loss_out,
+                             hipStream_t st) {
+    RedArgs a{};
+    a.part = part;
+    a.nchunks = (int)(mlp_pad(n) / kChunk);
+    a.np = m.np;
+    a.grad = grad;
+    a.theta = theta;
+    a.m1 = m1;
+    a.m2 = m2;
+    a.adam = adam != nullptr;
+    if (adam) {
+        a.lr = adam->lr;
+        a.beta1 = adam->beta1;
+        a.beta2 = adam->beta2;
+        a.eps = adam->eps;
+        a.bc1 = adam->bc1;
+        a.bc2 = adam->bc2;
+    }
+    a.loss_part = loss_part;
+    a.nloss = (int)mlp_loss_parts(n);
+    a.inv2n = 1.0f / (2.0f * (float)n);
+    a.loss_out = loss_out;
+    hipLaunchKernelGGL(k_mlp_reduce, dim3((m.np + 255) / 256), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_gather(const int64_t* ray_id, int64_t n, const float* labels, const CamParams* cam, int P,
+                             int V, int H, int W, float* od, int32_t* pose, float* target, uint32_t* bad,
+                             hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mlp_gather, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, ray_id, n, labels, cam, P,
+                       V, H, W, od, pose, target, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_infer_tiles(const InferLaunch& a, unsigned grid, hipStream_t st) {
+    hipLaunchKernelGGL(k_mlp_infer_tiles, dim3(grid), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+}  // namespace art

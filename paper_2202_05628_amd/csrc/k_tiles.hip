@@ -6,7 +6,8 @@
 //                    atomic per wave), so the persistent compositing waves only
 //                    ever take tiles with work.
 //   k_background   : one thread per pixel; the pixels of an empty tile get
-//                    F = 0, A = 0, T = 1 (no voxel on their ray).
+//                    F = 0, A = 0, T = 1 (no voxel on their ray), and the
+//                    empty interval label (1, 0) in a label pass.
 #include "device_util.h"
 #include "internal.h"
 
@@ -64,7 +65,8 @@ __global__ __launch_bounds__(256) void k_background(TileGeom g, const uint32_t* 
                                                     const uint32_t* __restrict__ tstart,
                                                     const uint32_t* __restrict__ tend,
                                                     float* __restrict__ out_feat, float* __restrict__ out_alpha,
-                                                    float* __restrict__ out_tfinal, int32_t* __restrict__ hit_count,
+                                                    float* __restrict__ out_tfinal, float* __restrict__ labels,
+                                                    int32_t* __restrict__ hit_count,
                                                     unsigned long long* __restrict__ stats) {
     const size_t HW = (size_t)g.H * g.W;
     const uint64_t total = (uint64_t)g.Pb * g.V * HW;
@@ -84,6 +86,7 @@ __global__ __launch_bounds__(256) void k_background(TileGeom g, const uint32_t* 
             for (int c = 0; c < g.C; ++c) out_feat[((size_t)pvi * g.C + c) * HW + pix] = 0.0f;
         if (out_alpha) out_alpha[(size_t)pvi * HW + pix] = 0.0f;
         if (out_tfinal) out_tfinal[(size_t)pvi * HW + pix] = 1.0f;
+        if (labels) reinterpret_cast<float2*>(labels)[(size_t)pvi * HW + pix] = make_float2(1.0f, 0.0f);
         if (hit_count) hit_count[pix] = 0;
     }
     if (stats) {
@@ -114,13 +117,13 @@ hipError_t launch_tiles(const TileLaunch& t, hipStream_t st) {
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(k_tile_compact, dim3((unsigned)blocks), dim3(256), 0, st, g, t.ovf, t.tile_start, t.tile_end,
                        t.items, t.counters);
-    if (t.out_feat || t.hit_count) {
+    if (t.out_feat || t.hit_count || t.labels) {
         const uint64_t pixels = (uint64_t)g.Pb * g.V * g.H * g.W;
         uint64_t wblocks = (pixels + 255) / 256;
         if (wblocks > 16384) wblocks = 16384;
         if (wblocks < 1) wblocks = 1;
         hipLaunchKernelGGL(k_background, dim3((unsigned)wblocks), dim3(256), 0, st, g, t.ovf, t.tile_start,
-                           t.tile_end, t.out_feat, t.out_alpha, t.out_tfinal, t.hit_count, t.stats);
+                           t.tile_end, t.out_feat, t.out_alpha, t.out_tfinal, t.labels, t.hit_count, t.stats);
     }
     return hipGetLastError();
 }

@@ -74,6 +74,12 @@ struct RArgs {
     const float* d_alpha;
     float* d_sigma;
     float* d_leaf_feat;
+    float* labels;                         // [Pb][V][H][W][2] interval labels (MODE 3)
+    const float* interval;                 // [Pb][V][H][W][2] proposed intervals (MODE 4),
+                                           // or [items][64][2] when interval_by_item
+    int interval_by_item;
+    float margin;                          // proposal margin (ray-parameter units)
+    float f2_tau;                          // F2 threshold on T (< 0: off)
     int max_hits;
     int debug_view;                        // view whose hit lists are recorded (MODE 2)
     int32_t* hit_leaf;                     // [H*W][max_hits] (single pose / view)
@@ -154,13 +160,15 @@ __device__ inline bool brick_overlap(const int* b3, const R* d, const R* q, cons
     return ok && (t1 > t0);
 }
 
-// MODE: 0 forward, 1 adjoint, 2 forward recording hit lists
+// MODE: 0 forward, 1 adjoint, 2 forward recording hit lists, 3 interval labels,
+// 4 forward guided by proposed intervals (with full-traversal fallbacks)
 #ifndef ART_RENDER_WAVES_PER_EU
 #define ART_RENDER_WAVES_PER_EU 1
 #endif
 // Render one non-empty tile (item = pose-in-launch * V + view, tile index).
 template <int C, int ST, typename R, int MODE>
-__device__ inline void render_tile(const RArgs& a, uint32_t item, int lane, uint32_t (*s_mask)[16][kStage],
+__device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, int lane,
+                                   uint32_t (*s_mask)[16][kStage],
                                    uint16_t (*s_pref)[16][kStage], uint32_t (*s_row)[kStage],
                                    uint32_t (*s_coord)[kStage]) {
     constexpr int wv = 0;
@@ -229,6 +237,29 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, int lane, uint
         }
     }
     bool active = pix_ok && hit_root && (tb > ta) && (ls < le);
+    const size_t pix = (size_t)py * a.W + px;
+    const size_t HW = (size_t)a.H * a.W;
+    const size_t map = (size_t)pvi;   // (pose-in-launch, view) map index
+
+    // ---- proposal (MODE 4): the first pass traverses only [ts, te] ----------------
+    const R ta_full = ta, tb_full = tb;
+    bool prop = false;
+    if constexpr (MODE == 4) {
+        if (active) {
+            const float2 u = reinterpret_cast<const float2*>(a.interval)[a.interval_by_item ? (size_t)idx * 64 + lane
+                                                                                            : map * HW + pix];
+            if (u.x <= u.y) {   // a predicted non-empty interval (u_near <= u_far)
+                const R span = tb - ta;
+                const R ts = fmax(ta, ta + (R)u.x * span - (R)a.margin);
+                const R te = fmin(tb, ta + (R)u.y * span + (R)a.margin);
+                if (te > ts) {
+                    ta = ts;
+                    tb = te;
+                    prop = true;
+                }
+            }
+        }
+    }
 
     // ---- per-lane accumulators --------------------------------------------------
     float T = 1.0f, Aacc = 0.0f;
@@ -236,9 +267,7 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, int lane, uint
 #pragma unroll
     for (int c = 0; c < C; ++c) F[c] = 0.0f;
     int nsamp = 0;
-    const size_t pix = (size_t)py * a.W + px;
-    const size_t HW = (size_t)a.H * a.W;
-    const size_t map = (size_t)pvi;   // (pose-in-launch, view) map index
+    R t_first = 0, t_last = 0;   // MODE 3: entry of the first / exit of the last sample
     // adjoint state
     float g[C], Ff[C], P[C];
     float gA = 0.0f, Tfin = 0.0f;
@@ -275,6 +304,30 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, int lane, uint
 
     uint32_t rounds = 0;   // wave-uniform traversal rounds (diagnostic)
     uint32_t nsteps = 0;   // partition steps of this lane (diagnostic)
+    uint32_t nfall = 0;    // MODE 4: this lane fell back to the full traversal
+    for (int pass = 0; pass < (MODE == 4 ? 2 : 1); ++pass) {
+    if constexpr (MODE == 4) {
+        if (pass == 1) {
+            // F1: the proposed interval held no occupied voxel; F2: the ray left
+            // it with transmittance above the threshold before the root's exit.
+            // Such lanes restart from t_a with the whole ray.
+            const bool fb = prop && (nsamp == 0 || (a.f2_tau >= 0.0f && T >= a.f2_tau && tb < tb_full));
+            if (__ballot(fb) == 0ull) break;
+            active = fb;
+            if (fb) {
+                T = 1.0f;
+                Aacc = 0.0f;
+#pragma unroll
+                for (int c = 0; c < C; ++c) F[c] = 0.0f;
+                nsamp = 0;
+                ta = ta_full;
+                tb = tb_full;
+                nfall = 1;
+            }
+            inb = false;
+            fresh = false;
+        }
+    }
     for (uint32_t base = ls; base < le; base += kStage) {
         if (__ballot(active) == 0ull) break;
         // stage up to 64 bricks of the tile's front-to-back list
@@ -320,6 +373,7 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, int lane, uint
         uint32_t rowA = 0;
         float dlA = 0.0f;
         double dxA = 0.0;
+        R sA0 = 0, sA1 = 0;
         float sgA = 0.0f;
         float fA[C];
 #pragma unroll
@@ -333,6 +387,7 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, int lane, uint
             uint32_t rowB = 0;
             float dlB = 0.0f;
             double dxB = 0.0;
+            R sB0 = 0, sB1 = 0;
             int guard = 0;
             while (active && !hasB && (inb || todo != 0ull) && guard < kStepsPerRound) {
                 ++guard;
@@ -381,6 +436,10 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, int lane, uint
                         rowB = row_base + s_pref[wv][wd][slot] + (uint32_t)__popc(mw & ((1u << bit) - 1u));
                         dlB = (float)(s1 - s);
                         if constexpr (MODE == 2) dxB = (double)(s1 - s);
+                        if constexpr (MODE == 3) {
+                            sB0 = s;
+                            sB1 = s1;
+                        }
                         hasB = true;
                     }
                 }
@@ -425,6 +484,10 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, int lane, uint
                             a.hit_delta[hit_base + nsamp] = dxA;
                         }
                     }
+                    if constexpr (MODE == 3) {
+                        if (nsamp == 0) t_first = sA0;
+                        t_last = sA1;
+                    }
                 }
                 T = Tn;
                 ++nsamp;
@@ -439,15 +502,28 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, int lane, uint
                 rowA = rowB;
                 dlA = dlB;
                 dxA = dxB;
+                sA0 = sB0;
+                sA1 = sB1;
                 // the FLUT row of the cell's collision winner
                 load_sample<C, ST>(a.sigma, a.feat, occ_win[rowA], sgA, fA);
             }
         }
         wave_sync();
     }
+    }   // passes
 
     // ---- outputs -----------------------------------------------------------------
-    if constexpr (MODE != 1) {
+    if constexpr (MODE == 3) {
+        if (pix_ok) {
+            float2 lab = make_float2(1.0f, 0.0f);   // no composited sample: empty interval
+            if (nsamp > 0) {
+                const R span = tb - ta;
+                lab.x = (float)((t_first - ta) / span);
+                lab.y = (float)((t_last - ta) / span);
+            }
+            reinterpret_cast<float2*>(a.labels)[map * HW + pix] = lab;
+        }
+    } else if constexpr (MODE != 1) {
         if (pix_ok) {
 #pragma unroll
             for (int c = 0; c < C; ++c) a.out_feat[(map * C + c) * HW + pix] = F[c];
@@ -472,6 +548,14 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, int lane, uint
         if (lane == 0 && rays) {
             atomicAdd(&a.stats[9], steps);
         }
+        if constexpr (MODE == 4) {
+            const uint64_t pr = __ballot(prop);
+            const uint64_t fl = __ballot(nfall != 0u);
+            if (lane == 0) {
+                atomicAdd(&a.stats[11], (unsigned long long)__popcll(pr));
+                atomicAdd(&a.stats[12], (unsigned long long)__popcll(fl));
+            }
+        }
     }
 }
 
@@ -491,12 +575,34 @@ void k_render(RArgs a) {
         if (lane == 0) idx = atomicAdd(a.queue, 1u);
         idx = (uint32_t)__shfl((int)idx, 0, kWave);
         if (idx >= n_items) break;
-        render_tile<C, ST, R, MODE>(a, a.items[idx], lane, s_mask, s_pref, s_row, s_coord);
+        render_tile<C, ST, R, MODE>(a, a.items[idx], idx, lane, s_mask, s_pref, s_row, s_coord);
         wave_sync();
     }
 }
 
 template <int C>
 hipError_t launch_render_c(const RenderLaunch& r, const RArgs& a, unsigned grid, hipStream_t st);
+
+template <int C, int ST, typename R>
+hipError_t launch_render_mode(const RenderLaunch& r, const RArgs& a, unsigned grid, hipStream_t st) {
+    switch (r.mode) {
+        case 0: hipLaunchKernelGGL((k_render<C, ST, R, 0>), dim3(grid), dim3(64), 0, st, a); break;
+        case 1: hipLaunchKernelGGL((k_render<C, ST, R, 1>), dim3(grid), dim3(64), 0, st, a); break;
+        case 2: hipLaunchKernelGGL((k_render<C, ST, R, 2>), dim3(grid), dim3(64), 0, st, a); break;
+        case 3: hipLaunchKernelGGL((k_render<C, ST, R, 3>), dim3(grid), dim3(64), 0, st, a); break;
+        case 4: hipLaunchKernelGGL((k_render<C, ST, R, 4>), dim3(grid), dim3(64), 0, st, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// Instantiates the kernels of C channels for both storage types and both
+// geometry precisions.
+template <int C>
+hipError_t launch_render_dispatch(const RenderLaunch& r, const RArgs& a, unsigned grid, hipStream_t st) {
+    const bool bf16 = r.storage == ART_BF16;
+    if (r.fp32) return bf16 ? launch_render_mode<C, 1, float>(r, a, grid, st) : launch_render_mode<C, 0, float>(r, a, grid, st);
+    return bf16 ? launch_render_mode<C, 1, double>(r, a, grid, st) : launch_render_mode<C, 0, double>(r, a, grid, st);
+}
 
 }  // namespace art
