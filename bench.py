@@ -88,6 +88,14 @@ def parse():
     ap.add_argument("--lambda-th", type=float, default=0.01)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-proposal", action="store_true", help="skip the learned-proposal comparison")
+    ap.add_argument("--proposal-steps", type=int, default=3)
+    ap.add_argument("--train-steps", type=int, default=5000)
+    ap.add_argument("--train-rays", type=int, default=4_000_000)
+    ap.add_argument("--margin-h", type=float, default=0.0,
+                    help="proposal start margin in leaf edges (0: calibrated on held-out rays)")
+    ap.add_argument("--f2-tau", type=float, default=-1.0)
+    ap.add_argument("--err-poses", type=int, default=4, help="poses on which the proposal error is measured")
     return ap.parse_args()
 
 
@@ -140,6 +148,117 @@ def cpu_baseline(scene, poses, K, c2w, H, W, lam, budget_s):
         "sample": (f"1 pose x {K.shape[0]} views at {H}x{W}: FK, skinning and occupancy of all "
                    f"{scene.n} leaves timed in full ({t_build:.2f} s); {n} of {n_all} rays rendered "
                    f"({t_render:.2f} s, uniform seeded sample) and extrapolated to the pose"),
+    }
+
+
+def _timed(torch, fn, steps):
+    """Wall time per call of `fn` over `steps` calls after one warm-up call,
+    bracketed by device synchronisation."""
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def proposal_leg(args, art, sg, torch):
+    """Learned ray-interval proposal vs the plain renderer on the proposal
+    workload (60 poses x 16 cameras at 1024^2, C = 16, FP32): the network is
+    trained on the GPU (own kernels) on labels of the plain renderer, then both
+    renderers are timed over the whole batch; the proposal's error against the
+    plain maps is measured on the first poses, together with the untrained
+    network (the control)."""
+    cfg = sg.CONFIGS["proposal"]
+    scene = sg.make_scene(cfg)
+    P, V, H, W = cfg.n_poses, cfg.n_views, cfg.height, cfg.width
+    poses = sg.make_poses(scene.J, P, cfg.pose_seed0)
+    K, c2w = sg.make_cameras(scene, V, H, W)
+    r = art.Renderer(0)
+    r.set_scene(scene)
+    r.set_poses(*poses)
+    r.set_cameras(K, c2w, H, W)
+    sig = torch.from_numpy(scene.sigma).cuda()
+    feat = torch.from_numpy(scene.feat).cuda()
+    lam = args.lambda_th
+    t0 = time.perf_counter()
+    lab = r.proposal_labels(sig, feat, lam)
+    hit = (lab[..., 0] <= lab[..., 1]).cpu().numpy()
+    ids = sg.sample_training_rays(args.train_rays, P, V, H, W, hit_mask=hit, seed=cfg.ray_seed)
+    del hit
+    od, pose, tgt = r.proposal_gather(torch.from_numpy(ids).cuda(), lab)
+    del lab
+    n_train = int(0.9 * len(ids))
+    theta0 = sg.make_mlp_init(scene.J, seed=cfg.mlp_seed)
+    r.set_proposal_weights(theta0)
+    val0, _ = r.proposal_grad(od[n_train:n_train + 65536], pose[n_train:n_train + 65536], tgt[n_train:n_train + 65536])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    losses = r.proposal_train(od[:n_train], pose[:n_train], tgt[:n_train], batch=16384, steps=args.train_steps,
+                              lr=1e-3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    val1, _ = r.proposal_grad(od[n_train:n_train + 65536], pose[n_train:n_train + 65536], tgt[n_train:n_train + 65536])
+    margin = args.margin_h or r.calibrate_proposal_margin(od[n_train:], pose[n_train:], tgt[n_train:])
+    print(f"[bench] proposal trained: {args.train_steps} steps in {t_train:.2f} s, validation loss "
+          f"{val0:.4f} -> {val1:.4f}; start margin {margin:.1f} h", file=sys.stderr, flush=True)
+    theta1 = r.get_proposal_weights()
+    del od, pose, tgt
+    F = torch.empty((P, V, cfg.C, H, W), dtype=torch.float32, device="cuda")
+    A = torch.empty((P, V, H, W), dtype=torch.float32, device="cuda")
+    out = (F, A, None)
+    rays = P * V * H * W
+    t_plain = _timed(torch, lambda: r.render(sig, feat, lam, out=out), args.proposal_steps)
+    st_plain = r.stats()
+    kw = dict(margin_h=margin, f2_tau=args.f2_tau, near_only=True)
+    t_prop = _timed(torch, lambda: r.render_proposal(sig, feat, None, lam, out=out, **kw), args.proposal_steps)
+    st = r.stats()
+    r.render_proposal(sig, feat, None, lam, out=out, timing=True, **kw)
+    tm = r.timing()
+    del F, A, out
+    # error on the first poses (plain vs trained vs untrained network)
+    Pe = min(args.err_poses, P)
+    r.set_poses(poses[0][:Pe], poses[1][:Pe], poses[2][:Pe])
+    F0, _, _ = r.render(sig, feat, lam, want_tfinal=False)
+    F1, _, _ = r.render_proposal(sig, feat, None, lam, want_tfinal=False, **kw)
+    den = float(F0.abs().sum())
+    err_mean = float((F1 - F0).abs().sum()) / den
+    err_max = max(float((F1[p, v] - F0[p, v]).abs().max() / F0[p, v].abs().max())
+                  for p in range(Pe) for v in range(V))
+    r.set_proposal_weights(theta0)
+    Fu, _, _ = r.render_proposal(sig, feat, None, lam, want_tfinal=False, **kw)
+    stu = r.stats()
+    err_u = float((Fu - F0).abs().sum()) / den
+    r.set_proposal_weights(theta1)
+    del F0, F1, Fu
+    return {
+        "workload": (f"learned proposal: depth {cfg.depth} octree, {scene.n} leaves, {scene.J} bones, C={cfg.C}, "
+                     f"{P} poses x {V} cameras at {H}x{W} ({rays} rays), lambda_th={lam}"),
+        "plain_mrays_s": round(rays / t_plain / 1e6, 2),
+        "proposal_mrays_s": round(rays / t_prop / 1e6, 2),
+        "speedup": round(t_plain / t_prop, 4),
+        "rel_mean_err": err_mean,
+        "rel_max_err": err_max,
+        "err_poses": Pe,
+        "margin_h": round(margin, 2),
+        "margin_rule": "calibrated: 99.9% quantile of late starts on held-out rays" if not args.margin_h else "fixed",
+        "interval": "near end only (traversal from t_a + u_near (t_b - t_a) - m to t_b)",
+        "f2_tau": args.f2_tau,
+        "partition_steps_plain": st_plain["steps"],
+        "partition_steps_proposal": st["steps"],
+        "rounds_plain": st_plain["rounds"],
+        "rounds_proposal": st["rounds"],
+        "proposal_rays": st["proposal_rays"],
+        "fallback_rate": round(st["fallbacks"] / max(st["proposal_rays"], 1), 4),
+        "inference_ms": round(tm["proposal"], 3),
+        "render_ms": round(tm["render"], 3),
+        "untrained_control": {"rel_mean_err": err_u,
+                              "fallback_rate": round(stu["fallbacks"] / max(stu["proposal_rays"], 1), 4)},
+        "training": {"rays": int(len(ids)), "train_rays": n_train, "steps": args.train_steps, "batch": 16384,
+                     "seconds": round(t_train, 3), "first_loss": float(losses[0]), "last_loss": float(losses[-1]),
+                     "val_loss_before": val0, "val_loss_after": val1,
+                     "setup_seconds": round(time.perf_counter() - t0, 2)},
     }
 
 
@@ -250,6 +369,11 @@ def main():
         "partition_steps_per_pose": st["steps"] // P,
         "launches_per_step": st["launches"],
     }
+    if not args.no_proposal:
+        print("[bench] learned proposal vs plain (proposal workload)", file=sys.stderr, flush=True)
+        del Fm, Am, Tm, out
+        torch.cuda.empty_cache()
+        line["proposal"] = proposal_leg(args, art, sg, torch)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(scene, poses, K, c2w, cfg.height, cfg.width,

@@ -62,6 +62,7 @@ typedef enum { ART_F32 = 0, ART_BF16 = 1 } art_dtype;
 #define ART_GEOM_FP32 1u   /* FP32 skinning and ray parameter (precision form);
                               default: FP64 skinning arithmetic and ray t      */
 #define ART_TIMING 2u      /* record per-stage HIP events, read by art_get_timing */
+#define ART_PROPOSAL_NEAR_ONLY 4u  /* art_render_proposal: use only u_near, traverse to t_b */
 
 /* Library version (major * 10000 + minor * 100 + patch). */
 int art_version(void);
@@ -208,9 +209,11 @@ art_status art_proposal_labels(art_ctx* ctx, int C, art_dtype dtype, const void*
  * [t_a, t_b], with m = margin_h * h; it falls back to the full traversal of
  * [t_a, t_b] when that interval held no occupied voxel (F1) or, with
  * f2_tau >= 0, when its transmittance on leaving the interval before t_b is
- * still >= f2_tau (F2).  A ray with u_near > u_far (predicted empty) is
- * traversed in full.  The result equals art_render's whenever every skipped
- * part of a ray holds no occupied voxel.
+ * still >= f2_tau (F2).  With ART_PROPOSAL_NEAR_ONLY in flags the interval
+ * ends at t_b (only the empty front of the ray is skipped; F2 cannot occur).
+ * A ray with u_near > u_far (predicted empty) is traversed in full.  The
+ * result equals art_render's whenever every skipped part of a ray holds no
+ * occupied voxel.
  * Errors: as art_render; ART_EINVAL for a negative or non-finite margin_h or
  * a NaN f2_tau; ART_ESTATE for NULL intervals without network weights.
  */

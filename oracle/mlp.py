@@ -21,12 +21,20 @@ Training: Adam with bias correction.
 Flat parameter order (FP32 on the GPU, the same order here):
     W1 (row-major), b1, W2, b2, W3, b3, W4, b4.
 
-``round_bf16=True`` rounds both operands of every matrix product to bfloat16
-before an FP64 product (the network's precision form: BF16 matrix-core
-operands, wide accumulation); everything else stays FP64.  The one exception
-is the pose-code part of the first layer in the forward pass, W1[:, 6:] code +
-b1, which depends only on the pose and is evaluated once per pose at full
-precision (it enters every ray of the pose as a bias).
+``precision`` selects how the matrix products are rounded (everything else
+stays FP64):
+  "fp64"   - plain FP64 (the definition);
+  "bf16"   - both operands of every product rounded to bfloat16 before an
+             FP64 product: the network's inference form (BF16 matrix-core
+             operands, wide accumulation);
+  "bf16x3" - every operand split into a bfloat16 head and a bfloat16 tail
+             (a = a_hi + a_lo, a_lo = bf16(a - a_hi)) and the product taken
+             as a_hi b_hi + a_hi b_lo + a_lo b_hi: the training form (three
+             BF16 matrix-core products per product, about 16 significant bits).
+In the "bf16" forms the pose-code part of the first layer, W1[:, 6:] code +
+b1, depends only on the pose and is evaluated once per pose at full
+precision (it enters every ray of the pose as a bias), and the bias
+gradients are plain sums of the deltas.
 """
 from __future__ import annotations
 
@@ -90,29 +98,43 @@ def inputs(o: np.ndarray, d: np.ndarray, code: np.ndarray) -> np.ndarray:
     return np.concatenate([o, d, code], axis=1)
 
 
-def _mm(a: np.ndarray, b: np.ndarray, bf16: bool) -> np.ndarray:
-    """a @ b, with both operands rounded to bfloat16 first when bf16 is set."""
-    if bf16:
-        a = bf16_round(a).astype(np.float64)
-        b = bf16_round(b).astype(np.float64)
-    return a @ b
+PRECISIONS = ("fp64", "bf16", "bf16x3")
+
+
+def _bf(x: np.ndarray) -> np.ndarray:
+    return bf16_round(x).astype(np.float64)
+
+
+def _mm(a: np.ndarray, b: np.ndarray, precision: str) -> np.ndarray:
+    """a @ b with the operand rounding of `precision`."""
+    if precision == "fp64":
+        return a @ b
+    if precision == "bf16":
+        return _bf(a) @ _bf(b)
+    if precision == "bf16x3":
+        ah = _bf(a)
+        bh = _bf(b)
+        al = _bf(a - ah)
+        bl = _bf(b - bh)
+        return al @ bh + ah @ bl + ah @ bh
+    raise ValueError(precision)
 
 
 def sigmoid(z: np.ndarray) -> np.ndarray:
     return 0.5 * (1.0 + np.tanh(0.5 * z))
 
 
-def forward(theta: np.ndarray, X: np.ndarray, J: int, round_bf16: bool = False):
+def forward(theta: np.ndarray, X: np.ndarray, J: int, precision: str = "fp64"):
     """Outputs y [n][2] and the activations of every layer."""
     p = unpack(theta, J)
     X = np.asarray(X, dtype=np.float64)
-    z1 = _mm(X[:, :6], p["W1"][:, :6].T, round_bf16) + (X[:, 6:] @ p["W1"][:, 6:].T + p["b1"])
+    z1 = _mm(X[:, :6], p["W1"][:, :6].T, precision) + (X[:, 6:] @ p["W1"][:, 6:].T + p["b1"])
     h1 = np.maximum(z1, 0.0)
-    z2 = _mm(h1, p["W2"].T, round_bf16) + p["b2"]
+    z2 = _mm(h1, p["W2"].T, precision) + p["b2"]
     h2 = np.maximum(z2, 0.0)
-    z3 = _mm(h2, p["W3"].T, round_bf16) + p["b3"]
+    z3 = _mm(h2, p["W3"].T, precision) + p["b3"]
     h3 = np.maximum(z3, 0.0)
-    z4 = _mm(h3, p["W4"].T, round_bf16) + p["b4"]
+    z4 = _mm(h3, p["W4"].T, precision) + p["b4"]
     y = sigmoid(z4)
     return y, {"X": X, "z1": z1, "h1": h1, "z2": z2, "h2": h2, "z3": z3, "h3": h3, "z4": z4, "y": y}
 
@@ -133,25 +155,25 @@ def loss(y: np.ndarray, target: np.ndarray) -> float:
 
 
 def grad(theta: np.ndarray, X: np.ndarray, target: np.ndarray, J: int,
-         round_bf16: bool = False) -> Tuple[float, np.ndarray]:
+         precision: str = "fp64") -> Tuple[float, np.ndarray]:
     """Loss and its gradient with respect to the flat parameters, by the chain
     rule written out layer by layer (backpropagation)."""
     p = unpack(theta, J)
-    y, a = forward(theta, X, J, round_bf16)
+    y, a = forward(theta, X, J, precision)
     t = np.asarray(target, dtype=np.float64)
     n = y.shape[0]
     L = loss(y, t)
     dy = smooth_l1_grad(y - t) / (2.0 * n)          # dL/dy
     d4 = dy * y * (1.0 - y)                          # dL/dz4 (sigmoid')
-    g = {"W4": _mm(d4.T, a["h3"], round_bf16), "b4": d4.sum(axis=0)}
-    d3 = _mm(d4, p["W4"], round_bf16) * (a["z3"] > 0)
-    g["W3"] = _mm(d3.T, a["h2"], round_bf16)
+    g = {"W4": _mm(d4.T, a["h3"], precision), "b4": d4.sum(axis=0)}
+    d3 = _mm(d4, p["W4"], precision) * (a["z3"] > 0)
+    g["W3"] = _mm(d3.T, a["h2"], precision)
     g["b3"] = d3.sum(axis=0)
-    d2 = _mm(d3, p["W3"], round_bf16) * (a["z2"] > 0)
-    g["W2"] = _mm(d2.T, a["h1"], round_bf16)
+    d2 = _mm(d3, p["W3"], precision) * (a["z2"] > 0)
+    g["W2"] = _mm(d2.T, a["h1"], precision)
     g["b2"] = d2.sum(axis=0)
-    d1 = _mm(d2, p["W2"], round_bf16) * (a["z1"] > 0)
-    g["W1"] = _mm(d1.T, a["X"], round_bf16)
+    d1 = _mm(d2, p["W2"], precision) * (a["z1"] > 0)
+    g["W1"] = _mm(d1.T, a["X"], precision)
     g["b1"] = d1.sum(axis=0)
     return L, pack(g, J)
 

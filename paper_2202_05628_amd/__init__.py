@@ -174,7 +174,7 @@ class Renderer:
 
     def render_proposal(self, sigma, feat, intervals, lambda_th: float = LAMBDA_TH,
                         margin_h: float = ART_PROPOSAL_MARGIN_H, f2_tau: float = -1.0, fp32_geom: bool = False,
-                        timing: bool = False, out=None, want_tfinal: bool = True):
+                        timing: bool = False, out=None, want_tfinal: bool = True, near_only: bool = False):
         """Forward render whose traversal starts from the proposed intervals
         [P][V][H][W][2] (u_near, u_far), with the full traversal as fallback."""
         torch = self._torch
@@ -187,8 +187,9 @@ class Renderer:
         else:
             F, A, T = out
         iv = None if intervals is None else intervals.contiguous().float()
+        flags = self._flags(fp32_geom, timing) | (_lib.ART_PROPOSAL_NEAR_ONLY if near_only else 0)
         self._check(self.lib.art_render_proposal(self._h, C, dtype, _tptr(sigma), _tptr(feat), float(lambda_th),
-                                                 self._flags(fp32_geom, timing), _tptr(iv), float(margin_h),
+                                                 flags, _tptr(iv), float(margin_h),
                                                  float(f2_tau), _tptr(F), _tptr(A), _tptr(T)),
                     "art_render_proposal")
         return F, A, T
@@ -236,6 +237,27 @@ class Renderer:
                                                _tptr(pose.contiguous()), _tptr(target.contiguous()), _tptr(g),
                                                _tptr(L)), "art_proposal_grad")
         return float(L.item()), g
+
+    def calibrate_proposal_margin(self, od, pose, target, quantile: float = 0.999, floor_h: float = 2.0) -> float:
+        """Margin (in leaf edges h) that covers the network's late starts on
+        held-out rays: the `quantile` of (predicted - true) entry of the first
+        sample over the rays that have one, in units of h (at least floor_h)."""
+        pred = self.proposal_forward(od, pose).cpu().numpy().astype(np.float64)
+        tgt = target.cpu().numpy().astype(np.float64)
+        x = od.cpu().numpy().astype(np.float64)
+        hit = tgt[:, 0] <= tgt[:, 1]
+        if not hit.any():
+            return float(floor_h)
+        o, d = x[hit, :3], x[hit, 3:]
+        with np.errstate(divide="ignore", invalid="ignore"):
+            t0 = (-1.0 - o) / d
+            t1 = (1.0 - o) / d
+        lo = np.where(d != 0, np.minimum(t0, t1), -np.inf).max(axis=1)
+        hi = np.where(d != 0, np.maximum(t0, t1), np.inf).min(axis=1)
+        span = hi - np.maximum(lo, 0.0)
+        h = 1.0 / (1 << self.depth)
+        late = (pred[hit, 0] - tgt[hit, 0]) * span / h
+        return float(max(floor_h, np.quantile(late, quantile)))
 
     def proposal_train(self, od, pose, target, batch: int = 16384, steps: int = 1000, lr: float = 1e-3,
                        betas=(0.9, 0.999), eps: float = 1e-8) -> np.ndarray:

@@ -251,6 +251,7 @@ struct PassOut {
     const float* intervals = nullptr;
     float margin = 0.0f;
     float f2_tau = -1.0f;
+    bool near_only = false;
     // debug
     int max_hits = 0;
     int debug_view = 0;
@@ -375,6 +376,7 @@ art_status run_batch(art_ctx* ctx, const CallPlan& pl, int mode, float lambda, c
     if (o.intervals) r.interval = o.intervals + m0 * HW * 2;
     r.margin = o.margin;
     r.f2_tau = o.f2_tau;
+    r.near_only = o.near_only;
     r.max_hits = o.max_hits;
     r.debug_view = o.debug_view;
     r.hit_leaf = o.hit_leaf;
@@ -591,6 +593,7 @@ hipError_t launch_render(const RenderLaunch& r, hipStream_t st) {
     a.interval_by_item = r.interval_by_item ? 1 : 0;
     a.margin = r.margin;
     a.f2_tau = r.f2_tau;
+    a.near_only = r.near_only ? 1 : 0;
     a.max_hits = r.max_hits;
     a.debug_view = r.debug_view;
     a.hit_leaf = r.hit_leaf;
@@ -899,7 +902,8 @@ art_status art_render_proposal(art_ctx* ctx, int C, art_dtype dtype, const void*
     o.intervals = intervals;
     o.margin = (float)(margin_h / (double)(1 << std::max(ctx->depth, 0)));
     o.f2_tau = f2_tau;
-    return render_call(ctx, C, dtype, sigma, feat, lambda_th, flags, 4, o, 0, ctx->P);
+    o.near_only = (flags & ART_PROPOSAL_NEAR_ONLY) != 0;
+    return render_call(ctx, C, dtype, sigma, feat, lambda_th, flags & ~ART_PROPOSAL_NEAR_ONLY, 4, o, 0, ctx->P);
 }
 
 int64_t art_proposal_param_count(int J) {
@@ -1016,7 +1020,7 @@ art_status art_proposal_grad(art_ctx* ctx, int64_t n, const float* od, const int
     const MlpDims m = mlp_dims(ctx->J);
     ART_TRY_HIP(launch_fill_u32(ctx->mlp_flag.as<uint32_t>(), 0u, 1, st), "fill");
     ART_TRY_HIP(launch_mlp_grad(ctx->mlp_packed.as<uint16_t>(), ctx->mlp_theta.as<float>(), ctx->mlp_cbias.as<float>(),
-                                ctx->mlp_code.as<float>(), m, od, pose, target, ctx->P, n, ctx->mlp_S.as<uint16_t>(),
+                                ctx->mlp_code.as<float>(), m, od, pose, target, ctx->P, n, ctx->mlp_S.as<float>(),
                                 ctx->mlp_part.as<float>(), ctx->mlp_lossp.as<float>(), ctx->mlp_flag.as<uint32_t>(),
                                 st),
                 "proposal gradient");
@@ -1057,7 +1061,7 @@ art_status art_proposal_train(art_ctx* ctx, int64_t n, const float* od, const in
                         "proposal prep");
         ART_TRY_HIP(launch_mlp_grad(ctx->mlp_packed.as<uint16_t>(), ctx->mlp_theta.as<float>(),
                                     ctx->mlp_cbias.as<float>(), ctx->mlp_code.as<float>(), m, od + off * 6,
-                                    pose + off, target + off * 2, ctx->P, batch, ctx->mlp_S.as<uint16_t>(),
+                                    pose + off, target + off * 2, ctx->P, batch, ctx->mlp_S.as<float>(),
                                     ctx->mlp_part.as<float>(), ctx->mlp_lossp.as<float>(),
                                     ctx->mlp_flag.as<uint32_t>(), st),
                     "proposal gradient");

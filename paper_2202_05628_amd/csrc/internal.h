@@ -240,6 +240,7 @@ struct RenderLaunch {
     bool interval_by_item;
     float margin;            // ray-parameter units
     float f2_tau;
+    bool near_only;          // mode 4: the interval ends at t_b
     int max_hits;
     int debug_view;
     int32_t* hit_leaf;
@@ -295,7 +296,7 @@ hipError_t launch_mlp_forward(const uint16_t* packed, const float* theta, const 
                               hipStream_t st);
 hipError_t launch_mlp_grad(const uint16_t* packed, const float* theta, const float* cbias, const float* code,
                            const MlpDims& m, const float* od, const int32_t* pose, const float* target, int P,
-                           int64_t n, uint16_t* S, float* part, float* loss_part, uint32_t* bad, hipStream_t st);
+                           int64_t n, float* S, float* part, float* loss_part, uint32_t* bad, hipStream_t st);
 hipError_t launch_mlp_reduce(const float* part, int64_t n, const MlpDims& m, float* grad, float* theta, float* m1,
                              float* m2, const AdamStep* adam, const float* loss_part, float* loss_out,
                              hipStream_t st);

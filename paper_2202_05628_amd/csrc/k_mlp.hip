@@ -7,8 +7,11 @@
 // c_p = W1[:, 6:] code_p + b1, depends only on the pose and is evaluated once
 // per pose in FP32 (k_mlp_prep); per ray the first layer is the 6-input
 // product plus that bias.  Every other product runs on
-// v_mfma_f32_16x16x32_bf16: BF16 operands, FP32 accumulation, FP32 master
-// weights.
+// v_mfma_f32_16x16x32_bf16 with FP32 accumulation and FP32 master weights:
+// inference takes single BF16 operands; training splits every operand into a
+// BF16 head and tail (a = a_hi + a_lo) and takes a_hi b_hi + a_hi b_lo +
+// a_lo b_hi (three matrix-core products, about 16 significant bits), so the
+// gradients are not dominated by operand rounding.
 //
 // Register layout of one wave working on 16 rays (lane l, r = l % 16,
 // g = l / 16):
@@ -20,7 +23,7 @@
 //   packed with the same feature permutation over K (k_mlp_prep);
 //   A operand (weights): lane holds W[16 m + r][phi(ks, g, e)].
 // The weight gradients are contractions over rays: the training forward /
-// backward kernel stores activations and deltas (BF16) feature-major, and
+// backward kernel stores activations and deltas (FP32) feature-major, and
 // k_mlp_wgrad reads 8 consecutive rays per lane as the K operand.  Partial
 // sums per chunk of 256 rays are reduced in a fixed order (deterministic).
 #include <algorithm>
@@ -44,7 +47,7 @@ constexpr int kB_W4T = 22;   // [mt]      W4^T, K = 2 outputs padded to 32
 constexpr int kB_W3T = 26;   // [mt][ks]
 constexpr int kB_W2T = 34;   // [mt][ks]
 constexpr int kBlocks = 42;
-constexpr int kPacked = kBlocks * 64 * 8;
+constexpr int kPacked = 2 * kBlocks * 64 * 8;   // heads, then tails
 // feature-major training scratch rows
 constexpr int kRowH1 = 0, kRowH2 = 64, kRowH3 = 128, kRowD1 = 192, kRowD2 = 256, kRowD3 = 320, kRowD4 = 384;
 constexpr int kRows = 400;
@@ -74,6 +77,41 @@ __device__ inline bf16x8 pack_tiles(const f32x4 a, const f32x4 b) {
 
 __device__ inline f32x4 mfma(const bf16x8 a, const bf16x8 b, const f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// v = hi + lo with hi = bf16(v), lo = bf16(v - hi)
+__device__ inline void split8(const float* v, bf16x8& hi, bf16x8& lo) {
+    u16x8 h, l;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        h[e] = f2bf(v[e]);
+        l[e] = f2bf(v[e] - __uint_as_float((uint32_t)h[e] << 16));
+    }
+    hi = __builtin_bit_cast(bf16x8, h);
+    lo = __builtin_bit_cast(bf16x8, l);
+}
+
+// B operands (head, tail) of the two k-steps of a 64-wide layer input held
+// as four accumulator tiles.
+template <bool SPLIT>
+__device__ inline void tiles_to_ops(const f32x4* t, bf16x8* Bh, bf16x8* Bl) {
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+        const float v[8] = {t[2 * ks][0], t[2 * ks][1], t[2 * ks][2], t[2 * ks][3],
+                            t[2 * ks + 1][0], t[2 * ks + 1][1], t[2 * ks + 1][2], t[2 * ks + 1][3]};
+        if (SPLIT) split8(v, Bh[ks], Bl[ks]);
+        else Bh[ks] = pack8(v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7]);
+    }
+}
+
+// A [16 x K] x B [K x 16] with K = 32 (one k-step): one or three products.
+template <bool SPLIT, typename WSrc>
+__device__ inline f32x4 mm1(const WSrc& w, int blk, const bf16x8 Bh, const bf16x8 Bl, f32x4 acc) {
+    if (SPLIT) {
+        acc = mfma(w.lo(blk), Bh, acc);
+        acc = mfma(w.get(blk), Bl, acc);
+    }
+    return mfma(w.get(blk), Bh, acc);
 }
 
 __host__ __device__ inline int phi(int ks, int g, int e) { return 16 * (2 * ks + (e >> 2)) + 4 * g + (e & 3); }
@@ -127,7 +165,10 @@ __global__ void k_mlp_prep(const float* __restrict__ theta, MlpDims m, const flo
     const float* W3 = theta + m.oW3;
     const float* W4 = theta + m.oW4;
     if (i < kPacked) {
-        const int blk = i / 512, lane = (i / 8) % 64, e = i % 8;
+        const int half = kPacked / 2;
+        const bool tail = i >= half;
+        const int ii = tail ? i - half : i;
+        const int blk = ii / 512, lane = (ii / 8) % 64, e = ii % 8;
         const int r = lane & 15, g = lane >> 4;
         float v = 0.0f;
         if (blk < kB_W2) {
@@ -152,7 +193,8 @@ __global__ void k_mlp_prep(const float* __restrict__ theta, MlpDims m, const flo
             const int mt = (blk - kB_W2T) >> 1, ks = (blk - kB_W2T) & 1;
             v = W2[phi(ks, g, e) * kHid + 16 * mt + r];
         }
-        packed[i] = f2bf(v);
+        const uint16_t hb = f2bf(v);
+        packed[i] = tail ? f2bf(v - __uint_as_float((uint32_t)hb << 16)) : hb;
         return;
     }
     const int j = i - kPacked;
@@ -167,63 +209,66 @@ __global__ void k_mlp_prep(const float* __restrict__ theta, MlpDims m, const flo
 }
 
 // Layer 2..4 forward of one 16-ray group from the layer-1 output h1.
-template <typename WSrc>
+template <bool SPLIT, typename WSrc>
 __device__ inline void forward_tail(const WSrc& w, const float* __restrict__ theta, const MlpDims& m, int g,
                                     const f32x4* h1, f32x4* h2, f32x4* h3, f32x4& z4) {
-    bf16x8 B0 = pack_tiles(h1[0], h1[1]);
-    bf16x8 B1 = pack_tiles(h1[2], h1[3]);
+    bf16x8 Bh[2], Bl[2];
+    tiles_to_ops<SPLIT>(h1, Bh, Bl);
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt) {
         f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-        acc = mfma(w.get(kB_W2 + 2 * mt), B0, acc);
-        acc = mfma(w.get(kB_W2 + 2 * mt + 1), B1, acc);
+        acc = mm1<SPLIT>(w, kB_W2 + 2 * mt, Bh[0], Bl[0], acc);
+        acc = mm1<SPLIT>(w, kB_W2 + 2 * mt + 1, Bh[1], Bl[1], acc);
 #pragma unroll
         for (int e = 0; e < 4; ++e) acc[e] = fmaxf(acc[e] + theta[m.ob2 + 16 * mt + 4 * g + e], 0.0f);
         h2[mt] = acc;
     }
-    B0 = pack_tiles(h2[0], h2[1]);
-    B1 = pack_tiles(h2[2], h2[3]);
+    tiles_to_ops<SPLIT>(h2, Bh, Bl);
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt) {
         f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-        acc = mfma(w.get(kB_W3 + 2 * mt), B0, acc);
-        acc = mfma(w.get(kB_W3 + 2 * mt + 1), B1, acc);
+        acc = mm1<SPLIT>(w, kB_W3 + 2 * mt, Bh[0], Bl[0], acc);
+        acc = mm1<SPLIT>(w, kB_W3 + 2 * mt + 1, Bh[1], Bl[1], acc);
 #pragma unroll
         for (int e = 0; e < 4; ++e) acc[e] = fmaxf(acc[e] + theta[m.ob3 + 16 * mt + 4 * g + e], 0.0f);
         h3[mt] = acc;
     }
-    B0 = pack_tiles(h3[0], h3[1]);
-    B1 = pack_tiles(h3[2], h3[3]);
+    tiles_to_ops<SPLIT>(h3, Bh, Bl);
     f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-    acc = mfma(w.get(kB_W4), B0, acc);
-    acc = mfma(w.get(kB_W4 + 1), B1, acc);
+    acc = mm1<SPLIT>(w, kB_W4, Bh[0], Bl[0], acc);
+    acc = mm1<SPLIT>(w, kB_W4 + 1, Bh[1], Bl[1], acc);
     z4 = acc;
 }
 
 // First layer: 6 ray inputs (lanes of group 0 carry them) plus the pose bias.
-template <typename WSrc>
+template <bool SPLIT, typename WSrc>
 __device__ inline void forward_head(const WSrc& w, const float* x, const float* __restrict__ cb, int g, f32x4* h1) {
-    const bf16x8 Bx = g == 0 ? pack8(x[0], x[1], x[2], x[3], x[4], x[5], 0.0f, 0.0f)
-                             : pack8(0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f);
+    const float v[8] = {g == 0 ? x[0] : 0.0f, g == 0 ? x[1] : 0.0f, g == 0 ? x[2] : 0.0f, g == 0 ? x[3] : 0.0f,
+                        g == 0 ? x[4] : 0.0f, g == 0 ? x[5] : 0.0f, 0.0f, 0.0f};
+    bf16x8 Bh, Bl;
+    if (SPLIT) split8(v, Bh, Bl);
+    else Bh = pack8(v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7]);
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt) {
         f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-        acc = mfma(w.get(kB_W1 + mt), Bx, acc);
+        acc = mm1<SPLIT>(w, kB_W1 + mt, Bh, Bl, acc);
 #pragma unroll
         for (int e = 0; e < 4; ++e) acc[e] = fmaxf(acc[e] + cb[16 * mt + 4 * g + e], 0.0f);
         h1[mt] = acc;
     }
 }
 
-struct WLds {   // operand blocks staged in LDS
-    const bf16x8* s;
+struct WGlobal {   // operand blocks read from device memory (heads, tails)
+    const bf16x8* p;
     int lane;
-    __device__ bf16x8 get(int blk) const { return s[blk * 64 + lane]; }
+    __device__ bf16x8 get(int blk) const { return p[blk * 64 + lane]; }
+    __device__ bf16x8 lo(int blk) const { return p[(kBlocks + blk) * 64 + lane]; }
 };
 
-struct WRegs {   // forward operand blocks held in registers
+struct WRegs {   // forward operand heads held in registers (inference)
     bf16x8 b[kB_W4T];
     __device__ bf16x8 get(int blk) const { return b[blk]; }
+    __device__ bf16x8 lo(int blk) const { return b[blk]; }   // unused: single BF16 operands
 };
 
 // ---------------------------------------------------------------------------
@@ -239,7 +284,7 @@ struct FbArgs {
     const float* target;      // [n][2]
     float* out;               // [n][2] (mode 0)
     int64_t n, n_pad;         // n_pad: multiple of kChunk
-    uint16_t* S;              // [kRows][n_pad] (mode 1)
+    float* S;                 // [kRows][n_pad] (mode 1)
     float* loss_part;         // [gridDim.x] sums of SmoothL1 over rays and outputs
     float inv2n;              // 1 / (2 n)
     int mode;
@@ -250,24 +295,16 @@ struct FbArgs {
 __device__ inline float smooth_l1f(float e) { const float a = fabsf(e); return a < 1.0f ? 0.5f * e * e : a - 0.5f; }
 __device__ inline float smooth_l1_gradf(float e) { return fabsf(e) < 1.0f ? e : (e > 0.0f ? 1.0f : -1.0f); }
 
-__device__ inline void store_tiles(uint16_t* S, int64_t stride, int row0, int64_t ray, int g, const f32x4* t, int nt) {
+__device__ inline void store_tiles(float* S, int64_t stride, int row0, int64_t ray, int g, const f32x4* t, int nt) {
     for (int mt = 0; mt < nt; ++mt)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) S[(int64_t)(row0 + 16 * mt + 4 * g + e) * stride + ray] = f2bf(t[mt][e]);
+        for (int e = 0; e < 4; ++e) S[(int64_t)(row0 + 16 * mt + 4 * g + e) * stride + ray] = t[mt][e];
 }
 
-__global__ __launch_bounds__(256) void k_mlp_fb(FbArgs a) {
-    __shared__ bf16x8 sw[kBlocks * 64];
-    __shared__ float sloss[4];
-    {
-        const uint4* src = reinterpret_cast<const uint4*>(a.packed);
-        uint4* dst = reinterpret_cast<uint4*>(sw);
-        for (int i = threadIdx.x; i < kBlocks * 64; i += blockDim.x) dst[i] = src[i];
-    }
-    __syncthreads();
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+template <bool SPLIT>
+__device__ inline void fb_body(const FbArgs& a, int lane, int w, float* sloss) {
     const int r = lane & 15, g = lane >> 4;
-    WLds W{sw, lane};
+    WGlobal W{reinterpret_cast<const bf16x8*>(a.packed), lane};
     const MlpDims& m = a.m;
     float lsum = 0.0f;
     const int64_t groups = a.n_pad / 16;
@@ -289,11 +326,11 @@ __global__ __launch_bounds__(256) void k_mlp_fb(FbArgs a) {
             for (int i = 0; i < 6; ++i) x[i] = a.od[ray * 6 + i];
         }
         f32x4 h1[4], h2[4], h3[4], z4;
-        forward_head(W, x, a.cbias + (size_t)p * kHid, g, h1);
-        forward_tail(W, a.theta, m, g, h1, h2, h3, z4);
+        forward_head<SPLIT>(W, x, a.cbias + (size_t)p * kHid, g, h1);
+        forward_tail<SPLIT>(W, a.theta, m, g, h1, h2, h3, z4);
         const float y0 = sigmoidf(z4[0] + a.theta[m.ob4]);
         const float y1 = sigmoidf(z4[1] + a.theta[m.ob4 + 1]);
-        if (a.mode == 0) {
+        if (!SPLIT) {
             if (valid && g == 0) reinterpret_cast<float2*>(a.out)[ray] = make_float2(y0, y1);
             continue;
         }
@@ -312,44 +349,59 @@ __global__ __launch_bounds__(256) void k_mlp_fb(FbArgs a) {
             const f32x4 d4 = {d40, d41, 0.0f, 0.0f};   // zero for g > 0
             store_tiles(a.S, a.n_pad, kRowD4, ray, g, &d4, 1);
         }
-        const bf16x8 Bd4 = pack8(d40, d41, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f);
+        bf16x8 Bh[2], Bl[2];
+        {
+            const float v[8] = {d40, d41, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+            split8(v, Bh[0], Bl[0]);
+        }
         f32x4 d3[4], d2[4], d1[4];
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) {
             f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-            acc = mfma(W.get(kB_W4T + mt), Bd4, acc);
+            acc = mm1<true>(W, kB_W4T + mt, Bh[0], Bl[0], acc);
 #pragma unroll
             for (int e = 0; e < 4; ++e) acc[e] = h3[mt][e] > 0.0f ? acc[e] : 0.0f;
             d3[mt] = acc;
         }
         store_tiles(a.S, a.n_pad, kRowD3, ray, g, d3, 4);
-        bf16x8 B0 = pack_tiles(d3[0], d3[1]), B1 = pack_tiles(d3[2], d3[3]);
+        tiles_to_ops<true>(d3, Bh, Bl);
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) {
             f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-            acc = mfma(W.get(kB_W3T + 2 * mt), B0, acc);
-            acc = mfma(W.get(kB_W3T + 2 * mt + 1), B1, acc);
+            acc = mm1<true>(W, kB_W3T + 2 * mt, Bh[0], Bl[0], acc);
+            acc = mm1<true>(W, kB_W3T + 2 * mt + 1, Bh[1], Bl[1], acc);
 #pragma unroll
             for (int e = 0; e < 4; ++e) acc[e] = h2[mt][e] > 0.0f ? acc[e] : 0.0f;
             d2[mt] = acc;
         }
         store_tiles(a.S, a.n_pad, kRowD2, ray, g, d2, 4);
-        B0 = pack_tiles(d2[0], d2[1]);
-        B1 = pack_tiles(d2[2], d2[3]);
+        tiles_to_ops<true>(d2, Bh, Bl);
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) {
             f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-            acc = mfma(W.get(kB_W2T + 2 * mt), B0, acc);
-            acc = mfma(W.get(kB_W2T + 2 * mt + 1), B1, acc);
+            acc = mm1<true>(W, kB_W2T + 2 * mt, Bh[0], Bl[0], acc);
+            acc = mm1<true>(W, kB_W2T + 2 * mt + 1, Bh[1], Bl[1], acc);
 #pragma unroll
             for (int e = 0; e < 4; ++e) acc[e] = h1[mt][e] > 0.0f ? acc[e] : 0.0f;
             d1[mt] = acc;
         }
         store_tiles(a.S, a.n_pad, kRowD1, ray, g, d1, 4);
     }
-    if (a.mode == 0) return;
+    if (!SPLIT) return;
     lsum = wave_sum(lsum);
     if (lane == 0) sloss[w] = lsum;
+}
+
+// mode 0: network outputs (inference precision, single BF16 operands);
+// mode 1: training forward + loss + backward (split BF16 operands).
+__global__ __launch_bounds__(256) void k_mlp_fb(FbArgs a) {
+    __shared__ float sloss[4];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (a.mode == 0) {
+        fb_body<false>(a, lane, w, sloss);
+        return;
+    }
+    fb_body<true>(a, lane, w, sloss);
     __syncthreads();
     if (threadIdx.x == 0) a.loss_part[blockIdx.x] = ((sloss[0] + sloss[1]) + sloss[2]) + sloss[3];
 }
@@ -358,7 +410,7 @@ __global__ __launch_bounds__(256) void k_mlp_fb(FbArgs a) {
 // weight gradients of one chunk of 256 rays: dW = sum_rays delta (x) input
 // ---------------------------------------------------------------------------
 struct WgArgs {
-    const uint16_t* S;
+    const float* S;
     int64_t n, n_pad;
     const float* od;
     const int32_t* pose;
@@ -368,8 +420,11 @@ struct WgArgs {
     float* part;           // [n_pad / kChunk][np]
 };
 
-__device__ inline bf16x8 load8(const uint16_t* p) {
-    return __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(p));
+__device__ inline void load8_split(const float* p, bf16x8& hi, bf16x8& lo) {
+    const float4 a = reinterpret_cast<const float4*>(p)[0];
+    const float4 b = reinterpret_cast<const float4*>(p)[1];
+    const float v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+    split8(v, hi, lo);
 }
 
 __global__ __launch_bounds__(256) void k_mlp_wgrad(WgArgs a) {
@@ -409,8 +464,8 @@ __global__ __launch_bounds__(256) void k_mlp_wgrad(WgArgs a) {
         f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
         for (int kb = 0; kb < kChunk / 32; ++kb) {
             const int64_t rb = R0 + kb * 32 + 8 * g;
-            const bf16x8 A = load8(a.S + (int64_t)arow * a.n_pad + rb);
-            bf16x8 B;
+            bf16x8 Ah, Al, Bh, Bl;
+            load8_split(a.S + (int64_t)arow * a.n_pad + rb, Ah, Al);
             if (layer == 1) {
                 float v[8];
 #pragma unroll
@@ -426,11 +481,13 @@ __global__ __launch_bounds__(256) void k_mlp_wgrad(WgArgs a) {
                     }
                     v[e] = x;
                 }
-                B = pack8(v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7]);
+                split8(v, Bh, Bl);
             } else {
-                B = load8(a.S + (int64_t)(brow + in) * a.n_pad + rb);
+                load8_split(a.S + (int64_t)(brow + in) * a.n_pad + rb, Bh, Bl);
             }
-            acc = mfma(A, B, acc);
+            acc = mfma(Al, Bh, acc);
+            acc = mfma(Ah, Bl, acc);
+            acc = mfma(Ah, Bh, acc);
         }
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
@@ -453,9 +510,9 @@ __global__ __launch_bounds__(256) void k_mlp_wgrad(WgArgs a) {
         else if (row < 2 * kHid) { srow = kRowD2 + row - kHid; dst = m.ob2 + row - kHid; }
         else if (row < 3 * kHid) { srow = kRowD3 + row - 2 * kHid; dst = m.ob3 + row - 2 * kHid; }
         else { srow = kRowD4 + row - 3 * kHid; dst = m.ob4 + row - 3 * kHid; }
-        const uint16_t* s = a.S + (int64_t)srow * a.n_pad + R0;
+        const float* s = a.S + (int64_t)srow * a.n_pad + R0;
         float acc = 0.0f;
-        for (int i = 0; i < kChunk; ++i) acc += bf16_to_f32(s[i]);
+        for (int i = 0; i < kChunk; ++i) acc += s[i];
         part[dst] = acc;
     }
 }
@@ -562,8 +619,8 @@ __global__ __launch_bounds__(256) void k_mlp_infer_tiles(InferLaunch a) {
             float x[6];
             ray_f32(cam, px, py, x, x + 3);
             f32x4 h1[4], h2[4], h3[4], z4;
-            forward_head(W, x, cb, g, h1);
-            forward_tail(W, a.theta, a.m, g, h1, h2, h3, z4);
+            forward_head<false>(W, x, cb, g, h1);
+            forward_tail<false>(W, a.theta, a.m, g, h1, h2, h3, z4);
             if (g == 0)
                 reinterpret_cast<float2*>(a.out)[(size_t)idx * 64 + pl] =
                     make_float2(sigmoidf(z4[0] + a.theta[a.m.ob4]), sigmoidf(z4[1] + a.theta[a.m.ob4 + 1]));
@@ -588,7 +645,7 @@ hipError_t launch_mlp_prep(const float* theta, const MlpDims& m, const float* co
 }
 
 int64_t mlp_pad(int64_t n) { return (n + kChunk - 1) / kChunk * kChunk; }
-size_t mlp_scratch_bytes(int64_t n) { return (size_t)kRows * (size_t)mlp_pad(n) * 2; }
+size_t mlp_scratch_bytes(int64_t n) { return (size_t)kRows * (size_t)mlp_pad(n) * 4; }
 int mlp_packed_elems() { return kPacked; }
 
 static unsigned fb_grid(int64_t n_pad) {
@@ -621,7 +678,7 @@ hipError_t launch_mlp_forward(const uint16_t* packed, const float* theta, const 
 
 hipError_t launch_mlp_grad(const uint16_t* packed, const float* theta, const float* cbias, const float* code,
                            const MlpDims& m, const float* od, const int32_t* pose, const float* target, int P,
-                           int64_t n, uint16_t* S, float* part, float* loss_part, uint32_t* bad, hipStream_t st) {
+                           int64_t n, float* S, float* part, float* loss_part, uint32_t* bad, hipStream_t st) {
     FbArgs a{};
     a.P = P;
     a.bad = bad;

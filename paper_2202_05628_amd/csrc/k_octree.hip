@@ -152,6 +152,11 @@ __global__ __launch_bounds__(kUThreads) void k_unique_write(
         const uint32_t ex = block_exclusive_scan<kUThreads>(nr | (nbk << 16), tmp, &tot);
         uint32_t m = carry_r + (ex & 0xFFFFu);
         uint32_t bc = carry_b + (ex >> 16);   // bricks started before this thread's items
+        // Cells of one mask word are consecutive in Morton order: their bits are
+        // gathered in a register and OR-ed into the word once per run (words
+        // shared with a neighbouring thread's items still meet in the atomic).
+        size_t word = ~(size_t)0;
+        uint32_t bits = 0;
 #pragma unroll
         for (int j = 0; j < kUItems; ++j) {
             const bool rs = (flags >> j) & 1u;
@@ -166,10 +171,17 @@ __global__ __launch_bounds__(kUThreads) void k_unique_write(
                 occ_key[m] = k[j];
                 occ_win[m] = id;
                 const uint32_t local = k[j] & 511u;
-                atomicOr(&brick_mask[(size_t)(bc - 1) * 16 + (local >> 5)], 1u << (local & 31u));
+                const size_t wi = (size_t)(bc - 1) * 16 + (local >> 5);
+                if (wi != word) {
+                    if (bits) atomicOr(&brick_mask[word], bits);
+                    word = wi;
+                    bits = 0;
+                }
+                bits |= 1u << (local & 31u);
                 ++m;
             }
         }
+        if (bits) atomicOr(&brick_mask[word], bits);
         carry_r += tot & 0xFFFFu;
         carry_b += tot >> 16;
     }

@@ -44,6 +44,21 @@ constexpr int kStage = 64;
 
 constexpr int kStepsPerRound = ART_STEPS_PER_ROUND;
 
+// 1: conservative FP32 slab test in the brick pre-pass (phase 1)
+#ifndef ART_PHASE1_F32
+#define ART_PHASE1_F32 1
+#endif
+// 1: fetch a sample's winner id one round before its FLUT row (three-stage
+// pipeline: step -> winner id -> FLUT row -> composite)
+#ifndef ART_ID_PREFETCH
+#define ART_ID_PREFETCH 1
+#endif
+// 1: a ray leaves a brick when its cell does, and continues into the next
+// listed brick without a ray/box test when its cell lies in it
+#ifndef ART_CELL_EXIT
+#define ART_CELL_EXIT 0
+#endif
+
 struct RArgs {
     const CamParams* cam;
     int Pb, V, H, W, TX, TY, TPV, depth;   // poses in this launch, views, image, tiles
@@ -80,6 +95,7 @@ struct RArgs {
     int interval_by_item;
     float margin;                          // proposal margin (ray-parameter units)
     float f2_tau;                          // F2 threshold on T (< 0: off)
+    int near_only;                         // MODE 4: only u_near is used (interval ends at t_b)
     int max_hits;
     int debug_view;                        // view whose hit lists are recorded (MODE 2)
     int32_t* hit_leaf;                     // [H*W][max_hits] (single pose / view)
@@ -160,10 +176,27 @@ __device__ inline bool brick_overlap(const int* b3, const R* d, const R* q, cons
     return ok && (t1 > t0);
 }
 
+// Span [ta, tb] of the ray inside the posed root (lattice planes 0 and G) along
+// the axes it moves on (t >= 0).
+template <typename R>
+__device__ inline void root_span(const R* d, const R* q, const R* inv, R h, int G, R& ta, R& tb) {
+    ta = 0;
+    tb = (R)INFINITY;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        if (d[i] != (R)0) {
+            const R u0 = tplane<R>(0, h, q[i], inv[i]);
+            const R u1 = tplane<R>(G, h, q[i], inv[i]);
+            ta = fmax(ta, fmin(u0, u1));
+            tb = fmin(tb, fmax(u0, u1));
+        }
+    }
+}
+
 // MODE: 0 forward, 1 adjoint, 2 forward recording hit lists, 3 interval labels,
 // 4 forward guided by proposed intervals (with full-traversal fallbacks)
 #ifndef ART_RENDER_WAVES_PER_EU
-#define ART_RENDER_WAVES_PER_EU 1
+#define ART_RENDER_WAVES_PER_EU 3
 #endif
 // Render one non-empty tile (item = pose-in-launch * V + view, tile index).
 template <int C, int ST, typename R, int MODE>
@@ -219,7 +252,8 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
         }
     }
     // clip to the posed root [-1, 1]^3 (lattice planes 0 and G)
-    R ta = 0, tb = (R)INFINITY;
+    R ta, tb;
+    root_span<R>(d, q, inv, h, G, ta, tb);
     bool hit_root = true;
     int c0[3];   // constant cell coordinate along axes the ray does not move on
 #pragma unroll
@@ -229,11 +263,6 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
             const R u = floor(q[i] * invh);
             hit_root = hit_root && (u >= (R)0) && (u < (R)G);
             c0[i] = hit_root ? (int)u : 0;
-        } else {
-            const R u0 = tplane<R>(0, h, q[i], inv[i]);
-            const R u1 = tplane<R>(G, h, q[i], inv[i]);
-            ta = fmax(ta, fmin(u0, u1));
-            tb = fmin(tb, fmax(u0, u1));
         }
     }
     bool active = pix_ok && hit_root && (tb > ta) && (ls < le);
@@ -242,7 +271,6 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
     const size_t map = (size_t)pvi;   // (pose-in-launch, view) map index
 
     // ---- proposal (MODE 4): the first pass traverses only [ts, te] ----------------
-    const R ta_full = ta, tb_full = tb;
     bool prop = false;
     if constexpr (MODE == 4) {
         if (active) {
@@ -251,7 +279,7 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
             if (u.x <= u.y) {   // a predicted non-empty interval (u_near <= u_far)
                 const R span = tb - ta;
                 const R ts = fmax(ta, ta + (R)u.x * span - (R)a.margin);
-                const R te = fmin(tb, ta + (R)u.y * span + (R)a.margin);
+                const R te = a.near_only ? tb : fmin(tb, ta + (R)u.y * span + (R)a.margin);
                 if (te > ts) {
                     ta = ts;
                     tb = te;
@@ -294,9 +322,11 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
     bool inb = false;
     R s = 0, t1 = 0;
     R tc[3] = {(R)INFINITY, (R)INFINITY, (R)INFINITY};
-    int kp[3] = {0, 0, 0};   // index of the next lattice plane crossed on each axis
-    int cg[3] = {c0[0], c0[1], c0[2]};   // lattice cell of the ray at s
-    int lo3[3] = {0, 0, 0};  // first lattice cell of the current brick
+    // index of the next lattice plane crossed on each axis (the constant cell
+    // coordinate on an axis the ray does not move along); the ray's cell at s
+    // is kp - 1 on axes with d > 0 and kp otherwise
+    int kp[3] = {c0[0], c0[1], c0[2]};
+    int lo3[3] = {0, 0, 0};  // first lattice cell of the current brick (+1 on axes with d > 0)
     bool fresh = false;      // plane state valid (set by the first brick entry)
     int slot = 0;
     int bsteps = 0;
@@ -311,6 +341,9 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
             // F1: the proposed interval held no occupied voxel; F2: the ray left
             // it with transmittance above the threshold before the root's exit.
             // Such lanes restart from t_a with the whole ray.
+            // the whole span is recomputed rather than kept in registers
+            R ta_full, tb_full;
+            root_span<R>(d, q, inv, h, G, ta_full, tb_full);
             const bool fb = prop && (nsamp == 0 || (a.f2_tau >= 0.0f && T >= a.f2_tau && tb < tb_full));
             if (__ballot(fb) == 0ull) break;
             active = fb;
@@ -355,6 +388,51 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
         }
         wave_sync();
         const int nchunk = (int)((le - base) < (uint32_t)kStage ? (le - base) : (uint32_t)kStage);
+#if ART_PHASE1_F32
+        // phase 1: which staged bricks may this lane's ray cross?  A
+        // conservative FP32 slab test against each brick grown by kGrow on
+        // every face: it never misses a brick the exact test accepts (the
+        // coefficients' rounding stays far below kGrow / |d|), and phase 2
+        // re-tests every brick exactly before entering it.
+        uint64_t todo = 0;
+        if (active) {
+            constexpr double kGrow = 1e-5;
+            float a8[3], a0[3], aw[3];
+            bool par[3];
+            // recomputed per chunk (opaque to loop-invariant hoisting) so that
+            // the coefficients are not held in registers across the tile
+            double hh = (double)h;
+            asm volatile("" : "+v"(hh));
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                par[i] = d[i] == (R)0;
+                const double iv = par[i] ? 0.0 : (double)inv[i];
+                a8[i] = (float)(8.0 * hh * iv);
+                a0[i] = (float)(-((double)q[i] + kGrow) * iv);
+                aw[i] = (float)((8.0 * hh + 2.0 * kGrow) * iv);
+            }
+            const float taf = (float)ta - 1e-5f, tbf = (float)tb + 1e-5f;
+#pragma unroll 1
+            for (int j = 0; j < nchunk; ++j) {
+                const uint32_t cc = s_coord[wv][j];
+                const int b3[3] = {(int)(cc & 1023u), (int)((cc >> 10) & 1023u), (int)(cc >> 20)};
+                float t0 = taf, t1f = tbf;
+                bool ok = true;
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    if (par[i]) {
+                        ok = ok && ((c0[i] >> 3) == b3[i]);
+                    } else {
+                        const float u0 = __fmaf_rn((float)b3[i], a8[i], a0[i]);
+                        const float u1 = u0 + aw[i];
+                        t0 = fmaxf(t0, fminf(u0, u1));
+                        t1f = fminf(t1f, fmaxf(u0, u1));
+                    }
+                }
+                if (ok && t1f > t0) todo |= 1ull << j;
+            }
+        }
+#else
         // phase 1: which staged bricks does this lane's ray cross (positive length)?
         uint64_t todo = 0;
         if (active) {
@@ -365,22 +443,28 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
                 if (brick_overlap<R>(b3, d, q, inv, c0, h, ta, tb, u0, u1)) todo |= 1ull << j;
             }
         }
+#endif
         // phase 2: walk the crossed bricks in list order.  Software pipeline of
         // depth one: each round advances the ray to its next occupied segment
         // while the current sample's gather is in flight, composites the current
         // sample, then issues the next sample's gather into the same registers.
         bool hasA = false;
-        uint32_t rowA = 0;
+        uint32_t rowA = 0, winA = 0;
         float dlA = 0.0f;
         double dxA = 0.0;
         R sA0 = 0, sA1 = 0;
         float sgA = 0.0f;
+        bool hasI = false;   // a sample whose winner id is in flight (ART_ID_PREFETCH)
+        uint32_t winI = 0;
+        float dlI = 0.0f;
+        double dxI = 0.0;
+        R sI0 = 0, sI1 = 0;
         float fA[C];
 #pragma unroll
         for (int c = 0; c < C; ++c) fA[c] = 0.0f;
         while (true) {
             const bool more = active && (inb || todo != 0ull);
-            if (__ballot(more || hasA) == 0ull) break;
+            if (__ballot(more || hasA || hasI) == 0ull) break;
             ++rounds;
             // (1) next occupied segment of this lane's ray (overlaps the gather of A)
             bool hasB = false;
@@ -397,13 +481,44 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
                     todo &= todo - 1ull;
                     const uint32_t cc = s_coord[wv][slot];
                     const int b3[3] = {(int)(cc & 1023u), (int)((cc >> 10) & 1023u), (int)(cc >> 20)};
+#if ART_CELL_EXIT
+                    // The ray continues into this brick when its current cell (it
+                    // just left the previous brick through a face) lies in it: the
+                    // plane state carries over and no ray/box test is needed.
+                    bool cont = fresh;
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) cont = cont && (((kp[i] - (d[i] > (R)0 ? 1 : 0)) >> 3) == b3[i]);
+                    if (!cont) {
+                        R t0, t1x;
+                        if (!brick_overlap<R>(b3, d, q, inv, c0, h, ta, tb, t0, t1x)) continue;
+                        // restart the plane state from the lattice coordinate at t0;
+                        // rounding there can only misplace a segment shorter than the
+                        // rounding itself (a plane index one too small costs one
+                        // empty step)
+#pragma unroll
+                        for (int i = 0; i < 3; ++i) {
+                            if (d[i] == (R)0) continue;
+                            const R u = (q[i] + t0 * d[i]) * invh;
+                            const int k = d[i] > (R)0 ? (int)floor(u) + 1 : (int)ceil(u) - 1;
+                            kp[i] = k;
+                            tc[i] = tplane<R>(k, h, q[i], inv[i]);
+                        }
+                        fresh = true;
+                        s = t0;
+                    }
+                    inb = true;
+                    bsteps = 0;
+                    row_base = s_row[wv][slot];
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) lo3[i] = 8 * b3[i] + (d[i] > (R)0 ? 1 : 0);
+#else
                     R t0;
                     if (!brick_overlap<R>(b3, d, q, inv, c0, h, ta, tb, t0, t1)) continue;
                     inb = true;
                     bsteps = 0;
                     row_base = s_row[wv][slot];
 #pragma unroll
-                    for (int i = 0; i < 3; ++i) lo3[i] = 8 * b3[i];
+                    for (int i = 0; i < 3; ++i) lo3[i] = 8 * b3[i] + (d[i] > (R)0 ? 1 : 0);
                     // Entering exactly where the ray left the previous brick (its
                     // neighbour), the plane state carries over unchanged.  Otherwise
                     // it restarts from the lattice coordinate at t0; rounding there
@@ -416,17 +531,21 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
                             const R u = (q[i] + t0 * d[i]) * invh;
                             const int k = d[i] > (R)0 ? (int)floor(u) + 1 : (int)ceil(u) - 1;
                             kp[i] = k;
-                            cg[i] = d[i] > (R)0 ? k - 1 : k;
                             tc[i] = tplane<R>(k, h, q[i], inv[i]);
                         }
                         fresh = true;
                     }
                     s = t0;
+#endif
                 }
-                // one segment of the exact partition: (s, s1) in cell cg
+                // one segment of the exact partition: (s, s1) in the ray's cell
+#if ART_CELL_EXIT
+                R s1 = fmin(fmin(tc[0], tc[1]), fmin(tc[2], tb));
+#else
                 R s1 = fmin(fmin(tc[0], tc[1]), fmin(tc[2], t1));
+#endif
                 s1 = fmax(s1, s);
-                const int l0 = cg[0] - lo3[0], l1 = cg[1] - lo3[1], l2 = cg[2] - lo3[2];
+                const int l0 = kp[0] - lo3[0], l1 = kp[1] - lo3[1], l2 = kp[2] - lo3[2];
                 if (s1 > s && (unsigned)l0 < 8u && (unsigned)l1 < 8u && (unsigned)l2 < 8u) {
                     const uint32_t m9 = spread3_small((uint32_t)l0) | (spread3_small((uint32_t)l1) << 1) |
                                         (spread3_small((uint32_t)l2) << 2);
@@ -448,14 +567,21 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
                     if (tc[i] <= s1) {
                         const int st = d[i] > (R)0 ? 1 : -1;
                         kp[i] += st;
-                        cg[i] += st;
                         tc[i] = tplane<R>(kp[i], h, q[i], inv[i]);
                     }
                 }
                 s = s1;
                 // a brick holds at most 3 * 8 plane crossings; the cap only guards
                 // against non-finite input
+#if ART_CELL_EXIT
+                {   // the ray leaves the brick when its cell does
+                    const int m0 = kp[0] - lo3[0], m1 = kp[1] - lo3[1], m2 = kp[2] - lo3[2];
+                    const bool inside = (unsigned)m0 < 8u && (unsigned)m1 < 8u && (unsigned)m2 < 8u;
+                    if (!inside || s >= tb || ++bsteps > 32) inb = false;
+                }
+#else
                 if (s >= t1 || ++bsteps > 32) inb = false;
+#endif
             }
             // (2) composite the current sample (Eq. 5-6, exclusive transmittance)
             if (hasA && active) {
@@ -470,7 +596,7 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
 #pragma unroll
                     for (int c = 0; c < C; ++c) acc += g[c] * (Tn * fA[c] - (Ff[c] - P[c]));
                     const float ds = dlA * (acc + gA * Tfin);
-                    const uint32_t leaf = occ_win[rowA];
+                    const uint32_t leaf = winA;
                     unsafeAtomicAdd(&a.d_sigma[leaf], ds);
 #pragma unroll
                     for (int c = 0; c < C; ++c) unsafeAtomicAdd(&a.d_leaf_feat[(size_t)leaf * C + c], w * g[c]);
@@ -480,7 +606,7 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
                     Aacc += w;
                     if constexpr (MODE == 2) {
                         if (nsamp < a.max_hits) {
-                            a.hit_leaf[hit_base + nsamp] = (int32_t)occ_win[rowA];
+                            a.hit_leaf[hit_base + nsamp] = (int32_t)winA;
                             a.hit_delta[hit_base + nsamp] = dxA;
                         }
                     }
@@ -496,6 +622,27 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
                     inb = false;
                 }
             }
+#if ART_ID_PREFETCH
+            // (3) the sample whose winner id has arrived issues its FLUT gather
+            hasA = hasI && active;
+            if (hasA) {
+                dlA = dlI;
+                dxA = dxI;
+                sA0 = sI0;
+                sA1 = sI1;
+                winA = winI;
+                load_sample<C, ST>(a.sigma, a.feat, winA, sgA, fA);
+            }
+            // (4) the new sample fetches its collision winner's id
+            hasI = hasB && active;
+            if (hasI) {
+                dlI = dlB;
+                dxI = dxB;
+                sI0 = sB0;
+                sI1 = sB1;
+                winI = occ_win[rowB];
+            }
+#else
             // (3) issue the next sample's gather into the freed registers
             hasA = hasB && active;
             if (hasA) {
@@ -505,8 +652,10 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
                 sA0 = sB0;
                 sA1 = sB1;
                 // the FLUT row of the cell's collision winner
-                load_sample<C, ST>(a.sigma, a.feat, occ_win[rowA], sgA, fA);
+                winA = occ_win[rowA];
+                load_sample<C, ST>(a.sigma, a.feat, winA, sgA, fA);
             }
+#endif
         }
         wave_sync();
     }

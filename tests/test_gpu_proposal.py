@@ -92,8 +92,11 @@ def test_f2_fallback_on_truncated_intervals(tiny2, lam):
     sig, f = flut(s)
     F0, A0, _ = rend.render(sig, f, lam)
     lab = rend.proposal_labels(sig, f, lam)
+    import torch
     trunc = lab.clone()
-    trunc[..., 1] = trunc[..., 0]   # keep only the surroundings of the first sample
+    hit = lab[..., 0] <= lab[..., 1]
+    # rays with samples keep only the surroundings of their first sample; misses keep (1, 0)
+    trunc[..., 1] = torch.where(hit, lab[..., 0], lab[..., 1])
     log(f"guided render, truncated intervals, F2 off / on, lambda={lam}")
     Fa, Aa, _ = rend.render_proposal(sig, f, trunc, lam, margin_h=0.5, f2_tau=-1.0)
     assert rend.stats()["fallbacks"] == 0

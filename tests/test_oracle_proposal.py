@@ -220,11 +220,26 @@ def test_pose_code_is_two_rotation_columns():
     assert np.array_equal(mlp.pose_code(np.zeros((1, 4, 3))), np.tile([1.0, 0, 0, 0, 1, 0], (1, 4)))
 
 
-def test_bf16_form_close_to_fp64():
+def test_bf16_forms_close_to_fp64():
     mlp, theta, X, t = _problem(J=4, n=64, seed=9)
     y64 = mlp.forward(theta, X, 4)[0]
-    y16 = mlp.forward(theta, X, 4, round_bf16=True)[0]
+    y16 = mlp.forward(theta, X, 4, precision="bf16")[0]
+    y48 = mlp.forward(theta, X, 4, precision="bf16x3")[0]
     assert np.abs(y64 - y16).max() < 2e-2
+    assert np.abs(y64 - y48).max() < 1e-4
     _, g64 = mlp.grad(theta, X, t, 4)
-    _, g16 = mlp.grad(theta, X, t, 4, round_bf16=True)
-    assert np.abs(g64 - g16).max() / np.abs(g64).max() < 5e-2
+    _, g16 = mlp.grad(theta, X, t, 4, precision="bf16")
+    _, g48 = mlp.grad(theta, X, t, 4, precision="bf16x3")
+    assert np.abs(g64 - g16).max() / np.abs(g64).max() < 1e-1
+    assert np.abs(g64 - g48).max() / np.abs(g64).max() < 1e-3
+
+
+def test_bf16x3_product_is_near_exact():
+    import oracle.mlp as mlp
+    rng = np.random.default_rng(12)
+    a = rng.normal(size=(40, 64))
+    b = rng.normal(size=(64, 30))
+    ref = a @ b
+    err = np.abs(mlp._mm(a, b, "bf16x3") - ref).max() / np.abs(ref).max()
+    err1 = np.abs(mlp._mm(a, b, "bf16") - ref).max() / np.abs(ref).max()
+    assert err < 2e-5 < err1
