@@ -8,10 +8,10 @@
 //   k_hist     per-block digit histogram           -> hist[pose][digit][block]
 //   k_hscan    one workgroup per (digit, pose) scans its row over the blocks
 //              and writes the digit total
-//   k_scatter  per block, stable ranks: lanes with equal digits are matched
-//              with 8 wave ballots, their rank is the popcount of the matching
-//              lanes below; waves are ordered through a small LDS table and a
-//              running per-digit counter keeps tiles of 256 keys in order.
+//   k_scatter  per block, tiles of 4096 keys staged in LDS in stable digit
+//              order (lanes with equal digits matched with 8 wave ballots and
+//              ranked by lane; waves and 256-key sub-tiles ordered through LDS
+//              counters), then written digit run by digit run.
 #include "device_util.h"
 #include "internal.h"
 
@@ -66,16 +66,29 @@ __global__ __launch_bounds__(1024) void k_hscan(uint32_t* __restrict__ hist, int
     if (b == 0) digit_tot[d] = total;
 }
 
+// Keys per block iteration of the scatter: 16 sub-tiles of 256.
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kSortThreads * kSortItems;
+
+// Stable scatter of one digit pass.  A block stages each tile of 4096 keys in
+// LDS in digit order (stable ranks: lanes with equal digits are matched with 8
+// wave ballots and ranked by lane; waves and sub-tiles are ordered through LDS
+// counters), then writes the tile digit run by digit run, so consecutive
+// threads store to consecutive addresses of a run.
 __global__ __launch_bounds__(kSortThreads) void k_scatter(
     const uint32_t* __restrict__ kin, uint32_t* __restrict__ kout, size_t kstride,
     const uint32_t* __restrict__ vin, uint32_t* __restrict__ vout, size_t vstride,
     const uint32_t* __restrict__ d_n, uint32_t nstride, int shift, const uint32_t* __restrict__ hist,
     const uint32_t* __restrict__ digit_tot) {
     constexpr int NW = kSortThreads / kWave;
-    __shared__ uint32_t base[256];
-    __shared__ uint32_t run[256];
-    __shared__ uint32_t cnt[NW][256];
+    __shared__ uint32_t base[256];     // next global position of each digit for this block
+    __shared__ uint32_t lstart[256];   // first staged slot of each digit in the tile
+    __shared__ uint32_t lcount[256];   // keys of each digit in the tile
+    __shared__ uint32_t run[256];      // keys of each digit staged so far
+    __shared__ uint32_t cnt[NW][256];  // per-wave digit counts of the current sub-tile
     __shared__ uint32_t tmp[NW + 1];
+    __shared__ uint32_t sk[kSortTile];
+    __shared__ uint32_t sv[kSortTile];
     const uint32_t p = blockIdx.y;
     kin += p * kstride;
     kout += p * kstride;
@@ -85,54 +98,81 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(
     digit_tot += (size_t)p * 256;
     const int t = threadIdx.x;
     const int w = t / kWave;
-    // global start of each digit for this block
     uint32_t tot;
-    uint32_t dpre = block_exclusive_scan<kSortThreads>(digit_tot[t], tmp, &tot);
+    const uint32_t dpre = block_exclusive_scan<kSortThreads>(digit_tot[t], tmp, &tot);
     base[t] = dpre + hist[t * gridDim.x + blockIdx.x];
-    run[t] = 0;
 #pragma unroll
     for (int q = 0; q < NW; ++q) cnt[q][t] = 0;
-    __syncthreads();
     uint32_t lo, hi;
     block_range(d_n[p * nstride], blockIdx.x, gridDim.x, kSortThreads, &lo, &hi);
     const uint64_t below = lanemask_lt();
-    for (uint32_t i0 = lo; i0 < hi; i0 += kSortThreads) {
-        const uint32_t i = i0 + t;
-        const bool valid = i < hi;
-        const uint32_t k = valid ? kin[i] : 0u;
-        const uint32_t v = valid ? vin[i] : 0u;
-        const uint32_t d = (k >> shift) & 255u;
-        uint64_t peers = __ballot(valid);
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            const bool bit = (d >> b) & 1u;
-            const uint64_t m = __ballot(bit);
-            peers &= bit ? m : ~m;
-        }
-        const uint32_t rank = (uint32_t)__popcll(peers & below);
-        if (valid && rank == 0) cnt[w][d] = (uint32_t)__popcll(peers);
+    for (uint32_t i0 = lo; i0 < hi; i0 += kSortTile) {
+        const uint32_t m = (hi - i0) < (uint32_t)kSortTile ? (hi - i0) : (uint32_t)kSortTile;
+        lcount[t] = 0;
+        run[t] = 0;
         __syncthreads();
-        if (valid) {
-            uint32_t pre = run[d] + rank;
-            for (int q = 0; q < w; ++q) pre += cnt[q][d];
-            const uint32_t dst = base[d] + pre;
-            kout[dst] = k;
-            vout[dst] = v;
+        uint32_t k[kSortItems], v[kSortItems];
+#pragma unroll
+        for (int j = 0; j < kSortItems; ++j) {
+            const uint32_t idx = (uint32_t)(j * kSortThreads + t);
+            const bool valid = idx < m;
+            k[j] = valid ? kin[i0 + idx] : 0u;
+            v[j] = valid ? vin[i0 + idx] : 0u;
+            if (valid) atomicAdd(&lcount[(k[j] >> shift) & 255u], 1u);
         }
         __syncthreads();
-        uint32_t add = 0;
+        uint32_t ttot;
+        lstart[t] = block_exclusive_scan<kSortThreads>(lcount[t], tmp, &ttot);
+        __syncthreads();
+        // stable staging, sub-tile by sub-tile
 #pragma unroll
-        for (int q = 0; q < NW; ++q) {
-            add += cnt[q][t];
-            cnt[q][t] = 0;
+        for (int j = 0; j < kSortItems; ++j) {
+            if ((uint32_t)(j * kSortThreads) >= m) break;   // uniform over the block
+            const bool valid = (uint32_t)(j * kSortThreads + t) < m;
+            const uint32_t d = (k[j] >> shift) & 255u;
+            uint64_t peers = __ballot(valid);
+#pragma unroll
+            for (int bb = 0; bb < 8; ++bb) {
+                const bool bit = (d >> bb) & 1u;
+                const uint64_t mm = __ballot(bit);
+                peers &= bit ? mm : ~mm;
+            }
+            const uint32_t rank = (uint32_t)__popcll(peers & below);
+            if (valid && rank == 0) cnt[w][d] = (uint32_t)__popcll(peers);
+            __syncthreads();
+            if (valid) {
+                uint32_t pre = run[d] + rank;
+                for (int q = 0; q < w; ++q) pre += cnt[q][d];
+                const uint32_t slot = lstart[d] + pre;
+                sk[slot] = k[j];
+                sv[slot] = v[j];
+            }
+            __syncthreads();
+            uint32_t add = 0;
+#pragma unroll
+            for (int q = 0; q < NW; ++q) {
+                add += cnt[q][t];
+                cnt[q][t] = 0;
+            }
+            run[t] += add;
+            __syncthreads();
         }
-        run[t] += add;
+        // write the staged tile run by run
+        for (uint32_t e = (uint32_t)t; e < m; e += kSortThreads) {
+            const uint32_t key = sk[e];
+            const uint32_t d = (key >> shift) & 255u;
+            const uint32_t dst = base[d] + (e - lstart[d]);
+            kout[dst] = key;
+            vout[dst] = sv[e];
+        }
+        __syncthreads();
+        base[t] += lcount[t];
         __syncthreads();
     }
 }
 
 hipError_t launch_radix_sort(const SortBatch& b, int bits, hipStream_t st, bool* result_in_1, int* launches) {
-    int nblk = (int)((b.n_cap + 2047) / 2048);
+    int nblk = (int)((b.n_cap + kSortTile - 1) / kSortTile);
     if (nblk < 1) nblk = 1;
     if (nblk > kSortBlocks) nblk = kSortBlocks;
     const int passes = (bits + 7) / 8;

@@ -95,6 +95,50 @@ __global__ __launch_bounds__(256) void k_background(TileGeom g, const uint32_t* 
     }
 }
 
+// Same as k_background for images whose width is a multiple of 4: a thread
+// owns 4 consecutive pixels of a row (one tile) and writes 16-byte vectors.
+__global__ __launch_bounds__(256) void k_background4(TileGeom g, const uint32_t* __restrict__ ovf,
+                                                     const uint32_t* __restrict__ tstart,
+                                                     const uint32_t* __restrict__ tend,
+                                                     float* __restrict__ out_feat, float* __restrict__ out_alpha,
+                                                     float* __restrict__ out_tfinal, float* __restrict__ labels,
+                                                     int32_t* __restrict__ hit_count,
+                                                     unsigned long long* __restrict__ stats) {
+    const size_t HW = (size_t)g.H * g.W;
+    const size_t HW4 = HW / 4;
+    const uint64_t total = (uint64_t)g.Pb * g.V * HW4;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    unsigned long long nrays = 0;
+    const float4 zero = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+        const uint32_t pvi = (uint32_t)(i / HW4);
+        const size_t q = (size_t)(i % HW4);   // 4-pixel group of the map
+        const size_t pix = q * 4;
+        const int py = (int)(pix / g.W), px = (int)(pix % g.W);
+        const int pb = (int)pvi / g.V, v = (int)pvi % g.V;
+        if (g.debug_view >= 0 && v != g.debug_view) continue;
+        if (ovf[2 * ((size_t)pb * g.ngroups + v / g.Vg)]) continue;   // re-run later by the host
+        const size_t item = (size_t)pvi * g.TPV + (size_t)(py >> 3) * g.TX + (px >> 3);
+        if (tend[item] > tstart[item]) continue;                      // rendered by k_render
+        nrays += 4;
+        if (out_feat)
+            for (int c = 0; c < g.C; ++c)
+                reinterpret_cast<float4*>(out_feat + ((size_t)pvi * g.C + c) * HW)[q] = zero;
+        if (out_alpha) reinterpret_cast<float4*>(out_alpha + (size_t)pvi * HW)[q] = zero;
+        if (out_tfinal) reinterpret_cast<float4*>(out_tfinal + (size_t)pvi * HW)[q] = make_float4(1.0f, 1.0f, 1.0f, 1.0f);
+        if (labels) {
+            float4* l = reinterpret_cast<float4*>(labels + ((size_t)pvi * HW + pix) * 2);
+            l[0] = make_float4(1.0f, 0.0f, 1.0f, 0.0f);
+            l[1] = make_float4(1.0f, 0.0f, 1.0f, 0.0f);
+        }
+        if (hit_count) reinterpret_cast<int4*>(hit_count)[q] = make_int4(0, 0, 0, 0);
+    }
+    if (stats) {
+        const unsigned long long w = wave_sum(nrays);
+        if (lane_id() == 0 && w) atomicAdd(&stats[0], w);
+    }
+}
+
 hipError_t launch_tiles(const TileLaunch& t, hipStream_t st) {
     TileGeom g;
     g.Pb = t.Pb;
@@ -122,8 +166,22 @@ hipError_t launch_tiles(const TileLaunch& t, hipStream_t st) {
         uint64_t wblocks = (pixels + 255) / 256;
         if (wblocks > 16384) wblocks = 16384;
         if (wblocks < 1) wblocks = 1;
-        hipLaunchKernelGGL(k_background, dim3((unsigned)wblocks), dim3(256), 0, st, g, t.ovf, t.tile_start,
-                           t.tile_end, t.out_feat, t.out_alpha, t.out_tfinal, t.labels, t.hit_count, t.stats);
+        // 16-byte stores when rows hold whole 4-pixel groups (and the caller's maps are
+        // 16-byte aligned, as device allocations are)
+        const bool vec = (g.W % 4) == 0 &&
+                         ((reinterpret_cast<uintptr_t>(t.out_feat) | reinterpret_cast<uintptr_t>(t.out_alpha) |
+                           reinterpret_cast<uintptr_t>(t.out_tfinal) | reinterpret_cast<uintptr_t>(t.labels) |
+                           reinterpret_cast<uintptr_t>(t.hit_count)) & 15u) == 0;
+        if (vec) {
+            uint64_t vblocks = (pixels / 4 + 255) / 256;
+            if (vblocks > 16384) vblocks = 16384;
+            if (vblocks < 1) vblocks = 1;
+            hipLaunchKernelGGL(k_background4, dim3((unsigned)vblocks), dim3(256), 0, st, g, t.ovf, t.tile_start,
+                               t.tile_end, t.out_feat, t.out_alpha, t.out_tfinal, t.labels, t.hit_count, t.stats);
+        } else {
+            hipLaunchKernelGGL(k_background, dim3((unsigned)wblocks), dim3(256), 0, st, g, t.ovf, t.tile_start,
+                               t.tile_end, t.out_feat, t.out_alpha, t.out_tfinal, t.labels, t.hit_count, t.stats);
+        }
     }
     return hipGetLastError();
 }
