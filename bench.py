@@ -96,6 +96,7 @@ def parse():
                     help="proposal start margin in leaf edges (0: calibrated on held-out rays)")
     ap.add_argument("--f2-tau", type=float, default=-1.0)
     ap.add_argument("--err-poses", type=int, default=4, help="poses on which the proposal error is measured")
+    ap.add_argument("--no-forms", action="store_true", help="skip the BF16-storage and adjoint legs")
     return ap.parse_args()
 
 
@@ -161,6 +162,60 @@ def _timed(torch, fn, steps):
         fn()
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) / steps
+
+
+def bf16_leg(args, art, sg, torch):
+    """Precision form: BF16 leaf storage, FP32 geometry and accumulation, FP64
+    bone chain; 30 poses x 16 cameras at 1024^2 (its errors against the FP64
+    oracle are measured by the parity tests)."""
+    cfg = sg.CONFIGS["bf16"]
+    scene = sg.make_scene(cfg)
+    P, V, H, W = cfg.n_poses, cfg.n_views, cfg.height, cfg.width
+    r = art.Renderer(0)
+    r.set_scene(scene)
+    r.set_poses(*sg.make_poses(scene.J, P, cfg.pose_seed0))
+    r.set_cameras(*sg.make_cameras(scene, V, H, W), H, W)
+    sig = torch.from_numpy(scene.sigma).cuda().to(torch.bfloat16)
+    feat = torch.from_numpy(scene.feat).cuda().to(torch.bfloat16)
+    F = torch.empty((P, V, cfg.C, H, W), dtype=torch.float32, device="cuda")
+    A = torch.empty((P, V, H, W), dtype=torch.float32, device="cuda")
+    out = (F, A, None)
+    t = _timed(torch, lambda: r.render(sig, feat, args.lambda_th, fp32_geom=True, out=out), args.proposal_steps)
+    r.render(sig, feat, args.lambda_th, fp32_geom=True, out=out, timing=True)
+    tm = r.timing()
+    st = r.stats()
+    rays = P * V * H * W
+    per_launch = algorithmic_bytes(st, cfg.C, 2, with_tfinal=False) / max(tm["n_render"], 1)
+    avg = tm["render"] / max(tm["n_render"], 1) / 1e3
+    del F, A, out
+    return {"workload": f"precision form: BF16 storage, FP32 geometry, {P} poses x {V} cameras at {H}x{W} ({rays} rays)",
+            "mrays_s": round(rays / t / 1e6, 2), "ms_per_step": round(t * 1e3, 3),
+            "render_ms": round(tm["render"], 3),
+            "render_hbm_frac": round(per_launch / avg / 1e9 / HBM_PEAK_GBS, 4),
+            "algorithmic_bytes_per_sample": 2 * (cfg.C + 1) + 4}
+
+
+def adjoint_leg(args, art, sg, torch):
+    """Differentiation form: L = 1/2 |F - F*|^2 over 4 cameras at 512^2, one
+    pose; the adjoint kernel re-traverses every ray (per-ray recomputation)."""
+    cfg = sg.CONFIGS["grad"]
+    scene = sg.make_scene(cfg)
+    P, V, H, W = cfg.n_poses, cfg.n_views, cfg.height, cfg.width
+    r = art.Renderer(0)
+    r.set_scene(scene)
+    r.set_poses(*sg.make_poses(scene.J, P, cfg.pose_seed0))
+    r.set_cameras(*sg.make_cameras(scene, V, H, W), H, W)
+    sig = torch.from_numpy(scene.sigma).cuda()
+    feat = torch.from_numpy(scene.feat).cuda()
+    tgt = torch.from_numpy(sg.make_targets(P, V, cfg.C, H, W, cfg.target_seed)).cuda()
+    F, A, T = r.render(sig, feat, args.lambda_th)
+    dF = (F - tgt).contiguous()
+    ds = torch.zeros_like(sig)
+    df = torch.zeros_like(feat)
+    t = _timed(torch, lambda: r.backward(sig, feat, F, T, dF, d_sigma=ds, d_feat=df), args.proposal_steps)
+    rays = P * V * H * W
+    return {"workload": f"adjoint: {P} pose x {V} cameras at {H}x{W} ({rays} rays), L2 loss to seeded targets",
+            "mrays_s": round(rays / t / 1e6, 2), "ms_per_call": round(t * 1e3, 3)}
 
 
 def proposal_leg(args, art, sg, torch):
@@ -369,10 +424,16 @@ def main():
         "partition_steps_per_pose": st["steps"] // P,
         "launches_per_step": st["launches"],
     }
+    del Fm, Am, Tm, out
+    torch.cuda.empty_cache()
+    if not args.no_forms:
+        print("[bench] BF16 precision form and adjoint", file=sys.stderr, flush=True)
+        line["bf16_form"] = bf16_leg(args, art, sg, torch)
+        torch.cuda.empty_cache()
+        line["adjoint_form"] = adjoint_leg(args, art, sg, torch)
+        torch.cuda.empty_cache()
     if not args.no_proposal:
         print("[bench] learned proposal vs plain (proposal workload)", file=sys.stderr, flush=True)
-        del Fm, Am, Tm, out
-        torch.cuda.empty_cache()
         line["proposal"] = proposal_leg(args, art, sg, torch)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)

@@ -154,7 +154,7 @@ hipError_t launch_tiles(const TileLaunch& t, hipStream_t st) {
     g.tiles_pow4 = t.tiles_pow4;
     g.debug_view = t.debug_view;
     const uint64_t total = (uint64_t)g.Pb * g.V * g.tiles_pow4;
-    hipError_t e = launch_fill_u32(t.counters, 0u, 2, st);   // n_items, queue
+    hipError_t e = launch_fill_u32(t.counters, 0u, 16, st);   // n_items, queue heads
     if (e != hipSuccess) return e;
     uint64_t blocks = (total + 255) / 256;
     if (blocks > 65536) blocks = 65536;

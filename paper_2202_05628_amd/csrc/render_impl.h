@@ -55,6 +55,10 @@ constexpr int kStepsPerRound = ART_STEPS_PER_ROUND;
 #endif
 // 1: a ray leaves a brick when its cell does, and continues into the next
 // listed brick without a ray/box test when its cell lies in it
+// parts of the tile work list
+#ifndef ART_XCD_QUEUES
+#define ART_XCD_QUEUES 1
+#endif
 #ifndef ART_CELL_EXIT
 #define ART_CELL_EXIT 1
 #endif
@@ -65,7 +69,7 @@ struct RArgs {
     int Vg, ngroups;                       // view groups of the tile lists
     const uint32_t* items;                 // compacted non-empty tiles: pvi * TPV + ty * TX + tx
     const uint32_t* n_items;               // device count of items
-    uint32_t* queue;                       // next item to take (zeroed before the launch)
+    uint32_t* queue;                       // [8] next item of each part of the list (zeroed before the launch)
     uint32_t ncap;                         // per-pose capacity of the octree arrays (leaves)
     uint32_t pair_cap;                     // per (pose, group) capacity of the tile lists
     float lambda;
@@ -738,13 +742,27 @@ void k_render(RArgs a) {
     __shared__ uint32_t s_coord[1][kStage];
     const int lane = threadIdx.x & 63;
     const uint32_t n_items = *a.n_items;
-    while (true) {
-        uint32_t idx = 0;
-        if (lane == 0) idx = atomicAdd(a.queue, 1u);
-        idx = (uint32_t)__shfl((int)idx, 0, kWave);
-        if (idx >= n_items) break;
-        render_tile<C, ST, R, MODE>(a, a.items[idx], idx, lane, s_mask, s_pref, s_row, s_coord);
-        wave_sync();
+    // The work list may be cut into kQueues contiguous parts (neighbouring
+    // tiles, which read the same bricks and FLUT rows, stay in one part);
+    // workgroups are dispatched to the XCDs in turn, so a workgroup starts on
+    // part blockIdx.x mod kQueues - the waves of one XCD then share its L2 -
+    // and helps the other parts once its own is drained.  (One part per XCD
+    // raised the L2 hit rate from 55 % to 58 % but the kernel ran 4 % longer,
+    // so the default is a single queue.)
+    constexpr uint32_t kQueues = ART_XCD_QUEUES;
+    const uint32_t home = blockIdx.x % kQueues;
+    for (uint32_t k = 0; k < kQueues; ++k) {
+        const uint32_t qi = (home + k) % kQueues;
+        const uint32_t beg = (uint32_t)((uint64_t)n_items * qi / kQueues);
+        const uint32_t end = (uint32_t)((uint64_t)n_items * (qi + 1) / kQueues);
+        while (true) {
+            uint32_t idx = 0;
+            if (lane == 0) idx = atomicAdd(&a.queue[qi], 1u);
+            idx = beg + (uint32_t)__shfl((int)idx, 0, kWave);
+            if (idx >= end) break;
+            render_tile<C, ST, R, MODE>(a, a.items[idx], idx, lane, s_mask, s_pref, s_row, s_coord);
+            wave_sync();
+        }
     }
 }
 
