@@ -35,6 +35,15 @@
 namespace art {
 
 constexpr int kStage = 64;
+// Row pitch of the staged mask words and prefixes: with a pitch of 64 words
+// every word of one brick falls into the same LDS bank, so lanes of a tile that
+// look up different words of one brick serialise; one extra word per row puts
+// word w of brick j into bank (w + j) mod 32.
+#ifndef ART_LDS_PAD
+#define ART_LDS_PAD 1
+#endif
+constexpr int kMaskPitch = kStage + ART_LDS_PAD;
+constexpr int kPrefPitch = kStage + 2 * ART_LDS_PAD;
 // Partition steps a lane may take per round while looking for its next
 // occupied segment.  Bounding it keeps one lane that crosses empty cells from
 // stalling the whole wave for many steps per composited sample.
@@ -224,8 +233,8 @@ __device__ inline void root_span(const R* d, const R* q, const R* inv, R h, int 
 // Render one non-empty tile (item = pose-in-launch * V + view, tile index).
 template <int C, int ST, typename R, int MODE>
 __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, int lane,
-                                   uint32_t (*s_mask)[16][kStage],
-                                   uint16_t (*s_pref)[16][kStage], uint32_t (*s_row)[kStage],
+                                   uint32_t (*s_mask)[16][kMaskPitch],
+                                   uint16_t (*s_pref)[16][kPrefPitch], uint32_t (*s_row)[kStage],
                                    uint32_t (*s_coord)[kStage]) {
     constexpr int wv = 0;
     const int pvi = (int)(item / (uint32_t)a.TPV);   // pose-in-launch * V + view
@@ -736,8 +745,8 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
 template <int C, int ST, typename R, int MODE>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MODE == 1 ? 1 : ART_RENDER_WAVES_PER_EU)))
 void k_render(RArgs a) {
-    __shared__ uint32_t s_mask[1][16][kStage];
-    __shared__ uint16_t s_pref[1][16][kStage];
+    __shared__ uint32_t s_mask[1][16][kMaskPitch];
+    __shared__ uint16_t s_pref[1][16][kPrefPitch];
     __shared__ uint32_t s_row[1][kStage];
     __shared__ uint32_t s_coord[1][kStage];
     const int lane = threadIdx.x & 63;
