@@ -64,6 +64,14 @@ constexpr int kStepsPerRound = ART_STEPS_PER_ROUND;
 #endif
 // 1: a ray leaves a brick when its cell does, and continues into the next
 // listed brick without a ray/box test when its cell lies in it
+// 1: an empty cell whose 2x2x2 block is empty jumps to the block's exit
+#ifndef ART_SKIP_EMPTY
+#define ART_SKIP_EMPTY 0
+#endif
+// 1: branch-free compositing step in the forward modes
+#ifndef ART_BRANCHLESS
+#define ART_BRANCHLESS 0
+#endif
 // parts of the tile work list
 #ifndef ART_XCD_QUEUES
 #define ART_XCD_QUEUES 1
@@ -593,13 +601,35 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
                         }
                         hasB = true;
                     }
+#if ART_SKIP_EMPTY
+                    else if (((mw >> (bit & ~7u)) & 0xFFu) == 0u) {
+                        // The cell's whole 2x2x2 block (8 consecutive mask bits in
+                        // Morton order) is empty: jump to the block's exit face.  The
+                        // exit is a lattice plane crossing computed by the same formula
+                        // as the cell-by-cell steps, so the partition after the jump
+                        // is unchanged; only empty segments are skipped.
+                        const int lc[3] = {l0, l1, l2};
+                        R tx = tb;
+#pragma unroll
+                        for (int i = 0; i < 3; ++i) {
+                            if (d[i] == (R)0) continue;
+                            const int pos = d[i] > (R)0 ? 1 : 0;
+                            const int ke = lo3[i] - pos + (lc[i] & ~1) + 2 * pos;
+                            tx = fmin(tx, tplane<R>(ke, h, q[i], inv[i]));
+                        }
+                        s1 = fmax(tx, s1);
+                    }
+#endif
                 }
 #pragma unroll
                 for (int i = 0; i < 3; ++i) {
-                    if (tc[i] <= s1) {
-                        const int st = d[i] > (R)0 ? 1 : -1;
-                        kp[i] += st;
-                        tc[i] = tplane<R>(kp[i], h, q[i], inv[i]);
+#pragma unroll
+                    for (int rep = 0; rep < (ART_SKIP_EMPTY ? 2 : 1); ++rep) {
+                        if (tc[i] <= s1) {
+                            const int st = d[i] > (R)0 ? 1 : -1;
+                            kp[i] += st;
+                            tc[i] = tplane<R>(kp[i], h, q[i], inv[i]);
+                        }
                     }
                 }
                 s = s1;
@@ -616,6 +646,24 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
 #endif
             }
             // (2) composite the current sample (Eq. 5-6, exclusive transmittance)
+#if ART_BRANCHLESS
+            // forward without hit lists: every lane runs the update, a lane without
+            // a sample with alpha = 0 (w = 0 leaves F, A and T unchanged exactly)
+            if constexpr (MODE == 0 || MODE == 4) {
+                const bool doA = hasA && active;
+                const float al = sample_alpha(doA ? sgA * dlA : 0.0f);
+                const float w = T * al;
+#pragma unroll
+                for (int c = 0; c < C; ++c) F[c] = __fmaf_rn(w, fA[c], F[c]);
+                Aacc += w;
+                T = __fmaf_rn(-T, al, T);
+                nsamp += doA ? 1 : 0;
+                if (doA && T < a.lambda) {
+                    active = false;
+                    inb = false;
+                }
+            } else
+#endif
             if (hasA && active) {
                 const float tau = sgA * dlA;
                 const float al = sample_alpha(tau);
@@ -655,25 +703,24 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
                 }
             }
 #if ART_ID_PREFETCH
-            // (3) the sample whose winner id has arrived issues its FLUT gather
+            // (3) the sample whose winner id has arrived issues its FLUT gather,
+            // (4) the new sample fetches its collision winner's id.  Both loads
+            // are issued by every lane every round (a lane without a sample
+            // reads row 0), so the wait before compositing only has to cover the
+            // FLUT row and leaves the winner-id load in flight.
             hasA = hasI && active;
-            if (hasA) {
-                dlA = dlI;
-                dxA = dxI;
-                sA0 = sI0;
-                sA1 = sI1;
-                winA = winI;
-                load_sample<C, ST>(a.sigma, a.feat, winA, sgA, fA);
-            }
-            // (4) the new sample fetches its collision winner's id
+            dlA = dlI;
+            dxA = dxI;
+            sA0 = sI0;
+            sA1 = sI1;
+            winA = hasA ? winI : 0u;
+            load_sample<C, ST>(a.sigma, a.feat, winA, sgA, fA);
             hasI = hasB && active;
-            if (hasI) {
-                dlI = dlB;
-                dxI = dxB;
-                sI0 = sB0;
-                sI1 = sB1;
-                winI = occ_win[rowB];
-            }
+            dlI = dlB;
+            dxI = dxB;
+            sI0 = sB0;
+            sI1 = sB1;
+            winI = occ_win[hasI ? rowB : 0u];
 #else
             // (3) issue the next sample's gather into the freed registers
             hasA = hasB && active;
