@@ -73,7 +73,7 @@ def _load():
     lib.oracle_render.restype = ctypes.c_int
     lib.oracle_render.argtypes = [ctypes.c_int64, P, P, ctypes.c_int, ctypes.c_double,
                                   ctypes.c_int64, P, P, ctypes.c_int, P, P, ctypes.c_double,
-                                  P, P, P, P, P, P, P, ctypes.c_int, P, P, P, ctypes.c_int]
+                                  P, P, P, P, P, P, P, ctypes.c_int, P, P, P, ctypes.c_double, P, ctypes.c_int]
     lib.oracle_backward.restype = ctypes.c_int
     lib.oracle_backward.argtypes = [ctypes.c_int64, P, P, ctypes.c_int, ctypes.c_double,
                                     ctypes.c_int64, P, P, ctypes.c_int, P, P, ctypes.c_double,
@@ -290,14 +290,16 @@ def camera_rays(K: np.ndarray, c2w: np.ndarray, H: int, W: int):
 
 def render(o: np.ndarray, d: np.ndarray, depth: int, occ_key: np.ndarray, occ_leaf: np.ndarray,
            sigma: np.ndarray, feat: np.ndarray, lambda_th: float, max_hits: int = 0,
-           n_threads: int = 0) -> Dict[str, np.ndarray]:
+           n_threads: int = 0, depth_sigma: float = 0.0) -> Dict[str, np.ndarray]:
     """Eq. 5-6 per ray over the exact voxel chords (see ray_oracle.c).
 
     o, d: [n][3] float64 rays (|d| = 1).  Returns F [n][C], A [n], T [n],
     n_comp [n], n_hit [n], min_gap [n], min_tgap [n] and, when max_hits > 0,
     hit_leaf/hit_delta [n][max_hits] of the composited samples, and seg [n][4]:
     t_a, t_b of the clipped ray (NaN on a miss) and the entry t of the first /
-    exit t of the last composited sample (NaN without samples)."""
+    exit t of the last composited sample (NaN without samples), and dist [n]:
+    the entry t of the first composited sample with density > depth_sigma
+    (+inf without one) - the depth buffer of the hybrid rendering (Section 5)."""
     lib = _load()
     o = np.ascontiguousarray(o, dtype=np.float64).reshape(-1, 3)
     d = np.ascontiguousarray(d, dtype=np.float64).reshape(-1, 3)
@@ -312,7 +314,7 @@ def render(o: np.ndarray, d: np.ndarray, depth: int, occ_key: np.ndarray, occ_le
     out = {
         "F": np.zeros((n, C)), "A": np.zeros(n), "T": np.ones(n),
         "n_comp": np.zeros(n, dtype=np.int32), "n_hit": np.zeros(n, dtype=np.int32),
-        "min_gap": np.zeros(n), "min_tgap": np.zeros(n), "seg": np.zeros((n, 4)),
+        "min_gap": np.zeros(n), "min_tgap": np.zeros(n), "seg": np.zeros((n, 4)), "dist": np.zeros(n),
     }
     hl = hd = None
     if max_hits > 0:
@@ -323,7 +325,8 @@ def render(o: np.ndarray, d: np.ndarray, depth: int, occ_key: np.ndarray, occ_le
                            C, _ptr(sigma), _ptr(feat), float(lambda_th),
                            _ptr(out["F"]), _ptr(out["A"]), _ptr(out["T"]), _ptr(out["n_comp"]),
                            _ptr(out["n_hit"]), _ptr(out["min_gap"]), _ptr(out["min_tgap"]),
-                           int(max_hits), _ptr(hl), _ptr(hd), _ptr(out["seg"]), int(n_threads))
+                           int(max_hits), _ptr(hl), _ptr(hd), _ptr(out["seg"]), float(depth_sigma),
+                           _ptr(out["dist"]), int(n_threads))
     if rc != 0:
         raise MemoryError("oracle_render failed")
     return out

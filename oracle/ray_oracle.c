@@ -154,6 +154,10 @@ static int64_t max_points(int G) { return 3 * (int64_t)(G + 1) + 2; }
  * t_a, t_b of the clipped ray (NaN on a miss), the entry t of the first
  * composited sample and the exit t of the last one (NaN without samples): the
  * interval a ray-interval proposal has to cover.
+ * Optional depth [n] (may be NULL) receives the depth-buffer value of the
+ * hybrid rendering of Section 5 ("Hybrid Rendering"): the distance t along
+ * the unit ray at which it enters the first voxel whose density exceeds
+ * depth_sigma, among the composited samples; +inf when there is none.
  * Returns 0, or -1 on allocation failure.
  */
 int oracle_render(int64_t n, const double* o, const double* d, int G, double h,
@@ -162,7 +166,7 @@ int oracle_render(int64_t n, const double* o, const double* d, int G, double h,
                   double* F, double* A, double* Tfin, int32_t* n_comp, int32_t* n_hit,
                   double* min_gap, double* min_tgap,
                   int max_hits, int64_t* hit_leaf, double* hit_delta, double* seg,
-                  int n_threads) {
+                  double depth_sigma, double* depth, int n_threads) {
     int failed = 0;
     int64_t cap = max_points(G);
 #ifdef _OPENMP
@@ -185,13 +189,14 @@ int oracle_render(int64_t n, const double* o, const double* d, int G, double h,
                 double gap, ta, tb;
                 int64_t ns = ray_samples(o + 3 * r, d + 3 * r, G, h, M, occ_key, occ_leaf,
                                          smp, cap, pts, &gap, &ta, &tb);
-                double T = 1.0, acc = 0.0, tg = INFINITY;
+                double T = 1.0, acc = 0.0, tg = INFINITY, dep = INFINITY;
                 double* Fr = F + (size_t)r * C;
                 for (int c = 0; c < C; ++c) Fr[c] = 0.0;
                 int64_t used = 0;
                 for (int64_t i = 0; i < ns; ++i) {
                     const double s = sigma[smp[i].leaf];
                     const double* f = feat + (size_t)smp[i].leaf * C;
+                    if (dep == INFINITY && s > depth_sigma) dep = smp[i].t0;
                     double tau = s * smp[i].delta;
                     double alpha = -expm1(-tau);
                     double w = T * alpha;
@@ -211,6 +216,7 @@ int oracle_render(int64_t n, const double* o, const double* d, int G, double h,
                 }
                 A[r] = acc;
                 Tfin[r] = T;
+                if (depth) depth[r] = dep;
                 if (seg) {
                     double* sg = seg + 4 * (size_t)r;
                     sg[0] = ta;
