@@ -195,6 +195,34 @@ def bf16_leg(args, art, sg, torch):
             "algorithmic_bytes_per_sample": 2 * (cfg.C + 1) + 4}
 
 
+def depth_leg(args, r, sig, feat, out, fp32_geom, torch, C, es, rays):
+    """Depth buffer of hybrid rendering on the main workload: the forward maps
+    plus, per ray, the distance to the first composited sample with density
+    above the median leaf density; timed against the plain forward."""
+    F, A, T = out
+    D = torch.empty_like(A)
+    th = float(sig.float().median())
+    outd = (F, A, T, D)
+    t_plain = _timed(torch, lambda: r.render(sig, feat, args.lambda_th, fp32_geom=fp32_geom, out=out),
+                     args.proposal_steps)
+    t_depth = _timed(torch, lambda: r.render_depth(sig, feat, th, args.lambda_th, fp32_geom=fp32_geom, out=outd),
+                     args.proposal_steps)
+    r.render_depth(sig, feat, th, args.lambda_th, fp32_geom=fp32_geom, out=outd, timing=True)
+    tm = r.timing()
+    st = r.stats()
+    per_launch = (algorithmic_bytes(st, C, es) + 4 * st["tile_rays"]) / max(tm["n_render"], 1)
+    avg = tm["render"] / max(tm["n_render"], 1) / 1e3
+    finite = int(torch.isfinite(D).sum())
+    del D, outd
+    return {"workload": "depth buffer on the main workload (density threshold = median leaf density)",
+            "mrays_s": round(rays / t_depth / 1e6, 2), "ms_per_step": round(t_depth * 1e3, 3),
+            "plain_ms_per_step": round(t_plain * 1e3, 3),
+            "overhead": round(t_depth / t_plain - 1.0, 4),
+            "render_ms": round(tm["render"], 3),
+            "render_hbm_frac": round(per_launch / avg / 1e9 / HBM_PEAK_GBS, 4),
+            "rays_with_depth": finite}
+
+
 def adjoint_leg(args, art, sg, torch):
     """Differentiation form: L = 1/2 |F - F*|^2 over 4 cameras at 512^2, one
     pose; the adjoint kernel re-traverses every ray (per-ray recomputation)."""
@@ -424,6 +452,9 @@ def main():
         "partition_steps_per_pose": st["steps"] // P,
         "launches_per_step": st["launches"],
     }
+    if not args.no_forms:
+        print("[bench] depth buffer", file=sys.stderr, flush=True)
+        line["depth_form"] = depth_leg(args, r, sig, feat, out, fp32_geom, torch, cfg.C, es, rays_per_step)
     del Fm, Am, Tm, out
     torch.cuda.empty_cache()
     if not args.no_forms:

@@ -222,6 +222,21 @@ art_status art_render_proposal(art_ctx* ctx, int C, art_dtype dtype, const void*
                                float f2_tau, float* out_feat, float* out_alpha, float* out_tfinal);
 
 /*
+ * Forward render (as art_render) that also writes the depth buffer of the
+ * hybrid rendering of Section 5: per pixel, the distance along the ray (unit
+ * direction, from the camera centre) at which it enters the first composited
+ * sample whose canonical density, as stored, exceeds depth_sigma (strictly).
+ * Only samples composited before the early stop count.  Pixels with no such
+ * sample, including every pixel of an empty tile, get +inf.  out_depth:
+ * device float32 [P][V][H][W], written in full.  The feature, opacity and
+ * transmittance maps are those of art_render, bit for bit.
+ * Errors: as art_render; ART_EINVAL for a NULL out_depth or a NaN depth_sigma.
+ */
+art_status art_render_depth(art_ctx* ctx, int C, art_dtype dtype, const void* sigma, const void* feat,
+                            float lambda_th, unsigned flags, float depth_sigma, float* out_feat, float* out_alpha,
+                            float* out_tfinal, float* out_depth);
+
+/*
  * The proposal network: x = [o (3), d (3), pose code (6 J)] -> 64 -> 64 -> 64
  * (ReLU) -> 2 (sigmoid) = (u_near, u_far), where (o, d) is the ray (origin,
  * unit direction, FP32) and the pose code holds, per bone j, the first and

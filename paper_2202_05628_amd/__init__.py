@@ -159,6 +159,27 @@ class Renderer:
                     "art_render")
         return F, A, T
 
+    def render_depth(self, sigma, feat, depth_sigma: float, lambda_th: float = LAMBDA_TH, fp32_geom: bool = False,
+                     timing: bool = False, out=None, want_tfinal: bool = True):
+        """render() plus the depth buffer [P][V][H][W]: distance along the ray to
+        the entry of the first composited sample with density > depth_sigma
+        (+inf if none)."""
+        torch = self._torch
+        C, dtype = self._flut(sigma, feat)
+        dev = sigma.device
+        if out is None:
+            F = torch.empty((self.P, self.V, C, self.H, self.W), dtype=torch.float32, device=dev)
+            A = torch.empty((self.P, self.V, self.H, self.W), dtype=torch.float32, device=dev)
+            T = torch.empty_like(A) if want_tfinal else None
+            D = torch.empty_like(A)
+        else:
+            F, A, T, D = out
+        self._check(self.lib.art_render_depth(self._h, C, dtype, _tptr(sigma), _tptr(feat), float(lambda_th),
+                                              self._flags(fp32_geom, timing), float(depth_sigma), _tptr(F), _tptr(A),
+                                              _tptr(T), _tptr(D)),
+                    "art_render_depth")
+        return F, A, T, D
+
     def proposal_labels(self, sigma, feat, lambda_th: float = LAMBDA_TH, fp32_geom: bool = False,
                         timing: bool = False, out=None):
         """Interval labels [P][V][H][W][2] = (u_near, u_far) of every ray from the

@@ -42,6 +42,7 @@ SIGNATURES = [
     ("art_backward", _I, [_P, _I, _I, _P, _P, _F, _U, _P, _P, _P, _P, _P, _P]),
     ("art_proposal_labels", _I, [_P, _I, _I, _P, _P, _F, _U, _P]),
     ("art_render_proposal", _I, [_P, _I, _I, _P, _P, _F, _U, _P, _F, _F, _P, _P, _P]),
+    ("art_render_depth", _I, [_P, _I, _I, _P, _P, _F, _U, _F, _P, _P, _P, _P]),
     ("art_proposal_param_count", _L, [_I]),
     ("art_proposal_set_weights", _I, [_P, _L, _P]),
     ("art_proposal_get_weights", _I, [_P, _L, _P]),

@@ -252,6 +252,9 @@ struct PassOut {
     float margin = 0.0f;
     float f2_tau = -1.0f;
     bool near_only = false;
+    // depth buffer (mode 5)
+    float* out_depth = nullptr;
+    float depth_sigma = 0.0f;
     // debug
     int max_hits = 0;
     int debug_view = 0;
@@ -377,6 +380,8 @@ art_status run_batch(art_ctx* ctx, const CallPlan& pl, int mode, float lambda, c
     r.margin = o.margin;
     r.f2_tau = o.f2_tau;
     r.near_only = o.near_only;
+    if (o.out_depth) r.out_depth = o.out_depth + m0 * HW;
+    r.depth_sigma = o.depth_sigma;
     r.max_hits = o.max_hits;
     r.debug_view = o.debug_view;
     r.hit_leaf = o.hit_leaf;
@@ -403,6 +408,7 @@ art_status run_batch(art_ctx* ctx, const CallPlan& pl, int mode, float lambda, c
     tl.out_alpha = r.out_alpha;
     tl.out_tfinal = r.out_tfinal;
     tl.labels = r.labels;
+    tl.out_depth = r.out_depth;
     tl.hit_count = r.hit_count;
     tl.stats = s.stats.as<unsigned long long>();
     ART_TRY_HIP(launch_tiles(tl, st), "tile compaction");
@@ -594,6 +600,8 @@ hipError_t launch_render(const RenderLaunch& r, hipStream_t st) {
     a.margin = r.margin;
     a.f2_tau = r.f2_tau;
     a.near_only = r.near_only ? 1 : 0;
+    a.out_depth = r.out_depth;
+    a.depth_sigma = r.depth_sigma;
     a.max_hits = r.max_hits;
     a.debug_view = r.debug_view;
     a.hit_leaf = r.hit_leaf;
@@ -869,6 +877,22 @@ art_status art_backward(art_ctx* ctx, int C, art_dtype dtype, const void* sigma,
     o.d_sigma = d_sigma;
     o.d_leaf_feat = d_leaf_feat;
     return render_call(ctx, C, dtype, sigma, feat, lambda_th, flags, 1, o, 0, ctx->P);
+}
+
+art_status art_render_depth(art_ctx* ctx, int C, art_dtype dtype, const void* sigma, const void* feat,
+                            float lambda_th, unsigned flags, float depth_sigma, float* out_feat, float* out_alpha,
+                            float* out_tfinal, float* out_depth) {
+    if (!ctx) return ART_EINVAL;
+    if (!out_feat || !out_alpha || !out_depth) return fail(ctx, ART_EINVAL, "out_feat / out_alpha / out_depth is NULL");
+    if (!(depth_sigma == depth_sigma)) return fail(ctx, ART_EINVAL, "depth_sigma is NaN");
+    DeviceGuard g(ctx->device);
+    PassOut o;
+    o.out_feat = out_feat;
+    o.out_alpha = out_alpha;
+    o.out_tfinal = out_tfinal;
+    o.out_depth = out_depth;
+    o.depth_sigma = depth_sigma;
+    return render_call(ctx, C, dtype, sigma, feat, lambda_th, flags, 5, o, 0, ctx->P);
 }
 
 art_status art_proposal_labels(art_ctx* ctx, int C, art_dtype dtype, const void* sigma, const void* feat,

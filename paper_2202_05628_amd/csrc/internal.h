@@ -215,7 +215,7 @@ __global__ void k_pairs(const PoseCounters* __restrict__ c, unsigned long long* 
 struct RenderLaunch {
     int C, storage;
     bool fp32;
-    int mode;            // 0 forward, 1 backward, 2 debug hit lists, 3 labels, 4 proposal
+    int mode;            // 0 forward, 1 backward, 2 debug hit lists, 3 labels, 4 proposal, 5 forward + depth
     int depth;
     int Pb, V, H, W;     // poses in the launch (slots 0..Pb-1), views, image
     int Vg, ngroups;     // view groups of the tile lists
@@ -241,6 +241,8 @@ struct RenderLaunch {
     float margin;            // ray-parameter units
     float f2_tau;
     bool near_only;          // mode 4: the interval ends at t_b
+    float* out_depth;        // [Pb][V][H][W] (mode 5)
+    float depth_sigma;       // density threshold of the depth buffer
     int max_hits;
     int debug_view;
     int32_t* hit_leaf;
@@ -264,6 +266,7 @@ struct TileLaunch {
     float* out_alpha;
     float* out_tfinal;
     float* labels;             // interval labels (label pass)
+    float* out_depth;          // depth buffer (+inf on empty tiles)
     int32_t* hit_count;
     unsigned long long* stats;
 };

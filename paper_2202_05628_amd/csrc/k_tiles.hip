@@ -66,7 +66,7 @@ __global__ __launch_bounds__(256) void k_background(TileGeom g, const uint32_t* 
                                                     const uint32_t* __restrict__ tend,
                                                     float* __restrict__ out_feat, float* __restrict__ out_alpha,
                                                     float* __restrict__ out_tfinal, float* __restrict__ labels,
-                                                    int32_t* __restrict__ hit_count,
+                                                    float* __restrict__ out_depth, int32_t* __restrict__ hit_count,
                                                     unsigned long long* __restrict__ stats) {
     const size_t HW = (size_t)g.H * g.W;
     const uint64_t total = (uint64_t)g.Pb * g.V * HW;
@@ -87,6 +87,7 @@ __global__ __launch_bounds__(256) void k_background(TileGeom g, const uint32_t* 
         if (out_alpha) out_alpha[(size_t)pvi * HW + pix] = 0.0f;
         if (out_tfinal) out_tfinal[(size_t)pvi * HW + pix] = 1.0f;
         if (labels) reinterpret_cast<float2*>(labels)[(size_t)pvi * HW + pix] = make_float2(1.0f, 0.0f);
+        if (out_depth) out_depth[(size_t)pvi * HW + pix] = INFINITY;
         if (hit_count) hit_count[pix] = 0;
     }
     if (stats) {
@@ -102,7 +103,7 @@ __global__ __launch_bounds__(256) void k_background4(TileGeom g, const uint32_t*
                                                      const uint32_t* __restrict__ tend,
                                                      float* __restrict__ out_feat, float* __restrict__ out_alpha,
                                                      float* __restrict__ out_tfinal, float* __restrict__ labels,
-                                                     int32_t* __restrict__ hit_count,
+                                                     float* __restrict__ out_depth, int32_t* __restrict__ hit_count,
                                                      unsigned long long* __restrict__ stats) {
     const size_t HW = (size_t)g.H * g.W;
     const size_t HW4 = HW / 4;
@@ -131,6 +132,8 @@ __global__ __launch_bounds__(256) void k_background4(TileGeom g, const uint32_t*
             l[0] = make_float4(1.0f, 0.0f, 1.0f, 0.0f);
             l[1] = make_float4(1.0f, 0.0f, 1.0f, 0.0f);
         }
+        if (out_depth)
+            reinterpret_cast<float4*>(out_depth + (size_t)pvi * HW)[q] = make_float4(INFINITY, INFINITY, INFINITY, INFINITY);
         if (hit_count) reinterpret_cast<int4*>(hit_count)[q] = make_int4(0, 0, 0, 0);
     }
     if (stats) {
@@ -171,16 +174,17 @@ hipError_t launch_tiles(const TileLaunch& t, hipStream_t st) {
         const bool vec = (g.W % 4) == 0 &&
                          ((reinterpret_cast<uintptr_t>(t.out_feat) | reinterpret_cast<uintptr_t>(t.out_alpha) |
                            reinterpret_cast<uintptr_t>(t.out_tfinal) | reinterpret_cast<uintptr_t>(t.labels) |
-                           reinterpret_cast<uintptr_t>(t.hit_count)) & 15u) == 0;
+                           reinterpret_cast<uintptr_t>(t.out_depth) | reinterpret_cast<uintptr_t>(t.hit_count)) &
+                          15u) == 0;
         if (vec) {
             uint64_t vblocks = (pixels / 4 + 255) / 256;
             if (vblocks > 16384) vblocks = 16384;
             if (vblocks < 1) vblocks = 1;
             hipLaunchKernelGGL(k_background4, dim3((unsigned)vblocks), dim3(256), 0, st, g, t.ovf, t.tile_start,
-                               t.tile_end, t.out_feat, t.out_alpha, t.out_tfinal, t.labels, t.hit_count, t.stats);
+                               t.tile_end, t.out_feat, t.out_alpha, t.out_tfinal, t.labels, t.out_depth, t.hit_count, t.stats);
         } else {
             hipLaunchKernelGGL(k_background, dim3((unsigned)wblocks), dim3(256), 0, st, g, t.ovf, t.tile_start,
-                               t.tile_end, t.out_feat, t.out_alpha, t.out_tfinal, t.labels, t.hit_count, t.stats);
+                               t.tile_end, t.out_feat, t.out_alpha, t.out_tfinal, t.labels, t.out_depth, t.hit_count, t.stats);
         }
     }
     return hipGetLastError();

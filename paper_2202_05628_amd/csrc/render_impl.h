@@ -117,6 +117,8 @@ struct RArgs {
     float margin;                          // proposal margin (ray-parameter units)
     float f2_tau;                          // F2 threshold on T (< 0: off)
     int near_only;                         // MODE 4: only u_near is used (interval ends at t_b)
+    float* out_depth;                      // [Pb][V][H][W] depth buffer (MODE 5)
+    float depth_sigma;                     // MODE 5: density threshold of the depth buffer
     int max_hits;
     int debug_view;                        // view whose hit lists are recorded (MODE 2)
     int32_t* hit_leaf;                     // [H*W][max_hits] (single pose / view)
@@ -234,7 +236,10 @@ __device__ inline void root_span(const R* d, const R* q, const R* inv, R h, int 
 }
 
 // MODE: 0 forward, 1 adjoint, 2 forward recording hit lists, 3 interval labels,
-// 4 forward guided by proposed intervals (with full-traversal fallbacks)
+// 4 forward guided by proposed intervals (with full-traversal fallbacks),
+// 5 forward with the depth buffer (Section 5, hybrid rendering: the distance
+// along the unit ray at which it enters the first composited sample whose
+// density exceeds a threshold; +inf when there is none)
 #ifndef ART_RENDER_WAVES_PER_EU
 #define ART_RENDER_WAVES_PER_EU 3
 #endif
@@ -336,6 +341,7 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
     for (int c = 0; c < C; ++c) F[c] = 0.0f;
     int nsamp = 0;
     R t_first = 0, t_last = 0;   // MODE 3: entry of the first / exit of the last sample
+    float zdep = INFINITY;       // MODE 5: depth
     // adjoint state
     float g[C], Ff[C], P[C];
     float gA = 0.0f, Tfin = 0.0f;
@@ -599,6 +605,7 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
                             sB0 = s;
                             sB1 = s1;
                         }
+                        if constexpr (MODE == 5) sB0 = s;
                         hasB = true;
                     }
 #if ART_SKIP_EMPTY
@@ -694,6 +701,9 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
                         if (nsamp == 0) t_first = sA0;
                         t_last = sA1;
                     }
+                    if constexpr (MODE == 5) {
+                        if (zdep == INFINITY && sgA > a.depth_sigma) zdep = (float)sA0;
+                    }
                 }
                 T = Tn;
                 ++nsamp;
@@ -758,6 +768,7 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
             a.out_alpha[map * HW + pix] = Aacc;
             if (a.out_tfinal) a.out_tfinal[map * HW + pix] = T;
             if constexpr (MODE == 2) a.hit_count[pix] = nsamp;
+            if constexpr (MODE == 5) a.out_depth[map * HW + pix] = zdep;
         }
     }
     if (a.stats) {
@@ -833,6 +844,7 @@ hipError_t launch_render_mode(const RenderLaunch& r, const RArgs& a, unsigned gr
         case 2: hipLaunchKernelGGL((k_render<C, ST, R, 2>), dim3(grid), dim3(64), 0, st, a); break;
         case 3: hipLaunchKernelGGL((k_render<C, ST, R, 3>), dim3(grid), dim3(64), 0, st, a); break;
         case 4: hipLaunchKernelGGL((k_render<C, ST, R, 4>), dim3(grid), dim3(64), 0, st, a); break;
+        case 5: hipLaunchKernelGGL((k_render<C, ST, R, 5>), dim3(grid), dim3(64), 0, st, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
