@@ -164,7 +164,8 @@ art_status ensure_scratch(art_ctx* ctx, const CallPlan& pl, int slots) {
     const size_t nblk = (size_t)std::max(kScanBlocks, kUniqueBlocks);
     s.bin_stride = n * pl.Vg;
     art_status rc = ensure_bufs(ctx, {
-        {&s.keys0, S * n * 4}, {&s.vals0, S * n * 4}, {&s.keys1, S * n * 4}, {&s.vals1, S * n * 4},
+        {&s.keys0, S * n * 4}, {&s.keys1, S * n * 4},
+        {&s.bmap, S * brick_words(ctx->depth) * 4}, {&s.wpref, S * brick_words(ctx->depth) * 4},
         {&s.hist, S * 256 * (size_t)kSortBlocks * 4}, {&s.digit_tot, S * 256 * 4},
         {&s.blk0, S * nblk * 4}, {&s.blk1, S * nblk * 4},
         {&s.counters, S * sizeof(PoseCounters)}, {&s.stats, 16 * sizeof(unsigned long long)},
@@ -264,7 +265,7 @@ struct PassOut {
     bool single_pose = false;   // maps hold one pose only
 };
 
-// Skin + sort + octree build of poses [p0, p0 + batch) into slots 0..batch-1.
+// Skinning + octree build of poses [p0, p0 + batch) into slots 0..batch-1.
 art_status build_batch(art_ctx* ctx, const CallPlan& pl, int p0, int batch, const void* sigma, const void* feat,
                        int* launches, Timing& tm) {
     Scratch& s = ctx->s;
@@ -274,37 +275,21 @@ art_status build_batch(art_ctx* ctx, const CallPlan& pl, int p0, int batch, cons
     tm.record(st, -1);
     ART_TRY_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(cnt), 0u, (size_t)batch * sizeof(PoseCounters) / 4, st),
                 "fill");
+    const uint32_t bwords = brick_words(ctx->depth);
+    ART_TRY_HIP(launch_fill_u32(s.bmap.as<uint32_t>(), 0u, (size_t)batch * bwords, st), "fill");
     ART_TRY_HIP(launch_skin(ctx->ijk.as<uint16_t>(), ctx->bone.as<uint8_t>(), ctx->weight.as<float>(), ctx->n,
                             ctx->depth, ctx->B64.as<double>() + (size_t)p0 * ctx->J * 12,
                             ctx->B32.as<float>() + (size_t)p0 * ctx->J * 12, ctx->J, pl.fp32, batch,
-                            s.keys0.as<uint32_t>(), s.vals0.as<uint32_t>(), st),
+                            s.keys0.as<uint32_t>(), nullptr, s.bmap.as<uint32_t>(), bwords, cnt, st),
                 "skin");
-    *launches += 2;
+    *launches += 3;
     tm.record(st, 1);
-    // every pose sorts n keys: the count word of the first pose serves them all
-    ART_TRY_HIP(launch_fill_u32(&cnt[0].pad[2], (uint32_t)n, 1, st), "fill");
-    SortBatch sb;
-    sb.k0 = s.keys0.as<uint32_t>();
-    sb.k1 = s.keys1.as<uint32_t>();
-    sb.v0 = s.vals0.as<uint32_t>();
-    sb.v1 = s.vals1.as<uint32_t>();
-    sb.kstride = n;
-    sb.vstride = n;
-    sb.d_n = &cnt[0].pad[2];
-    sb.nstride = 0;
-    sb.n_cap = (uint32_t)n;
-    sb.hist = s.hist.as<uint32_t>();
-    sb.digit_tot = s.digit_tot.as<uint32_t>();
-    sb.batch = batch;
-    bool in1 = false;
-    ART_TRY_HIP(launch_radix_sort(sb, 32, st, &in1, launches), "radix sort");
-    const uint32_t* sk = in1 ? s.keys1.as<uint32_t>() : s.keys0.as<uint32_t>();
-    const uint32_t* sv = in1 ? s.vals1.as<uint32_t>() : s.vals0.as<uint32_t>();
-    ART_TRY_HIP(launch_build_octree(sk, sv, (uint32_t)n, s, octree_slot(ctx, pl, 0), batch, st, launches),
+    ART_TRY_HIP(launch_build_octree_dense(s.keys0.as<uint32_t>(), (uint32_t)n, ctx->depth, s,
+                                          octree_slot(ctx, pl, 0), batch, st, launches),
                 "octree build");
     hipLaunchKernelGGL(k_accum, dim3((batch + 63) / 64), dim3(64), 0, st, (const PoseCounters*)cnt,
                        s.stats.as<unsigned long long>(), (uint32_t)n, batch);
-    *launches += 2;
+    *launches += 1;
     tm.record(st, 2);
     return ART_OK;
 }
@@ -652,7 +637,7 @@ void art_destroy(art_ctx* ctx) {
         else (void)hipDeviceSynchronize();
         DevBuf* bufs[] = {&ctx->ijk, &ctx->bone, &ctx->weight, &ctx->parent, &ctx->rest, &ctx->pose,
                           &ctx->cam, &ctx->B64, &ctx->B32, &ctx->Gtmp,
-                          &ctx->s.keys0, &ctx->s.vals0, &ctx->s.keys1, &ctx->s.vals1, &ctx->s.hist,
+                          &ctx->s.keys0, &ctx->s.keys1, &ctx->s.bmap, &ctx->s.wpref, &ctx->s.hist,
                           &ctx->s.digit_tot, &ctx->s.blk0, &ctx->s.blk1, &ctx->s.occ_key, &ctx->s.occ_win,
                           &ctx->s.brick_key, &ctx->s.brick_row, &ctx->s.brick_mask, &ctx->s.bin_cnt, &ctx->s.bin_off, &ctx->s.pk0, &ctx->s.pv0,
                           &ctx->s.pk1, &ctx->s.pair_v, &ctx->s.tile_start, &ctx->s.tile_end,
@@ -1170,7 +1155,6 @@ art_status art_get_posed_keys(art_ctx* ctx, int pose, unsigned flags, uint32_t* 
     ART_TRY_HIP(ctx->B64.ensure(nb * 8), "device allocation");
     ART_TRY_HIP(ctx->B32.ensure(nb * 4), "device allocation");
     ART_TRY_HIP(ctx->Gtmp.ensure(nb * 8), "device allocation");
-    ART_TRY_HIP(ctx->s.vals0.ensure((size_t)ctx->n * 4), "device allocation");
     hipStream_t st = ctx->stream;
     ART_TRY_HIP(launch_fk(ctx->parent.as<int32_t>(), ctx->rest.as<double>(), ctx->pose.as<double>(), ctx->J,
                           ctx->P, ctx->Gtmp.as<double>(), ctx->B64.as<double>(), ctx->B32.as<float>(), st),
@@ -1178,7 +1162,7 @@ art_status art_get_posed_keys(art_ctx* ctx, int pose, unsigned flags, uint32_t* 
     ART_TRY_HIP(launch_skin(ctx->ijk.as<uint16_t>(), ctx->bone.as<uint8_t>(), ctx->weight.as<float>(), ctx->n,
                             ctx->depth, ctx->B64.as<double>() + (size_t)pose * ctx->J * 12,
                             ctx->B32.as<float>() + (size_t)pose * ctx->J * 12, ctx->J,
-                            (flags & ART_GEOM_FP32) != 0, 1, keys, ctx->s.vals0.as<uint32_t>(), st),
+                            (flags & ART_GEOM_FP32) != 0, 1, keys, nullptr, nullptr, 0u, nullptr, st),
                 "skin");
     ART_TRY_HIP(hipStreamSynchronize(st), "skin");
     return ART_OK;

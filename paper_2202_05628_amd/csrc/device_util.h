@@ -109,6 +109,36 @@ __device__ inline void block_range(uint32_t n, uint32_t b, uint32_t nb, uint32_t
     *hi = (uint32_t)(h < n ? h : n);
 }
 
+// Workgroup-local merging of OR-updates to 32-bit words named by a key (any
+// value but kInvalidKey): an open-addressing table of N entries (a power of
+// two) in LDS, so that each distinct key costs one global atomic per
+// workgroup instead of one per update.
+template <int N>
+struct LdsOrTable {
+    uint32_t key[N];
+    uint32_t bits[N];
+    __device__ void init() {
+        for (int e = threadIdx.x; e < N; e += blockDim.x) {
+            key[e] = kInvalidKey;
+            bits[e] = 0u;
+        }
+    }
+    // false when the table is full: the caller then updates the global word itself
+    __device__ bool insert(uint32_t k, uint32_t b) {
+        static_assert((N & (N - 1)) == 0, "N must be a power of two");
+        uint32_t h = (k * 0x9E3779B1u) >> (32 - __builtin_ctz(N));
+        for (int probe = 0; probe < N; ++probe) {
+            const uint32_t old = atomicCAS(&key[h], kInvalidKey, k);
+            if (old == kInvalidKey || old == k) {
+                atomicOr(&bits[h], b);
+                return true;
+            }
+            h = (h + 1u) & (uint32_t)(N - 1);
+        }
+        return false;
+    }
+};
+
 __device__ inline float bf16_to_f32(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
 
 // Rotation matrix (row-major 3x3) of an axis-angle vector r, FP64 (Rodrigues).

@@ -88,9 +88,10 @@ constexpr int kScanBlocks = 256;      // fixed grid (per pose) of device-sized s
 constexpr int kUniqueBlocks = 512;    // fixed grid (per pose) of the unique / compaction step
 
 struct Scratch {
-    DevBuf keys0, vals0, keys1, vals1;   // sort ping-pong [slots][n]
+    DevBuf keys0, keys1;                 // [slots][n] posed key / posed row of each leaf
     DevBuf hist, digit_tot;              // [slots][256 * kSortBlocks], [slots][256]
     DevBuf blk0, blk1;                   // block partials [slots][max(kScanBlocks, kUniqueBlocks)]
+    DevBuf bmap, wpref;                  // [slots][bwords] brick occupancy bits, bricks before each word
     DevBuf occ_key, occ_win;             // [slots][n] posed cells + winners
     DevBuf brick_key, brick_row, brick_mask;  // [slots][n], [slots][n+1], [slots][n*16]
     DevBuf bin_cnt, bin_off;             // [slots][n * Vg]
@@ -172,7 +173,8 @@ hipError_t launch_fk(const int32_t* parent, const double* rest, const double* po
                      double* G, double* B64, float* B32, hipStream_t st);
 hipError_t launch_skin(const uint16_t* ijk, const uint8_t* bone, const float* w, int64_t n,
                        int depth, const double* B64, const float* B32, int J, bool fp32, int batch,
-                       uint32_t* keys, uint32_t* vals, hipStream_t st);
+                       uint32_t* keys, uint32_t* vals, uint32_t* bmap, uint32_t bwords, PoseCounters* cnt,
+                       hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t st);
 
 struct SortBatch {
@@ -199,8 +201,15 @@ struct OctreeSlot {
     uint32_t* brick_row;    // [n + 1]
     uint32_t* brick_mask;   // [n][16]
 };
-hipError_t launch_build_octree(const uint32_t* skeys, const uint32_t* svals, uint32_t n, Scratch& s,
-                               const OctreeSlot& o, int batch, hipStream_t st, int* launches);
+// Words of the brick occupancy bitmap of a posed lattice of depth + 1.
+inline uint32_t brick_words(int depth) {
+    const int bits = 3 * (depth + 1) - 9;   // bits of a brick key (key >> 9)
+    return bits <= 5 ? 1u : (1u << (bits - 5));
+}
+// Octree build from the unsorted posed keys of a batch (keys + pose * n, the
+// invalid key for dropped leaves) and the brick bitmap the skinning marked.
+hipError_t launch_build_octree_dense(const uint32_t* keys, uint32_t n, int depth, Scratch& s, const OctreeSlot& o,
+                                     int batch, hipStream_t st, int* launches);
 int bin_key_bits(int Vg, int H, int W, int depth, int* mbits);
 // Tile lists of views [v0, v0 + Vg) of every pose of the batch: sorted brick
 // ids into pair_v + (p * ngroups + group) * pair_cap, per-tile ranges into

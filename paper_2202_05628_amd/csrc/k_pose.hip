@@ -84,17 +84,33 @@ __global__ __launch_bounds__(256) void k_skin(const uint16_t* __restrict__ ijk,
                                               uint32_t n, int depth,
                                               const R* __restrict__ Bpose, int J,
                                               uint32_t* __restrict__ keys,
-                                              uint32_t* __restrict__ vals) {
+                                              uint32_t* __restrict__ vals,
+                                              uint32_t* __restrict__ bmap, uint32_t bwords,
+                                              PoseCounters* __restrict__ cnt) {
     __shared__ R sB[256 * 12];
     Bpose += (size_t)blockIdx.y * J * 12;
     keys += (size_t)blockIdx.y * n;
-    vals += (size_t)blockIdx.y * n;
+    if (vals) vals += (size_t)blockIdx.y * n;
+    if (bmap) {
+        bmap += (size_t)blockIdx.y * bwords;
+        cnt += blockIdx.y;
+    }
+    __shared__ LdsOrTable<256> tab;   // brick-bitmap words touched by this workgroup
     for (int i = threadIdx.x; i < J * 12; i += blockDim.x) sB[i] = Bpose[i];
+    tab.init();
     __syncthreads();
     const R h = (R)1 / (R)(1 << depth);
     const R invh = (R)(1 << depth);
     const R G = (R)(2 << depth);
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    // Each workgroup skins a contiguous range of leaves (neighbouring canonical
+    // leaves land in few posed bricks).  The lanes of a wave hold consecutive
+    // leaves, so the lanes still in the loop are a prefix of the wave (lane - 1
+    // of an active lane is active).
+    uint32_t lo, hi;
+    block_range(n, blockIdx.x, gridDim.x, 256, &lo, &hi);
+    for (uint32_t base = lo; base < hi; base += blockDim.x) {
+        const uint32_t i = base + threadIdx.x;
+        if (i >= hi) break;
         const R x = (R)-0.5 + ((R)ijk[i] + (R)0.5) * h;
         const R y = (R)-0.5 + ((R)ijk[n + i] + (R)0.5) * h;
         const R z = (R)-0.5 + ((R)ijk[2 * (size_t)n + i] + (R)0.5) * h;
@@ -118,8 +134,32 @@ __global__ __launch_bounds__(256) void k_skin(const uint16_t* __restrict__ ijk,
             ok = ok && (u >= (R)0) && (u < G);
             c[a] = ok ? (uint32_t)u : 0u;
         }
-        keys[i] = ok ? morton3(c[0], c[1], c[2]) : kInvalidKey;
-        vals[i] = i;
+        const uint32_t key = ok ? morton3(c[0], c[1], c[2]) : kInvalidKey;
+        keys[i] = key;
+        if (vals) vals[i] = i;
+        if (bmap) {
+            // mark the leaf's brick (key >> 9) in the occupancy bitmap: the bits
+            // of each run of lanes with the same bitmap word are OR-ed into the
+            // run's first lane, which merges them into the workgroup's table
+            const uint32_t wk = ok ? key >> 14 : kInvalidKey;
+            uint32_t bits = ok ? 1u << ((key >> 9) & 31u) : 0u;
+            const int lane = lane_id();
+#pragma unroll
+            for (int d = 1; d < kWave; d <<= 1) {
+                const uint32_t ob = __shfl_down(bits, d, kWave);
+                const uint32_t ow = __shfl_down(wk, d, kWave);
+                if (lane + d < kWave && i + (uint32_t)d < hi && ow == wk) bits |= ob;
+            }
+            const uint32_t prev = __shfl_up(wk, 1, kWave);
+            if (ok && (lane == 0 || prev != wk) && !tab.insert(wk, bits)) atomicOr(&bmap[wk], bits);
+            const uint64_t drop = __ballot(!ok);
+            if (lane == 0 && drop) atomicAdd(&cnt->dropped, (uint32_t)__popcll(drop));
+        }
+    }
+    if (bmap) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < 256; e += blockDim.x)
+            if (tab.key[e] != kInvalidKey) atomicOr(&bmap[tab.key[e]], tab.bits[e]);
     }
 }
 
@@ -133,16 +173,17 @@ hipError_t launch_fk(const int32_t* parent, const double* rest, const double* po
 
 hipError_t launch_skin(const uint16_t* ijk, const uint8_t* bone, const float* w, int64_t n,
                        int depth, const double* B64, const float* B32, int J, bool fp32, int batch,
-                       uint32_t* keys, uint32_t* vals, hipStream_t st) {
+                       uint32_t* keys, uint32_t* vals, uint32_t* bmap, uint32_t bwords, PoseCounters* cnt,
+                       hipStream_t st) {
     const int bs = 256;
     int grid = (int)((n + bs - 1) / bs);
-    if (grid > 2048) grid = 2048;
+    if (grid > 1024) grid = 1024;
     if (fp32)
         hipLaunchKernelGGL(k_skin<float>, dim3(grid, batch), dim3(bs), 0, st, ijk, bone, w, (uint32_t)n,
-                           depth, B32, J, keys, vals);
+                           depth, B32, J, keys, vals, bmap, bwords, cnt);
     else
         hipLaunchKernelGGL(k_skin<double>, dim3(grid, batch), dim3(bs), 0, st, ijk, bone, w, (uint32_t)n,
-                           depth, B64, J, keys, vals);
+                           depth, B64, J, keys, vals, bmap, bwords, cnt);
     return hipGetLastError();
 }
 
