@@ -109,6 +109,29 @@ __device__ inline void block_range(uint32_t n, uint32_t b, uint32_t nb, uint32_t
     *hi = (uint32_t)(h < n ? h : n);
 }
 
+// Streaming stores of output maps, which nothing reads again in the same
+// launch: non-temporal, so they do not displace the gathered FLUT rows and
+// octree lines from the caches.
+#ifndef ART_NT_STORES
+#define ART_NT_STORES 1
+#endif
+typedef float art_f4 __attribute__((ext_vector_type(4)));
+__device__ inline void store_stream(float* p, float v) {
+#if ART_NT_STORES
+    __builtin_nontemporal_store(v, p);
+#else
+    *p = v;
+#endif
+}
+__device__ inline void store_stream4(float* p, float4 v) {   // p 16-byte aligned
+    const art_f4 w = {v.x, v.y, v.z, v.w};
+#if ART_NT_STORES
+    __builtin_nontemporal_store(w, reinterpret_cast<art_f4*>(p));
+#else
+    *reinterpret_cast<art_f4*>(p) = w;
+#endif
+}
+
 // Workgroup-local merging of OR-updates to 32-bit words named by a key (any
 // value but kInvalidKey): an open-addressing table of N entries (a power of
 // two) in LDS, so that each distinct key costs one global atomic per

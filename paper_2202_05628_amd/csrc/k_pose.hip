@@ -87,7 +87,8 @@ __global__ __launch_bounds__(256) void k_skin(const uint16_t* __restrict__ ijk,
                                               uint32_t* __restrict__ vals,
                                               uint32_t* __restrict__ bmap, uint32_t bwords,
                                               PoseCounters* __restrict__ cnt) {
-    __shared__ R sB[256 * 12];
+    extern __shared__ __align__(16) unsigned char s_dyn[];   // J * 12 bone-matrix entries
+    R* sB = reinterpret_cast<R*>(s_dyn);
     Bpose += (size_t)blockIdx.y * J * 12;
     keys += (size_t)blockIdx.y * n;
     if (vals) vals += (size_t)blockIdx.y * n;
@@ -179,10 +180,10 @@ hipError_t launch_skin(const uint16_t* ijk, const uint8_t* bone, const float* w,
     int grid = (int)((n + bs - 1) / bs);
     if (grid > 1024) grid = 1024;
     if (fp32)
-        hipLaunchKernelGGL(k_skin<float>, dim3(grid, batch), dim3(bs), 0, st, ijk, bone, w, (uint32_t)n,
+        hipLaunchKernelGGL(k_skin<float>, dim3(grid, batch), dim3(bs), (size_t)J * 12 * 4, st, ijk, bone, w, (uint32_t)n,
                            depth, B32, J, keys, vals, bmap, bwords, cnt);
     else
-        hipLaunchKernelGGL(k_skin<double>, dim3(grid, batch), dim3(bs), 0, st, ijk, bone, w, (uint32_t)n,
+        hipLaunchKernelGGL(k_skin<double>, dim3(grid, batch), dim3(bs), (size_t)J * 12 * 8, st, ijk, bone, w, (uint32_t)n,
                            depth, B64, J, keys, vals, bmap, bwords, cnt);
     return hipGetLastError();
 }

@@ -83,9 +83,9 @@ __global__ __launch_bounds__(256) void k_background(TileGeom g, const uint32_t* 
         if (tend[item] > tstart[item]) continue;                      // rendered by k_render
         ++nrays;
         if (out_feat)
-            for (int c = 0; c < g.C; ++c) out_feat[((size_t)pvi * g.C + c) * HW + pix] = 0.0f;
-        if (out_alpha) out_alpha[(size_t)pvi * HW + pix] = 0.0f;
-        if (out_tfinal) out_tfinal[(size_t)pvi * HW + pix] = 1.0f;
+            for (int c = 0; c < g.C; ++c) store_stream(&out_feat[((size_t)pvi * g.C + c) * HW + pix], 0.0f);
+        if (out_alpha) store_stream(&out_alpha[(size_t)pvi * HW + pix], 0.0f);
+        if (out_tfinal) store_stream(&out_tfinal[(size_t)pvi * HW + pix], 1.0f);
         if (labels) reinterpret_cast<float2*>(labels)[(size_t)pvi * HW + pix] = make_float2(1.0f, 0.0f);
         if (out_depth) out_depth[(size_t)pvi * HW + pix] = INFINITY;
         if (hit_count) hit_count[pix] = 0;
@@ -123,10 +123,9 @@ __global__ __launch_bounds__(256) void k_background4(TileGeom g, const uint32_t*
         if (tend[item] > tstart[item]) continue;                      // rendered by k_render
         nrays += 4;
         if (out_feat)
-            for (int c = 0; c < g.C; ++c)
-                reinterpret_cast<float4*>(out_feat + ((size_t)pvi * g.C + c) * HW)[q] = zero;
-        if (out_alpha) reinterpret_cast<float4*>(out_alpha + (size_t)pvi * HW)[q] = zero;
-        if (out_tfinal) reinterpret_cast<float4*>(out_tfinal + (size_t)pvi * HW)[q] = make_float4(1.0f, 1.0f, 1.0f, 1.0f);
+            for (int c = 0; c < g.C; ++c) store_stream4(out_feat + ((size_t)pvi * g.C + c) * HW + pix, zero);
+        if (out_alpha) store_stream4(out_alpha + (size_t)pvi * HW + pix, zero);
+        if (out_tfinal) store_stream4(out_tfinal + (size_t)pvi * HW + pix, make_float4(1.0f, 1.0f, 1.0f, 1.0f));
         if (labels) {
             float4* l = reinterpret_cast<float4*>(labels + ((size_t)pvi * HW + pix) * 2);
             l[0] = make_float4(1.0f, 0.0f, 1.0f, 0.0f);

@@ -764,9 +764,9 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
     } else if constexpr (MODE != 1) {
         if (pix_ok) {
 #pragma unroll
-            for (int c = 0; c < C; ++c) a.out_feat[(map * C + c) * HW + pix] = F[c];
-            a.out_alpha[map * HW + pix] = Aacc;
-            if (a.out_tfinal) a.out_tfinal[map * HW + pix] = T;
+            for (int c = 0; c < C; ++c) store_stream(&a.out_feat[(map * C + c) * HW + pix], F[c]);
+            store_stream(&a.out_alpha[map * HW + pix], Aacc);
+            if (a.out_tfinal) store_stream(&a.out_tfinal[map * HW + pix], T);
             if constexpr (MODE == 2) a.hit_count[pix] = nsamp;
             if constexpr (MODE == 5) a.out_depth[map * HW + pix] = zdep;
         }
