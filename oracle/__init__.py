@@ -24,7 +24,10 @@ Articulated Neural Pets with Appearance and Motion Synthesis", 2022):
                                the coarse opacity map and the early stop at
                                lambda_th (C code in ``ray_oracle.c``);
 * ``mlp``                    - FP64 reference of the ray-interval proposal MLP
-                               (not in the paper).
+                               (not in the paper);
+* ``train``                  - the FLUT training step: the voxel regularisation
+                               term (Eq. 10), the point-query operator Q and the
+                               projected Adam update.
 
 Readings of the paper where it is silent or inconsistent (exclusive
 transmittance, chord-length samples, the strict stop test, min-id collision
