@@ -246,6 +246,33 @@ def adjoint_leg(args, art, sg, torch):
             "mrays_s": round(rays / t / 1e6, 2), "ms_per_call": round(t * 1e3, 3)}
 
 
+def train_leg(args, art, sg, torch):
+    """FLUT training step on the differentiation workload (1 pose x 4 cameras at
+    512^2, C = 16, FP32): render, L2 map loss to seeded targets, adjoint,
+    voxel regularisation term (lambda_vrt = 0.05), Adam on sigma and features."""
+    cfg = sg.CONFIGS["grad"]
+    scene = sg.make_scene(cfg)
+    P, V, H, W = cfg.n_poses, cfg.n_views, cfg.height, cfg.width
+    r = art.Renderer(0)
+    r.set_scene(scene)
+    r.set_poses(*sg.make_poses(scene.J, P, cfg.pose_seed0))
+    r.set_cameras(*sg.make_cameras(scene, V, H, W), H, W)
+    sig = torch.from_numpy(scene.sigma).cuda()
+    feat = torch.from_numpy(scene.feat).cuda()
+    tgt = torch.from_numpy(sg.make_targets(P, V, cfg.C, H, W, cfg.target_seed)).cuda()
+    st = r.train_state(sig, feat)
+    losses = []
+    t = _timed(torch, lambda: losses.append(r.train_step(sig, feat, st, tgt, lr=1e-2, lambda_vrt=0.05)),
+               args.proposal_steps)
+    t_vrt = _timed(torch, lambda: r.vrt(feat, 0.05), args.proposal_steps)
+    rays = P * V * H * W
+    return {"workload": f"FLUT training step: {P} pose x {V} cameras at {H}x{W} ({rays} rays), L2 map loss, "
+                        f"VRT lambda 0.05, Adam lr 1e-2",
+            "ms_per_step": round(t * 1e3, 3), "mrays_s": round(rays / t / 1e6, 2),
+            "vrt_ms": round(t_vrt * 1e3, 3),
+            "loss_first": round(losses[0]["total"], 6), "loss_last": round(losses[-1]["total"], 6)}
+
+
 def proposal_leg(args, art, sg, torch):
     """Learned ray-interval proposal vs the plain renderer on the proposal
     workload (60 poses x 16 cameras at 1024^2, C = 16, FP32): the network is
@@ -462,6 +489,8 @@ def main():
         line["bf16_form"] = bf16_leg(args, art, sg, torch)
         torch.cuda.empty_cache()
         line["adjoint_form"] = adjoint_leg(args, art, sg, torch)
+        torch.cuda.empty_cache()
+        line["train_step"] = train_leg(args, art, sg, torch)
         torch.cuda.empty_cache()
     if not args.no_proposal:
         print("[bench] learned proposal vs plain (proposal workload)", file=sys.stderr, flush=True)

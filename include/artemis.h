@@ -237,6 +237,46 @@ art_status art_render_depth(art_ctx* ctx, int C, art_dtype dtype, const void* si
                             float* out_tfinal, float* out_depth);
 
 /*
+ * Voxel regularisation term of Section 3.1 ("Training", Eq. 10) for every pose
+ * and its gradient with respect to the features.  For each canonical leaf i
+ * whose posed centre lies inside the posed root, Q(p_i^t, T^t) is the feature
+ * of the leaf the posed octree holds at that cell (the collision winner:
+ * smallest leaf id); the pose's term is lambda_vrt / N_v * sum_i
+ * |Q(p_i^t, T^t) - f_i|_1 with N_v the leaves inside the root, and the terms
+ * of all poses add up.  feat: device [n][C] (FP32 or BF16 per dtype).
+ * d_feat: device float32 [n][C]; the gradient is ADDED (sign(Q - f_i) *
+ * lambda / N_v to the winner's row, its negative to leaf i's), so the buffer
+ * can also hold art_backward's gradient.  *loss (host) receives the loss.
+ * Errors: ART_EINVAL (NULL pointer, negative or non-finite lambda_vrt, flags
+ * other than ART_GEOM_FP32), ART_EUNSUPPORTED (C), ART_ESTATE (missing octree,
+ * skin, skeleton or poses).
+ */
+art_status art_vrt(art_ctx* ctx, int C, art_dtype dtype, const void* feat, float lambda_vrt, unsigned flags,
+                   float* d_feat, double* loss);
+
+/*
+ * The point-query operator Q of Eq. 10 as an index: for each of n points of
+ * the posed space (device float64 [n][3]) of pose `pose`, the canonical leaf
+ * the posed octree holds at the point's cell (floor((p + 1) / h) on the posed
+ * lattice), or -1 when the cell is empty or outside the posed root.
+ * leaf: device int32 [n].
+ * Errors: ART_EINVAL (n < 0, NULL with n > 0, pose out of range, unknown
+ * flags), ART_ESTATE (missing octree, skin, skeleton or poses).
+ */
+art_status art_query(art_ctx* ctx, int pose, unsigned flags, int64_t n, const double* points, int32_t* leaf);
+
+/*
+ * One Adam update (step counts from 1, bias-corrected) of a device float32
+ * FLUT array of `count` entries from its gradient, moments m and v updated in
+ * place, then param = max(param, lower) (pass -INFINITY for none; 0 keeps
+ * densities non-negative).  Enqueued on the context's stream.
+ * Errors: ART_EINVAL (count < 0, NULL buffer, step < 1, lr < 0, beta outside
+ * [0, 1), eps <= 0, NaN lower).
+ */
+art_status art_flut_adam(art_ctx* ctx, int64_t count, float* param, const float* grad, float* m, float* v, int step,
+                         float lr, float beta1, float beta2, float eps, float lower);
+
+/*
  * The proposal network: x = [o (3), d (3), pose code (6 J)] -> 64 -> 64 -> 64
  * (ReLU) -> 2 (sigmoid) = (u_near, u_far), where (o, d) is the ray (origin,
  * unit direction, FP32) and the pose code holds, per bone j, the first and

@@ -308,6 +308,78 @@ class Renderer:
                     "art_backward")
         return d_sigma, d_feat
 
+    # ---- training step ----------------------------------------------------------------
+    def vrt(self, feat, lambda_vrt: float, d_feat=None, fp32_geom: bool = False):
+        """Voxel regularisation term (Eq. 10) summed over the poses; its gradient
+        is added into d_feat [n][C] (float32).  Returns (loss, d_feat)."""
+        torch = self._torch
+        if feat.dtype not in (torch.float32, torch.bfloat16) or not feat.is_cuda or not feat.is_contiguous():
+            raise TypeError("feat must be a contiguous float32 or bfloat16 device tensor")
+        if feat.dim() != 2 or feat.shape[0] != self.n:
+            raise ValueError(f"expected feat [{self.n}, C]")
+        C = int(feat.shape[1])
+        dtype = ART_BF16 if feat.dtype == torch.bfloat16 else ART_F32
+        if d_feat is None:
+            d_feat = torch.zeros((self.n, C), dtype=torch.float32, device=feat.device)
+        loss = ctypes.c_double(0.0)
+        self._check(self.lib.art_vrt(self._h, C, dtype, _tptr(feat), float(lambda_vrt),
+                                     ART_GEOM_FP32 if fp32_geom else 0, _tptr(d_feat), ctypes.byref(loss)),
+                    "art_vrt")
+        return float(loss.value), d_feat
+
+    def query(self, pose: int, points, fp32_geom: bool = False):
+        """Leaf held by the posed octree of `pose` at each point [n][3] (float64
+        device tensor); -1 for empty cells and points outside the root."""
+        torch = self._torch
+        pts = points.contiguous().to(torch.float64)
+        out = torch.empty((pts.shape[0],), dtype=torch.int32, device=pts.device)
+        self._check(self.lib.art_query(self._h, int(pose), ART_GEOM_FP32 if fp32_geom else 0, int(pts.shape[0]),
+                                       _tptr(pts), _tptr(out)), "art_query")
+        return out
+
+    def flut_adam(self, param, grad, m, v, step: int, lr: float, beta1: float = 0.9, beta2: float = 0.999,
+                  eps: float = 1e-8, lower: float = float("-inf")) -> None:
+        """In-place Adam update of a float32 FLUT tensor (then param >= lower)."""
+        for t in (param, grad, m, v):
+            if t.dtype != self._torch.float32 or not t.is_cuda or not t.is_contiguous() or t.numel() != param.numel():
+                raise TypeError("param, grad, m, v must be contiguous float32 device tensors of one size")
+        self._check(self.lib.art_flut_adam(self._h, int(param.numel()), _tptr(param), _tptr(grad), _tptr(m),
+                                           _tptr(v), int(step), float(lr), float(beta1), float(beta2), float(eps),
+                                           float(lower)), "art_flut_adam")
+
+    def train_state(self, sigma, feat) -> dict:
+        """Adam moments of a float32 FLUT (sigma [n], feat [n][C]) and the step count."""
+        torch = self._torch
+        return {"step": 0, "m_s": torch.zeros_like(sigma), "v_s": torch.zeros_like(sigma),
+                "m_f": torch.zeros_like(feat), "v_f": torch.zeros_like(feat)}
+
+    def train_step(self, sigma, feat, state: dict, F_target, A_target=None, lr: float = 1e-2,
+                   lambda_vrt: float = 0.0, lambda_th: float = LAMBDA_TH, fp32_geom: bool = False) -> dict:
+        """One FLUT training step (Section 3.1, "Training", without the shading
+        network): render every pose and view, the map loss
+        L_map = 1/(2R) [sum (F - F*)^2 + sum (A - A*)^2] over the R rays (the A
+        term when A_target is given), its gradient by the adjoint kernel, the
+        voxel regularisation term and its gradient (lambda_vrt > 0), then Adam
+        on sigma (projected onto sigma >= 0) and feat, in place.  Returns the
+        losses of the FLUT before the update."""
+        torch = self._torch
+        F, A, T = self.render(sigma, feat, lambda_th, fp32_geom=fp32_geom)
+        R = float(self.P * self.V * self.H * self.W)
+        dF = (F - F_target) / R
+        l_map = 0.5 * float((dF * (F - F_target)).sum())
+        dA = None
+        if A_target is not None:
+            dA = (A - A_target) / R
+            l_map += 0.5 * float((dA * (A - A_target)).sum())
+        d_sigma, d_feat = self.backward(sigma, feat, F, T, dF, dA, lambda_th, fp32_geom=fp32_geom)
+        l_vrt = 0.0
+        if lambda_vrt > 0.0:
+            l_vrt, _ = self.vrt(feat, lambda_vrt, d_feat=d_feat, fp32_geom=fp32_geom)
+        state["step"] += 1
+        self.flut_adam(sigma, d_sigma, state["m_s"], state["v_s"], state["step"], lr, lower=0.0)
+        self.flut_adam(feat, d_feat, state["m_f"], state["v_f"], state["step"], lr)
+        return {"map": l_map, "vrt": l_vrt, "total": l_map + l_vrt}
+
     # ---- inspection ------------------------------------------------------------------
     def get_bones(self) -> np.ndarray:
         B = np.zeros((self.P, self.J, 3, 4), dtype=np.float64)

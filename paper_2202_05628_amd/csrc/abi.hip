@@ -145,8 +145,9 @@ size_t slot_bytes(const art_ctx* ctx, const CallPlan& pl, size_t pair_cap) {
     const size_t n = (size_t)ctx->n;
     const size_t es = pl.storage ? 2 : 4;
     const size_t tiles = (size_t)ctx->V * ((ctx->W + 7) / 8) * ((ctx->H + 7) / 8);
-    // octree slot + sort scratch + bin counts + tile lists and their sort scratch + tile ranges
-    return n * (4 + 4 + 4 + 4 + 64) + n * 16 + n * pl.Vg * 8 +
+    // octree slot + per-leaf keys and rows + brick bitmap + bin counts + tile lists and their sort
+    // scratch + tile ranges
+    return n * (4 + 4 + 4 + 4 + 64) + n * 8 + (size_t)brick_words(ctx->depth) * 8 + n * pl.Vg * 8 +
            (size_t)pl.ngroups * pair_cap * 8 + pair_cap * 8 + tiles * 12 + (size_t)pl.ngroups * 9 +
            (pl.net ? tiles * 64 * 8 : 0);
 }
@@ -179,7 +180,7 @@ art_status ensure_scratch(art_ctx* ctx, const CallPlan& pl, int slots) {
         {&s.redo, S * pl.ngroups},
         {&s.tile_start, S * tiles * 4}, {&s.tile_end, S * tiles * 4},
         {&s.ovf, S * pl.ngroups * 2 * 4},
-        {&s.items, S * tiles * 4}, {&s.queue, 64},
+        {&s.items, S * tiles * 4}, {&s.queue, 64}, {&s.loss, 8},
         {&s.interval, pl.net ? S * tiles * 64 * 8 : 0},
     });
     if (rc == ART_OK) s.slots = std::max(s.slots, slots);
@@ -641,7 +642,7 @@ void art_destroy(art_ctx* ctx) {
                           &ctx->s.digit_tot, &ctx->s.blk0, &ctx->s.blk1, &ctx->s.occ_key, &ctx->s.occ_win,
                           &ctx->s.brick_key, &ctx->s.brick_row, &ctx->s.brick_mask, &ctx->s.bin_cnt, &ctx->s.bin_off, &ctx->s.pk0, &ctx->s.pv0,
                           &ctx->s.pk1, &ctx->s.pair_v, &ctx->s.tile_start, &ctx->s.tile_end,
-                          &ctx->s.counters, &ctx->s.stats, &ctx->s.ovf, &ctx->s.items, &ctx->s.queue,
+                          &ctx->s.counters, &ctx->s.stats, &ctx->s.ovf, &ctx->s.items, &ctx->s.queue, &ctx->s.loss,
                           &ctx->s.redo, &ctx->s.interval, &ctx->mlp_theta, &ctx->mlp_m1, &ctx->mlp_m2,
                           &ctx->mlp_packed, &ctx->mlp_cbias, &ctx->mlp_code, &ctx->mlp_S, &ctx->mlp_part,
                           &ctx->mlp_lossp, &ctx->mlp_loss, &ctx->mlp_flag};
@@ -878,6 +879,107 @@ art_status art_render_depth(art_ctx* ctx, int C, art_dtype dtype, const void* si
     o.out_depth = out_depth;
     o.depth_sigma = depth_sigma;
     return render_call(ctx, C, dtype, sigma, feat, lambda_th, flags, 5, o, 0, ctx->P);
+}
+
+art_status art_vrt(art_ctx* ctx, int C, art_dtype dtype, const void* feat, float lambda_vrt, unsigned flags,
+                   float* d_feat, double* loss) {
+    if (!ctx) return ART_EINVAL;
+    if (!feat || !d_feat || !loss) return fail(ctx, ART_EINVAL, "feat / d_feat / loss is NULL");
+    if (!(lambda_vrt >= 0.0f && lambda_vrt < 1e30f)) return fail(ctx, ART_EINVAL, "lambda_vrt must be finite and >= 0");
+    if (!supported_C(C)) return fail(ctx, ART_EUNSUPPORTED, "C must be 4, 8, 16 or 32");
+    if (dtype != ART_F32 && dtype != ART_BF16) return fail(ctx, ART_EINVAL, "dtype must be ART_F32 or ART_BF16");
+    if (flags & ~ART_GEOM_FP32) return fail(ctx, ART_EINVAL, "unknown flag bits");
+    art_status rc = check_build_state(ctx);
+    if (rc != ART_OK) return rc;
+    DeviceGuard g(ctx->device);
+    CallPlan pl;   // octrees only: no cameras involved
+    pl.C = C;
+    pl.storage = dtype == ART_BF16 ? 1 : 0;
+    pl.fp32 = (flags & ART_GEOM_FP32) != 0;
+    pl.Vg = 1;
+    pl.ngroups = 1;
+    if (ctx->s.pair_cap == 0) ctx->s.pair_cap = initial_pair_cap(1);
+    const int slots = (int)std::min<size_t>((size_t)ctx->P,
+                                            std::max<size_t>(1, slot_budget_bytes() / slot_bytes(ctx, pl, ctx->s.pair_cap)));
+    rc = ensure_scratch(ctx, pl, slots);
+    if (rc != ART_OK) return rc;
+    hipStream_t st = ctx->stream;
+    Scratch& s = ctx->s;
+    int launches = 0;
+    Timing tm;
+    ART_TRY_HIP(launch_fill_u32(s.stats.as<uint32_t>(), 0u, 32, st), "fill");
+    ART_TRY_HIP(launch_fill_u32(s.loss.as<uint32_t>(), 0u, 2, st), "fill");
+    ART_TRY_HIP(launch_fk(ctx->parent.as<int32_t>(), ctx->rest.as<double>(), ctx->pose.as<double>(), ctx->J,
+                          ctx->P, ctx->Gtmp.as<double>(), ctx->B64.as<double>(), ctx->B32.as<float>(), st),
+                "fk");
+    for (int p0 = 0; p0 < ctx->P; p0 += slots) {
+        const int batch = std::min(ctx->P, p0 + slots) - p0;
+        rc = build_batch(ctx, pl, p0, batch, nullptr, feat, &launches, tm);
+        if (rc != ART_OK) return rc;
+        ART_TRY_HIP(launch_vrt(s.keys1.as<uint32_t>(), s.occ_win.as<uint32_t>(), (uint32_t)ctx->n, C, pl.storage,
+                               feat, s.counters.as<PoseCounters>(), lambda_vrt, batch, d_feat, s.loss.as<double>(), st),
+                    "vrt");
+    }
+    double h = 0.0;
+    ART_TRY_HIP(hipMemcpyAsync(&h, s.loss.p, 8, hipMemcpyDeviceToHost, st), "copy");
+    ART_TRY_HIP(hipStreamSynchronize(st), "vrt");
+    *loss = h;
+    return ART_OK;
+}
+
+art_status art_query(art_ctx* ctx, int pose, unsigned flags, int64_t n, const double* points, int32_t* leaf) {
+    if (!ctx) return ART_EINVAL;
+    if (n < 0) return fail(ctx, ART_EINVAL, "n must be >= 0");
+    if (n > 0 && (!points || !leaf)) return fail(ctx, ART_EINVAL, "points / leaf is NULL");
+    if (flags & ~ART_GEOM_FP32) return fail(ctx, ART_EINVAL, "unknown flag bits");
+    art_status rc = check_build_state(ctx);
+    if (rc != ART_OK) return rc;
+    if (pose < 0 || pose >= ctx->P) return fail(ctx, ART_EINVAL, "pose out of range");
+    DeviceGuard g(ctx->device);
+    CallPlan pl;
+    pl.C = 4;
+    pl.storage = 0;
+    pl.fp32 = (flags & ART_GEOM_FP32) != 0;
+    pl.Vg = 1;
+    pl.ngroups = 1;
+    if (ctx->s.pair_cap == 0) ctx->s.pair_cap = initial_pair_cap(1);
+    rc = ensure_scratch(ctx, pl, 1);
+    if (rc != ART_OK) return rc;
+    hipStream_t st = ctx->stream;
+    Timing tm;
+    int launches = 0;
+    ART_TRY_HIP(launch_fill_u32(ctx->s.stats.as<uint32_t>(), 0u, 32, st), "fill");
+    ART_TRY_HIP(launch_fk(ctx->parent.as<int32_t>(), ctx->rest.as<double>(), ctx->pose.as<double>(), ctx->J,
+                          ctx->P, ctx->Gtmp.as<double>(), ctx->B64.as<double>(), ctx->B32.as<float>(), st),
+                "fk");
+    rc = build_batch(ctx, pl, pose, 1, nullptr, nullptr, &launches, tm);
+    if (rc != ART_OK) return rc;
+    ART_TRY_HIP(launch_query(points, n, ctx->depth, octree_slot(ctx, pl, 0), ctx->s.counters.as<PoseCounters>(),
+                             leaf, st),
+                "query");
+    ART_TRY_HIP(hipStreamSynchronize(st), "query");
+    return ART_OK;
+}
+
+art_status art_flut_adam(art_ctx* ctx, int64_t count, float* param, const float* grad, float* m, float* v, int step,
+                         float lr, float beta1, float beta2, float eps, float lower) {
+    if (!ctx) return ART_EINVAL;
+    if (count < 0) return fail(ctx, ART_EINVAL, "count must be >= 0");
+    if (count > 0 && (!param || !grad || !m || !v)) return fail(ctx, ART_EINVAL, "NULL buffer");
+    if (step < 1) return fail(ctx, ART_EINVAL, "step counts from 1");
+    if (!(lr >= 0.0f && lr < 1e30f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) ||
+        !(eps > 0.0f && eps < 1e30f) || lower != lower)
+        return fail(ctx, ART_EINVAL, "invalid Adam parameters");
+    DeviceGuard g(ctx->device);
+    AdamStep a;
+    a.lr = lr;
+    a.beta1 = beta1;
+    a.beta2 = beta2;
+    a.eps = eps;
+    a.bc1 = (float)(1.0 - std::pow((double)beta1, (double)step));
+    a.bc2 = (float)(1.0 - std::pow((double)beta2, (double)step));
+    ART_TRY_HIP(launch_flut_adam(param, grad, m, v, count, a, lower, ctx->stream), "flut adam");
+    return ART_OK;
 }
 
 art_status art_proposal_labels(art_ctx* ctx, int C, art_dtype dtype, const void* sigma, const void* feat,

@@ -106,6 +106,7 @@ struct Scratch {
     DevBuf items;                        // [slots][V][tiles] compacted non-empty tiles
     DevBuf redo;                         // [slots][groups] items re-run after an overflow
     DevBuf queue;                        // [2] item count, queue head
+    DevBuf loss;                         // [1] double: loss accumulator of the training-step kernels
     DevBuf interval;                     // [slots][V][tiles][64] float2 proposed intervals
     size_t pair_cap = 0;
     int slots = 0;                       // poses whose octrees are held at once
@@ -285,6 +286,15 @@ hipError_t launch_tiles(const TileLaunch& t, hipStream_t st);
 struct AdamStep {
     float lr, beta1, beta2, eps, bc1, bc2;   // bc = 1 - beta^step
 };
+// FLUT training step (k_train.hip).  rows: [batch][n] posed row of each leaf
+// from the octree build (kInvalidKey for dropped leaves).
+hipError_t launch_vrt(const uint32_t* rows, const uint32_t* occ_win, uint32_t n, int C, int storage,
+                      const void* feat, const PoseCounters* cnt, float lambda, int batch, float* d_feat,
+                      double* loss, hipStream_t st);
+hipError_t launch_query(const double* pts, int64_t n, int depth, const OctreeSlot& o, const PoseCounters* cnt,
+                        int32_t* out, hipStream_t st);
+hipError_t launch_flut_adam(float* param, const float* grad, float* m, float* v, int64_t count, const AdamStep& a,
+                            float lower, hipStream_t st);
 struct InferLaunch {
     const uint16_t* packed;
     const float* theta;

@@ -1,0 +1,176 @@
+"""The FLUT training step through the C ABI: the voxel regularisation term
+(Eq. 10) with its gradient, the point-query operator Q and the projected Adam
+update against the FP64 oracle (oracle/train.py), then a training run that
+fits a FLUT to seeded target maps.
+
+The VRT decisions (which leaf wins a cell, the sign of f_w - f_i) are exact
+on both sides: the posed keys are bit-exact outside the rounding guard band
+(no leaf of these scenes lies within 1e-9 h of a cell face), and the sign of a
+rounded FP32 difference is the sign of the exact one.  The gradient entries
+are sums of +-lambda / N_v; the loss is summed in FP64."""
+import numpy as np
+import pytest
+
+import oracle
+import oracle.train as otr
+import scenegen as sg
+from gpu_common import guard_leaves, log, make_renderer
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    s = sg.make_scene("tiny")
+    poses = sg.make_poses(s.J, 3)
+    K, c2w = sg.make_cameras(s, 2, 48, 40)
+    rend = make_renderer(s, poses, K, c2w, 48, 40)
+    B = oracle.fk(s.parent, s.rest_joint, *poses)
+    keys = []
+    for p in range(B.shape[0]):
+        _, _, cells, valid, pt = oracle.pose_occupancy(s.ijk, s.depth, s.bone, s.weight, B[p])
+        assert not guard_leaves(pt[valid], s.depth).any()
+        keys.append(oracle.posed_keys(cells, valid).astype(np.int64))
+    return s, rend, B, keys, K, c2w
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_vrt_matches_oracle(tiny, storage):
+    import torch
+    s, rend, B, keys, _, _ = tiny
+    f = torch.from_numpy(s.feat).cuda()
+    if storage == "bf16":
+        f = f.to(torch.bfloat16)
+    f_np = f.float().cpu().numpy().astype(np.float64)
+    lam = 0.25
+    L, g = rend.vrt(f.contiguous(), lam)
+    Lr, gr = 0.0, np.zeros_like(f_np)
+    scales = []
+    for p, k in enumerate(keys):
+        lp, gp, nv = otr.vrt(k, f_np, lam)
+        Lr += lp
+        gr += gp
+        scales.append(lam / nv)
+    g = g.cpu().numpy().astype(np.float64)
+    log(f"vrt {storage}: loss {L:.6f} vs oracle {Lr:.6f}; {int((gr != 0).any(axis=1).sum())} leaves with gradient")
+    assert Lr > 0
+    assert L == pytest.approx(Lr, rel=1e-6)
+    np.testing.assert_allclose(g, gr, rtol=1e-5, atol=1e-6 * min(scales))
+
+
+def test_vrt_accumulates_into_the_gradient(tiny):
+    import torch
+    s, rend, _, _, _, _ = tiny
+    f = torch.from_numpy(s.feat).cuda()
+    base = torch.full_like(f, 0.5)
+    L1, g1 = rend.vrt(f, 0.25)
+    L2, g2 = rend.vrt(f, 0.25, d_feat=base.clone())
+    assert L1 == pytest.approx(L2, rel=1e-12)
+    assert torch.allclose(g2 - 0.5, g1, atol=1e-6)
+    L0, g0 = rend.vrt(f, 0.0)
+    assert L0 == 0.0 and not g0.any()
+
+
+def test_query_matches_oracle(tiny):
+    import torch
+    s, rend, B, keys, _, _ = tiny
+    rng = np.random.default_rng(12)
+    h = 1.0 / (1 << s.depth)
+    for p in range(B.shape[0]):
+        _, _, cells, valid, pt = oracle.pose_occupancy(s.ijk, s.depth, s.bone, s.weight, B[p])
+        pts = np.concatenate([pt[rng.choice(len(pt), 3000)],                      # posed leaf centres
+                              (cells[rng.choice(len(pt), 2000)] + rng.random((2000, 3))) * h - 1.0,
+                              rng.uniform(-1.0, 1.0, (2000, 3)),
+                              rng.uniform(-1.5, 1.5, (500, 3))])
+        got = rend.query(p, torch.from_numpy(pts).cuda()).cpu().numpy()
+        want = otr.query(pts, s.depth, keys[p])
+        log(f"query pose {p}: {int((want >= 0).sum())} of {len(pts)} points in occupied cells")
+        assert np.array_equal(got, want)
+
+
+def test_flut_adam_matches_oracle(tiny):
+    import torch
+    s, rend, _, _, _, _ = tiny
+    rng = np.random.default_rng(13)
+    n = 10007
+    p0 = rng.normal(size=n).astype(np.float32)
+    p = torch.from_numpy(p0).cuda()
+    m = torch.zeros_like(p)
+    v = torch.zeros_like(p)
+    pr, mr, vr = p0.astype(np.float64), np.zeros(n), np.zeros(n)
+    mabs = np.zeros(n)   # the first moment of |g|: scale of the FP32 rounding of m (m may cancel)
+    # the hyper-parameters as the kernel receives them (FP32 values)
+    lr, b1, b2, eps = (float(np.float32(x)) for x in (0.05, 0.9, 0.999, 1e-8))
+    for step in range(1, 4):
+        g = rng.normal(size=n).astype(np.float32) * 10.0 ** rng.uniform(-3, 1, n).astype(np.float32)
+        rend.flut_adam(p, torch.from_numpy(g).cuda(), m, v, step, lr, b1, b2, eps, lower=0.0)
+        pr, mr, vr = otr.flut_adam(pr, mr, vr, g.astype(np.float64), step, lr, b1, b2, eps, lower=0.0)
+        mabs = 0.9 * mabs + 0.1 * np.abs(g)
+    np.testing.assert_allclose(p.cpu().numpy(), pr, rtol=1e-5, atol=1e-6)
+    assert np.all(np.abs(m.cpu().numpy() - mr) <= 1e-6 * mabs)
+    np.testing.assert_allclose(v.cpu().numpy(), vr, rtol=1e-5, atol=0)
+    assert (p.cpu().numpy() >= 0).all()
+
+
+def test_training_step_gradient_matches_oracle(tiny):
+    """The gradient a training step applies (adjoint of the map loss + VRT)
+    against the oracle's: oracle.backward over every ray + oracle VRT."""
+    import torch
+    s, rend, B, keys, K, c2w = tiny
+    H, W = rend.H, rend.W
+    rng = np.random.default_rng(14)
+    sig = torch.from_numpy(s.sigma).cuda()
+    f = torch.from_numpy(s.feat).cuda()
+    Ft = torch.from_numpy(rng.normal(size=(rend.P, rend.V, f.shape[1], H, W)).astype(np.float32)).cuda()
+    F, A, T = rend.render(sig, f, 0.01)
+    R = float(rend.P * rend.V * H * W)
+    dF = (F - Ft) / R
+    ds, df = rend.backward(sig, f, F, T, dF, None, 0.01)
+    lam = 0.25
+    _, df = rend.vrt(f, lam, d_feat=df)
+    o, d = oracle.camera_rays(K, c2w, H, W)
+    gs = np.zeros(s.n)
+    gf = np.zeros((s.n, f.shape[1]))
+    dF_np = dF.cpu().numpy().astype(np.float64)
+    for p in range(B.shape[0]):
+        ok, ol, _, _, _ = oracle.pose_occupancy(s.ijk, s.depth, s.bone, s.weight, B[p])
+        for v in range(rend.V):
+            gF = dF_np[p, v].reshape(f.shape[1], -1).T
+            a, b = oracle.backward(o[v].reshape(-1, 3), d[v].reshape(-1, 3), s.depth, ok, ol, s.sigma, s.feat,
+                                   0.01, gF)
+            gs += a
+            gf += b
+        gf += otr.vrt(keys[p], s.feat.astype(np.float64), lam)[1]
+    e_s = np.abs(ds.cpu().numpy() - gs).max() / np.abs(gs).max()
+    e_f = np.abs(df.cpu().numpy() - gf).max() / np.abs(gf).max()
+    log(f"training-step gradient: dsigma rel_max {e_s:.2e}, dfeat rel_max {e_f:.2e}")
+    assert e_s <= 1e-4 and e_f <= 1e-4
+
+
+def test_training_fits_target_maps(tiny):
+    """Targets rendered from a seeded FLUT; training starts from another seeded
+    FLUT.  The map loss falls by a large factor; with the VRT on, the features
+    of colliding leaves end closer to their cell winner's than without it."""
+    import torch
+    s, rend, B, keys, _, _ = tiny
+    rng = np.random.default_rng(15)
+    sig_t = torch.from_numpy(s.sigma).cuda()
+    f_t = torch.from_numpy(s.feat).cuda()
+    Ft, At, _ = rend.render(sig_t, f_t, 0.01)
+    results = {}
+    for lam in (0.0, 0.05):
+        sig = torch.from_numpy(rng.uniform(5, 50, s.n).astype(np.float32)).cuda()
+        f = torch.from_numpy(rng.normal(size=s.feat.shape).astype(np.float32)).cuda()
+        st = rend.train_state(sig, f)
+        first = rend.train_step(sig, f, st, Ft, At, lr=0.05, lambda_vrt=lam)
+        for _ in range(150):
+            last = rend.train_step(sig, f, st, Ft, At, lr=0.05, lambda_vrt=lam)
+        vrt_end, _ = rend.vrt(f, 1.0)
+        results[lam] = (first["map"], last["map"], vrt_end)
+        log(f"lambda_vrt {lam}: map loss {first['map']:.4f} -> {last['map']:.4f}, VRT measure {vrt_end:.4f}")
+        assert (sig >= 0).all()
+    for lam, (a, b, _) in results.items():
+        assert b < 0.2 * a, lam
+    assert results[0.05][2] < results[0.0][2]
