@@ -23,6 +23,9 @@ Articulated Neural Pets with Appearance and Motion Synthesis", 2022):
 * ``render``/``backward``    - Eq. 5 and Eq. 6 over the exact ray/voxel chords,
                                the coarse opacity map and the early stop at
                                lambda_th (C code in ``ray_oracle.c``);
+* ``render_sh``/``sh_basis`` - Eq. 5 with the view-dependent features of Eq. 2
+                               (real SH up to degree 2) at the canonical ray
+                               direction d^c = (R_i^t)^-1 d;
 * ``mlp``                    - FP64 reference of the ray-interval proposal MLP
                                (not in the paper);
 * ``train``                  - the FLUT training step: the voxel regularisation
@@ -81,6 +84,12 @@ def _load():
     lib.oracle_backward.argtypes = [ctypes.c_int64, P, P, ctypes.c_int, ctypes.c_double,
                                     ctypes.c_int64, P, P, ctypes.c_int, P, P, ctypes.c_double,
                                     P, P, P, P, ctypes.c_int]
+    lib.oracle_render_sh.restype = ctypes.c_int
+    lib.oracle_render_sh.argtypes = [ctypes.c_int64, P, P, ctypes.c_int, ctypes.c_double,
+                                     ctypes.c_int64, P, P, ctypes.c_int, ctypes.c_int, P, P, P, P,
+                                     ctypes.c_double, P, P, P, P, P, ctypes.c_int]
+    lib.oracle_sh_basis.restype = None
+    lib.oracle_sh_basis.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double, P]
     lib.oracle_max_threads.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -332,6 +341,56 @@ def render(o: np.ndarray, d: np.ndarray, depth: int, occ_key: np.ndarray, occ_le
                            _ptr(out["dist"]), int(n_threads))
     if rc != 0:
         raise MemoryError("oracle_render failed")
+    return out
+
+
+def sh_basis(H: int, dirs: np.ndarray) -> np.ndarray:
+    """Real SH basis values Y_0..Y_{H-1} (Eq. 2; H = 1, 4, 9) at unit directions
+    [n][3], from ray_oracle.c."""
+    lib = _load()
+    dirs = np.asarray(dirs, dtype=np.float64).reshape(-1, 3)
+    out = np.zeros((dirs.shape[0], 9))
+    for i, (x, y, z) in enumerate(dirs.tolist()):
+        lib.oracle_sh_basis(int(H), x, y, z, _ptr(out[i]))
+    return out[:, :H]
+
+
+def dominant_bone(bone: np.ndarray, weight: np.ndarray) -> np.ndarray:
+    """Per leaf, the bone of its largest skin weight (the first of equal ones):
+    the bone whose rotation stands for the voxel rotation R_i^t."""
+    bone = np.asarray(bone)
+    weight = np.asarray(weight)
+    slot = np.argmax(weight, axis=0)
+    return bone[slot, np.arange(bone.shape[1])].astype(np.int32)
+
+
+def render_sh(o: np.ndarray, d: np.ndarray, depth: int, occ_key: np.ndarray, occ_leaf: np.ndarray,
+              sigma: np.ndarray, feat: np.ndarray, H: int, dom_bone: np.ndarray, B_pose: np.ndarray,
+              lambda_th: float, n_threads: int = 0):
+    """Eq. 5 with the view-dependent feature S(f, d^c) of Eq. 2: feat [N][H][C]
+    SH coefficients, d^c = R^T d with R the rotation of the leaf's dominant bone
+    in the pose (B_pose [J][3][4]).  Returns F [n][C], A, T and the guard-band
+    measures min_gap, min_tgap."""
+    lib = _load()
+    o = np.ascontiguousarray(o, dtype=np.float64).reshape(-1, 3)
+    d = np.ascontiguousarray(d, dtype=np.float64).reshape(-1, 3)
+    n = o.shape[0]
+    feat = np.ascontiguousarray(feat, dtype=np.float64)
+    N = feat.shape[0]
+    C = feat.shape[-1]
+    assert feat.shape == (N, H, C)
+    rot = np.ascontiguousarray(np.asarray(B_pose, dtype=np.float64)[:, :, :3].reshape(-1, 9))
+    out = {"F": np.zeros((n, C)), "A": np.zeros(n), "T": np.zeros(n), "min_gap": np.zeros(n),
+           "min_tgap": np.zeros(n)}
+    rc = lib.oracle_render_sh(n, _ptr(o), _ptr(d), 1 << (depth + 1), 1.0 / (1 << depth), len(occ_key),
+                              _ptr(np.ascontiguousarray(occ_key, dtype=np.int64)),
+                              _ptr(np.ascontiguousarray(occ_leaf, dtype=np.int64)), C, H,
+                              _ptr(np.ascontiguousarray(sigma, dtype=np.float64)), _ptr(feat),
+                              _ptr(np.ascontiguousarray(dom_bone, dtype=np.int32)), _ptr(rot), float(lambda_th),
+                              _ptr(out["F"]), _ptr(out["A"]), _ptr(out["T"]), _ptr(out["min_gap"]),
+                              _ptr(out["min_tgap"]), int(n_threads))
+    if rc != 0:
+        raise MemoryError("oracle_render_sh failed")
     return out
 
 

@@ -237,6 +237,103 @@ int oracle_render(int64_t n, const double* o, const double* d, int G, double h,
 }
 
 /*
+ * Real spherical-harmonic basis Y_0 .. Y_{H-1} (H = 1, 4 or 9: degrees 0, 1,
+ * 2) at the unit direction (x, y, z): the orthonormal real harmonics,
+ * ordered by degree l and then m = -l .. l, without the Condon-Shortley
+ * phase:  l = 0: 1/(2 sqrt(pi));  l = 1: sqrt(3/(4 pi)) * (y, z, x);
+ * l = 2: sqrt(15/pi)/2 * xy, sqrt(15/pi)/2 * yz, sqrt(5/pi)/4 * (3z^2 - 1),
+ *        sqrt(15/pi)/2 * xz, sqrt(15/pi)/4 * (x^2 - y^2).
+ */
+void oracle_sh_basis(int H, double x, double y, double z, double* Y) {
+    const double pi = 3.14159265358979323846;
+    Y[0] = 0.5 / sqrt(pi);
+    if (H < 4) return;
+    const double c1 = sqrt(3.0 / (4.0 * pi));
+    Y[1] = c1 * y;
+    Y[2] = c1 * z;
+    Y[3] = c1 * x;
+    if (H < 9) return;
+    const double c2 = 0.5 * sqrt(15.0 / pi);
+    Y[4] = c2 * x * y;
+    Y[5] = c2 * y * z;
+    Y[6] = 0.25 * sqrt(5.0 / pi) * (3.0 * z * z - 1.0);
+    Y[7] = c2 * x * z;
+    Y[8] = 0.5 * c2 * (x * x - y * y);
+}
+
+/*
+ * Eq. 5 with view-dependent features (Eq. 2): as oracle_render (without the
+ * debug outputs), but sample i contributes w_i S(f_i, d^c) with
+ * S_c = sum_h k_{h,c} Y_h(d^c), the coefficients feat [N][H][C] of the
+ * winner leaf, and the canonical direction d^c = R^T d of the ray's unit
+ * direction d, R the rotation (row-major 3x3, rot [J][9]) of the leaf's
+ * dominant bone dom_bone [N] (the reading of the voxel rotation R_i^t).
+ */
+int oracle_render_sh(int64_t n, const double* o, const double* d, int G, double h,
+                     int64_t M, const int64_t* occ_key, const int64_t* occ_leaf,
+                     int C, int H, const double* sigma, const double* feat, const int32_t* dom_bone,
+                     const double* rot, double lambda_th, double* F, double* A, double* Tfin,
+                     double* min_gap, double* min_tgap, int n_threads) {
+    int failed = 0;
+    int64_t cap = max_points(G);
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel
+#endif
+    {
+        double* pts = (double*)malloc(sizeof(double) * (size_t)cap);
+        sample_t* smp = (sample_t*)malloc(sizeof(sample_t) * (size_t)cap);
+        if (!pts || !smp) {
+#ifdef _OPENMP
+#pragma omp atomic write
+#endif
+            failed = 1;
+        } else {
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 64)
+#endif
+            for (int64_t r = 0; r < n; ++r) {
+                double gap, ta, tb;
+                const double* dr = d + 3 * r;
+                int64_t ns = ray_samples(o + 3 * r, dr, G, h, M, occ_key, occ_leaf, smp, cap, pts, &gap, &ta, &tb);
+                double T = 1.0, acc = 0.0, tg = INFINITY;
+                double* Fr = F + (size_t)r * C;
+                for (int c = 0; c < C; ++c) Fr[c] = 0.0;
+                for (int64_t i = 0; i < ns; ++i) {
+                    const int64_t leaf = smp[i].leaf;
+                    const double* R = rot + 9 * (size_t)dom_bone[leaf];
+                    double dc[3], Y[9];
+                    for (int a = 0; a < 3; ++a) dc[a] = R[a] * dr[0] + R[3 + a] * dr[1] + R[6 + a] * dr[2];
+                    oracle_sh_basis(H, dc[0], dc[1], dc[2], Y);
+                    const double s = sigma[leaf];
+                    const double tau = s * smp[i].delta;
+                    const double w = T * -expm1(-tau);
+                    for (int c = 0; c < C; ++c) {
+                        double S = 0.0;
+                        for (int k = 0; k < H; ++k) S += feat[((size_t)leaf * H + k) * C + c] * Y[k];
+                        Fr[c] += w * S;
+                    }
+                    acc += w;
+                    T = T * exp(-tau);
+                    if (lambda_th > 0.0) {
+                        double g = fabs(T - lambda_th) / lambda_th;
+                        if (g < tg) tg = g;
+                    }
+                    if (T < lambda_th) break;
+                }
+                A[r] = acc;
+                Tfin[r] = T;
+                min_gap[r] = gap;
+                min_tgap[r] = tg;
+            }
+        }
+        free(pts);
+        free(smp);
+    }
+    return failed ? -1 : 0;
+}
+
+/*
  * Adjoint of oracle_render for the loss whose gradients with respect to the
  * outputs are gF [n][C] and gA [n] (gA may be NULL for zero).  Accumulates
  * (+=) into dsigma [N] and dfeat [N][C].  Returns 0 or -1.
