@@ -223,6 +223,29 @@ def depth_leg(args, r, sig, feat, out, fp32_geom, torch, C, es, rays):
             "rays_with_depth": finite}
 
 
+def sh_leg(args, r, scene, out, fp32_geom, torch, C, rays, nsh=9):
+    """View-dependent features on the main workload: nsh real-SH coefficient
+    blocks of C channels per leaf (seeded), canonical direction from the
+    dominant bone's rotation."""
+    import numpy as np
+    rng = np.random.default_rng(40)
+    sig = torch.from_numpy(scene.sigma).cuda()
+    k = torch.from_numpy(rng.normal(size=(scene.n, nsh, C)).astype(np.float32)).cuda()
+    t = _timed(torch, lambda: r.render_sh(sig, k, args.lambda_th, fp32_geom=fp32_geom, out=out), args.proposal_steps)
+    r.render_sh(sig, k, args.lambda_th, fp32_geom=fp32_geom, out=out, timing=True)
+    tm = r.timing()
+    st = r.stats()
+    # per composited sample: sigma, the nsh x C coefficients, the winner id, the dominant bone
+    per_sample = 4 * (1 + nsh * C) + 4 + 1
+    per_launch = (st["samples"] * per_sample + st["tile_rays"] * (4 * (C + 2))) / max(tm["n_render"], 1)
+    avg = tm["render"] / max(tm["n_render"], 1) / 1e3
+    del k
+    return {"workload": f"view-dependent features on the main workload: H = {nsh} SH blocks of C = {C}, FP32",
+            "mrays_s": round(rays / t / 1e6, 2), "ms_per_step": round(t * 1e3, 3),
+            "render_ms": round(tm["render"], 3), "algorithmic_bytes_per_sample": per_sample,
+            "render_hbm_frac": round(per_launch / avg / 1e9 / HBM_PEAK_GBS, 4)}
+
+
 def adjoint_leg(args, art, sg, torch):
     """Differentiation form: L = 1/2 |F - F*|^2 over 4 cameras at 512^2, one
     pose; the adjoint kernel re-traverses every ray (per-ray recomputation)."""
@@ -482,6 +505,9 @@ def main():
     if not args.no_forms:
         print("[bench] depth buffer", file=sys.stderr, flush=True)
         line["depth_form"] = depth_leg(args, r, sig, feat, out, fp32_geom, torch, cfg.C, es, rays_per_step)
+        if cfg.storage == "f32":
+            print("[bench] view-dependent features", file=sys.stderr, flush=True)
+            line["sh_form"] = sh_leg(args, r, scene, out, fp32_geom, torch, cfg.C, rays_per_step)
     del Fm, Am, Tm, out
     torch.cuda.empty_cache()
     if not args.no_forms:

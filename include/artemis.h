@@ -237,6 +237,24 @@ art_status art_render_depth(art_ctx* ctx, int C, art_dtype dtype, const void* si
                             float* out_tfinal, float* out_depth);
 
 /*
+ * Forward render (as art_render) with view-dependent features: Eq. 5 with
+ * S(f, d^c) of Eq. 2 in place of f.  feat: device [n][H][C] (FP32 or BF16 per
+ * dtype), H = 1, 4 or 9 real spherical-harmonic coefficients (degrees 0..2,
+ * orthonormal, ordered by degree then m = -l..l, no Condon-Shortley phase:
+ * Y = 1/(2 sqrt pi); sqrt(3/(4 pi)) (y, z, x); sqrt(15/pi)/2 xy,
+ * sqrt(15/pi)/2 yz, sqrt(5/pi)/4 (3z^2 - 1), sqrt(15/pi)/2 xz,
+ * sqrt(15/pi)/4 (x^2 - y^2)) of C channels per leaf.  A sample of leaf i
+ * contributes w_i sum_h k_{i,h} Y_h(d^c), d^c = R^T d with d the ray's unit
+ * direction and R the rotation of the leaf's dominant bone (largest skin
+ * weight) in the pose: the reading of the voxel rotation R_i^t.  Outputs as
+ * art_render.
+ * Errors: as art_render; ART_EUNSUPPORTED for H not in {1, 4, 9} or more than
+ * 64 bones.
+ */
+art_status art_render_sh(art_ctx* ctx, int C, int H, art_dtype dtype, const void* sigma, const void* feat,
+                         float lambda_th, unsigned flags, float* out_feat, float* out_alpha, float* out_tfinal);
+
+/*
  * Voxel regularisation term of Section 3.1 ("Training", Eq. 10) for every pose
  * and its gradient with respect to the features.  For each canonical leaf i
  * whose posed centre lies inside the posed root, Q(p_i^t, T^t) is the feature

@@ -180,6 +180,28 @@ class Renderer:
                     "art_render_depth")
         return F, A, T, D
 
+    def render_sh(self, sigma, feat, lambda_th: float = LAMBDA_TH, fp32_geom: bool = False, timing: bool = False,
+                  out=None, want_tfinal: bool = True):
+        """Feature maps with view-dependent features (Eq. 2): feat [n][H][C] real
+        SH coefficients (H = 1, 4 or 9).  Returns F [P][V][C][H][W], A, T."""
+        torch = self._torch
+        if feat.dim() != 3:
+            raise ValueError("feat must be [n][H][C]")
+        H = int(feat.shape[1])
+        C, dtype = self._flut(sigma, feat.reshape(feat.shape[0], -1))
+        C //= H
+        dev = sigma.device
+        if out is None:
+            F = torch.empty((self.P, self.V, C, self.H, self.W), dtype=torch.float32, device=dev)
+            A = torch.empty((self.P, self.V, self.H, self.W), dtype=torch.float32, device=dev)
+            T = torch.empty_like(A) if want_tfinal else None
+        else:
+            F, A, T = out
+        self._check(self.lib.art_render_sh(self._h, C, H, dtype, _tptr(sigma), _tptr(feat), float(lambda_th),
+                                           self._flags(fp32_geom, timing), _tptr(F), _tptr(A), _tptr(T)),
+                    "art_render_sh")
+        return F, A, T
+
     def proposal_labels(self, sigma, feat, lambda_th: float = LAMBDA_TH, fp32_geom: bool = False,
                         timing: bool = False, out=None):
         """Interval labels [P][V][H][W][2] = (u_near, u_far) of every ray from the

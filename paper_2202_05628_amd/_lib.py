@@ -43,6 +43,7 @@ SIGNATURES = [
     ("art_proposal_labels", _I, [_P, _I, _I, _P, _P, _F, _U, _P]),
     ("art_render_proposal", _I, [_P, _I, _I, _P, _P, _F, _U, _P, _F, _F, _P, _P, _P]),
     ("art_render_depth", _I, [_P, _I, _I, _P, _P, _F, _U, _F, _P, _P, _P, _P]),
+    ("art_render_sh", _I, [_P, _I, _I, _I, _P, _P, _F, _U, _P, _P, _P]),
     ("art_vrt", _I, [_P, _I, _I, _P, _F, _U, _P, ctypes.POINTER(ctypes.c_double)]),
     ("art_query", _I, [_P, _I, _U, _L, _P, _P]),
     ("art_flut_adam", _I, [_P, _L, _P, _P, _P, _P, _I, _F, _F, _F, _F, _F]),

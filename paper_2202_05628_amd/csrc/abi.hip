@@ -257,6 +257,8 @@ struct PassOut {
     // depth buffer (mode 5)
     float* out_depth = nullptr;
     float depth_sigma = 0.0f;
+    // view-dependent features (mode 6)
+    int sh_H = 1;
     // debug
     int max_hits = 0;
     int debug_view = 0;
@@ -368,6 +370,10 @@ art_status run_batch(art_ctx* ctx, const CallPlan& pl, int mode, float lambda, c
     r.near_only = o.near_only;
     if (o.out_depth) r.out_depth = o.out_depth + m0 * HW;
     r.depth_sigma = o.depth_sigma;
+    r.sh_H = o.sh_H;
+    r.J = ctx->J;
+    r.dom_bone = ctx->dom_bone.as<uint8_t>();
+    r.bone_rot = ctx->B32.as<float>() + (size_t)p0 * ctx->J * 12;
     r.max_hits = o.max_hits;
     r.debug_view = o.debug_view;
     r.hit_leaf = o.hit_leaf;
@@ -588,6 +594,10 @@ hipError_t launch_render(const RenderLaunch& r, hipStream_t st) {
     a.near_only = r.near_only ? 1 : 0;
     a.out_depth = r.out_depth;
     a.depth_sigma = r.depth_sigma;
+    a.sh_H = r.sh_H;
+    a.J = r.J;
+    a.dom_bone = r.dom_bone;
+    a.bone_rot = r.bone_rot;
     a.max_hits = r.max_hits;
     a.debug_view = r.debug_view;
     a.hit_leaf = r.hit_leaf;
@@ -636,7 +646,7 @@ void art_destroy(art_ctx* ctx) {
         DeviceGuard g(ctx->device);
         if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
         else (void)hipDeviceSynchronize();
-        DevBuf* bufs[] = {&ctx->ijk, &ctx->bone, &ctx->weight, &ctx->parent, &ctx->rest, &ctx->pose,
+        DevBuf* bufs[] = {&ctx->ijk, &ctx->bone, &ctx->weight, &ctx->dom_bone, &ctx->parent, &ctx->rest, &ctx->pose,
                           &ctx->cam, &ctx->B64, &ctx->B32, &ctx->Gtmp,
                           &ctx->s.keys0, &ctx->s.keys1, &ctx->s.bmap, &ctx->s.wpref, &ctx->s.hist,
                           &ctx->s.digit_tot, &ctx->s.blk0, &ctx->s.blk1, &ctx->s.occ_key, &ctx->s.occ_win,
@@ -700,25 +710,40 @@ art_status art_set_skin(art_ctx* ctx, const uint8_t* bone, const float* weight) 
             return fail(ctx, ART_EINVAL, "skin weights must be finite and >= 0");
         mb = std::max(mb, (int)bone[i]);
     }
+    // the bone of each leaf's largest weight (the first of equal ones) stands
+    // for the leaf's rotation in the view-dependent features
+    std::vector<uint8_t> dom(n);
+    for (size_t i = 0; i < n; ++i) {
+        int best = 0;
+        for (int k = 1; k < 4; ++k)
+            if (weight[k * n + i] > weight[best * n + i]) best = k;
+        dom[i] = bone[best * n + i];
+    }
     DeviceGuard g(ctx->device);
-    DevBuf b, w;
+    DevBuf b, w, db;
     ART_TRY_HIP(b.ensure(4 * n), "device allocation");
     hipError_t e = w.ensure(4 * n * 4);
+    if (e == hipSuccess) e = db.ensure(n);
     if (e != hipSuccess) {
         b.release();
+        w.release();
         return hip_fail(ctx, e, "device allocation");
     }
     e = hipMemcpy(b.p, bone, 4 * n, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(w.p, weight, 4 * n * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(db.p, dom.data(), n, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         b.release();
         w.release();
+        db.release();
         return hip_fail(ctx, e, "copy");
     }
     ctx->bone.release();
     ctx->weight.release();
+    ctx->dom_bone.release();
     ctx->bone = b;
     ctx->weight = w;
+    ctx->dom_bone = db;
     ctx->has_skin = true;
     ctx->max_bone = mb;
     return ART_OK;
@@ -879,6 +904,23 @@ art_status art_render_depth(art_ctx* ctx, int C, art_dtype dtype, const void* si
     o.out_depth = out_depth;
     o.depth_sigma = depth_sigma;
     return render_call(ctx, C, dtype, sigma, feat, lambda_th, flags, 5, o, 0, ctx->P);
+}
+
+art_status art_render_sh(art_ctx* ctx, int C, int H, art_dtype dtype, const void* sigma, const void* feat,
+                         float lambda_th, unsigned flags, float* out_feat, float* out_alpha, float* out_tfinal) {
+    if (!ctx) return ART_EINVAL;
+    if (!out_feat || !out_alpha) return fail(ctx, ART_EINVAL, "out_feat / out_alpha is NULL");
+    if (H != 1 && H != 4 && H != 9) return fail(ctx, ART_EUNSUPPORTED, "H must be 1, 4 or 9 (SH degree <= 2)");
+    if (ctx->J > kMaxBonesSH)
+        return fail(ctx, ART_EUNSUPPORTED, "view-dependent features support at most " + std::to_string(kMaxBonesSH) +
+                                               " bones");
+    DeviceGuard g(ctx->device);
+    PassOut o;
+    o.out_feat = out_feat;
+    o.out_alpha = out_alpha;
+    o.out_tfinal = out_tfinal;
+    o.sh_H = H;
+    return render_call(ctx, C, dtype, sigma, feat, lambda_th, flags, 6, o, 0, ctx->P);
 }
 
 art_status art_vrt(art_ctx* ctx, int C, art_dtype dtype, const void* feat, float lambda_vrt, unsigned flags,

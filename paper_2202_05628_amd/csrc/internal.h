@@ -83,6 +83,7 @@ struct RunStats {
 };
 
 constexpr int kNumStats = 14;
+constexpr int kMaxBonesSH = 64;       // bone rotations staged in LDS by the view-dependent (SH) render
 constexpr int kSortBlocks = 512;      // fixed grid (per pose) of the radix-sort passes
 constexpr int kScanBlocks = 256;      // fixed grid (per pose) of device-sized scans
 constexpr int kUniqueBlocks = 512;    // fixed grid (per pose) of the unique / compaction step
@@ -125,6 +126,7 @@ struct art_ctx {
     art::DevBuf ijk;      // uint16 [3][n]
     art::DevBuf bone;     // uint8 [4][n]
     art::DevBuf weight;   // float [4][n]
+    art::DevBuf dom_bone; // uint8 [n]: bone of each leaf's largest skin weight
     bool has_skin = false;
     int max_bone = -1;
 
@@ -225,7 +227,8 @@ __global__ void k_pairs(const PoseCounters* __restrict__ c, unsigned long long* 
 struct RenderLaunch {
     int C, storage;
     bool fp32;
-    int mode;            // 0 forward, 1 backward, 2 debug hit lists, 3 labels, 4 proposal, 5 forward + depth
+    int mode;            // 0 forward, 1 backward, 2 debug hit lists, 3 labels, 4 proposal, 5 forward + depth,
+                         // 6 forward with SH features
     int depth;
     int Pb, V, H, W;     // poses in the launch (slots 0..Pb-1), views, image
     int Vg, ngroups;     // view groups of the tile lists
@@ -253,6 +256,10 @@ struct RenderLaunch {
     bool near_only;          // mode 4: the interval ends at t_b
     float* out_depth;        // [Pb][V][H][W] (mode 5)
     float depth_sigma;       // density threshold of the depth buffer
+    int sh_H;                // SH coefficients per leaf (mode 6)
+    int J;
+    const uint8_t* dom_bone; // [n] (mode 6)
+    const float* bone_rot;   // [Pb][J][12] bone transforms of the launch's poses (mode 6)
     int max_hits;
     int debug_view;
     int32_t* hit_leaf;

@@ -118,6 +118,10 @@ struct RArgs {
     float f2_tau;                          // F2 threshold on T (< 0: off)
     int near_only;                         // MODE 4: only u_near is used (interval ends at t_b)
     float* out_depth;                      // [Pb][V][H][W] depth buffer (MODE 5)
+    int sh_H;                              // MODE 6: SH coefficients per leaf (1, 4 or 9)
+    int J;                                 // bones
+    const uint8_t* dom_bone;               // [n] dominant bone of each canonical leaf (MODE 6)
+    const float* bone_rot;                 // [Pb][J][12] bone transforms of the launch's poses (MODE 6)
     float depth_sigma;                     // MODE 5: density threshold of the depth buffer
     int max_hits;
     int debug_view;                        // view whose hit lists are recorded (MODE 2)
@@ -127,13 +131,11 @@ struct RArgs {
     unsigned long long* stats;             // RunStats
 };
 
+// C features of one FLUT row block starting at element `foff`.
 template <int C, int ST>
-__device__ inline void load_sample(const void* psig, const void* pfeat, uint32_t row, float& sg,
-                                   float* f) {
+__device__ inline void load_feat(const void* pfeat, size_t foff, float* f) {
     if constexpr (ST == 0) {
-        sg = reinterpret_cast<const float*>(psig)[row];
-        const float4* p = reinterpret_cast<const float4*>(reinterpret_cast<const float*>(pfeat) +
-                                                          (size_t)row * C);
+        const float4* p = reinterpret_cast<const float4*>(reinterpret_cast<const float*>(pfeat) + foff);
 #pragma unroll
         for (int q = 0; q < C / 4; ++q) {
             const float4 v = p[q];
@@ -143,8 +145,7 @@ __device__ inline void load_sample(const void* psig, const void* pfeat, uint32_t
             f[4 * q + 3] = v.w;
         }
     } else {
-        sg = bf16_to_f32(reinterpret_cast<const uint16_t*>(psig)[row]);
-        const uint16_t* base = reinterpret_cast<const uint16_t*>(pfeat) + (size_t)row * C;
+        const uint16_t* base = reinterpret_cast<const uint16_t*>(pfeat) + foff;
         if constexpr (C % 8 == 0) {
             const uint4* p = reinterpret_cast<const uint4*>(base);
 #pragma unroll
@@ -165,6 +166,36 @@ __device__ inline void load_sample(const void* psig, const void* pfeat, uint32_t
             f[3] = __uint_as_float(v.y & 0xFFFF0000u);
         }
     }
+}
+
+// Density of FLUT row `row` and the C features at element offset `foff`.
+template <int C, int ST>
+__device__ inline void load_sample(const void* psig, const void* pfeat, uint32_t row, size_t foff, float& sg,
+                                   float* f) {
+    if constexpr (ST == 0) sg = reinterpret_cast<const float*>(psig)[row];
+    else sg = bf16_to_f32(reinterpret_cast<const uint16_t*>(psig)[row]);
+    load_feat<C, ST>(pfeat, foff, f);
+}
+
+// Real spherical-harmonic basis of degree <= 2 (Eq. 2) at the unit direction
+// (x, y, z): the orthonormal real harmonics ordered by degree l and then
+// m = -l .. l, without the Condon-Shortley phase.  Entries beyond H are 0.
+__device__ inline void sh_basis(int H, float x, float y, float z, float* Y) {
+    const float k0 = 0.28209479177387814f;   // 1 / (2 sqrt(pi))
+    const float k1 = 0.4886025119029199f;    // sqrt(3 / (4 pi))
+    const float k2 = 1.0925484305920792f;    // sqrt(15 / pi) / 2
+    const float k3 = 0.31539156525252005f;   // sqrt(5 / pi) / 4
+    const float k4 = 0.5462742152960396f;    // sqrt(15 / pi) / 4
+    const bool d1 = H >= 4, d2 = H >= 9;
+    Y[0] = k0;
+    Y[1] = d1 ? k1 * y : 0.0f;
+    Y[2] = d1 ? k1 * z : 0.0f;
+    Y[3] = d1 ? k1 * x : 0.0f;
+    Y[4] = d2 ? k2 * x * y : 0.0f;
+    Y[5] = d2 ? k2 * y * z : 0.0f;
+    Y[6] = d2 ? k3 * (3.0f * z * z - 1.0f) : 0.0f;
+    Y[7] = d2 ? k2 * x * z : 0.0f;
+    Y[8] = d2 ? k4 * (x * x - y * y) : 0.0f;
 }
 
 // Opacity alpha = 1 - exp(-tau) of one sample, tau >= 0.  Below tau = 1/32 a
@@ -239,7 +270,11 @@ __device__ inline void root_span(const R* d, const R* q, const R* inv, R h, int 
 // 4 forward guided by proposed intervals (with full-traversal fallbacks),
 // 5 forward with the depth buffer (Section 5, hybrid rendering: the distance
 // along the unit ray at which it enters the first composited sample whose
-// density exceeds a threshold; +inf when there is none)
+// density exceeds a threshold; +inf when there is none),
+// 6 forward with view-dependent features (Eq. 2 in Eq. 5): the FLUT holds H
+// blocks of C SH coefficients per leaf, and a sample contributes
+// w sum_h k_h Y_h(d^c) at the canonical direction d^c = R^T d, R the rotation
+// of the leaf's dominant bone in the tile's pose
 #ifndef ART_RENDER_WAVES_PER_EU
 #define ART_RENDER_WAVES_PER_EU 3
 #endif
@@ -248,7 +283,7 @@ template <int C, int ST, typename R, int MODE>
 __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, int lane,
                                    uint32_t (*s_mask)[16][kMaskPitch],
                                    uint16_t (*s_pref)[16][kPrefPitch], uint32_t (*s_row)[kStage],
-                                   uint32_t (*s_coord)[kStage]) {
+                                   uint32_t (*s_coord)[kStage], float* s_rot) {
     constexpr int wv = 0;
     const int pvi = (int)(item / (uint32_t)a.TPV);   // pose-in-launch * V + view
     const int tile_in_view = (int)(item % (uint32_t)a.TPV);
@@ -271,6 +306,12 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
     const uint32_t* brick_mask = a.brick_mask + (size_t)pb * a.ncap * 16;
     const uint32_t* occ_win = a.occ_win + (size_t)pb * a.ncap;
     const size_t es = ST == 0 ? 4 : 2;
+    if constexpr (MODE == 6) {
+        // rotations (row-major 3x3) of the tile pose's bone transforms, for d^c = R^T d
+        const float* Bp = a.bone_rot + (size_t)pb * a.J * 12;
+        for (int e = lane; e < a.J * 9; e += kWave) s_rot[e] = Bp[(e / 9) * 12 + ((e % 9) / 3) * 4 + (e % 3)];
+        wave_sync();
+    }
 
 
     // ---- ray r_p = (o, d) of pixel (px, py) -----------------------------------
@@ -508,6 +549,7 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
         float fA[C];
 #pragma unroll
         for (int c = 0; c < C; ++c) fA[c] = 0.0f;
+        uint32_t domA = 0;   // MODE 6: dominant bone of the sample's leaf
         while (true) {
             const bool more = active && (inb || todo != 0ull);
             if (__ballot(more || hasA || hasI) == 0ull) break;
@@ -672,6 +714,9 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
             } else
 #endif
             if (hasA && active) {
+                // no FMA contraction here: every mode rounds w = T alpha and
+                // A += w identically (the FMAs below are explicit)
+#pragma clang fp contract(off)
                 const float tau = sgA * dlA;
                 const float al = sample_alpha(tau);
                 const float w = T * al;
@@ -688,8 +733,30 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
 #pragma unroll
                     for (int c = 0; c < C; ++c) unsafeAtomicAdd(&a.d_leaf_feat[(size_t)leaf * C + c], w * g[c]);
                 } else {
+                    if constexpr (MODE == 6) {
+                        // S_c = sum_h k_{h,c} Y_h(R^T d); the first block is the prefetched row
+                        const float* Rm = s_rot + domA * 9;
+                        const float dx = (float)d[0], dy = (float)d[1], dz = (float)d[2];
+                        float Y[9];
+                        sh_basis(a.sh_H, Rm[0] * dx + Rm[3] * dy + Rm[6] * dz, Rm[1] * dx + Rm[4] * dy + Rm[7] * dz,
+                                 Rm[2] * dx + Rm[5] * dy + Rm[8] * dz, Y);
+                        const float w0 = w * Y[0];
 #pragma unroll
-                    for (int c = 0; c < C; ++c) F[c] = __fmaf_rn(w, fA[c], F[c]);
+                        for (int c = 0; c < C; ++c) F[c] = __fmaf_rn(w0, fA[c], F[c]);
+#pragma unroll
+                        for (int hb = 1; hb < 9; ++hb) {
+                            if (hb < a.sh_H) {
+                                float fb[C];
+                                load_feat<C, ST>(a.feat, ((size_t)winA * a.sh_H + hb) * C, fb);
+                                const float wy = w * Y[hb];
+#pragma unroll
+                                for (int c = 0; c < C; ++c) F[c] = __fmaf_rn(wy, fb[c], F[c]);
+                            }
+                        }
+                    } else {
+#pragma unroll
+                        for (int c = 0; c < C; ++c) F[c] = __fmaf_rn(w, fA[c], F[c]);
+                    }
                     Aacc += w;
                     if constexpr (MODE == 2) {
                         if (nsamp < a.max_hits) {
@@ -724,7 +791,9 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
             sA0 = sI0;
             sA1 = sI1;
             winA = hasA ? winI : 0u;
-            load_sample<C, ST>(a.sigma, a.feat, winA, sgA, fA);
+            load_sample<C, ST>(a.sigma, a.feat, winA, (size_t)winA * (MODE == 6 ? (size_t)a.sh_H * C : (size_t)C),
+                               sgA, fA);
+            if constexpr (MODE == 6) domA = a.dom_bone[winA];
             hasI = hasB && active;
             dlI = dlB;
             dxI = dxB;
@@ -742,7 +811,9 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
                 sA1 = sB1;
                 // the FLUT row of the cell's collision winner
                 winA = occ_win[rowA];
-                load_sample<C, ST>(a.sigma, a.feat, winA, sgA, fA);
+                load_sample<C, ST>(a.sigma, a.feat, winA, (size_t)winA * (MODE == 6 ? (size_t)a.sh_H * C : (size_t)C),
+                               sgA, fA);
+            if constexpr (MODE == 6) domA = a.dom_bone[winA];
             }
 #endif
         }
@@ -801,12 +872,13 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
 // Persistent compositing kernel: each single-wave workgroup takes non-empty
 // tiles from the queue until it is exhausted (every wave reaches the exit).
 template <int C, int ST, typename R, int MODE>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MODE == 1 ? 1 : ART_RENDER_WAVES_PER_EU)))
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MODE == 1 ? 1 : (MODE == 6 ? 2 : ART_RENDER_WAVES_PER_EU))))
 void k_render(RArgs a) {
     __shared__ uint32_t s_mask[1][16][kMaskPitch];
     __shared__ uint16_t s_pref[1][16][kPrefPitch];
     __shared__ uint32_t s_row[1][kStage];
     __shared__ uint32_t s_coord[1][kStage];
+    __shared__ float s_rot[MODE == 6 ? kMaxBonesSH * 9 : 1];
     const int lane = threadIdx.x & 63;
     const uint32_t n_items = *a.n_items;
     // The work list may be cut into kQueues contiguous parts (neighbouring
@@ -827,7 +899,7 @@ void k_render(RArgs a) {
             if (lane == 0) idx = atomicAdd(&a.queue[qi], 1u);
             idx = beg + (uint32_t)__shfl((int)idx, 0, kWave);
             if (idx >= end) break;
-            render_tile<C, ST, R, MODE>(a, a.items[idx], idx, lane, s_mask, s_pref, s_row, s_coord);
+            render_tile<C, ST, R, MODE>(a, a.items[idx], idx, lane, s_mask, s_pref, s_row, s_coord, s_rot);
             wave_sync();
         }
     }
@@ -845,6 +917,7 @@ hipError_t launch_render_mode(const RenderLaunch& r, const RArgs& a, unsigned gr
         case 3: hipLaunchKernelGGL((k_render<C, ST, R, 3>), dim3(grid), dim3(64), 0, st, a); break;
         case 4: hipLaunchKernelGGL((k_render<C, ST, R, 4>), dim3(grid), dim3(64), 0, st, a); break;
         case 5: hipLaunchKernelGGL((k_render<C, ST, R, 5>), dim3(grid), dim3(64), 0, st, a); break;
+        case 6: hipLaunchKernelGGL((k_render<C, ST, R, 6>), dim3(grid), dim3(64), 0, st, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
