@@ -246,6 +246,26 @@ def sh_leg(args, r, scene, out, fp32_geom, torch, C, rays, nsh=9):
             "render_hbm_frac": round(per_launch / avg / 1e9 / HBM_PEAK_GBS, 4)}
 
 
+def shading_leg(args, r, F, torch, C, maps=32):
+    """The Light shading network (FP16 matrix cores) on `maps` rendered feature
+    maps of the main workload; achieved TFLOP/s of its convolutions."""
+    import scenegen as sgm
+    H, W = F.shape[-2], F.shape[-1]
+    Fm = F.reshape(-1, C, H, W)[:maps].contiguous()
+    r.set_shading_weights(C, sgm.make_shading_weights(C))
+    out = torch.empty((maps, 4, H, W), dtype=torch.float32, device=F.device)
+    t = _timed(torch, lambda: r.shade(Fm, out=out), args.proposal_steps)
+    # multiply-adds of the 3x3 convolutions (Cin of layer 0 padded to 32) and the head
+    px = maps * H * W
+    macs = 9 * px * (32 * 32 + 32 * 32) + 9 * px // 4 * (32 * 64 + 64 * 64) + 9 * px // 16 * (64 * 128 + 128 * 128) \
+        + 9 * px // 64 * (128 * 256 + 256 * 256) + 9 * px // 16 * (384 * 128 + 128 * 128) \
+        + 9 * px // 4 * (192 * 64 + 64 * 64) + 9 * px * (96 * 32 + 32 * 32) + px * 32 * 4
+    tflops = 2 * macs / t / 1e12
+    return {"workload": f"Light shading network, {maps} maps of {H}x{W}, C = {C}, FP16 operands, FP32 accumulation",
+            "ms": round(t * 1e3, 3), "maps_per_s": round(maps / t, 1), "tflop_per_map": round(2 * macs / maps / 1e12, 4),
+            "achieved_tflops": round(tflops, 1), "peak_tflops": 2500.0, "frac": round(tflops / 2500.0, 4)}
+
+
 def adjoint_leg(args, art, sg, torch):
     """Differentiation form: L = 1/2 |F - F*|^2 over 4 cameras at 512^2, one
     pose; the adjoint kernel re-traverses every ray (per-ray recomputation)."""
@@ -505,6 +525,8 @@ def main():
     if not args.no_forms:
         print("[bench] depth buffer", file=sys.stderr, flush=True)
         line["depth_form"] = depth_leg(args, r, sig, feat, out, fp32_geom, torch, cfg.C, es, rays_per_step)
+        print("[bench] shading network", file=sys.stderr, flush=True)
+        line["shading_form"] = shading_leg(args, r, Fm, torch, cfg.C)
         if cfg.storage == "f32":
             print("[bench] view-dependent features", file=sys.stderr, flush=True)
             line["sh_form"] = sh_leg(args, r, scene, out, fp32_geom, torch, cfg.C, rays_per_step)

@@ -255,6 +255,34 @@ art_status art_render_sh(art_ctx* ctx, int C, int H, art_dtype dtype, const void
                          float lambda_th, unsigned flags, float* out_feat, float* out_alpha, float* out_tfinal);
 
 /*
+ * Neural shading network G of Section 3.1 ("Neural Shading"), the "Light"
+ * variant of the runtime analysis (Tab. 5): a single encoder-decoder (U-Net)
+ * branch that turns the feature map F into RGB and an opacity map, in half
+ * precision.  Layers (3x3 convolutions, padding 1, bias, ReLU): encoder levels
+ * of 32, 64, 128, 256 channels, two convolutions each, 2x2 max pooling between
+ * levels; decoder levels of 128, 64, 32 channels whose first convolution reads
+ * the concatenation [encoder output of the level, nearest 2x upsampling of the
+ * level below], then a second convolution; a 1x1 head to 4 channels and a
+ * sigmoid.  FP16 operands and activations, FP32 accumulation (matrix cores),
+ * FP32 head.
+ *
+ * art_shading_param_count: FP32 parameters for C input channels (1..32), in
+ * the order of the 14 convolutions (weight [Cout][Cin][3][3], then bias
+ * [Cout]; layer 0 has Cin = C), then the head (weight [4][32], bias [4]);
+ * -1 for C outside 1..32.
+ * art_shading_set_weights: copy them in (host), converted to FP16.
+ * art_shading_forward: N maps F (device float32 [N][C][H][W], H and W
+ * multiples of 8) -> out (device float32 [N][4][H][W]: R, G, B, opacity).
+ * Enqueued on the context's stream; activations use a context buffer of
+ * 332 bytes per pixel of the batch.
+ * Errors: ART_EINVAL (counts, NULL, non-finite weights, sizes),
+ * ART_EUNSUPPORTED (C), ART_ESTATE (no weights for this C), ART_ENOMEM.
+ */
+int64_t art_shading_param_count(int C);
+art_status art_shading_set_weights(art_ctx* ctx, int C, int64_t count, const float* w);
+art_status art_shading_forward(art_ctx* ctx, int C, int N, int H, int W, const float* F, float* out);
+
+/*
  * Voxel regularisation term of Section 3.1 ("Training", Eq. 10) for every pose
  * and its gradient with respect to the features.  For each canonical leaf i
  * whose posed centre lies inside the posed root, Q(p_i^t, T^t) is the feature

@@ -330,6 +330,27 @@ class Renderer:
                     "art_backward")
         return d_sigma, d_feat
 
+    # ---- shading network --------------------------------------------------------------
+    def shading_param_count(self, C: int) -> int:
+        return int(self.lib.art_shading_param_count(int(C)))
+
+    def set_shading_weights(self, C: int, w) -> None:
+        w = np.ascontiguousarray(w, dtype=np.float32).reshape(-1)
+        self._check(self.lib.art_shading_set_weights(self._h, int(C), w.size, _ptr(w)), "art_shading_set_weights")
+
+    def shade(self, F, out=None):
+        """The Light shading network on feature maps F [N][C][H][W] (float32,
+        device; any leading dims are flattened into N): RGB + opacity
+        [N][4][H][W]."""
+        torch = self._torch
+        C, H, W = int(F.shape[-3]), int(F.shape[-2]), int(F.shape[-1])
+        Fc = F.reshape(-1, C, H, W).contiguous().float()
+        N = int(Fc.shape[0])
+        if out is None:
+            out = torch.empty((N, 4, H, W), dtype=torch.float32, device=Fc.device)
+        self._check(self.lib.art_shading_forward(self._h, C, N, H, W, _tptr(Fc), _tptr(out)), "art_shading_forward")
+        return out
+
     # ---- training step ----------------------------------------------------------------
     def vrt(self, feat, lambda_vrt: float, d_feat=None, fp32_geom: bool = False):
         """Voxel regularisation term (Eq. 10) summed over the poses; its gradient

@@ -44,6 +44,9 @@ SIGNATURES = [
     ("art_render_proposal", _I, [_P, _I, _I, _P, _P, _F, _U, _P, _F, _F, _P, _P, _P]),
     ("art_render_depth", _I, [_P, _I, _I, _P, _P, _F, _U, _F, _P, _P, _P, _P]),
     ("art_render_sh", _I, [_P, _I, _I, _I, _P, _P, _F, _U, _P, _P, _P]),
+    ("art_shading_param_count", _L, [_I]),
+    ("art_shading_set_weights", _I, [_P, _I, _L, _P]),
+    ("art_shading_forward", _I, [_P, _I, _I, _I, _I, _P, _P]),
     ("art_vrt", _I, [_P, _I, _I, _P, _F, _U, _P, ctypes.POINTER(ctypes.c_double)]),
     ("art_query", _I, [_P, _I, _U, _L, _P, _P]),
     ("art_flut_adam", _I, [_P, _L, _P, _P, _P, _P, _I, _F, _F, _F, _F, _F]),

@@ -617,6 +617,31 @@ hipError_t launch_render(const RenderLaunch& r, hipStream_t st) {
 }  // namespace art
 
 // ---------------------------------------------------------------------------
+// Shading network ("Light" U-Net) layer table
+// ---------------------------------------------------------------------------
+namespace art {
+struct ShadeLayer {
+    int cin_a, cin_b, cout;   // channels from the same-resolution source, from the upsampled one, out
+};
+// Encoder levels of 32, 64, 128 and 256 channels (two 3x3 convolutions each,
+// 2x2 max pooling between levels); decoder levels 128, 64, 32 whose first
+// convolution reads [skip connection, nearest-upsampled deeper level]; a 1x1
+// head to RGB + opacity.  Layer 0's input width is the feature width C.
+constexpr int kShadeLayers = 14;
+constexpr ShadeLayer kShade[kShadeLayers] = {
+    {0, 0, 32},    {32, 0, 32},                       // level 0 (cin of layer 0 = C)
+    {32, 0, 64},   {64, 0, 64},                       // level 1
+    {64, 0, 128},  {128, 0, 128},                     // level 2
+    {128, 0, 256}, {256, 0, 256},                     // level 3
+    {128, 256, 128}, {128, 0, 128},                   // decoder level 2
+    {64, 128, 64},   {64, 0, 64},                     // decoder level 1
+    {32, 64, 32},    {32, 0, 32},                     // decoder level 0
+};
+inline int shade_cin(int l, int C) { return l == 0 ? C : kShade[l].cin_a + kShade[l].cin_b; }
+inline int shade_cin_pad(int l) { return l == 0 ? 32 : kShade[l].cin_a + kShade[l].cin_b; }
+}  // namespace art
+
+// ---------------------------------------------------------------------------
 // ABI
 // ---------------------------------------------------------------------------
 extern "C" {
@@ -646,7 +671,8 @@ void art_destroy(art_ctx* ctx) {
         DeviceGuard g(ctx->device);
         if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
         else (void)hipDeviceSynchronize();
-        DevBuf* bufs[] = {&ctx->ijk, &ctx->bone, &ctx->weight, &ctx->dom_bone, &ctx->parent, &ctx->rest, &ctx->pose,
+        DevBuf* bufs[] = {&ctx->ijk, &ctx->bone, &ctx->weight, &ctx->dom_bone, &ctx->shade_w, &ctx->shade_b,
+                          &ctx->shade_head, &ctx->shade_act, &ctx->parent, &ctx->rest, &ctx->pose,
                           &ctx->cam, &ctx->B64, &ctx->B32, &ctx->Gtmp,
                           &ctx->s.keys0, &ctx->s.keys1, &ctx->s.bmap, &ctx->s.wpref, &ctx->s.hist,
                           &ctx->s.digit_tot, &ctx->s.blk0, &ctx->s.blk1, &ctx->s.occ_key, &ctx->s.occ_win,
@@ -921,6 +947,130 @@ art_status art_render_sh(art_ctx* ctx, int C, int H, art_dtype dtype, const void
     o.out_tfinal = out_tfinal;
     o.sh_H = H;
     return render_call(ctx, C, dtype, sigma, feat, lambda_th, flags, 6, o, 0, ctx->P);
+}
+
+int64_t art_shading_param_count(int C) {
+    if (C < 1 || C > 32) return -1;
+    int64_t n = 0;
+    for (int l = 0; l < kShadeLayers; ++l) n += (int64_t)kShade[l].cout * shade_cin(l, C) * 9 + kShade[l].cout;
+    return n + 4 * 32 + 4;
+}
+
+art_status art_shading_set_weights(art_ctx* ctx, int C, int64_t count, const float* w) {
+    if (!ctx) return ART_EINVAL;
+    if (C < 1 || C > 32) return fail(ctx, ART_EUNSUPPORTED, "C must be in 1..32");
+    if (!w || count != art_shading_param_count(C)) return fail(ctx, ART_EINVAL, "weight count mismatch or NULL");
+    for (int64_t i = 0; i < count; ++i)
+        if (!std::isfinite(w[i])) return fail(ctx, ART_EINVAL, "weights must be finite");
+    // PyTorch layout [Cout][Cin][3][3] + bias per layer -> FP16 [3][3][Cout][Cin_pad] + FP32 bias
+    std::vector<_Float16> hw;
+    std::vector<float> hb, hh(4 * 32 + 4);
+    const float* p = w;
+    for (int l = 0; l < kShadeLayers; ++l) {
+        const int co = kShade[l].cout, ci = shade_cin(l, C), cp = shade_cin_pad(l);
+        const size_t base = hw.size();
+        hw.resize(base + (size_t)9 * co * cp, (_Float16)0.0f);
+        for (int o = 0; o < co; ++o)
+            for (int i = 0; i < ci; ++i)
+                for (int k = 0; k < 9; ++k) hw[base + ((size_t)k * co + o) * cp + i] = (_Float16)p[((size_t)o * ci + i) * 9 + k];
+        p += (size_t)co * ci * 9;
+        hb.insert(hb.end(), p, p + co);
+        p += co;
+    }
+    std::copy(p, p + 4 * 32 + 4, hh.begin());
+    DeviceGuard g(ctx->device);
+    ART_TRY_HIP(ctx->shade_w.ensure(hw.size() * 2), "device allocation");
+    ART_TRY_HIP(ctx->shade_b.ensure(hb.size() * 4), "device allocation");
+    ART_TRY_HIP(ctx->shade_head.ensure(hh.size() * 4), "device allocation");
+    ART_TRY_HIP(hipMemcpy(ctx->shade_w.p, hw.data(), hw.size() * 2, hipMemcpyHostToDevice), "copy");
+    ART_TRY_HIP(hipMemcpy(ctx->shade_b.p, hb.data(), hb.size() * 4, hipMemcpyHostToDevice), "copy");
+    ART_TRY_HIP(hipMemcpy(ctx->shade_head.p, hh.data(), hh.size() * 4, hipMemcpyHostToDevice), "copy");
+    ctx->shade_C = C;
+    return ART_OK;
+}
+
+art_status art_shading_forward(art_ctx* ctx, int C, int N, int H, int W, const float* F, float* out) {
+    if (!ctx) return ART_EINVAL;
+    if (ctx->shade_C == 0 || ctx->shade_C != C) return fail(ctx, ART_ESTATE, "no shading weights for this C");
+    if (N < 1 || H < 8 || W < 8 || (H % 8) || (W % 8)) return fail(ctx, ART_EINVAL, "N >= 1; H, W multiples of 8");
+    if (!F || !out) return fail(ctx, ART_EINVAL, "F / out is NULL");
+    DeviceGuard g(ctx->device);
+    hipStream_t st = ctx->stream;
+    const size_t HW = (size_t)N * H * W;   // pixels of level 0 over all images
+    // activation buffers (halves): level 0: X, T0, E0 (32 ch); level 1: P0 (32), T1, E1 (64);
+    // level 2: P1 (64), T2, E2 (128); level 3: P2 (128), T3, B (256)
+    const size_t sz[12] = {HW * 32, HW * 32, HW * 32, HW / 4 * 32, HW / 4 * 64, HW / 4 * 64,
+                           HW / 16 * 64, HW / 16 * 128, HW / 16 * 128, HW / 64 * 128, HW / 64 * 256, HW / 64 * 256};
+    size_t off[12], tot = 0;
+    for (int i = 0; i < 12; ++i) {
+        off[i] = tot;
+        tot += (sz[i] + 127) / 128 * 128;
+    }
+    ART_TRY_HIP(ctx->shade_act.ensure(tot * 2), "device allocation");
+    uint16_t* base = ctx->shade_act.as<uint16_t>();
+    uint16_t* X = base + off[0];
+    uint16_t* T0 = base + off[1];
+    uint16_t* E0 = base + off[2];
+    uint16_t* P0 = base + off[3];
+    uint16_t* T1 = base + off[4];
+    uint16_t* E1 = base + off[5];
+    uint16_t* P1 = base + off[6];
+    uint16_t* T2 = base + off[7];
+    uint16_t* E2 = base + off[8];
+    uint16_t* P2 = base + off[9];
+    uint16_t* T3 = base + off[10];
+    uint16_t* Bt = base + off[11];
+    const uint16_t* wl[kShadeLayers];
+    const float* bl[kShadeLayers];
+    {
+        const uint16_t* wp = ctx->shade_w.as<uint16_t>();
+        const float* bp = ctx->shade_b.as<float>();
+        for (int l = 0; l < kShadeLayers; ++l) {
+            wl[l] = wp;
+            bl[l] = bp;
+            wp += (size_t)9 * kShade[l].cout * shade_cin_pad(l);
+            bp += kShade[l].cout;
+        }
+    }
+    auto conv = [&](int l, const uint16_t* s1, int c1, const uint16_t* s2, int c2, uint16_t* o, int h, int w) {
+        ConvLaunch a{};
+        a.src1 = s1;
+        a.C1 = c1;
+        a.src2 = s2;
+        a.C2 = c2;
+        a.wgt = wl[l];
+        a.bias = bl[l];
+        a.out = o;
+        a.N = N;
+        a.H = h;
+        a.W = w;
+        a.Cout = kShade[l].cout;
+        a.relu = 1;
+        return launch_conv3x3(a, st);
+    };
+    hipError_t e = launch_to_nhwc(F, N, C, H, W, 32, X, st);
+    const int H1 = H / 2, W1 = W / 2, H2 = H / 4, W2 = W / 4, H3 = H / 8, W3 = W / 8;
+    if (e == hipSuccess) e = conv(0, X, 32, nullptr, 0, T0, H, W);
+    if (e == hipSuccess) e = conv(1, T0, 32, nullptr, 0, E0, H, W);
+    if (e == hipSuccess) e = launch_maxpool2(E0, N, H, W, 32, P0, st);
+    if (e == hipSuccess) e = conv(2, P0, 32, nullptr, 0, T1, H1, W1);
+    if (e == hipSuccess) e = conv(3, T1, 64, nullptr, 0, E1, H1, W1);
+    if (e == hipSuccess) e = launch_maxpool2(E1, N, H1, W1, 64, P1, st);
+    if (e == hipSuccess) e = conv(4, P1, 64, nullptr, 0, T2, H2, W2);
+    if (e == hipSuccess) e = conv(5, T2, 128, nullptr, 0, E2, H2, W2);
+    if (e == hipSuccess) e = launch_maxpool2(E2, N, H2, W2, 128, P2, st);
+    if (e == hipSuccess) e = conv(6, P2, 128, nullptr, 0, T3, H3, W3);
+    if (e == hipSuccess) e = conv(7, T3, 256, nullptr, 0, Bt, H3, W3);
+    if (e == hipSuccess) e = conv(8, E2, 128, Bt, 256, T2, H2, W2);
+    if (e == hipSuccess) e = conv(9, T2, 128, nullptr, 0, E2, H2, W2);
+    if (e == hipSuccess) e = conv(10, E1, 64, E2, 128, T1, H1, W1);
+    if (e == hipSuccess) e = conv(11, T1, 64, nullptr, 0, E1, H1, W1);
+    if (e == hipSuccess) e = conv(12, E0, 32, E1, 64, T0, H, W);
+    if (e == hipSuccess) e = conv(13, T0, 32, nullptr, 0, X, H, W);
+    if (e == hipSuccess)
+        e = launch_head(X, N, H, W, ctx->shade_head.as<float>(), ctx->shade_head.as<float>() + 128, out, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "shading network");
+    return ART_OK;
 }
 
 art_status art_vrt(art_ctx* ctx, int C, art_dtype dtype, const void* feat, float lambda_vrt, unsigned flags,

@@ -127,6 +127,12 @@ struct art_ctx {
     art::DevBuf bone;     // uint8 [4][n]
     art::DevBuf weight;   // float [4][n]
     art::DevBuf dom_bone; // uint8 [n]: bone of each leaf's largest skin weight
+
+    // shading network: FP16 conv weights [3][3][Cout][Cin] per layer, FP32
+    // biases, FP32 head; activation scratch
+    int shade_C = 0;
+    art::DevBuf shade_w, shade_b, shade_head;
+    art::DevBuf shade_act;
     bool has_skin = false;
     int max_bone = -1;
 
@@ -302,6 +308,22 @@ hipError_t launch_query(const double* pts, int64_t n, int depth, const OctreeSlo
                         int32_t* out, hipStream_t st);
 hipError_t launch_flut_adam(float* param, const float* grad, float* m, float* v, int64_t count, const AdamStep& a,
                             float lower, hipStream_t st);
+// Shading network (k_shade.hip).  FP16 tensors are passed as uint16_t.
+struct ConvLaunch {
+    const uint16_t* src1;   // NHWC [N][H][W][C1]
+    int C1;                 // multiple of 32
+    const uint16_t* src2;   // NHWC [N][H/2][W/2][C2] read nearest-upsampled, or null (C2 = 0)
+    int C2;                 // multiple of 32
+    const uint16_t* wgt;    // [3][3][Cout][C1 + C2]
+    const float* bias;      // [Cout]
+    uint16_t* out;          // NHWC [N][H][W][Cout], Cout a multiple of 32
+    int N, H, W, Cout, relu;
+};
+hipError_t launch_conv3x3(const ConvLaunch& a, hipStream_t st);
+hipError_t launch_to_nhwc(const float* F, int N, int C, int H, int W, int Cp, uint16_t* out, hipStream_t st);
+hipError_t launch_maxpool2(const uint16_t* in, int N, int H, int W, int C, uint16_t* out, hipStream_t st);
+hipError_t launch_head(const uint16_t* in, int N, int H, int W, const float* w, const float* b, float* out,
+                       hipStream_t st);
 struct InferLaunch {
     const uint16_t* packed;
     const float* theta;

@@ -1,0 +1,237 @@
+// Neural shading network G, the "Light" variant of Section 3.1 / Section 6
+// ("Neural Shading", runtime analysis): one encoder-decoder (U-Net) branch that
+// turns the feature map F into an RGB image and an opacity map (the opacity
+// branch removed, one output channel added), in half precision.
+//
+// Layout: activations NHWC in FP16 (channels innermost, multiples of 32);
+// weights [3][3][Cout][Cin] FP16; bias FP32.  Every 3x3 convolution (pad 1,
+// stride 1, bias, optional ReLU) is an implicit GEMM on the matrix cores:
+// D[cout][pixel] += W[cout][k] X[k][pixel] over k = (ky, kx, cin), with
+// v_mfma_f32_16x16x32_f16 (FP16 operands, FP32 accumulation).  A workgroup
+// (4 waves) computes 128 consecutive pixels of one image row for 16 NCB output
+// channels; per 32-channel chunk and kernel row it stages the input row (with
+// its halo) and the 3 x 16 NCB weight rows in LDS.  The decoder's input
+// (skip connection, nearest-upsampled deeper level) is read by the staging
+// directly: channels [0, C1) from the same-resolution source, [C1, C1 + C2)
+// from the half-resolution one at (y/2, x/2), so neither the upsampled tensor
+// nor the concatenation is materialised.
+//
+// MFMA operand layout of the 16x16x32 shape (wave64): lane l holds
+//   A[l % 16][8 (l / 16) + e], B[8 (l / 16) + e][l % 16] for e = 0..7 and
+//   D[4 (l / 16) + e][l % 16] for e = 0..3.
+#include "device_util.h"
+#include "internal.h"
+
+namespace art {
+
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef _Float16 half4 __attribute__((ext_vector_type(4)));
+typedef float fl4 __attribute__((ext_vector_type(4)));
+
+constexpr int kPix = 40;            // halves per staged pixel / weight row: 32 channels + 8 (bank spread)
+constexpr int kConvWaves = 4;
+constexpr int kConvPB = 2;          // 16-pixel blocks per wave
+constexpr int kConvTP = kConvWaves * 16 * kConvPB;   // 128 pixels per workgroup
+
+template <int NCB>
+__global__ __launch_bounds__(256) void k_conv3x3(ConvLaunch a) {
+    const _Float16* src1 = reinterpret_cast<const _Float16*>(a.src1);
+    const _Float16* src2 = reinterpret_cast<const _Float16*>(a.src2);
+    const _Float16* wgt = reinterpret_cast<const _Float16*>(a.wgt);
+    _Float16* outp = reinterpret_cast<_Float16*>(a.out);
+    constexpr int TC = 16 * NCB;    // output channels per workgroup
+    __shared__ __align__(16) _Float16 s_in[(kConvTP + 2) * kPix];
+    __shared__ __align__(16) _Float16 s_w[3 * TC * kPix];
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6;
+    const int lane = tid & 63;
+    const int x0 = blockIdx.x * kConvTP;
+    const int y = blockIdx.y;
+    const int ntc = a.Cout / TC;
+    const int ct = blockIdx.z % ntc;
+    const int n = blockIdx.z / ntc;
+    const int Cin = a.C1 + a.C2;
+    const int H2 = a.H >> 1, W2 = a.W >> 1;
+    fl4 acc[kConvPB][NCB];
+#pragma unroll
+    for (int p = 0; p < kConvPB; ++p)
+#pragma unroll
+        for (int c = 0; c < NCB; ++c) acc[p][c] = fl4{0.0f, 0.0f, 0.0f, 0.0f};
+
+    for (int c0 = 0; c0 < Cin; c0 += 32) {
+        const bool up = c0 >= a.C1;   // this chunk comes from the half-resolution source
+        for (int ky = 0; ky < 3; ++ky) {
+            const int yy = y + ky - 1;
+            __syncthreads();   // the previous stage has been read
+            // input row yy, pixels x0 - 1 .. x0 + kConvTP, 32 channels (zero outside the image)
+            for (int v = tid; v < (kConvTP + 2) * 4; v += 256) {
+                const int px = v >> 2, q = v & 3;
+                const int xx = x0 - 1 + px;
+                half8 val = half8{0, 0, 0, 0, 0, 0, 0, 0};
+                if (yy >= 0 && yy < a.H && xx >= 0 && xx < a.W) {
+                    if (!up)
+                        val = *reinterpret_cast<const half8*>(
+                            src1 + (((size_t)n * a.H + yy) * a.W + xx) * a.C1 + c0 + 8 * q);
+                    else
+                        val = *reinterpret_cast<const half8*>(
+                            src2 + (((size_t)n * H2 + (yy >> 1)) * W2 + (xx >> 1)) * a.C2 + (c0 - a.C1) + 8 * q);
+                }
+                *reinterpret_cast<half8*>(s_in + px * kPix + 8 * q) = val;
+            }
+            // weights of kernel row ky: [kx][cout][32 channels]
+            for (int v = tid; v < 3 * TC * 4; v += 256) {
+                const int q = v & 3;
+                const int r = v >> 2;
+                const int co = r % TC, kx = r / TC;
+                *reinterpret_cast<half8*>(s_w + r * kPix + 8 * q) = *reinterpret_cast<const half8*>(
+                    wgt + ((size_t)(ky * 3 + kx) * a.Cout + ct * TC + co) * Cin + c0 + 8 * q);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int kx = 0; kx < 3; ++kx) {
+                half8 bx[kConvPB];
+#pragma unroll
+                for (int p = 0; p < kConvPB; ++p) {
+                    const int px = (wave * kConvPB + p) * 16 + (lane & 15) + kx;
+                    bx[p] = *reinterpret_cast<const half8*>(s_in + px * kPix + 8 * (lane >> 4));
+                }
+#pragma unroll
+                for (int c = 0; c < NCB; ++c) {
+                    const half8 aw =
+                        *reinterpret_cast<const half8*>(s_w + (kx * TC + c * 16 + (lane & 15)) * kPix + 8 * (lane >> 4));
+#pragma unroll
+                    for (int p = 0; p < kConvPB; ++p)
+                        acc[p][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(aw, bx[p], acc[p][c], 0, 0, 0);
+                }
+            }
+        }
+    }
+    // epilogue: bias, ReLU, FP16 NHWC store (4 consecutive channels per lane)
+#pragma unroll
+    for (int p = 0; p < kConvPB; ++p) {
+        const int x = x0 + (wave * kConvPB + p) * 16 + (lane & 15);
+        if (x >= a.W) continue;
+        _Float16* o = outp + (((size_t)n * a.H + y) * a.W + x) * a.Cout + ct * TC;
+#pragma unroll
+        for (int c = 0; c < NCB; ++c) {
+            const int co = c * 16 + 4 * (lane >> 4);
+            half4 h;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                float v = acc[p][c][e] + a.bias[ct * TC + co + e];
+                if (a.relu) v = fmaxf(v, 0.0f);
+                h[e] = (_Float16)v;
+            }
+            *reinterpret_cast<half4*>(o + co) = h;
+        }
+    }
+}
+
+hipError_t launch_conv3x3(const ConvLaunch& a, hipStream_t st) {
+    if ((a.C1 % 32) || (a.C2 % 32) || a.C1 <= 0 || (a.C2 > 0 && !a.src2)) return hipErrorInvalidValue;
+    const int NCB = a.Cout % 64 == 0 ? 4 : (a.Cout % 32 == 0 ? 2 : 0);
+    if (NCB == 0) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)((a.W + kConvTP - 1) / kConvTP), (unsigned)a.H, (unsigned)(a.N * (a.Cout / (16 * NCB))));
+    if (NCB == 4) hipLaunchKernelGGL(k_conv3x3<4>, grid, dim3(256), 0, st, a);
+    else hipLaunchKernelGGL(k_conv3x3<2>, grid, dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+// Planar FP32 feature maps [N][C][H][W] -> NHWC FP16 with Cp >= C channels (zero padded).
+__global__ __launch_bounds__(256) void k_to_nhwc(const float* __restrict__ F, int N, int C, int H, int W, int Cp,
+                                                 _Float16* __restrict__ out) {
+    const size_t HW = (size_t)H * W;
+    const size_t total = (size_t)N * HW;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+        const size_t n = i / HW, pix = i % HW;
+        _Float16* o = out + i * Cp;
+        for (int c = 0; c < Cp; c += 4) {
+            half4 h;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) h[e] = (_Float16)(c + e < C ? F[(n * C + c + e) * HW + pix] : 0.0f);
+            *reinterpret_cast<half4*>(o + c) = h;
+        }
+    }
+}
+
+// 2x2 max pooling of NHWC FP16 (H, W even), 8 channels per thread.
+__global__ __launch_bounds__(256) void k_maxpool2(const _Float16* __restrict__ in, int N, int H, int W, int C,
+                                                  _Float16* __restrict__ out) {
+    const int H2 = H >> 1, W2 = W >> 1, C8 = C >> 3;
+    const size_t total = (size_t)N * H2 * W2 * C8;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+        const int c8 = (int)(i % C8);
+        const size_t r = i / C8;
+        const int x = (int)(r % W2), y = (int)((r / W2) % H2);
+        const size_t n = r / ((size_t)W2 * H2);
+        const _Float16* b = in + ((n * H + 2 * y) * W + 2 * x) * C + 8 * c8;
+        half8 m = *reinterpret_cast<const half8*>(b);
+        const half8 v1 = *reinterpret_cast<const half8*>(b + C);
+        const half8 v2 = *reinterpret_cast<const half8*>(b + (size_t)W * C);
+        const half8 v3 = *reinterpret_cast<const half8*>(b + (size_t)W * C + C);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            _Float16 t = m[e] > v1[e] ? m[e] : v1[e];
+            t = t > v2[e] ? t : v2[e];
+            m[e] = t > v3[e] ? t : v3[e];
+        }
+        *reinterpret_cast<half8*>(out + i * 8) = m;
+    }
+}
+
+// Output head: 1x1 convolution of the Cin = 32 channel decoder output to 4
+// channels (RGB, opacity) and a sigmoid; planar FP32 [N][4][H][W].
+__global__ __launch_bounds__(256) void k_head(const _Float16* __restrict__ in, int N, int H, int W,
+                                              const float* __restrict__ w, const float* __restrict__ b,
+                                              float* __restrict__ out) {
+    __shared__ float sw[4 * 32 + 4];
+    for (int i = threadIdx.x; i < 4 * 32 + 4; i += blockDim.x) sw[i] = i < 128 ? w[i] : b[i - 128];
+    __syncthreads();
+    const size_t HW = (size_t)H * W;
+    const size_t total = (size_t)N * HW;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+        const half8* p = reinterpret_cast<const half8*>(in + i * 32);
+        float x[32];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const half8 v = p[q];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) x[8 * q + e] = (float)v[e];
+        }
+        const size_t n = i / HW, pix = i % HW;
+#pragma unroll
+        for (int o = 0; o < 4; ++o) {
+            float s = sw[128 + o];
+#pragma unroll
+            for (int c = 0; c < 32; ++c) s = fmaf(sw[o * 32 + c], x[c], s);
+            out[(n * 4 + o) * HW + pix] = 1.0f / (1.0f + expf(-s));
+        }
+    }
+}
+
+static unsigned grid_for(size_t total) {
+    size_t g = (total + 255) / 256;
+    if (g > 16384) g = 16384;
+    return (unsigned)(g < 1 ? 1 : g);
+}
+
+hipError_t launch_to_nhwc(const float* F, int N, int C, int H, int W, int Cp, uint16_t* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_to_nhwc, dim3(grid_for((size_t)N * H * W)), dim3(256), 0, st, F, N, C, H, W, Cp,
+                       reinterpret_cast<_Float16*>(out));
+    return hipGetLastError();
+}
+
+hipError_t launch_maxpool2(const uint16_t* in, int N, int H, int W, int C, uint16_t* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_maxpool2, dim3(grid_for((size_t)N * (H / 2) * (W / 2) * (C / 8))), dim3(256), 0, st,
+                       reinterpret_cast<const _Float16*>(in), N, H, W, C, reinterpret_cast<_Float16*>(out));
+    return hipGetLastError();
+}
+
+hipError_t launch_head(const uint16_t* in, int N, int H, int W, const float* w, const float* b, float* out,
+                       hipStream_t st) {
+    hipLaunchKernelGGL(k_head, dim3(grid_for((size_t)N * H * W)), dim3(256), 0, st,
+                       reinterpret_cast<const _Float16*>(in), N, H, W, w, b, out);
+    return hipGetLastError();
+}
+
+}  // namespace art

@@ -36,7 +36,8 @@ from typing import Dict, List, Optional, Tuple
 import numpy as np
 
 __all__ = [
-    "SceneConfig", "Scene", "CONFIGS", "make_scene", "make_poses", "make_cameras",
+    "SceneConfig", "Scene", "CONFIGS", "make_scene", "make_poses", "make_cameras", "make_shading_weights",
+    "shading_shapes",
     "make_targets", "sample_training_rays", "rotation_about",
 ]
 
@@ -464,3 +465,26 @@ def sample_training_rays(n: int, P: int, V: int, H: int, W: int, hit_mask: Optio
     out = np.concatenate([a, b])
     rng.shuffle(out)
     return out
+
+
+# (Cout, Cin) of the 14 convolutions of the Light shading network (Cin of the
+# first one is the feature width C), then the 1x1 head (4, 32): shapes only,
+# for seeding the weights.
+def shading_shapes(C: int):
+    return [(32, C), (32, 32), (64, 32), (64, 64), (128, 64), (128, 128), (256, 128), (256, 256),
+            (128, 384), (128, 128), (64, 192), (64, 64), (32, 96), (32, 32)]
+
+
+def make_shading_weights(C: int, seed: int = 9) -> np.ndarray:
+    """Seeded FP32 weights of the Light shading network in the library's flat
+    order: per 3x3 convolution weight [Cout][Cin][3][3] ~ N(0, 2 / (9 Cin))
+    (He initialisation) and bias ~ N(0, 0.01^2); then the head weight [4][32]
+    ~ N(0, 1/32) and bias [4] = 0."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for co, ci in shading_shapes(C):
+        parts.append(rng.normal(0.0, math.sqrt(2.0 / (9 * ci)), co * ci * 9))
+        parts.append(rng.normal(0.0, 0.01, co))
+    parts.append(rng.normal(0.0, math.sqrt(1.0 / 32), 4 * 32))
+    parts.append(np.zeros(4))
+    return np.concatenate(parts).astype(np.float32)
