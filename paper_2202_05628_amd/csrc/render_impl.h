@@ -278,9 +278,16 @@ __device__ inline void root_span(const R* d, const R* q, const R* inv, R h, int 
 #ifndef ART_RENDER_WAVES_PER_EU
 #define ART_RENDER_WAVES_PER_EU 3
 #endif
+// Run statistics of one wave (in its workgroup's LDS, written by lane 0 only),
+// added to the device counters once when the wave exits: per-tile atomics on
+// the same few words would serialise.
+struct WaveStats {
+    unsigned long long v[13];
+};
+
 // Render one non-empty tile (item = pose-in-launch * V + view, tile index).
 template <int C, int ST, typename R, int MODE>
-__device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, int lane,
+__device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, int lane, WaveStats& ws,
                                    uint32_t (*s_mask)[16][kMaskPitch],
                                    uint16_t (*s_pref)[16][kPrefPitch], uint32_t (*s_row)[kStage],
                                    uint32_t (*s_coord)[kStage], float* s_rot) {
@@ -846,24 +853,22 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
         const uint64_t rays = __ballot(pix_ok);
         const uint64_t hits = __ballot(pix_ok && nsamp > 0);
         const unsigned long long ns = (unsigned long long)wave_sum((unsigned)nsamp);
-        if (lane == 0 && rays) {
-            atomicAdd(&a.stats[0], (unsigned long long)__popcll(rays));
-            atomicAdd(&a.stats[1], ns);
-            atomicAdd(&a.stats[2], (unsigned long long)__popcll(hits));
-            atomicAdd(&a.stats[7], (unsigned long long)(le - ls));
-            atomicAdd(&a.stats[10], (unsigned long long)__popcll(rays));
-            atomicAdd(&a.stats[8], (unsigned long long)rounds);
-        }
         const unsigned long long steps = (unsigned long long)wave_sum(nsteps);
-        if (lane == 0 && rays) {
-            atomicAdd(&a.stats[9], steps);
+        if (lane == 0 && rays) {   // wave-uniform values
+            ws.v[0] += (unsigned long long)__popcll(rays);
+            ws.v[1] += ns;
+            ws.v[2] += (unsigned long long)__popcll(hits);
+            ws.v[7] += (unsigned long long)(le - ls);
+            ws.v[10] += (unsigned long long)__popcll(rays);
+            ws.v[8] += (unsigned long long)rounds;
+            ws.v[9] += steps;
         }
         if constexpr (MODE == 4) {
             const uint64_t pr = __ballot(prop);
             const uint64_t fl = __ballot(nfall != 0u);
             if (lane == 0) {
-                atomicAdd(&a.stats[11], (unsigned long long)__popcll(pr));
-                atomicAdd(&a.stats[12], (unsigned long long)__popcll(fl));
+                ws.v[11] += (unsigned long long)__popcll(pr);
+                ws.v[12] += (unsigned long long)__popcll(fl);
             }
         }
     }
@@ -881,6 +886,9 @@ void k_render(RArgs a) {
     __shared__ float s_rot[MODE == 6 ? kMaxBonesSH * 9 : 1];
     const int lane = threadIdx.x & 63;
     const uint32_t n_items = *a.n_items;
+    __shared__ WaveStats ws;
+    if (lane == 0)
+        for (int i = 0; i < 13; ++i) ws.v[i] = 0ull;
     // The work list may be cut into kQueues contiguous parts (neighbouring
     // tiles, which read the same bricks and FLUT rows, stay in one part);
     // workgroups are dispatched to the XCDs in turn, so a workgroup starts on
@@ -899,10 +907,13 @@ void k_render(RArgs a) {
             if (lane == 0) idx = atomicAdd(&a.queue[qi], 1u);
             idx = beg + (uint32_t)__shfl((int)idx, 0, kWave);
             if (idx >= end) break;
-            render_tile<C, ST, R, MODE>(a, a.items[idx], idx, lane, s_mask, s_pref, s_row, s_coord, s_rot);
+            render_tile<C, ST, R, MODE>(a, a.items[idx], idx, lane, ws, s_mask, s_pref, s_row, s_coord, s_rot);
             wave_sync();
         }
     }
+    if (a.stats && lane == 0)
+        for (int i = 0; i < 13; ++i)
+            if (ws.v[i]) atomicAdd(&a.stats[i], ws.v[i]);
 }
 
 template <int C>
