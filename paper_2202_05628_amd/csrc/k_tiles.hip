@@ -90,9 +90,15 @@ __global__ __launch_bounds__(256) void k_background(TileGeom g, const uint32_t* 
         if (out_depth) out_depth[(size_t)pvi * HW + pix] = INFINITY;
         if (hit_count) hit_count[pix] = 0;
     }
-    if (stats) {
+    if (stats) {   // one atomic per workgroup
+        __shared__ unsigned long long part[256 / kWave];
         const unsigned long long w = wave_sum(nrays);
-        if (lane_id() == 0 && w) atomicAdd(&stats[0], w);
+        if (lane_id() == 0) part[threadIdx.x / kWave] = w;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const unsigned long long t = part[0] + part[1] + part[2] + part[3];
+            if (t) atomicAdd(&stats[0], t);
+        }
     }
 }
 
@@ -135,9 +141,15 @@ __global__ __launch_bounds__(256) void k_background4(TileGeom g, const uint32_t*
             reinterpret_cast<float4*>(out_depth + (size_t)pvi * HW)[q] = make_float4(INFINITY, INFINITY, INFINITY, INFINITY);
         if (hit_count) reinterpret_cast<int4*>(hit_count)[q] = make_int4(0, 0, 0, 0);
     }
-    if (stats) {
+    if (stats) {   // one atomic per workgroup
+        __shared__ unsigned long long part[256 / kWave];
         const unsigned long long w = wave_sum(nrays);
-        if (lane_id() == 0 && w) atomicAdd(&stats[0], w);
+        if (lane_id() == 0) part[threadIdx.x / kWave] = w;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const unsigned long long t = part[0] + part[1] + part[2] + part[3];
+            if (t) atomicAdd(&stats[0], t);
+        }
     }
 }
 

@@ -874,6 +874,11 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
     }
 }
 
+// Consecutive work-list tiles a wave takes per queue atomic.
+#ifndef ART_TILES_PER_GRAB
+#define ART_TILES_PER_GRAB 1
+#endif
+
 // Persistent compositing kernel: each single-wave workgroup takes non-empty
 // tiles from the queue until it is exhausted (every wave reaches the exit).
 template <int C, int ST, typename R, int MODE>
@@ -904,11 +909,14 @@ void k_render(RArgs a) {
         const uint32_t end = (uint32_t)((uint64_t)n_items * (qi + 1) / kQueues);
         while (true) {
             uint32_t idx = 0;
-            if (lane == 0) idx = atomicAdd(&a.queue[qi], 1u);
+            if (lane == 0) idx = atomicAdd(&a.queue[qi], (uint32_t)ART_TILES_PER_GRAB);
             idx = beg + (uint32_t)__shfl((int)idx, 0, kWave);
             if (idx >= end) break;
-            render_tile<C, ST, R, MODE>(a, a.items[idx], idx, lane, ws, s_mask, s_pref, s_row, s_coord, s_rot);
-            wave_sync();
+            for (uint32_t t = 0; t < (uint32_t)ART_TILES_PER_GRAB && idx + t < end; ++t) {
+                render_tile<C, ST, R, MODE>(a, a.items[idx + t], idx + t, lane, ws, s_mask, s_pref, s_row, s_coord,
+                                            s_rot);
+                wave_sync();
+            }
         }
     }
     if (a.stats && lane == 0)
