@@ -278,6 +278,32 @@ __device__ inline void root_span(const R* d, const R* q, const R* inv, R h, int 
 #ifndef ART_RENDER_WAVES_PER_EU
 #define ART_RENDER_WAVES_PER_EU 3
 #endif
+// Adjoint gradient scatter through LDS: each round the lanes with a sample
+// stage (leaf, w); the feature gradients w g_c are then added with lanes
+// mapped to (sample, channel), so the 16 lanes of one atomic instruction
+// that share a sample update consecutive words of one leaf row (one cache
+// line) instead of 16 lanes hitting 16 different lines.
+#ifndef ART_ADJ_LINES
+#define ART_ADJ_LINES 1
+#endif
+template <int C>
+struct AdjLds {
+    float g[64 * C];     // dL/dF of each lane's ray
+    uint32_t leaf[64];   // leaf of the lane's sample this round (kInvalidKey: none)
+    float w[64];
+};
+
+// The adjoint's LDS staging (only the adjoint kernels allocate it).
+template <int C, int MODE>
+__device__ inline AdjLds<C>* adj_lds() {
+    if constexpr (MODE == 1) {
+        __shared__ AdjLds<C> s;
+        return &s;
+    } else {
+        return nullptr;
+    }
+}
+
 // Run statistics of one wave (in its workgroup's LDS, written by lane 0 only),
 // added to the device counters once when the wave exits: per-tile atomics on
 // the same few words would serialise.
@@ -290,7 +316,7 @@ template <int C, int ST, typename R, int MODE>
 __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, int lane, WaveStats& ws,
                                    uint32_t (*s_mask)[16][kMaskPitch],
                                    uint16_t (*s_pref)[16][kPrefPitch], uint32_t (*s_row)[kStage],
-                                   uint32_t (*s_coord)[kStage], float* s_rot) {
+                                   uint32_t (*s_coord)[kStage], float* s_rot, AdjLds<C>* s_adj) {
     constexpr int wv = 0;
     const int pvi = (int)(item / (uint32_t)a.TPV);   // pose-in-launch * V + view
     const int tile_in_view = (int)(item % (uint32_t)a.TPV);
@@ -409,6 +435,12 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
             gA = a.d_alpha ? a.d_alpha[map * HW + pix] : 0.0f;
             Tfin = a.fwd_tfinal[map * HW + pix];
         }
+#if ART_ADJ_LINES
+#pragma unroll
+        for (int c = 0; c < C; ++c) s_adj->g[lane * C + c] = g[c];
+        s_adj->leaf[lane] = kInvalidKey;
+        wave_sync();
+#endif
     }
     const size_t hit_base = pix * (size_t)(MODE == 2 ? a.max_hits : 0);
 
@@ -737,8 +769,13 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
                     const float ds = dlA * (acc + gA * Tfin);
                     const uint32_t leaf = winA;
                     unsafeAtomicAdd(&a.d_sigma[leaf], ds);
+#if ART_ADJ_LINES
+                    s_adj->leaf[lane] = leaf;
+                    s_adj->w[lane] = w;
+#else
 #pragma unroll
                     for (int c = 0; c < C; ++c) unsafeAtomicAdd(&a.d_leaf_feat[(size_t)leaf * C + c], w * g[c]);
+#endif
                 } else {
                     if constexpr (MODE == 6) {
                         // S_c = sum_h k_{h,c} Y_h(R^T d); the first block is the prefetched row
@@ -786,6 +823,28 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
                     inb = false;
                 }
             }
+#if ART_ADJ_LINES
+            if constexpr (MODE == 1) {
+                const uint64_t staged = __ballot(s_adj->leaf[lane] != kInvalidKey);
+                if (staged) {
+                    wave_sync();
+                    constexpr int SPI = 64 / C;   // samples per atomic instruction
+                    const int cc = lane % C, sub = lane / C;
+                    constexpr uint64_t kGroup = SPI >= 64 ? ~0ull : ((1ull << SPI) - 1ull);
+#pragma unroll 4
+                    for (int s0 = 0; s0 < 64; s0 += SPI) {
+                        if (((staged >> s0) & kGroup) == 0ull) continue;   // wave-uniform
+                        const int sm = s0 + sub;
+                        const uint32_t lf = s_adj->leaf[sm];
+                        if (lf != kInvalidKey)
+                            unsafeAtomicAdd(&a.d_leaf_feat[(size_t)lf * C + cc], s_adj->w[sm] * s_adj->g[sm * C + cc]);
+                    }
+                    wave_sync();
+                    s_adj->leaf[lane] = kInvalidKey;
+                    wave_sync();
+                }
+            }
+#endif
 #if ART_ID_PREFETCH
             // (3) the sample whose winner id has arrived issues its FLUT gather,
             // (4) the new sample fetches its collision winner's id.  Both loads
@@ -889,6 +948,7 @@ void k_render(RArgs a) {
     __shared__ uint32_t s_row[1][kStage];
     __shared__ uint32_t s_coord[1][kStage];
     __shared__ float s_rot[MODE == 6 ? kMaxBonesSH * 9 : 1];
+    AdjLds<C>* s_adj = adj_lds<C, MODE>();
     const int lane = threadIdx.x & 63;
     const uint32_t n_items = *a.n_items;
     __shared__ WaveStats ws;
@@ -914,7 +974,7 @@ void k_render(RArgs a) {
             if (idx >= end) break;
             for (uint32_t t = 0; t < (uint32_t)ART_TILES_PER_GRAB && idx + t < end; ++t) {
                 render_tile<C, ST, R, MODE>(a, a.items[idx + t], idx + t, lane, ws, s_mask, s_pref, s_row, s_coord,
-                                            s_rot);
+                                            s_rot, s_adj);
                 wave_sync();
             }
         }
