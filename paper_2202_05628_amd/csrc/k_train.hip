@@ -22,42 +22,66 @@ __device__ inline float flut_feat(const void* feat, size_t idx) {
     else return bf16_to_f32(reinterpret_cast<const uint16_t*>(feat)[idx]);
 }
 
+// The colliding leaves of 256 consecutive leaves are listed in LDS as
+// (winner, leaf) pairs; the pairs are then processed with one thread per
+// (pair, channel), so the 16 (C) threads of one pair update consecutive words
+// of the two FLUT rows with each atomic instruction.
 template <int ST>
 __global__ __launch_bounds__(256) void k_vrt(const uint32_t* __restrict__ rows, const uint32_t* __restrict__ occ_win,
                                              uint32_t n, int C, const void* __restrict__ feat,
                                              const PoseCounters* __restrict__ cnt, float lambda,
                                              float* __restrict__ d_feat, double* __restrict__ loss) {
     __shared__ double part[256 / kWave];
+    __shared__ uint32_t s_win[256], s_leaf[256];
+    __shared__ uint32_t s_n;
     const size_t p = blockIdx.y;
     rows += p * n;
     occ_win += p * n;
     const uint32_t nv = n - cnt[p].dropped;
     const float scale = nv ? lambda / (float)nv : 0.0f;
+    if (threadIdx.x == 0) s_n = 0;
+    __syncthreads();
     double acc = 0.0;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const uint32_t row = rows[i];
-        if (row == kInvalidKey) continue;
-        const uint32_t w = occ_win[row];
-        if (w == i) continue;   // the winner itself: Q returns its own feature
-        float l1 = 0.0f;
-        for (int c = 0; c < C; ++c) {
-            const float diff = flut_feat<ST>(feat, (size_t)w * C + c) - flut_feat<ST>(feat, (size_t)i * C + c);
-            l1 += fabsf(diff);
-            const float g = diff > 0.0f ? scale : (diff < 0.0f ? -scale : 0.0f);
-            if (g != 0.0f) {
-                unsafeAtomicAdd(&d_feat[(size_t)w * C + c], g);
-                unsafeAtomicAdd(&d_feat[(size_t)i * C + c], -g);
+    const int cc = (int)threadIdx.x % C, sub = (int)threadIdx.x / C, per = 256 / C;
+    for (uint32_t base = blockIdx.x * 256u; base < n; base += gridDim.x * 256u) {
+        const uint32_t i = base + threadIdx.x;
+        uint32_t w = 0;
+        bool lose = false;
+        if (i < n) {
+            const uint32_t row = rows[i];
+            if (row != kInvalidKey) {
+                w = occ_win[row];
+                lose = w != i;   // a winner's Q is its own feature: no term
             }
         }
-        acc += (double)l1;
+        if (lose) {
+            const uint32_t k = atomicAdd(&s_n, 1u);
+            s_win[k] = w;
+            s_leaf[k] = i;
+        }
+        __syncthreads();
+        const uint32_t m = s_n;
+        for (uint32_t e = (uint32_t)sub; e < m; e += (uint32_t)per) {
+            const uint32_t wi = s_win[e], li = s_leaf[e];
+            const float diff = flut_feat<ST>(feat, (size_t)wi * C + cc) - flut_feat<ST>(feat, (size_t)li * C + cc);
+            acc += (double)fabsf(diff);
+            const float g = diff > 0.0f ? scale : (diff < 0.0f ? -scale : 0.0f);
+            if (g != 0.0f) {
+                unsafeAtomicAdd(&d_feat[(size_t)wi * C + cc], g);
+                unsafeAtomicAdd(&d_feat[(size_t)li * C + cc], -g);
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) s_n = 0;
+        __syncthreads();
     }
     acc = wave_sum(acc);
     if (lane_id() == 0) part[threadIdx.x / kWave] = acc;
     __syncthreads();
     if (threadIdx.x == 0) {
-        double s = 0.0;
-        for (int q = 0; q < 256 / kWave; ++q) s += part[q];
-        if (s != 0.0) unsafeAtomicAdd(loss, s * (double)scale);
+        double t = 0.0;
+        for (int q = 0; q < 256 / kWave; ++q) t += part[q];
+        if (t != 0.0) unsafeAtomicAdd(loss, t * (double)scale);
     }
 }
 
