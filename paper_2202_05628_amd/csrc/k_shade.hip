@@ -9,8 +9,9 @@
 // D[cout][pixel] += W[cout][k] X[k][pixel] over k = (ky, kx, cin), with
 // v_mfma_f32_16x16x32_f16 (FP16 operands, FP32 accumulation).  A workgroup
 // (4 waves) computes 128 consecutive pixels of one image row for 16 NCB output
-// channels; per 32-channel chunk and kernel row it stages the input row (with
-// its halo) and the 3 x 16 NCB weight rows in LDS.  The decoder's input
+// channels; per 32-channel chunk and kernel row (a stage) it stages the input
+// row (with its halo) and the 3 x 16 NCB weight rows in LDS, the global loads
+// of the next stage in flight while the matrix cores work on the current one.  The decoder's input
 // (skip connection, nearest-upsampled deeper level) is read by the staging
 // directly: channels [0, C1) from the same-resolution source, [C1, C1 + C2)
 // from the half-resolution one at (y/2, x/2), so neither the upsampled tensor
@@ -39,7 +40,11 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvLaunch a) {
     const _Float16* src2 = reinterpret_cast<const _Float16*>(a.src2);
     const _Float16* wgt = reinterpret_cast<const _Float16*>(a.wgt);
     _Float16* outp = reinterpret_cast<_Float16*>(a.out);
-    constexpr int TC = 16 * NCB;    // output channels per workgroup
+    constexpr int TC = 16 * NCB;                         // output channels per workgroup
+    constexpr int kInVec = (kConvTP + 2) * 4;            // 16-byte vectors of a staged input row
+    constexpr int kWVec = 3 * TC * 4;                    // 16-byte vectors of a staged kernel row
+    constexpr int kInIt = (kInVec + 255) / 256;
+    constexpr int kWIt = (kWVec + 255) / 256;
     __shared__ __align__(16) _Float16 s_in[(kConvTP + 2) * kPix];
     __shared__ __align__(16) _Float16 s_w[3 * TC * kPix];
     const int tid = threadIdx.x;
@@ -52,22 +57,27 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvLaunch a) {
     const int n = blockIdx.z / ntc;
     const int Cin = a.C1 + a.C2;
     const int H2 = a.H >> 1, W2 = a.W >> 1;
+    const int nstage = (Cin / 32) * 3;                   // (32-channel chunk, kernel row) stages
     fl4 acc[kConvPB][NCB];
 #pragma unroll
     for (int p = 0; p < kConvPB; ++p)
 #pragma unroll
         for (int c = 0; c < NCB; ++c) acc[p][c] = fl4{0.0f, 0.0f, 0.0f, 0.0f};
 
-    for (int c0 = 0; c0 < Cin; c0 += 32) {
-        const bool up = c0 >= a.C1;   // this chunk comes from the half-resolution source
-        for (int ky = 0; ky < 3; ++ky) {
-            const int yy = y + ky - 1;
-            __syncthreads();   // the previous stage has been read
-            // input row yy, pixels x0 - 1 .. x0 + kConvTP, 32 channels (zero outside the image)
-            for (int v = tid; v < (kConvTP + 2) * 4; v += 256) {
+    // Software pipeline: the global loads of stage s + 1 go to registers while
+    // the matrix cores work on stage s from LDS.
+    half8 rin[kInIt], rw[kWIt];
+    auto load_stage = [&](int st) {
+        const int c0 = (st / 3) * 32, ky = st % 3;
+        const int yy = y + ky - 1;
+        const bool up = c0 >= a.C1;
+#pragma unroll
+        for (int j = 0; j < kInIt; ++j) {
+            const int v = tid + 256 * j;
+            half8 val = half8{0, 0, 0, 0, 0, 0, 0, 0};
+            if (v < kInVec) {
                 const int px = v >> 2, q = v & 3;
                 const int xx = x0 - 1 + px;
-                half8 val = half8{0, 0, 0, 0, 0, 0, 0, 0};
                 if (yy >= 0 && yy < a.H && xx >= 0 && xx < a.W) {
                     if (!up)
                         val = *reinterpret_cast<const half8*>(
@@ -76,34 +86,59 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvLaunch a) {
                         val = *reinterpret_cast<const half8*>(
                             src2 + (((size_t)n * H2 + (yy >> 1)) * W2 + (xx >> 1)) * a.C2 + (c0 - a.C1) + 8 * q);
                 }
-                *reinterpret_cast<half8*>(s_in + px * kPix + 8 * q) = val;
             }
-            // weights of kernel row ky: [kx][cout][32 channels]
-            for (int v = tid; v < 3 * TC * 4; v += 256) {
-                const int q = v & 3;
-                const int r = v >> 2;
+            rin[j] = val;
+        }
+#pragma unroll
+        for (int j = 0; j < kWIt; ++j) {
+            const int v = tid + 256 * j;
+            if (v < kWVec) {
+                const int q = v & 3, r = v >> 2;
                 const int co = r % TC, kx = r / TC;
-                *reinterpret_cast<half8*>(s_w + r * kPix + 8 * q) = *reinterpret_cast<const half8*>(
-                    wgt + ((size_t)(ky * 3 + kx) * a.Cout + ct * TC + co) * Cin + c0 + 8 * q);
+                rw[j] = *reinterpret_cast<const half8*>(wgt + ((size_t)(ky * 3 + kx) * a.Cout + ct * TC + co) * Cin +
+                                                         c0 + 8 * q);
             }
+        }
+    };
+    auto store_stage = [&]() {
+#pragma unroll
+        for (int j = 0; j < kInIt; ++j) {
+            const int v = tid + 256 * j;
+            if (v < kInVec) *reinterpret_cast<half8*>(s_in + (v >> 2) * kPix + 8 * (v & 3)) = rin[j];
+        }
+#pragma unroll
+        for (int j = 0; j < kWIt; ++j) {
+            const int v = tid + 256 * j;
+            if (v < kWVec) *reinterpret_cast<half8*>(s_w + (v >> 2) * kPix + 8 * (v & 3)) = rw[j];
+        }
+    };
+
+    load_stage(0);
+    store_stage();
+    __syncthreads();
+    for (int st = 0; st < nstage; ++st) {
+        if (st + 1 < nstage) load_stage(st + 1);
+#pragma unroll
+        for (int kx = 0; kx < 3; ++kx) {
+            half8 bx[kConvPB];
+#pragma unroll
+            for (int p = 0; p < kConvPB; ++p) {
+                const int px = (wave * kConvPB + p) * 16 + (lane & 15) + kx;
+                bx[p] = *reinterpret_cast<const half8*>(s_in + px * kPix + 8 * (lane >> 4));
+            }
+#pragma unroll
+            for (int c = 0; c < NCB; ++c) {
+                const half8 aw =
+                    *reinterpret_cast<const half8*>(s_w + (kx * TC + c * 16 + (lane & 15)) * kPix + 8 * (lane >> 4));
+#pragma unroll
+                for (int p = 0; p < kConvPB; ++p)
+                    acc[p][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(aw, bx[p], acc[p][c], 0, 0, 0);
+            }
+        }
+        __syncthreads();   // every wave has read this stage
+        if (st + 1 < nstage) {
+            store_stage();
             __syncthreads();
-#pragma unroll
-            for (int kx = 0; kx < 3; ++kx) {
-                half8 bx[kConvPB];
-#pragma unroll
-                for (int p = 0; p < kConvPB; ++p) {
-                    const int px = (wave * kConvPB + p) * 16 + (lane & 15) + kx;
-                    bx[p] = *reinterpret_cast<const half8*>(s_in + px * kPix + 8 * (lane >> 4));
-                }
-#pragma unroll
-                for (int c = 0; c < NCB; ++c) {
-                    const half8 aw =
-                        *reinterpret_cast<const half8*>(s_w + (kx * TC + c * 16 + (lane & 15)) * kPix + 8 * (lane >> 4));
-#pragma unroll
-                    for (int p = 0; p < kConvPB; ++p)
-                        acc[p][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(aw, bx[p], acc[p][c], 0, 0, 0);
-                }
-            }
         }
     }
     // epilogue: bias, ReLU, FP16 NHWC store (4 consecutive channels per lane)
