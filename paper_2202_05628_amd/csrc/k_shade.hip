@@ -31,11 +31,13 @@ typedef float fl4 __attribute__((ext_vector_type(4)));
 
 constexpr int kPix = 40;            // halves per staged pixel / weight row: 32 channels + 8 (bank spread)
 constexpr int kConvWaves = 4;
-constexpr int kConvPB = 2;          // 16-pixel blocks per wave
-constexpr int kConvTP = kConvWaves * 16 * kConvPB;   // 128 pixels per workgroup
 
-template <int NCB>
+// NCB blocks of 16 output channels per workgroup; PB blocks of 16 pixels per
+// wave (a workgroup covers 64 PB pixels of a row).
+template <int NCB, int PB>
 __global__ __launch_bounds__(256) void k_conv3x3(ConvLaunch a) {
+    constexpr int kConvPB = PB;
+    constexpr int kConvTP = kConvWaves * 16 * PB;
     const _Float16* src1 = reinterpret_cast<const _Float16*>(a.src1);
     const _Float16* src2 = reinterpret_cast<const _Float16*>(a.src2);
     const _Float16* wgt = reinterpret_cast<const _Float16*>(a.wgt);
@@ -162,13 +164,30 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvLaunch a) {
     }
 }
 
+template <int NCB, int PB>
+static void conv_launch(const ConvLaunch& a, hipStream_t st) {
+    constexpr int TP = kConvWaves * 16 * PB;
+    const dim3 grid((unsigned)((a.W + TP - 1) / TP), (unsigned)a.H, (unsigned)(a.N * (a.Cout / (16 * NCB))));
+    hipLaunchKernelGGL((k_conv3x3<NCB, PB>), grid, dim3(256), 0, st, a);
+}
+
+// 64 output channels per workgroup when Cout allows, else 32; the pixel tile
+// (64, 128 or 256 pixels of a row) no wider than the row needs, and wider for
+// the 32-channel layers so that each staged operand feeds more matrix ops.
 hipError_t launch_conv3x3(const ConvLaunch& a, hipStream_t st) {
     if ((a.C1 % 32) || (a.C2 % 32) || a.C1 <= 0 || (a.C2 > 0 && !a.src2)) return hipErrorInvalidValue;
     const int NCB = a.Cout % 64 == 0 ? 4 : (a.Cout % 32 == 0 ? 2 : 0);
     if (NCB == 0) return hipErrorInvalidValue;
-    const dim3 grid((unsigned)((a.W + kConvTP - 1) / kConvTP), (unsigned)a.H, (unsigned)(a.N * (a.Cout / (16 * NCB))));
-    if (NCB == 4) hipLaunchKernelGGL(k_conv3x3<4>, grid, dim3(256), 0, st, a);
-    else hipLaunchKernelGGL(k_conv3x3<2>, grid, dim3(256), 0, st, a);
+    if (a.W <= 64) {
+        if (NCB == 4) conv_launch<4, 1>(a, st);
+        else conv_launch<2, 1>(a, st);
+    } else if (NCB == 4) {
+        conv_launch<4, 2>(a, st);
+    } else if (a.W >= 256) {
+        conv_launch<2, 4>(a, st);
+    } else {
+        conv_launch<2, 2>(a, st);
+    }
     return hipGetLastError();
 }
 
@@ -180,11 +199,11 @@ __global__ __launch_bounds__(256) void k_to_nhwc(const float* __restrict__ F, in
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
         const size_t n = i / HW, pix = i % HW;
         _Float16* o = out + i * Cp;
-        for (int c = 0; c < Cp; c += 4) {
-            half4 h;
+        for (int c = 0; c < Cp; c += 8) {
+            half8 h;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) h[e] = (_Float16)(c + e < C ? F[(n * C + c + e) * HW + pix] : 0.0f);
-            *reinterpret_cast<half4*>(o + c) = h;
+            for (int e = 0; e < 8; ++e) h[e] = (_Float16)(c + e < C ? F[(n * C + c + e) * HW + pix] : 0.0f);
+            *reinterpret_cast<half8*>(o + c) = h;
         }
     }
 }
