@@ -100,7 +100,7 @@ def test_bf16_form_errors():
             assert rmax <= TOL_BF16 and rmean <= TOL_BF16, (name, v, rmax, rmean)
         log(f"  view {v}: {row}")
         report["maps"].append(row)
-    out = os.path.join(os.environ.get("GRAFT_REPO_ROOT", "."), "gpurun_out")
-    if os.path.isdir(out):
+    out = os.environ.get("ARTEMIS_REPORT_DIR")   # optional: where to keep the per-map error report
+    if out and os.path.isdir(out):
         with open(os.path.join(out, "bf16_errors.json"), "w") as fh:
             json.dump(report, fh, indent=1)
