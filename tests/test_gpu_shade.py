@@ -24,7 +24,7 @@ def rend():
     return art.Renderer(0)
 
 
-@pytest.mark.parametrize("C,N,H,W", [(16, 2, 32, 48), (16, 1, 24, 136), (8, 3, 16, 16), (16, 1, 16, 264)])
+@pytest.mark.parametrize("C,N,H,W", [(16, 2, 32, 48), (16, 1, 24, 136), (8, 3, 16, 16), (16, 1, 16, 264), (32, 1, 16, 32), (4, 2, 8, 72)])
 def test_shading_matches_reference(rend, C, N, H, W):
     import torch
     rng = np.random.default_rng(60 + C + W)

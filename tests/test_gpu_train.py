@@ -174,3 +174,32 @@ def test_training_fits_target_maps(tiny):
     for lam, (a, b, _) in results.items():
         assert b < 0.2 * a, lam
     assert results[0.05][2] < results[0.0][2]
+
+
+def test_vrt_with_leaves_outside_the_root():
+    """A global translation pushes part of the animal out of the posed root:
+    the dropped leaves have no Q and N_v counts only the leaves inside."""
+    import torch
+    s = sg.make_scene("tiny")
+    r, R, T = sg.make_poses(s.J, 2)
+    T = T.copy()
+    T[0] = [0.8, 0.0, 0.0]
+    T[1] = [0.0, -0.7, 0.3]
+    K, c2w = sg.make_cameras(s, 1, 16, 16)
+    rend = make_renderer(s, (r, R, T), K, c2w, 16, 16)
+    B = oracle.fk(s.parent, s.rest_joint, r, R, T)
+    f = torch.from_numpy(s.feat).cuda()
+    lam = 0.5
+    L, g = rend.vrt(f, lam)
+    Lr, gr, dropped = 0.0, np.zeros(s.feat.shape), 0
+    for p in range(2):
+        _, _, cells, valid, pt = oracle.pose_occupancy(s.ijk, s.depth, s.bone, s.weight, B[p])
+        assert not guard_leaves(pt[valid], s.depth).any()
+        lp, gp, nv = otr.vrt(oracle.posed_keys(cells, valid).astype(np.int64), s.feat.astype(np.float64), lam)
+        Lr += lp
+        gr += gp
+        dropped += s.n - nv
+    log(f"vrt with {dropped} dropped leaf-poses: loss {L:.6f} vs {Lr:.6f}")
+    assert dropped > 1000
+    assert L == pytest.approx(Lr, rel=1e-6)
+    np.testing.assert_allclose(g.cpu().numpy(), gr, rtol=1e-5, atol=1e-9)
