@@ -278,6 +278,9 @@ __device__ inline void root_span(const R* d, const R* q, const R* inv, R h, int 
 #ifndef ART_RENDER_WAVES_PER_EU
 #define ART_RENDER_WAVES_PER_EU 3
 #endif
+#ifndef ART_RENDER_WAVES_PER_EU_F32
+#define ART_RENDER_WAVES_PER_EU_F32 4   // FP32 geometry (the BF16 form): fewer registers, one more wave
+#endif
 // Adjoint gradient scatter through LDS: each round the lanes with a sample
 // stage (leaf, w); the feature gradients w g_c are then added with lanes
 // mapped to (sample, channel), so the 16 lanes of one atomic instruction
@@ -941,7 +944,8 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
 // Persistent compositing kernel: each single-wave workgroup takes non-empty
 // tiles from the queue until it is exhausted (every wave reaches the exit).
 template <int C, int ST, typename R, int MODE>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MODE == 1 ? 1 : (MODE == 6 ? 2 : ART_RENDER_WAVES_PER_EU))))
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(
+    MODE == 1 ? 1 : (MODE == 6 ? 2 : (sizeof(R) == 4 ? ART_RENDER_WAVES_PER_EU_F32 : ART_RENDER_WAVES_PER_EU)))))
 void k_render(RArgs a) {
     __shared__ uint32_t s_mask[1][16][kMaskPitch];
     __shared__ uint16_t s_pref[1][16][kPrefPitch];
