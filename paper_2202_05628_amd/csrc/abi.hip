@@ -499,6 +499,7 @@ art_status render_call(art_ctx* ctx, int C, art_dtype dtype, const void* sigma, 
             std::vector<char> redo(items, 0);
             size_t need = 0;
             bool any = false;
+            for (size_t i = 0; i < items; ++i) ctx->s.pair_hint = std::max<size_t>(ctx->s.pair_hint, hov[2 * i + 1]);
             for (size_t i = 0; i < items; ++i)
                 if (hov[2 * i] != 0u && hov[2 * i + 1] > ctx->s.pair_cap) {
                     redo[i] = 1;

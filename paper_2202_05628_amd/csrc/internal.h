@@ -110,6 +110,7 @@ struct Scratch {
     DevBuf loss;                         // [1] double: loss accumulator of the training-step kernels
     DevBuf interval;                     // [slots][V][tiles][64] float2 proposed intervals
     size_t pair_cap = 0;
+    size_t pair_hint = 0;                // largest tile-list length seen (sizes the list sort's grid)
     int slots = 0;                       // poses whose octrees are held at once
 };
 

@@ -16,6 +16,8 @@
 //                 per covered tile
 //   (stable radix sort of the pairs)
 //   k_tile_mark : first / one-past-last pair of each tile
+#include <algorithm>
+
 #include "device_util.h"
 #include "internal.h"
 
@@ -256,7 +258,10 @@ hipError_t launch_bin(Scratch& s, const CamParams* cam_dev, const OctreeSlot& o,
     sb.vstride = vstride;
     sb.d_n = &cnt[0].pad[0];
     sb.nstride = sizeof(PoseCounters) / 4;
-    sb.n_cap = (uint32_t)s.pair_cap;
+    // size the sort grid by the largest list seen so far (plus a quarter), so
+    // that blocks take whole 4096-key tiles; any larger list is still sorted in
+    // full (blocks then take several tiles)
+    sb.n_cap = (uint32_t)(s.pair_hint ? std::min(s.pair_cap, s.pair_hint + s.pair_hint / 4 + 4096) : s.pair_cap);
     sb.hist = s.hist.as<uint32_t>();
     sb.digit_tot = s.digit_tot.as<uint32_t>();
     sb.batch = batch;
