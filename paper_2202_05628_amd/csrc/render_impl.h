@@ -402,7 +402,9 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
                 const R span = tb - ta;
                 const R ts = fmax(ta, ta + (R)u.x * span - (R)a.margin);
                 const R te = a.near_only ? tb : fmin(tb, ta + (R)u.y * span + (R)a.margin);
-                if (te > ts) {
+                // an interval (with its margin) that covers the whole span skips
+                // nothing, and a fallback could only repeat the same traversal
+                if (te > ts && (ts > ta || te < tb)) {
                     ta = ts;
                     tb = te;
                     prop = true;
