@@ -255,9 +255,10 @@ def shading_leg(args, r, F, torch, C, maps=32):
     r.set_shading_weights(C, sgm.make_shading_weights(C))
     out = torch.empty((maps, 4, H, W), dtype=torch.float32, device=F.device)
     t = _timed(torch, lambda: r.shade(Fm, out=out), args.proposal_steps)
-    # multiply-adds of the 3x3 convolutions (Cin of layer 0 padded to 32) and the head
+    # multiply-adds of the 3x3 convolutions (layer 0 counted with its C input
+    # channels, not the 32 it is padded to) and the head
     px = maps * H * W
-    macs = 9 * px * (32 * 32 + 32 * 32) + 9 * px // 4 * (32 * 64 + 64 * 64) + 9 * px // 16 * (64 * 128 + 128 * 128) \
+    macs = 9 * px * (C * 32 + 32 * 32) + 9 * px // 4 * (32 * 64 + 64 * 64) + 9 * px // 16 * (64 * 128 + 128 * 128) \
         + 9 * px // 64 * (128 * 256 + 256 * 256) + 9 * px // 16 * (384 * 128 + 128 * 128) \
         + 9 * px // 4 * (192 * 64 + 64 * 64) + 9 * px * (96 * 32 + 32 * 32) + px * 32 * 4
     tflops = 2 * macs / t / 1e12

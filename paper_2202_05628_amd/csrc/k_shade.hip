@@ -31,18 +31,41 @@ typedef float fl4 __attribute__((ext_vector_type(4)));
 
 constexpr int kPix = 40;            // halves per staged pixel / weight row: 32 channels + 8 (bank spread)
 constexpr int kConvWaves = 4;
+// Fourth descriptor word of a raw buffer resource (32-bit data format, no
+// swizzle) for CDNA3 / CDNA4.
+constexpr int kBufferFlags = 0x00020000;
 
-// NCB blocks of 16 output channels per workgroup; PB blocks of 16 pixels per
-// wave (a workgroup covers 64 PB pixels of a row).
-template <int NCB, int PB>
-__global__ __launch_bounds__(256) void k_conv3x3(ConvLaunch a) {
+// Workgroup tile: 4 waves, WC of them side by side over output channels and
+// 4 / WC over pixels; each wave computes PB blocks of 16 pixels x NCB blocks
+// of 16 output channels, so a workgroup covers TP = 16 PB (4 / WC) pixels of
+// a row and TC = 16 NCB WC output channels.  A larger wave tile reads fewer
+// LDS operands per matrix product (PB + NCB reads for PB NCB products).
+template <int NCB, int PB, int WC>
+struct ConvTile {
+    static constexpr int WP = kConvWaves / WC;
+    static constexpr int TP = 16 * PB * WP;
+    static constexpr int TC = 16 * NCB * WC;
+    static constexpr int lds_bytes = ((TP + 2) + 3 * TC) * kPix * 2;
+    static constexpr int in_it = ((TP + 2) * 4 + 255) / 256;   // staged 16-byte vectors per thread
+    static constexpr int w_it = (3 * TC * 4 + 255) / 256;
+    // registers per lane: accumulators, B operands, staged loads, their offsets, the rest
+    static constexpr int vgprs = 4 * PB * NCB + 4 * PB + 4 * (in_it + w_it) + 2 * in_it + w_it + 24;
+    static constexpr int by_lds = 163840 / lds_bytes;   // resident workgroups per CU (160 KB LDS)
+    static constexpr int by_regs = 512 / vgprs;
+    static constexpr int waves_per_simd = by_lds < by_regs ? (by_lds < 4 ? by_lds : 4) : (by_regs < 4 ? by_regs : 4);
+};
+
+template <int NCB, int PB, int WC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ConvTile<NCB, PB, WC>::waves_per_simd)))
+void k_conv3x3(ConvLaunch a) {
+    using Tl = ConvTile<NCB, PB, WC>;
     constexpr int kConvPB = PB;
-    constexpr int kConvTP = kConvWaves * 16 * PB;
+    constexpr int kConvTP = Tl::TP;
     const _Float16* src1 = reinterpret_cast<const _Float16*>(a.src1);
     const _Float16* src2 = reinterpret_cast<const _Float16*>(a.src2);
     const _Float16* wgt = reinterpret_cast<const _Float16*>(a.wgt);
     _Float16* outp = reinterpret_cast<_Float16*>(a.out);
-    constexpr int TC = 16 * NCB;                         // output channels per workgroup
+    constexpr int TC = Tl::TC;                           // output channels per workgroup
     constexpr int kInVec = (kConvTP + 2) * 4;            // 16-byte vectors of a staged input row
     constexpr int kWVec = 3 * TC * 4;                    // 16-byte vectors of a staged kernel row
     constexpr int kInIt = (kInVec + 255) / 256;
@@ -51,6 +74,7 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvLaunch a) {
     __shared__ __align__(16) _Float16 s_w[3 * TC * kPix];
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
+    const int wp = wave % Tl::WP, wc = wave / Tl::WP;   // pixel / channel position of the wave
     const int lane = tid & 63;
     const int x0 = blockIdx.x * kConvTP;
     const int y = blockIdx.y;
@@ -66,6 +90,43 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvLaunch a) {
 #pragma unroll
         for (int c = 0; c < NCB; ++c) acc[p][c] = fl4{0.0f, 0.0f, 0.0f, 0.0f};
 
+    // The image's input tensors and the weights are read through buffer
+    // resources: a load at an offset beyond a resource returns zeros, which is
+    // the zero padding of the halo pixels and of the rows above and below the
+    // image.  Offsets are bytes: a lane part (fixed over the stages) plus a
+    // wave-uniform stage part, each either inside the resource (< 2^30 bytes,
+    // checked by the launcher) or kOOB, so their sum cannot wrap.
+    constexpr uint32_t kOOB = 1u << 30;
+    const __amdgpu_buffer_rsrc_t rs1 = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(src1 + (size_t)n * a.H * a.W * a.C1), (short)0, a.H * a.W * a.C1 * 2, kBufferFlags);
+    const __amdgpu_buffer_rsrc_t rs2 =
+        a.C2 ? __builtin_amdgcn_make_buffer_rsrc((void*)(src2 + (size_t)n * H2 * W2 * a.C2), (short)0,
+                                                 H2 * W2 * a.C2 * 2, kBufferFlags)
+             : rs1;
+    const __amdgpu_buffer_rsrc_t rsw =
+        __builtin_amdgcn_make_buffer_rsrc((void*)wgt, (short)0, 9 * a.Cout * Cin * 2, kBufferFlags);
+    // input vector v = tid + 256 j is channel quarter v % 4 of pixel v / 4 of
+    // the staged row (x = x0 - 1 + v / 4); weight vector v is quarter v % 4 of
+    // kernel-row entry v / 4 = (kx, output channel)
+    uint32_t in_b1[kInIt], in_b2[kInIt];
+#pragma unroll
+    for (int j = 0; j < kInIt; ++j) {
+        const int v = tid + 256 * j;
+        const int q = v & 3;
+        const int xx = x0 - 1 + (v >> 2);
+        const bool ok = v < kInVec && xx >= 0 && xx < a.W;
+        in_b1[j] = ok ? (uint32_t)(xx * a.C1 + 8 * q) * 2u : kOOB;
+        in_b2[j] = ok ? (uint32_t)((xx >> 1) * a.C2 + 8 * q) * 2u : kOOB;
+    }
+    uint32_t w_b[kWIt];
+#pragma unroll
+    for (int j = 0; j < kWIt; ++j) {
+        const int v = tid + 256 * j;
+        const int q = v & 3, r = v >> 2;
+        const int co = r % TC, kx = r / TC;
+        w_b[j] = v < kWVec ? (uint32_t)((kx * a.Cout + ct * TC + co) * Cin + 8 * q) * 2u : kOOB;
+    }
+
     // Software pipeline: the global loads of stage s + 1 go to registers while
     // the matrix cores work on stage s from LDS.
     half8 rin[kInIt], rw[kWIt];
@@ -73,34 +134,17 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvLaunch a) {
         const int c0 = (st / 3) * 32, ky = st % 3;
         const int yy = y + ky - 1;
         const bool up = c0 >= a.C1;
+        const uint32_t row = (yy < 0 || yy >= a.H) ? kOOB
+                             : up ? (uint32_t)(((yy >> 1) * W2) * a.C2 + (c0 - a.C1)) * 2u
+                                  : (uint32_t)((yy * a.W) * a.C1 + c0) * 2u;
 #pragma unroll
-        for (int j = 0; j < kInIt; ++j) {
-            const int v = tid + 256 * j;
-            half8 val = half8{0, 0, 0, 0, 0, 0, 0, 0};
-            if (v < kInVec) {
-                const int px = v >> 2, q = v & 3;
-                const int xx = x0 - 1 + px;
-                if (yy >= 0 && yy < a.H && xx >= 0 && xx < a.W) {
-                    if (!up)
-                        val = *reinterpret_cast<const half8*>(
-                            src1 + (((size_t)n * a.H + yy) * a.W + xx) * a.C1 + c0 + 8 * q);
-                    else
-                        val = *reinterpret_cast<const half8*>(
-                            src2 + (((size_t)n * H2 + (yy >> 1)) * W2 + (xx >> 1)) * a.C2 + (c0 - a.C1) + 8 * q);
-                }
-            }
-            rin[j] = val;
-        }
+        for (int j = 0; j < kInIt; ++j)
+            rin[j] = __builtin_bit_cast(half8, __builtin_amdgcn_raw_buffer_load_b128(up ? rs2 : rs1,
+                                                                                     (up ? in_b2[j] : in_b1[j]) + row, 0, 0));
+        const uint32_t wrow = (uint32_t)(ky * 3 * a.Cout * Cin + c0) * 2u;
 #pragma unroll
-        for (int j = 0; j < kWIt; ++j) {
-            const int v = tid + 256 * j;
-            if (v < kWVec) {
-                const int q = v & 3, r = v >> 2;
-                const int co = r % TC, kx = r / TC;
-                rw[j] = *reinterpret_cast<const half8*>(wgt + ((size_t)(ky * 3 + kx) * a.Cout + ct * TC + co) * Cin +
-                                                         c0 + 8 * q);
-            }
-        }
+        for (int j = 0; j < kWIt; ++j)
+            rw[j] = __builtin_bit_cast(half8, __builtin_amdgcn_raw_buffer_load_b128(rsw, w_b[j] + wrow, 0, 0));
     };
     auto store_stage = [&]() {
 #pragma unroll
@@ -125,13 +169,14 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvLaunch a) {
             half8 bx[kConvPB];
 #pragma unroll
             for (int p = 0; p < kConvPB; ++p) {
-                const int px = (wave * kConvPB + p) * 16 + (lane & 15) + kx;
+                const int px = (wp * kConvPB + p) * 16 + (lane & 15) + kx;
                 bx[p] = *reinterpret_cast<const half8*>(s_in + px * kPix + 8 * (lane >> 4));
             }
 #pragma unroll
             for (int c = 0; c < NCB; ++c) {
                 const half8 aw =
-                    *reinterpret_cast<const half8*>(s_w + (kx * TC + c * 16 + (lane & 15)) * kPix + 8 * (lane >> 4));
+                    *reinterpret_cast<const half8*>(s_w + (kx * TC + (wc * NCB + c) * 16 + (lane & 15)) * kPix +
+                                                    8 * (lane >> 4));
 #pragma unroll
                 for (int p = 0; p < kConvPB; ++p)
                     acc[p][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(aw, bx[p], acc[p][c], 0, 0, 0);
@@ -146,12 +191,12 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvLaunch a) {
     // epilogue: bias, ReLU, FP16 NHWC store (4 consecutive channels per lane)
 #pragma unroll
     for (int p = 0; p < kConvPB; ++p) {
-        const int x = x0 + (wave * kConvPB + p) * 16 + (lane & 15);
+        const int x = x0 + (wp * kConvPB + p) * 16 + (lane & 15);
         if (x >= a.W) continue;
         _Float16* o = outp + (((size_t)n * a.H + y) * a.W + x) * a.Cout + ct * TC;
 #pragma unroll
         for (int c = 0; c < NCB; ++c) {
-            const int co = c * 16 + 4 * (lane >> 4);
+            const int co = (wc * NCB + c) * 16 + 4 * (lane >> 4);
             half4 h;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
@@ -164,30 +209,49 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvLaunch a) {
     }
 }
 
-template <int NCB, int PB>
+template <int NCB, int PB, int WC>
 static void conv_launch(const ConvLaunch& a, hipStream_t st) {
-    constexpr int TP = kConvWaves * 16 * PB;
-    const dim3 grid((unsigned)((a.W + TP - 1) / TP), (unsigned)a.H, (unsigned)(a.N * (a.Cout / (16 * NCB))));
-    hipLaunchKernelGGL((k_conv3x3<NCB, PB>), grid, dim3(256), 0, st, a);
+    using Tl = ConvTile<NCB, PB, WC>;
+    const dim3 grid((unsigned)((a.W + Tl::TP - 1) / Tl::TP), (unsigned)a.H, (unsigned)(a.N * (a.Cout / Tl::TC)));
+    hipLaunchKernelGGL((k_conv3x3<NCB, PB, WC>), grid, dim3(256), 0, st, a);
 }
 
-// 64 output channels per workgroup when Cout allows, else 32; the pixel tile
-// (64, 128 or 256 pixels of a row) no wider than the row needs, and wider for
-// the 32-channel layers so that each staged operand feeds more matrix ops.
+template <int NCB, int WC>
+static void conv_launch_pb(const ConvLaunch& a, int pb, hipStream_t st) {
+    switch (pb) {
+        case 1: conv_launch<NCB, 1, WC>(a, st); break;
+        case 2: conv_launch<NCB, 2, WC>(a, st); break;
+        default: conv_launch<NCB, 4, WC>(a, st); break;
+    }
+}
+
+// Tile choice: 64 output channels per wave when Cout allows (else 32), the
+// waves spread over as many channel tiles as Cout holds (up to 4), then the
+// widest pixel tile (up to 4 blocks of 16 per wave) that the row fills.  (8
+// blocks per wave for the 32-channel layers ran 10-20 % longer: two waves per
+// SIMD.)
 hipError_t launch_conv3x3(const ConvLaunch& a, hipStream_t st) {
     if ((a.C1 % 32) || (a.C2 % 32) || a.C1 <= 0 || (a.C2 > 0 && !a.src2)) return hipErrorInvalidValue;
-    const int NCB = a.Cout % 64 == 0 ? 4 : (a.Cout % 32 == 0 ? 2 : 0);
-    if (NCB == 0) return hipErrorInvalidValue;
-    if (a.W <= 64) {
-        if (NCB == 4) conv_launch<4, 1>(a, st);
-        else conv_launch<2, 1>(a, st);
-    } else if (NCB == 4) {
-        conv_launch<4, 2>(a, st);
-    } else if (a.W >= 256) {
-        conv_launch<2, 4>(a, st);
-    } else {
-        conv_launch<2, 2>(a, st);
+    // buffer resources: one image of each input, and the weights, below 2^30 bytes
+    const int64_t lim = (int64_t)1 << 30;
+    if ((int64_t)a.H * a.W * a.C1 * 2 >= lim || (int64_t)(a.H / 2) * (a.W / 2) * a.C2 * 2 >= lim ||
+        (int64_t)9 * a.Cout * (a.C1 + a.C2) * 2 >= lim)
+        return hipErrorInvalidValue;
+    if (a.Cout % 32) return hipErrorInvalidValue;
+    if (a.Cout % 64) {   // 32 output channels per workgroup, 4 waves over pixels
+        if (a.W >= 256) conv_launch<2, 4, 1>(a, st);
+        else if (a.W >= 128) conv_launch<2, 2, 1>(a, st);
+        else conv_launch<2, 1, 1>(a, st);
+        return hipGetLastError();
     }
+    const int tiles = a.Cout / 64;
+    const int wc = tiles % 4 == 0 ? 4 : (tiles % 2 == 0 ? 2 : 1);
+    const int wp = kConvWaves / wc;
+    int pb = 4;
+    while (pb > 1 && 16 * pb * wp > a.W) pb >>= 1;
+    if (wc == 4) conv_launch_pb<4, 4>(a, pb, st);
+    else if (wc == 2) conv_launch_pb<4, 2>(a, pb, st);
+    else conv_launch_pb<4, 1>(a, pb, st);
     return hipGetLastError();
 }
 
