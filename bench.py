@@ -141,6 +141,12 @@ def cpu_baseline(scene, poses, K, c2w, H, W, lam, budget_s):
     oracle.render(o[idx], d[idx], scene.depth, ok, ol, scene.sigma, scene.feat, lam)
     t_render = time.perf_counter() - t1
     t_pose = t_build + t_render * (n_all / n)
+    # the render on one host thread, on a sample of about 2 s
+    n1 = int(min(n_all, max(500, 2.0 * rate / max(threads, 1))))
+    idx = rng.choice(n_all, n1, replace=False)
+    t1 = time.perf_counter()
+    oracle.render(o[idx], d[idx], scene.depth, ok, ol, scene.sigma, scene.feat, lam, n_threads=1)
+    t_one = time.perf_counter() - t1
     return {
         "value": n_all / t_pose / 1e6,
         "unit": "Mrays/s",
@@ -149,6 +155,8 @@ def cpu_baseline(scene, poses, K, c2w, H, W, lam, budget_s):
         "sample": (f"1 pose x {K.shape[0]} views at {H}x{W}: FK, skinning and occupancy of all "
                    f"{scene.n} leaves timed in full ({t_build:.2f} s); {n} of {n_all} rays rendered "
                    f"({t_render:.2f} s, uniform seeded sample) and extrapolated to the pose"),
+        "one_core_render_mrays_s": n1 / t_one / 1e6,
+        "one_core_sample": f"{n1} rays of the same pose on one host thread ({t_one:.2f} s)",
     }
 
 
@@ -281,13 +289,26 @@ def adjoint_leg(args, art, sg, torch):
     feat = torch.from_numpy(scene.feat).cuda()
     tgt = torch.from_numpy(sg.make_targets(P, V, cfg.C, H, W, cfg.target_seed)).cuda()
     F, A, T = r.render(sig, feat, args.lambda_th)
+    st = r.stats()
     dF = (F - tgt).contiguous()
     ds = torch.zeros_like(sig)
     df = torch.zeros_like(feat)
     t = _timed(torch, lambda: r.backward(sig, feat, F, T, dF, d_sigma=ds, d_feat=df), args.proposal_steps)
+    r.backward(sig, feat, F, T, dF, d_sigma=ds, d_feat=df, timing=True)
+    tm = r.timing()
     rays = P * V * H * W
+    # per composited sample: the re-gathered density, features and leaf index
+    # (72 B) and the gradient atomics (C + 1 floats); per ray of a non-empty
+    # tile: dL/dF, F and T_final
+    per_sample = 4 * (cfg.C + 1) + 4 + 4 * (cfg.C + 1)
+    per_ray = 4 * cfg.C + 4 * cfg.C + 4
+    alg = st["samples"] * per_sample + st["tile_rays"] * per_ray
+    kern_ms = tm["render"] / max(tm["n_render"], 1)
     return {"workload": f"adjoint: {P} pose x {V} cameras at {H}x{W} ({rays} rays), L2 loss to seeded targets",
-            "mrays_s": round(rays / t / 1e6, 2), "ms_per_call": round(t * 1e3, 3)}
+            "mrays_s": round(rays / t / 1e6, 2), "ms_per_call": round(t * 1e3, 3),
+            "adjoint_kernel_ms": round(kern_ms, 4), "samples": st["samples"],
+            "algorithmic_bytes_per_sample": per_sample, "algorithmic_bytes_per_ray": per_ray,
+            "adjoint_hbm_frac": round(alg / (kern_ms * 1e-3) / 8e12, 4)}
 
 
 def train_leg(args, art, sg, torch):
