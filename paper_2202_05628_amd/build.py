@@ -29,13 +29,19 @@ CFLAGS = [
 ]
 
 
+# per-file extra flags: the proposal network's inference keeps its matrix-core
+# accumulators in ordinary VGPRs (no AGPR copies before the BF16 conversions)
+EXTRA = {"k_mlp.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+
+
 def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
 def _compile(src: str, build_dir: str, defines) -> str:
     obj = os.path.join(build_dir, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *CFLAGS, *[f"-D{d}" for d in defines], "-I", os.path.join(HERE, "..", "include"),
+    cmd = [HIPCC, *CFLAGS, *EXTRA.get(os.path.basename(src), []), *[f"-D{d}" for d in defines],
+           "-I", os.path.join(HERE, "..", "include"),
            "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

@@ -272,6 +272,78 @@ struct WRegs {   // forward operand heads held in registers (inference)
 };
 
 // ---------------------------------------------------------------------------
+// inference precision (single BF16 operands): the biases enter as the
+// accumulator input of a layer's first product, activations are rounded to
+// BF16 by the hardware conversion (round to nearest even, as f2bf) and the
+// ReLU is taken on the rounded values (rounding keeps the sign, so this is
+// the ReLU of the FP32 value, rounded), as a 16-bit integer maximum with 0.
+// ---------------------------------------------------------------------------
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ inline uint32_t cvt2(float a, float b) {   // two floats -> packed BF16 (a in the low half)
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{a, b}, bf16x2));
+}
+__device__ inline uint32_t relu2(uint32_t h) {
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(s16x2, h), s16x2{0, 0}));
+}
+__device__ inline bf16x8 cvt8(float v0, float v1, float v2, float v3, float v4, float v5, float v6, float v7) {
+    return __builtin_bit_cast(bf16x8, u32x4{cvt2(v0, v1), cvt2(v2, v3), cvt2(v4, v5), cvt2(v6, v7)});
+}
+__device__ inline bf16x8 relu_bf16(const f32x4 a, const f32x4 b) {
+    return __builtin_bit_cast(bf16x8, u32x4{relu2(cvt2(a[0], a[1])), relu2(cvt2(a[2], a[3])),
+                                            relu2(cvt2(b[0], b[1])), relu2(cvt2(b[2], b[3]))});
+}
+
+// Per-lane layer biases in accumulator layout (element e of tile mt is
+// output 16 mt + 4 g + e).
+struct InferBias {
+    f32x4 b2[4], b3[4];
+    float b4[2];
+};
+__device__ inline void load_infer_bias(const float* __restrict__ theta, const MlpDims& m, int g, InferBias& B) {
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            B.b2[mt][e] = theta[m.ob2 + 16 * mt + 4 * g + e];
+            B.b3[mt][e] = theta[m.ob3 + 16 * mt + 4 * g + e];
+        }
+    B.b4[0] = theta[m.ob4];
+    B.b4[1] = theta[m.ob4 + 1];
+}
+__device__ inline void load_pose_bias(const float* __restrict__ cb, int g, f32x4* c1) {
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) c1[mt][e] = cb[16 * mt + 4 * g + e];
+}
+
+// Outputs (u_near, u_far) of the 16 rays of a group; x: the ray inputs, read
+// by the lanes of group 0 (g = 0) only; c1: the pose's first-layer bias.
+template <typename WSrc>
+__device__ inline float2 infer_group(const WSrc& w, const InferBias& B, const f32x4* c1, const float* x, int g) {
+    const bf16x8 X = cvt8(g == 0 ? x[0] : 0.0f, g == 0 ? x[1] : 0.0f, g == 0 ? x[2] : 0.0f, g == 0 ? x[3] : 0.0f,
+                          g == 0 ? x[4] : 0.0f, g == 0 ? x[5] : 0.0f, 0.0f, 0.0f);
+    f32x4 t[4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) t[mt] = mfma(w.get(kB_W1 + mt), X, c1[mt]);
+    bf16x8 H0 = relu_bf16(t[0], t[1]), H1 = relu_bf16(t[2], t[3]);
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) t[mt] = mfma(w.get(kB_W2 + 2 * mt + 1), H1, mfma(w.get(kB_W2 + 2 * mt), H0, B.b2[mt]));
+    H0 = relu_bf16(t[0], t[1]);
+    H1 = relu_bf16(t[2], t[3]);
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) t[mt] = mfma(w.get(kB_W3 + 2 * mt + 1), H1, mfma(w.get(kB_W3 + 2 * mt), H0, B.b3[mt]));
+    H0 = relu_bf16(t[0], t[1]);
+    H1 = relu_bf16(t[2], t[3]);
+    const f32x4 z = mfma(w.get(kB_W4 + 1), H1, mfma(w.get(kB_W4), H0, f32x4{B.b4[0], B.b4[1], 0.0f, 0.0f}));
+    return make_float2(sigmoidf(z[0]), sigmoidf(z[1]));
+}
+
+// ---------------------------------------------------------------------------
 // forward (mode 0) / forward + loss + backward (mode 1) over n rays
 // ---------------------------------------------------------------------------
 struct FbArgs {
@@ -325,15 +397,20 @@ __device__ inline void fb_body(const FbArgs& a, int lane, int w, float* sloss) {
 #pragma unroll
             for (int i = 0; i < 6; ++i) x[i] = a.od[ray * 6 + i];
         }
+        if constexpr (!SPLIT) {
+            InferBias B;
+            load_infer_bias(a.theta, m, g, B);
+            f32x4 c1[4];
+            load_pose_bias(a.cbias + (size_t)p * kHid, g, c1);
+            const float2 y = infer_group(W, B, c1, x, g);
+            if (valid && g == 0) reinterpret_cast<float2*>(a.out)[ray] = y;
+            continue;
+        }
         f32x4 h1[4], h2[4], h3[4], z4;
         forward_head<SPLIT>(W, x, a.cbias + (size_t)p * kHid, g, h1);
         forward_tail<SPLIT>(W, a.theta, m, g, h1, h2, h3, z4);
         const float y0 = sigmoidf(z4[0] + a.theta[m.ob4]);
         const float y1 = sigmoidf(z4[1] + a.theta[m.ob4 + 1]);
-        if (!SPLIT) {
-            if (valid && g == 0) reinterpret_cast<float2*>(a.out)[ray] = make_float2(y0, y1);
-            continue;
-        }
         // loss and dL/dz4 (lanes of group 0 hold the two outputs of ray r)
         float d40 = 0.0f, d41 = 0.0f;
         if (valid && g == 0) {
@@ -602,6 +679,8 @@ __global__ __launch_bounds__(256) void k_mlp_infer_tiles(InferLaunch a) {
 #pragma unroll
         for (int b = 0; b < kB_W4T; ++b) W.b[b] = P[b * 64 + lane];
     }
+    InferBias B;
+    load_infer_bias(a.theta, a.m, g, B);
     const uint32_t n_items = *a.n_items;
     const uint32_t nw = gridDim.x * (blockDim.x / 64);
     for (uint32_t idx = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); idx < n_items; idx += nw) {
@@ -610,20 +689,19 @@ __global__ __launch_bounds__(256) void k_mlp_infer_tiles(InferLaunch a) {
         const int tile = (int)(item % (uint32_t)a.TPV);
         const int pb = pvi / a.V, v = pvi % a.V;
         const int tx = tile % a.TX, ty = tile / a.TX;
-        const float* cb = a.cbias + (size_t)(a.pose0 + pb) * kHid;
-        const CamParams& cam = a.cam[v];
+        f32x4 c1[4];
+        load_pose_bias(a.cbias + (size_t)(a.pose0 + pb) * kHid, g, c1);
+        // the ray of the tile pixel `lane` (row-major 8x8); group q reads the
+        // inputs of pixels 16 q .. 16 q + 15 from those lanes
+        float xl[6];
+        ray_f32(a.cam[v], tx * 8 + (lane & 7), ty * 8 + (lane >> 3), xl, xl + 3);
 #pragma unroll 1
         for (int q = 0; q < 4; ++q) {
-            const int pl = q * 16 + r;   // pixel of the tile (row-major 8x8)
-            const int px = tx * 8 + (pl & 7), py = ty * 8 + (pl >> 3);
             float x[6];
-            ray_f32(cam, px, py, x, x + 3);
-            f32x4 h1[4], h2[4], h3[4], z4;
-            forward_head<false>(W, x, cb, g, h1);
-            forward_tail<false>(W, a.theta, a.m, g, h1, h2, h3, z4);
-            if (g == 0)
-                reinterpret_cast<float2*>(a.out)[(size_t)idx * 64 + pl] =
-                    make_float2(sigmoidf(z4[0] + a.theta[a.m.ob4]), sigmoidf(z4[1] + a.theta[a.m.ob4 + 1]));
+#pragma unroll
+            for (int i = 0; i < 6; ++i) x[i] = __shfl(xl[i], 16 * q + r, kWave);
+            const float2 y = infer_group(W, B, c1, x, g);
+            if (g == 0) reinterpret_cast<float2*>(a.out)[(size_t)idx * 64 + 16 * q + r] = y;
         }
     }
 }
