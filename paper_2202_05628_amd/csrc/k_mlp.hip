@@ -340,7 +340,8 @@ __device__ inline float2 infer_group(const WSrc& w, const InferBias& B, const f3
     H0 = relu_bf16(t[0], t[1]);
     H1 = relu_bf16(t[2], t[3]);
     const f32x4 z = mfma(w.get(kB_W4 + 1), H1, mfma(w.get(kB_W4), H0, f32x4{B.b4[0], B.b4[1], 0.0f, 0.0f}));
-    return make_float2(sigmoidf(z[0]), sigmoidf(z[1]));
+    // sigmoid with the hardware reciprocal (1 ulp)
+    return make_float2(__builtin_amdgcn_rcpf(1.0f + __expf(-z[0])), __builtin_amdgcn_rcpf(1.0f + __expf(-z[1])));
 }
 
 // ---------------------------------------------------------------------------

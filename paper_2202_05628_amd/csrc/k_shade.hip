@@ -8,10 +8,11 @@
 // stride 1, bias, optional ReLU) is an implicit GEMM on the matrix cores:
 // D[cout][pixel] += W[cout][k] X[k][pixel] over k = (ky, kx, cin), with
 // v_mfma_f32_16x16x32_f16 (FP16 operands, FP32 accumulation).  A workgroup
-// (4 waves) computes 128 consecutive pixels of one image row for 16 NCB output
-// channels; per 32-channel chunk and kernel row (a stage) it stages the input
-// row (with its halo) and the 3 x 16 NCB weight rows in LDS, the global loads
-// of the next stage in flight while the matrix cores work on the current one.  The decoder's input
+// (4 waves) computes TP consecutive pixels of one image row for TC output
+// channels (the tile is chosen per layer, see ConvTile); per 32-channel chunk
+// and kernel row (a stage) it stages the input row (with its halo) and the
+// 3 x TC weight rows in LDS, the global loads of the next stage in flight
+// while the matrix cores work on the current one.  The decoder's input
 // (skip connection, nearest-upsampled deeper level) is read by the staging
 // directly: channels [0, C1) from the same-resolution source, [C1, C1 + C2)
 // from the half-resolution one at (y/2, x/2), so neither the upsampled tensor
@@ -31,6 +32,10 @@ typedef float fl4 __attribute__((ext_vector_type(4)));
 
 constexpr int kPix = 40;            // halves per staged pixel / weight row: 32 channels + 8 (bank spread)
 constexpr int kConvWaves = 4;
+#ifndef ART_CONV_XCD
+#define ART_CONV_XCD 1
+#endif
+constexpr uint32_t kXcds = 8;
 // Fourth descriptor word of a raw buffer resource (32-bit data format, no
 // swizzle) for CDNA3 / CDNA4.
 constexpr int kBufferFlags = 0x00020000;
@@ -76,11 +81,27 @@ void k_conv3x3(ConvLaunch a) {
     const int wave = tid >> 6;
     const int wp = wave % Tl::WP, wc = wave / Tl::WP;   // pixel / channel position of the wave
     const int lane = tid & 63;
-    const int x0 = blockIdx.x * kConvTP;
-    const int y = blockIdx.y;
+    // Workgroups are dealt to the 8 XCDs in turn (XCD = linear id mod 8);
+    // renumbering them so that each XCD gets a contiguous range of (pixel
+    // tile, row, image) keeps the neighbouring rows that read the same input
+    // rows, and the weights, in one XCD's L2.
+    int bx = blockIdx.x, y = blockIdx.y, bz = blockIdx.z;
+#if ART_CONV_XCD
+    {
+        const uint32_t gx = gridDim.x, gy = gridDim.y;
+        const uint32_t nb = gx * gy * gridDim.z;
+        const uint32_t hw = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+        const uint32_t q = nb / kXcds, r = nb % kXcds, k = hw % kXcds;
+        const uint32_t L = k * q + (k < r ? k : r) + hw / kXcds;
+        bx = (int)(L % gx);
+        y = (int)((L / gx) % gy);
+        bz = (int)(L / (gx * gy));
+    }
+#endif
+    const int x0 = bx * kConvTP;
     const int ntc = a.Cout / TC;
-    const int ct = blockIdx.z % ntc;
-    const int n = blockIdx.z / ntc;
+    const int ct = bz % ntc;
+    const int n = bz / ntc;
     const int Cin = a.C1 + a.C2;
     const int H2 = a.H >> 1, W2 = a.W >> 1;
     const int nstage = (Cin / 32) * 3;                   // (32-channel chunk, kernel row) stages
