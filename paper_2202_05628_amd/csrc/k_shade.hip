@@ -58,6 +58,7 @@ struct ConvTile {
     static constexpr int by_lds = 163840 / lds_bytes;   // resident workgroups per CU (160 KB LDS)
     static constexpr int by_regs = 512 / vgprs;
     static constexpr int waves_per_simd = by_lds < by_regs ? (by_lds < 4 ? by_lds : 4) : (by_regs < 4 ? by_regs : 4);
+    static_assert(waves_per_simd >= 1, "convolution tile does not fit one CU");
 };
 
 template <int NCB, int PB, int WC>
