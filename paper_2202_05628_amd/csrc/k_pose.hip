@@ -8,6 +8,8 @@
 //            plus its own index as the sort payload.  Leaf geometry is read as
 //            SoA planes (ijk, bone ids, weights), so consecutive threads read
 //            consecutive addresses of every plane.
+#include <algorithm>
+
 #include "device_util.h"
 #include "internal.h"
 
@@ -76,33 +78,36 @@ __global__ void k_fk(const int32_t* __restrict__ parent, const double* __restric
     }
 }
 
-// Batched over poses: pose p = blockIdx.y reads B[p] and writes keys/vals + p * n.
+// Poses skinned by one workgroup (at most): the canonical leaf data (cell,
+// bones, weights) is read once and kept in registers for all of them.
+constexpr int kSkinPoses = 4;
+
+// Batched over poses: workgroup row blockIdx.y skins poses ppb blockIdx.y ..
+// + ppb - 1 (those below `batch`, ppb <= kSkinPoses); pose p reads B[p] and
+// writes keys/vals + p * n.
 template <typename R>
 __global__ __launch_bounds__(256) void k_skin(const uint16_t* __restrict__ ijk,
                                               const uint8_t* __restrict__ bone,
                                               const float* __restrict__ w,
                                               uint32_t n, int depth,
-                                              const R* __restrict__ Bpose, int J,
+                                              const R* __restrict__ Bpose, int J, int batch, int ppb,
                                               uint32_t* __restrict__ keys,
                                               uint32_t* __restrict__ vals,
                                               uint32_t* __restrict__ bmap, uint32_t bwords,
                                               PoseCounters* __restrict__ cnt) {
-    extern __shared__ __align__(16) unsigned char s_dyn[];   // J * 12 bone-matrix entries
+    extern __shared__ __align__(16) unsigned char s_dyn[];   // ppb * J * 12 bone-matrix entries
     R* sB = reinterpret_cast<R*>(s_dyn);
-    Bpose += (size_t)blockIdx.y * J * 12;
-    keys += (size_t)blockIdx.y * n;
-    if (vals) vals += (size_t)blockIdx.y * n;
-    if (bmap) {
-        bmap += (size_t)blockIdx.y * bwords;
-        cnt += blockIdx.y;
-    }
-    __shared__ LdsOrTable<256> tab;   // brick-bitmap words touched by this workgroup
-    for (int i = threadIdx.x; i < J * 12; i += blockDim.x) sB[i] = Bpose[i];
-    tab.init();
+    const int p0 = (int)blockIdx.y * ppb;
+    const int np = batch - p0 < ppb ? batch - p0 : ppb;
+    __shared__ LdsOrTable<256> tab[kSkinPoses];   // brick-bitmap words touched by this workgroup, per pose
+    for (int i = threadIdx.x; i < np * J * 12; i += blockDim.x) sB[i] = Bpose[(size_t)p0 * J * 12 + i];
+#pragma unroll
+    for (int pp = 0; pp < kSkinPoses; ++pp) tab[pp].init();
     __syncthreads();
     const R h = (R)1 / (R)(1 << depth);
     const R invh = (R)(1 << depth);
     const R G = (R)(2 << depth);
+    const int lane = lane_id();
     // Each workgroup skins a contiguous range of leaves (neighbouring canonical
     // leaves land in few posed bricks).  The lanes of a wave hold consecutive
     // leaves, so the lanes still in the loop are a prefix of the wave (lane - 1
@@ -115,52 +120,62 @@ __global__ __launch_bounds__(256) void k_skin(const uint16_t* __restrict__ ijk,
         const R x = (R)-0.5 + ((R)ijk[i] + (R)0.5) * h;
         const R y = (R)-0.5 + ((R)ijk[n + i] + (R)0.5) * h;
         const R z = (R)-0.5 + ((R)ijk[2 * (size_t)n + i] + (R)0.5) * h;
-        R A[12];
-#pragma unroll
-        for (int e = 0; e < 12; ++e) A[e] = (R)0;
+        int bk[4];
+        R wk[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const int b = bone[(size_t)k * n + i];
-            const R wk = (R)w[(size_t)k * n + i];
-            const R* Bb = sB + b * 12;
-#pragma unroll
-            for (int e = 0; e < 12; ++e) A[e] += wk * Bb[e];
+            bk[k] = bone[(size_t)k * n + i];
+            wk[k] = (R)w[(size_t)k * n + i];
         }
-        uint32_t c[3];
-        bool ok = true;
+        for (int pp = 0; pp < np; ++pp) {
+            const int p = p0 + pp;
+            const R* sBp = sB + (size_t)pp * J * 12;
+            R A[12];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const R p = A[4 * a] * x + A[4 * a + 1] * y + A[4 * a + 2] * z + A[4 * a + 3];
-            const R u = floor((p + (R)1) * invh);
-            ok = ok && (u >= (R)0) && (u < G);
-            c[a] = ok ? (uint32_t)u : 0u;
-        }
-        const uint32_t key = ok ? morton3(c[0], c[1], c[2]) : kInvalidKey;
-        keys[i] = key;
-        if (vals) vals[i] = i;
-        if (bmap) {
-            // mark the leaf's brick (key >> 9) in the occupancy bitmap: the bits
-            // of each run of lanes with the same bitmap word are OR-ed into the
-            // run's first lane, which merges them into the workgroup's table
-            const uint32_t wk = ok ? key >> 14 : kInvalidKey;
-            uint32_t bits = ok ? 1u << ((key >> 9) & 31u) : 0u;
-            const int lane = lane_id();
+            for (int e = 0; e < 12; ++e) A[e] = (R)0;
 #pragma unroll
-            for (int d = 1; d < kWave; d <<= 1) {
-                const uint32_t ob = __shfl_down(bits, d, kWave);
-                const uint32_t ow = __shfl_down(wk, d, kWave);
-                if (lane + d < kWave && i + (uint32_t)d < hi && ow == wk) bits |= ob;
+            for (int k = 0; k < 4; ++k) {
+                const R* Bb = sBp + bk[k] * 12;
+#pragma unroll
+                for (int e = 0; e < 12; ++e) A[e] += wk[k] * Bb[e];
             }
-            const uint32_t prev = __shfl_up(wk, 1, kWave);
-            if (ok && (lane == 0 || prev != wk) && !tab.insert(wk, bits)) atomicOr(&bmap[wk], bits);
-            const uint64_t drop = __ballot(!ok);
-            if (lane == 0 && drop) atomicAdd(&cnt->dropped, (uint32_t)__popcll(drop));
+            uint32_t c[3];
+            bool ok = true;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const R pa = A[4 * a] * x + A[4 * a + 1] * y + A[4 * a + 2] * z + A[4 * a + 3];
+                const R u = floor((pa + (R)1) * invh);
+                ok = ok && (u >= (R)0) && (u < G);
+                c[a] = ok ? (uint32_t)u : 0u;
+            }
+            const uint32_t key = ok ? morton3(c[0], c[1], c[2]) : kInvalidKey;
+            keys[(size_t)p * n + i] = key;
+            if (vals) vals[(size_t)p * n + i] = i;
+            if (bmap) {
+                // mark the leaf's brick (key >> 9) in the occupancy bitmap: the bits
+                // of each run of lanes with the same bitmap word are OR-ed into the
+                // run's first lane, which merges them into the workgroup's table
+                const uint32_t wkey = ok ? key >> 14 : kInvalidKey;
+                uint32_t bits = ok ? 1u << ((key >> 9) & 31u) : 0u;
+#pragma unroll
+                for (int d = 1; d < kWave; d <<= 1) {
+                    const uint32_t ob = __shfl_down(bits, d, kWave);
+                    const uint32_t ow = __shfl_down(wkey, d, kWave);
+                    if (lane + d < kWave && i + (uint32_t)d < hi && ow == wkey) bits |= ob;
+                }
+                const uint32_t prev = __shfl_up(wkey, 1, kWave);
+                if (ok && (lane == 0 || prev != wkey) && !tab[pp].insert(wkey, bits))
+                    atomicOr(&bmap[(size_t)p * bwords + wkey], bits);
+                const uint64_t drop = __ballot(!ok);
+                if (lane == 0 && drop) atomicAdd(&cnt[p].dropped, (uint32_t)__popcll(drop));
+            }
         }
     }
     if (bmap) {
         __syncthreads();
-        for (int e = threadIdx.x; e < 256; e += blockDim.x)
-            if (tab.key[e] != kInvalidKey) atomicOr(&bmap[tab.key[e]], tab.bits[e]);
+        for (int pp = 0; pp < np; ++pp)
+            for (int e = threadIdx.x; e < 256; e += blockDim.x)
+                if (tab[pp].key[e] != kInvalidKey) atomicOr(&bmap[(size_t)(p0 + pp) * bwords + tab[pp].key[e]], tab[pp].bits[e]);
     }
 }
 
@@ -179,12 +194,17 @@ hipError_t launch_skin(const uint16_t* ijk, const uint8_t* bone, const float* w,
     const int bs = 256;
     int grid = (int)((n + bs - 1) / bs);
     if (grid > 1024) grid = 1024;
+    // poses per workgroup: up to kSkinPoses, their bone matrices within 48 KB of LDS
+    const size_t per_pose = (size_t)J * 12 * (fp32 ? 4 : 8);
+    int ppb = (int)std::min<size_t>((size_t)kSkinPoses, std::max<size_t>(1, (size_t)49152 / per_pose));
+    ppb = std::min(ppb, std::max(batch, 1));
+    const unsigned gy = (unsigned)((batch + ppb - 1) / ppb);
     if (fp32)
-        hipLaunchKernelGGL(k_skin<float>, dim3(grid, batch), dim3(bs), (size_t)J * 12 * 4, st, ijk, bone, w, (uint32_t)n,
-                           depth, B32, J, keys, vals, bmap, bwords, cnt);
+        hipLaunchKernelGGL(k_skin<float>, dim3(grid, gy), dim3(bs), (size_t)ppb * per_pose, st, ijk, bone, w,
+                           (uint32_t)n, depth, B32, J, batch, ppb, keys, vals, bmap, bwords, cnt);
     else
-        hipLaunchKernelGGL(k_skin<double>, dim3(grid, batch), dim3(bs), (size_t)J * 12 * 8, st, ijk, bone, w, (uint32_t)n,
-                           depth, B64, J, keys, vals, bmap, bwords, cnt);
+        hipLaunchKernelGGL(k_skin<double>, dim3(grid, gy), dim3(bs), (size_t)ppb * per_pose, st, ijk, bone, w,
+                           (uint32_t)n, depth, B64, J, batch, ppb, keys, vals, bmap, bwords, cnt);
     return hipGetLastError();
 }
 
