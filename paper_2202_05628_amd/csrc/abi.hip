@@ -202,36 +202,35 @@ OctreeSlot octree_slot(art_ctx* ctx, const CallPlan& pl, int slot) {
 
 struct Timing {
     bool on = false;
-    std::vector<hipEvent_t> ev;
-    std::vector<int> stage;   // stage id of the interval ending at ev[i]
-    ~Timing() {
-        for (auto e : ev) (void)hipEventDestroy(e);
-    }
+    std::vector<hipEvent_t>* pool = nullptr;   // the context's events, created once and reused
+    size_t used = 0;
+    std::vector<int> stage;   // stage id of the interval ending at event i
     void record(hipStream_t st, int stage_id) {
-        if (!on) return;
-        hipEvent_t e;
-        if (hipEventCreate(&e) != hipSuccess) return;
-        (void)hipEventRecord(e, st);
-        ev.push_back(e);
+        if (!on || !pool) return;
+        if (used == pool->size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return;
+            pool->push_back(e);
+        }
+        (void)hipEventRecord((*pool)[used++], st);
         stage.push_back(stage_id);
     }
     void finish(art_ctx* ctx) {
         for (int i = 0; i < 7; ++i) ctx->timing_ms[i] = 0.0f;
         ctx->timing_nrender = 0;
-        for (size_t i = 1; i < ev.size(); ++i) {
+        for (size_t i = 1; i < used; ++i) {
             float ms = 0.0f;
-            if (hipEventElapsedTime(&ms, ev[i - 1], ev[i]) == hipSuccess && stage[i] >= 0) {
+            if (hipEventElapsedTime(&ms, (*pool)[i - 1], (*pool)[i]) == hipSuccess && stage[i] >= 0) {
                 ctx->timing_ms[stage[i]] += ms;
                 if (stage[i] == 4) ctx->timing_nrender++;
             }
         }
-        if (ev.size() >= 2) {
+        if (used >= 2) {
             float ms = 0.0f;
-            if (hipEventElapsedTime(&ms, ev.front(), ev.back()) == hipSuccess) ctx->timing_ms[5] = ms;
+            if (hipEventElapsedTime(&ms, (*pool)[0], (*pool)[used - 1]) == hipSuccess) ctx->timing_ms[5] = ms;
         }
         ctx->timing_valid = on;
-        for (auto e : ev) (void)hipEventDestroy(e);
-        ev.clear();
+        used = 0;
         stage.clear();
     }
 };
@@ -477,6 +476,7 @@ art_status render_call(art_ctx* ctx, int C, art_dtype dtype, const void* sigma, 
     int launches = 0;
     Timing tm;
     tm.on = (flags & ART_TIMING) != 0;
+    tm.pool = &ctx->ev_pool;
 
     ART_TRY_HIP(launch_fill_u32(ctx->s.stats.as<uint32_t>(), 0u, 32, st), "fill");
     tm.record(st, -1);
@@ -485,6 +485,7 @@ art_status render_call(art_ctx* ctx, int C, art_dtype dtype, const void* sigma, 
                 "fk");
     launches += 2;
     tm.record(st, 0);
+    unsigned long long hst[16] = {0};
     for (int p0 = pose_lo; p0 < pose_hi; p0 += slots) {
         const int p1 = std::min(pose_hi, p0 + slots);
         const size_t items = (size_t)(p1 - p0) * pl.ngroups;
@@ -495,6 +496,9 @@ art_status render_call(art_ctx* ctx, int C, art_dtype dtype, const void* sigma, 
         for (int attempt = 0; attempt < 3; ++attempt) {
             std::vector<uint32_t> hov(items * 2);
             ART_TRY_HIP(hipMemcpyAsync(hov.data(), ctx->s.ovf.p, items * 2 * 4, hipMemcpyDeviceToHost, st), "copy");
+            // the run statistics come back with the same synchronisation (the
+            // copy after the last batch's last attempt is the call's total)
+            ART_TRY_HIP(hipMemcpyAsync(hst, ctx->s.stats.p, sizeof(hst), hipMemcpyDeviceToHost, st), "copy");
             ART_TRY_HIP(hipStreamSynchronize(st), "render");
             std::vector<char> redo(items, 0);
             size_t need = 0;
@@ -515,9 +519,6 @@ art_status render_call(art_ctx* ctx, int C, art_dtype dtype, const void* sigma, 
             if (rc != ART_OK) return rc;
         }
     }
-    unsigned long long hst[16];
-    ART_TRY_HIP(hipMemcpyAsync(hst, ctx->s.stats.p, sizeof(hst), hipMemcpyDeviceToHost, st), "copy");
-    ART_TRY_HIP(hipStreamSynchronize(st), "render");
     for (int i = 0; i < 7; ++i) ctx->stats[i] = (int64_t)hst[i];
     ctx->stats[7] = launches;
     ctx->stats[8] = (int64_t)hst[7];
@@ -672,6 +673,7 @@ void art_destroy(art_ctx* ctx) {
         DeviceGuard g(ctx->device);
         if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
         else (void)hipDeviceSynchronize();
+        for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
         DevBuf* bufs[] = {&ctx->ijk, &ctx->bone, &ctx->weight, &ctx->dom_bone, &ctx->shade_w, &ctx->shade_b,
                           &ctx->shade_head, &ctx->shade_act, &ctx->parent, &ctx->rest, &ctx->pose,
                           &ctx->cam, &ctx->B64, &ctx->B32, &ctx->Gtmp,

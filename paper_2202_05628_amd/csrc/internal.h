@@ -167,6 +167,9 @@ struct art_ctx {
     int64_t poses_version = 0;     // bumped by art_set_poses
     int64_t code_version = -1;     // poses_version the pose codes were computed for
 
+    // timing events of the stages, reused by every call that asks for timings
+    std::vector<hipEvent_t> ev_pool;
+
     // last-call bookkeeping
     int64_t stats[art::kNumStats] = {0};
     float timing_ms[7] = {0};
