@@ -277,20 +277,36 @@ hipError_t launch_conv3x3(const ConvLaunch& a, hipStream_t st) {
     return hipGetLastError();
 }
 
-// Planar FP32 feature maps [N][C][H][W] -> NHWC FP16 with Cp >= C channels (zero padded).
-__global__ __launch_bounds__(256) void k_to_nhwc(const float* __restrict__ F, int N, int C, int H, int W, int Cp,
+// Planar FP32 feature maps [N][C][H][W] -> NHWC FP16 with 32 channels (C <= 32,
+// zero padded).  A workgroup converts 256 consecutive pixels of one image
+// through LDS: each channel plane is read with one coalesced 1 KB row per
+// wave, and the 64-byte pixel rows are written as contiguous 4 KB blocks.
+constexpr int kNhwcPix = 256;
+constexpr int kNhwcPitch = 40;   // halves per staged pixel (32 channels + 8: 16-byte aligned rows)
+__global__ __launch_bounds__(256) void k_to_nhwc(const float* __restrict__ F, int C, int HW, int blocks_per_image,
                                                  _Float16* __restrict__ out) {
-    const size_t HW = (size_t)H * W;
-    const size_t total = (size_t)N * HW;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
-        const size_t n = i / HW, pix = i % HW;
-        _Float16* o = out + i * Cp;
-        for (int c = 0; c < Cp; c += 8) {
-            half8 h;
+    __shared__ __align__(16) _Float16 s[kNhwcPix * kNhwcPitch];
+    const int n = blockIdx.x / blocks_per_image;
+    const int p0 = (blockIdx.x % blocks_per_image) * kNhwcPix;
+    const int t = threadIdx.x;
+    const int pix = p0 + t;
+    const float* f = F + (size_t)n * C * HW;
+#pragma unroll 4
+    for (int c = 0; c < 32; c += 2) {
+        const float a = (pix < HW && c < C) ? f[(size_t)c * HW + pix] : 0.0f;
+        const float b = (pix < HW && c + 1 < C) ? f[(size_t)(c + 1) * HW + pix] : 0.0f;
+        s[t * kNhwcPitch + c] = (_Float16)a;
+        s[t * kNhwcPitch + c + 1] = (_Float16)b;
+    }
+    __syncthreads();
+    _Float16* o = out + ((size_t)n * HW + p0) * 32;
 #pragma unroll
-            for (int e = 0; e < 8; ++e) h[e] = (_Float16)(c + e < C ? F[(n * C + c + e) * HW + pix] : 0.0f);
-            *reinterpret_cast<half8*>(o + c) = h;
-        }
+    for (int r = 0; r < kNhwcPix * 4 / 256; ++r) {
+        const int v = r * 256 + t;               // 16-byte chunk v % 4 of pixel v / 4
+        const int px = v >> 2, q = v & 3;
+        if (p0 + px < HW)
+            *reinterpret_cast<half8*>(o + (size_t)px * 32 + 8 * q) =
+                *reinterpret_cast<const half8*>(s + px * kNhwcPitch + 8 * q);
     }
 }
 
@@ -356,7 +372,10 @@ static unsigned grid_for(size_t total) {
 }
 
 hipError_t launch_to_nhwc(const float* F, int N, int C, int H, int W, int Cp, uint16_t* out, hipStream_t st) {
-    hipLaunchKernelGGL(k_to_nhwc, dim3(grid_for((size_t)N * H * W)), dim3(256), 0, st, F, N, C, H, W, Cp,
+    if (Cp != 32 || C < 1 || C > 32) return hipErrorInvalidValue;
+    const int HW = H * W;
+    const int bpi = (HW + kNhwcPix - 1) / kNhwcPix;
+    hipLaunchKernelGGL(k_to_nhwc, dim3((unsigned)(N * bpi)), dim3(256), 0, st, F, C, HW, bpi,
                        reinterpret_cast<_Float16*>(out));
     return hipGetLastError();
 }
