@@ -201,3 +201,42 @@ def test_training_lowers_the_loss_and_guides_the_traversal(net):
     log(f"  held-out |u_near error| on hit rays: trained {mae_t:.4f}, untrained {mae_u:.4f}; "
         f"steps saved {steps0 - st['steps']} of {steps0}")
     assert mae_t < 0.5 * mae_u
+
+
+@pytest.mark.parametrize("H,W", [(64, 64), (40, 52)])
+def test_render_inference_matches_network_forward(net, H, W):
+    """The guided render evaluates the network itself for the rays of every
+    non-empty tile; handing it the outputs of art_proposal_forward for the
+    same rays (inputs from art_proposal_gather) must give the same maps bit for
+    bit.  This pins the pixel of each inference lane (tile, 16-ray group,
+    shuffle of the ray inputs), also for ragged tiles (W = 52)."""
+    import torch
+    from gpu_common import flut
+    s = net["s"]
+    poses = net["poses"]
+    K, c2w = sg.make_cameras(s, 2, H, W)
+    rend = make_renderer(s, poses, K, c2w, H, W)
+    theta = sg.make_mlp_init(s.J)
+    theta[-2:] = [-0.85, 0.85]   # output biases: intervals around [0.3, 0.7] of each span, varying per ray
+    rend.set_proposal_weights(theta)
+    sig, f = flut(s)
+    P, V = len(poses[0]), 2
+    lab = rend.proposal_labels(sig, f, 0.01)
+    ids = torch.arange(P * V * H * W, dtype=torch.int64, device="cuda")
+    od, pose, _ = rend.proposal_gather(ids, lab)
+    iv = rend.proposal_forward(od, pose).reshape(P, V, H, W, 2)
+    kw = dict(margin_h=2.0, f2_tau=-1.0)
+    Fa, Aa, Ta = rend.render_proposal(sig, f, None, 0.01, **kw)
+    st_a = rend.stats()
+    Fb, Ab, Tb = rend.render_proposal(sig, f, iv, 0.01, **kw)
+    st_b = rend.stats()
+    log(f"inference in the render vs network forward {H}x{W}: proposal rays {st_a['proposal_rays']}, "
+        f"fallbacks {st_a['fallbacks']} / {st_b['fallbacks']}")
+    assert st_a["proposal_rays"] > 0
+    assert torch.equal(Fa, Fb) and torch.equal(Aa, Ab) and torch.equal(Ta, Tb)
+    assert st_a["proposal_rays"] == st_b["proposal_rays"] and st_a["fallbacks"] == st_b["fallbacks"]
+    assert st_a["rounds"] == st_b["rounds"]
+    # control: the intervals of the neighbouring pixel change the maps, so the
+    # comparison above does see which pixel an interval belongs to
+    Fc, _, _ = rend.render_proposal(sig, f, torch.roll(iv, 1, dims=3).contiguous(), 0.01, **kw)
+    assert not torch.equal(Fa, Fc)
