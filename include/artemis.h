@@ -63,6 +63,13 @@ typedef enum { ART_F32 = 0, ART_BF16 = 1 } art_dtype;
                               default: FP64 skinning arithmetic and ray t      */
 #define ART_TIMING 2u      /* record per-stage HIP events, read by art_get_timing */
 #define ART_PROPOSAL_NEAR_ONLY 4u  /* art_render_proposal: use only u_near, traverse to t_b */
+#define ART_REUSE_BUILD 8u /* art_backward, art_vrt: reuse the posed octrees (and tile
+                              lists) the last art_render call on this context left,
+                              when that call covered every pose in one batch and
+                              nothing they depend on (octree, skin, skeleton, poses,
+                              cameras, ART_GEOM_FP32) changed since, and no other
+                              call rebuilt them; otherwise they are rebuilt, as
+                              without the flag.  The FLUT does not enter them.     */
 
 /* Library version (major * 10000 + minor * 100 + patch). */
 int art_version(void);

@@ -313,9 +313,12 @@ class Renderer:
         return log[:steps]
 
     def backward(self, sigma, feat, F, T, dF, dA=None, lambda_th: float = LAMBDA_TH,
-                 fp32_geom: bool = False, timing: bool = False, d_sigma=None, d_feat=None):
+                 fp32_geom: bool = False, timing: bool = False, d_sigma=None, d_feat=None,
+                 reuse_build: bool = False):
         """Accumulate dL/dsigma [n] and dL/dfeat [n][C] (float32) for the last
-        render's inputs; returns (d_sigma, d_feat)."""
+        render's inputs; returns (d_sigma, d_feat).  reuse_build: use the posed
+        octrees and tile lists the last render left when still valid
+        (ART_REUSE_BUILD)."""
         torch = self._torch
         C, dtype = self._flut(sigma, feat)
         if d_sigma is None:
@@ -324,8 +327,9 @@ class Renderer:
             d_feat = torch.zeros((self.n, C), dtype=torch.float32, device=sigma.device)
         dF = dF.contiguous().float()
         dA = None if dA is None else dA.contiguous().float()
+        flags = self._flags(fp32_geom, timing) | (_lib.ART_REUSE_BUILD if reuse_build else 0)
         self._check(self.lib.art_backward(self._h, C, dtype, _tptr(sigma), _tptr(feat), float(lambda_th),
-                                          self._flags(fp32_geom, timing), _tptr(F), _tptr(T), _tptr(dF),
+                                          flags, _tptr(F), _tptr(T), _tptr(dF),
                                           _tptr(dA), _tptr(d_sigma), _tptr(d_feat)),
                     "art_backward")
         return d_sigma, d_feat
@@ -352,9 +356,11 @@ class Renderer:
         return out
 
     # ---- training step ----------------------------------------------------------------
-    def vrt(self, feat, lambda_vrt: float, d_feat=None, fp32_geom: bool = False):
+    def vrt(self, feat, lambda_vrt: float, d_feat=None, fp32_geom: bool = False, reuse_build: bool = False):
         """Voxel regularisation term (Eq. 10) summed over the poses; its gradient
-        is added into d_feat [n][C] (float32).  Returns (loss, d_feat)."""
+        is added into d_feat [n][C] (float32).  Returns (loss, d_feat).
+        reuse_build: use the posed octrees the last render left when still
+        valid (ART_REUSE_BUILD)."""
         torch = self._torch
         if feat.dtype not in (torch.float32, torch.bfloat16) or not feat.is_cuda or not feat.is_contiguous():
             raise TypeError("feat must be a contiguous float32 or bfloat16 device tensor")
@@ -365,8 +371,9 @@ class Renderer:
         if d_feat is None:
             d_feat = torch.zeros((self.n, C), dtype=torch.float32, device=feat.device)
         loss = ctypes.c_double(0.0)
+        flags = (ART_GEOM_FP32 if fp32_geom else 0) | (_lib.ART_REUSE_BUILD if reuse_build else 0)
         self._check(self.lib.art_vrt(self._h, C, dtype, _tptr(feat), float(lambda_vrt),
-                                     ART_GEOM_FP32 if fp32_geom else 0, _tptr(d_feat), ctypes.byref(loss)),
+                                     flags, _tptr(d_feat), ctypes.byref(loss)),
                     "art_vrt")
         return float(loss.value), d_feat
 
@@ -414,10 +421,12 @@ class Renderer:
         if A_target is not None:
             dA = (A - A_target) / R
             l_map += 0.5 * float((dA * (A - A_target)).sum())
-        d_sigma, d_feat = self.backward(sigma, feat, F, T, dF, dA, lambda_th, fp32_geom=fp32_geom)
+        # the adjoint and the VRT read the posed octrees (and tile lists) the
+        # render just built: the poses and the octree did not change
+        d_sigma, d_feat = self.backward(sigma, feat, F, T, dF, dA, lambda_th, fp32_geom=fp32_geom, reuse_build=True)
         l_vrt = 0.0
         if lambda_vrt > 0.0:
-            l_vrt, _ = self.vrt(feat, lambda_vrt, d_feat=d_feat, fp32_geom=fp32_geom)
+            l_vrt, _ = self.vrt(feat, lambda_vrt, d_feat=d_feat, fp32_geom=fp32_geom, reuse_build=True)
         state["step"] += 1
         self.flut_adam(sigma, d_sigma, state["m_s"], state["v_s"], state["step"], lr, lower=0.0)
         self.flut_adam(feat, d_feat, state["m_f"], state["v_f"], state["step"], lr)
@@ -510,8 +519,9 @@ def _make_fn():
             sigma, feat, F, T = ctx.saved_tensors
             if dF is None:
                 dF = torch.zeros_like(F)
+            # the octrees of the forward are reused when nothing they depend on changed since
             ds, df = ctx.renderer.backward(sigma.detach(), feat.detach(), F, T, dF, dA,
-                                           ctx.lambda_th, ctx.fp32_geom)
+                                           ctx.lambda_th, ctx.fp32_geom, reuse_build=True)
             return ds.to(sigma.dtype), df.to(feat.dtype), None, None, None
 
     return RenderFn

@@ -18,6 +18,7 @@ ART_GEOM_FP32 = 1
 ART_TIMING = 2
 ART_PROPOSAL_MARGIN_H = 2.0
 ART_PROPOSAL_NEAR_ONLY = 4
+ART_REUSE_BUILD = 8
 
 STATUS_NAMES = {0: "ART_OK", -1: "ART_EINVAL", -2: "ART_ENOMEM", -3: "ART_EDEVICE",
                 -4: "ART_ESTATE", -5: "ART_EUNSUPPORTED"}

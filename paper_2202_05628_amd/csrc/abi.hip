@@ -265,6 +265,7 @@ struct PassOut {
     double* hit_delta = nullptr;
     int32_t* hit_count = nullptr;
     bool single_pose = false;   // maps hold one pose only
+    bool reuse = false;         // ART_REUSE_BUILD was asked for
 };
 
 // Skinning + octree build of poses [p0, p0 + batch) into slots 0..batch-1.
@@ -274,6 +275,7 @@ art_status build_batch(art_ctx* ctx, const CallPlan& pl, int p0, int batch, cons
     hipStream_t st = ctx->stream;
     PoseCounters* cnt = s.counters.as<PoseCounters>();
     const size_t n = (size_t)ctx->n;
+    ctx->memo.valid = false;   // the slots are overwritten
     tm.record(st, -1);
     ART_TRY_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(cnt), 0u, (size_t)batch * sizeof(PoseCounters) / 4, st),
                 "fill");
@@ -296,16 +298,13 @@ art_status build_batch(art_ctx* ctx, const CallPlan& pl, int p0, int batch, cons
     return ART_OK;
 }
 
-// One batch of poses [p0, p1): build every pose into its slot, bin its view
-// groups, then render all (pose, view) maps of the batch in one launch.
-// `redo` (indexed by slot * ngroups + group) restricts the render to the
+// Build every pose of the batch [p0, p0 + Pb) into its slot and bin its view
+// groups into tile lists.  `redo` (indexed by slot * ngroups + group) marks the
 // (pose, group) items whose tile lists overflowed in an earlier attempt.
-art_status run_batch(art_ctx* ctx, const CallPlan& pl, int mode, float lambda, const void* sigma,
-                     const void* feat, const PassOut& o, int p0, int p1,
-                     const std::vector<char>* redo, int* launches, Timing& tm) {
+art_status build_and_bin(art_ctx* ctx, const CallPlan& pl, int p0, int Pb, const void* sigma, const void* feat,
+                         const std::vector<char>* redo, int* launches, Timing& tm) {
     Scratch& s = ctx->s;
     hipStream_t st = ctx->stream;
-    const int Pb = p1 - p0;
     const size_t TPV = (size_t)((ctx->W + 7) / 8) * ((ctx->H + 7) / 8);
     art_status rc = build_batch(ctx, pl, p0, Pb, sigma, feat, launches, tm);
     if (rc != ART_OK) return rc;
@@ -330,6 +329,24 @@ art_status run_batch(art_ctx* ctx, const CallPlan& pl, int mode, float lambda, c
         hipLaunchKernelGGL(k_pairs, dim3((Pb + 63) / 64), dim3(64), 0, st, (const PoseCounters*)s.counters.as<PoseCounters>(),
                            s.stats.as<unsigned long long>(), s.ovf.as<uint32_t>(), pl.ngroups, gi, redo_dev, Pb);
         *launches += 1;
+    }
+    return ART_OK;
+}
+
+// One batch of poses [p0, p1): build every pose into its slot, bin its view
+// groups (both skipped when `reuse`: the slots already hold this batch's
+// octrees and tile lists), then render all (pose, view) maps of the batch in
+// one launch.  `redo` restricts the render to the items that overflowed.
+art_status run_batch(art_ctx* ctx, const CallPlan& pl, int mode, float lambda, const void* sigma,
+                     const void* feat, const PassOut& o, int p0, int p1,
+                     const std::vector<char>* redo, int* launches, Timing& tm, bool reuse = false) {
+    Scratch& s = ctx->s;
+    hipStream_t st = ctx->stream;
+    const int Pb = p1 - p0;
+    const size_t TPV = (size_t)((ctx->W + 7) / 8) * ((ctx->H + 7) / 8);
+    if (!reuse) {
+        art_status rc = build_and_bin(ctx, pl, p0, Pb, sigma, feat, redo, launches, tm);
+        if (rc != ART_OK) return rc;
     }
     tm.record(st, 3);
     tm.record(st, -1);
@@ -453,6 +470,33 @@ art_status mlp_prepare(art_ctx* ctx) {
     return ART_OK;
 }
 
+// Whether the scratch slots still hold the posed octrees and tile lists of a
+// whole-batch call that a call with plan `pl` can use unchanged.
+bool memo_matches(const art_ctx* ctx, const CallPlan& pl) {
+    const art_ctx::BuildMemo& m = ctx->memo;
+    return m.valid && m.version == ctx->state_version && m.fp32 == pl.fp32 && m.P == ctx->P && m.Vg == pl.Vg &&
+           m.ngroups == pl.ngroups && m.H == ctx->H && m.W == ctx->W && m.pair_cap == ctx->s.pair_cap &&
+           m.occ == ctx->s.occ_win.p && m.lists == ctx->s.pair_v.p && m.rows == ctx->s.keys1.p &&
+           m.tiles == ctx->s.tile_start.p && m.counters == ctx->s.counters.p;
+}
+void take_memo(art_ctx* ctx, const CallPlan& pl) {
+    art_ctx::BuildMemo& m = ctx->memo;
+    m.valid = true;
+    m.version = ctx->state_version;
+    m.fp32 = pl.fp32;
+    m.P = ctx->P;
+    m.Vg = pl.Vg;
+    m.ngroups = pl.ngroups;
+    m.H = ctx->H;
+    m.W = ctx->W;
+    m.pair_cap = ctx->s.pair_cap;
+    m.occ = ctx->s.occ_win.p;
+    m.lists = ctx->s.pair_v.p;
+    m.rows = ctx->s.keys1.p;
+    m.tiles = ctx->s.tile_start.p;
+    m.counters = ctx->s.counters.p;
+}
+
 art_status render_call(art_ctx* ctx, int C, art_dtype dtype, const void* sigma, const void* feat,
                        float lambda, unsigned flags, int mode, const PassOut& o, int pose_lo,
                        int pose_hi) {
@@ -477,19 +521,24 @@ art_status render_call(art_ctx* ctx, int C, art_dtype dtype, const void* sigma, 
     Timing tm;
     tm.on = (flags & ART_TIMING) != 0;
     tm.pool = &ctx->ev_pool;
+    const bool whole = pose_lo == 0 && pose_hi == ctx->P && slots >= P;   // one batch, every pose
+    const bool reuse = o.reuse && whole && memo_matches(ctx, pl);
 
     ART_TRY_HIP(launch_fill_u32(ctx->s.stats.as<uint32_t>(), 0u, 32, st), "fill");
     tm.record(st, -1);
-    ART_TRY_HIP(launch_fk(ctx->parent.as<int32_t>(), ctx->rest.as<double>(), ctx->pose.as<double>(), ctx->J,
-                          ctx->P, ctx->Gtmp.as<double>(), ctx->B64.as<double>(), ctx->B32.as<float>(), st),
-                "fk");
-    launches += 2;
+    if (!reuse) {
+        ART_TRY_HIP(launch_fk(ctx->parent.as<int32_t>(), ctx->rest.as<double>(), ctx->pose.as<double>(), ctx->J,
+                              ctx->P, ctx->Gtmp.as<double>(), ctx->B64.as<double>(), ctx->B32.as<float>(), st),
+                    "fk");
+        launches += 1;
+    }
+    launches += 1;
     tm.record(st, 0);
     unsigned long long hst[16] = {0};
     for (int p0 = pose_lo; p0 < pose_hi; p0 += slots) {
         const int p1 = std::min(pose_hi, p0 + slots);
         const size_t items = (size_t)(p1 - p0) * pl.ngroups;
-        rc = run_batch(ctx, pl, mode, lambda, sigma, feat, o, p0, p1, nullptr, &launches, tm);
+        rc = run_batch(ctx, pl, mode, lambda, sigma, feat, o, p0, p1, nullptr, &launches, tm, reuse);
         if (rc != ART_OK) return rc;
         // a (pose, view group) whose tile lists overflowed was skipped by the
         // render kernel: grow the list buffers and run those items again
@@ -528,6 +577,7 @@ art_status render_call(art_ctx* ctx, int C, art_dtype dtype, const void* sigma, 
     ctx->stats[12] = (int64_t)hst[11];
     ctx->stats[13] = (int64_t)hst[12];
     tm.finish(ctx);
+    if (whole) take_memo(ctx, pl);   // the slots hold every pose's octree and tile lists
     return ART_OK;
 }
 
@@ -694,6 +744,7 @@ const char* art_last_error(const art_ctx* ctx) { return ctx ? ctx->err.c_str() :
 
 art_status art_load_octree(art_ctx* ctx, int depth, int64_t n, const uint16_t* ijk) {
     if (!ctx) return ART_EINVAL;
+    ctx->state_version++;   // posed octrees and tile lists of earlier calls no longer apply
     if (depth < 1 || depth > 9) return fail(ctx, ART_EINVAL, "depth must be in 1..9");
     if (n < 1 || n > ((int64_t)1 << (3 * depth)) || n > 0x7FFFFFFFLL)
         return fail(ctx, ART_EINVAL, "leaf count out of range");
@@ -730,6 +781,7 @@ art_status art_load_octree(art_ctx* ctx, int depth, int64_t n, const uint16_t* i
 
 art_status art_set_skin(art_ctx* ctx, const uint8_t* bone, const float* weight) {
     if (!ctx) return ART_EINVAL;
+    ctx->state_version++;   // posed octrees and tile lists of earlier calls no longer apply
     if (ctx->n <= 0) return fail(ctx, ART_ESTATE, "no octree loaded (art_load_octree)");
     if (!bone || !weight) return fail(ctx, ART_EINVAL, "bone / weight is NULL");
     const size_t n = (size_t)ctx->n;
@@ -780,6 +832,7 @@ art_status art_set_skin(art_ctx* ctx, const uint8_t* bone, const float* weight) 
 
 art_status art_set_skeleton(art_ctx* ctx, int J, const int32_t* parent, const double* rest_joint) {
     if (!ctx) return ART_EINVAL;
+    ctx->state_version++;   // posed octrees and tile lists of earlier calls no longer apply
     if (J < 1 || J > 255) return fail(ctx, ART_EINVAL, "J must be in 1..255");
     if (!parent || !rest_joint) return fail(ctx, ART_EINVAL, "parent / rest_joint is NULL");
     if (parent[0] != -1) return fail(ctx, ART_EINVAL, "parent[0] must be -1");
@@ -812,6 +865,7 @@ art_status art_set_skeleton(art_ctx* ctx, int J, const int32_t* parent, const do
 
 art_status art_set_poses(art_ctx* ctx, int P, const double* r, const double* R, const double* T) {
     if (!ctx) return ART_EINVAL;
+    ctx->state_version++;   // posed octrees and tile lists of earlier calls no longer apply
     if (ctx->J <= 0) return fail(ctx, ART_ESTATE, "no skeleton (art_set_skeleton)");
     if (P < 1 || P > 4096) return fail(ctx, ART_EINVAL, "P must be in 1..4096");
     if (!r || !R || !T) return fail(ctx, ART_EINVAL, "r / R / T is NULL");
@@ -842,6 +896,7 @@ art_status art_set_poses(art_ctx* ctx, int P, const double* r, const double* R, 
 
 art_status art_set_cameras(art_ctx* ctx, int V, int H, int W, const double* K, const double* c2w) {
     if (!ctx) return ART_EINVAL;
+    ctx->state_version++;   // posed octrees and tile lists of earlier calls no longer apply
     if (V < 1 || V > 4096) return fail(ctx, ART_EINVAL, "V must be in 1..4096");
     if (H < 1 || H > 8192 || W < 1 || W > 8192) return fail(ctx, ART_EINVAL, "H, W must be in 1..8192");
     if (!K || !c2w) return fail(ctx, ART_EINVAL, "K / c2w is NULL");
@@ -916,7 +971,8 @@ art_status art_backward(art_ctx* ctx, int C, art_dtype dtype, const void* sigma,
     o.d_alpha = d_alpha;
     o.d_sigma = d_sigma;
     o.d_leaf_feat = d_leaf_feat;
-    return render_call(ctx, C, dtype, sigma, feat, lambda_th, flags, 1, o, 0, ctx->P);
+    o.reuse = (flags & ART_REUSE_BUILD) != 0;
+    return render_call(ctx, C, dtype, sigma, feat, lambda_th, flags & ~ART_REUSE_BUILD, 1, o, 0, ctx->P);
 }
 
 art_status art_render_depth(art_ctx* ctx, int C, art_dtype dtype, const void* sigma, const void* feat,
@@ -1083,7 +1139,7 @@ art_status art_vrt(art_ctx* ctx, int C, art_dtype dtype, const void* feat, float
     if (!(lambda_vrt >= 0.0f && lambda_vrt < 1e30f)) return fail(ctx, ART_EINVAL, "lambda_vrt must be finite and >= 0");
     if (!supported_C(C)) return fail(ctx, ART_EUNSUPPORTED, "C must be 4, 8, 16 or 32");
     if (dtype != ART_F32 && dtype != ART_BF16) return fail(ctx, ART_EINVAL, "dtype must be ART_F32 or ART_BF16");
-    if (flags & ~ART_GEOM_FP32) return fail(ctx, ART_EINVAL, "unknown flag bits");
+    if (flags & ~(ART_GEOM_FP32 | ART_REUSE_BUILD)) return fail(ctx, ART_EINVAL, "unknown flag bits");
     art_status rc = check_build_state(ctx);
     if (rc != ART_OK) return rc;
     DeviceGuard g(ctx->device);
@@ -1104,6 +1160,14 @@ art_status art_vrt(art_ctx* ctx, int C, art_dtype dtype, const void* feat, float
     Timing tm;
     ART_TRY_HIP(launch_fill_u32(s.stats.as<uint32_t>(), 0u, 32, st), "fill");
     ART_TRY_HIP(launch_fill_u32(s.loss.as<uint32_t>(), 0u, 2, st), "fill");
+    // the octrees of a whole-batch render (any view grouping: only the octrees are read)
+    const art_ctx::BuildMemo& m = ctx->memo;
+    if ((flags & ART_REUSE_BUILD) && m.valid && m.version == ctx->state_version && m.fp32 == pl.fp32 &&
+        m.P == ctx->P && m.occ == s.occ_win.p && m.rows == s.keys1.p && m.counters == s.counters.p) {
+        ART_TRY_HIP(launch_vrt(s.keys1.as<uint32_t>(), s.occ_win.as<uint32_t>(), (uint32_t)ctx->n, C, pl.storage, feat,
+                               s.counters.as<PoseCounters>(), lambda_vrt, ctx->P, d_feat, s.loss.as<double>(), st),
+                    "vrt");
+    } else {
     ART_TRY_HIP(launch_fk(ctx->parent.as<int32_t>(), ctx->rest.as<double>(), ctx->pose.as<double>(), ctx->J,
                           ctx->P, ctx->Gtmp.as<double>(), ctx->B64.as<double>(), ctx->B32.as<float>(), st),
                 "fk");
@@ -1114,6 +1178,7 @@ art_status art_vrt(art_ctx* ctx, int C, art_dtype dtype, const void* feat, float
         ART_TRY_HIP(launch_vrt(s.keys1.as<uint32_t>(), s.occ_win.as<uint32_t>(), (uint32_t)ctx->n, C, pl.storage,
                                feat, s.counters.as<PoseCounters>(), lambda_vrt, batch, d_feat, s.loss.as<double>(), st),
                     "vrt");
+    }
     }
     double h = 0.0;
     ART_TRY_HIP(hipMemcpyAsync(&h, s.loss.p, 8, hipMemcpyDeviceToHost, st), "copy");

@@ -170,6 +170,25 @@ struct art_ctx {
     // timing events of the stages, reused by every call that asks for timings
     std::vector<hipEvent_t> ev_pool;
 
+    // The posed octrees and tile lists a render call leaves in the scratch
+    // slots, for an adjoint or VRT call that asks to reuse them (they depend
+    // only on the octree, skin, skeleton, poses, cameras and the geometry
+    // precision, not on the FLUT).  Every setter bumps state_version; every
+    // build clears `valid`; a reallocated scratch buffer changes its pointers.
+    uint64_t state_version = 0;
+    struct BuildMemo {
+        bool valid = false;
+        uint64_t version = 0;
+        bool fp32 = false;
+        int P = 0, Vg = 0, ngroups = 0, H = 0, W = 0;
+        size_t pair_cap = 0;
+        const void* occ = nullptr;     // s.occ_win.p when the memo was taken
+        const void* lists = nullptr;   // s.pair_v.p
+        const void* rows = nullptr;    // s.keys1.p
+        const void* tiles = nullptr;   // s.tile_start.p
+        const void* counters = nullptr;   // s.counters.p
+    } memo;
+
     // last-call bookkeeping
     int64_t stats[art::kNumStats] = {0};
     float timing_ms[7] = {0};
