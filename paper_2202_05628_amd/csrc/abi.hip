@@ -114,7 +114,11 @@ art_status plan_call(art_ctx* ctx, int C, art_dtype dtype, unsigned flags, CallP
 }
 
 art_status ensure_bufs(art_ctx* ctx, std::initializer_list<std::pair<DevBuf*, size_t>> req) {
-    for (auto& r : req) ART_TRY_HIP(r.first->ensure(r.second), "device allocation");
+    for (auto& r : req) {
+        const size_t cap = r.first->cap;
+        ART_TRY_HIP(r.first->ensure(r.second), "device allocation");
+        if (r.first->cap != cap) ctx->memo.valid = false;   // a reallocated buffer lost its contents
+    }
     return ART_OK;
 }
 
