@@ -174,6 +174,8 @@ art_status art_render(art_ctx* ctx, int C, art_dtype dtype, const void* sigma, c
  * d_leaf_feat: device float32 [n][C], accumulated (+=) with dL/df.
  * Gradients reach only collision winners; dropped and hidden leaves get 0.
  * Float atomics make the summation order, and so the last bits, vary.
+ * flags: as art_render, plus ART_REUSE_BUILD (skip the octree rebuild when the
+ * last art_render's octrees still apply).
  * Errors: as art_render.
  */
 art_status art_backward(art_ctx* ctx, int C, art_dtype dtype, const void* sigma, const void* feat,
@@ -300,9 +302,11 @@ art_status art_shading_forward(art_ctx* ctx, int C, int N, int H, int W, const f
  * d_feat: device float32 [n][C]; the gradient is ADDED (sign(Q - f_i) *
  * lambda / N_v to the winner's row, its negative to leaf i's), so the buffer
  * can also hold art_backward's gradient.  *loss (host) receives the loss.
- * Errors: ART_EINVAL (NULL pointer, negative or non-finite lambda_vrt, flags
- * other than ART_GEOM_FP32), ART_EUNSUPPORTED (C), ART_ESTATE (missing octree,
- * skin, skeleton or poses).
+ * flags: ART_GEOM_FP32, ART_REUSE_BUILD (use the octrees the last whole-batch
+ * render left when they still apply), or 0.
+ * Errors: ART_EINVAL (NULL pointer, negative or non-finite lambda_vrt, other
+ * flag bits), ART_EUNSUPPORTED (C), ART_ESTATE (missing octree, skin,
+ * skeleton or poses).
  */
 art_status art_vrt(art_ctx* ctx, int C, art_dtype dtype, const void* feat, float lambda_vrt, unsigned flags,
                    float* d_feat, double* loss);
