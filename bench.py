@@ -296,6 +296,10 @@ def adjoint_leg(args, art, sg, torch):
     t = _timed(torch, lambda: r.backward(sig, feat, F, T, dF, d_sigma=ds, d_feat=df), args.proposal_steps)
     r.backward(sig, feat, F, T, dF, d_sigma=ds, d_feat=df, timing=True)
     tm = r.timing()
+    # as the autograd backward runs it: the forward's posed octrees reused
+    r.render(sig, feat, args.lambda_th, out=(F, A, T))
+    t_reuse = _timed(torch, lambda: r.backward(sig, feat, F, T, dF, d_sigma=ds, d_feat=df, reuse_build=True),
+                     args.proposal_steps)
     rays = P * V * H * W
     # per composited sample: the re-gathered density, features and leaf index
     # (72 B) and the gradient atomics (C + 1 floats); per ray of a non-empty
@@ -306,6 +310,7 @@ def adjoint_leg(args, art, sg, torch):
     kern_ms = tm["render"] / max(tm["n_render"], 1)
     return {"workload": f"adjoint: {P} pose x {V} cameras at {H}x{W} ({rays} rays), L2 loss to seeded targets",
             "mrays_s": round(rays / t / 1e6, 2), "ms_per_call": round(t * 1e3, 3),
+            "ms_per_call_reusing_forward_octrees": round(t_reuse * 1e3, 3),
             "adjoint_kernel_ms": round(kern_ms, 4), "samples": st["samples"],
             "algorithmic_bytes_per_sample": per_sample, "algorithmic_bytes_per_ray": per_ray,
             "adjoint_hbm_frac": round(alg / (kern_ms * 1e-3) / 8e12, 4)}
