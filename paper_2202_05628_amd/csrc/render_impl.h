@@ -279,7 +279,7 @@ __device__ inline void root_span(const R* d, const R* q, const R* inv, R h, int 
 #define ART_RENDER_WAVES_PER_EU 3
 #endif
 #ifndef ART_RENDER_WAVES_PER_EU_F32
-#define ART_RENDER_WAVES_PER_EU_F32 4   // FP32 geometry (the BF16 form): fewer registers, one more wave
+#define ART_RENDER_WAVES_PER_EU_F32 5   // FP32 geometry (the BF16 form): fewer registers, two more waves
 #endif
 // Adjoint gradient scatter through LDS: each round the lanes with a sample
 // stage (leaf, w); the feature gradients w g_c are then added with lanes
