@@ -273,8 +273,10 @@ struct PassOut {
 };
 
 // Skinning + octree build of poses [p0, p0 + batch) into slots 0..batch-1.
+// cell_keys: also store the posed key of each occupied cell (occ_key), which
+// only the inspection call reads.
 art_status build_batch(art_ctx* ctx, const CallPlan& pl, int p0, int batch, const void* sigma, const void* feat,
-                       int* launches, Timing& tm) {
+                       int* launches, Timing& tm, bool cell_keys = false) {
     Scratch& s = ctx->s;
     hipStream_t st = ctx->stream;
     PoseCounters* cnt = s.counters.as<PoseCounters>();
@@ -292,8 +294,10 @@ art_status build_batch(art_ctx* ctx, const CallPlan& pl, int p0, int batch, cons
                 "skin");
     *launches += 3;
     tm.record(st, 1);
-    ART_TRY_HIP(launch_build_octree_dense(s.keys0.as<uint32_t>(), (uint32_t)n, ctx->depth, s,
-                                          octree_slot(ctx, pl, 0), batch, st, launches),
+    OctreeSlot os = octree_slot(ctx, pl, 0);
+    if (!cell_keys) os.occ_key = nullptr;
+    ART_TRY_HIP(launch_build_octree_dense(s.keys0.as<uint32_t>(), (uint32_t)n, ctx->depth, s, os, batch, st,
+                                          launches),
                 "octree build");
     hipLaunchKernelGGL(k_accum, dim3((batch + 63) / 64), dim3(64), 0, st, (const PoseCounters*)cnt,
                        s.stats.as<unsigned long long>(), (uint32_t)n, batch);
@@ -1571,7 +1575,7 @@ art_status art_get_octree(art_ctx* ctx, int pose, unsigned flags, int64_t* count
     }
     Timing tm;
     int launches = 0;
-    rc = build_batch(ctx, pl, pose, 1, zs.p, zf.p, &launches, tm);
+    rc = build_batch(ctx, pl, pose, 1, zs.p, zf.p, &launches, tm, true);
     PoseCounters hc{};
     if (rc == ART_OK) {
         e = hipMemcpyAsync(&hc, ctx->s.counters.p, sizeof(hc), hipMemcpyDeviceToHost, st);

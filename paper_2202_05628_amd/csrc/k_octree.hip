@@ -192,7 +192,7 @@ __global__ __launch_bounds__(256) void k_dense_place(const uint32_t* __restrict_
     wpref += p * bwords;
     mask += p * n * 16;
     brick_row += p * (n + 1);
-    occ_key += p * n;
+    if (occ_key) occ_key += p * n;
     occ_win += p * n;
     rows += p * n;
     const uint32_t step = gridDim.x * blockDim.x * kLeafUnroll;
@@ -226,7 +226,7 @@ __global__ __launch_bounds__(256) void k_dense_place(const uint32_t* __restrict_
                     }
                 }
                 row = brick_row[bi] + below;
-                occ_key[row] = key[u];
+                if (occ_key) occ_key[row] = key[u];
                 occ_win[row] = i;
             }
             if (i < n) rows[i] = row;
