@@ -88,6 +88,31 @@ void art_destroy(art_ctx* ctx);
 const char* art_last_error(const art_ctx* ctx);
 
 /*
+ * Counter of the inputs the posed octrees depend on: every call of
+ * art_load_octree, art_set_skin, art_set_skeleton, art_set_poses and
+ * art_set_cameras increments it (even when it fails).  A caller that keeps the
+ * outputs of a render for a later art_backward (an autograd graph) records it
+ * with the render and checks it before the backward: the adjoint re-traverses
+ * the rays of the context's current poses and cameras.  0 for a NULL ctx.
+ */
+uint64_t art_state_version(const art_ctx* ctx);
+
+/*
+ * Bound on the context's working memory: the device buffers the library
+ * allocates beyond the copies of its inputs (posed octrees, tile lists, sort
+ * and scan scratch, proposal-network state and scratch, shading activations).
+ * bytes <= 0 removes the bound (the default).  A call that would grow the
+ * working buffers beyond the bound fails with ART_ENOMEM before allocating and
+ * leaves the context usable; render calls first shrink their pose batches to
+ * fit it.  Buffers already held are not released.
+ * art_get_memory: current working bytes and the bound (host int64, either
+ * pointer may be NULL).
+ * Errors: ART_EINVAL (NULL ctx).
+ */
+art_status art_set_memory_limit(art_ctx* ctx, int64_t bytes);
+art_status art_get_memory(art_ctx* ctx, int64_t* working_bytes, int64_t* limit);
+
+/*
  * Load the canonical octree: the occupied leaf array P of Section 3.1
  * ("Octree Feature Indexing"), as n leaves at depth `depth` (1..9).
  * ijk: host uint16 [3][n] SoA planes (x plane, y plane, z plane), each < 2^depth,
@@ -146,7 +171,11 @@ art_status art_set_cameras(art_ctx* ctx, int V, int H, int W, const double* K, c
  * C: feature channels, one of 4, 8, 16, 32.
  * dtype: storage of the FLUT (ART_F32 or ART_BF16; BF16 is converted to FP32
  *        on load, transmittance and accumulation are always FP32).
- * sigma: device [n] densities (>= 0) of the canonical leaves, in dtype.
+ * sigma: device [n] densities of the canonical leaves, in dtype; every one
+ *        finite and >= 0 (checked on the device: otherwise the call renders
+ *        nothing, returns ART_EINVAL, and the outputs are unspecified).  The
+ *        features are not checked: a non-finite feature reaches the maps of
+ *        the pixels that composite it.
  * feat:  device [n][C] features of the canonical leaves, in dtype (row-major).
  * out_feat:   device float32 [P][V][C][H][W] feature maps F.
  * out_alpha:  device float32 [P][V][H][W] coarse opacity maps A (sum of weights).
@@ -155,7 +184,8 @@ art_status art_set_cameras(art_ctx* ctx, int V, int H, int W, const double* K, c
  * Collisions: when several leaves warp into one posed cell the one with the
  * smallest canonical index is rendered.
  * Errors: ART_ESTATE (octree, skin, skeleton, poses or cameras missing),
- * ART_EINVAL (null pointers, lambda_th outside [0,1), bone id >= J),
+ * ART_EINVAL (null pointers, lambda_th outside [0,1), bone id >= J, a
+ * negative or non-finite density),
  * ART_EUNSUPPORTED (C), ART_ENOMEM, ART_EDEVICE.
  */
 art_status art_render(art_ctx* ctx, int C, art_dtype dtype, const void* sigma, const void* feat,

@@ -310,8 +310,10 @@ def render(o: np.ndarray, d: np.ndarray, depth: int, occ_key: np.ndarray, occ_le
     hit_leaf/hit_delta [n][max_hits] of the composited samples, and seg [n][4]:
     t_a, t_b of the clipped ray (NaN on a miss) and the entry t of the first /
     exit t of the last composited sample (NaN without samples), and dist [n]:
-    the entry t of the first composited sample with density > depth_sigma
-    (+inf without one) - the depth buffer of the hybrid rendering (Section 5)."""
+    the entry t of the first occupied voxel along the whole clipped ray with
+    density > depth_sigma, whether or not the early stop came before it (+inf
+    without one) - the depth buffer of the hybrid rendering (Section 3.1,
+    paragraph "Hybrid Rendering")."""
     lib = _load()
     o = np.ascontiguousarray(o, dtype=np.float64).reshape(-1, 3)
     d = np.ascontiguousarray(d, dtype=np.float64).reshape(-1, 3)

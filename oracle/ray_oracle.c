@@ -155,9 +155,12 @@ static int64_t max_points(int G) { return 3 * (int64_t)(G + 1) + 2; }
  * composited sample and the exit t of the last one (NaN without samples): the
  * interval a ray-interval proposal has to cover.
  * Optional depth [n] (may be NULL) receives the depth-buffer value of the
- * hybrid rendering of Section 5 ("Hybrid Rendering"): the distance t along
- * the unit ray at which it enters the first voxel whose density exceeds
- * depth_sigma, among the composited samples; +inf when there is none.
+ * hybrid rendering (Section 3.1, paragraph "Hybrid Rendering"): the ray is
+ * traced through the whole clipped span, and the value is the distance t
+ * along the unit ray at which it enters the first occupied voxel (the
+ * collision winner of its cell) whose density is above depth_sigma; +inf
+ * when there is none.  The early stop of the compositing does not end this
+ * search.
  * Returns 0, or -1 on allocation failure.
  */
 int oracle_render(int64_t n, const double* o, const double* d, int G, double h,
@@ -192,11 +195,17 @@ int oracle_render(int64_t n, const double* o, const double* d, int G, double h,
                 double T = 1.0, acc = 0.0, tg = INFINITY, dep = INFINITY;
                 double* Fr = F + (size_t)r * C;
                 for (int c = 0; c < C; ++c) Fr[c] = 0.0;
+                /* depth buffer: first occupied voxel of the whole ray above the threshold */
+                for (int64_t i = 0; i < ns; ++i) {
+                    if (sigma[smp[i].leaf] > depth_sigma) {
+                        dep = smp[i].t0;
+                        break;
+                    }
+                }
                 int64_t used = 0;
                 for (int64_t i = 0; i < ns; ++i) {
                     const double s = sigma[smp[i].leaf];
                     const double* f = feat + (size_t)smp[i].leaf * C;
-                    if (dep == INFINITY && s > depth_sigma) dep = smp[i].t0;
                     double tau = s * smp[i].delta;
                     double alpha = -expm1(-tau);
                     double w = T * alpha;

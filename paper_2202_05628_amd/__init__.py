@@ -77,6 +77,20 @@ class Renderer:
         except Exception:
             pass
 
+    def state_version(self) -> int:
+        """Counter of the octree / skin / skeleton / poses / cameras setters."""
+        return int(self.lib.art_state_version(self._h))
+
+    def set_memory_limit(self, nbytes: int) -> None:
+        """Bound the library's working device memory (0: no bound)."""
+        self._check(self.lib.art_set_memory_limit(self._h, int(nbytes)), "art_set_memory_limit")
+
+    def memory(self) -> dict:
+        held = ctypes.c_int64(0)
+        lim = ctypes.c_int64(0)
+        self._check(self.lib.art_get_memory(self._h, ctypes.byref(held), ctypes.byref(lim)), "art_get_memory")
+        return {"working_bytes": int(held.value), "limit": int(lim.value)}
+
     def _check(self, rc: int, what: str):
         if rc != 0:
             msg = self.lib.art_last_error(self._h)
@@ -512,11 +526,17 @@ def _make_fn():
             ctx.renderer = renderer
             ctx.lambda_th = lambda_th
             ctx.fp32_geom = fp32_geom
+            # the adjoint re-traverses the context's current poses and cameras
+            ctx.state_version = renderer.state_version()
             return F, A
 
         @staticmethod
         def backward(ctx, dF, dA):
             sigma, feat, F, T = ctx.saved_tensors
+            if ctx.renderer.state_version() != ctx.state_version:
+                raise ArtemisError(_lib.ART_ESTATE,
+                                   "the octree, skin, skeleton, poses or cameras changed between the forward "
+                                   "render and its backward; render again before backward")
             if dF is None:
                 dF = torch.zeros_like(F)
             # the octrees of the forward are reused when nothing they depend on changed since

@@ -34,6 +34,9 @@ SIGNATURES = [
     ("art_create", _I, [_I, _P, ctypes.POINTER(_P)]),
     ("art_destroy", None, [_P]),
     ("art_last_error", ctypes.c_char_p, [_P]),
+    ("art_state_version", ctypes.c_uint64, [_P]),
+    ("art_set_memory_limit", _I, [_P, _L]),
+    ("art_get_memory", _I, [_P, _P, _P]),
     ("art_load_octree", _I, [_P, _I, _L, _P]),
     ("art_set_skin", _I, [_P, _P, _P]),
     ("art_set_skeleton", _I, [_P, _I, _P, _P]),

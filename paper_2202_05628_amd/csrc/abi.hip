@@ -67,6 +67,32 @@ __global__ void k_accum(const PoseCounters* __restrict__ c, unsigned long long* 
     atomicAdd(&st[5], (unsigned long long)c[p].nb);
 }
 
+// k_check_sigma: count the FLUT densities that are negative or not finite
+// (the densities of Eq. 5-6 are non-negative) into *bad.  The compositing
+// kernel reads the count and renders nothing when it is not zero.
+template <int ST>
+__global__ __launch_bounds__(256) void k_check_sigma(const void* __restrict__ sigma, int64_t n,
+                                                     unsigned long long* __restrict__ bad) {
+    unsigned cnt = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const float v = ST == 0 ? reinterpret_cast<const float*>(sigma)[i]
+                                : bf16_to_f32(reinterpret_cast<const uint16_t*>(sigma)[i]);
+        cnt += (v >= 0.0f && v <= 3.402823466e38f) ? 0u : 1u;   // false for NaN
+    }
+    const unsigned w = wave_sum(cnt);
+    if (lane_id() == 0 && w) atomicAdd(bad, (unsigned long long)w);
+}
+
+hipError_t launch_check_sigma(const void* sigma, int storage, int64_t n, unsigned long long* bad, hipStream_t st) {
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 2048) blocks = 2048;
+    if (blocks < 1) blocks = 1;
+    if (storage) hipLaunchKernelGGL(k_check_sigma<1>, dim3((unsigned)blocks), dim3(256), 0, st, sigma, n, bad);
+    else hipLaunchKernelGGL(k_check_sigma<0>, dim3((unsigned)blocks), dim3(256), 0, st, sigma, n, bad);
+    return hipGetLastError();
+}
+
 struct CallPlan {
     int C = 0;
     int storage = 0;
@@ -113,9 +139,36 @@ art_status plan_call(art_ctx* ctx, int C, art_dtype dtype, unsigned flags, CallP
     return ART_OK;
 }
 
+// The context's working buffers: everything the library allocates beyond the
+// copies of its inputs (scratch of the render, octree, proposal-network and
+// shading calls).  art_set_memory_limit bounds their total capacity.
+std::vector<DevBuf*> working_bufs(art_ctx* ctx) {
+    Scratch& s = ctx->s;
+    return {&ctx->B64, &ctx->B32, &ctx->Gtmp, &ctx->shade_act,
+            &s.keys0, &s.keys1, &s.bmap, &s.wpref, &s.hist, &s.digit_tot, &s.blk0, &s.blk1, &s.occ_key,
+            &s.occ_win, &s.brick_key, &s.brick_row, &s.brick_mask, &s.bin_cnt, &s.bin_off, &s.pk0, &s.pv0,
+            &s.pk1, &s.pair_v, &s.tile_start, &s.tile_end, &s.counters, &s.stats, &s.ovf, &s.items, &s.queue,
+            &s.loss, &s.redo, &s.interval, &ctx->mlp_theta, &ctx->mlp_m1, &ctx->mlp_m2, &ctx->mlp_packed, &ctx->mlp_cbias,
+            &ctx->mlp_code, &ctx->mlp_S, &ctx->mlp_part, &ctx->mlp_lossp, &ctx->mlp_loss, &ctx->mlp_flag};
+}
+
+size_t working_bytes(art_ctx* ctx) {
+    size_t t = 0;
+    for (const DevBuf* b : working_bufs(ctx)) t += b->cap;
+    return t;
+}
+
 art_status ensure_bufs(art_ctx* ctx, std::initializer_list<std::pair<DevBuf*, size_t>> req) {
     for (auto& r : req) {
         const size_t cap = r.first->cap;
+        if (ctx->mem_limit > 0 && r.second > cap) {
+            // growing this buffer frees its old storage and allocates max(bytes, 256)
+            const size_t held = working_bytes(ctx);
+            const size_t after = (held >= cap ? held - cap : 0) + std::max<size_t>(r.second, 256);
+            if (after > ctx->mem_limit)
+                return fail(ctx, ART_ENOMEM, "working memory would reach " + std::to_string(after) +
+                                                 " bytes, above the limit of " + std::to_string(ctx->mem_limit));
+        }
         ART_TRY_HIP(r.first->ensure(r.second), "device allocation");
         if (r.first->cap != cap) ctx->memo.valid = false;   // a reallocated buffer lost its contents
     }
@@ -125,13 +178,16 @@ art_status ensure_bufs(art_ctx* ctx, std::initializer_list<std::pair<DevBuf*, si
 // Device memory held for the posed octrees of one batch of poses (48 GiB by
 // default, ARTEMIS_SLOT_BUDGET_MB overrides); the poses of a call are processed
 // in batches that fit it.
-size_t slot_budget_bytes() {
+size_t slot_budget_bytes(const art_ctx* ctx) {
+    size_t b = (size_t)48 << 30;
     const char* e = getenv("ARTEMIS_SLOT_BUDGET_MB");
     if (e && *e) {
         const long long mb = atoll(e);
-        if (mb > 0) return (size_t)mb << 20;
+        if (mb > 0) b = (size_t)mb << 20;
     }
-    return (size_t)48 << 30;
+    // under a working-memory limit the batches shrink to fit it
+    if (ctx->mem_limit > 0) b = std::min(b, ctx->mem_limit);
+    return b;
 }
 
 // Initial capacity of one (pose, view group) tile list (ARTEMIS_PAIR_CAP
@@ -521,7 +577,7 @@ art_status render_call(art_ctx* ctx, int C, art_dtype dtype, const void* sigma, 
         const size_t tiles_g = (size_t)pl.Vg * ((ctx->W + 7) / 8) * ((ctx->H + 7) / 8);
         ctx->s.pair_cap = initial_pair_cap(tiles_g);
     }
-    int slots = (int)std::min<size_t>((size_t)P, std::max<size_t>(1, slot_budget_bytes() / slot_bytes(ctx, pl, ctx->s.pair_cap)));
+    int slots = (int)std::min<size_t>((size_t)P, std::max<size_t>(1, slot_budget_bytes(ctx) / slot_bytes(ctx, pl, ctx->s.pair_cap)));
     rc = ensure_scratch(ctx, pl, slots);
     if (rc != ART_OK) return rc;
     hipStream_t st = ctx->stream;
@@ -533,6 +589,10 @@ art_status render_call(art_ctx* ctx, int C, art_dtype dtype, const void* sigma, 
     const bool reuse = o.reuse && whole && memo_matches(ctx, pl);
 
     ART_TRY_HIP(launch_fill_u32(ctx->s.stats.as<uint32_t>(), 0u, 32, st), "fill");
+    ART_TRY_HIP(launch_check_sigma(sigma, pl.storage, ctx->n, ctx->s.stats.as<unsigned long long>() + kStatBadSigma,
+                                   st),
+                "density check");
+    launches += 1;
     tm.record(st, -1);
     if (!reuse) {
         ART_TRY_HIP(launch_fk(ctx->parent.as<int32_t>(), ctx->rest.as<double>(), ctx->pose.as<double>(), ctx->J,
@@ -543,6 +603,7 @@ art_status render_call(art_ctx* ctx, int C, art_dtype dtype, const void* sigma, 
     launches += 1;
     tm.record(st, 0);
     unsigned long long hst[16] = {0};
+    bool reran = false;   // some (pose, view group) items were rendered again after an overflow
     for (int p0 = pose_lo; p0 < pose_hi; p0 += slots) {
         const int p1 = std::min(pose_hi, p0 + slots);
         const size_t items = (size_t)(p1 - p0) * pl.ngroups;
@@ -557,6 +618,9 @@ art_status render_call(art_ctx* ctx, int C, art_dtype dtype, const void* sigma, 
             // copy after the last batch's last attempt is the call's total)
             ART_TRY_HIP(hipMemcpyAsync(hst, ctx->s.stats.p, sizeof(hst), hipMemcpyDeviceToHost, st), "copy");
             ART_TRY_HIP(hipStreamSynchronize(st), "render");
+            if (hst[kStatBadSigma] != 0ull)   // the compositing kernel rendered nothing
+                return fail(ctx, ART_EINVAL, std::to_string(hst[kStatBadSigma]) +
+                                                 " FLUT densities are negative or not finite");
             std::vector<char> redo(items, 0);
             size_t need = 0;
             bool any = false;
@@ -569,6 +633,7 @@ art_status render_call(art_ctx* ctx, int C, art_dtype dtype, const void* sigma, 
                 }
             if (!any) break;
             if (attempt == 2) return fail(ctx, ART_EDEVICE, "tile list buffer overflow persisted");
+            reran = true;
             ctx->s.pair_cap = need + need / 4 + 1024;
             rc = ensure_scratch(ctx, pl, slots);
             if (rc != ART_OK) return rc;
@@ -585,7 +650,10 @@ art_status render_call(art_ctx* ctx, int C, art_dtype dtype, const void* sigma, 
     ctx->stats[12] = (int64_t)hst[11];
     ctx->stats[13] = (int64_t)hst[12];
     tm.finish(ctx);
-    if (whole) take_memo(ctx, pl);   // the slots hold every pose's octree and tile lists
+    // the slots hold every pose's octree and tile lists - unless an overflow
+    // re-run rebuilt only some items: the others' overflow flags then mark them
+    // as done, and a reusing call would skip them
+    if (whole && !reran) take_memo(ctx, pl);
     return ART_OK;
 }
 
@@ -749,6 +817,21 @@ void art_destroy(art_ctx* ctx) {
 }
 
 const char* art_last_error(const art_ctx* ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+uint64_t art_state_version(const art_ctx* ctx) { return ctx ? ctx->state_version : 0; }
+
+art_status art_set_memory_limit(art_ctx* ctx, int64_t bytes) {
+    if (!ctx) return ART_EINVAL;
+    ctx->mem_limit = bytes > 0 ? (size_t)bytes : 0;
+    return ART_OK;
+}
+
+art_status art_get_memory(art_ctx* ctx, int64_t* working_bytes_out, int64_t* limit_out) {
+    if (!ctx) return ART_EINVAL;
+    if (working_bytes_out) *working_bytes_out = (int64_t)working_bytes(ctx);
+    if (limit_out) *limit_out = (int64_t)ctx->mem_limit;
+    return ART_OK;
+}
 
 art_status art_load_octree(art_ctx* ctx, int depth, int64_t n, const uint16_t* ijk) {
     if (!ctx) return ART_EINVAL;
@@ -1073,7 +1156,10 @@ art_status art_shading_forward(art_ctx* ctx, int C, int N, int H, int W, const f
         off[i] = tot;
         tot += (sz[i] + 127) / 128 * 128;
     }
-    ART_TRY_HIP(ctx->shade_act.ensure(tot * 2), "device allocation");
+    {
+        const art_status ra = ensure_bufs(ctx, {{&ctx->shade_act, tot * 2}});
+        if (ra != ART_OK) return ra;
+    }
     uint16_t* base = ctx->shade_act.as<uint16_t>();
     uint16_t* X = base + off[0];
     uint16_t* T0 = base + off[1];
@@ -1159,7 +1245,7 @@ art_status art_vrt(art_ctx* ctx, int C, art_dtype dtype, const void* feat, float
     pl.ngroups = 1;
     if (ctx->s.pair_cap == 0) ctx->s.pair_cap = initial_pair_cap(1);
     const int slots = (int)std::min<size_t>((size_t)ctx->P,
-                                            std::max<size_t>(1, slot_budget_bytes() / slot_bytes(ctx, pl, ctx->s.pair_cap)));
+                                            std::max<size_t>(1, slot_budget_bytes(ctx) / slot_bytes(ctx, pl, ctx->s.pair_cap)));
     rc = ensure_scratch(ctx, pl, slots);
     if (rc != ART_OK) return rc;
     hipStream_t st = ctx->stream;
@@ -1333,7 +1419,10 @@ art_status art_proposal_gather(art_ctx* ctx, int64_t n, const int64_t* ray_id, c
     if (n > 0 && (!ray_id || !labels || !od || !pose || !target)) return fail(ctx, ART_EINVAL, "NULL buffer");
     DeviceGuard g(ctx->device);
     hipStream_t st = ctx->stream;
-    ART_TRY_HIP(ctx->mlp_flag.ensure(64), "device allocation");
+    {
+        const art_status rf = ensure_bufs(ctx, {{&ctx->mlp_flag, 64}});
+        if (rf != ART_OK) return rf;
+    }
     ART_TRY_HIP(launch_fill_u32(ctx->mlp_flag.as<uint32_t>(), 0u, 1, st), "fill");
     ART_TRY_HIP(launch_mlp_gather(ray_id, n, labels, ctx->cam.as<CamParams>(), ctx->P, ctx->V, ctx->H, ctx->W, od,
                                   pose, target, ctx->mlp_flag.as<uint32_t>(), st),
@@ -1375,7 +1464,10 @@ art_status art_proposal_forward(art_ctx* ctx, int64_t n, const float* od, const 
     art_status rc = mlp_prepare(ctx);
     if (rc != ART_OK) return rc;
     if (n == 0) return ART_OK;
-    ART_TRY_HIP(ctx->mlp_flag.ensure(64), "device allocation");
+    {
+        const art_status rf = ensure_bufs(ctx, {{&ctx->mlp_flag, 64}});
+        if (rf != ART_OK) return rf;
+    }
     ART_TRY_HIP(launch_fill_u32(ctx->mlp_flag.as<uint32_t>(), 0u, 1, ctx->stream), "fill");
     ART_TRY_HIP(launch_mlp_forward(ctx->mlp_packed.as<uint16_t>(), ctx->mlp_theta.as<float>(),
                                    ctx->mlp_cbias.as<float>(), mlp_dims(ctx->J), od, pose, ctx->P, n, out,
@@ -1501,9 +1593,10 @@ art_status art_get_bones(art_ctx* ctx, double* B) {
     if (ctx->P <= 0) return fail(ctx, ART_ESTATE, "no poses (art_set_poses)");
     DeviceGuard g(ctx->device);
     const size_t nb = (size_t)ctx->P * ctx->J * 12;
-    ART_TRY_HIP(ctx->B64.ensure(nb * 8), "device allocation");
-    ART_TRY_HIP(ctx->B32.ensure(nb * 4), "device allocation");
-    ART_TRY_HIP(ctx->Gtmp.ensure(nb * 8), "device allocation");
+    {
+        const art_status rb = ensure_bufs(ctx, {{&ctx->B64, nb * 8}, {&ctx->B32, nb * 4}, {&ctx->Gtmp, nb * 8}});
+        if (rb != ART_OK) return rb;
+    }
     ART_TRY_HIP(launch_fk(ctx->parent.as<int32_t>(), ctx->rest.as<double>(), ctx->pose.as<double>(), ctx->J,
                           ctx->P, ctx->Gtmp.as<double>(), ctx->B64.as<double>(), ctx->B32.as<float>(),
                           ctx->stream),
@@ -1522,9 +1615,10 @@ art_status art_get_posed_keys(art_ctx* ctx, int pose, unsigned flags, uint32_t* 
     if (flags & ~ART_GEOM_FP32) return fail(ctx, ART_EINVAL, "unknown flag bits");
     DeviceGuard g(ctx->device);
     const size_t nb = (size_t)ctx->P * ctx->J * 12;
-    ART_TRY_HIP(ctx->B64.ensure(nb * 8), "device allocation");
-    ART_TRY_HIP(ctx->B32.ensure(nb * 4), "device allocation");
-    ART_TRY_HIP(ctx->Gtmp.ensure(nb * 8), "device allocation");
+    {
+        const art_status rb = ensure_bufs(ctx, {{&ctx->B64, nb * 8}, {&ctx->B32, nb * 4}, {&ctx->Gtmp, nb * 8}});
+        if (rb != ART_OK) return rb;
+    }
     hipStream_t st = ctx->stream;
     ART_TRY_HIP(launch_fk(ctx->parent.as<int32_t>(), ctx->rest.as<double>(), ctx->pose.as<double>(), ctx->J,
                           ctx->P, ctx->Gtmp.as<double>(), ctx->B64.as<double>(), ctx->B32.as<float>(), st),

@@ -83,6 +83,7 @@ struct RunStats {
 };
 
 constexpr int kNumStats = 14;
+constexpr int kStatBadSigma = 15;     // device run-statistics slot: FLUT densities < 0 or not finite
 constexpr int kMaxBonesSH = 64;       // bone rotations staged in LDS by the view-dependent (SH) render
 constexpr int kSortBlocks = 512;      // fixed grid (per pose) of the radix-sort passes
 constexpr int kScanBlocks = 256;      // fixed grid (per pose) of device-sized scans
@@ -176,6 +177,7 @@ struct art_ctx {
     // precision, not on the FLUT).  Every setter bumps state_version; every
     // build clears `valid`; a reallocated scratch buffer changes its pointers.
     uint64_t state_version = 0;
+    size_t mem_limit = 0;          // bound on the working buffers' total capacity (0: none)
     struct BuildMemo {
         bool valid = false;
         uint64_t version = 0;

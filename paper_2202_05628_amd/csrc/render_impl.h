@@ -268,9 +268,11 @@ __device__ inline void root_span(const R* d, const R* q, const R* inv, R h, int 
 
 // MODE: 0 forward, 1 adjoint, 2 forward recording hit lists, 3 interval labels,
 // 4 forward guided by proposed intervals (with full-traversal fallbacks),
-// 5 forward with the depth buffer (Section 5, hybrid rendering: the distance
-// along the unit ray at which it enters the first composited sample whose
-// density exceeds a threshold; +inf when there is none),
+// 5 forward with the depth buffer (Section 3.1, paragraph "Hybrid Rendering":
+// the distance along the unit ray at which it enters the first occupied voxel
+// whose density is above a threshold, searched along the whole ray: a lane
+// whose compositing stops early without a depth keeps traversing, without
+// compositing, until it finds one; +inf when there is none),
 // 6 forward with view-dependent features (Eq. 2 in Eq. 5): the FLUT holds H
 // blocks of C SH coefficients per leaf, and a sample contributes
 // w sum_h k_h Y_h(d^c) at the canonical direction d^c = R^T d, R the rotation
@@ -421,6 +423,7 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
     int nsamp = 0;
     R t_first = 0, t_last = 0;   // MODE 3: entry of the first / exit of the last sample
     float zdep = INFINITY;       // MODE 5: depth
+    bool cdone = false;          // MODE 5: compositing stopped, the depth search goes on
     // adjoint state
     float g[C], Ff[C], P[C];
     float gA = 0.0f, Tfin = 0.0f;
@@ -739,6 +742,14 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
 #endif
             }
             // (2) composite the current sample (Eq. 5-6, exclusive transmittance)
+            if (MODE == 5 && cdone) {
+                // depth search past the early stop: no compositing
+                if (hasA && active && sgA > a.depth_sigma) {
+                    zdep = (float)sA0;
+                    active = false;
+                    inb = false;
+                }
+            } else
 #if ART_BRANCHLESS
             // forward without hit lists: every lane runs the update, a lane without
             // a sample with alpha = 0 (w = 0 leaves F, A and T unchanged exactly)
@@ -824,8 +835,12 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
                 T = Tn;
                 ++nsamp;
                 if (T < a.lambda) {
-                    active = false;
-                    inb = false;
+                    if (MODE == 5 && zdep == INFINITY) {
+                        cdone = true;
+                    } else {
+                        active = false;
+                        inb = false;
+                    }
                 }
             }
 #if ART_ADJ_LINES
@@ -956,6 +971,8 @@ void k_render(RArgs a) {
     __shared__ float s_rot[MODE == 6 ? kMaxBonesSH * 9 : 1];
     AdjLds<C>* s_adj = adj_lds<C, MODE>();
     const int lane = threadIdx.x & 63;
+    // invalid densities in the FLUT: nothing is rendered (the call reports it)
+    if (a.stats[kStatBadSigma] != 0ull) return;
     const uint32_t n_items = *a.n_items;
     __shared__ WaveStats ws;
     if (lane == 0)

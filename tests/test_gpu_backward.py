@@ -13,9 +13,11 @@ pytestmark = pytest.mark.gpu
 TOL_GRAD = 1e-4
 
 
-@pytest.fixture(scope="module")
-def tiny():
-    s = sg.make_scene("tiny")
+# C = 16 and 32 map 4 and 2 samples onto one atomic instruction of the
+# adjoint's row-wise gradient scatter, C = 8 eight: each is its own code path
+@pytest.fixture(scope="module", params=[8, 16, 32], ids=["C8", "C16", "C32"])
+def tiny(request):
+    s = sg.make_scene("tiny", C=request.param)
     poses = sg.make_poses(s.J, 2)
     K, c2w = sg.make_cameras(s, 2, 96, 96)
     rend = make_renderer(s, poses, K, c2w, 96, 96)
@@ -54,7 +56,7 @@ def test_adjoint_matches_oracle(tiny, lam):
     sig, f = flut(s)
     sig.requires_grad_(True)
     f.requires_grad_(True)
-    log(f"adjoint: tiny, 2 poses x 2 views, lambda {lam}")
+    log(f"adjoint: tiny, C = {s.C}, 2 poses x 2 views, lambda {lam}")
     F, A = art.render(rend, sig, f, lambda_th=lam)
     tgt = torch.from_numpy(target).cuda()
     loss = 0.5 * ((F - tgt) ** 2).sum() + (A * torch.from_numpy(gA).cuda()).sum()

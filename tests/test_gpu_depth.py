@@ -1,8 +1,10 @@
-"""The depth buffer of hybrid rendering (Section 5) through the C ABI.
+"""The depth buffer of hybrid rendering (Section 3.1, paragraph "Hybrid
+Rendering") through the C ABI.
 
-Per pixel: the distance along the ray to the entry of the first composited
-sample whose density exceeds a threshold (+inf if none), against the FP64
-oracle on the same seeded scene.  The threshold decision is taken on the
+Per pixel: the distance along the ray to the entry of the first occupied voxel
+whose density is above a threshold, searched along the whole ray whether or not
+the compositing stopped early (+inf if none), against the FP64 oracle on the
+same seeded scene.  The threshold decision is taken on the
 stored density on both sides (FP32 or BF16 values, a threshold representable
 in FP32), so the set of counted samples is exact; the distance is compared to
 FP32 rounding.  The maps written beside the depth equal art_render's bit for
@@ -98,3 +100,37 @@ def test_depth_argument_errors(tiny2):
     sig, f = flut(s)
     with pytest.raises(art.ArtemisError):
         rend.render_depth(sig, f, float("nan"), 0.01)
+
+
+@pytest.mark.parametrize("C", [8, 16])
+def test_depth_past_the_early_stop(C):
+    """A threshold above most densities: many rays turn opaque (T < 0.01)
+    before they reach a voxel above it, and their depth lies beyond the last
+    composited sample; the kernel's depth-only scan past the stop must find it."""
+    import torch
+    s = sg.make_scene("tiny", C=C)
+    poses = sg.make_poses(s.J, 2)
+    H, W = 90, 102
+    K, c2w = sg.make_cameras(s, 2, H, W)
+    rend = make_renderer(s, poses, K, c2w, H, W)
+    B = oracle.fk(s.parent, s.rest_joint, *poses)
+    sig, f = flut(s)
+    sig_np = sig.cpu().numpy().astype(np.float64)
+    th = float(np.float32(np.quantile(sig_np, 0.97)))
+    log(f"depth past the stop: C = {C}, threshold {th:.3f}")
+    F0, A0, T0 = rend.render(sig, f, 0.01)
+    F1, A1, T1, D = rend.render_depth(sig, f, th, 0.01)
+    assert np.array_equal(F0.cpu().numpy(), F1.cpu().numpy())
+    assert np.array_equal(A0.cpu().numpy(), A1.cpu().numpy())
+    assert np.array_equal(T0.cpu().numpy(), T1.cpu().numpy())
+    n_fin = _check(s, B, K, c2w, H, W, 0.01, sig_np, s.feat.astype(np.float64), th, D.cpu().numpy())
+    o, d = oracle.camera_rays(K, c2w, H, W)
+    late = 0
+    for p in range(2):
+        ok, ol, _, _, _ = oracle.pose_occupancy(s.ijk, s.depth, s.bone, s.weight, B[p])
+        for v in range(2):
+            ref = oracle.render(o[v].reshape(-1, 3), d[v].reshape(-1, 3), s.depth, ok, ol, sig_np,
+                                s.feat.astype(np.float64), 0.01, depth_sigma=th)
+            late += int((np.isfinite(ref["dist"]) & (ref["dist"] >= ref["seg"][:, 3])).sum())
+    log(f"  {n_fin} finite depths checked, {late} of them beyond the early stop")
+    assert late > 100

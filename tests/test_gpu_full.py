@@ -27,22 +27,44 @@ def full():
     return s, rend, B, K, c2w, cfg
 
 
-def test_full_octree_bit_exact(full):
+@pytest.mark.parametrize("pi", [0, 1], ids=["pose0", "pose29"])
+def test_full_octree_bit_exact(full, pi):
+    """Posed keys, occupied cells, winners and the brick level of a pose against
+    the oracle's set constructions.  A leaf whose posed centre lies within
+    1e-9 h of a lattice plane (the rounding guard band) may land in either
+    cell; the cells such a leaf can reach (its key on either side) are left
+    out of the comparison, everything else is compared exactly, and the brick
+    rows are checked for consistency with the GPU's own cell list."""
     s, rend, B, *_ = full
-    log("full: posed keys + octree of pose 0")
-    pt = oracle.lbs(s.ijk, s.depth, s.bone, s.weight, B[0])
+    log(f"full: posed keys + octree of pose {POSES[pi]}")
+    pt = oracle.lbs(s.ijk, s.depth, s.bone, s.weight, B[pi])
     cells, valid = oracle.posed_cells(pt, s.depth)
     ko = oracle.posed_keys(cells, valid)
-    kg = rend.get_posed_keys(0)
+    kg = rend.get_posed_keys(pi)
     band = guard_leaves(pt, s.depth)
+    log(f"  {int(band.sum())} leaves in the guard band")
     assert band.sum() <= 5
     assert np.array_equal(kg[~band], ko[~band])
-    if band.sum() == 0:
-        g = rend.get_octree(0)
-        o = oracle.posed_octree(ko)
+    g = rend.get_octree(pi)
+    o = oracle.posed_octree(ko)
+    assert g["collisions"] > 0
+    skip = set(int(k) for k in np.concatenate([kg[band], ko[band]]) if k != 0xFFFFFFFF)
+    gw = {int(k): int(w) for k, w in zip(g["keys"], g["winner"]) if int(k) not in skip}
+    ow = {int(k): int(w) for k, w in zip(o["keys"], o["winner"]) if int(k) not in skip}
+    assert gw == ow
+    skip_b = set(k >> 9 for k in skip)
+    gb = {int(b): m for b, m in zip(g["brick_keys"], g["brick_mask"]) if int(b) not in skip_b}
+    ob = {int(b): m for b, m in zip(o["brick_keys"], o["brick_mask"]) if int(b) not in skip_b}
+    assert gb.keys() == ob.keys()
+    assert all(np.array_equal(gb[b], ob[b]) for b in gb)
+    if not skip:
         for k in ["keys", "winner", "brick_keys", "brick_row", "brick_mask"]:
             assert np.array_equal(g[k], o[k]), k
-        assert g["collisions"] > 0
+    # every brick row points at the first cell of its brick in the GPU's list
+    keys, rows, bk = g["keys"].astype(np.int64), g["brick_row"], g["brick_keys"].astype(np.int64)
+    assert np.all(keys[rows] >> 9 == bk)
+    assert np.all(rows[1:] > rows[:-1]) and rows[0] == 0
+    assert np.all(keys[rows[1:] - 1] >> 9 == bk[:-1])
 
 
 @pytest.mark.parametrize("lam", [0.0, 0.01])

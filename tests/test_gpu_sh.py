@@ -35,16 +35,19 @@ def tiny2():
     return s, rend, B, K, c2w, H, W
 
 
-def _sh_feat(s, nsh, seed):
+def _sh_feat(s, nsh, C, seed):
     rng = np.random.default_rng(seed)
-    return rng.normal(size=(s.n, nsh, s.feat.shape[1])).astype(np.float32)
+    return rng.normal(size=(s.n, nsh, C)).astype(np.float32)
 
 
-@pytest.mark.parametrize("nsh,storage", [(1, "f32"), (4, "f32"), (9, "f32"), (9, "bf16")])
-def test_sh_render_matches_oracle(tiny2, nsh, storage):
+# C = 16 is the channel count of the full workload (its kernels are their own
+# template instances)
+@pytest.mark.parametrize("nsh,storage,C", [(1, "f32", 8), (4, "f32", 8), (9, "f32", 8), (9, "bf16", 8),
+                                           (9, "f32", 16), (9, "bf16", 16)])
+def test_sh_render_matches_oracle(tiny2, nsh, storage, C):
     import torch
     s, rend, B, K, c2w, H, W = tiny2
-    k = _sh_feat(s, nsh, 30 + nsh)
+    k = _sh_feat(s, nsh, C, 30 + nsh + C)
     sig = torch.from_numpy(s.sigma).cuda()
     f = torch.from_numpy(k).cuda()
     if storage == "bf16":
@@ -68,7 +71,7 @@ def test_sh_render_matches_oracle(tiny2, nsh, storage):
             got = Fn[p, v].reshape(Fn.shape[2], -1).T
             err = np.abs(got - ref["F"])[~band].max() / np.abs(ref["F"]).max()
             worst = max(worst, err)
-    log(f"SH H={nsh} {storage}: rel_max {worst:.2e}")
+    log(f"SH H={nsh} C={C} {storage}: rel_max {worst:.2e}")
     assert worst <= TOL
 
 

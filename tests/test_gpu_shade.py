@@ -25,9 +25,10 @@ def rend():
 
 
 # widths 512 and 1024 take the widest tiles (64 pixels x 64 channels per wave,
-# waves over pixels and channels) at every level, as the 512^2 maps do
+# waves over pixels and channels) at every level, as the 512^2 maps do; the
+# 512 x 512 map is the benchmark's own shape (every level's full row count)
 @pytest.mark.parametrize("C,N,H,W", [(16, 2, 32, 48), (16, 1, 24, 136), (8, 3, 16, 16), (16, 1, 16, 264), (32, 1, 16, 32),
-                                     (4, 2, 8, 72), (16, 1, 16, 512), (12, 1, 8, 1024)])
+                                     (4, 2, 8, 72), (16, 1, 16, 512), (12, 1, 8, 1024), (16, 1, 512, 512)])
 def test_shading_matches_reference(rend, C, N, H, W):
     import torch
     rng = np.random.default_rng(60 + C + W)

@@ -1,7 +1,8 @@
-"""Pins of the oracle's depth buffer (Section 5, "Hybrid Rendering": the
-distance at which a pixel's ray enters the first voxel whose density exceeds a
-threshold): an all-voxel slab brute force on tiny grids and the hand-derived
-two-voxel column."""
+"""Pins of the oracle's depth buffer (Section 3.1, paragraph "Hybrid
+Rendering": the distance at which a pixel's ray enters the first voxel whose
+density is above a threshold, found by tracing the whole ray): an all-voxel
+slab brute force on tiny grids, with and without the compositing's early stop
+(which must not change the depth), and the hand-derived two-voxel column."""
 import json
 import math
 import os
@@ -26,8 +27,9 @@ def _slab(o, d, lo, hi):
     return t0, t1
 
 
+@pytest.mark.parametrize("lam", [0.0, 0.01, 0.5])
 @pytest.mark.parametrize("depth,frac", [(1, 0.4), (2, 0.15), (3, 0.03)])
-def test_depth_equals_brute_force(oracle_mod, depth, frac):
+def test_depth_equals_brute_force(oracle_mod, depth, frac, lam):
     rng = np.random.default_rng(70 + depth)
     G = 1 << (depth + 1)
     occ = rng.random((G, G, G)) < frac
@@ -42,7 +44,7 @@ def test_depth_equals_brute_force(oracle_mod, depth, frac):
     o = rng.uniform(-2.5, 2.5, (300, 3))
     d = rng.uniform(-0.9, 0.9, (300, 3)) - o
     d /= np.linalg.norm(d, axis=1, keepdims=True)
-    out = oracle_mod.render(o, d, depth, lin, np.arange(n), sig, np.zeros((n, 1)), 0.0, depth_sigma=th)
+    out = oracle_mod.render(o, d, depth, lin, np.arange(n), sig, np.zeros((n, 1)), lam, depth_sigma=th)
     h = 1.0 / (1 << depth)
     checked = found = 0
     for r in range(len(o)):
@@ -67,6 +69,11 @@ def test_depth_equals_brute_force(oracle_mod, depth, frac):
             assert abs(out["dist"][r] - best) < 1e-12
         checked += 1
     assert checked > 250 and found > 30
+    if lam == 0.5:
+        # on some rays the early stop ends the compositing before the depth
+        # voxel is reached (its entry lies at or after the last composited exit)
+        late = np.isfinite(out["dist"]) & (out["dist"] >= out["seg"][:, 3])
+        assert late.sum() >= 1
 
 
 def test_depth_golden_column(oracle_mod):
