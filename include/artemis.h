@@ -262,11 +262,13 @@ art_status art_render_proposal(art_ctx* ctx, int C, art_dtype dtype, const void*
 
 /*
  * Forward render (as art_render) that also writes the depth buffer of the
- * hybrid rendering of Section 5: per pixel, the distance along the ray (unit
- * direction, from the camera centre) at which it enters the first composited
- * sample whose canonical density, as stored, exceeds depth_sigma (strictly).
- * Only samples composited before the early stop count.  Pixels with no such
- * sample, including every pixel of an empty tile, get +inf.  out_depth:
+ * hybrid rendering (Section 3.1, paragraph "Hybrid Rendering"): per pixel,
+ * the distance along the ray (unit direction, from the camera centre) at
+ * which it enters the first occupied posed voxel (its collision winner) whose
+ * canonical density, as stored, exceeds depth_sigma (strictly).  The search
+ * covers the whole clipped ray: the early stop of the compositing does not
+ * end it.  Pixels with no such voxel, including every pixel of an empty
+ * tile, get +inf.  out_depth:
  * device float32 [P][V][H][W], written in full.  The feature, opacity and
  * transmittance maps are those of art_render, bit for bit.
  * Errors: as art_render; ART_EINVAL for a NULL out_depth or a NaN depth_sigma.

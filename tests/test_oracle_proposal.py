@@ -230,7 +230,7 @@ def test_bf16_forms_close_to_fp64():
     _, g64 = mlp.grad(theta, X, t, 4)
     _, g16 = mlp.grad(theta, X, t, 4, precision="bf16")
     _, g48 = mlp.grad(theta, X, t, 4, precision="bf16x3")
-    assert np.abs(g64 - g16).max() / np.abs(g64).max() < 1e-1
+    assert np.abs(g64 - g16).max() / np.abs(g64).max() < 5e-2
     assert np.abs(g64 - g48).max() / np.abs(g64).max() < 1e-3
 
 
