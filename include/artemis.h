@@ -324,6 +324,27 @@ art_status art_shading_set_weights(art_ctx* ctx, int C, int64_t count, const flo
 art_status art_shading_forward(art_ctx* ctx, int C, int N, int H, int W, const float* F, float* out);
 
 /*
+ * art_shading_forward for callers that cannot allocate device memory during
+ * the call (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same kernels, arguments, layouts and results, but the
+ * activations live in a fixed array of ART_SHADING_NOALLOC_BYTES that the
+ * library holds on every GPU it runs on (from its load until the process
+ * ends) instead of a context buffer; the call allocates nothing.  The weights
+ * (art_shading_set_weights) and the caller's F and out are used as in
+ * art_shading_forward.
+ * A batch needs 332 bytes per pixel of N * H * W plus under 3 KB of
+ * alignment: at most about 303,000 pixels (one 512 x 512 map, two of
+ * 384 x 384).
+ * Every call on one GPU, from any context, uses that GPU's one array and
+ * leaves the last call's activations in it: calls that overlap on one GPU
+ * (other streams, threads or contexts) race, and the caller serialises them.
+ * Errors: as art_shading_forward; ART_EINVAL when the batch needs more than
+ * ART_SHADING_NOALLOC_BYTES (nothing is enqueued).
+ */
+#define ART_SHADING_NOALLOC_BYTES 100663296u   /* 96 MiB */
+art_status art_shading_forward_noalloc(art_ctx* ctx, int C, int N, int H, int W, const float* F, float* out);
+
+/*
  * Voxel regularisation term of Section 3.1 ("Training", Eq. 10) for every pose
  * and its gradient with respect to the features.  For each canonical leaf i
  * whose posed centre lies inside the posed root, Q(p_i^t, T^t) is the feature

@@ -356,17 +356,24 @@ class Renderer:
         w = np.ascontiguousarray(w, dtype=np.float32).reshape(-1)
         self._check(self.lib.art_shading_set_weights(self._h, int(C), w.size, _ptr(w)), "art_shading_set_weights")
 
-    def shade(self, F, out=None):
+    def shade(self, F, out=None, no_alloc: bool = False):
         """The Light shading network on feature maps F [N][C][H][W] (float32,
         device; any leading dims are flattened into N): RGB + opacity
-        [N][4][H][W]."""
+        [N][4][H][W].  no_alloc: the library's allocation-free entry point
+        (activations in its fixed per-GPU array; batches up to
+        ART_SHADING_NOALLOC_BYTES of activations)."""
         torch = self._torch
         C, H, W = int(F.shape[-3]), int(F.shape[-2]), int(F.shape[-1])
         Fc = F.reshape(-1, C, H, W).contiguous().float()
         N = int(Fc.shape[0])
         if out is None:
             out = torch.empty((N, 4, H, W), dtype=torch.float32, device=Fc.device)
-        self._check(self.lib.art_shading_forward(self._h, C, N, H, W, _tptr(Fc), _tptr(out)), "art_shading_forward")
+        if no_alloc:
+            self._check(self.lib.art_shading_forward_noalloc(self._h, C, N, H, W, _tptr(Fc), _tptr(out)),
+                        "art_shading_forward_noalloc")
+        else:
+            self._check(self.lib.art_shading_forward(self._h, C, N, H, W, _tptr(Fc), _tptr(out)),
+                        "art_shading_forward")
         return out
 
     # ---- training step ----------------------------------------------------------------

@@ -19,6 +19,7 @@ ART_TIMING = 2
 ART_PROPOSAL_MARGIN_H = 2.0
 ART_PROPOSAL_NEAR_ONLY = 4
 ART_REUSE_BUILD = 8
+ART_SHADING_NOALLOC_BYTES = 100663296
 
 STATUS_NAMES = {0: "ART_OK", -1: "ART_EINVAL", -2: "ART_ENOMEM", -3: "ART_EDEVICE",
                 -4: "ART_ESTATE", -5: "ART_EUNSUPPORTED"}
@@ -51,6 +52,7 @@ SIGNATURES = [
     ("art_shading_param_count", _L, [_I]),
     ("art_shading_set_weights", _I, [_P, _I, _L, _P]),
     ("art_shading_forward", _I, [_P, _I, _I, _I, _I, _P, _P]),
+    ("art_shading_forward_noalloc", _I, [_P, _I, _I, _I, _I, _P, _P]),
     ("art_vrt", _I, [_P, _I, _I, _P, _F, _U, _P, ctypes.POINTER(ctypes.c_double)]),
     ("art_query", _I, [_P, _I, _U, _L, _P, _P]),
     ("art_flut_adam", _I, [_P, _L, _P, _P, _P, _P, _I, _F, _F, _F, _F, _F]),

@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -767,7 +768,55 @@ constexpr ShadeLayer kShade[kShadeLayers] = {
 };
 inline int shade_cin(int l, int C) { return l == 0 ? C : kShade[l].cin_a + kShade[l].cin_b; }
 inline int shade_cin_pad(int l) { return l == 0 ? 32 : kShade[l].cin_a + kShade[l].cin_b; }
+
+// Activation buffers of the network for HW level-0 pixels (halves, each
+// buffer 256-byte aligned): level 0: X, T0, E0 (32 ch); level 1: P0 (32), T1,
+// E1 (64); level 2: P1 (64), T2, E2 (128); level 3: P2 (128), T3, B (256).
+// 166 halves per pixel in all.
+constexpr int kShadeBufs = 12;
+inline size_t shade_layout(size_t HW, size_t off[kShadeBufs]) {
+    const size_t sz[kShadeBufs] = {HW * 32, HW * 32, HW * 32, HW / 4 * 32, HW / 4 * 64, HW / 4 * 64,
+                                   HW / 16 * 64, HW / 16 * 128, HW / 16 * 128, HW / 64 * 128, HW / 64 * 256,
+                                   HW / 64 * 256};
+    size_t tot = 0;
+    for (int i = 0; i < kShadeBufs; ++i) {
+        off[i] = tot;
+        tot += (sz[i] + 127) / 128 * 128;
+    }
+    return tot;
+}
 }  // namespace art
+
+// Fixed activation array of art_shading_forward_noalloc: every GPU the library
+// runs on holds one copy from the code object's load until the process ends.
+// In host code `scratch` is only a stand-in for the symbol: its device address
+// on each GPU comes from hipGetSymbolAddress (fixed_scratch_address), and only
+// that address is passed to kernels.
+static __device__ __align__(256) uint16_t scratch[ART_SHADING_NOALLOC_BYTES / 2];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_fixed_mu;
+void* g_fixed_addr[kMaxDevices] = {};
+
+// Device address of the fixed array on `device`, resolved once per device with
+// that device current.
+hipError_t fixed_scratch_address(int device, void** out) {
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_fixed_mu);
+    if (!g_fixed_addr[device]) {
+        DeviceGuard g(device);
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_fixed_addr[device] = p;
+    }
+    *out = g_fixed_addr[device];
+    return hipSuccess;
+}
+}  // namespace
 
 // ---------------------------------------------------------------------------
 // ABI
@@ -785,10 +834,16 @@ art_status art_create(int device, void* stream, art_ctx** out) {
         return ART_EDEVICE;
     }
     if (device < 0 || device >= count) return ART_EINVAL;
+    void* fixed = nullptr;
+    if (fixed_scratch_address(device, &fixed) != hipSuccess) {
+        (void)hipGetLastError();
+        return ART_EDEVICE;
+    }
     art_ctx* ctx = new (std::nothrow) art_ctx();
     if (!ctx) return ART_ENOMEM;
     ctx->device = device;
     ctx->stream = static_cast<hipStream_t>(stream);
+    ctx->shade_fixed = fixed;
     *out = ctx;
     return ART_OK;
 }
@@ -1139,28 +1194,20 @@ art_status art_shading_set_weights(art_ctx* ctx, int C, int64_t count, const flo
     return ART_OK;
 }
 
-art_status art_shading_forward(art_ctx* ctx, int C, int N, int H, int W, const float* F, float* out) {
-    if (!ctx) return ART_EINVAL;
+}  // extern "C"
+
+namespace {
+art_status shade_check(art_ctx* ctx, int C, int N, int H, int W, const float* F, const float* out) {
     if (ctx->shade_C == 0 || ctx->shade_C != C) return fail(ctx, ART_ESTATE, "no shading weights for this C");
     if (N < 1 || H < 8 || W < 8 || (H % 8) || (W % 8)) return fail(ctx, ART_EINVAL, "N >= 1; H, W multiples of 8");
     if (!F || !out) return fail(ctx, ART_EINVAL, "F / out is NULL");
-    DeviceGuard g(ctx->device);
+    return ART_OK;
+}
+
+// The network on N maps with its activations at `base` (laid out by shade_layout).
+art_status shade_run(art_ctx* ctx, int C, int N, int H, int W, const float* F, float* out, uint16_t* base,
+                     const size_t off[kShadeBufs]) {
     hipStream_t st = ctx->stream;
-    const size_t HW = (size_t)N * H * W;   // pixels of level 0 over all images
-    // activation buffers (halves): level 0: X, T0, E0 (32 ch); level 1: P0 (32), T1, E1 (64);
-    // level 2: P1 (64), T2, E2 (128); level 3: P2 (128), T3, B (256)
-    const size_t sz[12] = {HW * 32, HW * 32, HW * 32, HW / 4 * 32, HW / 4 * 64, HW / 4 * 64,
-                           HW / 16 * 64, HW / 16 * 128, HW / 16 * 128, HW / 64 * 128, HW / 64 * 256, HW / 64 * 256};
-    size_t off[12], tot = 0;
-    for (int i = 0; i < 12; ++i) {
-        off[i] = tot;
-        tot += (sz[i] + 127) / 128 * 128;
-    }
-    {
-        const art_status ra = ensure_bufs(ctx, {{&ctx->shade_act, tot * 2}});
-        if (ra != ART_OK) return ra;
-    }
-    uint16_t* base = ctx->shade_act.as<uint16_t>();
     uint16_t* X = base + off[0];
     uint16_t* T0 = base + off[1];
     uint16_t* E0 = base + off[2];
@@ -1224,6 +1271,37 @@ art_status art_shading_forward(art_ctx* ctx, int C, int N, int H, int W, const f
         e = launch_head(X, N, H, W, ctx->shade_head.as<float>(), ctx->shade_head.as<float>() + 128, out, st);
     if (e != hipSuccess) return hip_fail(ctx, e, "shading network");
     return ART_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+art_status art_shading_forward(art_ctx* ctx, int C, int N, int H, int W, const float* F, float* out) {
+    if (!ctx) return ART_EINVAL;
+    art_status rc = shade_check(ctx, C, N, H, W, F, out);
+    if (rc != ART_OK) return rc;
+    DeviceGuard g(ctx->device);
+    size_t off[kShadeBufs];
+    const size_t tot = shade_layout((size_t)N * H * W, off);
+    rc = ensure_bufs(ctx, {{&ctx->shade_act, tot * 2}});
+    if (rc != ART_OK) return rc;
+    return shade_run(ctx, C, N, H, W, F, out, ctx->shade_act.as<uint16_t>(), off);
+}
+
+art_status art_shading_forward_noalloc(art_ctx* ctx, int C, int N, int H, int W, const float* F, float* out) {
+    if (!ctx) return ART_EINVAL;
+    art_status rc = shade_check(ctx, C, N, H, W, F, out);
+    if (rc != ART_OK) return rc;
+    size_t off[kShadeBufs];
+    const size_t tot = shade_layout((size_t)N * H * W, off);
+    if (tot * 2 > (size_t)ART_SHADING_NOALLOC_BYTES)
+        return fail(ctx, ART_EINVAL, "the batch needs " + std::to_string(tot * 2) +
+                                         " bytes of activations, above the fixed array of " +
+                                         std::to_string((size_t)ART_SHADING_NOALLOC_BYTES) + " bytes");
+    if (!ctx->shade_fixed) return fail(ctx, ART_EDEVICE, "fixed activation array not resolved");
+    DeviceGuard g(ctx->device);
+    return shade_run(ctx, C, N, H, W, F, out, static_cast<uint16_t*>(ctx->shade_fixed), off);
 }
 
 art_status art_vrt(art_ctx* ctx, int C, art_dtype dtype, const void* feat, float lambda_vrt, unsigned flags,

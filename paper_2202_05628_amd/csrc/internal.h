@@ -135,6 +135,7 @@ struct art_ctx {
     int shade_C = 0;
     art::DevBuf shade_w, shade_b, shade_head;
     art::DevBuf shade_act;
+    void* shade_fixed = nullptr;   // device address of the fixed activation array on this device
     bool has_skin = false;
     int max_bone = -1;
 
