@@ -97,6 +97,8 @@ def parse():
     ap.add_argument("--f2-tau", type=float, default=-1.0)
     ap.add_argument("--err-poses", type=int, default=4, help="poses on which the proposal error is measured")
     ap.add_argument("--no-forms", action="store_true", help="skip the BF16-storage and adjoint legs")
+    ap.add_argument("--leg", choices=["bf16", "adjoint", "train", "proposal"], default=None,
+                    help="run only this form and print its record (profiling)")
     return ap.parse_args()
 
 
@@ -455,6 +457,11 @@ def main():
 
     import paper_2202_05628_amd as art
     import scenegen as sg
+
+    if args.leg:
+        legs = {"bf16": bf16_leg, "adjoint": adjoint_leg, "train": train_leg, "proposal": proposal_leg}
+        print(json.dumps({args.leg: legs[args.leg](args, art, sg, torch)}), flush=True)
+        return
 
     cfg = sg.CONFIGS[args.config]
     scene = sg.make_scene(cfg)

@@ -52,6 +52,12 @@ constexpr int kPrefPitch = kStage + 2 * ART_LDS_PAD;
 #endif
 
 constexpr int kStepsPerRound = ART_STEPS_PER_ROUND;
+// The adjoint's workloads (one pose, a few views) hold too few tiles to hide
+// the memory latency of a round, so its lanes may cross several empty cells
+// per round to reach their next sample.
+#ifndef ART_STEPS_PER_ROUND_ADJ
+#define ART_STEPS_PER_ROUND_ADJ 1
+#endif
 
 // 1: conservative FP32 slab test in the brick pre-pass (phase 1)
 #ifndef ART_PHASE1_F32
@@ -283,19 +289,35 @@ __device__ inline void root_span(const R* d, const R* q, const R* inv, R h, int 
 #ifndef ART_RENDER_WAVES_PER_EU_F32
 #define ART_RENDER_WAVES_PER_EU_F32 5   // FP32 geometry (the BF16 form): fewer registers, two more waves
 #endif
-// Adjoint gradient scatter through LDS: each round the lanes with a sample
-// stage (leaf, w); the feature gradients w g_c are then added with lanes
-// mapped to (sample, channel), so the 16 lanes of one atomic instruction
-// that share a sample update consecutive words of one leaf row (one cache
-// line) instead of 16 lanes hitting 16 different lines.
+// Adjoint gradient scatter through LDS.  Each round the lanes with a sample
+// append (leaf, w, dL/dsigma, lane) to a record buffer (ballot + prefix
+// count); when the buffer may not hold another round, and at the end of the
+// tile, the wave adds the records' gradients with atomics in one burst: the
+// density gradients one record per lane, the feature gradients w g_c with
+// lanes mapped to (record, channel), so the C lanes of one atomic
+// instruction that share a record update consecutive words of one leaf row
+// (one cache line).  Batching matters because the vector-memory counter
+// retires in order: a load issued after an atomic cannot be waited for
+// without waiting for the atomic, so atomics issued every round would put
+// their round trip into every round of the traversal.
 #ifndef ART_ADJ_LINES
 #define ART_ADJ_LINES 1
 #endif
+#ifndef ART_ADJ_ROUNDS
+#define ART_ADJ_ROUNDS 8   // rounds of records between bursts
+#endif
+constexpr int kAdjRec = 64 * ART_ADJ_ROUNDS;
+// Row pitch of a ray's dL/dF in LDS: 16-byte rows, offset so that the rows of
+// consecutive lanes start in different banks.
+template <int C>
+constexpr int kAdjPitch = C + 4;
 template <int C>
 struct AdjLds {
-    float g[64 * C];     // dL/dF of each lane's ray
-    uint32_t leaf[64];   // leaf of the lane's sample this round (kInvalidKey: none)
-    float w[64];
+    float g[64 * kAdjPitch<C>];   // dL/dF of each lane's ray
+    uint32_t leaf[kAdjRec];       // records: winner leaf of a composited sample,
+    float w[kAdjRec];             // its weight,
+    float ds[kAdjRec];            // its density gradient
+    uint8_t src[kAdjRec];         // and the lane (ray) it belongs to
 };
 
 // The adjoint's LDS staging (only the adjoint kernels allocate it).
@@ -307,6 +329,24 @@ __device__ inline AdjLds<C>* adj_lds() {
     } else {
         return nullptr;
     }
+}
+
+// Add the gradients of the n buffered records (wave-uniform n) and empty the
+// buffer.
+template <int C>
+__device__ inline void adj_flush(const RArgs& a, AdjLds<C>* s_adj, int& n, int lane) {
+    wave_sync();
+    for (int i = lane; i < n; i += 64) unsafeAtomicAdd(&a.d_sigma[s_adj->leaf[i]], s_adj->ds[i]);
+    constexpr int SPI = 64 / C;   // records per atomic instruction
+    const int cc = lane % C, sub = lane / C;
+    for (int s0 = 0; s0 < n; s0 += SPI) {   // wave-uniform bound
+        const int sm = s0 + sub;
+        if (sm < n)
+            unsafeAtomicAdd(&a.d_leaf_feat[(size_t)s_adj->leaf[sm] * C + cc],
+                            s_adj->w[sm] * s_adj->g[(int)s_adj->src[sm] * kAdjPitch<C> + cc]);
+    }
+    wave_sync();   // the records are read before the buffer is reused
+    n = 0;
 }
 
 // Run statistics of one wave (in its workgroup's LDS, written by lane 0 only),
@@ -424,29 +464,28 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
     R t_first = 0, t_last = 0;   // MODE 3: entry of the first / exit of the last sample
     float zdep = INFINITY;       // MODE 5: depth
     bool cdone = false;          // MODE 5: compositing stopped, the depth search goes on
-    // adjoint state
-    float g[C], Ff[C], P[C];
-    float gA = 0.0f, Tfin = 0.0f;
+    int adj_n = 0;   // MODE 1: records in the LDS buffer (wave-uniform)
+    // adjoint state.  With g = dL/dF of the ray, the density gradient of
+    // sample i needs g . (T_{i+1} f_i - (F - P_i)), P_i = sum_{k<=i} w_k f_k;
+    // it is kept as scalars: g . (F - P_i) = gF - gP_i with gF = g . F (from
+    // the forward's map) and gP_i = sum_{k<=i} w_k (g . f_k).
+    float g[C];
+    float gA = 0.0f, Tfin = 0.0f, gF = 0.0f, gP = 0.0f;
     if constexpr (MODE == 1) {
 #pragma unroll
-        for (int c = 0; c < C; ++c) {
-            g[c] = 0.0f;
-            Ff[c] = 0.0f;
-            P[c] = 0.0f;
-        }
+        for (int c = 0; c < C; ++c) g[c] = 0.0f;
         if (active) {
 #pragma unroll
             for (int c = 0; c < C; ++c) {
                 g[c] = a.d_feat[(map * C + c) * HW + pix];
-                Ff[c] = a.fwd_feat[(map * C + c) * HW + pix];
+                gF = __fmaf_rn(g[c], a.fwd_feat[(map * C + c) * HW + pix], gF);
             }
             gA = a.d_alpha ? a.d_alpha[map * HW + pix] : 0.0f;
             Tfin = a.fwd_tfinal[map * HW + pix];
         }
 #if ART_ADJ_LINES
 #pragma unroll
-        for (int c = 0; c < C; ++c) s_adj->g[lane * C + c] = g[c];
-        s_adj->leaf[lane] = kInvalidKey;
+        for (int c = 0; c < C; ++c) s_adj->g[lane * kAdjPitch<C> + c] = g[c];
         wave_sync();
 #endif
     }
@@ -597,6 +636,9 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
 #pragma unroll
         for (int c = 0; c < C; ++c) fA[c] = 0.0f;
         uint32_t domA = 0;   // MODE 6: dominant bone of the sample's leaf
+        bool adj_has = false;   // MODE 1: this lane composited a sample this round
+        uint32_t adj_leaf = 0;
+        float adj_w = 0.0f, adj_ds = 0.0f;
         while (true) {
             const bool more = active && (inb || todo != 0ull);
             if (__ballot(more || hasA || hasI) == 0ull) break;
@@ -608,7 +650,8 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
             double dxB = 0.0;
             R sB0 = 0, sB1 = 0;
             int guard = 0;
-            while (active && !hasB && (inb || todo != 0ull) && guard < kStepsPerRound) {
+            while (active && !hasB && (inb || todo != 0ull) &&
+                   guard < (MODE == 1 ? ART_STEPS_PER_ROUND_ADJ : kStepsPerRound)) {
                 ++guard;
                 ++nsteps;
                 if (!inb) {
@@ -777,18 +820,32 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
                 const float w = T * al;
                 const float Tn = __fmaf_rn(-T, al, T);
                 if constexpr (MODE == 1) {
+                    float gf = 0.0f;   // g . f_i (g read back from LDS: fewer live registers)
+#if ART_ADJ_LINES
+                    const float4* g4 = reinterpret_cast<const float4*>(&s_adj->g[lane * kAdjPitch<C>]);
 #pragma unroll
-                    for (int c = 0; c < C; ++c) P[c] = __fmaf_rn(w, fA[c], P[c]);
-                    float acc = 0.0f;
+                    for (int q = 0; q < C / 4; ++q) {
+                        const float4 gv = g4[q];
+                        gf = __fmaf_rn(gv.x, fA[4 * q + 0], gf);
+                        gf = __fmaf_rn(gv.y, fA[4 * q + 1], gf);
+                        gf = __fmaf_rn(gv.z, fA[4 * q + 2], gf);
+                        gf = __fmaf_rn(gv.w, fA[4 * q + 3], gf);
+                    }
+#else
 #pragma unroll
-                    for (int c = 0; c < C; ++c) acc += g[c] * (Tn * fA[c] - (Ff[c] - P[c]));
+                    for (int c = 0; c < C; ++c) gf = __fmaf_rn(g[c], fA[c], gf);
+#endif
+                    gP = __fmaf_rn(w, gf, gP);
+                    const float acc = Tn * gf - (gF - gP);
                     const float ds = dlA * (acc + gA * Tfin);
                     const uint32_t leaf = winA;
-                    unsafeAtomicAdd(&a.d_sigma[leaf], ds);
 #if ART_ADJ_LINES
-                    s_adj->leaf[lane] = leaf;
-                    s_adj->w[lane] = w;
+                    adj_leaf = leaf;
+                    adj_w = w;
+                    adj_ds = ds;
+                    adj_has = true;
 #else
+                    unsafeAtomicAdd(&a.d_sigma[leaf], ds);
 #pragma unroll
                     for (int c = 0; c < C; ++c) unsafeAtomicAdd(&a.d_leaf_feat[(size_t)leaf * C + c], w * g[c]);
 #endif
@@ -845,23 +902,20 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
             }
 #if ART_ADJ_LINES
             if constexpr (MODE == 1) {
-                const uint64_t staged = __ballot(s_adj->leaf[lane] != kInvalidKey);
+                const uint64_t staged = __ballot(adj_has);
                 if (staged) {
-                    wave_sync();
-                    constexpr int SPI = 64 / C;   // samples per atomic instruction
-                    const int cc = lane % C, sub = lane / C;
-                    constexpr uint64_t kGroup = SPI >= 64 ? ~0ull : ((1ull << SPI) - 1ull);
-#pragma unroll 4
-                    for (int s0 = 0; s0 < 64; s0 += SPI) {
-                        if (((staged >> s0) & kGroup) == 0ull) continue;   // wave-uniform
-                        const int sm = s0 + sub;
-                        const uint32_t lf = s_adj->leaf[sm];
-                        if (lf != kInvalidKey)
-                            unsafeAtomicAdd(&a.d_leaf_feat[(size_t)lf * C + cc], s_adj->w[sm] * s_adj->g[sm * C + cc]);
+                    if (adj_has) {   // append this round's samples to the records
+                        const int slotc = adj_n + (int)__builtin_amdgcn_mbcnt_hi(
+                                                     (uint32_t)(staged >> 32),
+                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)staged, 0u));
+                        s_adj->leaf[slotc] = adj_leaf;
+                        s_adj->w[slotc] = adj_w;
+                        s_adj->ds[slotc] = adj_ds;
+                        s_adj->src[slotc] = (uint8_t)lane;
                     }
-                    wave_sync();
-                    s_adj->leaf[lane] = kInvalidKey;
-                    wave_sync();
+                    adj_n += __popcll(staged);
+                    adj_has = false;
+                    if (adj_n > kAdjRec - 64) adj_flush<C>(a, s_adj, adj_n, lane);
                 }
             }
 #endif
@@ -906,6 +960,12 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
         wave_sync();
     }
     }   // passes
+
+#if ART_ADJ_LINES
+    if constexpr (MODE == 1) {
+        if (adj_n > 0) adj_flush<C>(a, s_adj, adj_n, lane);
+    }
+#endif
 
     // ---- outputs -----------------------------------------------------------------
     if constexpr (MODE == 3) {
