@@ -30,8 +30,14 @@ CFLAGS = [
 
 
 # per-file extra flags: the proposal network's inference keeps its matrix-core
-# accumulators in ordinary VGPRs (no AGPR copies before the BF16 conversions)
-EXTRA = {"k_mlp.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+# accumulators in ordinary VGPRs (no AGPR copies before the BF16 conversions);
+# the compositing kernels run with the IEEE mode bit off, so a float min / max
+# needs no NaN-quieting operand copies (they see no NaN: ray parameters and
+# cell bounds are finite or +inf, and the FLUT densities are checked before
+# the launch; results are unchanged for non-NaN values)
+_RENDER = ["-mno-amdgpu-ieee", "-fno-honor-nans"]
+EXTRA = {"k_mlp.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+         **{f"render_c{c}.hip": _RENDER for c in (4, 8, 16, 32)}}
 
 
 def sources():

@@ -174,13 +174,54 @@ __device__ inline void load_feat(const void* pfeat, size_t foff, float* f) {
     }
 }
 
-// Density of FLUT row `row` and the C features at element offset `foff`.
+// A FLUT feature row as loaded: C FP32 words, or C / 2 words of two BF16
+// values each (channel 2k in the low half).  The BF16 row is widened to FP32
+// where it is used, so a prefetched row holds half the registers and its load
+// is waited for only when the sample is composited.
 template <int C, int ST>
-__device__ inline void load_sample(const void* psig, const void* pfeat, uint32_t row, size_t foff, float& sg,
-                                   float* f) {
-    if constexpr (ST == 0) sg = reinterpret_cast<const float*>(psig)[row];
-    else sg = bf16_to_f32(reinterpret_cast<const uint16_t*>(psig)[row]);
-    load_feat<C, ST>(pfeat, foff, f);
+constexpr int kRowWords = ST == 0 ? C : C / 2;
+
+template <int ST>
+__device__ inline float row_at(const uint32_t* w, int c) {
+    if constexpr (ST == 0) return __uint_as_float(w[c]);
+    else return __uint_as_float((c & 1) ? (w[c >> 1] & 0xFFFF0000u) : (w[c >> 1] << 16));
+}
+
+// Density of FLUT row `row` (as FP32) and the raw feature words at element
+// offset `foff`.
+template <int C, int ST>
+__device__ inline void load_sample_raw(const void* psig, const void* pfeat, uint32_t row, size_t foff, float& sg,
+                                       uint32_t* w) {
+    if constexpr (ST == 0) {
+        sg = reinterpret_cast<const float*>(psig)[row];
+        const uint4* p = reinterpret_cast<const uint4*>(reinterpret_cast<const float*>(pfeat) + foff);
+#pragma unroll
+        for (int q = 0; q < C / 4; ++q) {
+            const uint4 v = p[q];
+            w[4 * q + 0] = v.x;
+            w[4 * q + 1] = v.y;
+            w[4 * q + 2] = v.z;
+            w[4 * q + 3] = v.w;
+        }
+    } else {
+        sg = bf16_to_f32(reinterpret_cast<const uint16_t*>(psig)[row]);
+        const uint16_t* base = reinterpret_cast<const uint16_t*>(pfeat) + foff;
+        if constexpr (C % 8 == 0) {
+            const uint4* p = reinterpret_cast<const uint4*>(base);
+#pragma unroll
+            for (int q = 0; q < C / 8; ++q) {
+                const uint4 v = p[q];
+                w[4 * q + 0] = v.x;
+                w[4 * q + 1] = v.y;
+                w[4 * q + 2] = v.z;
+                w[4 * q + 3] = v.w;
+            }
+        } else {
+            const uint2 v = *reinterpret_cast<const uint2*>(base);
+            w[0] = v.x;
+            w[1] = v.y;
+        }
+    }
 }
 
 // Real spherical-harmonic basis of degree <= 2 (Eq. 2) at the unit direction
@@ -226,6 +267,18 @@ __device__ inline float sample_alpha(float tau) {
 __device__ inline uint32_t spread3_small(uint32_t v) {   // 3-bit x -> bits 0, 3, 6
     return (v & 1u) | ((v & 2u) << 2) | ((v & 4u) << 4);
 }
+
+// 1: the in-brick Morton index of a cell comes from a 512-entry LDS table
+// indexed by x + 8 y + 64 z (one LDS read instead of about twenty bit
+// operations per partition step; the compositing kernels are bound by their
+// vector instruction issue).  Only the FP64-geometry kernels use it: the
+// FP32-geometry ones run 20 single-wave workgroups per CU, whose LDS the
+// table would push to the CU's limit (measured slower).
+#ifndef ART_MORTON_LUT
+#define ART_MORTON_LUT 1
+#endif
+template <typename R>
+constexpr bool kMortonLut = ART_MORTON_LUT && sizeof(R) == 8;
 
 // Ray parameter of lattice plane k on one axis: (-1 + k h - o) / d, written with
 // q = 1 + o and the reciprocal of d.
@@ -361,6 +414,7 @@ template <int C, int ST, typename R, int MODE>
 __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, int lane, WaveStats& ws,
                                    uint32_t (*s_mask)[16][kMaskPitch],
                                    uint16_t (*s_pref)[16][kPrefPitch], uint32_t (*s_row)[kStage],
+                                   const uint16_t* s_mlut,
                                    uint32_t (*s_coord)[kStage], float* s_rot, AdjLds<C>* s_adj) {
     constexpr int wv = 0;
     const int pvi = (int)(item / (uint32_t)a.TPV);   // pose-in-launch * V + view
@@ -632,9 +686,9 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
         float dlI = 0.0f;
         double dxI = 0.0;
         R sI0 = 0, sI1 = 0;
-        float fA[C];
+        uint32_t fA[kRowWords<C, ST>];   // the sample's feature row as loaded
 #pragma unroll
-        for (int c = 0; c < C; ++c) fA[c] = 0.0f;
+        for (int c = 0; c < kRowWords<C, ST>; ++c) fA[c] = 0u;
         uint32_t domA = 0;   // MODE 6: dominant bone of the sample's leaf
         bool adj_has = false;   // MODE 1: this lane composited a sample this round
         uint32_t adj_leaf = 0;
@@ -725,8 +779,12 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
                 s1 = fmax(s1, s);
                 const int l0 = kp[0] - lo3[0], l1 = kp[1] - lo3[1], l2 = kp[2] - lo3[2];
                 if (s1 > s && (unsigned)l0 < 8u && (unsigned)l1 < 8u && (unsigned)l2 < 8u) {
-                    const uint32_t m9 = spread3_small((uint32_t)l0) | (spread3_small((uint32_t)l1) << 1) |
-                                        (spread3_small((uint32_t)l2) << 2);
+                    uint32_t m9;
+                    if constexpr (kMortonLut<R>)
+                        m9 = s_mlut[l0 + 8 * l1 + 64 * l2];
+                    else
+                        m9 = spread3_small((uint32_t)l0) | (spread3_small((uint32_t)l1) << 1) |
+                             (spread3_small((uint32_t)l2) << 2);
                     const uint32_t wd = m9 >> 5, bit = m9 & 31u;
                     const uint32_t mw = s_mask[wv][wd][slot];
                     if ((mw >> bit) & 1u) {
@@ -801,7 +859,7 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
                 const float al = sample_alpha(doA ? sgA * dlA : 0.0f);
                 const float w = T * al;
 #pragma unroll
-                for (int c = 0; c < C; ++c) F[c] = __fmaf_rn(w, fA[c], F[c]);
+                for (int c = 0; c < C; ++c) F[c] = __fmaf_rn(w, row_at<ST>(fA, c), F[c]);
                 Aacc += w;
                 T = __fmaf_rn(-T, al, T);
                 nsamp += doA ? 1 : 0;
@@ -826,14 +884,14 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
 #pragma unroll
                     for (int q = 0; q < C / 4; ++q) {
                         const float4 gv = g4[q];
-                        gf = __fmaf_rn(gv.x, fA[4 * q + 0], gf);
-                        gf = __fmaf_rn(gv.y, fA[4 * q + 1], gf);
-                        gf = __fmaf_rn(gv.z, fA[4 * q + 2], gf);
-                        gf = __fmaf_rn(gv.w, fA[4 * q + 3], gf);
+                        gf = __fmaf_rn(gv.x, row_at<ST>(fA, 4 * q + 0), gf);
+                        gf = __fmaf_rn(gv.y, row_at<ST>(fA, 4 * q + 1), gf);
+                        gf = __fmaf_rn(gv.z, row_at<ST>(fA, 4 * q + 2), gf);
+                        gf = __fmaf_rn(gv.w, row_at<ST>(fA, 4 * q + 3), gf);
                     }
 #else
 #pragma unroll
-                    for (int c = 0; c < C; ++c) gf = __fmaf_rn(g[c], fA[c], gf);
+                    for (int c = 0; c < C; ++c) gf = __fmaf_rn(g[c], row_at<ST>(fA, c), gf);
 #endif
                     gP = __fmaf_rn(w, gf, gP);
                     const float acc = Tn * gf - (gF - gP);
@@ -859,7 +917,7 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
                                  Rm[2] * dx + Rm[5] * dy + Rm[8] * dz, Y);
                         const float w0 = w * Y[0];
 #pragma unroll
-                        for (int c = 0; c < C; ++c) F[c] = __fmaf_rn(w0, fA[c], F[c]);
+                        for (int c = 0; c < C; ++c) F[c] = __fmaf_rn(w0, row_at<ST>(fA, c), F[c]);
 #pragma unroll
                         for (int hb = 1; hb < 9; ++hb) {
                             if (hb < a.sh_H) {
@@ -872,7 +930,7 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
                         }
                     } else {
 #pragma unroll
-                        for (int c = 0; c < C; ++c) F[c] = __fmaf_rn(w, fA[c], F[c]);
+                        for (int c = 0; c < C; ++c) F[c] = __fmaf_rn(w, row_at<ST>(fA, c), F[c]);
                     }
                     Aacc += w;
                     if constexpr (MODE == 2) {
@@ -931,8 +989,8 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
             sA0 = sI0;
             sA1 = sI1;
             winA = hasA ? winI : 0u;
-            load_sample<C, ST>(a.sigma, a.feat, winA, (size_t)winA * (MODE == 6 ? (size_t)a.sh_H * C : (size_t)C),
-                               sgA, fA);
+            load_sample_raw<C, ST>(a.sigma, a.feat, winA,
+                                   (size_t)winA * (MODE == 6 ? (size_t)a.sh_H * C : (size_t)C), sgA, fA);
             if constexpr (MODE == 6) domA = a.dom_bone[winA];
             hasI = hasB && active;
             dlI = dlB;
@@ -951,8 +1009,8 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
                 sA1 = sB1;
                 // the FLUT row of the cell's collision winner
                 winA = occ_win[rowA];
-                load_sample<C, ST>(a.sigma, a.feat, winA, (size_t)winA * (MODE == 6 ? (size_t)a.sh_H * C : (size_t)C),
-                               sgA, fA);
+                load_sample_raw<C, ST>(a.sigma, a.feat, winA,
+                                       (size_t)winA * (MODE == 6 ? (size_t)a.sh_H * C : (size_t)C), sgA, fA);
             if constexpr (MODE == 6) domA = a.dom_bone[winA];
             }
 #endif
@@ -1029,10 +1087,17 @@ void k_render(RArgs a) {
     __shared__ uint32_t s_row[1][kStage];
     __shared__ uint32_t s_coord[1][kStage];
     __shared__ float s_rot[MODE == 6 ? kMaxBonesSH * 9 : 1];
+    __shared__ uint16_t s_mlut[kMortonLut<R> ? 512 : 1];
     AdjLds<C>* s_adj = adj_lds<C, MODE>();
     const int lane = threadIdx.x & 63;
     // invalid densities in the FLUT: nothing is rendered (the call reports it)
     if (a.stats[kStatBadSigma] != 0ull) return;
+    if constexpr (kMortonLut<R>) {
+        for (int e = lane; e < 512; e += kWave)
+            s_mlut[e] = (uint16_t)(spread3_small((uint32_t)e & 7u) | (spread3_small(((uint32_t)e >> 3) & 7u) << 1) |
+                                   (spread3_small((uint32_t)e >> 6) << 2));
+        wave_sync();
+    }
     const uint32_t n_items = *a.n_items;
     __shared__ WaveStats ws;
     if (lane == 0)
@@ -1056,8 +1121,8 @@ void k_render(RArgs a) {
             idx = beg + (uint32_t)__shfl((int)idx, 0, kWave);
             if (idx >= end) break;
             for (uint32_t t = 0; t < (uint32_t)ART_TILES_PER_GRAB && idx + t < end; ++t) {
-                render_tile<C, ST, R, MODE>(a, a.items[idx + t], idx + t, lane, ws, s_mask, s_pref, s_row, s_coord,
-                                            s_rot, s_adj);
+                render_tile<C, ST, R, MODE>(a, a.items[idx + t], idx + t, lane, ws, s_mask, s_pref, s_row, s_mlut,
+                                            s_coord, s_rot, s_adj);
                 wave_sync();
             }
         }
