@@ -376,6 +376,20 @@ art_status art_vrt(art_ctx* ctx, int C, art_dtype dtype, const void* feat, float
 art_status art_query(art_ctx* ctx, int pose, unsigned flags, int64_t n, const double* points, int32_t* leaf);
 
 /*
+ * Map loss of the FLUT training loop (Section 3.1, "Training", with the
+ * shading network left out: the rendered maps are compared with target maps
+ * directly, reading A23) over R = rays pixels:
+ * L = 1/(2R) [sum (F - F*)^2 + sum (A - A*)^2], the A term only when
+ * A_target is not NULL.  F, F_target, d_feat: device float32 [n_feat];
+ * A, A_target, d_alpha: device float32 [rays].  Writes dL/dF = (F - F*) / R
+ * and dL/dA = (A - A*) / R; *loss (host) receives L, summed in FP64 in a
+ * fixed order.  Synchronous.
+ * Errors: ART_EINVAL (n_feat < 0, rays < 1, a NULL buffer that is needed).
+ */
+art_status art_map_loss(art_ctx* ctx, int64_t n_feat, int64_t rays, const float* F, const float* F_target,
+                        const float* A, const float* A_target, float* d_feat, float* d_alpha, double* loss);
+
+/*
  * One Adam update (step counts from 1, bias-corrected) of a device float32
  * FLUT array of `count` entries from its gradient, moments m and v updated in
  * place, then param = max(param, lower) (pass -INFINITY for none; 0 keeps
@@ -452,6 +466,38 @@ art_status art_proposal_grad(art_ctx* ctx, int64_t n, const float* od, const int
 art_status art_proposal_train(art_ctx* ctx, int64_t n, const float* od, const int32_t* pose, const float* target,
                               int64_t batch, int steps, float lr, float beta1, float beta2, float eps,
                               float* loss_log);
+
+/*
+ * Start margin of the guided traversal for the current network, from
+ * held-out rays (the arrays of art_proposal_gather): for each ray whose label
+ * holds a sample (u_near <= u_far), its late start in leaf edges h,
+ * (predicted u_near - labelled u_near) * (t_b - t_a) / h with [t_a, t_b] the
+ * ray's span inside the posed root ([-1, 1]^3, t_a >= 0); *margin_h (host)
+ * receives the `quantile` of these values (linear interpolation between
+ * order statistics), at least floor_h; floor_h when no ray has a sample.
+ * A margin at the 0.999 quantile covers all but 0.1 % of the late starts on
+ * the held-out rays.  Synchronous.
+ * Errors: as art_proposal_forward; ART_EINVAL for quantile outside [0, 1] or
+ * a negative or non-finite floor_h.
+ */
+art_status art_proposal_calibrate(art_ctx* ctx, int64_t n, const float* od, const int32_t* pose, const float* target,
+                                  float quantile, float floor_h, float* margin_h);
+
+/*
+ * Save (save != 0) or load the proposal network's training state: the FP32
+ * weights, both Adam moments and the Adam step count, so that training
+ * resumes where it stopped (the next art_proposal_train step continues the
+ * bias correction from the saved count and gives the same weights, bit for
+ * bit, as an uninterrupted run).  File (little-endian): the 8 bytes
+ * "ARTPROP1", int32 J, int32 0, int64 parameter count, int64 step, then the
+ * weights, the first and the second moments (FP32, the order of
+ * art_proposal_set_weights).  Loading checks the magic, J, the count, that
+ * every value is finite and the second moments are >= 0, and that nothing
+ * follows; on failure the context keeps its previous state.  Synchronous.
+ * Errors: ART_EINVAL (NULL path, I/O failure, a file that does not match),
+ * ART_ESTATE (no skeleton; save: no weights for the current skeleton).
+ */
+art_status art_proposal_io(art_ctx* ctx, int save, const char* path);
 
 /* ---------------------------------------------------------------------------
  * Inspection of intermediate results (parity tests, debugging)

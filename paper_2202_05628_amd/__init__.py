@@ -15,6 +15,7 @@ PyTorch only supplies device memory and the stream.
 from __future__ import annotations
 
 import ctypes
+import os
 from typing import Optional, Tuple
 
 import numpy as np
@@ -298,23 +299,22 @@ class Renderer:
     def calibrate_proposal_margin(self, od, pose, target, quantile: float = 0.999, floor_h: float = 2.0) -> float:
         """Margin (in leaf edges h) that covers the network's late starts on
         held-out rays: the `quantile` of (predicted - true) entry of the first
-        sample over the rays that have one, in units of h (at least floor_h)."""
-        pred = self.proposal_forward(od, pose).cpu().numpy().astype(np.float64)
-        tgt = target.cpu().numpy().astype(np.float64)
-        x = od.cpu().numpy().astype(np.float64)
-        hit = tgt[:, 0] <= tgt[:, 1]
-        if not hit.any():
-            return float(floor_h)
-        o, d = x[hit, :3], x[hit, 3:]
-        with np.errstate(divide="ignore", invalid="ignore"):
-            t0 = (-1.0 - o) / d
-            t1 = (1.0 - o) / d
-        lo = np.where(d != 0, np.minimum(t0, t1), -np.inf).max(axis=1)
-        hi = np.where(d != 0, np.maximum(t0, t1), np.inf).min(axis=1)
-        span = hi - np.maximum(lo, 0.0)
-        h = 1.0 / (1 << self.depth)
-        late = (pred[hit, 0] - tgt[hit, 0]) * span / h
-        return float(max(floor_h, np.quantile(late, quantile)))
+        sample over the rays that have one, in units of h (at least floor_h);
+        computed by the library (art_proposal_calibrate)."""
+        m = ctypes.c_float(0.0)
+        self._check(self.lib.art_proposal_calibrate(self._h, od.shape[0], _tptr(od.contiguous()),
+                                                    _tptr(pose.contiguous()), _tptr(target.contiguous()),
+                                                    float(quantile), float(floor_h), ctypes.byref(m)),
+                    "art_proposal_calibrate")
+        return float(m.value)
+
+    def save_proposal(self, path: str) -> None:
+        """Write the network's weights, Adam moments and step count (art_proposal_io)."""
+        self._check(self.lib.art_proposal_io(self._h, 1, os.fsencode(path)), "art_proposal_io")
+
+    def load_proposal(self, path: str) -> None:
+        """Read a state written by save_proposal; training resumes from it."""
+        self._check(self.lib.art_proposal_io(self._h, 0, os.fsencode(path)), "art_proposal_io")
 
     def proposal_train(self, od, pose, target, batch: int = 16384, steps: int = 1000, lr: float = 1e-3,
                        betas=(0.9, 0.999), eps: float = 1e-8) -> np.ndarray:
@@ -418,6 +418,30 @@ class Renderer:
                                            _tptr(v), int(step), float(lr), float(beta1), float(beta2), float(eps),
                                            float(lower)), "art_flut_adam")
 
+    def map_loss(self, F, F_target, A=None, A_target=None):
+        """L2 map loss 1/(2R) [sum (F - F*)^2 + sum (A - A*)^2] over the R rays of
+        the current poses and cameras (A term when A_target is given) and its
+        gradients (art_map_loss): (loss, dL/dF, dL/dA or None)."""
+        torch = self._torch
+        R = self.P * self.V * self.H * self.W
+        F = F.contiguous()
+        Ft = F_target.contiguous().float()
+        if Ft.shape != F.shape:
+            raise ValueError("F_target must have the shape of F")
+        dF = torch.empty_like(F)
+        dA = None
+        At = None
+        if A_target is not None:
+            A = A.contiguous()
+            At = A_target.contiguous().float()
+            if At.shape != A.shape or A.numel() != R:
+                raise ValueError("A and A_target must hold one value per ray")
+            dA = torch.empty_like(A)
+        loss = ctypes.c_double(0.0)
+        self._check(self.lib.art_map_loss(self._h, F.numel(), R, _tptr(F), _tptr(Ft), _tptr(A) if At is not None else None,
+                                          _tptr(At), _tptr(dF), _tptr(dA), ctypes.byref(loss)), "art_map_loss")
+        return float(loss.value), dF, dA
+
     def train_state(self, sigma, feat) -> dict:
         """Adam moments of a float32 FLUT (sigma [n], feat [n][C]) and the step count."""
         torch = self._torch
@@ -435,13 +459,7 @@ class Renderer:
         losses of the FLUT before the update."""
         torch = self._torch
         F, A, T = self.render(sigma, feat, lambda_th, fp32_geom=fp32_geom)
-        R = float(self.P * self.V * self.H * self.W)
-        dF = (F - F_target) / R
-        l_map = 0.5 * float((dF * (F - F_target)).sum())
-        dA = None
-        if A_target is not None:
-            dA = (A - A_target) / R
-            l_map += 0.5 * float((dA * (A - A_target)).sum())
+        l_map, dF, dA = self.map_loss(F, F_target, A, A_target)
         # the adjoint and the VRT read the posed octrees (and tile lists) the
         # render just built: the poses and the octree did not change
         d_sigma, d_feat = self.backward(sigma, feat, F, T, dF, dA, lambda_th, fp32_geom=fp32_geom, reuse_build=True)

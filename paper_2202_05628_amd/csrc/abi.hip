@@ -150,7 +150,8 @@ std::vector<DevBuf*> working_bufs(art_ctx* ctx) {
             &s.occ_win, &s.brick_key, &s.brick_row, &s.brick_mask, &s.bin_cnt, &s.bin_off, &s.pk0, &s.pv0,
             &s.pk1, &s.pair_v, &s.tile_start, &s.tile_end, &s.counters, &s.stats, &s.ovf, &s.items, &s.queue,
             &s.loss, &s.redo, &s.interval, &ctx->mlp_theta, &ctx->mlp_m1, &ctx->mlp_m2, &ctx->mlp_packed, &ctx->mlp_cbias,
-            &ctx->mlp_code, &ctx->mlp_S, &ctx->mlp_part, &ctx->mlp_lossp, &ctx->mlp_loss, &ctx->mlp_flag};
+            &ctx->mlp_code, &ctx->mlp_S, &ctx->mlp_part, &ctx->mlp_lossp, &ctx->mlp_loss, &ctx->mlp_flag,
+            &ctx->mlp_calib};
 }
 
 size_t working_bytes(art_ctx* ctx) {
@@ -865,7 +866,7 @@ void art_destroy(art_ctx* ctx) {
                           &ctx->s.counters, &ctx->s.stats, &ctx->s.ovf, &ctx->s.items, &ctx->s.queue, &ctx->s.loss,
                           &ctx->s.redo, &ctx->s.interval, &ctx->mlp_theta, &ctx->mlp_m1, &ctx->mlp_m2,
                           &ctx->mlp_packed, &ctx->mlp_cbias, &ctx->mlp_code, &ctx->mlp_S, &ctx->mlp_part,
-                          &ctx->mlp_lossp, &ctx->mlp_loss, &ctx->mlp_flag};
+                          &ctx->mlp_lossp, &ctx->mlp_loss, &ctx->mlp_flag, &ctx->mlp_calib};
         for (DevBuf* b : bufs) b->release();
     }
     delete ctx;
@@ -1775,6 +1776,200 @@ art_status art_get_octree(art_ctx* ctx, int pose, unsigned flags, int64_t* count
     zs.release();
     zf.release();
     return rc;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Training-side calls: proposal margin calibration, proposal state file, map loss
+// ---------------------------------------------------------------------------
+namespace {
+
+// Late start of the proposed entry, in leaf edges h, of each ray whose label
+// holds a sample (u_near <= u_far): (predicted - labelled u_near) times the
+// ray's span inside the posed root [-1, 1]^3 (from max(t_entry, 0) to t_exit),
+// over h; NaN for rays without a sample.
+__global__ __launch_bounds__(256) void k_calib_late(const float* __restrict__ od, const float* __restrict__ target,
+                                                    const float* __restrict__ pred, int64_t n, double h,
+                                                    float* __restrict__ late) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float un = target[2 * i], uf = target[2 * i + 1];
+    if (!(un <= uf)) {
+        late[i] = __builtin_nanf("");
+        return;
+    }
+    double lo = -INFINITY, hi = INFINITY;
+    for (int a = 0; a < 3; ++a) {
+        const double o = od[6 * i + a], d = od[6 * i + 3 + a];
+        if (d == 0.0) continue;
+        const double t0 = (-1.0 - o) / d, t1 = (1.0 - o) / d;
+        lo = fmax(lo, fmin(t0, t1));
+        hi = fmin(hi, fmax(t0, t1));
+    }
+    const double span = hi - fmax(lo, 0.0);
+    late[i] = (float)(((double)pred[2 * i] - (double)un) * span / h);
+}
+
+// L2 map loss: d = (x - y) * inv_r into dx, per-block partial sums of
+// (x - y)^2 (FP64) into part[blockIdx.x].
+__global__ __launch_bounds__(256) void k_map_loss(const float* __restrict__ x, const float* __restrict__ y,
+                                                  int64_t n, float inv_r, float* __restrict__ dx,
+                                                  double* __restrict__ part) {
+    __shared__ double red[256 / kWave];
+    double acc = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const float e = x[i] - y[i];
+        dx[i] = e * inv_r;
+        acc += (double)e * (double)e;
+    }
+    for (int off = kWave / 2; off > 0; off >>= 1) acc += __shfl_down(acc, off, kWave);
+    if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < 256 / kWave; ++w) t += red[w];
+        part[blockIdx.x] = t;
+    }
+}
+
+constexpr int kLossBlocks = 1024;
+
+// Sum of (x - y)^2 over n elements (FP64, fixed order) and dx = (x - y) inv_r.
+art_status map_loss_part(art_ctx* ctx, const float* x, const float* y, int64_t n, float inv_r, float* dx,
+                         double* sum) {
+    *sum = 0.0;
+    if (n == 0) return ART_OK;
+    hipStream_t st = ctx->stream;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > kLossBlocks) blocks = kLossBlocks;
+    art_status rc = ensure_bufs(ctx, {{&ctx->mlp_calib, (size_t)kLossBlocks * 8}});
+    if (rc != ART_OK) return rc;
+    hipLaunchKernelGGL(k_map_loss, dim3((unsigned)blocks), dim3(256), 0, st, x, y, n, inv_r, dx,
+                       ctx->mlp_calib.as<double>());
+    ART_TRY_HIP(hipGetLastError(), "map loss");
+    std::vector<double> part((size_t)blocks);
+    ART_TRY_HIP(hipMemcpyAsync(part.data(), ctx->mlp_calib.p, (size_t)blocks * 8, hipMemcpyDeviceToHost, st), "copy");
+    ART_TRY_HIP(hipStreamSynchronize(st), "map loss");
+    for (double v : part) *sum += v;
+    return ART_OK;
+}
+
+constexpr char kPropMagic[8] = {'A', 'R', 'T', 'P', 'R', 'O', 'P', '1'};
+
+}  // namespace
+
+extern "C" {
+
+art_status art_proposal_calibrate(art_ctx* ctx, int64_t n, const float* od, const int32_t* pose, const float* target,
+                                  float quantile, float floor_h, float* margin_h) {
+    if (!ctx) return ART_EINVAL;
+    if (!margin_h) return fail(ctx, ART_EINVAL, "margin_h is NULL");
+    if (n < 0 || (n > 0 && (!od || !pose || !target))) return fail(ctx, ART_EINVAL, "n < 0 or NULL buffer");
+    if (!(quantile >= 0.0f && quantile <= 1.0f)) return fail(ctx, ART_EINVAL, "quantile must be in [0, 1]");
+    if (!(floor_h >= 0.0f) || !std::isfinite(floor_h)) return fail(ctx, ART_EINVAL, "floor_h must be finite, >= 0");
+    if (ctx->depth <= 0) return fail(ctx, ART_ESTATE, "no octree loaded (art_load_octree)");
+    DeviceGuard g(ctx->device);
+    hipStream_t st = ctx->stream;
+    *margin_h = floor_h;
+    if (n == 0) return ART_OK;
+    art_status rc = ensure_bufs(ctx, {{&ctx->mlp_calib, (size_t)n * 12}});
+    if (rc != ART_OK) return rc;
+    float* pred = ctx->mlp_calib.as<float>();   // [n][2], then the late starts [n]
+    float* late = pred + 2 * n;
+    rc = art_proposal_forward(ctx, n, od, pose, pred);
+    if (rc != ART_OK) return rc;
+    const double h = 1.0 / (double)(1 << ctx->depth);
+    hipLaunchKernelGGL(k_calib_late, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, od, target, pred, n, h, late);
+    ART_TRY_HIP(hipGetLastError(), "calibration");
+    std::vector<float> v((size_t)n);
+    ART_TRY_HIP(hipMemcpyAsync(v.data(), late, (size_t)n * 4, hipMemcpyDeviceToHost, st), "copy");
+    ART_TRY_HIP(hipStreamSynchronize(st), "calibration");
+    v.erase(std::remove_if(v.begin(), v.end(), [](float x) { return std::isnan(x); }), v.end());
+    if (v.empty()) return ART_OK;
+    // quantile with linear interpolation between the order statistics
+    std::sort(v.begin(), v.end());
+    const double pos = (double)quantile * (double)(v.size() - 1);
+    const size_t k = (size_t)pos;
+    const double frac = pos - (double)k;
+    double q = v[k];
+    if (k + 1 < v.size()) q += frac * ((double)v[k + 1] - (double)v[k]);
+    *margin_h = (float)std::max((double)floor_h, q);
+    return ART_OK;
+}
+
+art_status art_proposal_io(art_ctx* ctx, int save, const char* path) {
+    if (!ctx) return ART_EINVAL;
+    if (!path) return fail(ctx, ART_EINVAL, "path is NULL");
+    if (ctx->J <= 0) return fail(ctx, ART_ESTATE, "no skeleton (art_set_skeleton)");
+    const MlpDims m = mlp_dims(ctx->J);
+    const size_t np = (size_t)m.np;
+    DeviceGuard g(ctx->device);
+    hipStream_t st = ctx->stream;
+    std::vector<float> buf(3 * np);
+    if (save) {
+        if (ctx->mlp_J != ctx->J)
+            return fail(ctx, ART_ESTATE, "no proposal weights for the current skeleton (art_proposal_set_weights)");
+        ART_TRY_HIP(hipMemcpyAsync(buf.data(), ctx->mlp_theta.p, np * 4, hipMemcpyDeviceToHost, st), "copy");
+        ART_TRY_HIP(hipMemcpyAsync(buf.data() + np, ctx->mlp_m1.p, np * 4, hipMemcpyDeviceToHost, st), "copy");
+        ART_TRY_HIP(hipMemcpyAsync(buf.data() + 2 * np, ctx->mlp_m2.p, np * 4, hipMemcpyDeviceToHost, st), "copy");
+        ART_TRY_HIP(hipStreamSynchronize(st), "copy");
+        FILE* f = fopen(path, "wb");
+        if (!f) return fail(ctx, ART_EINVAL, std::string("cannot open ") + path + " for writing");
+        const int32_t hdr[2] = {ctx->J, 0};
+        const int64_t cnt[2] = {m.np, ctx->mlp_step};
+        bool ok = fwrite(kPropMagic, 1, 8, f) == 8 && fwrite(hdr, 4, 2, f) == 2 && fwrite(cnt, 8, 2, f) == 2 &&
+                  fwrite(buf.data(), 4, 3 * np, f) == 3 * np;
+        ok = (fclose(f) == 0) && ok;
+        if (!ok) return fail(ctx, ART_EINVAL, std::string("write to ") + path + " failed");
+        return ART_OK;
+    }
+    FILE* f = fopen(path, "rb");
+    if (!f) return fail(ctx, ART_EINVAL, std::string("cannot open ") + path);
+    char magic[8];
+    int32_t hdr[2];
+    int64_t cnt[2];
+    bool ok = fread(magic, 1, 8, f) == 8 && memcmp(magic, kPropMagic, 8) == 0 && fread(hdr, 4, 2, f) == 2 &&
+              fread(cnt, 8, 2, f) == 2;
+    ok = ok && hdr[0] == ctx->J && cnt[0] == m.np && cnt[1] >= 0 && fread(buf.data(), 4, 3 * np, f) == 3 * np;
+    char extra;
+    ok = ok && fread(&extra, 1, 1, f) == 0;   // nothing after the state
+    fclose(f);
+    if (!ok) return fail(ctx, ART_EINVAL, std::string(path) + " is not a proposal state for J = " + std::to_string(ctx->J));
+    for (size_t i = 0; i < 3 * np; ++i)
+        if (!std::isfinite(buf[i]) || (i >= 2 * np && buf[i] < 0.0f))
+            return fail(ctx, ART_EINVAL, std::string(path) + ": non-finite value or negative second moment");
+    const size_t bytes = np * 4;
+    art_status rc = ensure_bufs(ctx, {{&ctx->mlp_theta, bytes}, {&ctx->mlp_m1, bytes}, {&ctx->mlp_m2, bytes}});
+    if (rc != ART_OK) return rc;
+    ART_TRY_HIP(hipMemcpyAsync(ctx->mlp_theta.p, buf.data(), bytes, hipMemcpyHostToDevice, st), "copy");
+    ART_TRY_HIP(hipMemcpyAsync(ctx->mlp_m1.p, buf.data() + np, bytes, hipMemcpyHostToDevice, st), "copy");
+    ART_TRY_HIP(hipMemcpyAsync(ctx->mlp_m2.p, buf.data() + 2 * np, bytes, hipMemcpyHostToDevice, st), "copy");
+    ART_TRY_HIP(hipStreamSynchronize(st), "copy");
+    ctx->mlp_J = ctx->J;
+    ctx->mlp_step = cnt[1];
+    return ART_OK;
+}
+
+art_status art_map_loss(art_ctx* ctx, int64_t n_feat, int64_t rays, const float* F, const float* F_target,
+                        const float* A, const float* A_target, float* d_feat, float* d_alpha, double* loss) {
+    if (!ctx) return ART_EINVAL;
+    if (!loss) return fail(ctx, ART_EINVAL, "loss is NULL");
+    if (n_feat < 0 || rays < 1) return fail(ctx, ART_EINVAL, "n_feat >= 0 and rays >= 1");
+    if (n_feat > 0 && (!F || !F_target || !d_feat)) return fail(ctx, ART_EINVAL, "NULL feature buffer");
+    if (A_target && (!A || !d_alpha)) return fail(ctx, ART_EINVAL, "NULL opacity buffer");
+    DeviceGuard g(ctx->device);
+    const float inv_r = (float)(1.0 / (double)rays);
+    double sf = 0.0, sa = 0.0;
+    art_status rc = map_loss_part(ctx, F, F_target, n_feat, inv_r, d_feat, &sf);
+    if (rc != ART_OK) return rc;
+    if (A_target) {
+        rc = map_loss_part(ctx, A, A_target, rays, inv_r, d_alpha, &sa);
+        if (rc != ART_OK) return rc;
+    }
+    *loss = 0.5 * (sf + sa) / (double)rays;
+    return ART_OK;
 }
 
 art_status art_get_stats(art_ctx* ctx, int64_t* stats) {

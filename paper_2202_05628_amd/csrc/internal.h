@@ -166,6 +166,7 @@ struct art_ctx {
     art::DevBuf mlp_cbias;         // [P][64] per-pose first-layer bias
     art::DevBuf mlp_code;          // [P][6J] pose codes
     art::DevBuf mlp_S, mlp_part, mlp_lossp, mlp_loss, mlp_flag;
+    art::DevBuf mlp_calib;         // margin calibration and map-loss scratch
     int64_t poses_version = 0;     // bumped by art_set_poses
     int64_t code_version = -1;     // poses_version the pose codes were computed for
 
