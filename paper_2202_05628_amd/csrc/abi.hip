@@ -892,21 +892,10 @@ art_status art_get_memory(art_ctx* ctx, int64_t* working_bytes_out, int64_t* lim
 art_status art_load_octree(art_ctx* ctx, int depth, int64_t n, const uint16_t* ijk) {
     if (!ctx) return ART_EINVAL;
     ctx->state_version++;   // posed octrees and tile lists of earlier calls no longer apply
-    if (depth < 1 || depth > 9) return fail(ctx, ART_EINVAL, "depth must be in 1..9");
-    if (n < 1 || n > ((int64_t)1 << (3 * depth)) || n > 0x7FFFFFFFLL)
-        return fail(ctx, ART_EINVAL, "leaf count out of range");
-    if (!ijk) return fail(ctx, ART_EINVAL, "ijk is NULL");
-    const int64_t G = (int64_t)1 << depth;
-    std::vector<uint32_t> lin((size_t)n);
-    for (int64_t i = 0; i < n; ++i) {
-        const int64_t x = ijk[i], y = ijk[n + i], z = ijk[2 * n + i];
-        if (x >= G || y >= G || z >= G)
-            return fail(ctx, ART_EINVAL, "leaf " + std::to_string(i) + " outside the 2^depth grid");
-        lin[(size_t)i] = (uint32_t)((z * G + y) * G + x);
+    {
+        const std::string err = check_octree(depth, n, ijk);
+        if (!err.empty()) return fail(ctx, ART_EINVAL, err);
     }
-    std::sort(lin.begin(), lin.end());
-    for (size_t i = 1; i < lin.size(); ++i)
-        if (lin[i] == lin[i - 1]) return fail(ctx, ART_EINVAL, "duplicate leaf cells");
     DeviceGuard g(ctx->device);
     DevBuf nb;
     ART_TRY_HIP(nb.ensure((size_t)n * 3 * 2), "device allocation");
@@ -930,22 +919,14 @@ art_status art_set_skin(art_ctx* ctx, const uint8_t* bone, const float* weight) 
     if (!ctx) return ART_EINVAL;
     ctx->state_version++;   // posed octrees and tile lists of earlier calls no longer apply
     if (ctx->n <= 0) return fail(ctx, ART_ESTATE, "no octree loaded (art_load_octree)");
-    if (!bone || !weight) return fail(ctx, ART_EINVAL, "bone / weight is NULL");
     const size_t n = (size_t)ctx->n;
     int mb = -1;
-    for (size_t i = 0; i < 4 * n; ++i) {
-        if (!(weight[i] >= 0.0f) || !std::isfinite(weight[i]))
-            return fail(ctx, ART_EINVAL, "skin weights must be finite and >= 0");
-        mb = std::max(mb, (int)bone[i]);
-    }
     // the bone of each leaf's largest weight (the first of equal ones) stands
     // for the leaf's rotation in the view-dependent features
-    std::vector<uint8_t> dom(n);
-    for (size_t i = 0; i < n; ++i) {
-        int best = 0;
-        for (int k = 1; k < 4; ++k)
-            if (weight[k * n + i] > weight[best * n + i]) best = k;
-        dom[i] = bone[best * n + i];
+    std::vector<uint8_t> dom;
+    {
+        const std::string err = check_skin(ctx->n, bone, weight, &mb, &dom);
+        if (!err.empty()) return fail(ctx, ART_EINVAL, err);
     }
     DeviceGuard g(ctx->device);
     DevBuf b, w, db;
@@ -980,13 +961,10 @@ art_status art_set_skin(art_ctx* ctx, const uint8_t* bone, const float* weight) 
 art_status art_set_skeleton(art_ctx* ctx, int J, const int32_t* parent, const double* rest_joint) {
     if (!ctx) return ART_EINVAL;
     ctx->state_version++;   // posed octrees and tile lists of earlier calls no longer apply
-    if (J < 1 || J > 255) return fail(ctx, ART_EINVAL, "J must be in 1..255");
-    if (!parent || !rest_joint) return fail(ctx, ART_EINVAL, "parent / rest_joint is NULL");
-    if (parent[0] != -1) return fail(ctx, ART_EINVAL, "parent[0] must be -1");
-    for (int j = 1; j < J; ++j)
-        if (parent[j] < 0 || parent[j] >= j) return fail(ctx, ART_EINVAL, "parent[j] must be in [0, j)");
-    for (int i = 0; i < 3 * J; ++i)
-        if (!std::isfinite(rest_joint[i])) return fail(ctx, ART_EINVAL, "rest joints must be finite");
+    {
+        const std::string err = check_skeleton(J, parent, rest_joint);
+        if (!err.empty()) return fail(ctx, ART_EINVAL, err);
+    }
     DeviceGuard g(ctx->device);
     DevBuf pb, rb;
     ART_TRY_HIP(pb.ensure((size_t)J * 4), "device allocation");
@@ -1014,18 +992,11 @@ art_status art_set_poses(art_ctx* ctx, int P, const double* r, const double* R, 
     if (!ctx) return ART_EINVAL;
     ctx->state_version++;   // posed octrees and tile lists of earlier calls no longer apply
     if (ctx->J <= 0) return fail(ctx, ART_ESTATE, "no skeleton (art_set_skeleton)");
-    if (P < 1 || P > 4096) return fail(ctx, ART_EINVAL, "P must be in 1..4096");
-    if (!r || !R || !T) return fail(ctx, ART_EINVAL, "r / R / T is NULL");
-    const int J = ctx->J;
-    std::vector<double> buf((size_t)P * (J + 2) * 3);
-    for (int p = 0; p < P; ++p) {
-        double* dst = buf.data() + (size_t)p * (J + 2) * 3;
-        memcpy(dst, r + (size_t)p * J * 3, sizeof(double) * J * 3);
-        memcpy(dst + J * 3, R + 3 * p, sizeof(double) * 3);
-        memcpy(dst + J * 3 + 3, T + 3 * p, sizeof(double) * 3);
+    std::vector<double> buf;
+    {
+        const std::string err = pack_poses(ctx->J, P, r, R, T, &buf);
+        if (!err.empty()) return fail(ctx, ART_EINVAL, err);
     }
-    for (double v : buf)
-        if (!std::isfinite(v)) return fail(ctx, ART_EINVAL, "pose parameters must be finite");
     DeviceGuard g(ctx->device);
     DevBuf pb;
     ART_TRY_HIP(pb.ensure(buf.size() * 8), "device allocation");
@@ -1044,35 +1015,10 @@ art_status art_set_poses(art_ctx* ctx, int P, const double* r, const double* R, 
 art_status art_set_cameras(art_ctx* ctx, int V, int H, int W, const double* K, const double* c2w) {
     if (!ctx) return ART_EINVAL;
     ctx->state_version++;   // posed octrees and tile lists of earlier calls no longer apply
-    if (V < 1 || V > 4096) return fail(ctx, ART_EINVAL, "V must be in 1..4096");
-    if (H < 1 || H > 8192 || W < 1 || W > 8192) return fail(ctx, ART_EINVAL, "H, W must be in 1..8192");
-    if (!K || !c2w) return fail(ctx, ART_EINVAL, "K / c2w is NULL");
-    std::vector<CamParams> cams((size_t)V);
-    for (int v = 0; v < V; ++v) {
-        const double* k = K + 9 * v;
-        const double* m = c2w + 12 * v;
-        for (int i = 0; i < 9; ++i)
-            if (!std::isfinite(k[i])) return fail(ctx, ART_EINVAL, "K must be finite");
-        for (int i = 0; i < 12; ++i)
-            if (!std::isfinite(m[i])) return fail(ctx, ART_EINVAL, "c2w must be finite");
-        if (!(k[0] != 0.0) || !(k[4] != 0.0)) return fail(ctx, ART_EINVAL, "focal lengths must be non-zero");
-        // the camera-to-world rotation must be orthonormal (columns: right, down, forward)
-        for (int a = 0; a < 3; ++a)
-            for (int b = 0; b < 3; ++b) {
-                double dot = 0.0;
-                for (int r = 0; r < 3; ++r) dot += m[4 * r + a] * m[4 * r + b];
-                if (fabs(dot - (a == b ? 1.0 : 0.0)) > 1e-6)
-                    return fail(ctx, ART_EINVAL, "c2w rotation must be orthonormal");
-            }
-        CamParams& c = cams[(size_t)v];
-        c.fx = k[0];
-        c.fy = k[4];
-        c.cx = k[2];
-        c.cy = k[5];
-        for (int a = 0; a < 3; ++a) {
-            for (int b = 0; b < 3; ++b) c.R[3 * a + b] = m[4 * a + b];
-            c.t[a] = m[4 * a + 3];
-        }
+    std::vector<CamParams> cams;
+    {
+        const std::string err = check_cameras(V, H, W, K, c2w, &cams);
+        if (!err.empty()) return fail(ctx, ART_EINVAL, err);
     }
     DeviceGuard g(ctx->device);
     DevBuf cb;

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/artemis.h"
+#include "validate.h"
 
 namespace art {
 
@@ -37,12 +38,6 @@ struct DevBuf {
     template <typename T> T* as() const { return static_cast<T*>(p); }
 };
 
-// Per-view camera as used by the kernels (FP64).
-struct CamParams {
-    double fx, fy, cx, cy;
-    double R[9];   // row-major camera-to-world rotation (columns: right, down, forward)
-    double t[3];   // camera centre
-};
 
 // Parameter layout of the proposal network for J bones (flat FP32 vector:
 // W1 [64][n_in], b1, W2 [64][64], b2, W3 [64][64], b3, W4 [2][64], b4).
