@@ -60,9 +60,13 @@ def measured_traffic(workload):
         return None
 
 
-def copy_ceiling(torch, nbytes=1 << 30, reps=5):
+def copy_probe(torch, nbytes=1 << 30, reps=5):
     """Device-to-device copy bandwidth (read + write bytes / time) of one
-    torch copy kernel over nbytes, timed with events on the current stream."""
+    torch copy kernel over nbytes, timed with events on the current stream.
+    Run only with --copy-probe: the profiling runs use this copy of known size
+    to scale the FETCH_SIZE / WRITE_SIZE counters to bytes.  It is not a
+    bound of the compositing kernel (a gather of rows that partly hit in the
+    caches), so the record does not compare the kernel with it."""
     x = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
     y = torch.empty_like(x)
     y.copy_(x)
@@ -97,6 +101,8 @@ def parse():
     ap.add_argument("--f2-tau", type=float, default=-1.0)
     ap.add_argument("--err-poses", type=int, default=4, help="poses on which the proposal error is measured")
     ap.add_argument("--no-forms", action="store_true", help="skip the BF16-storage and adjoint legs")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="time a 1 GiB device copy (the counter scale of the profiling runs)")
     ap.add_argument("--leg", choices=["bf16", "adjoint", "train", "proposal"], default=None,
                     help="run only this form and print its record (profiling)")
     return ap.parse_args()
@@ -153,6 +159,8 @@ def cpu_baseline(scene, poses, K, c2w, H, W, lam, budget_s):
         "value": n_all / t_pose / 1e6,
         "unit": "Mrays/s",
         "cores": threads,
+        "cpu_model": cpu_model(),
+        "host_cpus": os.cpu_count(),
         "kind": "oracle",
         "sample": (f"1 pose x {K.shape[0]} views at {H}x{W}: FK, skinning and occupancy of all "
                    f"{scene.n} leaves timed in full ({t_build:.2f} s); {n} of {n_all} rays rendered "
@@ -160,6 +168,149 @@ def cpu_baseline(scene, poses, K, c2w, H, W, lam, budget_s):
         "one_core_render_mrays_s": n1 / t_one / 1e6,
         "one_core_sample": f"{n1} rays of the same pose on one host thread ({t_one:.2f} s)",
     }
+
+
+def cpu_model():
+    """Model name of the host CPU (first entry of /proc/cpuinfo), or None."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def oracle_checks(art, sg, torch, lam, n_grad_rays=4000, pixels_per_map=120, bf16_poses=(0, 29)):
+    """Errors of the extra forms against the FP64 oracle (part of the CPU-oracle
+    leg, the only leg that runs the oracle):
+
+    * precision form: per (pose, view) map of poses `bf16_poses` of the BF16
+      workload, rel_max = max|F - F_ref| / max|F_ref| and rel_mean =
+      sum|F - F_ref| / sum|F_ref| over sampled pixels (3/4 of them from pixels
+      with a sample), against the oracle on the unrounded FP32 FLUT (the whole
+      error of the form) and on the BF16-rounded FLUT (arithmetic and FP32
+      geometry only); rel_max also outside the rounding guard band (pixels
+      whose ray crosses a cell that a leaf within 1e-4 h of a lattice plane
+      may land in, where FP32 skinning may place it differently);
+    * adjoint: the gradient of L = 1/2 sum (F - F*)^2 over a seeded subset of
+      rays of the differentiation workload (dL/dF zero elsewhere), GPU adjoint
+      vs the oracle's adjoint over every leaf (rel_max of dsigma and df)."""
+    import itertools
+    import numpy as np
+
+    import oracle
+    out = {}
+    # ---- precision form ------------------------------------------------------------
+    cfg = sg.CONFIGS["bf16"]
+    s = sg.make_scene(cfg)
+    r_, R_, T_ = sg.make_poses(s.J, cfg.n_poses, cfg.pose_seed0)
+    sel = list(bf16_poses)
+    H, W = cfg.height, cfg.width
+    K, c2w = sg.make_cameras(s, cfg.n_views, H, W)
+    rend = art.Renderer(0)
+    rend.set_scene(s)
+    rend.set_poses(r_[sel], R_[sel], T_[sel])
+    rend.set_cameras(K, c2w, H, W)
+    F, A, _ = rend.render(torch.from_numpy(s.sigma).cuda().to(torch.bfloat16),
+                          torch.from_numpy(s.feat).cuda().to(torch.bfloat16), lam, fp32_geom=True,
+                          want_tfinal=False)
+    F = F.cpu().numpy()
+    A = A.cpu().numpy()
+    rend.close()
+    sig_r, feat_r = oracle.bf16_round(s.sigma), oracle.bf16_round(s.feat)
+    o, d = oracle.camera_rays(K, c2w, H, W)
+    h = 1.0 / (1 << s.depth)
+    G = 1 << (s.depth + 1)
+    rng = np.random.default_rng(77)
+    B = oracle.fk(s.parent, s.rest_joint, r_[sel], R_[sel], T_[sel])
+    maps = []
+    for pi in range(len(sel)):
+        pt = oracle.lbs(s.ijk, s.depth, s.bone, s.weight, B[pi])
+        cells, valid = oracle.posed_cells(pt, s.depth)
+        ok_, ol_ = oracle.occupancy_from_cells(cells, valid, s.depth)
+        u = (pt + 1.0) * (1 << s.depth)
+        k = np.round(u)
+        near = np.abs(u - k) < 1e-4
+        amb = set()
+        for i in np.flatnonzero(near.any(axis=1)):
+            opts = [(int(k[i, a]) - 1, int(k[i, a])) if near[i, a] else (int(np.floor(u[i, a])),) for a in range(3)]
+            amb.update((z * G + y) * G + x for x, y, z in itertools.product(*opts))
+        amb_lin = np.array(sorted(amb), dtype=np.int64)
+        for v in range(cfg.n_views):
+            hitpix = np.flatnonzero(A[pi, v].reshape(-1) > 0)
+            nh = min(len(hitpix), pixels_per_map * 3 // 4)
+            pix = np.concatenate([rng.choice(hitpix, nh, replace=False),
+                                  rng.integers(0, H * W, pixels_per_map - nh)])
+            ov, dv = o[v].reshape(-1, 3)[pix], d[v].reshape(-1, 3)[pix]
+            ref_a = oracle.render(ov, dv, s.depth, ok_, ol_, s.sigma, s.feat, lam)
+            ref_b = oracle.render(ov, dv, s.depth, ok_, ol_, sig_r, feat_r, lam)
+            band = ref_a["min_gap"] < 1e-4 * h
+            if len(amb_lin):
+                band |= oracle.render(ov, dv, s.depth, amb_lin, np.zeros(len(amb_lin), dtype=np.int64),
+                                      np.zeros(1), np.zeros((1, 1)), 0.0)["n_hit"] > 0
+            Fg = F[pi, v].reshape(s.C, -1)[:, pix]
+            row = {"pose": sel[pi], "view": v, "pixels": int(len(pix)), "in_guard_band": int(band.sum())}
+            for name, ref in (("total", ref_a), ("arith", ref_b)):
+                Fr = ref["F"].T
+                err = np.abs(Fg - Fr)
+                row[f"{name}_rel_max"] = float(err.max() / np.abs(Fr).max())
+                row[f"{name}_rel_max_outside_band"] = float(err[:, ~band].max() / np.abs(Fr[:, ~band]).max())
+                row[f"{name}_rel_mean"] = float(err.sum() / np.abs(Fr).sum())
+            maps.append(row)
+    keys = [k for k in maps[0] if k.endswith(("rel_max", "rel_mean", "outside_band"))]
+    out["bf16_form"] = {
+        "reference": "FP64 oracle; total = vs the FP32 FLUT, arith = vs the BF16-rounded FLUT",
+        "poses": sel, "views": cfg.n_views, "pixels_per_map": pixels_per_map,
+        "worst_over_maps": {k: max(m[k] for m in maps) for k in keys},
+        "mean_over_maps": {k: float(np.mean([m[k] for m in maps])) for k in keys},
+        "maps": maps,
+    }
+    # ---- adjoint --------------------------------------------------------------------
+    cfg = sg.CONFIGS["grad"]
+    s = sg.make_scene(cfg)
+    poses = sg.make_poses(s.J, cfg.n_poses, cfg.pose_seed0)
+    H, W, V = cfg.height, cfg.width, cfg.n_views
+    K, c2w = sg.make_cameras(s, V, H, W)
+    rend = art.Renderer(0)
+    rend.set_scene(s)
+    rend.set_poses(*poses)
+    rend.set_cameras(K, c2w, H, W)
+    B = oracle.fk(s.parent, s.rest_joint, *poses)
+    ok_, ol_, _, _, _ = oracle.pose_occupancy(s.ijk, s.depth, s.bone, s.weight, B[0])
+    o, d = oracle.camera_rays(K, c2w, H, W)
+    o, d = o.reshape(-1, 3), d.reshape(-1, 3)
+    tgt = sg.make_targets(1, V, s.C, H, W, seed=cfg.target_seed)[0]
+    tgt_rays = np.moveaxis(tgt.reshape(V, s.C, H * W), 1, 2).reshape(-1, s.C)
+    rng = np.random.default_rng(1001)
+    cand = rng.choice(V * H * W, 6 * n_grad_rays, replace=False)
+    ref = oracle.render(o[cand], d[cand], s.depth, ok_, ol_, s.sigma, s.feat, lam)
+    good = (ref["min_gap"] >= 1e-9 * h) & (ref["min_tgap"] >= 1e-5)   # away from the rounding guard bands
+    hit = good & (ref["n_comp"] > 0)
+    sub = np.sort(cand[hit][:n_grad_rays])
+    sig = torch.from_numpy(s.sigma).cuda()
+    ft = torch.from_numpy(s.feat).cuda()
+    Fm, _, Tm = rend.render(sig, ft, lam)
+    Fr = Fm[0].permute(0, 2, 3, 1).reshape(-1, s.C)
+    g = torch.zeros_like(Fr)
+    idx = torch.from_numpy(sub).cuda()
+    g[idx] = Fr[idx] - torch.from_numpy(tgt_rays[sub]).cuda()
+    dF = g.reshape(1, V, H, W, s.C).permute(0, 1, 4, 2, 3).contiguous()
+    ds, df = rend.backward(sig, ft, Fm, Tm, dF, None, lam, reuse_build=True)
+    ds = ds.cpu().numpy().astype(np.float64)
+    df = df.cpu().numpy().astype(np.float64)
+    rend.close()
+    refs = oracle.render(o[sub], d[sub], s.depth, ok_, ol_, s.sigma, s.feat, lam)
+    ds_ref, df_ref = oracle.backward(o[sub], d[sub], s.depth, ok_, ol_, s.sigma, s.feat, lam,
+                                     refs["F"] - tgt_rays[sub])
+    out["adjoint_form"] = {
+        "reference": "FP64 oracle adjoint, L = 1/2 sum (F - F*)^2 over a seeded subset of rays",
+        "rays_in_loss": int(len(sub)), "leaves_with_gradient": int((ds_ref != 0).sum()),
+        "dsigma_rel_max": float(np.abs(ds - ds_ref).max() / np.abs(ds_ref).max()),
+        "dfeat_rel_max": float(np.abs(df - df_ref).max() / np.abs(df_ref).max()),
+    }
+    return out
 
 
 def _timed(torch, fn, steps):
@@ -481,7 +632,7 @@ def main():
     out = (Fm, Am, Tm)
     fp32_geom = cfg.storage == "bf16"
 
-    copy_gbs = copy_ceiling(torch)
+    copy_gbs = copy_probe(torch) if args.copy_probe else None
     for i in range(args.warmup):
         r.render(sig, feat, args.lambda_th, fp32_geom=fp32_geom, out=out)
         print(f"[bench] warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
@@ -540,8 +691,7 @@ def main():
             "traffic": measured_traffic(workload),
             "kernel": "k_render (forward compositing)",
             "render_source_hash": render_source_hash(),
-            "copy_ceiling_GBps": round(copy_gbs, 1),
-            "frac_of_copy_ceiling": round(achieved / copy_gbs, 4),
+            "copy_probe_GBps": None if copy_gbs is None else round(copy_gbs, 1),
             "launches_per_step": launches_per_call,
             "avg_launch_us": round(avg_launch_s * 1e6, 2),
             "algorithmic_bytes_per_launch": int(per_launch_bytes),
@@ -581,6 +731,11 @@ def main():
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(scene, poses, K, c2w, cfg.height, cfg.width,
                                             args.lambda_th, args.cpu_seconds)
+        if not args.no_forms:
+            print("[bench] errors of the extra forms against the FP64 oracle", file=sys.stderr, flush=True)
+            errs = oracle_checks(art, sg, torch, args.lambda_th)
+            line["bf16_form"]["error_vs_fp64_oracle"] = errs["bf16_form"]
+            line["adjoint_form"]["gradient_vs_fp64_oracle"] = errs["adjoint_form"]
     print(json.dumps(line), flush=True)
 
 
