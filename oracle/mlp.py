@@ -15,7 +15,11 @@ Network (all FP64 here):
     z4  = W4 h3 + b4,  y  = sigmoid(z4)     W4: [2][64];  y = (u_near, u_far)
 The pose code of a pose is, for every bone j, the first two columns of its
 local rotation Rot(r_j) (the 6-D rotation representation), column by column.
-Loss: mean over rays and both outputs of SmoothL1 with beta = 1.
+Loss: mean over rays and both outputs of SmoothL1 with beta = 1 (default), or
+of the pinball (quantile) loss rho_tau(t - y) = max(tau (t - y), (tau - 1) (t - y))
+with a level tau per output: its minimiser over a constant is the
+tau-quantile of the targets, so a small tau for u_near makes late starts rare
+and a large one for u_far makes early ends rare (a one-sided interval).
 Training: Adam with bias correction.
 
 Flat parameter order (FP32 on the GPU, the same order here):
@@ -149,21 +153,44 @@ def smooth_l1_grad(e: np.ndarray, beta: float = 1.0) -> np.ndarray:
     return np.where(np.abs(e) < beta, e / beta, np.sign(e))
 
 
-def loss(y: np.ndarray, target: np.ndarray) -> float:
-    """Mean SmoothL1 (beta = 1) over rays and both outputs."""
-    return float(smooth_l1(np.asarray(y) - np.asarray(target, dtype=np.float64)).mean())
+def pinball(r: np.ndarray, tau) -> np.ndarray:
+    """Elementwise pinball loss of the residual r = target - prediction at level
+    tau (broadcast over the last axis): tau r for r >= 0, (tau - 1) r below."""
+    tau = np.asarray(tau, dtype=np.float64)
+    return np.maximum(tau * r, (tau - 1.0) * r)
+
+
+def pinball_grad(r: np.ndarray, tau) -> np.ndarray:
+    """d pinball / d prediction: -tau where the target is above the prediction,
+    1 - tau where it is below, 0 where they are equal."""
+    tau = np.asarray(tau, dtype=np.float64) * np.ones_like(r)
+    return np.where(r > 0, -tau, np.where(r < 0, 1.0 - tau, 0.0))
+
+
+def loss(y: np.ndarray, target: np.ndarray, kind: str = "smooth_l1", tau=(0.5, 0.5)) -> float:
+    """Mean over rays and both outputs of SmoothL1 (beta = 1) or of the pinball
+    loss at levels tau = (tau_near, tau_far)."""
+    y = np.asarray(y, dtype=np.float64)
+    t = np.asarray(target, dtype=np.float64)
+    if kind == "pinball":
+        return float(pinball(t - y, tau).mean())
+    return float(smooth_l1(y - t).mean())
 
 
 def grad(theta: np.ndarray, X: np.ndarray, target: np.ndarray, J: int,
-         precision: str = "fp64") -> Tuple[float, np.ndarray]:
-    """Loss and its gradient with respect to the flat parameters, by the chain
-    rule written out layer by layer (backpropagation)."""
+         precision: str = "fp64", kind: str = "smooth_l1", tau=(0.5, 0.5)) -> Tuple[float, np.ndarray]:
+    """Loss (`kind`, levels `tau` for the pinball loss) and its gradient with
+    respect to the flat parameters, by the chain rule written out layer by
+    layer (backpropagation)."""
     p = unpack(theta, J)
     y, a = forward(theta, X, J, precision)
     t = np.asarray(target, dtype=np.float64)
     n = y.shape[0]
-    L = loss(y, t)
-    dy = smooth_l1_grad(y - t) / (2.0 * n)          # dL/dy
+    L = loss(y, t, kind, tau)
+    if kind == "pinball":
+        dy = pinball_grad(t - y, tau) / (2.0 * n)    # dL/dy
+    else:
+        dy = smooth_l1_grad(y - t) / (2.0 * n)      # dL/dy
     d4 = dy * y * (1.0 - y)                          # dL/dz4 (sigmoid')
     g = {"W4": _mm(d4.T, a["h3"], precision), "b4": d4.sum(axis=0)}
     d3 = _mm(d4, p["W4"], precision) * (a["z3"] > 0)

@@ -243,3 +243,45 @@ def test_bf16x3_product_is_near_exact():
     err = np.abs(mlp._mm(a, b, "bf16x3") - ref).max() / np.abs(ref).max()
     err1 = np.abs(mlp._mm(a, b, "bf16") - ref).max() / np.abs(ref).max()
     assert err < 2e-5 < err1
+
+
+def test_pinball_minimiser_is_the_quantile():
+    """Over a constant prediction the pinball loss at level tau is smallest at
+    the tau-quantile of the targets: brute force over every order statistic
+    (the minimum of a piecewise-linear convex function lies at one of its
+    breakpoints)."""
+    import oracle.mlp as mlp
+    rng = np.random.default_rng(14)
+    t = rng.uniform(0.0, 1.0, 501)
+    ts = np.sort(t)
+    for tau in (0.01, 0.1, 0.5, 0.9, 0.99):
+        losses = [mlp.pinball(t - c, tau).mean() for c in ts]
+        best = ts[int(np.argmin(losses))]
+        # the tau-quantile: the smallest order statistic with at least tau of the mass at or below it
+        k = int(np.ceil(tau * len(t))) - 1
+        assert best == ts[k], (tau, best, ts[k])
+
+
+def test_pinball_half_is_half_the_absolute_error():
+    import oracle.mlp as mlp
+    rng = np.random.default_rng(15)
+    y = rng.uniform(0, 1, (50, 2))
+    t = rng.uniform(0, 1, (50, 2))
+    assert np.allclose(mlp.loss(y, t, "pinball", (0.5, 0.5)), 0.5 * np.abs(y - t).mean(), rtol=0, atol=1e-15)
+    # one-sided weights: a prediction above the target costs 1 - tau per unit
+    assert np.isclose(mlp.loss(np.array([[0.7, 0.2]]), np.array([[0.5, 0.5]]), "pinball", (0.1, 0.9)),
+                      0.5 * ((1 - 0.1) * 0.2 + 0.9 * 0.3))
+
+
+def test_mlp_pinball_gradient_finite_differences():
+    mlp, theta, X, t = _problem(J=3, n=40, seed=16)
+    tau = (0.02, 0.97)
+    L, g = mlp.grad(theta, X, t, 3, kind="pinball", tau=tau)
+    rng = np.random.default_rng(17)
+    eps = 1e-6
+    for i in rng.choice(theta.size, 40, replace=False):
+        tp = theta.copy(); tp[i] += eps
+        tm = theta.copy(); tm[i] -= eps
+        lp = mlp.loss(mlp.forward(tp, X, 3)[0], t, "pinball", tau)
+        lm = mlp.loss(mlp.forward(tm, X, 3)[0], t, "pinball", tau)
+        assert abs((lp - lm) / (2 * eps) - g[i]) <= 1e-7 * max(1.0, np.abs(g).max()), i
