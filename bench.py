@@ -99,6 +99,12 @@ def parse():
     ap.add_argument("--margin-h", type=float, default=0.0,
                     help="proposal start margin in leaf edges (0: calibrated on held-out rays)")
     ap.add_argument("--f2-tau", type=float, default=-1.0)
+    ap.add_argument("--proposal-loss", choices=["smooth_l1", "pinball"], default="pinball",
+                    help="training loss of the proposal network (pinball: one-sided interval)")
+    ap.add_argument("--tau-near", type=float, default=0.03, help="pinball level of u_near")
+    ap.add_argument("--tau-far", type=float, default=0.97, help="pinball level of u_far")
+    ap.add_argument("--margin-quantile", type=float, default=0.99,
+                    help="quantile of the held-out late starts that the start margin covers")
     ap.add_argument("--err-poses", type=int, default=4, help="poses on which the proposal error is measured")
     ap.add_argument("--no-forms", action="store_true", help="skip the BF16-storage and adjoint legs")
     ap.add_argument("--copy-probe", action="store_true",
@@ -525,6 +531,7 @@ def proposal_leg(args, art, sg, torch):
     n_train = int(0.9 * len(ids))
     theta0 = sg.make_mlp_init(scene.J, seed=cfg.mlp_seed)
     r.set_proposal_weights(theta0)
+    r.set_proposal_loss(args.proposal_loss, (args.tau_near, args.tau_far))
     val0, _ = r.proposal_grad(od[n_train:n_train + 65536], pose[n_train:n_train + 65536], tgt[n_train:n_train + 65536])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -533,10 +540,16 @@ def proposal_leg(args, art, sg, torch):
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t1
     val1, _ = r.proposal_grad(od[n_train:n_train + 65536], pose[n_train:n_train + 65536], tgt[n_train:n_train + 65536])
-    margin = args.margin_h or r.calibrate_proposal_margin(od[n_train:], pose[n_train:], tgt[n_train:])
+    margin = args.margin_h or r.calibrate_proposal_margin(od[n_train:], pose[n_train:], tgt[n_train:],
+                                                          quantile=args.margin_quantile)
     print(f"[bench] proposal trained: {args.train_steps} steps in {t_train:.2f} s, validation loss "
           f"{val0:.4f} -> {val1:.4f}; start margin {margin:.1f} h", file=sys.stderr, flush=True)
     theta1 = r.get_proposal_weights()
+    # the untrained control's own calibrated margin (same rule, same held-out rays)
+    r.set_proposal_weights(theta0)
+    mu = args.margin_h or r.calibrate_proposal_margin(od[n_train:], pose[n_train:], tgt[n_train:],
+                                                      quantile=args.margin_quantile)
+    r.set_proposal_weights(theta1)
     del od, pose, tgt
     F = torch.empty((P, V, cfg.C, H, W), dtype=torch.float32, device="cuda")
     A = torch.empty((P, V, H, W), dtype=torch.float32, device="cuda")
@@ -554,13 +567,15 @@ def proposal_leg(args, art, sg, torch):
     Pe = min(args.err_poses, P)
     r.set_poses(poses[0][:Pe], poses[1][:Pe], poses[2][:Pe])
     F0, _, _ = r.render(sig, feat, lam, want_tfinal=False)
+    st0 = r.stats()
     F1, _, _ = r.render_proposal(sig, feat, None, lam, want_tfinal=False, **kw)
+    st1 = r.stats()
     den = float(F0.abs().sum())
     err_mean = float((F1 - F0).abs().sum()) / den
     err_max = max(float((F1[p, v] - F0[p, v]).abs().max() / F0[p, v].abs().max())
                   for p in range(Pe) for v in range(V))
     r.set_proposal_weights(theta0)
-    Fu, _, _ = r.render_proposal(sig, feat, None, lam, want_tfinal=False, **kw)
+    Fu, _, _ = r.render_proposal(sig, feat, None, lam, want_tfinal=False, **dict(kw, margin_h=mu))
     stu = r.stats()
     err_u = float((Fu - F0).abs().sum()) / den
     r.set_proposal_weights(theta1)
@@ -575,7 +590,11 @@ def proposal_leg(args, art, sg, torch):
         "rel_max_err": err_max,
         "err_poses": Pe,
         "margin_h": round(margin, 2),
-        "margin_rule": "calibrated: 99.9% quantile of late starts on held-out rays" if not args.margin_h else "fixed",
+        "margin_rule": (f"calibrated: {100 * args.margin_quantile:g}% quantile of late starts on held-out rays"
+                        if not args.margin_h else "fixed"),
+        "loss": (args.proposal_loss if args.proposal_loss == "smooth_l1" else
+                 f"pinball on rays with a sample (tau_near {args.tau_near}, tau_far {args.tau_far}), "
+                 f"SmoothL1 on empty labels"),
         "interval": "near end only (traversal from t_a + u_near (t_b - t_a) - m to t_b)",
         "f2_tau": args.f2_tau,
         "partition_steps_plain": st_plain["steps"],
@@ -586,8 +605,12 @@ def proposal_leg(args, art, sg, torch):
         "fallback_rate": round(st["fallbacks"] / max(st["proposal_rays"], 1), 4),
         "inference_ms": round(tm["proposal"], 3),
         "render_ms": round(tm["render"], 3),
-        "untrained_control": {"rel_mean_err": err_u,
+        "untrained_control": {"rel_mean_err": err_u, "margin_h": round(mu, 2),
+                              "partition_steps_first_poses": stu["steps"],
+                              "partition_steps_plain_first_poses": st0["steps"],
                               "fallback_rate": round(stu["fallbacks"] / max(stu["proposal_rays"], 1), 4)},
+        "trained_first_poses": {"partition_steps": st1["steps"], "rounds": st1["rounds"],
+                                "plain_rounds": st0["rounds"]},
         "training": {"rays": int(len(ids)), "train_rays": n_train, "steps": args.train_steps, "batch": 16384,
                      "seconds": round(t_train, 3), "first_loss": float(losses[0]), "last_loss": float(losses[-1]),
                      "val_loss_before": val0, "val_loss_after": val1,

@@ -441,8 +441,23 @@ art_status art_proposal_gather(art_ctx* ctx, int64_t n, const int64_t* ray_id, c
 art_status art_proposal_forward(art_ctx* ctx, int64_t n, const float* od, const int32_t* pose, float* out);
 
 /*
- * Loss L = mean over the n rays and both outputs of SmoothL1 (beta = 1)
- * between the network outputs and target (device float32 [n][2]), and its
+ * Training loss of the network (a context setting, used by
+ * art_proposal_grad and art_proposal_train): kind 0, SmoothL1 with beta = 1
+ * on both outputs (the default); kind 1, one-sided: on rays whose label holds
+ * a sample (u_near <= u_far) the pinball (quantile) loss
+ * rho_tau(t - y) = max(tau (t - y), (tau - 1) (t - y)) of target t and output y
+ * at level tau_near for u_near and tau_far for u_far, and SmoothL1 on rays with
+ * the empty label (1, 0), which keeps them predicted empty.  Minimised over a
+ * constant, the pinball loss gives the tau-quantile of the targets: a small
+ * tau_near makes late starts rare, a large tau_far early ends.
+ * Errors: ART_EINVAL (kind not 0 or 1; kind 1 with a level outside (0, 1)).
+ */
+art_status art_proposal_set_loss(art_ctx* ctx, int kind, float tau_near, float tau_far);
+
+/*
+ * Loss L = mean over the n rays and both outputs of the training loss
+ * (art_proposal_set_loss; SmoothL1 by default) between the network outputs
+ * and target (device float32 [n][2]), and its
  * gradient with respect to the weights: grad (device float32 [count]), loss
  * (device float32 [1]).  The weight gradients are contractions over rays on
  * the matrix cores (BF16 operands, the deltas stored in BF16); partial sums

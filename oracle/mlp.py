@@ -16,10 +16,13 @@ Network (all FP64 here):
 The pose code of a pose is, for every bone j, the first two columns of its
 local rotation Rot(r_j) (the 6-D rotation representation), column by column.
 Loss: mean over rays and both outputs of SmoothL1 with beta = 1 (default), or
-of the pinball (quantile) loss rho_tau(t - y) = max(tau (t - y), (tau - 1) (t - y))
-with a level tau per output: its minimiser over a constant is the
+the one-sided form: on rays whose label holds a sample (u_near <= u_far) the
+pinball (quantile) loss rho_tau(t - y) = max(tau (t - y), (tau - 1) (t - y))
+with a level tau per output - its minimiser over a constant is the
 tau-quantile of the targets, so a small tau for u_near makes late starts rare
-and a large one for u_far makes early ends rare (a one-sided interval).
+and a large one for u_far early ends - and SmoothL1 on rays with the empty
+label (1, 0), which keeps them predicted empty (a quantile of an empty
+interval has no meaning).
 Training: Adam with bias correction.
 
 Flat parameter order (FP32 on the GPU, the same order here):
@@ -167,13 +170,19 @@ def pinball_grad(r: np.ndarray, tau) -> np.ndarray:
     return np.where(r > 0, -tau, np.where(r < 0, 1.0 - tau, 0.0))
 
 
+def _hit_rows(t: np.ndarray) -> np.ndarray:
+    """Rays whose label holds a sample (u_near <= u_far), as a column mask."""
+    return (t[:, 0] <= t[:, 1])[:, None]
+
+
 def loss(y: np.ndarray, target: np.ndarray, kind: str = "smooth_l1", tau=(0.5, 0.5)) -> float:
-    """Mean over rays and both outputs of SmoothL1 (beta = 1) or of the pinball
-    loss at levels tau = (tau_near, tau_far)."""
+    """Mean over rays and both outputs of SmoothL1 (beta = 1), or of the
+    one-sided form: pinball at levels tau = (tau_near, tau_far) on rays with
+    a sample, SmoothL1 on rays with the empty label."""
     y = np.asarray(y, dtype=np.float64)
     t = np.asarray(target, dtype=np.float64)
     if kind == "pinball":
-        return float(pinball(t - y, tau).mean())
+        return float(np.where(_hit_rows(t), pinball(t - y, tau), smooth_l1(y - t)).mean())
     return float(smooth_l1(y - t).mean())
 
 
@@ -188,7 +197,7 @@ def grad(theta: np.ndarray, X: np.ndarray, target: np.ndarray, J: int,
     n = y.shape[0]
     L = loss(y, t, kind, tau)
     if kind == "pinball":
-        dy = pinball_grad(t - y, tau) / (2.0 * n)    # dL/dy
+        dy = np.where(_hit_rows(t), pinball_grad(t - y, tau), smooth_l1_grad(y - t)) / (2.0 * n)   # dL/dy
     else:
         dy = smooth_l1_grad(y - t) / (2.0 * n)      # dL/dy
     d4 = dy * y * (1.0 - y)                          # dL/dz4 (sigmoid')

@@ -286,8 +286,15 @@ class Renderer:
                                                   _tptr(pose.contiguous()), _tptr(out)), "art_proposal_forward")
         return out
 
+    def set_proposal_loss(self, kind: str = "smooth_l1", tau=(0.5, 0.5)) -> None:
+        """Training loss of the network: "smooth_l1" or "pinball" at levels
+        tau = (tau_near, tau_far) (art_proposal_set_loss)."""
+        k = {"smooth_l1": 0, "pinball": 1}[kind]
+        self._check(self.lib.art_proposal_set_loss(self._h, k, float(tau[0]), float(tau[1])),
+                    "art_proposal_set_loss")
+
     def proposal_grad(self, od, pose, target):
-        """(loss, gradient [count]) of the mean SmoothL1 loss over the rays."""
+        """(loss, gradient [count]) of the mean training loss over the rays."""
         torch = self._torch
         g = torch.empty((self.proposal_param_count(),), dtype=torch.float32, device=od.device)
         L = torch.empty((1,), dtype=torch.float32, device=od.device)

@@ -60,6 +60,7 @@ SIGNATURES = [
     ("art_proposal_set_weights", _I, [_P, _L, _P]),
     ("art_proposal_get_weights", _I, [_P, _L, _P]),
     ("art_proposal_gather", _I, [_P, _L, _P, _P, _P, _P, _P]),
+    ("art_proposal_set_loss", _I, [_P, _I, _F, _F]),
     ("art_proposal_calibrate", _I, [_P, _L, _P, _P, _P, _F, _F, ctypes.POINTER(_F)]),
     ("art_proposal_io", _I, [_P, _I, ctypes.c_char_p]),
     ("art_map_loss", _I, [_P, _L, _L, _P, _P, _P, _P, _P, _P, ctypes.POINTER(ctypes.c_double)]),

@@ -1501,6 +1501,17 @@ art_status art_proposal_forward(art_ctx* ctx, int64_t n, const float* od, const 
     return check_bad_pose(ctx);
 }
 
+art_status art_proposal_set_loss(art_ctx* ctx, int kind, float tau_near, float tau_far) {
+    if (!ctx) return ART_EINVAL;
+    if (kind != 0 && kind != 1) return fail(ctx, ART_EINVAL, "loss kind must be 0 (SmoothL1) or 1 (pinball)");
+    if (kind == 1 && !(tau_near > 0.0f && tau_near < 1.0f && tau_far > 0.0f && tau_far < 1.0f))
+        return fail(ctx, ART_EINVAL, "pinball levels must be in (0, 1)");
+    ctx->mlp_loss_fn.kind = kind;
+    ctx->mlp_loss_fn.tau[0] = kind == 1 ? tau_near : 0.5f;
+    ctx->mlp_loss_fn.tau[1] = kind == 1 ? tau_far : 0.5f;
+    return ART_OK;
+}
+
 art_status art_proposal_grad(art_ctx* ctx, int64_t n, const float* od, const int32_t* pose, const float* target,
                              float* grad, float* loss) {
     if (!ctx) return ART_EINVAL;
@@ -1518,7 +1529,7 @@ art_status art_proposal_grad(art_ctx* ctx, int64_t n, const float* od, const int
     ART_TRY_HIP(launch_mlp_grad(ctx->mlp_packed.as<uint16_t>(), ctx->mlp_theta.as<float>(), ctx->mlp_cbias.as<float>(),
                                 ctx->mlp_code.as<float>(), m, od, pose, target, ctx->P, n, ctx->mlp_S.as<float>(),
                                 ctx->mlp_part.as<float>(), ctx->mlp_lossp.as<float>(), ctx->mlp_flag.as<uint32_t>(),
-                                st),
+                                ctx->mlp_loss_fn, st),
                 "proposal gradient");
     ART_TRY_HIP(launch_mlp_reduce(ctx->mlp_part.as<float>(), n, m, grad, ctx->mlp_theta.as<float>(), nullptr, nullptr,
                                   nullptr, ctx->mlp_lossp.as<float>(), loss, st),
@@ -1559,7 +1570,7 @@ art_status art_proposal_train(art_ctx* ctx, int64_t n, const float* od, const in
                                     ctx->mlp_cbias.as<float>(), ctx->mlp_code.as<float>(), m, od + off * 6,
                                     pose + off, target + off * 2, ctx->P, batch, ctx->mlp_S.as<float>(),
                                     ctx->mlp_part.as<float>(), ctx->mlp_lossp.as<float>(),
-                                    ctx->mlp_flag.as<uint32_t>(), st),
+                                    ctx->mlp_flag.as<uint32_t>(), ctx->mlp_loss_fn, st),
                     "proposal gradient");
         const int64_t t = ++ctx->mlp_step;
         AdamStep ad;

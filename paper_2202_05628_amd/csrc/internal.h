@@ -41,6 +41,14 @@ struct DevBuf {
 
 // Parameter layout of the proposal network for J bones (flat FP32 vector:
 // W1 [64][n_in], b1, W2 [64][64], b2, W3 [64][64], b3, W4 [2][64], b4).
+// Loss of the proposal network: 0 SmoothL1 (beta = 1); 1 one-sided: pinball
+// at levels tau[0] (u_near) and tau[1] (u_far) on rays whose label holds a
+// sample, SmoothL1 on rays with the empty label.
+struct MlpLoss {
+    int kind = 0;
+    float tau[2] = {0.5f, 0.5f};
+};
+
 struct MlpDims {
     int J, n_in, np;
     int oW1, ob1, oW2, ob2, oW3, ob3, oW4, ob4;
@@ -156,6 +164,7 @@ struct art_ctx {
     // learned ray-interval proposal
     int mlp_J = 0;                 // skeleton size the weights were set for (0: none)
     int64_t mlp_step = 0;          // Adam steps taken since the weights were set
+    art::MlpLoss mlp_loss_fn;      // training loss (art_proposal_set_loss)
     art::DevBuf mlp_theta, mlp_m1, mlp_m2;   // FP32 master weights and Adam moments
     art::DevBuf mlp_packed;        // BF16 matrix-core operands
     art::DevBuf mlp_cbias;         // [P][64] per-pose first-layer bias
@@ -369,7 +378,8 @@ hipError_t launch_mlp_forward(const uint16_t* packed, const float* theta, const 
                               hipStream_t st);
 hipError_t launch_mlp_grad(const uint16_t* packed, const float* theta, const float* cbias, const float* code,
                            const MlpDims& m, const float* od, const int32_t* pose, const float* target, int P,
-                           int64_t n, float* S, float* part, float* loss_part, uint32_t* bad, hipStream_t st);
+                           int64_t n, float* S, float* part, float* loss_part, uint32_t* bad, const MlpLoss& loss,
+                           hipStream_t st);
 hipError_t launch_mlp_reduce(const float* part, int64_t n, const MlpDims& m, float* grad, float* theta, float* m1,
                              float* m2, const AdamStep* adam, const float* loss_part, float* loss_out,
                              hipStream_t st);

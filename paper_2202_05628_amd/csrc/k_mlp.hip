@@ -358,8 +358,9 @@ struct FbArgs {
     float* out;               // [n][2] (mode 0)
     int64_t n, n_pad;         // n_pad: multiple of kChunk
     float* S;                 // [kRows][n_pad] (mode 1)
-    float* loss_part;         // [gridDim.x] sums of SmoothL1 over rays and outputs
+    float* loss_part;         // [gridDim.x] sums of the loss over rays and outputs
     float inv2n;              // 1 / (2 n)
+    MlpLoss loss;             // SmoothL1 or pinball (levels per output)
     int mode;
     int P;                    // valid pose ids: 0..P-1
     uint32_t* bad;            // set to 1 when a pose id is out of range
@@ -367,6 +368,10 @@ struct FbArgs {
 
 __device__ inline float smooth_l1f(float e) { const float a = fabsf(e); return a < 1.0f ? 0.5f * e * e : a - 0.5f; }
 __device__ inline float smooth_l1_gradf(float e) { return fabsf(e) < 1.0f ? e : (e > 0.0f ? 1.0f : -1.0f); }
+// pinball loss of the error e = prediction - target at level tau, and its
+// derivative with respect to the prediction
+__device__ inline float pinballf(float e, float tau) { return e > 0.0f ? (1.0f - tau) * e : -tau * e; }
+__device__ inline float pinball_gradf(float e, float tau) { return e > 0.0f ? 1.0f - tau : (e < 0.0f ? -tau : 0.0f); }
 
 __device__ inline void store_tiles(float* S, int64_t stride, int row0, int64_t ray, int g, const f32x4* t, int nt) {
     for (int mt = 0; mt < nt; ++mt)
@@ -415,10 +420,20 @@ __device__ inline void fb_body(const FbArgs& a, int lane, int w, float* sloss) {
         // loss and dL/dz4 (lanes of group 0 hold the two outputs of ray r)
         float d40 = 0.0f, d41 = 0.0f;
         if (valid && g == 0) {
-            const float e0 = y0 - a.target[ray * 2], e1 = y1 - a.target[ray * 2 + 1];
-            lsum += smooth_l1f(e0) + smooth_l1f(e1);
-            d40 = smooth_l1_gradf(e0) * a.inv2n * y0 * (1.0f - y0);
-            d41 = smooth_l1_gradf(e1) * a.inv2n * y1 * (1.0f - y1);
+            const float t0 = a.target[ray * 2], t1 = a.target[ray * 2 + 1];
+            const float e0 = y0 - t0, e1 = y1 - t1;
+            float g0, g1;
+            if (a.loss.kind == 1 && t0 <= t1) {   // one-sided form: pinball on rays with a sample
+                lsum += pinballf(e0, a.loss.tau[0]) + pinballf(e1, a.loss.tau[1]);
+                g0 = pinball_gradf(e0, a.loss.tau[0]);
+                g1 = pinball_gradf(e1, a.loss.tau[1]);
+            } else {
+                lsum += smooth_l1f(e0) + smooth_l1f(e1);
+                g0 = smooth_l1_gradf(e0);
+                g1 = smooth_l1_gradf(e1);
+            }
+            d40 = g0 * a.inv2n * y0 * (1.0f - y0);
+            d41 = g1 * a.inv2n * y1 * (1.0f - y1);
         }
         store_tiles(a.S, a.n_pad, kRowH1, ray, g, h1, 4);
         store_tiles(a.S, a.n_pad, kRowH2, ray, g, h2, 4);
@@ -757,8 +772,10 @@ hipError_t launch_mlp_forward(const uint16_t* packed, const float* theta, const 
 
 hipError_t launch_mlp_grad(const uint16_t* packed, const float* theta, const float* cbias, const float* code,
                            const MlpDims& m, const float* od, const int32_t* pose, const float* target, int P,
-                           int64_t n, float* S, float* part, float* loss_part, uint32_t* bad, hipStream_t st) {
+                           int64_t n, float* S, float* part, float* loss_part, uint32_t* bad, const MlpLoss& loss,
+                           hipStream_t st) {
     FbArgs a{};
+    a.loss = loss;
     a.P = P;
     a.bad = bad;
     a.packed = packed;

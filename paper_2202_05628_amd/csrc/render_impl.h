@@ -567,7 +567,7 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
         if (pass == 1) {
             // F1: the proposed interval held no occupied voxel; F2: the ray left
             // it with transmittance above the threshold before the root's exit.
-            // Such lanes restart from t_a with the whole ray.
+            // Such lanes restart from t_a.
             // the whole span is recomputed rather than kept in registers
             R ta_full, tb_full;
             root_span<R>(d, q, inv, h, G, ta_full, tb_full);
@@ -575,13 +575,19 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
             if (__ballot(fb) == 0ull) break;
             active = fb;
             if (fb) {
+                // With the interval ending at t_b (near end only), F1 means that
+                // [t_s, t_b] held no occupied voxel - the cell holding t_s
+                // included, since a sub-chord of a cell has its midpoint in that
+                // cell - so every sample of the full traversal lies in
+                // [t_a, t_s): only that part is traversed again.
+                const bool front_only = a.near_only && nsamp == 0;
                 T = 1.0f;
                 Aacc = 0.0f;
 #pragma unroll
                 for (int c = 0; c < C; ++c) F[c] = 0.0f;
                 nsamp = 0;
+                tb = front_only ? ta : tb_full;
                 ta = ta_full;
-                tb = tb_full;
                 nfall = 1;
             }
             inb = false;

@@ -150,13 +150,16 @@ def test_argument_errors(net):
 
 def test_training_lowers_the_loss_and_guides_the_traversal(net):
     """Train on labels of the plain renderer (seeded rays, about half with a
-    composited sample), calibrate the start margin on held-out rays, then
-    render with the network's intervals (front skipping only): the error
-    against the plain render stays within 1e-3 (rel_mean).  What the trained
-    network gains over the untrained one (the control): a much lower held-out
-    loss and start estimates closer to the true entry; the partition steps it
-    saves are recorded (on this coarse scene the calibrated margin covers most
-    of the empty front)."""
+    composited sample) with the one-sided loss (pinball at levels 0.03 / 0.97
+    on rays with a sample, SmoothL1 on empty labels), calibrate the start
+    margin on held-out rays (99 % of the late starts covered), then render
+    with the network's intervals (front skipping only).  Gain criterion: the
+    guided render takes fewer partition steps than the plain render with the
+    error against it within 1e-3 (rel_mean).  The trained network meets it;
+    the untrained network, calibrated by the same rule, does not (its margin
+    covers the whole front: no step is saved).  The wave rounds are not
+    asserted: the lanes that fall back (F1) cost the tile a second pass over
+    its brick list, which on this scene outweighs the saved steps."""
     import torch
     rend, s = net["rend"], net["s"]
     sig = torch.from_numpy(s.sigma).cuda()
@@ -168,39 +171,73 @@ def test_training_lowers_the_loss_and_guides_the_traversal(net):
     F0, _, _ = rend.render(sig, f, 0.01)
     steps0 = rend.stats()["steps"]
     theta0 = sg.make_mlp_init(s.J)
+    val = slice(54000, None)
+
+    def guided(q=0.99):
+        m = rend.calibrate_proposal_margin(od[val], pose[val], tgt[val], quantile=q)
+        Fg, _, _ = rend.render_proposal(sig, f, None, 0.01, margin_h=m, near_only=True)
+        st = rend.stats()
+        return m, float((Fg - F0).abs().sum() / F0.abs().sum()), st["steps"], st
+
+    rend.set_proposal_loss("pinball", (0.03, 0.97))
     rend.set_proposal_weights(theta0)
-    L0, _ = rend.proposal_grad(od[54000:], pose[54000:], tgt[54000:])
-    log_ = rend.proposal_train(od[:54000], pose[:54000], tgt[:54000], batch=4096, steps=1500, lr=3e-3)
-    L1, _ = rend.proposal_grad(od[54000:], pose[54000:], tgt[54000:])
+    mu, err_u, steps_u, _ = guided()
+    L0, _ = rend.proposal_grad(od[val], pose[val], tgt[val])
+    log_ = rend.proposal_train(od[:54000], pose[:54000], tgt[:54000], batch=4096, steps=6000, lr=3e-3)
+    L1, _ = rend.proposal_grad(od[val], pose[val], tgt[val])
     log(f"  train loss {log_[0]:.4f} -> {log_[-1]:.4f}; validation {L0:.4f} -> {L1:.4f}")
     assert L1 < 0.3 * L0
-    margin = rend.calibrate_proposal_margin(od[54000:], pose[54000:], tgt[54000:])
-    Ft, _, _ = rend.render_proposal(sig, f, None, 0.01, margin_h=margin, near_only=True)
-    st = rend.stats()
-    err = float((Ft - F0).abs().sum() / F0.abs().sum())
-    trained = rend.get_proposal_weights()
-    rend.set_proposal_weights(theta0)
-    Fu, _, _ = rend.render_proposal(sig, f, None, 0.01, margin_h=margin, near_only=True)
-    stu = rend.stats()
-    err_u = float((Fu - F0).abs().sum() / F0.abs().sum())
-    rend.set_proposal_weights(trained)
-    log(f"  calibrated margin {margin:.1f} h: rel_mean {err:.2e}, steps {st['steps']} vs plain {steps0} "
-        f"(fallbacks {st['fallbacks']} of {st['proposal_rays']}); untrained: rel_mean {err_u:.2e}, steps "
-        f"{stu['steps']} (fallbacks {stu['fallbacks']} of {stu['proposal_rays']})")
-    assert err <= 1e-3
+    mt, err, steps_t, st = guided()
+    log(f"  trained: margin {mt:.2f} h, rel_mean {err:.2e}, steps {steps_t} vs plain {steps0} "
+        f"(fallbacks {st['fallbacks']} of {st['proposal_rays']}); untrained: margin {mu:.2f} h, "
+        f"rel_mean {err_u:.2e}, steps {steps_u}")
+    assert err <= 1e-3 and steps_t < steps0          # the trained network saves work within the bar
+    assert not (err_u <= 1e-3 and steps_u < steps0)  # the control does not
+    assert steps_u == steps0
     # start estimates of the held-out hit rays: trained vs untrained network
-    val = slice(54000, None)
     hitv = (tgt[val, 0] <= tgt[val, 1]).cpu().numpy()
     yt = rend.proposal_forward(od[val], pose[val]).cpu().numpy()
+    trained = rend.get_proposal_weights()
     rend.set_proposal_weights(theta0)
     yu = rend.proposal_forward(od[val], pose[val]).cpu().numpy()
     rend.set_proposal_weights(trained)
+    rend.set_proposal_loss("smooth_l1")
     tv = tgt[val].cpu().numpy()
-    mae_t = float(np.abs(yt[hitv, 0] - tv[hitv, 0]).mean())
-    mae_u = float(np.abs(yu[hitv, 0] - tv[hitv, 0]).mean())
-    log(f"  held-out |u_near error| on hit rays: trained {mae_t:.4f}, untrained {mae_u:.4f}; "
-        f"steps saved {steps0 - st['steps']} of {steps0}")
-    assert mae_t < 0.5 * mae_u
+    # the pinball level 0.03 asks for late starts on about 3 % of the rays
+    late_t = float((yt[hitv, 0] > tv[hitv, 0]).mean())
+    late_u = float((yu[hitv, 0] > tv[hitv, 0]).mean())
+    over_t = float(np.maximum(yt[hitv, 0] - tv[hitv, 0], 0.0).mean())
+    over_u = float(np.maximum(yu[hitv, 0] - tv[hitv, 0], 0.0).mean())
+    log(f"  held-out hit rays starting late: trained {late_t:.4f} (mean late part {over_t:.5f}), "
+        f"untrained {late_u:.4f} ({over_u:.5f})")
+    assert late_t <= 0.1
+    assert over_t < 0.5 * over_u
+
+
+def test_pinball_gradient_matches_oracle(net):
+    """The one-sided loss (pinball on rays with a sample, SmoothL1 on empty
+    labels) and its gradient on the GPU against the oracle network, in FP64
+    and in the oracle's emulation of the split-BF16 training products."""
+    import torch
+    rend, dev = net["rend"], net["dev"]
+    J = net["s"].J
+    tau = (0.05, 0.9)
+    tgt = net["tgt"].copy()
+    tgt[::4] = (1.0, 0.0)   # every fourth ray with the empty label
+    rend.set_proposal_weights(net["theta"].astype(np.float32))   # the fixture's weights (earlier tests train)
+    rend.set_proposal_loss("pinball", tau)
+    try:
+        L, g = rend.proposal_grad(dev["od"], dev["pose"], torch.from_numpy(tgt.astype(np.float32)).cuda())
+    finally:
+        rend.set_proposal_loss("smooth_l1")
+    g = g.cpu().numpy().astype(np.float64)
+    L64, g64 = omlp.grad(net["theta"], net["X"], tgt, J, kind="pinball", tau=tau)
+    L48, g48 = omlp.grad(net["theta"], net["X"], tgt, J, precision="bf16x3", kind="pinball", tau=tau)
+    log(f"pinball loss {L:.6f} vs oracle {L64:.6f}; gradient vs fp64 {_rel_max(g, g64):.2e}, "
+        f"vs split form {_rel_max(g, g48):.2e}")
+    assert abs(L - L64) <= 1e-4 * abs(L64)
+    assert _rel_max(g, g48) <= TOL_FORM
+    assert _rel_max(g, g64) <= TOL_FP64
 
 
 @pytest.mark.parametrize("H,W", [(64, 64), (40, 52)])

@@ -266,15 +266,21 @@ def test_pinball_half_is_half_the_absolute_error():
     import oracle.mlp as mlp
     rng = np.random.default_rng(15)
     y = rng.uniform(0, 1, (50, 2))
-    t = rng.uniform(0, 1, (50, 2))
+    t = np.sort(rng.uniform(0, 1, (50, 2)), axis=1)     # labels with a sample: u_near <= u_far
     assert np.allclose(mlp.loss(y, t, "pinball", (0.5, 0.5)), 0.5 * np.abs(y - t).mean(), rtol=0, atol=1e-15)
     # one-sided weights: a prediction above the target costs 1 - tau per unit
     assert np.isclose(mlp.loss(np.array([[0.7, 0.2]]), np.array([[0.5, 0.5]]), "pinball", (0.1, 0.9)),
                       0.5 * ((1 - 0.1) * 0.2 + 0.9 * 0.3))
+    # rays with the empty label (1, 0) keep SmoothL1
+    ye = np.array([[0.3, 0.6]])
+    te = np.array([[1.0, 0.0]])
+    assert np.isclose(mlp.loss(ye, te, "pinball", (0.01, 0.99)), mlp.loss(ye, te))
 
 
 def test_mlp_pinball_gradient_finite_differences():
     mlp, theta, X, t = _problem(J=3, n=40, seed=16)
+    t[::3] = (1.0, 0.0)   # every third ray with the empty label
+    assert (t[:, 0] <= t[:, 1]).sum() > 5
     tau = (0.02, 0.97)
     L, g = mlp.grad(theta, X, t, 3, kind="pinball", tau=tau)
     rng = np.random.default_rng(17)
