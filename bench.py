@@ -359,6 +359,9 @@ def bf16_leg(args, art, sg, torch):
             "mrays_s": round(rays / t / 1e6, 2), "ms_per_step": round(t * 1e3, 3),
             "render_ms": round(tm["render"], 3),
             "render_hbm_frac": round(per_launch / avg / 1e9 / HBM_PEAK_GBS, 4),
+            "render_launches": tm["n_render"], "avg_launch_us": round(avg * 1e6, 2),
+            "samples": st["samples"], "tile_rays": st["tile_rays"],
+            "algorithmic_bytes_per_launch": int(per_launch),
             "algorithmic_bytes_per_sample": 2 * (cfg.C + 1) + 4}
 
 
@@ -470,7 +473,8 @@ def adjoint_leg(args, art, sg, torch):
     return {"workload": f"adjoint: {P} pose x {V} cameras at {H}x{W} ({rays} rays), L2 loss to seeded targets",
             "mrays_s": round(rays / t / 1e6, 2), "ms_per_call": round(t * 1e3, 3),
             "ms_per_call_reusing_forward_octrees": round(t_reuse * 1e3, 3),
-            "adjoint_kernel_ms": round(kern_ms, 4), "samples": st["samples"],
+            "adjoint_kernel_ms": round(kern_ms, 4), "samples": st["samples"], "tile_rays": st["tile_rays"],
+            "algorithmic_bytes_per_launch": int(alg),
             "algorithmic_bytes_per_sample": per_sample, "algorithmic_bytes_per_ray": per_ray,
             "adjoint_hbm_frac": round(alg / (kern_ms * 1e-3) / 8e12, 4)}
 
