@@ -479,6 +479,38 @@ def adjoint_leg(args, art, sg, torch):
             "adjoint_hbm_frac": round(alg / (kern_ms * 1e-3) / 8e12, 4)}
 
 
+def adjoint_main_leg(args, r, sig, feat, out, torch, C, rays):
+    """The adjoint kernel on the main workload (30 poses x 8 cameras at
+    512^2): L = 1/2 |F - F*|^2 to seeded N(0, 1) targets, one backward call
+    after the forward.  The differentiation workload (1 pose x 4 cameras)
+    holds about 2,600 non-empty tiles, fewer than the GPU has wave slots, so
+    its time is the serial chain of its longest rays; here the kernel has
+    enough tiles to show its throughput."""
+    F, A, T = out
+    g = torch.Generator(device="cuda")
+    g.manual_seed(3)
+    dF = torch.randn(F.shape, generator=g, device="cuda", dtype=torch.float32)
+    dF.sub_(F).neg_()                                     # dL/dF = F - F*
+    ds = torch.zeros_like(sig)
+    df = torch.zeros_like(feat)
+    r.render(sig, feat, args.lambda_th, out=out)
+    st = r.stats()
+    r.backward(sig, feat, F, T, dF, None, args.lambda_th, d_sigma=ds, d_feat=df, reuse_build=True)   # warm-up
+    r.render(sig, feat, args.lambda_th, out=out)
+    r.backward(sig, feat, F, T, dF, None, args.lambda_th, d_sigma=ds, d_feat=df, reuse_build=True, timing=True)
+    tm = r.timing()
+    per_sample = 4 * (C + 1) + 4 + 4 * (C + 1)
+    per_ray = 4 * C + 4 * C + 4
+    alg = st["samples"] * per_sample + st["tile_rays"] * per_ray
+    kern_ms = tm["render"] / max(tm["n_render"], 1)
+    del dF, ds, df
+    return {"workload": "adjoint on the main workload (30 poses x 8 cameras at 512x512), L2 loss to seeded targets",
+            "adjoint_kernel_ms": round(kern_ms, 3), "launches": tm["n_render"], "samples": st["samples"],
+            "algorithmic_bytes_per_launch": int(alg / max(tm["n_render"], 1)),
+            "adjoint_hbm_frac": round(alg / max(tm["n_render"], 1) / (kern_ms * 1e-3) / 8e12, 4),
+            "mrays_s_kernel": round(rays / (tm["render"] * 1e-3) / 1e6, 2)}
+
+
 def train_leg(args, art, sg, torch):
     """FLUT training step on the differentiation workload (1 pose x 4 cameras at
     512^2, C = 16, FP32): render, L2 map loss to seeded targets, adjoint,
@@ -741,6 +773,8 @@ def main():
         if cfg.storage == "f32":
             print("[bench] view-dependent features", file=sys.stderr, flush=True)
             line["sh_form"] = sh_leg(args, r, scene, out, fp32_geom, torch, cfg.C, rays_per_step)
+            print("[bench] adjoint on the main workload", file=sys.stderr, flush=True)
+            line["adjoint_main_workload"] = adjoint_main_leg(args, r, sig, feat, out, torch, cfg.C, rays_per_step)
     del Fm, Am, Tm, out
     torch.cuda.empty_cache()
     if not args.no_forms:
