@@ -25,7 +25,8 @@
  *   (e.g. torch tensors) that must stay valid until the call returns.
  * - Every device write happens on the HIP stream given to art_create.
  *   art_render and art_backward synchronise that stream before returning, so
- *   their outputs are complete when they return.
+ *   their outputs are complete when they return - unless called with
+ *   ART_ASYNC (see there and art_render_status).
  * - Canonical grid: depth D, 2^D cells per axis over [-1/2, 1/2]^3, leaf edge
  *   h = 2^-D; leaf centre p = -1/2 + (ijk + 1/2) h.
  * - Posed grid: [-1, 1]^3 with the same leaf edge, G = 2^(D+1) cells per axis;
@@ -70,6 +71,18 @@ typedef enum { ART_F32 = 0, ART_BF16 = 1 } art_dtype;
                               cameras, ART_GEOM_FP32) changed since, and no other
                               call rebuilt them; otherwise they are rebuilt, as
                               without the flag.  The FLUT does not enter them.     */
+#define ART_ASYNC 16u      /* render calls and art_backward: enqueue the work and
+                              return without synchronising the stream, when the
+                              poses fit one batch of the context's working memory
+                              (else the call is synchronous).  The call uses the
+                              tile-list capacity earlier calls established: a
+                              (pose, view group) whose lists overflow is not
+                              rendered (its maps are unspecified), and a negative
+                              or non-finite density makes the call render
+                              nothing, without an error.  art_render_status
+                              reports both, and the statistics, for the last
+                              call; a later call grows the lists as needed.
+                              Excludes ART_TIMING.                                 */
 
 /* Library version (major * 10000 + minor * 100 + patch). */
 int art_version(void);
@@ -557,6 +570,20 @@ art_status art_get_octree(art_ctx* ctx, int pose, unsigned flags, int64_t* count
 art_status art_get_hits(art_ctx* ctx, int pose, int view, int C, art_dtype dtype,
                         const void* sigma, const void* feat, float lambda_th, unsigned flags,
                         int max_hits, int32_t* leaf, double* delta, int32_t* count);
+
+/*
+ * Outcome of the last render / backward call made with ART_ASYNC: synchronises
+ * the context's stream, then *overflowed_items receives the number of
+ * (pose, view group) items whose tile lists overflowed (their maps were not
+ * rendered: render them again, the next call has the capacity) and
+ * *bad_densities the number of negative or non-finite FLUT densities (the
+ * call rendered nothing); art_get_stats then holds that call's counters.
+ * Both 0 when the last call was synchronous (it reported such errors itself).
+ * Either pointer may be NULL.  Call it before the next render call on the
+ * context, which starts a new record.
+ * Errors: ART_EINVAL (NULL ctx), ART_EDEVICE.
+ */
+art_status art_render_status(art_ctx* ctx, int64_t* overflowed_items, int64_t* bad_densities);
 
 /*
  * Counters of the last render / backward / label call, host int64 [14]:

@@ -152,14 +152,16 @@ class Renderer:
         dtype = ART_BF16 if sigma.dtype == torch.bfloat16 else ART_F32
         return int(feat.shape[1]), dtype
 
-    def _flags(self, fp32_geom: bool, timing: bool) -> int:
-        return (ART_GEOM_FP32 if fp32_geom else 0) | (ART_TIMING if timing else 0)
+    def _flags(self, fp32_geom: bool, timing: bool, sync: bool = True) -> int:
+        return (ART_GEOM_FP32 if fp32_geom else 0) | (ART_TIMING if timing else 0) | (0 if sync else _lib.ART_ASYNC)
 
     # ---- rendering ------------------------------------------------------------------
     def render(self, sigma, feat, lambda_th: float = LAMBDA_TH, fp32_geom: bool = False,
-               timing: bool = False, out=None, want_tfinal: bool = True):
+               timing: bool = False, out=None, want_tfinal: bool = True, sync: bool = True):
         """Feature maps [P][V][C][H][W], opacity [P][V][H][W], final transmittance
-        [P][V][H][W] (or None) for every pose and camera."""
+        [P][V][H][W] (or None) for every pose and camera.  sync=False: the call
+        only enqueues the work (ART_ASYNC); render_status() reports overflows
+        and invalid densities afterwards."""
         torch = self._torch
         C, dtype = self._flut(sigma, feat)
         dev = sigma.device
@@ -170,9 +172,17 @@ class Renderer:
         else:
             F, A, T = out
         self._check(self.lib.art_render(self._h, C, dtype, _tptr(sigma), _tptr(feat), float(lambda_th),
-                                        self._flags(fp32_geom, timing), _tptr(F), _tptr(A), _tptr(T)),
+                                        self._flags(fp32_geom, timing, sync), _tptr(F), _tptr(A), _tptr(T)),
                     "art_render")
         return F, A, T
+
+    def render_status(self) -> dict:
+        """Outcome of the last call made with sync=False (art_render_status):
+        overflowed (pose, view group) items and invalid densities."""
+        ov = ctypes.c_int64(0)
+        bad = ctypes.c_int64(0)
+        self._check(self.lib.art_render_status(self._h, ctypes.byref(ov), ctypes.byref(bad)), "art_render_status")
+        return {"overflowed_items": int(ov.value), "bad_densities": int(bad.value)}
 
     def render_depth(self, sigma, feat, depth_sigma: float, lambda_th: float = LAMBDA_TH, fp32_geom: bool = False,
                      timing: bool = False, out=None, want_tfinal: bool = True):

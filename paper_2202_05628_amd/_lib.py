@@ -19,6 +19,7 @@ ART_TIMING = 2
 ART_PROPOSAL_MARGIN_H = 2.0
 ART_PROPOSAL_NEAR_ONLY = 4
 ART_REUSE_BUILD = 8
+ART_ASYNC = 16
 ART_SHADING_NOALLOC_BYTES = 100663296
 
 STATUS_NAMES = {0: "ART_OK", -1: "ART_EINVAL", -2: "ART_ENOMEM", -3: "ART_EDEVICE",
@@ -72,6 +73,7 @@ SIGNATURES = [
     ("art_get_octree", _I, [_P, _I, _U, _P, _P, _P, _P, _P, _P]),
     ("art_get_hits", _I, [_P, _I, _I, _I, _I, _P, _P, _F, _U, _I, _P, _P, _P]),
     ("art_get_stats", _I, [_P, _P]),
+    ("art_render_status", _I, [_P, _P, _P]),
     ("art_get_timing", _I, [_P, _P, _P]),
 ]
 

@@ -125,7 +125,9 @@ art_status check_render_state(art_ctx* ctx) {
 art_status plan_call(art_ctx* ctx, int C, art_dtype dtype, unsigned flags, CallPlan* pl) {
     if (!supported_C(C)) return fail(ctx, ART_EUNSUPPORTED, "C must be 4, 8, 16 or 32");
     if (dtype != ART_F32 && dtype != ART_BF16) return fail(ctx, ART_EINVAL, "dtype must be ART_F32 or ART_BF16");
-    if (flags & ~(ART_GEOM_FP32 | ART_TIMING)) return fail(ctx, ART_EINVAL, "unknown flag bits");
+    if (flags & ~(ART_GEOM_FP32 | ART_TIMING | ART_ASYNC)) return fail(ctx, ART_EINVAL, "unknown flag bits");
+    if ((flags & ART_ASYNC) && (flags & ART_TIMING))
+        return fail(ctx, ART_EINVAL, "ART_ASYNC and ART_TIMING exclude each other");
     pl->C = C;
     pl->storage = dtype == ART_BF16 ? 1 : 0;
     pl->fp32 = (flags & ART_GEOM_FP32) != 0;
@@ -589,6 +591,10 @@ art_status render_call(art_ctx* ctx, int C, art_dtype dtype, const void* sigma, 
     tm.pool = &ctx->ev_pool;
     const bool whole = pose_lo == 0 && pose_hi == ctx->P && slots >= P;   // one batch, every pose
     const bool reuse = o.reuse && whole && memo_matches(ctx, pl);
+    // ART_ASYNC: nothing is read back when the poses fit one batch (otherwise
+    // the slots are reused and the call stays synchronous)
+    const bool async = (flags & ART_ASYNC) != 0 && slots >= P;
+    ctx->async_pending = false;
 
     ART_TRY_HIP(launch_fill_u32(ctx->s.stats.as<uint32_t>(), 0u, 32, st), "fill");
     ART_TRY_HIP(launch_check_sigma(sigma, pl.storage, ctx->n, ctx->s.stats.as<unsigned long long>() + kStatBadSigma,
@@ -611,6 +617,12 @@ art_status render_call(art_ctx* ctx, int C, art_dtype dtype, const void* sigma, 
         const size_t items = (size_t)(p1 - p0) * pl.ngroups;
         rc = run_batch(ctx, pl, mode, lambda, sigma, feat, o, p0, p1, nullptr, &launches, tm, reuse);
         if (rc != ART_OK) return rc;
+        if (async) {   // art_render_status reads the overflow flags and statistics
+            ctx->async_pending = true;
+            ctx->async_items = items;
+            ctx->async_launches = launches;
+            return ART_OK;
+        }
         // a (pose, view group) whose tile lists overflowed was skipped by the
         // render kernel: grow the list buffers and run those items again
         for (int attempt = 0; attempt < 3; ++attempt) {
@@ -1616,7 +1628,8 @@ art_status art_get_hits(art_ctx* ctx, int pose, int view, int C, art_dtype dtype
     o.hit_leaf = leaf;
     o.hit_delta = delta;
     o.hit_count = count;
-    art_status rc = render_call(ctx, C, dtype, sigma, feat, lambda_th, flags, 2, o, pose, pose + 1);
+    // the hit lists are complete when the call returns (ART_ASYNC does not apply)
+    art_status rc = render_call(ctx, C, dtype, sigma, feat, lambda_th, flags & ~ART_ASYNC, 2, o, pose, pose + 1);
     tf.release();
     ta.release();
     return rc;
@@ -1926,6 +1939,39 @@ art_status art_map_loss(art_ctx* ctx, int64_t n_feat, int64_t rays, const float*
         if (rc != ART_OK) return rc;
     }
     *loss = 0.5 * (sf + sa) / (double)rays;
+    return ART_OK;
+}
+
+art_status art_render_status(art_ctx* ctx, int64_t* overflowed_items, int64_t* bad_densities) {
+    if (!ctx) return ART_EINVAL;
+    int64_t ov = 0, bad = 0;
+    if (ctx->async_pending) {
+        DeviceGuard g(ctx->device);
+        hipStream_t st = ctx->stream;
+        const size_t items = ctx->async_items;
+        std::vector<uint32_t> hov(items * 2);
+        unsigned long long hst[16] = {0};
+        ART_TRY_HIP(hipMemcpyAsync(hov.data(), ctx->s.ovf.p, items * 2 * 4, hipMemcpyDeviceToHost, st), "copy");
+        ART_TRY_HIP(hipMemcpyAsync(hst, ctx->s.stats.p, sizeof(hst), hipMemcpyDeviceToHost, st), "copy");
+        ART_TRY_HIP(hipStreamSynchronize(st), "render status");
+        size_t need = 0;
+        for (size_t i = 0; i < items; ++i) {
+            ctx->s.pair_hint = std::max<size_t>(ctx->s.pair_hint, hov[2 * i + 1]);
+            if (hov[2 * i] != 0u && hov[2 * i + 1] > ctx->s.pair_cap) {
+                ++ov;
+                need = std::max<size_t>(need, hov[2 * i + 1]);
+            }
+        }
+        // the next call's tile lists hold what this one needed
+        if (need) ctx->s.pair_cap = need + need / 4 + 1024;
+        bad = (int64_t)hst[kStatBadSigma];
+        for (int i = 0; i < 7; ++i) ctx->stats[i] = (int64_t)hst[i];
+        ctx->stats[7] = ctx->async_launches;
+        for (int i = 8; i < 14; ++i) ctx->stats[i] = (int64_t)hst[i - 1];
+        ctx->async_pending = false;
+    }
+    if (overflowed_items) *overflowed_items = ov;
+    if (bad_densities) *bad_densities = bad;
     return ART_OK;
 }
 

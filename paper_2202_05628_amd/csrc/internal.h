@@ -184,6 +184,11 @@ struct art_ctx {
     // build clears `valid`; a reallocated scratch buffer changes its pointers.
     uint64_t state_version = 0;
     size_t mem_limit = 0;          // bound on the working buffers' total capacity (0: none)
+    // last call made with ART_ASYNC whose overflow flags and statistics were
+    // not read back yet (art_render_status)
+    bool async_pending = false;
+    size_t async_items = 0;
+    int async_launches = 0;
     struct BuildMemo {
         bool valid = false;
         uint64_t version = 0;
