@@ -586,15 +586,19 @@ art_status art_get_hits(art_ctx* ctx, int pose, int view, int C, art_dtype dtype
 art_status art_render_status(art_ctx* ctx, int64_t* overflowed_items, int64_t* bad_densities);
 
 /*
- * Counters of the last render / backward / label call, host int64 [14]:
+ * Counters of the last render / backward / label call, host int64
+ * [ART_NUM_STATS]:
  * {rays, composited samples, rays with at least one sample, dropped leaves,
  *  collisions, bricks (summed over poses), tile/brick pairs, kernel launches,
  *  tile-list entries summed over the 8x8 tiles, traversal rounds summed over
  *  the compositing kernel's waves, ray/voxel partition steps summed over rays,
  *  rays of the tiles the compositing kernel rendered (non-empty brick list),
  *  rays that started from a proposed interval, rays of those that fell back
- *  to the full traversal (art_render_proposal only; 0 otherwise)}.
+ *  to the full traversal (art_render_proposal only; 0 otherwise),
+ *  leaf-gradient additions (art_backward only: one per composited sample, or
+ *  one per distinct leaf of a burst when the adjoint merges them; 0 otherwise)}.
  */
+#define ART_NUM_STATS 15
 art_status art_get_stats(art_ctx* ctx, int64_t* stats);
 
 /*

@@ -538,10 +538,10 @@ class Renderer:
         return leaf.cpu().numpy(), delta.cpu().numpy(), count.cpu().numpy()
 
     def stats(self) -> dict:
-        s = np.zeros(14, dtype=np.int64)
+        s = np.zeros(_lib.ART_NUM_STATS, dtype=np.int64)
         self._check(self.lib.art_get_stats(self._h, _ptr(s)), "art_get_stats")
         keys = ["rays", "samples", "hit_rays", "dropped", "collisions", "bricks", "pairs", "launches",
-                "list_entries", "rounds", "steps", "tile_rays", "proposal_rays", "fallbacks"]
+                "list_entries", "rounds", "steps", "tile_rays", "proposal_rays", "fallbacks", "grad_adds"]
         return dict(zip(keys, (int(x) for x in s)))
 
     def timing(self) -> dict:

@@ -19,6 +19,7 @@ ART_TIMING = 2
 ART_PROPOSAL_MARGIN_H = 2.0
 ART_PROPOSAL_NEAR_ONLY = 4
 ART_REUSE_BUILD = 8
+ART_NUM_STATS = 15
 ART_ASYNC = 16
 ART_SHADING_NOALLOC_BYTES = 100663296
 

@@ -194,6 +194,16 @@ size_t slot_budget_bytes(const art_ctx* ctx) {
     return b;
 }
 
+// Whether the adjoint merges the gradient records of one leaf before adding
+// them (ARTEMIS_ADJ_MERGE = 0 never, 1 always; by default when the launch has
+// at least two tiles per workgroup).
+int adj_merge_policy() {
+    const char* e = getenv("ARTEMIS_ADJ_MERGE");
+    if (e && *e == '0') return 0;
+    if (e && *e == '1') return 1;
+    return 2;
+}
+
 // Initial capacity of one (pose, view group) tile list (ARTEMIS_PAIR_CAP
 // overrides; the capacity grows when a list overflows).
 size_t initial_pair_cap(size_t tiles_g) {
@@ -663,6 +673,7 @@ art_status render_call(art_ctx* ctx, int C, art_dtype dtype, const void* sigma, 
     ctx->stats[11] = (int64_t)hst[10];
     ctx->stats[12] = (int64_t)hst[11];
     ctx->stats[13] = (int64_t)hst[12];
+    ctx->stats[14] = (int64_t)hst[13];
     tm.finish(ctx);
     // the slots hold every pose's octree and tile lists - unless an overflow
     // re-run rebuilt only some items: the others' overflow flags then mark them
@@ -740,6 +751,7 @@ hipError_t launch_render(const RenderLaunch& r, hipStream_t st) {
     a.J = r.J;
     a.dom_bone = r.dom_bone;
     a.bone_rot = r.bone_rot;
+    a.adj_merge = adj_merge_policy();
     a.max_hits = r.max_hits;
     a.debug_view = r.debug_view;
     a.hit_leaf = r.hit_leaf;
@@ -1967,7 +1979,7 @@ art_status art_render_status(art_ctx* ctx, int64_t* overflowed_items, int64_t* b
         bad = (int64_t)hst[kStatBadSigma];
         for (int i = 0; i < 7; ++i) ctx->stats[i] = (int64_t)hst[i];
         ctx->stats[7] = ctx->async_launches;
-        for (int i = 8; i < 14; ++i) ctx->stats[i] = (int64_t)hst[i - 1];
+        for (int i = 8; i < 15; ++i) ctx->stats[i] = (int64_t)hst[i - 1];
         ctx->async_pending = false;
     }
     if (overflowed_items) *overflowed_items = ov;

@@ -85,7 +85,7 @@ struct RunStats {
         steps, tile_rays;
 };
 
-constexpr int kNumStats = 14;
+constexpr int kNumStats = 15;
 constexpr int kStatBadSigma = 15;     // device run-statistics slot: FLUT densities < 0 or not finite
 constexpr int kMaxBonesSH = 64;       // bone rotations staged in LDS by the view-dependent (SH) render
 constexpr int kSortBlocks = 512;      // fixed grid (per pose) of the radix-sort passes

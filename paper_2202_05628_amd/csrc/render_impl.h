@@ -129,6 +129,7 @@ struct RArgs {
     const uint8_t* dom_bone;               // [n] dominant bone of each canonical leaf (MODE 6)
     const float* bone_rot;                 // [Pb][J][12] bone transforms of the launch's poses (MODE 6)
     float depth_sigma;                     // MODE 5: density threshold of the depth buffer
+    int adj_merge;                         // MODE 1: 0 never, 1 always, 2 with >= 2 tiles per workgroup
     int max_hits;
     int debug_view;                        // view whose hit lists are recorded (MODE 2)
     int32_t* hit_leaf;                     // [H*W][max_hits] (single pose / view)
@@ -277,8 +278,11 @@ __device__ inline uint32_t spread3_small(uint32_t v) {   // 3-bit x -> bits 0, 3
 #ifndef ART_MORTON_LUT
 #define ART_MORTON_LUT 1
 #endif
-template <typename R>
-constexpr bool kMortonLut = ART_MORTON_LUT && sizeof(R) == 8;
+#ifndef ART_ADJ_SORT
+#define ART_ADJ_SORT 1   // 1: the adjoint merges the records of one leaf before a burst
+#endif
+template <typename R, int MODE>
+constexpr bool kMortonLut = ART_MORTON_LUT && sizeof(R) == 8 && !(MODE == 1 && ART_ADJ_SORT);
 
 // Ray parameter of lattice plane k on one axis: (-1 + k h - o) / d, written with
 // q = 1 + o and the reciprocal of d.
@@ -357,7 +361,7 @@ __device__ inline void root_span(const R* d, const R* q, const R* inv, R h, int 
 #define ART_ADJ_LINES 1
 #endif
 #ifndef ART_ADJ_ROUNDS
-#define ART_ADJ_ROUNDS 8   // rounds of records between bursts
+#define ART_ADJ_ROUNDS 7   // rounds of records between bursts
 #endif
 constexpr int kAdjRec = 64 * ART_ADJ_ROUNDS;
 // Row pitch of a ray's dL/dF in LDS: 16-byte rows, offset so that the rows of
@@ -371,6 +375,11 @@ struct AdjLds {
     float w[kAdjRec];             // its weight,
     float ds[kAdjRec];            // its density gradient
     uint8_t src[kAdjRec];         // and the lane (ray) it belongs to
+#if ART_ADJ_SORT
+    uint16_t ord[2][kAdjRec];   // record orders of the two counting-sort passes
+    uint32_t cnt[64];           // bucket counts, then bucket starts
+    uint32_t merge;             // this launch merges the records of one leaf
+#endif
 };
 
 // The adjoint's LDS staging (only the adjoint kernels allocate it).
@@ -384,14 +393,118 @@ __device__ inline AdjLds<C>* adj_lds() {
     }
 }
 
-// Add the gradients of the n buffered records (wave-uniform n) and empty the
-// buffer.
-template <int C>
-__device__ inline void adj_flush(const RArgs& a, AdjLds<C>* s_adj, int& n, int lane) {
+#if ART_ADJ_SORT
+// One stable-in-practice counting-sort pass over the n buffered records
+// (wave-uniform n): takes them in the order `in` (record index order when
+// null) and writes the order by bucket key(leaf) in [0, NB) to `out`.  A
+// record's rank within its bucket comes from an LDS atomic on the bucket's
+// count; the bucket starts are the exclusive scan of the counts across the
+// wave's lanes.
+template <int C, int NB, typename Key>
+__device__ inline void adj_sort_pass(AdjLds<C>* s, const uint16_t* in, uint16_t* out, int n, int lane, Key key) {
+    static_assert(NB <= 64, "one bucket per lane");
+    if (lane < NB) s->cnt[lane] = 0u;
     wave_sync();
-    for (int i = lane; i < n; i += 64) unsafeAtomicAdd(&a.d_sigma[s_adj->leaf[i]], s_adj->ds[i]);
+    uint32_t rk[kAdjRec / 64];
+#pragma unroll
+    for (int k = 0; k < kAdjRec / 64; ++k) {
+        const int p = k * 64 + lane;
+        rk[k] = 0u;
+        if (p < n) rk[k] = atomicAdd(&s->cnt[key(s->leaf[in ? (int)in[p] : p])], 1u);
+    }
+    wave_sync();
+    const uint32_t c = lane < NB ? s->cnt[lane] : 0u;
+    const uint32_t start = wave_inclusive_scan(c) - c;
+    wave_sync();
+    if (lane < NB) s->cnt[lane] = start;
+    wave_sync();
+#pragma unroll
+    for (int k = 0; k < kAdjRec / 64; ++k) {
+        const int p = k * 64 + lane;
+        if (p < n) {
+            const int i = in ? (int)in[p] : p;
+            out[s->cnt[key(s->leaf[i])] + rk[k]] = (uint16_t)i;
+        }
+    }
+    wave_sync();
+}
+#endif
+
+// Add the gradients of the n buffered records (wave-uniform n) and empty the
+// buffer.  Every float atomic is performed at the memory side, and the
+// request rate bounds the adjoint.  One atomic instruction costs one request
+// per 64-byte segment its lanes touch - unless lanes hit the same word, which
+// splits it into many more requests (one per lane when every word is hit
+// several times).  Neighbouring rays often composite
+// the same leaf in the same round, so the records are first ordered by the
+// low 12 bits of their leaf (two 64-bucket passes; leaves are in Morton
+// order, so the leaves of a burst share few 64-byte segments of the density
+// gradient), the records of one leaf (a run) are summed, and each distinct
+// leaf is added once.  A leaf whose records are not adjacent (two leaves of
+// the burst 4096 apart with equal low bits) is added once per run: correct,
+// only slower.  The merge lengthens each burst, so it pays only where the
+// request rate binds: launches with many tiles per wave (RArgs::adj_merge).
+// With fewer tiles than wave slots the kernel's time is the chain of its
+// longest tile, and the records are added in buffer order.
+#if ART_ADJ_SORT
+template <int C>
+__device__ inline int adj_flush_merged(const RArgs& a, AdjLds<C>* s_adj, int n, int lane) {
+    constexpr int SPI = 64 / C;   // runs per atomic instruction
+    const int cc = lane % C, sub = lane / C;
+    adj_sort_pass<C, 64>(s_adj, nullptr, s_adj->ord[0], n, lane, [](uint32_t l) { return l & 63u; });
+    adj_sort_pass<C, 64>(s_adj, s_adj->ord[0], s_adj->ord[1], n, lane, [](uint32_t l) { return (l >> 6) & 63u; });
+    const uint16_t* ord = s_adj->ord[1];
+    uint16_t* head = s_adj->ord[0];   // sorted positions where a run starts
+    int nd = 0;                       // runs (wave-uniform)
+    for (int p0 = 0; p0 < n; p0 += 64) {
+        const int p = p0 + lane;
+        const bool h = p < n && (p == 0 || s_adj->leaf[ord[p]] != s_adj->leaf[ord[p - 1]]);
+        const uint64_t m = __ballot(h);
+        if (h)
+            head[nd + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))] =
+                (uint16_t)p;
+        nd += __popcll(m);
+    }
+    wave_sync();
+    for (int r = lane; r < nd; r += 64) {
+        const int b = head[r], e = r + 1 < nd ? (int)head[r + 1] : n;
+        float v = 0.0f;
+        for (int p = b; p < e; ++p) v += s_adj->ds[ord[p]];
+        unsafeAtomicAdd(&a.d_sigma[s_adj->leaf[ord[b]]], v);
+    }
+    for (int r0 = 0; r0 < nd; r0 += SPI) {   // wave-uniform bound
+        const int r = r0 + sub;
+        if (r < nd) {
+            const int b = head[r], e = r + 1 < nd ? (int)head[r + 1] : n;
+            float v = 0.0f;
+            for (int p = b; p < e; ++p) {
+                const int i = ord[p];
+                v = __fmaf_rn(s_adj->w[i], s_adj->g[(int)s_adj->src[i] * kAdjPitch<C> + cc], v);
+            }
+            unsafeAtomicAdd(&a.d_leaf_feat[(size_t)s_adj->leaf[ord[b]] * C + cc], v);
+        }
+    }
+    return nd;
+}
+#endif
+
+// adds: leaf-gradient additions issued (records, or runs when merged).
+template <int C>
+__device__ inline void adj_flush(const RArgs& a, AdjLds<C>* s_adj, int& n, int lane, uint32_t& adds) {
+    wave_sync();
+#if ART_ADJ_SORT
+    if (__builtin_amdgcn_readfirstlane(s_adj->merge)) {
+        adds += (uint32_t)adj_flush_merged<C>(a, s_adj, n, lane);
+        wave_sync();   // the records are read before the buffer is reused
+        n = 0;
+        return;
+    }
+#endif
+    adds += (uint32_t)n;
+    // records in buffer order
     constexpr int SPI = 64 / C;   // records per atomic instruction
     const int cc = lane % C, sub = lane / C;
+    for (int i = lane; i < n; i += 64) unsafeAtomicAdd(&a.d_sigma[s_adj->leaf[i]], s_adj->ds[i]);
     for (int s0 = 0; s0 < n; s0 += SPI) {   // wave-uniform bound
         const int sm = s0 + sub;
         if (sm < n)
@@ -406,7 +519,7 @@ __device__ inline void adj_flush(const RArgs& a, AdjLds<C>* s_adj, int& n, int l
 // added to the device counters once when the wave exits: per-tile atomics on
 // the same few words would serialise.
 struct WaveStats {
-    unsigned long long v[13];
+    unsigned long long v[14];
 };
 
 // Render one non-empty tile (item = pose-in-launch * V + view, tile index).
@@ -518,7 +631,8 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
     R t_first = 0, t_last = 0;   // MODE 3: entry of the first / exit of the last sample
     float zdep = INFINITY;       // MODE 5: depth
     bool cdone = false;          // MODE 5: compositing stopped, the depth search goes on
-    int adj_n = 0;   // MODE 1: records in the LDS buffer (wave-uniform)
+    int adj_n = 0;          // MODE 1: records in the LDS buffer (wave-uniform)
+    uint32_t adj_adds = 0;  // MODE 1: leaf-gradient additions issued (wave-uniform)
     // adjoint state.  With g = dL/dF of the ray, the density gradient of
     // sample i needs g . (T_{i+1} f_i - (F - P_i)), P_i = sum_{k<=i} w_k f_k;
     // it is kept as scalars: g . (F - P_i) = gF - gP_i with gF = g . F (from
@@ -786,7 +900,7 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
                 const int l0 = kp[0] - lo3[0], l1 = kp[1] - lo3[1], l2 = kp[2] - lo3[2];
                 if (s1 > s && (unsigned)l0 < 8u && (unsigned)l1 < 8u && (unsigned)l2 < 8u) {
                     uint32_t m9;
-                    if constexpr (kMortonLut<R>)
+                    if constexpr (kMortonLut<R, MODE>)
                         m9 = s_mlut[l0 + 8 * l1 + 64 * l2];
                     else
                         m9 = spread3_small((uint32_t)l0) | (spread3_small((uint32_t)l1) << 1) |
@@ -979,7 +1093,7 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
                     }
                     adj_n += __popcll(staged);
                     adj_has = false;
-                    if (adj_n > kAdjRec - 64) adj_flush<C>(a, s_adj, adj_n, lane);
+                    if (adj_n > kAdjRec - 64) adj_flush<C>(a, s_adj, adj_n, lane, adj_adds);
                 }
             }
 #endif
@@ -1027,7 +1141,7 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
 
 #if ART_ADJ_LINES
     if constexpr (MODE == 1) {
-        if (adj_n > 0) adj_flush<C>(a, s_adj, adj_n, lane);
+        if (adj_n > 0) adj_flush<C>(a, s_adj, adj_n, lane, adj_adds);
     }
 #endif
 
@@ -1066,6 +1180,9 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
             ws.v[8] += (unsigned long long)rounds;
             ws.v[9] += steps;
         }
+        if constexpr (MODE == 1) {
+            if (lane == 0) ws.v[13] += (unsigned long long)adj_adds;
+        }
         if constexpr (MODE == 4) {
             const uint64_t pr = __ballot(prop);
             const uint64_t fl = __ballot(nfall != 0u);
@@ -1093,21 +1210,28 @@ void k_render(RArgs a) {
     __shared__ uint32_t s_row[1][kStage];
     __shared__ uint32_t s_coord[1][kStage];
     __shared__ float s_rot[MODE == 6 ? kMaxBonesSH * 9 : 1];
-    __shared__ uint16_t s_mlut[kMortonLut<R> ? 512 : 1];
+    __shared__ uint16_t s_mlut[kMortonLut<R, MODE> ? 512 : 1];
     AdjLds<C>* s_adj = adj_lds<C, MODE>();
     const int lane = threadIdx.x & 63;
     // invalid densities in the FLUT: nothing is rendered (the call reports it)
     if (a.stats[kStatBadSigma] != 0ull) return;
-    if constexpr (kMortonLut<R>) {
+    if constexpr (kMortonLut<R, MODE>) {
         for (int e = lane; e < 512; e += kWave)
             s_mlut[e] = (uint16_t)(spread3_small((uint32_t)e & 7u) | (spread3_small(((uint32_t)e >> 3) & 7u) << 1) |
                                    (spread3_small((uint32_t)e >> 6) << 2));
         wave_sync();
     }
     const uint32_t n_items = *a.n_items;
+#if ART_ADJ_SORT
+    if constexpr (MODE == 1) {
+        if (lane == 0)
+            s_adj->merge = a.adj_merge == 1 || (a.adj_merge == 2 && (uint64_t)n_items >= 2ull * gridDim.x);
+        wave_sync();
+    }
+#endif
     __shared__ WaveStats ws;
     if (lane == 0)
-        for (int i = 0; i < 13; ++i) ws.v[i] = 0ull;
+        for (int i = 0; i < 14; ++i) ws.v[i] = 0ull;
     // The work list may be cut into kQueues contiguous parts (neighbouring
     // tiles, which read the same bricks and FLUT rows, stay in one part);
     // workgroups are dispatched to the XCDs in turn, so a workgroup starts on
@@ -1134,7 +1258,7 @@ void k_render(RArgs a) {
         }
     }
     if (a.stats && lane == 0)
-        for (int i = 0; i < 13; ++i)
+        for (int i = 0; i < 14; ++i)
             if (ws.v[i]) atomicAdd(&a.stats[i], ws.v[i]);
 }
 

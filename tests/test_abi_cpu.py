@@ -41,3 +41,14 @@ def test_null_context_is_rejected_without_device_work():
     for fn, args in [("art_load_octree", (None, 3, 1, None)), ("art_set_skin", (None, None, None)),
                      ("art_render", (None, 8, 0, None, None, 0.0, 0, None, None, None))]:
         assert getattr(lib, fn)(*args) == _lib.ART_EINVAL
+
+
+def test_binding_constants_match_the_header():
+    """Every integer constant the header defines has the same value in the
+    binding (flags, sizes and the length of the statistics record)."""
+    from paper_2202_05628_amd import _lib
+    src = open(os.path.join(ROOT, "include", "artemis.h")).read()
+    consts = {m.group(1): int(m.group(2)) for m in re.finditer(r"^#define (ART_[A-Z0-9_]+) (\d+)u?\b", src, re.M)}
+    assert {"ART_GEOM_FP32", "ART_TIMING", "ART_ASYNC", "ART_NUM_STATS"} <= set(consts)
+    for name, value in consts.items():
+        assert getattr(_lib, name) == value, name

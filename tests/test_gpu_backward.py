@@ -44,11 +44,16 @@ def _oracle_grad(s, B, K, c2w, H, W, lam, target, gA):
     return ds, df, F_all
 
 
+@pytest.mark.parametrize("merge", ["default", "merged"])
 @pytest.mark.parametrize("lam", [0.0, 0.01])
-def test_adjoint_matches_oracle(tiny, lam):
+def test_adjoint_matches_oracle(tiny, lam, merge, monkeypatch):
+    """merge: the records of one leaf summed before the atomics (forced; by
+    default a launch this small adds them in buffer order)."""
     import torch
     import paper_2202_05628_amd as art
 
+    if merge == "merged":
+        monkeypatch.setenv("ARTEMIS_ADJ_MERGE", "1")
     s, rend, B, K, c2w = tiny
     rng = np.random.default_rng(3)
     target = rng.normal(size=(2, 2, s.C, 96, 96)).astype(np.float32)
@@ -66,10 +71,16 @@ def test_adjoint_matches_oracle(tiny, lam):
     df = f.grad.cpu().numpy()
     es = np.abs(ds - ds_ref).max() / np.abs(ds_ref).max()
     ef = np.abs(df - df_ref).max() / np.abs(df_ref).max()
-    log(f"  dsigma rel_max {es:.2e}, dfeat rel_max {ef:.2e}")
+    st = rend.stats()
+    log(f"  {merge}: dsigma rel_max {es:.2e}, dfeat rel_max {ef:.2e}; "
+        f"{st['grad_adds']} gradient additions for {st['samples']} samples")
     assert es <= TOL_GRAD and ef <= TOL_GRAD
     # hidden leaves and collision losers get exactly zero
     assert np.all(ds[ds_ref == 0] == 0)
+    if merge == "default":
+        assert st["grad_adds"] == st["samples"]
+    else:
+        assert st["grad_adds"] < st["samples"]
 
 
 def test_adjoint_against_finite_differences(tiny):

@@ -76,21 +76,33 @@ def _gpu_grad(s, rend, tgt_rays, sub, H, W, V):
     return ds.cpu().numpy().astype(np.float64), df.cpu().numpy().astype(np.float64)
 
 
-def test_adjoint_full_matches_oracle(grad_full):
+def test_adjoint_full_matches_oracle(grad_full, monkeypatch):
+    """Both ways the adjoint adds its gradients: records in buffer order (the
+    default at this workload, which has fewer tiles than workgroups) and the
+    records of one leaf merged first (forced)."""
     s, rend, ok, ol, o, d, tgt_rays, sub = grad_full
     cfg = sg.CONFIGS["grad"]
-    ds, df = _gpu_grad(s, rend, tgt_rays, sub, cfg.height, cfg.width, cfg.n_views)
     ref = oracle.render(o[sub], d[sub], s.depth, ok, ol, s.sigma, s.feat, LAM)
     ds_ref, df_ref = oracle.backward(o[sub], d[sub], s.depth, ok, ol, s.sigma, s.feat, LAM,
                                      ref["F"] - tgt_rays[sub])
-    es = np.abs(ds - ds_ref).max() / np.abs(ds_ref).max()
-    ef = np.abs(df - df_ref).max() / np.abs(df_ref).max()
     touched = int((ds_ref != 0).sum())
-    log(f"  {touched} leaves with a gradient; dsigma rel_max {es:.2e}, dfeat rel_max {ef:.2e}")
     assert touched > 10_000
-    assert es <= TOL_GRAD and ef <= TOL_GRAD
-    # leaves no ray of the subset composites get exactly zero
-    assert np.all(ds[ds_ref == 0] == 0) and np.all(df[df_ref == 0] == 0)
+    for mode in ("default", "merged"):
+        if mode == "merged":
+            monkeypatch.setenv("ARTEMIS_ADJ_MERGE", "1")
+        ds, df = _gpu_grad(s, rend, tgt_rays, sub, cfg.height, cfg.width, cfg.n_views)
+        st = rend.stats()
+        es = np.abs(ds - ds_ref).max() / np.abs(ds_ref).max()
+        ef = np.abs(df - df_ref).max() / np.abs(df_ref).max()
+        log(f"  {mode}: {touched} leaves with a gradient; dsigma rel_max {es:.2e}, dfeat rel_max {ef:.2e}; "
+            f"{st['grad_adds']} gradient additions for {st['samples']} samples")
+        assert es <= TOL_GRAD and ef <= TOL_GRAD
+        # leaves no ray of the subset composites get exactly zero
+        assert np.all(ds[ds_ref == 0] == 0) and np.all(df[df_ref == 0] == 0)
+        if mode == "default":
+            assert st["grad_adds"] == st["samples"]
+        else:
+            assert st["grad_adds"] < 0.9 * st["samples"]
 
 
 def test_adjoint_full_finite_differences(grad_full):
