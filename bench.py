@@ -114,14 +114,23 @@ def parse():
     return ap.parse_args()
 
 
-def algorithmic_bytes(stats, C, es, with_tfinal=True):
+def written_rays(stats, W):
+    """Rays whose output maps the compositing kernel writes: every ray of the
+    call when its waves also write the background pixels (tiles with no
+    brick; the library's default for maps whose width is a multiple of 4),
+    else the rays of the tiles it renders (the background kernel writes the
+    rest)."""
+    fused = os.environ.get("ARTEMIS_BG_KERNEL") != "1" and W % 4 == 0
+    return stats["rays"] if fused else stats["tile_rays"]
+
+
+def algorithmic_bytes(stats, C, es, W, with_tfinal=True):
     """Bytes the compositing kernel must move: per composited sample the
-    density, the C features and the 4-byte leaf-index word; per ray of the
-    tiles it renders the C + 1 output floats (+ the final transmittance).
-    (Pixels of tiles with no brick are written by the background kernel.)"""
+    density, the C features and the 4-byte leaf-index word; per ray it
+    writes the C + 1 output floats (+ the final transmittance)."""
     per_sample = es * (C + 1) + 4
     per_ray = 4 * (C + 1) + (4 if with_tfinal else 0)
-    return stats["samples"] * per_sample + stats["tile_rays"] * per_ray
+    return stats["samples"] * per_sample + written_rays(stats, W) * per_ray
 
 
 def cpu_baseline(scene, poses, K, c2w, H, W, lam, budget_s):
@@ -352,7 +361,7 @@ def bf16_leg(args, art, sg, torch):
     tm = r.timing()
     st = r.stats()
     rays = P * V * H * W
-    per_launch = algorithmic_bytes(st, cfg.C, 2, with_tfinal=False) / max(tm["n_render"], 1)
+    per_launch = algorithmic_bytes(st, cfg.C, 2, W, with_tfinal=False) / max(tm["n_render"], 1)
     avg = tm["render"] / max(tm["n_render"], 1) / 1e3
     del F, A, out
     return {"workload": f"precision form: BF16 storage, FP32 geometry, {P} poses x {V} cameras at {H}x{W} ({rays} rays)",
@@ -360,7 +369,7 @@ def bf16_leg(args, art, sg, torch):
             "render_ms": round(tm["render"], 3),
             "render_hbm_frac": round(per_launch / avg / 1e9 / HBM_PEAK_GBS, 4),
             "render_launches": tm["n_render"], "avg_launch_us": round(avg * 1e6, 2),
-            "samples": st["samples"], "tile_rays": st["tile_rays"],
+            "samples": st["samples"], "tile_rays": st["tile_rays"], "written_rays": written_rays(st, W),
             "algorithmic_bytes_per_launch": int(per_launch),
             "algorithmic_bytes_per_sample": 2 * (cfg.C + 1) + 4}
 
@@ -380,7 +389,7 @@ def depth_leg(args, r, sig, feat, out, fp32_geom, torch, C, es, rays):
     r.render_depth(sig, feat, th, args.lambda_th, fp32_geom=fp32_geom, out=outd, timing=True)
     tm = r.timing()
     st = r.stats()
-    per_launch = (algorithmic_bytes(st, C, es) + 4 * st["tile_rays"]) / max(tm["n_render"], 1)
+    per_launch = (algorithmic_bytes(st, C, es, r.W) + 4 * written_rays(st, r.W)) / max(tm["n_render"], 1)
     avg = tm["render"] / max(tm["n_render"], 1) / 1e3
     finite = int(torch.isfinite(D).sum())
     del D, outd
@@ -407,7 +416,7 @@ def sh_leg(args, r, scene, out, fp32_geom, torch, C, rays, nsh=9):
     st = r.stats()
     # per composited sample: sigma, the nsh x C coefficients, the winner id, the dominant bone
     per_sample = 4 * (1 + nsh * C) + 4 + 1
-    per_launch = (st["samples"] * per_sample + st["tile_rays"] * (4 * (C + 2))) / max(tm["n_render"], 1)
+    per_launch = (st["samples"] * per_sample + written_rays(st, r.W) * (4 * (C + 2))) / max(tm["n_render"], 1)
     avg = tm["render"] / max(tm["n_render"], 1) / 1e3
     del k
     return {"workload": f"view-dependent features on the main workload: H = {nsh} SH blocks of C = {C}, FP32",
@@ -713,7 +722,7 @@ def main():
     rays_per_step = P * cfg.n_views * cfg.height * cfg.width
     value = rays_per_step * args.steps / elapsed / 1e6
     es = 2 if cfg.storage == "bf16" else 4
-    bytes_call = algorithmic_bytes(st, cfg.C, es)
+    bytes_call = algorithmic_bytes(st, cfg.C, es, cfg.width)
     launches_per_call = n_render / args.steps
     per_launch_bytes = bytes_call / launches_per_call
     avg_launch_s = render_ms / n_render / 1e3

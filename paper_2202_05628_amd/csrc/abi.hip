@@ -204,6 +204,13 @@ int adj_merge_policy() {
     return 2;
 }
 
+// Whether the compositing kernel writes the forward maps' background pixels
+// (ARTEMIS_BG_KERNEL=1: a kernel of its own before the compositing kernel).
+bool bg_in_render_enabled() {
+    const char* e = getenv("ARTEMIS_BG_KERNEL");
+    return !(e && *e == '1');
+}
+
 // Initial capacity of one (pose, view group) tile list (ARTEMIS_PAIR_CAP
 // overrides; the capacity grows when a list overflows).
 size_t initial_pair_cap(size_t tiles_g) {
@@ -497,8 +504,14 @@ art_status run_batch(art_ctx* ctx, const CallPlan& pl, int mode, float lambda, c
     tl.out_depth = r.out_depth;
     tl.hit_count = r.hit_count;
     tl.stats = s.stats.as<unsigned long long>();
+    // the forward maps' background pixels are written by the compositing
+    // kernel's waves between their tiles (overlapping their compositing)
+    tl.bg_in_render = (mode == 0 || mode == 4 || mode == 5 || mode == 6) && tl.out_feat && !tl.labels &&
+                      !tl.hit_count && background_vectorised(tl) && bg_in_render_enabled() &&
+                      (uint64_t)Pb * ctx->V * ctx->H * ctx->W / 4 < (1ull << 32);
+    r.bg_in_render = tl.bg_in_render;
     ART_TRY_HIP(launch_tiles(tl, st), "tile compaction");
-    *launches += (r.out_feat || r.hit_count || r.labels) ? 3 : 2;
+    *launches += ((r.out_feat || r.hit_count || r.labels) && !tl.bg_in_render) ? 3 : 2;
     tm.record(st, 3);
     if (mode == 4 && !o.intervals) {   // proposal network: intervals of the rays of every non-empty tile
         InferLaunch ia{};
@@ -752,6 +765,7 @@ hipError_t launch_render(const RenderLaunch& r, hipStream_t st) {
     a.dom_bone = r.dom_bone;
     a.bone_rot = r.bone_rot;
     a.adj_merge = adj_merge_policy();
+    a.bg_in_render = r.bg_in_render ? 1 : 0;
     a.max_hits = r.max_hits;
     a.debug_view = r.debug_view;
     a.hit_leaf = r.hit_leaf;

@@ -272,6 +272,7 @@ struct RenderLaunch {
     int mode;            // 0 forward, 1 backward, 2 debug hit lists, 3 labels, 4 proposal, 5 forward + depth,
                          // 6 forward with SH features
     int depth;
+    bool bg_in_render;   // the compositing kernel also writes the background pixels
     int Pb, V, H, W;     // poses in the launch (slots 0..Pb-1), views, image
     int Vg, ngroups;     // view groups of the tile lists
     uint32_t ncap;       // leaves per slot
@@ -328,8 +329,12 @@ struct TileLaunch {
     float* out_depth;          // depth buffer (+inf on empty tiles)
     int32_t* hit_count;
     unsigned long long* stats;
+    bool bg_in_render;         // the compositing kernel writes the background (vectorised maps only)
 };
 hipError_t launch_tiles(const TileLaunch& t, hipStream_t st);
+// Whether the launch's maps take the vectorised background (width a multiple
+// of 4, 16-byte aligned maps).
+bool background_vectorised(const TileLaunch& t);
 
 // Proposal network (k_mlp.hip).
 struct AdamStep {

@@ -8,6 +8,7 @@
 //   k_background   : one thread per pixel; the pixels of an empty tile get
 //                    F = 0, A = 0, T = 1 (no voxel on their ray), and the
 //                    empty interval label (1, 0) in a label pass.
+#include "background.h"
 #include "device_util.h"
 #include "internal.h"
 
@@ -104,43 +105,12 @@ __global__ __launch_bounds__(256) void k_background(TileGeom g, const uint32_t* 
 
 // Same as k_background for images whose width is a multiple of 4: a thread
 // owns 4 consecutive pixels of a row (one tile) and writes 16-byte vectors.
-__global__ __launch_bounds__(256) void k_background4(TileGeom g, const uint32_t* __restrict__ ovf,
-                                                     const uint32_t* __restrict__ tstart,
-                                                     const uint32_t* __restrict__ tend,
-                                                     float* __restrict__ out_feat, float* __restrict__ out_alpha,
-                                                     float* __restrict__ out_tfinal, float* __restrict__ labels,
-                                                     float* __restrict__ out_depth, int32_t* __restrict__ hit_count,
-                                                     unsigned long long* __restrict__ stats) {
-    const size_t HW = (size_t)g.H * g.W;
-    const size_t HW4 = HW / 4;
-    const uint64_t total = (uint64_t)g.Pb * g.V * HW4;
+__global__ __launch_bounds__(256) void k_background4(BgArgs g, uint64_t total, unsigned long long* __restrict__ stats) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     unsigned long long nrays = 0;
-    const float4 zero = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
-        const uint32_t pvi = (uint32_t)(i / HW4);
-        const size_t q = (size_t)(i % HW4);   // 4-pixel group of the map
-        const size_t pix = q * 4;
-        const int py = (int)(pix / g.W), px = (int)(pix % g.W);
-        const int pb = (int)pvi / g.V, v = (int)pvi % g.V;
-        if (g.debug_view >= 0 && v != g.debug_view) continue;
-        if (ovf[2 * ((size_t)pb * g.ngroups + v / g.Vg)]) continue;   // re-run later by the host
-        const size_t item = (size_t)pvi * g.TPV + (size_t)(py >> 3) * g.TX + (px >> 3);
-        if (tend[item] > tstart[item]) continue;                      // rendered by k_render
-        nrays += 4;
-        if (out_feat)
-            for (int c = 0; c < g.C; ++c) store_stream4(out_feat + ((size_t)pvi * g.C + c) * HW + pix, zero);
-        if (out_alpha) store_stream4(out_alpha + (size_t)pvi * HW + pix, zero);
-        if (out_tfinal) store_stream4(out_tfinal + (size_t)pvi * HW + pix, make_float4(1.0f, 1.0f, 1.0f, 1.0f));
-        if (labels) {
-            float4* l = reinterpret_cast<float4*>(labels + ((size_t)pvi * HW + pix) * 2);
-            l[0] = make_float4(1.0f, 0.0f, 1.0f, 0.0f);
-            l[1] = make_float4(1.0f, 0.0f, 1.0f, 0.0f);
-        }
-        if (out_depth)
-            reinterpret_cast<float4*>(out_depth + (size_t)pvi * HW)[q] = make_float4(INFINITY, INFINITY, INFINITY, INFINITY);
-        if (hit_count) reinterpret_cast<int4*>(hit_count)[q] = make_int4(0, 0, 0, 0);
-    }
+    const uint64_t HW4 = (uint64_t)g.H * g.W / 4;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride)
+        nrays += (unsigned long long)bg_group4(g, (uint32_t)(i / HW4), (uint32_t)(i % HW4));
     if (stats) {   // one atomic per workgroup
         __shared__ unsigned long long part[256 / kWave];
         const unsigned long long w = wave_sum(nrays);
@@ -159,6 +129,37 @@ __global__ __launch_bounds__(256) void k_background4(TileGeom g, const uint32_t*
 #ifndef ART_BG_BLOCKS
 #define ART_BG_BLOCKS 65536
 #endif
+
+BgArgs bg_args(const TileLaunch& t, const TileGeom& g) {
+    BgArgs b;
+    b.V = g.V;
+    b.Vg = g.Vg;
+    b.ngroups = g.ngroups;
+    b.H = g.H;
+    b.W = g.W;
+    b.C = g.C;
+    b.TX = g.TX;
+    b.TPV = g.TPV;
+    b.debug_view = g.debug_view;
+    b.ovf = t.ovf;
+    b.tile_start = t.tile_start;
+    b.tile_end = t.tile_end;
+    b.out_feat = t.out_feat;
+    b.out_alpha = t.out_alpha;
+    b.out_tfinal = t.out_tfinal;
+    b.labels = t.labels;
+    b.out_depth = t.out_depth;
+    b.hit_count = t.hit_count;
+    return b;
+}
+
+bool background_vectorised(const TileLaunch& t) {
+    return (t.W % 4) == 0 &&
+           ((reinterpret_cast<uintptr_t>(t.out_feat) | reinterpret_cast<uintptr_t>(t.out_alpha) |
+             reinterpret_cast<uintptr_t>(t.out_tfinal) | reinterpret_cast<uintptr_t>(t.labels) |
+             reinterpret_cast<uintptr_t>(t.out_depth) | reinterpret_cast<uintptr_t>(t.hit_count)) &
+            15u) == 0;
+}
 
 hipError_t launch_tiles(const TileLaunch& t, hipStream_t st) {
     TileGeom g;
@@ -189,17 +190,15 @@ hipError_t launch_tiles(const TileLaunch& t, hipStream_t st) {
         if (wblocks < 1) wblocks = 1;
         // 16-byte stores when rows hold whole 4-pixel groups (and the caller's maps are
         // 16-byte aligned, as device allocations are)
-        const bool vec = (g.W % 4) == 0 &&
-                         ((reinterpret_cast<uintptr_t>(t.out_feat) | reinterpret_cast<uintptr_t>(t.out_alpha) |
-                           reinterpret_cast<uintptr_t>(t.out_tfinal) | reinterpret_cast<uintptr_t>(t.labels) |
-                           reinterpret_cast<uintptr_t>(t.out_depth) | reinterpret_cast<uintptr_t>(t.hit_count)) &
-                          15u) == 0;
+        const bool vec = background_vectorised(t);
         if (vec) {
-            uint64_t vblocks = (pixels / 4 + 255) / 256;
-            if (vblocks > ART_BG_BLOCKS) vblocks = ART_BG_BLOCKS;
-            if (vblocks < 1) vblocks = 1;
-            hipLaunchKernelGGL(k_background4, dim3((unsigned)vblocks), dim3(256), 0, st, g, t.ovf, t.tile_start,
-                               t.tile_end, t.out_feat, t.out_alpha, t.out_tfinal, t.labels, t.out_depth, t.hit_count, t.stats);
+            if (!t.bg_in_render) {
+                uint64_t vblocks = (pixels / 4 + 255) / 256;
+                if (vblocks > ART_BG_BLOCKS) vblocks = ART_BG_BLOCKS;
+                if (vblocks < 1) vblocks = 1;
+                hipLaunchKernelGGL(k_background4, dim3((unsigned)vblocks), dim3(256), 0, st, bg_args(t, g), pixels / 4,
+                                   t.stats);
+            }
         } else {
             hipLaunchKernelGGL(k_background, dim3((unsigned)wblocks), dim3(256), 0, st, g, t.ovf, t.tile_start,
                                t.tile_end, t.out_feat, t.out_alpha, t.out_tfinal, t.labels, t.out_depth, t.hit_count, t.stats);

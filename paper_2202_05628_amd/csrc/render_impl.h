@@ -29,6 +29,7 @@
 // tiles that read the same bricks and FLUT rows.
 #pragma once
 
+#include "background.h"
 #include "device_util.h"
 #include "internal.h"
 
@@ -130,6 +131,7 @@ struct RArgs {
     const float* bone_rot;                 // [Pb][J][12] bone transforms of the launch's poses (MODE 6)
     float depth_sigma;                     // MODE 5: density threshold of the depth buffer
     int adj_merge;                         // MODE 1: 0 never, 1 always, 2 with >= 2 tiles per workgroup
+    int bg_in_render;                      // the waves also write the background pixels (empty tiles)
     int max_hits;
     int debug_view;                        // view whose hit lists are recorded (MODE 2)
     int32_t* hit_leaf;                     // [H*W][max_hits] (single pose / view)
@@ -1194,6 +1196,49 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
     }
 }
 
+// One background chunk (kBgChunkGroups 4-pixel groups) taken from its queue
+// by a wave; false when every chunk has been taken.  The chunk's geometry
+// comes from the kernel arguments at each call (nothing of it stays live
+// across the tiles).  Launches with background work hold fewer than 2^32
+// groups (the host checks).
+template <int C>
+__device__ inline bool bg_take(const RArgs& a, uint32_t n_bg, uint32_t groups, int lane, WaveStats& ws) {
+    if (n_bg == 0u) return false;
+    uint32_t c = 0;
+    if (lane == 0) c = atomicAdd(&a.queue[8], 1u);
+    c = (uint32_t)__shfl((int)c, 0, kWave);
+    if (c >= n_bg) return false;
+    BgArgs bg;
+    bg.V = a.V;
+    bg.Vg = a.Vg;
+    bg.ngroups = a.ngroups;
+    bg.H = a.H;
+    bg.W = a.W;
+    bg.C = C;
+    bg.TX = a.TX;
+    bg.TPV = a.TPV;
+    bg.debug_view = -1;
+    bg.ovf = a.ovf;
+    bg.tile_start = a.tile_start;
+    bg.tile_end = a.tile_end;
+    bg.out_feat = a.out_feat;
+    bg.out_alpha = a.out_alpha;
+    bg.out_tfinal = a.out_tfinal;
+    bg.labels = nullptr;
+    bg.out_depth = a.out_depth;
+    bg.hit_count = nullptr;
+    const uint32_t HW4 = (uint32_t)a.H * (uint32_t)a.W / 4u;
+    int n = 0;
+#pragma unroll 1
+    for (uint32_t k = 0; k < kBgChunkGroups / kWave; ++k) {
+        const uint32_t i = c * kBgChunkGroups + k * kWave + (uint32_t)lane;
+        if (i < groups) n += bg_group4(bg, i / HW4, i % HW4);
+    }
+    const unsigned long long w = (unsigned long long)wave_sum((unsigned)n);
+    if (lane == 0) ws.v[0] += w;
+    return true;
+}
+
 // Consecutive work-list tiles a wave takes per queue atomic.
 #ifndef ART_TILES_PER_GRAB
 #define ART_TILES_PER_GRAB 1
@@ -1232,6 +1277,17 @@ void k_render(RArgs a) {
     __shared__ WaveStats ws;
     if (lane == 0)
         for (int i = 0; i < 14; ++i) ws.v[i] = 0ull;
+    // Background pixels (when this launch writes them): a wave takes a chunk
+    // after every `every` tiles - spread so that the stores overlap the
+    // compositing - and the remaining chunks once the work list is drained.
+    uint32_t n_bg = 0, every = 0xFFFFFFFFu, since = 0, bg_groups = 0;
+    if constexpr (MODE == 0 || MODE == 4 || MODE == 5 || MODE == 6) {
+        if (a.bg_in_render) {
+            bg_groups = (uint32_t)((uint64_t)a.Pb * a.V * a.H * a.W / 4);
+            n_bg = (bg_groups + kBgChunkGroups - 1) / kBgChunkGroups;
+            every = n_items / n_bg > 1u ? n_items / n_bg : 1u;
+        }
+    }
     // The work list may be cut into kQueues contiguous parts (neighbouring
     // tiles, which read the same bricks and FLUT rows, stay in one part);
     // workgroups are dispatched to the XCDs in turn, so a workgroup starts on
@@ -1241,21 +1297,29 @@ void k_render(RArgs a) {
     // so the default is a single queue.)
     constexpr uint32_t kQueues = ART_XCD_QUEUES;
     const uint32_t home = blockIdx.x % kQueues;
-    for (uint32_t k = 0; k < kQueues; ++k) {
-        const uint32_t qi = (home + k) % kQueues;
-        const uint32_t beg = (uint32_t)((uint64_t)n_items * qi / kQueues);
-        const uint32_t end = (uint32_t)((uint64_t)n_items * (qi + 1) / kQueues);
-        while (true) {
+    uint32_t part = 0;
+    bool tiles_left = true;
+    while (true) {
+        if (tiles_left) {
+            const uint32_t qi = (home + part) % kQueues;
+            const uint32_t beg = (uint32_t)((uint64_t)n_items * qi / kQueues);
+            const uint32_t end = (uint32_t)((uint64_t)n_items * (qi + 1) / kQueues);
             uint32_t idx = 0;
             if (lane == 0) idx = atomicAdd(&a.queue[qi], (uint32_t)ART_TILES_PER_GRAB);
             idx = beg + (uint32_t)__shfl((int)idx, 0, kWave);
-            if (idx >= end) break;
+            if (idx >= end) {
+                if (++part == kQueues) tiles_left = false;
+                continue;   // the next part, or the remaining background
+            }
             for (uint32_t t = 0; t < (uint32_t)ART_TILES_PER_GRAB && idx + t < end; ++t) {
                 render_tile<C, ST, R, MODE>(a, a.items[idx + t], idx + t, lane, ws, s_mask, s_pref, s_row, s_mlut,
                                             s_coord, s_rot, s_adj);
                 wave_sync();
             }
+            if (++since < every) continue;   // (every is 2^32 - 1 without background work)
+            since = 0;
         }
+        if (!bg_take<C>(a, n_bg, bg_groups, lane, ws) && !tiles_left) break;
     }
     if (a.stats && lane == 0)
         for (int i = 0; i < 14; ++i)
