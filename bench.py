@@ -109,7 +109,7 @@ def parse():
     ap.add_argument("--no-forms", action="store_true", help="skip the BF16-storage and adjoint legs")
     ap.add_argument("--copy-probe", action="store_true",
                     help="time a 1 GiB device copy (the counter scale of the profiling runs)")
-    ap.add_argument("--leg", choices=["bf16", "adjoint", "train", "proposal"], default=None,
+    ap.add_argument("--leg", choices=["bf16", "adjoint", "adjoint_main", "train", "proposal"], default=None,
                     help="run only this form and print its record (profiling)")
     return ap.parse_args()
 
@@ -183,6 +183,69 @@ def cpu_baseline(scene, poses, K, c2w, H, W, lam, budget_s):
         "one_core_render_mrays_s": n1 / t_one / 1e6,
         "one_core_sample": f"{n1} rays of the same pose on one host thread ({t_one:.2f} s)",
     }
+
+
+def cpu_other_configs(sg, scene, lam, seconds=2.0):
+    """The FP64 oracle (all host threads) on the other plain-render workloads:
+    the tiny scene (1 pose x 1 camera at 128^2) in full, and one pose of the
+    precision-form (16 cameras at 1024^2, BF16-rounded FLUT) and
+    learned-proposal (the same cameras, the proposal workload's first pose)
+    workloads: FK, skinning and occupancy in full, a seeded uniform ray sample
+    of about `seconds`, extrapolated to the pose."""
+    import numpy as np
+
+    import oracle
+
+    out = []
+    cfg = sg.CONFIGS["tiny"]
+    st = sg.make_scene(cfg)
+    pt = sg.make_poses(st.J, 1, cfg.pose_seed0)
+    Kt, ct = sg.make_cameras(st, cfg.n_views, cfg.height, cfg.width)
+    t0 = time.perf_counter()
+    B = oracle.fk(st.parent, st.rest_joint, *pt)[0]
+    ok, ol, _, _, _ = oracle.pose_occupancy(st.ijk, st.depth, st.bone, st.weight, B)
+    o, d = oracle.camera_rays(Kt, ct, cfg.height, cfg.width)
+    oracle.render(o.reshape(-1, 3), d.reshape(-1, 3), st.depth, ok, ol, st.sigma, st.feat, lam)
+    t = time.perf_counter() - t0
+    n_all = cfg.n_views * cfg.height * cfg.width
+    out.append({"workload": f"tiny: depth {cfg.depth}, {st.n} leaves, C = {cfg.C}, 1 pose x {cfg.n_views} camera at "
+                            f"{cfg.height}x{cfg.width}", "value": n_all / t / 1e6, "unit": "Mrays/s",
+                "sample": f"in full ({n_all} rays, FK, skinning and occupancy included, {t:.3f} s)"})
+    rng = np.random.default_rng(17)
+    for name in ("bf16", "proposal"):
+        cfg = sg.CONFIGS[name]
+        sig, feat = scene.sigma, scene.feat
+        if cfg.storage == "bf16":   # the values the precision form stores
+            import torch
+            sig = torch.from_numpy(sig).to(torch.bfloat16).float().numpy()
+            feat = torch.from_numpy(feat).to(torch.bfloat16).float().numpy()
+        p = sg.make_poses(scene.J, 1, cfg.pose_seed0)
+        K, c2w = sg.make_cameras(scene, cfg.n_views, cfg.height, cfg.width)
+        t0 = time.perf_counter()
+        B = oracle.fk(scene.parent, scene.rest_joint, *p)[0]
+        ok, ol, _, _, _ = oracle.pose_occupancy(scene.ijk, scene.depth, scene.bone, scene.weight, B)
+        t_build = time.perf_counter() - t0
+        o, d = oracle.camera_rays(K, c2w, cfg.height, cfg.width)
+        o = o.reshape(-1, 3)
+        d = d.reshape(-1, 3)
+        n_all = o.shape[0]
+        idx = rng.choice(n_all, 4000, replace=False)
+        t1 = time.perf_counter()
+        oracle.render(o[idx], d[idx], scene.depth, ok, ol, sig, feat, lam)
+        rate = 4000 / max(time.perf_counter() - t1, 1e-6)
+        n = int(min(n_all, max(4000, rate * seconds)))
+        idx = rng.choice(n_all, n, replace=False)
+        t1 = time.perf_counter()
+        oracle.render(o[idx], d[idx], scene.depth, ok, ol, sig, feat, lam)
+        t_render = time.perf_counter() - t1
+        t_pose = t_build + t_render * (n_all / n)
+        out.append({"workload": f"{name}: {cfg.n_poses} poses x {cfg.n_views} cameras at {cfg.height}x{cfg.width}"
+                                + (" (BF16-rounded FLUT)" if cfg.storage == "bf16" else ""),
+                    "value": n_all / t_pose / 1e6, "unit": "Mrays/s",
+                    "sample": f"1 pose: build in full ({t_build:.2f} s); {n} of {n_all} rays ({100.0 * n / n_all:.2f} %, "
+                              f"{t_render:.2f} s, uniform seeded sample) extrapolated to the pose; "
+                              f"the other poses cost the same"})
+    return out
 
 
 def cpu_model():
@@ -520,6 +583,24 @@ def adjoint_main_leg(args, r, sig, feat, out, torch, C, rays):
             "mrays_s_kernel": round(rays / (tm["render"] * 1e-3) / 1e6, 2)}
 
 
+def adjoint_main_only_leg(args, art, sg, torch):
+    """The adjoint on the main workload on its own (for counter runs): the
+    forward, then adjoint_main_leg."""
+    cfg = sg.CONFIGS["full"]
+    scene = sg.make_scene(cfg)
+    P, V, H, W = cfg.n_poses, cfg.n_views, cfg.height, cfg.width
+    r = art.Renderer(0)
+    r.set_scene(scene)
+    r.set_poses(*sg.make_poses(scene.J, P, cfg.pose_seed0))
+    r.set_cameras(*sg.make_cameras(scene, V, H, W), H, W)
+    sig = torch.from_numpy(scene.sigma).cuda()
+    feat = torch.from_numpy(scene.feat).cuda()
+    F = torch.empty((P, V, cfg.C, H, W), dtype=torch.float32, device="cuda")
+    A = torch.empty((P, V, H, W), dtype=torch.float32, device="cuda")
+    T = torch.empty_like(A)
+    return adjoint_main_leg(args, r, sig, feat, (F, A, T), torch, cfg.C, P * V * H * W)
+
+
 def train_leg(args, art, sg, torch):
     """FLUT training step on the differentiation workload (1 pose x 4 cameras at
     512^2, C = 16, FP32): render, L2 map loss to seeded targets, adjoint,
@@ -678,7 +759,8 @@ def main():
     import scenegen as sg
 
     if args.leg:
-        legs = {"bf16": bf16_leg, "adjoint": adjoint_leg, "train": train_leg, "proposal": proposal_leg}
+        legs = {"bf16": bf16_leg, "adjoint": adjoint_leg, "adjoint_main": adjoint_main_only_leg, "train": train_leg,
+                "proposal": proposal_leg}
         print(json.dumps({args.leg: legs[args.leg](args, art, sg, torch)}), flush=True)
         return
 
@@ -801,6 +883,7 @@ def main():
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(scene, poses, K, c2w, cfg.height, cfg.width,
                                             args.lambda_th, args.cpu_seconds)
+        line["cpu_baseline"]["other_workloads"] = cpu_other_configs(sg, scene, args.lambda_th)
         if not args.no_forms:
             print("[bench] errors of the extra forms against the FP64 oracle", file=sys.stderr, flush=True)
             errs = oracle_checks(art, sg, torch, args.lambda_th)

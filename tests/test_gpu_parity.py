@@ -152,3 +152,28 @@ def test_forward_is_deterministic(tiny):
         assert bool((x == y).all())
     st = rend.stats()
     assert st["rays"] == 3 * 2 * 128 * 128 and st["samples"] > 0
+
+
+@pytest.mark.parametrize("bf16", [False, True], ids=["f32", "bf16"])
+def test_background_in_kernel_equals_background_kernel(tiny, monkeypatch, bf16):
+    """The compositing kernel's waves write the background pixels (tiles with
+    no brick) of the forward maps and the depth buffer; the separate
+    background kernel (ARTEMIS_BG_KERNEL=1) must give the same maps bit for
+    bit, and both count every ray."""
+    s, rend, *_ = tiny
+    sig, f = flut(s, "bf16" if bf16 else "f32")
+    th = float(np.median(s.sigma))
+    a = rend.render(sig, f, 0.01, fp32_geom=bf16)
+    da = rend.render_depth(sig, f, th, 0.01, fp32_geom=bf16)
+    st_a = rend.stats()
+    monkeypatch.setenv("ARTEMIS_BG_KERNEL", "1")
+    b = rend.render(sig, f, 0.01, fp32_geom=bf16)
+    db = rend.render_depth(sig, f, th, 0.01, fp32_geom=bf16)
+    st_b = rend.stats()
+    for x, y in zip(a + da, b + db):
+        assert bool((x == y).all())
+    assert st_a["rays"] == st_b["rays"] == 3 * 2 * 128 * 128
+    # background pixels exist in these maps, and they hold F = 0, A = 0, T = 1
+    F, A, T = a
+    bgpix = T == 1.0
+    assert int(bgpix.sum()) > 0 and bool((A[bgpix] == 0).all())
