@@ -1,7 +1,7 @@
 // Skeleton and skinning kernels (Section 3.1, "Rigging and Deformation", Eq. 4).
 //
-//   k_fk   : one thread per pose composes the bone chain in FP64 and writes the
-//            skinning matrices B_j = M^t_j (M^c_j)^-1 (FP64 and an FP32 copy).
+//   k_fk   : one workgroup per pose composes the bone chain in FP64 and writes
+//            the skinning matrices B_j = M^t_j (M^c_j)^-1 (FP64 and an FP32 copy).
 //   k_skin : one thread per leaf blends its four bone matrices with its skin
 //            weights, moves the leaf centre and writes the Morton key of the
 //            posed cell (or the invalid key for a leaf outside the posed root)
@@ -24,55 +24,90 @@ __device__ inline void mat3_mul(const double* A, const double* B, double* C) {
 }
 
 // G: scratch [P][J][12] (row-major 3x4 posed joint transforms).
-__global__ void k_fk(const int32_t* __restrict__ parent, const double* __restrict__ rest,
-                     const double* __restrict__ pose, int J, int P, double* __restrict__ G,
-                     double* __restrict__ B64, float* __restrict__ B32) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= P) return;
+// One workgroup per pose, one thread per bone (J <= 255 < 256 threads): the
+// bones' rotations R_j (axis-angle, Rodrigues) are independent and computed
+// in parallel into LDS; one thread then composes the chain in bone order
+// (parent[j] < j) from LDS - only the 3x3 products and offsets are serial,
+// with no global-memory round trip per bone - and the threads write G, B and
+// its FP32 copy in parallel.
+constexpr int kFkThreads = 256;
+__global__ __launch_bounds__(kFkThreads) void k_fk(const int32_t* __restrict__ parent, const double* __restrict__ rest,
+                                                   const double* __restrict__ pose, int J, int P,
+                                                   double* __restrict__ G, double* __restrict__ B64,
+                                                   float* __restrict__ B32) {
+    __shared__ double s_R[kFkThreads][9];   // local rotation of each bone (the root's with the global one)
+    __shared__ double s_G[kFkThreads][12];  // posed joint transforms
+    const int p = blockIdx.x;
+    const int j = threadIdx.x;
     const double* pr = pose + (size_t)p * (J + 2) * 3;
     const double* Rg = pr + (size_t)J * 3;
     const double* Tg = Rg + 3;
-    double* Gp = G + (size_t)p * J * 12;
-    for (int j = 0; j < J; ++j) {
-        double Rj[9], Rot[9], t[3];
+    if (j < J) {
+        double Rj[9];
         axis_angle_to_matrix(pr + 3 * j, Rj);
-        const double* Jj = rest + 3 * j;
-        const int pa = parent[j];
-        if (pa < 0) {
+        if (parent[j] < 0) {
             double Rglob[9];
             axis_angle_to_matrix(Rg, Rglob);
-            mat3_mul(Rglob, Rj, Rot);
-            t[0] = Jj[0] + Tg[0];
-            t[1] = Jj[1] + Tg[1];
-            t[2] = Jj[2] + Tg[2];
+            mat3_mul(Rglob, Rj, s_R[j]);
         } else {
-            const double* Gq = Gp + (size_t)pa * 12;
-            const double Rq[9] = {Gq[0], Gq[1], Gq[2], Gq[4], Gq[5], Gq[6], Gq[8], Gq[9], Gq[10]};
-            mat3_mul(Rq, Rj, Rot);
-            const double* Jq = rest + 3 * pa;
-            const double off[3] = {Jj[0] - Jq[0], Jj[1] - Jq[1], Jj[2] - Jq[2]};
 #pragma unroll
-            for (int a = 0; a < 3; ++a)
-                t[a] = Rq[3 * a] * off[0] + Rq[3 * a + 1] * off[1] + Rq[3 * a + 2] * off[2] + Gq[4 * a + 3];
+            for (int e = 0; e < 9; ++e) s_R[j][e] = Rj[e];
         }
-        double* Gj = Gp + (size_t)j * 12;
+    }
+    __syncthreads();
+    if (j == 0) {
+        for (int b = 0; b < J; ++b) {
+            const double* Jb = rest + 3 * b;
+            const int pa = parent[b];
+            double Rot[9], t[3];
+            if (pa < 0) {
+#pragma unroll
+                for (int e = 0; e < 9; ++e) Rot[e] = s_R[b][e];
+                t[0] = Jb[0] + Tg[0];
+                t[1] = Jb[1] + Tg[1];
+                t[2] = Jb[2] + Tg[2];
+            } else {
+                const double* Gq = s_G[pa];
+                const double Rq[9] = {Gq[0], Gq[1], Gq[2], Gq[4], Gq[5], Gq[6], Gq[8], Gq[9], Gq[10]};
+                mat3_mul(Rq, s_R[b], Rot);
+                const double* Jq = rest + 3 * pa;
+                const double off[3] = {Jb[0] - Jq[0], Jb[1] - Jq[1], Jb[2] - Jq[2]};
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+                    t[a] = Rq[3 * a] * off[0] + Rq[3 * a + 1] * off[1] + Rq[3 * a + 2] * off[2] + Gq[4 * a + 3];
+            }
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                s_G[b][4 * a + 0] = Rot[3 * a + 0];
+                s_G[b][4 * a + 1] = Rot[3 * a + 1];
+                s_G[b][4 * a + 2] = Rot[3 * a + 2];
+                s_G[b][4 * a + 3] = t[a];
+            }
+        }
+    }
+    __syncthreads();
+    if (j < J) {
+        const double* Jj = rest + 3 * j;
+        const double* Gs = s_G[j];
+        double* Gj = G + ((size_t)p * J + j) * 12;
         double* Bj = B64 + ((size_t)p * J + j) * 12;
         float* Bf = B32 + ((size_t)p * J + j) * 12;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            Gj[4 * a + 0] = Rot[3 * a + 0];
-            Gj[4 * a + 1] = Rot[3 * a + 1];
-            Gj[4 * a + 2] = Rot[3 * a + 2];
-            Gj[4 * a + 3] = t[a];
+            const double r0 = Gs[4 * a + 0], r1 = Gs[4 * a + 1], r2 = Gs[4 * a + 2], t = Gs[4 * a + 3];
+            Gj[4 * a + 0] = r0;
+            Gj[4 * a + 1] = r1;
+            Gj[4 * a + 2] = r2;
+            Gj[4 * a + 3] = t;
             // B_j = G_j [I | -J_j]
-            const double tb = t[a] - (Rot[3 * a] * Jj[0] + Rot[3 * a + 1] * Jj[1] + Rot[3 * a + 2] * Jj[2]);
-            Bj[4 * a + 0] = Rot[3 * a + 0];
-            Bj[4 * a + 1] = Rot[3 * a + 1];
-            Bj[4 * a + 2] = Rot[3 * a + 2];
+            const double tb = t - (r0 * Jj[0] + r1 * Jj[1] + r2 * Jj[2]);
+            Bj[4 * a + 0] = r0;
+            Bj[4 * a + 1] = r1;
+            Bj[4 * a + 2] = r2;
             Bj[4 * a + 3] = tb;
-            Bf[4 * a + 0] = (float)Rot[3 * a + 0];
-            Bf[4 * a + 1] = (float)Rot[3 * a + 1];
-            Bf[4 * a + 2] = (float)Rot[3 * a + 2];
+            Bf[4 * a + 0] = (float)r0;
+            Bf[4 * a + 1] = (float)r1;
+            Bf[4 * a + 2] = (float)r2;
             Bf[4 * a + 3] = (float)tb;
         }
     }
@@ -181,9 +216,8 @@ __global__ __launch_bounds__(256) void k_skin(const uint16_t* __restrict__ ijk,
 
 hipError_t launch_fk(const int32_t* parent, const double* rest, const double* pose, int J, int P,
                      double* G, double* B64, float* B32, hipStream_t st) {
-    const int bs = 64;
-    hipLaunchKernelGGL(k_fk, dim3((P + bs - 1) / bs), dim3(bs), 0, st, parent, rest, pose, J, P, G,
-                       B64, B32);
+    if (J < 1 || J > kFkThreads || P < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_fk, dim3((unsigned)P), dim3(kFkThreads), 0, st, parent, rest, pose, J, P, G, B64, B32);
     return hipGetLastError();
 }
 
