@@ -504,9 +504,36 @@ def shading_leg(args, r, F, torch, C, maps=32):
         + 9 * px // 64 * (128 * 256 + 256 * 256) + 9 * px // 16 * (384 * 128 + 128 * 128) \
         + 9 * px // 4 * (192 * 64 + 64 * 64) + 9 * px * (96 * 32 + 32 * 32) + px * 32 * 4
     tflops = 2 * macs / t / 1e12
+    bound = shading_layer_bound(maps, H, W, C)
     return {"workload": f"Light shading network, {maps} maps of {H}x{W}, C = {C}, FP16 operands, FP32 accumulation",
             "ms": round(t * 1e3, 3), "maps_per_s": round(maps / t, 1), "tflop_per_map": round(2 * macs / maps / 1e12, 4),
-            "achieved_tflops": round(tflops, 1), "peak_tflops": 2500.0, "frac": round(tflops / 2500.0, 4)}
+            "achieved_tflops": round(tflops, 1), "peak_tflops": 2500.0, "frac": round(tflops / 2500.0, 4),
+            "layer_bound_ms": round(bound * 1e3, 3), "frac_of_layer_bound": round(bound / t, 4)}
+
+
+def shading_layer_bound(maps, H, W, C, peak_flops=2.5e15, peak_bytes=8e12):
+    """Lower bound of the shading network's time: per layer the larger of its
+    FP16 matrix-core time (2 x 9 x Cin x Cout per output pixel at 2.5 PFLOP/s)
+    and its HBM time (each input read once - a decoder's deeper input at half
+    resolution - and the output written once, FP16 NHWC, at 8 TB/s), plus the
+    input conversion (16 FP32 planes in, 32 FP16 channels out), the three 2x2
+    max pools and the head (32 FP16 in, 4 FP32 out), which are HBM-bound."""
+    px = maps * H * W
+    # (resolution divisor, C1 same-resolution inputs, C2 half-resolution inputs, Cout, real Cin for the flops)
+    convs = [(1, 32, 0, 32, C), (1, 32, 0, 32, 32), (2, 32, 0, 64, 32), (2, 64, 0, 64, 64), (4, 64, 0, 128, 64),
+             (4, 128, 0, 128, 128), (8, 128, 0, 256, 128), (8, 256, 0, 256, 256), (4, 128, 256, 128, 384),
+             (4, 128, 0, 128, 128), (2, 64, 128, 64, 192), (2, 64, 0, 64, 64), (1, 32, 64, 32, 96),
+             (1, 32, 0, 32, 32)]
+    t = 0.0
+    for div, c1, c2, co, cin in convs:
+        n = px // (div * div)
+        flops = 2 * 9 * cin * co * n
+        bytes_ = 2 * n * (c1 + co) + 2 * (n // 4) * c2 + 2 * 9 * (c1 + c2) * co
+        t += max(flops / peak_flops, bytes_ / peak_bytes)
+    t += px * (4 * C + 2 * 32) / peak_bytes                                          # conversion
+    t += sum((px // (d * d)) * 2 * c * 5 / 4 for d, c in ((1, 32), (2, 64), (4, 128))) / peak_bytes  # pools
+    t += px * (2 * 32 + 4 * 4) / peak_bytes                                          # head
+    return t
 
 
 def adjoint_leg(args, art, sg, torch):
