@@ -508,7 +508,7 @@ art_status run_batch(art_ctx* ctx, const CallPlan& pl, int mode, float lambda, c
     // kernel's waves between their tiles (overlapping their compositing)
     tl.bg_in_render = (mode == 0 || mode == 4 || mode == 5 || mode == 6) && tl.out_feat && !tl.labels &&
                       !tl.hit_count && background_vectorised(tl) && bg_in_render_enabled() &&
-                      (uint64_t)Pb * ctx->V * ctx->H * ctx->W / 4 < (1ull << 32);
+                      (uint64_t)Pb * ctx->V * ctx->H * ctx->W / 4 < (1ull << 31);
     r.bg_in_render = tl.bg_in_render;
     ART_TRY_HIP(launch_tiles(tl, st), "tile compaction");
     *launches += ((r.out_feat || r.hit_count || r.labels) && !tl.bg_in_render) ? 3 : 2;

@@ -1199,8 +1199,8 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
 // One background chunk (kBgChunkGroups 4-pixel groups) taken from its queue
 // by a wave; false when every chunk has been taken.  The chunk's geometry
 // comes from the kernel arguments at each call (nothing of it stays live
-// across the tiles).  Launches with background work hold fewer than 2^32
-// groups (the host checks).
+// across the tiles).  Launches with background work hold fewer than 2^31
+// groups (the host checks), so the 32-bit group index of a chunk cannot wrap.
 template <int C>
 __device__ inline bool bg_take(const RArgs& a, uint32_t n_bg, uint32_t groups, int lane, WaveStats& ws) {
     if (n_bg == 0u) return false;
