@@ -271,6 +271,17 @@ __device__ inline uint32_t spread3_small(uint32_t v) {   // 3-bit x -> bits 0, 3
     return (v & 1u) | ((v & 2u) << 2) | ((v & 4u) << 4);
 }
 
+// In-brick Morton index of cell (x, y, z), each in [0, 8): one byte permute
+// looks the three coordinates up in the 8-entry table of spread3_small values
+// (bytes 0x00 01 08 09 40 41 48 49) and two shift-or steps interleave them.
+#ifndef ART_MORTON_PERM
+#define ART_MORTON_PERM 1
+#endif
+__device__ inline uint32_t morton9_perm(uint32_t x, uint32_t y, uint32_t z) {
+    const uint32_t r = __builtin_amdgcn_perm(0x49484140u, 0x09080100u, x | (y << 8) | (z << 16));
+    return (r & 0xFFu) | (((r >> 8) & 0xFFu) << 1) | ((r >> 16) << 2);
+}
+
 // 1: the in-brick Morton index of a cell comes from a 512-entry LDS table
 // indexed by x + 8 y + 64 z (one LDS read instead of about twenty bit
 // operations per partition step; the compositing kernels are bound by their
@@ -905,8 +916,9 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
                     if constexpr (kMortonLut<R, MODE>)
                         m9 = s_mlut[l0 + 8 * l1 + 64 * l2];
                     else
-                        m9 = spread3_small((uint32_t)l0) | (spread3_small((uint32_t)l1) << 1) |
-                             (spread3_small((uint32_t)l2) << 2);
+                        m9 = ART_MORTON_PERM ? morton9_perm((uint32_t)l0, (uint32_t)l1, (uint32_t)l2)
+                                             : spread3_small((uint32_t)l0) | (spread3_small((uint32_t)l1) << 1) |
+                                                   (spread3_small((uint32_t)l2) << 2);
                     const uint32_t wd = m9 >> 5, bit = m9 & 31u;
                     const uint32_t mw = s_mask[wv][wd][slot];
                     if ((mw >> bit) & 1u) {
