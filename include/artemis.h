@@ -578,6 +578,9 @@ art_status art_get_hits(art_ctx* ctx, int pose, int view, int C, art_dtype dtype
  * rendered: render them again, the next call has the capacity) and
  * *bad_densities the number of negative or non-finite FLUT densities (the
  * call rendered nothing); art_get_stats then holds that call's counters.
+ * When both are 0 the posed octrees and tile lists the call built may be
+ * reused by a following ART_REUSE_BUILD call, as after a synchronous one (an
+ * asynchronous call whose status is never read leaves nothing to reuse).
  * Both 0 when the last call was synchronous (it reported such errors itself).
  * Either pointer may be NULL.  Call it before the next render call on the
  * context, which starts a new record.

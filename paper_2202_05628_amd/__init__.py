@@ -475,8 +475,16 @@ class Renderer:
         on sigma (projected onto sigma >= 0) and feat, in place.  Returns the
         losses of the FLUT before the update."""
         torch = self._torch
-        F, A, T = self.render(sigma, feat, lambda_th, fp32_geom=fp32_geom)
+        # the render only enqueues its work; the map loss reads its value back
+        # (one synchronisation), after which the render's status is read
+        # without waiting: a step whose tile lists overflowed renders again
+        # with the grown lists (an invalid density raises there)
+        F, A, T = self.render(sigma, feat, lambda_th, fp32_geom=fp32_geom, sync=False)
         l_map, dF, dA = self.map_loss(F, F_target, A, A_target)
+        st = self.render_status()
+        if st["overflowed_items"] or st["bad_densities"]:
+            F, A, T = self.render(sigma, feat, lambda_th, fp32_geom=fp32_geom)
+            l_map, dF, dA = self.map_loss(F, F_target, A, A_target)
         # the adjoint and the VRT read the posed octrees (and tile lists) the
         # render just built: the poses and the octree did not change
         d_sigma, d_feat = self.backward(sigma, feat, F, T, dF, dA, lambda_th, fp32_geom=fp32_geom, reuse_build=True)

@@ -570,8 +570,7 @@ bool memo_matches(const art_ctx* ctx, const CallPlan& pl) {
            m.occ == ctx->s.occ_win.p && m.lists == ctx->s.pair_v.p && m.rows == ctx->s.keys1.p &&
            m.tiles == ctx->s.tile_start.p && m.counters == ctx->s.counters.p;
 }
-void take_memo(art_ctx* ctx, const CallPlan& pl) {
-    art_ctx::BuildMemo& m = ctx->memo;
+void fill_memo(const art_ctx* ctx, const CallPlan& pl, art_ctx::BuildMemo& m) {
     m.valid = true;
     m.version = ctx->state_version;
     m.fp32 = pl.fp32;
@@ -587,6 +586,7 @@ void take_memo(art_ctx* ctx, const CallPlan& pl) {
     m.tiles = ctx->s.tile_start.p;
     m.counters = ctx->s.counters.p;
 }
+void take_memo(art_ctx* ctx, const CallPlan& pl) { fill_memo(ctx, pl, ctx->memo); }
 
 art_status render_call(art_ctx* ctx, int C, art_dtype dtype, const void* sigma, const void* feat,
                        float lambda, unsigned flags, int mode, const PassOut& o, int pose_lo,
@@ -618,6 +618,7 @@ art_status render_call(art_ctx* ctx, int C, art_dtype dtype, const void* sigma, 
     // the slots are reused and the call stays synchronous)
     const bool async = (flags & ART_ASYNC) != 0 && slots >= P;
     ctx->async_pending = false;
+    ctx->async_memo.valid = false;
 
     ART_TRY_HIP(launch_fill_u32(ctx->s.stats.as<uint32_t>(), 0u, 32, st), "fill");
     ART_TRY_HIP(launch_check_sigma(sigma, pl.storage, ctx->n, ctx->s.stats.as<unsigned long long>() + kStatBadSigma,
@@ -644,6 +645,9 @@ art_status render_call(art_ctx* ctx, int C, art_dtype dtype, const void* sigma, 
             ctx->async_pending = true;
             ctx->async_items = items;
             ctx->async_launches = launches;
+            // the slots hold every pose's octree and tile lists unless an item
+            // overflowed, which only the status call can tell
+            if (whole) fill_memo(ctx, pl, ctx->async_memo);
             return ART_OK;
         }
         // a (pose, view group) whose tile lists overflowed was skipped by the
@@ -1995,6 +1999,9 @@ art_status art_render_status(art_ctx* ctx, int64_t* overflowed_items, int64_t* b
         ctx->stats[7] = ctx->async_launches;
         for (int i = 8; i < 15; ++i) ctx->stats[i] = (int64_t)hst[i - 1];
         ctx->async_pending = false;
+        // a complete build may be reused (ART_REUSE_BUILD) as after a synchronous call
+        if (ctx->async_memo.valid && ov == 0 && bad == 0) ctx->memo = ctx->async_memo;
+        ctx->async_memo.valid = false;
     }
     if (overflowed_items) *overflowed_items = ov;
     if (bad_densities) *bad_densities = bad;

@@ -201,6 +201,9 @@ struct art_ctx {
         const void* tiles = nullptr;   // s.tile_start.p
         const void* counters = nullptr;   // s.counters.p
     } memo;
+    // the build of the last ART_ASYNC call, made the memo by art_render_status
+    // when none of its items overflowed
+    BuildMemo async_memo;
 
     // last-call bookkeeping
     int64_t stats[art::kNumStats] = {0};

@@ -107,3 +107,31 @@ def test_async_several_batches_and_flags(tiny):
     with pytest.raises(art.ArtemisError) as e:
         rend.render(sig, f, 0.01, timing=True, sync=False)
     assert e.value.status == art._lib.ART_EINVAL
+
+
+def test_async_render_leaves_a_reusable_build(tiny):
+    """After an asynchronous render whose status reports nothing, a reusing
+    adjoint (ART_REUSE_BUILD) skips the build and gives the rebuilt adjoint's
+    gradients; without the status call nothing is reused."""
+    import torch
+    s, poses, K, c2w = tiny
+    sig, f = flut(s)
+    rend = make_renderer(s, poses, K, c2w, 80, 72)
+    F, A, T = rend.render(sig, f, 0.01, sync=False)
+    assert rend.render_status() == {"overflowed_items": 0, "bad_densities": 0}
+    dF = torch.randn_like(F)
+
+    def grads(reuse):
+        ds, df = rend.backward(sig, f, F, T, dF, lambda_th=0.01, reuse_build=reuse)
+        return ds, df, rend.stats()["launches"]
+
+    ds1, df1, n1 = grads(True)
+    ds0, df0, n0 = grads(False)
+    log(f"async render then adjoint: {n1} launches reusing the build, {n0} rebuilding")
+    assert n1 < n0
+    rel = lambda a, b: float((a - b).abs().max()) / float(b.abs().max())
+    assert rel(ds1, ds0) <= 1e-5 and rel(df1, df0) <= 1e-5
+    # the status never read: the build is not taken as complete
+    rend.render(sig, f, 0.01, sync=False)
+    _, _, n2 = grads(True)
+    assert n2 == n0
