@@ -569,13 +569,41 @@ def adjoint_leg(args, art, sg, torch):
     per_ray = 4 * cfg.C + 4 * cfg.C + 4
     alg = st["samples"] * per_sample + st["tile_rays"] * per_ray
     kern_ms = tm["render"] / max(tm["n_render"], 1)
+    # the segmented adjoint: the forward records a checkpoint every `every`
+    # samples of a ray (K per ray), the adjoint runs the K + 1 segments of
+    # every ray in parallel; the records it reads (C + 4 words each) count
+    # in its algorithmic bytes
+    r.render(sig, feat, args.lambda_th, out=(F, A, T), timing=True)
+    fwd_ms = r.timing()["render"]
+    seg = []
+    for K, every in ((4, 48), (6, 36), (8, 32)):
+        Fc, Ac, Tc, ck = r.render_ckpt(sig, feat, args.lambda_th, K=K, every=every, timing=True)
+        fwd_ck_ms = r.timing()["render"]
+        r.backward(sig, feat, Fc, Tc, dF, d_sigma=ds, d_feat=df, reuse_build=True, ckpt=ck)   # warm-up
+        t_seg = _timed(torch, lambda: r.backward(sig, feat, Fc, Tc, dF, d_sigma=ds, d_feat=df, reuse_build=True,
+                                                 ckpt=ck), args.proposal_steps)
+        r.backward(sig, feat, Fc, Tc, dF, d_sigma=ds, d_feat=df, reuse_build=True, ckpt=ck, timing=True)
+        tms = r.timing()
+        k_ms = tms["render"] / max(tms["n_render"], 1)
+        recs = int(ck[1].sum())
+        alg_s = alg + recs * 4 * (cfg.C + 4)
+        seg.append({"K": K, "every": every, "records": recs, "adjoint_kernel_ms": round(k_ms, 4),
+                    "ms_per_call_reusing_forward_octrees": round(t_seg * 1e3, 3),
+                    "adjoint_hbm_frac": round(alg_s / (k_ms * 1e-3) / 8e12, 4),
+                    "forward_kernel_ms_with_checkpoints": round(fwd_ck_ms, 4)})
+        del Fc, Ac, Tc, ck
+    best = min(seg, key=lambda x: x["adjoint_kernel_ms"])
     return {"workload": f"adjoint: {P} pose x {V} cameras at {H}x{W} ({rays} rays), L2 loss to seeded targets",
             "mrays_s": round(rays / t / 1e6, 2), "ms_per_call": round(t * 1e3, 3),
             "ms_per_call_reusing_forward_octrees": round(t_reuse * 1e3, 3),
             "adjoint_kernel_ms": round(kern_ms, 4), "samples": st["samples"], "tile_rays": st["tile_rays"],
             "algorithmic_bytes_per_launch": int(alg),
             "algorithmic_bytes_per_sample": per_sample, "algorithmic_bytes_per_ray": per_ray,
-            "adjoint_hbm_frac": round(alg / (kern_ms * 1e-3) / 8e12, 4)}
+            "adjoint_hbm_frac": round(alg / (kern_ms * 1e-3) / 8e12, 4),
+            "forward_kernel_ms": round(fwd_ms, 4),
+            "segmented": {"best": best, "sweep": seg,
+                          "note": "art_render_ckpt + art_backward_ckpt: K + 1 segments per ray from the "
+                                  "forward's records; algorithmic bytes add the records read"}}
 
 
 def adjoint_main_leg(args, r, sig, feat, out, torch, C, rays):

@@ -227,6 +227,44 @@ art_status art_backward(art_ctx* ctx, int C, art_dtype dtype, const void* sigma,
                         const float* d_feat, const float* d_alpha,
                         float* d_sigma, float* d_leaf_feat);
 
+/*
+ * Segmented adjoint.  The adjoint's time on a launch with fewer 8x8 tiles
+ * than the GPU has wave slots is the serial chain of its longest rays (one
+ * sample after the other, Eq. 5-6).  art_render_ckpt renders as art_render
+ * and also records, before every `every`-th composited sample of a ray
+ * (samples every, 2 every, ... K every), the sample's entry distance t, the
+ * transmittance T before it and the running sum P = sum of w f (the feature
+ * map so far); art_backward_ckpt then splits each ray into K + 1 segments
+ * that run in parallel, each starting from its record: the same samples,
+ * transmittances and stop as the unsegmented adjoint, with the density
+ * gradient's running sum of w (g . f) started at g . P (so only the order of
+ * that sum changes).
+ *
+ * K: records per ray, 1..64; every: samples per segment, 1..65536; rays with
+ *    more than (K + 1) every samples run their last segment to the end.
+ * ckpt:   device float32 [P][V][H][W][K][C + 4], 8-byte aligned: record j of
+ *         a ray = {t as a float64 in words 0-1, T, P[C], one unused word}.
+ * ckpt_n: device int32 [P][V][H][W]: records written (min(K, (n - 1) / every)
+ *         for a ray of n >= 1 composited samples, else 0); entries of rays in
+ *         tiles that no occupied brick covers are not written (the adjoint
+ *         does not read them).
+ * Both are caller-owned; art_backward_ckpt must get those written by an
+ * art_render_ckpt call with the same poses, cameras, FLUT, lambda_th,
+ * flags, K and every, together with its out_feat and out_tfinal.
+ * Errors: as art_render / art_backward, and ART_EINVAL for K, every, null
+ * or misaligned checkpoint buffers.
+ */
+art_status art_render_ckpt(art_ctx* ctx, int C, art_dtype dtype, const void* sigma, const void* feat,
+                           float lambda_th, unsigned flags,
+                           float* out_feat, float* out_alpha, float* out_tfinal,
+                           int K, int every, float* ckpt, int32_t* ckpt_n);
+art_status art_backward_ckpt(art_ctx* ctx, int C, art_dtype dtype, const void* sigma, const void* feat,
+                             float lambda_th, unsigned flags,
+                             const float* out_feat, const float* out_tfinal,
+                             const float* d_feat, const float* d_alpha,
+                             float* d_sigma, float* d_leaf_feat,
+                             int K, int every, const float* ckpt, const int32_t* ckpt_n);
+
 /* ---------------------------------------------------------------------------
  * Learned ray-interval proposal (an addition to the paper's renderer: a small
  * network predicts, per ray, the stretch of the ray that holds its composited

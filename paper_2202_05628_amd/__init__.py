@@ -176,6 +176,24 @@ class Renderer:
                     "art_render")
         return F, A, T
 
+    def render_ckpt(self, sigma, feat, lambda_th: float = LAMBDA_TH, K: int = 8, every: int = 32,
+                    fp32_geom: bool = False, timing: bool = False):
+        """render() that also records ray checkpoints for backward(ckpt=...)
+        (art_render_ckpt): returns (F, A, T, ckpt) with ckpt = (records
+        [P][V][H][W][K][C + 4] float32, counts [P][V][H][W] int32, K, every)."""
+        torch = self._torch
+        C, dtype = self._flut(sigma, feat)
+        dev = sigma.device
+        F = torch.empty((self.P, self.V, C, self.H, self.W), dtype=torch.float32, device=dev)
+        A = torch.empty((self.P, self.V, self.H, self.W), dtype=torch.float32, device=dev)
+        T = torch.empty_like(A)
+        rec = torch.empty((self.P, self.V, self.H, self.W, K, C + 4), dtype=torch.float32, device=dev)
+        cnt = torch.zeros((self.P, self.V, self.H, self.W), dtype=torch.int32, device=dev)
+        self._check(self.lib.art_render_ckpt(self._h, C, dtype, _tptr(sigma), _tptr(feat), float(lambda_th),
+                                             self._flags(fp32_geom, timing), _tptr(F), _tptr(A), _tptr(T),
+                                             int(K), int(every), _tptr(rec), _tptr(cnt)), "art_render_ckpt")
+        return F, A, T, (rec, cnt, int(K), int(every))
+
     def render_status(self) -> dict:
         """Outcome of the last call made with sync=False (art_render_status):
         overflowed (pose, view group) items and invalid densities."""
@@ -345,11 +363,12 @@ class Renderer:
 
     def backward(self, sigma, feat, F, T, dF, dA=None, lambda_th: float = LAMBDA_TH,
                  fp32_geom: bool = False, timing: bool = False, d_sigma=None, d_feat=None,
-                 reuse_build: bool = False):
+                 reuse_build: bool = False, ckpt=None):
         """Accumulate dL/dsigma [n] and dL/dfeat [n][C] (float32) for the last
         render's inputs; returns (d_sigma, d_feat).  reuse_build: use the posed
         octrees and tile lists the last render left when still valid
-        (ART_REUSE_BUILD)."""
+        (ART_REUSE_BUILD).  ckpt: the checkpoints of render_ckpt (the
+        segmented adjoint, art_backward_ckpt)."""
         torch = self._torch
         C, dtype = self._flut(sigma, feat)
         if d_sigma is None:
@@ -359,6 +378,13 @@ class Renderer:
         dF = dF.contiguous().float()
         dA = None if dA is None else dA.contiguous().float()
         flags = self._flags(fp32_geom, timing) | (_lib.ART_REUSE_BUILD if reuse_build else 0)
+        if ckpt is not None:
+            rec, cnt, K, every = ckpt
+            self._check(self.lib.art_backward_ckpt(self._h, C, dtype, _tptr(sigma), _tptr(feat), float(lambda_th),
+                                                   flags, _tptr(F), _tptr(T), _tptr(dF), _tptr(dA),
+                                                   _tptr(d_sigma), _tptr(d_feat), int(K), int(every), _tptr(rec),
+                                                   _tptr(cnt)), "art_backward_ckpt")
+            return d_sigma, d_feat
         self._check(self.lib.art_backward(self._h, C, dtype, _tptr(sigma), _tptr(feat), float(lambda_th),
                                           flags, _tptr(F), _tptr(T), _tptr(dF),
                                           _tptr(dA), _tptr(d_sigma), _tptr(d_feat)),

@@ -47,6 +47,8 @@ SIGNATURES = [
     ("art_set_cameras", _I, [_P, _I, _I, _I, _P, _P]),
     ("art_render", _I, [_P, _I, _I, _P, _P, _F, _U, _P, _P, _P]),
     ("art_backward", _I, [_P, _I, _I, _P, _P, _F, _U, _P, _P, _P, _P, _P, _P]),
+    ("art_render_ckpt", _I, [_P, _I, _I, _P, _P, _F, _U, _P, _P, _P, _I, _I, _P, _P]),
+    ("art_backward_ckpt", _I, [_P, _I, _I, _P, _P, _F, _U, _P, _P, _P, _P, _P, _P, _I, _I, _P, _P]),
     ("art_proposal_labels", _I, [_P, _I, _I, _P, _P, _F, _U, _P]),
     ("art_render_proposal", _I, [_P, _I, _I, _P, _P, _F, _U, _P, _F, _F, _P, _P, _P]),
     ("art_render_depth", _I, [_P, _I, _I, _P, _P, _F, _U, _F, _P, _P, _P, _P]),

@@ -347,6 +347,10 @@ struct PassOut {
     int32_t* hit_count = nullptr;
     bool single_pose = false;   // maps hold one pose only
     bool reuse = false;         // ART_REUSE_BUILD was asked for
+    // ray checkpoints (mode 7 writes them, the segmented adjoint reads them)
+    float* ckpt = nullptr;
+    int32_t* ckpt_n = nullptr;
+    int ckpt_K = 0, ckpt_every = 0;
 };
 
 // Skinning + octree build of poses [p0, p0 + batch) into slots 0..batch-1.
@@ -458,6 +462,12 @@ art_status run_batch(art_ctx* ctx, const CallPlan& pl, int mode, float lambda, c
     if (o.out_feat) r.out_feat = o.out_feat + m0 * pl.C * HW;
     if (o.out_alpha) r.out_alpha = o.out_alpha + m0 * HW;
     if (o.out_tfinal) r.out_tfinal = o.out_tfinal + m0 * HW;
+    if (o.ckpt) {
+        r.ckpt = o.ckpt + m0 * HW * (size_t)o.ckpt_K * (pl.C + 4);
+        r.ckpt_n = o.ckpt_n + m0 * HW;
+        r.ckpt_K = o.ckpt_K;
+        r.ckpt_every = o.ckpt_every;
+    }
     if (o.fwd_feat) r.fwd_feat = o.fwd_feat + m0 * pl.C * HW;
     if (o.fwd_tfinal) r.fwd_tfinal = o.fwd_tfinal + m0 * HW;
     if (o.d_feat) r.d_feat = o.d_feat + m0 * pl.C * HW;
@@ -506,7 +516,7 @@ art_status run_batch(art_ctx* ctx, const CallPlan& pl, int mode, float lambda, c
     tl.stats = s.stats.as<unsigned long long>();
     // the forward maps' background pixels are written by the compositing
     // kernel's waves between their tiles (overlapping their compositing)
-    tl.bg_in_render = (mode == 0 || mode == 4 || mode == 5 || mode == 6) && tl.out_feat && !tl.labels &&
+    tl.bg_in_render = (mode == 0 || mode == 4 || mode == 5 || mode == 6 || mode == 7) && tl.out_feat && !tl.labels &&
                       !tl.hit_count && background_vectorised(tl) && bg_in_render_enabled() &&
                       (uint64_t)Pb * ctx->V * ctx->H * ctx->W / 4 < (1ull << 31);
     r.bg_in_render = tl.bg_in_render;
@@ -769,6 +779,10 @@ hipError_t launch_render(const RenderLaunch& r, hipStream_t st) {
     a.dom_bone = r.dom_bone;
     a.bone_rot = r.bone_rot;
     a.adj_merge = adj_merge_policy();
+    a.ckpt = r.ckpt;
+    a.ckpt_n = r.ckpt_n;
+    a.ckpt_K = r.ckpt_K;
+    a.ckpt_every = r.ckpt ? r.ckpt_every : 0;
     a.bg_in_render = r.bg_in_render ? 1 : 0;
     a.max_hits = r.max_hits;
     a.debug_view = r.debug_view;
@@ -1107,6 +1121,59 @@ art_status art_backward(art_ctx* ctx, int C, art_dtype dtype, const void* sigma,
     o.d_sigma = d_sigma;
     o.d_leaf_feat = d_leaf_feat;
     o.reuse = (flags & ART_REUSE_BUILD) != 0;
+    return render_call(ctx, C, dtype, sigma, feat, lambda_th, flags & ~ART_REUSE_BUILD, 1, o, 0, ctx->P);
+}
+
+// Ray checkpoints: K records of C + 4 words per ray, one every `every` samples.
+static art_status check_ckpt(art_ctx* ctx, int K, int every, const float* ckpt, const int32_t* ckpt_n) {
+    if (!ckpt || !ckpt_n) return fail(ctx, ART_EINVAL, "ckpt / ckpt_n is NULL");
+    if (K < 1 || K > 64) return fail(ctx, ART_EINVAL, "K must be in 1..64");
+    if (every < 1 || every > 65536) return fail(ctx, ART_EINVAL, "every must be in 1..65536");
+    if ((reinterpret_cast<uintptr_t>(ckpt) & 7u) != 0) return fail(ctx, ART_EINVAL, "ckpt must be 8-byte aligned");
+    return ART_OK;
+}
+
+art_status art_render_ckpt(art_ctx* ctx, int C, art_dtype dtype, const void* sigma, const void* feat,
+                           float lambda_th, unsigned flags, float* out_feat, float* out_alpha, float* out_tfinal,
+                           int K, int every, float* ckpt, int32_t* ckpt_n) {
+    if (!ctx) return ART_EINVAL;
+    if (!out_feat || !out_alpha || !out_tfinal) return fail(ctx, ART_EINVAL, "out_feat / out_alpha / out_tfinal is NULL");
+    art_status rc = check_ckpt(ctx, K, every, ckpt, ckpt_n);
+    if (rc != ART_OK) return rc;
+    DeviceGuard g(ctx->device);
+    PassOut o;
+    o.out_feat = out_feat;
+    o.out_alpha = out_alpha;
+    o.out_tfinal = out_tfinal;
+    o.ckpt = ckpt;
+    o.ckpt_n = ckpt_n;
+    o.ckpt_K = K;
+    o.ckpt_every = every;
+    return render_call(ctx, C, dtype, sigma, feat, lambda_th, flags, 7, o, 0, ctx->P);
+}
+
+art_status art_backward_ckpt(art_ctx* ctx, int C, art_dtype dtype, const void* sigma, const void* feat,
+                             float lambda_th, unsigned flags, const float* out_feat, const float* out_tfinal,
+                             const float* d_feat, const float* d_alpha, float* d_sigma, float* d_leaf_feat, int K,
+                             int every, const float* ckpt, const int32_t* ckpt_n) {
+    if (!ctx) return ART_EINVAL;
+    if (!out_feat || !out_tfinal || !d_feat || !d_sigma || !d_leaf_feat)
+        return fail(ctx, ART_EINVAL, "backward needs out_feat, out_tfinal, d_feat, d_sigma, d_leaf_feat");
+    art_status rc = check_ckpt(ctx, K, every, ckpt, ckpt_n);
+    if (rc != ART_OK) return rc;
+    DeviceGuard g(ctx->device);
+    PassOut o;
+    o.fwd_feat = out_feat;
+    o.fwd_tfinal = out_tfinal;
+    o.d_feat = d_feat;
+    o.d_alpha = d_alpha;
+    o.d_sigma = d_sigma;
+    o.d_leaf_feat = d_leaf_feat;
+    o.reuse = (flags & ART_REUSE_BUILD) != 0;
+    o.ckpt = const_cast<float*>(ckpt);   // read only in the adjoint
+    o.ckpt_n = const_cast<int32_t*>(ckpt_n);
+    o.ckpt_K = K;
+    o.ckpt_every = every;
     return render_call(ctx, C, dtype, sigma, feat, lambda_th, flags & ~ART_REUSE_BUILD, 1, o, 0, ctx->P);
 }
 

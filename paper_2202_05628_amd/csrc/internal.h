@@ -311,6 +311,9 @@ struct RenderLaunch {
     int32_t* hit_leaf;
     double* hit_delta;
     int32_t* hit_count;
+    float* ckpt;             // ray checkpoints of the launch's first map (mode 7 writes, mode 1 reads)
+    int32_t* ckpt_n;
+    int ckpt_K, ckpt_every;  // records per ray, samples per segment (0: none)
 };
 hipError_t launch_render(const RenderLaunch& r, hipStream_t st);
 int num_cus();   // compute units of the current device

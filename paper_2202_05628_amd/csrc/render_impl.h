@@ -131,6 +131,12 @@ struct RArgs {
     const float* bone_rot;                 // [Pb][J][12] bone transforms of the launch's poses (MODE 6)
     float depth_sigma;                     // MODE 5: density threshold of the depth buffer
     int adj_merge;                         // MODE 1: 0 never, 1 always, 2 with >= 2 tiles per workgroup
+    // ray checkpoints (MODE 7 writes them, MODE 1 starts its segments from
+    // them): before composited sample j S (j = 1 .. K) of a ray, record j - 1
+    // = {entry t (double), T, P[C] = sum of w f so far}, C + 4 words per record
+    float* ckpt;                           // [rays of the launch][K][C + 4]
+    int32_t* ckpt_n;                       // [rays of the launch] records written
+    int ckpt_K, ckpt_every;                // K records per ray, S samples per segment (0: no checkpoints)
     int bg_in_render;                      // the waves also write the background pixels (empty tiles)
     int max_hits;
     int debug_view;                        // view whose hit lists are recorded (MODE 2)
@@ -352,7 +358,8 @@ __device__ inline void root_span(const R* d, const R* q, const R* inv, R h, int 
 // 6 forward with view-dependent features (Eq. 2 in Eq. 5): the FLUT holds H
 // blocks of C SH coefficients per leaf, and a sample contributes
 // w sum_h k_h Y_h(d^c) at the canonical direction d^c = R^T d, R the rotation
-// of the leaf's dominant bone in the tile's pose
+// of the leaf's dominant bone in the tile's pose,
+// 7 forward recording ray checkpoints for a segmented adjoint (RArgs::ckpt)
 #ifndef ART_RENDER_WAVES_PER_EU
 #define ART_RENDER_WAVES_PER_EU 3
 #endif
@@ -541,7 +548,7 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
                                    uint32_t (*s_mask)[16][kMaskPitch],
                                    uint16_t (*s_pref)[16][kPrefPitch], uint32_t (*s_row)[kStage],
                                    const uint16_t* s_mlut,
-                                   uint32_t (*s_coord)[kStage], float* s_rot, AdjLds<C>* s_adj) {
+                                   uint32_t (*s_coord)[kStage], float* s_rot, AdjLds<C>* s_adj, int seg = 0) {
     constexpr int wv = 0;
     const int pvi = (int)(item / (uint32_t)a.TPV);   // pose-in-launch * V + view
     const int tile_in_view = (int)(item % (uint32_t)a.TPV);
@@ -635,8 +642,41 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
         }
     }
 
+    // ---- adjoint segment (MODE 1 with the forward's checkpoints) -----------------
+    // Segment seg of a ray covers its composited samples [seg S, (seg + 1) S)
+    // - the last one the rest of the ray - from the entry t, T and P recorded
+    // before sample seg S to the entry t of sample (seg + 1) S.  The partition
+    // restarted at a recorded entry (a lattice crossing or a brick entry)
+    // gives the same cells and chords, and from the recorded T the same
+    // transmittances and stop.
+    float T0 = 1.0f;
+    const float* ck_P = nullptr;
+    bool seg_counts = true;   // the ray-level statistics are counted once, in segment 0
+    if constexpr (MODE == 1) {
+        if (a.ckpt_every > 0) {
+            seg_counts = seg == 0;
+            if (active) {
+                const size_t ray = map * HW + pix;
+                const int nck = a.ckpt_n[ray];
+                const float* base = a.ckpt + ray * (size_t)a.ckpt_K * (C + 4);
+                if (seg > nck) {
+                    active = false;
+                } else {
+                    if (seg < nck) tb = fmin(tb, (R)*reinterpret_cast<const double*>(base + (size_t)seg * (C + 4)));
+                    if (seg > 0) {
+                        const float* rec = base + (size_t)(seg - 1) * (C + 4);
+                        ta = fmax(ta, (R)*reinterpret_cast<const double*>(rec));
+                        T0 = rec[2];
+                        ck_P = rec + 3;
+                    }
+                }
+            }
+            if (__ballot(active) == 0ull) return;   // no ray of the tile has this segment
+        }
+    }
+
     // ---- per-lane accumulators --------------------------------------------------
-    float T = 1.0f, Aacc = 0.0f;
+    float T = T0, Aacc = 0.0f;
     float F[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) F[c] = 0.0f;
@@ -663,6 +703,10 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
             }
             gA = a.d_alpha ? a.d_alpha[map * HW + pix] : 0.0f;
             Tfin = a.fwd_tfinal[map * HW + pix];
+            if (ck_P) {   // a later segment: g . P at its first sample
+#pragma unroll
+                for (int c = 0; c < C; ++c) gP = __fmaf_rn(g[c], ck_P[c], gP);
+            }
         }
 #if ART_ADJ_LINES
 #pragma unroll
@@ -929,7 +973,7 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
                             sB0 = s;
                             sB1 = s1;
                         }
-                        if constexpr (MODE == 5) sB0 = s;
+                        if constexpr (MODE == 5 || MODE == 7) sB0 = s;
                         hasB = true;
                     }
 #if ART_SKIP_EMPTY
@@ -1042,6 +1086,18 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
                     for (int c = 0; c < C; ++c) unsafeAtomicAdd(&a.d_leaf_feat[(size_t)leaf * C + c], w * g[c]);
 #endif
                 } else {
+                    if constexpr (MODE == 7) {
+                        // checkpoint before composited sample j S (j = 1 .. K): its entry
+                        // distance, T and the feature sum before it
+                        const int j = nsamp / a.ckpt_every;
+                        if (nsamp > 0 && nsamp == j * a.ckpt_every && j <= a.ckpt_K) {
+                            float* rec = a.ckpt + ((map * HW + pix) * (size_t)a.ckpt_K + (size_t)(j - 1)) * (C + 4);
+                            *reinterpret_cast<double*>(rec) = (double)sA0;
+                            rec[2] = T;
+#pragma unroll
+                            for (int c = 0; c < C; ++c) rec[3 + c] = F[c];
+                        }
+                    }
                     if constexpr (MODE == 6) {
                         // S_c = sum_h k_{h,c} Y_h(R^T d); the first block is the prefetched row
                         const float* Rm = s_rot + domA * 9;
@@ -1178,6 +1234,10 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
             if (a.out_tfinal) store_stream(&a.out_tfinal[map * HW + pix], T);
             if constexpr (MODE == 2) a.hit_count[pix] = nsamp;
             if constexpr (MODE == 5) a.out_depth[map * HW + pix] = zdep;
+            if constexpr (MODE == 7) {
+                const int nck = nsamp > 0 ? (nsamp - 1) / a.ckpt_every : 0;
+                a.ckpt_n[map * HW + pix] = nck < a.ckpt_K ? nck : a.ckpt_K;
+            }
         }
     }
     if (a.stats) {
@@ -1186,11 +1246,13 @@ __device__ inline void render_tile(const RArgs& a, uint32_t item, uint32_t idx, 
         const unsigned long long ns = (unsigned long long)wave_sum((unsigned)nsamp);
         const unsigned long long steps = (unsigned long long)wave_sum(nsteps);
         if (lane == 0 && rays) {   // wave-uniform values
-            ws.v[0] += (unsigned long long)__popcll(rays);
+            if (seg_counts) {
+                ws.v[0] += (unsigned long long)__popcll(rays);
+                ws.v[2] += (unsigned long long)__popcll(hits);
+                ws.v[7] += (unsigned long long)(le - ls);
+                ws.v[10] += (unsigned long long)__popcll(rays);
+            }
             ws.v[1] += ns;
-            ws.v[2] += (unsigned long long)__popcll(hits);
-            ws.v[7] += (unsigned long long)(le - ls);
-            ws.v[10] += (unsigned long long)__popcll(rays);
             ws.v[8] += (unsigned long long)rounds;
             ws.v[9] += steps;
         }
@@ -1278,7 +1340,11 @@ void k_render(RArgs a) {
                                    (spread3_small((uint32_t)e >> 6) << 2));
         wave_sync();
     }
-    const uint32_t n_items = *a.n_items;
+    const uint32_t n_tiles = *a.n_items;
+    // MODE 1 with checkpoints: K + 1 segments per tile, item v = (tile v / (K + 1),
+    // segment v mod (K + 1)) - the segments of one tile are taken together
+    const uint32_t nseg = (MODE == 1 && a.ckpt_every > 0) ? (uint32_t)a.ckpt_K + 1u : 1u;
+    const uint32_t n_items = n_tiles * nseg;
 #if ART_ADJ_SORT
     if constexpr (MODE == 1) {
         if (lane == 0)
@@ -1293,7 +1359,7 @@ void k_render(RArgs a) {
     // after every `every` tiles - spread so that the stores overlap the
     // compositing - and the remaining chunks once the work list is drained.
     uint32_t n_bg = 0, every = 0xFFFFFFFFu, since = 0, bg_groups = 0;
-    if constexpr (MODE == 0 || MODE == 4 || MODE == 5 || MODE == 6) {
+    if constexpr (MODE == 0 || MODE == 4 || MODE == 5 || MODE == 6 || MODE == 7) {
         if (a.bg_in_render) {
             bg_groups = (uint32_t)((uint64_t)a.Pb * a.V * a.H * a.W / 4);
             n_bg = (bg_groups + kBgChunkGroups - 1) / kBgChunkGroups;
@@ -1324,8 +1390,9 @@ void k_render(RArgs a) {
                 continue;   // the next part, or the remaining background
             }
             for (uint32_t t = 0; t < (uint32_t)ART_TILES_PER_GRAB && idx + t < end; ++t) {
-                render_tile<C, ST, R, MODE>(a, a.items[idx + t], idx + t, lane, ws, s_mask, s_pref, s_row, s_mlut,
-                                            s_coord, s_rot, s_adj);
+                const uint32_t v = idx + t;
+                render_tile<C, ST, R, MODE>(a, a.items[v / nseg], v / nseg, lane, ws, s_mask, s_pref, s_row, s_mlut,
+                                            s_coord, s_rot, s_adj, (int)(v % nseg));
                 wave_sync();
             }
             if (++since < every) continue;   // (every is 2^32 - 1 without background work)
@@ -1351,6 +1418,7 @@ hipError_t launch_render_mode(const RenderLaunch& r, const RArgs& a, unsigned gr
         case 4: hipLaunchKernelGGL((k_render<C, ST, R, 4>), dim3(grid), dim3(64), 0, st, a); break;
         case 5: hipLaunchKernelGGL((k_render<C, ST, R, 5>), dim3(grid), dim3(64), 0, st, a); break;
         case 6: hipLaunchKernelGGL((k_render<C, ST, R, 6>), dim3(grid), dim3(64), 0, st, a); break;
+        case 7: hipLaunchKernelGGL((k_render<C, ST, R, 7>), dim3(grid), dim3(64), 0, st, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
