@@ -177,10 +177,11 @@ class Renderer:
         return F, A, T
 
     def render_ckpt(self, sigma, feat, lambda_th: float = LAMBDA_TH, K: int = 8, every: int = 32,
-                    fp32_geom: bool = False, timing: bool = False):
+                    fp32_geom: bool = False, timing: bool = False, sync: bool = True):
         """render() that also records ray checkpoints for backward(ckpt=...)
         (art_render_ckpt): returns (F, A, T, ckpt) with ckpt = (records
-        [P][V][H][W][K][C + 4] float32, counts [P][V][H][W] int32, K, every)."""
+        [P][V][H][W][K][C + 4] float32, counts [P][V][H][W] int32, K, every).
+        sync=False: as render(sync=False)."""
         torch = self._torch
         C, dtype = self._flut(sigma, feat)
         dev = sigma.device
@@ -190,7 +191,7 @@ class Renderer:
         rec = torch.empty((self.P, self.V, self.H, self.W, K, C + 4), dtype=torch.float32, device=dev)
         cnt = torch.zeros((self.P, self.V, self.H, self.W), dtype=torch.int32, device=dev)
         self._check(self.lib.art_render_ckpt(self._h, C, dtype, _tptr(sigma), _tptr(feat), float(lambda_th),
-                                             self._flags(fp32_geom, timing), _tptr(F), _tptr(A), _tptr(T),
+                                             self._flags(fp32_geom, timing, sync), _tptr(F), _tptr(A), _tptr(T),
                                              int(K), int(every), _tptr(rec), _tptr(cnt)), "art_render_ckpt")
         return F, A, T, (rec, cnt, int(K), int(every))
 
@@ -492,28 +493,46 @@ class Renderer:
                 "m_f": torch.zeros_like(feat), "v_f": torch.zeros_like(feat)}
 
     def train_step(self, sigma, feat, state: dict, F_target, A_target=None, lr: float = 1e-2,
-                   lambda_vrt: float = 0.0, lambda_th: float = LAMBDA_TH, fp32_geom: bool = False) -> dict:
+                   lambda_vrt: float = 0.0, lambda_th: float = LAMBDA_TH, fp32_geom: bool = False,
+                   segments=None) -> dict:
         """One FLUT training step (Section 3.1, "Training", without the shading
         network): render every pose and view, the map loss
         L_map = 1/(2R) [sum (F - F*)^2 + sum (A - A*)^2] over the R rays (the A
         term when A_target is given), its gradient by the adjoint kernel, the
         voxel regularisation term and its gradient (lambda_vrt > 0), then Adam
         on sigma (projected onto sigma >= 0) and feat, in place.  Returns the
-        losses of the FLUT before the update."""
+        losses of the FLUT before the update.
+
+        segments = (K, every): the segmented adjoint from ray checkpoints
+        (render_ckpt); by default on launches of at most 8M rays (K = 6,
+        every = 36: there the adjoint's time is the chain of its longest rays,
+        and the checkpoints take 80 B per ray and record), "off" to disable."""
         torch = self._torch
+        rays = self.P * self.V * self.H * self.W
+        if segments is None:
+            segments = (6, 36) if rays <= 8 * 1024 * 1024 else "off"
+        ck = None
+
+        def render(sync):
+            if segments == "off":
+                return self.render(sigma, feat, lambda_th, fp32_geom=fp32_geom, sync=sync) + (None,)
+            return self.render_ckpt(sigma, feat, lambda_th, K=segments[0], every=segments[1],
+                                    fp32_geom=fp32_geom, sync=sync)
+
         # the render only enqueues its work; the map loss reads its value back
         # (one synchronisation), after which the render's status is read
         # without waiting: a step whose tile lists overflowed renders again
         # with the grown lists (an invalid density raises there)
-        F, A, T = self.render(sigma, feat, lambda_th, fp32_geom=fp32_geom, sync=False)
+        F, A, T, ck = render(False)
         l_map, dF, dA = self.map_loss(F, F_target, A, A_target)
         st = self.render_status()
         if st["overflowed_items"] or st["bad_densities"]:
-            F, A, T = self.render(sigma, feat, lambda_th, fp32_geom=fp32_geom)
+            F, A, T, ck = render(True)
             l_map, dF, dA = self.map_loss(F, F_target, A, A_target)
         # the adjoint and the VRT read the posed octrees (and tile lists) the
         # render just built: the poses and the octree did not change
-        d_sigma, d_feat = self.backward(sigma, feat, F, T, dF, dA, lambda_th, fp32_geom=fp32_geom, reuse_build=True)
+        d_sigma, d_feat = self.backward(sigma, feat, F, T, dF, dA, lambda_th, fp32_geom=fp32_geom, reuse_build=True,
+                                        ckpt=ck)
         l_vrt = 0.0
         if lambda_vrt > 0.0:
             l_vrt, _ = self.vrt(feat, lambda_vrt, d_feat=d_feat, fp32_geom=fp32_geom, reuse_build=True)

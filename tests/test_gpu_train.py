@@ -149,6 +149,40 @@ def test_training_step_gradient_matches_oracle(tiny):
     assert e_s <= 1e-4 and e_f <= 1e-4
 
 
+def test_training_step_segmented_equals_unsegmented(tiny):
+    """A training step with the segmented adjoint (checkpoints every 3
+    samples) applies the unsegmented step's update: the same losses (the
+    maps are the same bit for bit) and the same parameters up to the order of
+    the gradient's float sums."""
+    import torch
+    s, rend, *_ = tiny
+    rng = np.random.default_rng(16)
+    Ft = torch.from_numpy(rng.normal(size=(rend.P, rend.V, s.C, rend.H, rend.W)).astype(np.float32)).cuda()
+    out = {}
+    for seg in ((4, 3), "off"):
+        sig = torch.from_numpy(s.sigma).cuda()
+        f = torch.from_numpy(s.feat).cuda()
+        st = rend.train_state(sig, f)
+        loss = rend.train_step(sig, f, st, Ft, lr=0.01, lambda_vrt=0.05, segments=seg)
+        out[str(seg)] = (loss, sig.cpu().numpy(), f.cpu().numpy())
+    (la, sa, fa), (lb, sb, fb) = out["(4, 3)"], out["off"]
+    log(f"segmented training step: losses {la} / {lb}; max |d sigma| {np.abs(sa - sb).max():.2e}, "
+        f"max |d f| {np.abs(fa - fb).max():.2e}")
+    assert la["map"] == lb["map"]                       # the same maps
+    assert abs(la["vrt"] - lb["vrt"]) <= 1e-9 * max(1.0, abs(lb["vrt"]))   # summed with atomics
+    # Adam's first step moves a parameter by lr g / (|g| + eps): about lr sign(g)
+    # where |g| >> eps, where a change of g's last bits changes nothing; where
+    # |g| is near eps the step follows g's summation order
+    s0, f0 = s.sigma.astype(np.float32), s.feat.astype(np.float32)
+    big_s = np.abs(sb - s0) >= 0.005
+    big_f = np.abs(fb - f0) >= 0.005
+    assert big_s.mean() > 0.05 and big_f.mean() > 0.05
+    # within 4 units in the last place of the value, or 1e-6 for values near 0
+    close = lambda x, y: np.abs(x - y) <= np.maximum(4 * np.spacing(np.maximum(np.abs(x), np.abs(y))), 1e-6)
+    assert close(sa, sb)[big_s].all() and close(fa, fb)[big_f].all()
+    assert np.abs(sa - sb).max() <= 0.02 and np.abs(fa - fb).max() <= 0.02
+
+
 def test_training_fits_target_maps(tiny):
     """Targets rendered from a seeded FLUT; training starts from another seeded
     FLUT.  The map loss falls by a large factor; with the VRT on, the features
