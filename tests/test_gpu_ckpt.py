@@ -53,6 +53,37 @@ def test_checkpointed_forward_equals_forward(tiny):
         assert 0.0 < Tk[-1] and Tk[0] < 1.0 and Tk[-1] >= Tf[p, v, y, x]
 
 
+def test_checkpoints_after_tile_list_overflow(tiny, monkeypatch):
+    """With tile lists too small for the call (every item renders again after
+    the lists grow), the records and counts equal those of a call without
+    overflow bit for bit, and the segmented adjoint from them equals the one
+    from the records of the call without overflow."""
+    import torch
+    s, rend, B, K, c2w = tiny
+    sig, f = flut(s)
+    F0, A0, T0, (rec0, cnt0, _, _) = rend.render_ckpt(sig, f, 0.01, K=6, every=3)
+    monkeypatch.setenv("ARTEMIS_PAIR_CAP", "64")   # every tile list overflows
+    poses = sg.make_poses(s.J, 2)
+    rend2 = make_renderer(s, poses, K, c2w, 96, 96)
+    F, A, T, ck = rend2.render_ckpt(sig, f, 0.01, K=6, every=3)
+    monkeypatch.delenv("ARTEMIS_PAIR_CAP")
+    assert torch.equal(F, F0) and torch.equal(A, A0) and torch.equal(T, T0)
+    c0 = cnt0.cpu().numpy()
+    assert np.array_equal(ck[1].cpu().numpy(), c0)
+    r0, r1 = rec0.cpu().numpy(), ck[0].cpu().numpy()
+    k = np.arange(r0.shape[4])[None, None, None, None, :] < c0[..., None]   # written records
+    w = s.C + 3   # t (2 words), T, P[C]; the last word is unused
+    assert np.array_equal(r0[k][:, :w].view(np.uint32), r1[k][:, :w].view(np.uint32))
+    rng = np.random.default_rng(9)
+    dF = torch.from_numpy(rng.normal(size=tuple(F.shape)).astype(np.float32)).cuda()
+    ds0, df0 = rend.backward(sig, f, F0, T0, dF, None, 0.01, ckpt=(rec0, cnt0, 6, 3))
+    ds1, df1 = rend2.backward(sig, f, F, T, dF, None, 0.01, ckpt=ck, reuse_build=True)
+    es = (ds1 - ds0).abs().max().item() / ds0.abs().max().item()
+    ef = (df1 - df0).abs().max().item() / df0.abs().max().item()
+    log(f"checkpoints after overflow: dsigma rel {es:.2e}, dfeat rel {ef:.2e}")
+    assert es <= 1e-6 and ef <= 1e-6
+
+
 @pytest.mark.parametrize("lam", [0.0, 0.01])
 def test_segmented_adjoint_matches_oracle(tiny, lam):
     import torch
