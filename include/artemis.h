@@ -471,6 +471,15 @@ int64_t art_proposal_param_count(int J);
 art_status art_proposal_set_weights(art_ctx* ctx, int64_t count, const float* w);
 art_status art_proposal_get_weights(art_ctx* ctx, int64_t count, float* w);
 
+/* Seeded initial weights (resets the Adam state, as art_proposal_set_weights):
+ * every weight and bias of a layer with fan-in m is (2u - 1) / sqrt(m), u in
+ * [0, 1) the top 24 bits of output i + 1 of the SplitMix64 stream of `seed`
+ * (Steele, Lea and Flood, OOPSLA 2014) for flat parameter index i (the order
+ * of art_proposal_set_weights).  The same seed gives the same weights on any
+ * device.
+ * Errors: ART_ESTATE (no skeleton). */
+art_status art_proposal_init(art_ctx* ctx, uint64_t seed);
+
 /*
  * Network inputs and targets of selected rays: ray_id (device int64 [n]) are
  * indices into [P][V][H][W] of the current poses and cameras; labels is the

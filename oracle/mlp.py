@@ -45,6 +45,7 @@ gradients are plain sums of the deltas.
 """
 from __future__ import annotations
 
+import math
 from typing import Dict, List, Tuple
 
 import numpy as np
@@ -224,3 +225,35 @@ def adam_step(theta: np.ndarray, m: np.ndarray, v: np.ndarray, g: np.ndarray, st
     v_hat = v / (1.0 - beta2 ** step)
     theta = theta - lr * m_hat / (np.sqrt(v_hat) + eps)
     return theta, m, v
+
+
+_M64 = (1 << 64) - 1
+
+
+def splitmix64(seed: int, k: int) -> int:
+    """Output k (k = 1, 2, ...) of the SplitMix64 stream of `seed` (Steele, Lea
+    and Flood, "Fast splittable pseudorandom number generators", OOPSLA 2014):
+    the state after k steps of the odd increment 0x9E3779B97F4A7C15, mixed by
+    two xor-shift-multiply rounds and a final xor-shift (64-bit arithmetic)."""
+    z = (seed + k * 0x9E3779B97F4A7C15) & _M64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _M64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _M64
+    return z ^ (z >> 31)
+
+
+def init_params(J: int, seed: int) -> np.ndarray:
+    """Seeded initial parameters (flat order, float32): parameter i of a layer
+    with fan-in m is (2u - 1) / sqrt(m), u = (top 24 bits of output i + 1 of
+    the SplitMix64 stream of `seed`) / 2^24, so every value lies in
+    (-1/sqrt(m), 1/sqrt(m)) - the uniform initialisation of fully connected
+    layers."""
+    out = np.empty(param_count(J), dtype=np.float32)
+    i = 0
+    for name, shape in param_shapes(J):
+        fan_in = input_dim(J) if name in ("W1", "b1") else HIDDEN
+        k = 1.0 / math.sqrt(fan_in)
+        for _ in range(int(np.prod(shape))):
+            u = (splitmix64(seed, i + 1) >> 40) * 2.0 ** -24
+            out[i] = np.float32((2.0 * u - 1.0) * k)
+            i += 1
+    return out

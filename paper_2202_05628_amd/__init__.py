@@ -289,6 +289,11 @@ class Renderer:
         w = np.ascontiguousarray(w, dtype=np.float32).reshape(-1)
         self._check(self.lib.art_proposal_set_weights(self._h, w.size, _ptr(w)), "art_proposal_set_weights")
 
+    def init_proposal(self, seed: int) -> None:
+        """Seeded initial proposal weights drawn in the library
+        (art_proposal_init; resets the Adam state)."""
+        self._check(self.lib.art_proposal_init(self._h, int(seed) & ((1 << 64) - 1)), "art_proposal_init")
+
     def get_proposal_weights(self) -> np.ndarray:
         w = np.zeros(self.proposal_param_count(), dtype=np.float32)
         self._check(self.lib.art_proposal_get_weights(self._h, w.size, _ptr(w)), "art_proposal_get_weights")

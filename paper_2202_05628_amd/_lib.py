@@ -63,6 +63,7 @@ SIGNATURES = [
     ("art_proposal_param_count", _L, [_I]),
     ("art_proposal_set_weights", _I, [_P, _L, _P]),
     ("art_proposal_get_weights", _I, [_P, _L, _P]),
+    ("art_proposal_init", _I, [_P, ctypes.c_uint64]),
     ("art_proposal_gather", _I, [_P, _L, _P, _P, _P, _P, _P]),
     ("art_proposal_set_loss", _I, [_P, _I, _F, _F]),
     ("art_proposal_calibrate", _I, [_P, _L, _P, _P, _P, _F, _F, ctypes.POINTER(_F)]),

@@ -1532,6 +1532,34 @@ art_status art_proposal_set_weights(art_ctx* ctx, int64_t count, const float* w)
     return ART_OK;
 }
 
+// SplitMix64 (Steele, Lea and Flood, "Fast splittable pseudorandom number
+// generators", OOPSLA 2014): output k (k = 1, 2, ...) of the stream of `seed`.
+static uint64_t splitmix64(uint64_t seed, uint64_t k) {
+    uint64_t z = seed + k * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+art_status art_proposal_init(art_ctx* ctx, uint64_t seed) {
+    if (!ctx) return ART_EINVAL;
+    if (ctx->J <= 0) return fail(ctx, ART_ESTATE, "no skeleton (art_set_skeleton)");
+    const MlpDims m = mlp_dims(ctx->J);
+    // parameter i (flat order) takes output i + 1 of the stream: its top 24
+    // bits give u in [0, 1), the value (2u - 1) / sqrt(fan-in of its layer)
+    const int fan_in[4] = {m.n_in, 64, 64, 64};
+    const int start[5] = {m.oW1, m.oW2, m.oW3, m.oW4, m.np};
+    std::vector<float> w((size_t)m.np);
+    for (int l = 0; l < 4; ++l) {
+        const double k = 1.0 / std::sqrt((double)fan_in[l]);
+        for (int i = start[l]; i < start[l + 1]; ++i) {
+            const double u = (double)(splitmix64(seed, (uint64_t)i + 1u) >> 40) * 0x1.0p-24;
+            w[(size_t)i] = (float)((2.0 * u - 1.0) * k);
+        }
+    }
+    return art_proposal_set_weights(ctx, m.np, w.data());
+}
+
 art_status art_proposal_get_weights(art_ctx* ctx, int64_t count, float* w) {
     if (!ctx) return ART_EINVAL;
     if (ctx->mlp_J <= 0 || ctx->mlp_J != ctx->J)

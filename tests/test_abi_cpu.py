@@ -39,7 +39,8 @@ def test_null_context_is_rejected_without_device_work():
     assert lib.art_last_error(None) == b""
     lib.art_destroy(None)
     for fn, args in [("art_load_octree", (None, 3, 1, None)), ("art_set_skin", (None, None, None)),
-                     ("art_render", (None, 8, 0, None, None, 0.0, 0, None, None, None))]:
+                     ("art_render", (None, 8, 0, None, None, 0.0, 0, None, None, None)),
+                     ("art_proposal_init", (None, 1))]:
         assert getattr(lib, fn)(*args) == _lib.ART_EINVAL
 
 

@@ -9,7 +9,9 @@
   independently in float64 NumPy from the network's outputs and the rays'
   root spans (slab test written out here).
 * art_map_loss: dL/dF and dL/dA equal (x - y) * float32(1/R) bit for bit; the
-  loss matches the float64 sum of the FP32 differences squared."""
+  loss matches the float64 sum of the FP32 differences squared.
+* art_proposal_init: the seeded weights equal the oracle's initialisation bit
+  for bit and reset the Adam state."""
 import os
 
 import numpy as np
@@ -74,6 +76,39 @@ def test_proposal_state_resumes_bit_for_bit(setup, tmp_path):
     assert not np.array_equal(wa, d.get_proposal_weights())
     for r in (a, b, c, d):
         r.close()
+
+
+def test_seeded_init_matches_oracle_and_resets_adam(setup):
+    """art_proposal_init(seed): the weights equal the oracle's SplitMix64
+    initialisation bit for bit, and a second init with the same seed after
+    training restores them with a fresh Adam state (the same training steps
+    then give the same weights)."""
+    import oracle.mlp as omlp
+    import paper_2202_05628_amd as art
+    st = setup
+    od, pose, tgt = st["od"], st["pose"], st["tgt"]
+    J = st["s"].J
+    r = make_renderer(st["s"], st["poses"], st["K"], st["c2w"], st["H"], st["W"])
+    r.init_proposal(7)
+    w0 = r.get_proposal_weights()
+    ref = omlp.init_params(J, 7)
+    log(f"seeded init: {w0.size} weights, max |library - oracle| = {np.abs(w0 - ref).max():.3e}")
+    assert np.array_equal(w0.view(np.uint32), ref.view(np.uint32))
+    r.proposal_train(od, pose, tgt, steps=8, batch=1024, lr=1e-3)
+    w1 = r.get_proposal_weights()
+    assert not np.array_equal(w1, w0)
+    r.init_proposal(7)
+    assert np.array_equal(r.get_proposal_weights(), w0)
+    r.proposal_train(od, pose, tgt, steps=8, batch=1024, lr=1e-3)
+    assert np.array_equal(r.get_proposal_weights(), w1)
+    r.init_proposal(8)
+    assert not np.array_equal(r.get_proposal_weights(), w0)
+    r.close()
+    # no skeleton: refused
+    e = art.Renderer(0)
+    with pytest.raises(art.ArtemisError, match="ART_ESTATE"):
+        e.init_proposal(1)
+    e.close()
 
 
 def test_proposal_state_refuses_bad_files(setup, tmp_path):

@@ -146,6 +146,32 @@ def test_mlp_shapes():
     assert sg.make_mlp_init(40).size == 24258
 
 
+def test_splitmix64_published_outputs():
+    """The generator of the seeded initialisation against the first five
+    outputs of SplitMix64 for seed 1234567 as listed in the Rosetta Code task
+    "Pseudo-random numbers/Splitmix64"."""
+    import oracle.mlp as mlp
+    want = [6457827717110365317, 3203168211198807973, 9817491932198370423, 4593380528125082431,
+            16408922859458223821]
+    assert [mlp.splitmix64(1234567, k) for k in range(1, 6)] == want
+
+
+def test_seeded_init_ranges_and_moments():
+    """Every layer's values lie in (-1/sqrt(fan-in), 1/sqrt(fan-in)) with the
+    mean and spread of that uniform distribution; seeds give different draws."""
+    import oracle.mlp as mlp
+    J = 40
+    a, b = mlp.init_params(J, 7), mlp.init_params(J, 8)
+    assert a.dtype == np.float32 and a.size == mlp.param_count(J)
+    assert np.array_equal(a, mlp.init_params(J, 7)) and not np.array_equal(a, b)
+    p = mlp.unpack(a.astype(np.float64), J)
+    for name in ("W1", "W2", "W3"):
+        k = 1.0 / math.sqrt(p[name].shape[1])
+        w = p[name].reshape(-1)
+        assert np.abs(w).max() < k
+        assert abs(w.mean()) < 0.02 * k and abs(w.std() / (k / math.sqrt(3.0)) - 1.0) < 0.03
+
+
 def test_mlp_gradient_finite_differences():
     mlp, theta, X, t = _problem()
     L, g = mlp.grad(theta, X, t, 2)
