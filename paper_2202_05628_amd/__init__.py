@@ -511,7 +511,8 @@ class Renderer:
         segments = (K, every): the segmented adjoint from ray checkpoints
         (render_ckpt); by default on launches of at most 8M rays (K = 6,
         every = 36: there the adjoint's time is the chain of its longest rays,
-        and the checkpoints take 80 B per ray and record), "off" to disable."""
+        and the checkpoints take (C + 4) x 4 bytes per ray and record), "off"
+        to disable."""
         torch = self._torch
         rays = self.P * self.V * self.H * self.W
         if segments is None:
