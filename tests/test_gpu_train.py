@@ -183,6 +183,42 @@ def test_training_step_segmented_equals_unsegmented(tiny):
     assert np.abs(sa - sb).max() <= 0.02 and np.abs(fa - fb).max() <= 0.02
 
 
+def test_training_step_after_tile_list_overflow(tiny, monkeypatch):
+    """With tile lists too small for the call, the step's asynchronous render
+    reports the overflow and the step renders again (with its checkpoints)
+    before the adjoint: the losses and the update equal those of a step
+    without overflow."""
+    import torch
+    s, rend, _, _, K, c2w = tiny
+    rng = np.random.default_rng(17)
+    Ft = torch.from_numpy(rng.normal(size=(rend.P, rend.V, s.C, rend.H, rend.W)).astype(np.float32)).cuda()
+    monkeypatch.setenv("ARTEMIS_PAIR_CAP", "64")   # every tile list overflows
+    small = make_renderer(s, sg.make_poses(s.J, 3), K, c2w, 48, 40)
+    seen = []
+    status = small.render_status
+    small.render_status = lambda: seen.append(status()) or seen[-1]   # record what the step read
+    out = []
+    for r in (small, rend):
+        sig = torch.from_numpy(s.sigma).cuda()
+        f = torch.from_numpy(s.feat).cuda()
+        st = r.train_state(sig, f)
+        loss = r.train_step(sig, f, st, Ft, lr=0.01, segments=(4, 3))
+        out.append((loss, sig.cpu().numpy(), f.cpu().numpy()))
+    monkeypatch.delenv("ARTEMIS_PAIR_CAP")
+    small.close()
+    assert seen and seen[0]["overflowed_items"] > 0   # the step's first render did overflow
+    (la, sa, fa), (lb, sb, fb) = out
+    log(f"training step after overflow: losses {la} / {lb}; max |d sigma| {np.abs(sa - sb).max():.2e}, "
+        f"max |d f| {np.abs(fa - fb).max():.2e}")
+    assert la["map"] == lb["map"]
+    s0, f0 = s.sigma.astype(np.float32), s.feat.astype(np.float32)
+    big_s, big_f = np.abs(sb - s0) >= 0.005, np.abs(fb - f0) >= 0.005
+    assert big_s.mean() > 0.05 and big_f.mean() > 0.05
+    close = lambda x, y: np.abs(x - y) <= np.maximum(4 * np.spacing(np.maximum(np.abs(x), np.abs(y))), 1e-6)
+    assert close(sa, sb)[big_s].all() and close(fa, fb)[big_f].all()
+    assert np.abs(sa - sb).max() <= 0.02 and np.abs(fa - fb).max() <= 0.02
+
+
 def test_training_fits_target_maps(tiny):
     """Targets rendered from a seeded FLUT; training starts from another seeded
     FLUT.  The map loss falls by a large factor; with the VRT on, the features
