@@ -40,7 +40,10 @@ def test_null_context_is_rejected_without_device_work():
     lib.art_destroy(None)
     for fn, args in [("art_load_octree", (None, 3, 1, None)), ("art_set_skin", (None, None, None)),
                      ("art_render", (None, 8, 0, None, None, 0.0, 0, None, None, None)),
-                     ("art_proposal_init", (None, 1))]:
+                     ("art_proposal_init", (None, 1)),
+                     ("art_render_ckpt", (None, 8, 0, None, None, 0.0, 0, None, None, None, 6, 3, None, None)),
+                     ("art_backward_ckpt", (None, 8, 0, None, None, 0.0, 0, None, None, None, None, None, None, 6, 3,
+                                            None, None))]:
         assert getattr(lib, fn)(*args) == _lib.ART_EINVAL
 
 

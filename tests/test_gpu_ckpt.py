@@ -53,6 +53,34 @@ def test_checkpointed_forward_equals_forward(tiny):
         assert 0.0 < Tk[-1] and Tk[0] < 1.0 and Tk[-1] >= Tf[p, v, y, x]
 
 
+def test_checkpoint_arguments_are_checked(tiny):
+    """K outside 1..64, every outside 1..65536, a NULL or misaligned record
+    buffer: ART_EINVAL before any work, and the context renders afterwards."""
+    import ctypes
+    import torch
+    from paper_2202_05628_amd import _lib
+    s, rend, *_ = tiny
+    sig, f = flut(s)
+    F0, A0, T0 = rend.render(sig, f, 0.01)
+    F, A, T = torch.empty_like(F0), torch.empty_like(A0), torch.empty_like(T0)
+    cnt = torch.zeros_like(A0, dtype=torch.int32)
+    rec = torch.empty(A0.numel() * 6 * (s.C + 4) + 2, dtype=torch.float32, device="cuda")
+    ds, df = torch.zeros_like(sig), torch.zeros_like(f)
+    p = lambda t: ctypes.c_void_p(t.data_ptr())
+    bad = [(0, 3, p(rec)), (65, 3, p(rec)), (6, 0, p(rec)), (6, 65537, p(rec)), (6, 3, None),
+           (6, 3, ctypes.c_void_p(rec.data_ptr() + 4))]
+    for K, every, rp in bad:
+        rc = rend.lib.art_render_ckpt(rend._h, s.C, _lib.ART_F32, p(sig), p(f), 0.01, 0, p(F), p(A), p(T),
+                                      K, every, rp, p(cnt))
+        assert rc == _lib.ART_EINVAL, (K, every)
+        rc = rend.lib.art_backward_ckpt(rend._h, s.C, _lib.ART_F32, p(sig), p(f), 0.01, 0, p(F0), p(T0), p(F0),
+                                        None, p(ds), p(df), K, every, rp, p(cnt))
+        assert rc == _lib.ART_EINVAL, (K, every)
+    assert not ds.any() and not df.any()
+    F1, A1, T1 = rend.render(sig, f, 0.01)
+    assert torch.equal(F1, F0) and torch.equal(A1, A0) and torch.equal(T1, T0)
+
+
 def test_checkpoints_after_tile_list_overflow(tiny, monkeypatch):
     """With tile lists too small for the call (every item renders again after
     the lists grow), the records and counts equal those of a call without
