@@ -516,8 +516,9 @@ def shading_layer_bound(maps, H, W, C, peak_flops=2.5e15, peak_bytes=8e12):
     FP16 matrix-core time (2 x 9 x Cin x Cout per output pixel at 2.5 PFLOP/s)
     and its HBM time (each input read once - a decoder's deeper input at half
     resolution - and the output written once, FP16 NHWC, at 8 TB/s), plus the
-    input conversion (16 FP32 planes in, 32 FP16 channels out), the three 2x2
-    max pools and the head (32 FP16 in, 4 FP32 out), which are HBM-bound."""
+    input conversion (16 FP32 planes in, 32 FP16 channels out) and the three
+    2x2 max pools, which are HBM-bound.  The 1x1 head runs in the last
+    convolution, whose output is its 4 FP32 channels."""
     px = maps * H * W
     # (resolution divisor, C1 same-resolution inputs, C2 half-resolution inputs, Cout, real Cin for the flops)
     convs = [(1, 32, 0, 32, C), (1, 32, 0, 32, 32), (2, 32, 0, 64, 32), (2, 64, 0, 64, 64), (4, 64, 0, 128, 64),
@@ -525,14 +526,14 @@ def shading_layer_bound(maps, H, W, C, peak_flops=2.5e15, peak_bytes=8e12):
              (4, 128, 0, 128, 128), (2, 64, 128, 64, 192), (2, 64, 0, 64, 64), (1, 32, 64, 32, 96),
              (1, 32, 0, 32, 32)]
     t = 0.0
-    for div, c1, c2, co, cin in convs:
+    for i, (div, c1, c2, co, cin) in enumerate(convs):
         n = px // (div * div)
         flops = 2 * 9 * cin * co * n
-        bytes_ = 2 * n * (c1 + co) + 2 * (n // 4) * c2 + 2 * 9 * (c1 + c2) * co
+        out_bytes = 4 * 4 * n if i == len(convs) - 1 else 2 * n * co   # the last one writes the head's output
+        bytes_ = 2 * n * c1 + out_bytes + 2 * (n // 4) * c2 + 2 * 9 * (c1 + c2) * co
         t += max(flops / peak_flops, bytes_ / peak_bytes)
     t += px * (4 * C + 2 * 32) / peak_bytes                                          # conversion
     t += sum((px // (d * d)) * 2 * c * 5 / 4 for d, c in ((1, 32), (2, 64), (4, 128))) / peak_bytes  # pools
-    t += px * (2 * 32 + 4 * 4) / peak_bytes                                          # head
     return t
 
 

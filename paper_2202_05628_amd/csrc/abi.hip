@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "device_util.h"
+#include "shade.h"
 #include "internal.h"
 
 using namespace art;
@@ -202,6 +203,13 @@ int adj_merge_policy() {
     if (e && *e == '0') return 0;
     if (e && *e == '1') return 1;
     return 2;
+}
+
+// Whether the shading network's 1x1 head runs in its last convolution
+// (ARTEMIS_SHADE_HEAD=0: a kernel of its own after it).
+static bool fused_shading_head() {
+    const char* e = getenv("ARTEMIS_SHADE_HEAD");
+    return !(e && *e == '0');
 }
 
 // Whether the compositing kernel writes the forward maps' background pixels
@@ -1288,7 +1296,8 @@ art_status shade_run(art_ctx* ctx, int C, int N, int H, int W, const float* F, f
             bp += kShade[l].cout;
         }
     }
-    auto conv = [&](int l, const uint16_t* s1, int c1, const uint16_t* s2, int c2, uint16_t* o, int h, int w) {
+    auto conv = [&](int l, const uint16_t* s1, int c1, const uint16_t* s2, int c2, uint16_t* o, int h, int w,
+                    float* head_out = nullptr) {
         ConvLaunch a{};
         a.src1 = s1;
         a.C1 = c1;
@@ -1302,6 +1311,10 @@ art_status shade_run(art_ctx* ctx, int C, int N, int H, int W, const float* F, f
         a.W = w;
         a.Cout = kShade[l].cout;
         a.relu = 1;
+        if (head_out) {
+            const ConvHead hd{ctx->shade_head.as<float>(), ctx->shade_head.as<float>() + 128, head_out};
+            return launch_conv3x3_head(a, hd, st);
+        }
         return launch_conv3x3(a, st);
     };
     hipError_t e = launch_to_nhwc(F, N, C, H, W, 32, X, st);
@@ -1322,9 +1335,13 @@ art_status shade_run(art_ctx* ctx, int C, int N, int H, int W, const float* F, f
     if (e == hipSuccess) e = conv(10, E1, 64, E2, 128, T1, H1, W1);
     if (e == hipSuccess) e = conv(11, T1, 64, nullptr, 0, E1, H1, W1);
     if (e == hipSuccess) e = conv(12, E0, 32, E1, 64, T0, H, W);
-    if (e == hipSuccess) e = conv(13, T0, 32, nullptr, 0, X, H, W);
-    if (e == hipSuccess)
-        e = launch_head(X, N, H, W, ctx->shade_head.as<float>(), ctx->shade_head.as<float>() + 128, out, st);
+    if (fused_shading_head()) {   // the last convolution writes the head's sigmoid outputs
+        if (e == hipSuccess) e = conv(13, T0, 32, nullptr, 0, nullptr, H, W, out);
+    } else {
+        if (e == hipSuccess) e = conv(13, T0, 32, nullptr, 0, X, H, W);
+        if (e == hipSuccess)
+            e = launch_head(X, N, H, W, ctx->shade_head.as<float>(), ctx->shade_head.as<float>() + 128, out, st);
+    }
     if (e != hipSuccess) return hip_fail(ctx, e, "shading network");
     return ART_OK;
 }

@@ -23,6 +23,7 @@
 //   D[4 (l / 16) + e][l % 16] for e = 0..3.
 #include "device_util.h"
 #include "internal.h"
+#include "shade.h"
 
 namespace art {
 
@@ -61,9 +62,9 @@ struct ConvTile {
     static_assert(waves_per_simd >= 1, "convolution tile does not fit one CU");
 };
 
-template <int NCB, int PB, int WC>
+template <int NCB, int PB, int WC, bool HEAD>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ConvTile<NCB, PB, WC>::waves_per_simd)))
-void k_conv3x3(ConvLaunch a) {
+void k_conv3x3(ConvLaunch a, ConvHead hd) {
     using Tl = ConvTile<NCB, PB, WC>;
     constexpr int kConvPB = PB;
     constexpr int kConvTP = Tl::TP;
@@ -210,6 +211,51 @@ void k_conv3x3(ConvLaunch a) {
             __syncthreads();
         }
     }
+    if constexpr (HEAD) {
+        // The network's last convolution (32 output channels, one channel
+        // tile) with the 1x1 head fused: its outputs after bias and ReLU,
+        // rounded to FP16 as a stored activation is, enter
+        // out_k = sigmoid(b_k + sum_c w_kc x_c) in FP32 directly.  Lane group
+        // g = lane / 16 holds channels 16 c + 4 g + e of its pixel; the four
+        // groups' partial sums are added across lanes, and group g writes
+        // output k = g.
+        const int g = lane >> 4;
+        const size_t HW = (size_t)a.H * a.W;
+        // this lane's channels 16 c + 4 g + e: their biases and head weights,
+        // loaded once (the output stores could alias them)
+        fl4 bv[NCB], wv[NCB][4];
+#pragma unroll
+        for (int c = 0; c < NCB; ++c) {
+            bv[c] = *reinterpret_cast<const fl4*>(a.bias + c * 16 + 4 * g);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) wv[c][k] = *reinterpret_cast<const fl4*>(hd.w + k * 32 + c * 16 + 4 * g);
+        }
+        const float bg = hd.b[g];
+#pragma unroll
+        for (int p = 0; p < kConvPB; ++p) {
+            const int x = x0 + (wp * kConvPB + p) * 16 + (lane & 15);
+            float part[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int c = 0; c < NCB; ++c) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    float v = acc[p][c][e] + bv[c][e];
+                    if (a.relu) v = fmaxf(v, 0.0f);
+                    v = (float)(_Float16)v;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) part[k] = fmaf(wv[c][k][e], v, part[k]);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                part[k] += __shfl_xor(part[k], 16, kWave);
+                part[k] += __shfl_xor(part[k], 32, kWave);
+            }
+            const float z = bg + (g == 0 ? part[0] : g == 1 ? part[1] : g == 2 ? part[2] : part[3]);
+            if (x < a.W) hd.out[((size_t)n * 4 + g) * HW + (size_t)y * a.W + x] = 1.0f / (1.0f + expf(-z));
+        }
+        return;
+    }
     // epilogue: bias, ReLU, FP16 NHWC store (4 consecutive channels per lane)
 #pragma unroll
     for (int p = 0; p < kConvPB; ++p) {
@@ -231,11 +277,11 @@ void k_conv3x3(ConvLaunch a) {
     }
 }
 
-template <int NCB, int PB, int WC>
-static void conv_launch(const ConvLaunch& a, hipStream_t st) {
+template <int NCB, int PB, int WC, bool HEAD = false>
+static void conv_launch(const ConvLaunch& a, hipStream_t st, const ConvHead& hd = ConvHead{}) {
     using Tl = ConvTile<NCB, PB, WC>;
     const dim3 grid((unsigned)((a.W + Tl::TP - 1) / Tl::TP), (unsigned)a.H, (unsigned)(a.N * (a.Cout / Tl::TC)));
-    hipLaunchKernelGGL((k_conv3x3<NCB, PB, WC>), grid, dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_conv3x3<NCB, PB, WC, HEAD>), grid, dim3(256), 0, st, a, hd);
 }
 
 template <int NCB, int WC>
@@ -252,14 +298,26 @@ static void conv_launch_pb(const ConvLaunch& a, int pb, hipStream_t st) {
 // widest pixel tile (up to 4 blocks of 16 per wave) that the row fills.  (8
 // blocks per wave for the 32-channel layers ran 10-20 % longer: two waves per
 // SIMD.)
-hipError_t launch_conv3x3(const ConvLaunch& a, hipStream_t st) {
-    if ((a.C1 % 32) || (a.C2 % 32) || a.C1 <= 0 || (a.C2 > 0 && !a.src2)) return hipErrorInvalidValue;
+static bool conv_args_ok(const ConvLaunch& a) {
+    if ((a.C1 % 32) || (a.C2 % 32) || a.C1 <= 0 || (a.C2 > 0 && !a.src2)) return false;
     // buffer resources: one image of each input, and the weights, below 2^30 bytes
     const int64_t lim = (int64_t)1 << 30;
     if ((int64_t)a.H * a.W * a.C1 * 2 >= lim || (int64_t)(a.H / 2) * (a.W / 2) * a.C2 * 2 >= lim ||
         (int64_t)9 * a.Cout * (a.C1 + a.C2) * 2 >= lim)
-        return hipErrorInvalidValue;
-    if (a.Cout % 32) return hipErrorInvalidValue;
+        return false;
+    return a.Cout % 32 == 0;
+}
+
+hipError_t launch_conv3x3_head(const ConvLaunch& a, const ConvHead& h, hipStream_t st) {
+    if (!conv_args_ok(a) || a.Cout != 32 || !h.w || !h.b || !h.out) return hipErrorInvalidValue;
+    if (a.W >= 256) conv_launch<2, 4, 1, true>(a, st, h);
+    else if (a.W >= 128) conv_launch<2, 2, 1, true>(a, st, h);
+    else conv_launch<2, 1, 1, true>(a, st, h);
+    return hipGetLastError();
+}
+
+hipError_t launch_conv3x3(const ConvLaunch& a, hipStream_t st) {
+    if (!conv_args_ok(a)) return hipErrorInvalidValue;
     if (a.Cout % 64) {   // 32 output channels per workgroup, 4 waves over pixels
         if (a.W >= 256) conv_launch<2, 4, 1>(a, st);
         else if (a.W >= 128) conv_launch<2, 2, 1>(a, st);

@@ -54,3 +54,20 @@ def test_shading_argument_errors(rend):
         rend.shade(torch.zeros((1, 8, 16, 16), device="cuda"))       # weights are for C = 16
     with pytest.raises(art.ArtemisError):
         rend.set_shading_weights(16, np.zeros(10, dtype=np.float32))
+
+
+def test_fused_head_equals_separate_head(rend, monkeypatch):
+    """The head fused into the last convolution (default) against the separate
+    head kernel (ARTEMIS_SHADE_HEAD=0): the same FP16 activations enter both,
+    so the outputs differ only by the order of the 32-term FP32 sums."""
+    import torch
+    rng = np.random.default_rng(77)
+    F = torch.from_numpy(rng.normal(size=(2, 16, 40, 264)).astype(np.float32)).cuda()
+    rend.set_shading_weights(16, sg.make_shading_weights(16, seed=61))
+    fused = rend.shade(F)
+    monkeypatch.setenv("ARTEMIS_SHADE_HEAD", "0")
+    separate = rend.shade(F)
+    monkeypatch.delenv("ARTEMIS_SHADE_HEAD")
+    d = (fused - separate).abs().max().item()
+    log(f"fused head vs separate head kernel: max |diff| {d:.2e}")
+    assert d <= 1e-6
