@@ -6,7 +6,7 @@
 //
 // Radix pass (8-bit digit, blocks own contiguous key ranges of their pose):
 //   k_hist     per-block digit histogram           -> hist[pose][digit][block]
-//   k_hscan    one workgroup per (digit, pose) scans its row over the blocks
+//   k_hscan    one wave per (digit, pose) scans its row over the blocks
 //              and writes the digit total
 //   k_scatter  per block, tiles of 4096 keys staged in LDS in stable digit
 //              order (lanes with equal digits matched with 8 wave ballots and
@@ -50,20 +50,34 @@ __global__ __launch_bounds__(kSortThreads) void k_hist(const uint32_t* __restric
     hist[threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
 }
 
-// One workgroup per (digit, pose); nblk <= 1024 == blockDim.x.
-__global__ __launch_bounds__(1024) void k_hscan(uint32_t* __restrict__ hist, int nblk,
-                                                uint32_t* __restrict__ digit_tot) {
-    __shared__ uint32_t tmp[1024 / kWave + 1];
+// One wave per (digit, pose), nblk <= 512: each lane takes 8 consecutive
+// blocks of the digit's row (a serial prefix), the lanes' sums are scanned
+// across the wave.
+constexpr int kHscanPerLane = 8;
+static_assert(kSortBlocks <= kWave * kHscanPerLane, "one wave scans a digit's row");
+__global__ __launch_bounds__(kWave) void k_hscan(uint32_t* __restrict__ hist, int nblk,
+                                                 uint32_t* __restrict__ digit_tot) {
     const int d = blockIdx.x;
     const uint32_t p = blockIdx.y;
-    hist += (size_t)p * 256 * nblk;
-    digit_tot += (size_t)p * 256;
-    const int b = threadIdx.x;
-    uint32_t v = b < nblk ? hist[d * nblk + b] : 0u;
-    uint32_t total;
-    uint32_t ex = block_exclusive_scan<1024>(v, tmp, &total);
-    if (b < nblk) hist[d * nblk + b] = ex;
-    if (b == 0) digit_tot[d] = total;
+    uint32_t* row = hist + ((size_t)p * 256 + d) * nblk;
+    const int lane = threadIdx.x;
+    uint32_t v[kHscanPerLane];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int j = 0; j < kHscanPerLane; ++j) {
+        const int b = kHscanPerLane * lane + j;
+        v[j] = b < nblk ? row[b] : 0u;
+        sum += v[j];
+    }
+    const uint32_t incl = wave_inclusive_scan(sum);
+    uint32_t run = incl - sum;
+#pragma unroll
+    for (int j = 0; j < kHscanPerLane; ++j) {
+        const int b = kHscanPerLane * lane + j;
+        if (b < nblk) row[b] = run;
+        run += v[j];
+    }
+    if (lane == kWave - 1) digit_tot[(size_t)p * 256 + d] = incl;
 }
 
 // Keys per block iteration of the scatter: 16 sub-tiles of 256.
@@ -181,7 +195,7 @@ hipError_t launch_radix_sort(const SortBatch& b, int bits, hipStream_t st, bool*
         const int shift = 8 * p;
         hipLaunchKernelGGL(k_hist, dim3(nblk, b.batch), dim3(kSortThreads), 0, st, ki, b.kstride, b.d_n, b.nstride,
                            shift, b.hist);
-        hipLaunchKernelGGL(k_hscan, dim3(256, b.batch), dim3(1024), 0, st, b.hist, nblk, b.digit_tot);
+        hipLaunchKernelGGL(k_hscan, dim3(256, b.batch), dim3(kWave), 0, st, b.hist, nblk, b.digit_tot);
         hipLaunchKernelGGL(k_scatter, dim3(nblk, b.batch), dim3(kSortThreads), 0, st, ki, ko, b.kstride, vi, vo,
                            b.vstride, b.d_n, b.nstride, shift, b.hist, b.digit_tot);
         *launches += 3;
