@@ -2,9 +2,10 @@
 //
 //   k_tile_compact : one thread per tile slot (Morton order within each view);
 //                    tiles whose brick list is not empty are appended to the work
-//                    list with a wave ballot + popcount of the lanes below (one
-//                    atomic per wave), so the persistent compositing waves only
-//                    ever take tiles with work.
+//                    list in slot order within each workgroup's range of slots
+//                    (wave ballots, counts in LDS, one atomic per workgroup
+//                    range), so the persistent compositing waves only ever take
+//                    tiles with work.
 //   k_background   : one thread per pixel; the pixels of an empty tile get
 //                    F = 0, A = 0, T = 1 (no voxel on their ray), and the
 //                    empty interval label (1, 0) in a label pass.
@@ -37,25 +38,54 @@ __device__ inline bool tile_slot(const TileGeom& g, const uint32_t* ovf, uint64_
     return true;
 }
 
-__global__ __launch_bounds__(256) void k_tile_compact(TileGeom g, const uint32_t* __restrict__ ovf,
-                                                      const uint32_t* __restrict__ tstart,
-                                                      const uint32_t* __restrict__ tend,
-                                                      uint32_t* __restrict__ items,
-                                                      uint32_t* __restrict__ n_items) {
+// A workgroup compacts kCompactIters x 256 consecutive tile slots: the waves
+// count their slots with work (one ballot per iteration), the workgroup takes
+// its range of the work list with one atomic, and every item is written at
+// its slot-order position within the range.
+constexpr int kCompactThreads = 256;
+constexpr int kCompactWaves = kCompactThreads / kWave;
+constexpr int kCompactIters = 16;
+__global__ __launch_bounds__(kCompactThreads) void k_tile_compact(TileGeom g, const uint32_t* __restrict__ ovf,
+                                                                  const uint32_t* __restrict__ tstart,
+                                                                  const uint32_t* __restrict__ tend,
+                                                                  uint32_t* __restrict__ items,
+                                                                  uint32_t* __restrict__ n_items) {
+    __shared__ uint32_t s_cnt[kCompactIters][kCompactWaves];
+    __shared__ uint32_t s_base;
     const uint64_t total = (uint64_t)g.Pb * g.V * g.tiles_pow4;
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < total; base += stride) {
-        const uint64_t i = base + threadIdx.x;
-        uint32_t item = 0;
-        int tx, ty, pvi;
-        bool work = tile_slot(g, ovf, i, &item, &tx, &ty, &pvi);
-        work = work && tend[item] > tstart[item];
-        const uint64_t m = __ballot(work);
-        if (m == 0ull) continue;
-        uint32_t first = 0;
-        if (lane_id() == 0) first = atomicAdd(n_items, (uint32_t)__popcll(m));
-        first = (uint32_t)__shfl((int)first, 0, kWave);
-        if (work) items[first + (uint32_t)__popcll(m & lanemask_lt())] = item;
+    const uint64_t span = (uint64_t)kCompactIters * kCompactThreads;
+    const int w = (int)threadIdx.x / kWave;
+    const int lane = lane_id();
+    for (uint64_t b0 = (uint64_t)blockIdx.x * span; b0 < total; b0 += (uint64_t)gridDim.x * span) {
+        uint64_t mask[kCompactIters];
+        uint32_t item[kCompactIters];
+#pragma unroll
+        for (int k = 0; k < kCompactIters; ++k) {
+            const uint64_t i = b0 + (uint64_t)k * kCompactThreads + threadIdx.x;
+            int tx, ty, pvi;
+            item[k] = 0;
+            bool work = tile_slot(g, ovf, i, &item[k], &tx, &ty, &pvi);
+            work = work && tend[item[k]] > tstart[item[k]];
+            mask[k] = __ballot(work);
+            if (lane == 0) s_cnt[k][w] = (uint32_t)__popcll(mask[k]);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t tot = 0;
+            for (int k = 0; k < kCompactIters; ++k)
+                for (int q = 0; q < kCompactWaves; ++q) tot += s_cnt[k][q];
+            s_base = tot ? atomicAdd(n_items, tot) : 0u;
+        }
+        __syncthreads();
+        // slot order: iteration k, then wave q, then lane
+        uint32_t off = s_base;
+#pragma unroll
+        for (int k = 0; k < kCompactIters; ++k) {
+            for (int q = 0; q < w; ++q) off += s_cnt[k][q];
+            if ((mask[k] >> lane) & 1ull) items[off + (uint32_t)__popcll(mask[k] & lanemask_lt())] = item[k];
+            for (int q = w; q < kCompactWaves; ++q) off += s_cnt[k][q];
+        }
+        __syncthreads();   // s_cnt and s_base are rewritten by the next range
     }
 }
 
@@ -178,11 +208,12 @@ hipError_t launch_tiles(const TileLaunch& t, hipStream_t st) {
     const uint64_t total = (uint64_t)g.Pb * g.V * g.tiles_pow4;
     hipError_t e = launch_fill_u32(t.counters, 0u, 16, st);   // n_items, queue heads
     if (e != hipSuccess) return e;
-    uint64_t blocks = (total + 255) / 256;
+    const uint64_t span = (uint64_t)kCompactIters * kCompactThreads;
+    uint64_t blocks = (total + span - 1) / span;
     if (blocks > 65536) blocks = 65536;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_tile_compact, dim3((unsigned)blocks), dim3(256), 0, st, g, t.ovf, t.tile_start, t.tile_end,
-                       t.items, t.counters);
+    hipLaunchKernelGGL(k_tile_compact, dim3((unsigned)blocks), dim3(kCompactThreads), 0, st, g, t.ovf, t.tile_start,
+                       t.tile_end, t.items, t.counters);
     if (t.out_feat || t.hit_count || t.labels) {
         const uint64_t pixels = (uint64_t)g.Pb * g.V * g.H * g.W;
         uint64_t wblocks = (pixels + 255) / 256;
