@@ -114,28 +114,41 @@ __global__ __launch_bounds__(256) void k_dense_cells(const uint32_t* __restrict_
     tab.init();
     __syncthreads();
     const int lane = lane_id();
-    // a contiguous range of leaves per workgroup; active lanes are a prefix of the wave
+    // a contiguous range of leaves per workgroup, four rows of 256 leaves per
+    // step with their keys loaded together; lanes past the range hold no key
+    // (those with a key are a prefix of the wave)
     uint32_t lo, hi;
     block_range(n, blockIdx.x, gridDim.x, 256, &lo, &hi);
-    for (uint32_t base = lo; base < hi; base += blockDim.x) {
-        const uint32_t i = base + threadIdx.x;
-        if (i >= hi) break;
-        const uint32_t key = keys[i];
-        const bool ok = key != kInvalidKey;
-        // cells share a mask word iff their keys agree above the low 5 bits
-        const uint32_t wk = ok ? key >> 5 : kInvalidKey;
-        uint32_t bits = ok ? 1u << (key & 31u) : 0u;
-        // OR the bits of the following lanes with the same word into each lane;
-        // the first lane of every run then holds the run's bits
+    constexpr uint32_t kRows = 4;
+    for (uint32_t base0 = lo; base0 < hi; base0 += kRows * blockDim.x) {
+        uint32_t kk[kRows];
 #pragma unroll
-        for (int d = 1; d < kWave; d <<= 1) {
-            const uint32_t ob = __shfl_down(bits, d, kWave);
-            const uint32_t ow = __shfl_down(wk, d, kWave);
-            if (lane + d < kWave && i + (uint32_t)d < hi && ow == wk) bits |= ob;
+        for (uint32_t u = 0; u < kRows; ++u) {
+            const uint32_t i = base0 + u * blockDim.x + threadIdx.x;
+            kk[u] = i < hi ? keys[i] : kInvalidKey;
         }
-        const uint32_t prev = __shfl_up(wk, 1, kWave);
-        if (ok && (lane == 0 || prev != wk) && !tab.insert(wk, bits))
-            atomicOr(&mask[(size_t)brick_rank(bmap, wpref, wk >> 4) * 16 + (wk & 15u)], bits);
+#pragma unroll
+        for (uint32_t u = 0; u < kRows; ++u) {
+            const uint32_t base = base0 + u * blockDim.x;
+            if (base >= hi) break;   // uniform over the workgroup
+            const uint32_t i = base + threadIdx.x;
+            const uint32_t key = kk[u];
+            const bool ok = key != kInvalidKey;
+            // cells share a mask word iff their keys agree above the low 5 bits
+            const uint32_t wk = ok ? key >> 5 : kInvalidKey;
+            uint32_t bits = ok ? 1u << (key & 31u) : 0u;
+            // OR the bits of the following lanes with the same word into each
+            // lane; the first lane of every run then holds the run's bits
+#pragma unroll
+            for (int d = 1; d < kWave; d <<= 1) {
+                const uint32_t ob = __shfl_down(bits, d, kWave);
+                const uint32_t ow = __shfl_down(wk, d, kWave);
+                if (lane + d < kWave && i + (uint32_t)d < hi && ow == wk) bits |= ob;
+            }
+            const uint32_t prev = __shfl_up(wk, 1, kWave);
+            if (ok && (lane == 0 || prev != wk) && !tab.insert(wk, bits))
+                atomicOr(&mask[(size_t)brick_rank(bmap, wpref, wk >> 4) * 16 + (wk & 15u)], bits);
+        }
     }
     __syncthreads();
     for (int e = threadIdx.x; e < 1024; e += blockDim.x) {
@@ -177,7 +190,7 @@ __global__ __launch_bounds__(1024) void k_dense_rows(const uint32_t* __restrict_
 
 // The per-leaf passes below take 4 leaves per thread, 256 apart, so that each
 // thread has 4 independent chains of dependent loads in flight.
-constexpr uint32_t kLeafUnroll = 4;
+constexpr uint32_t kLeafUnroll = 4;   // 8 measured the same or slower
 
 __global__ __launch_bounds__(256) void k_dense_place(const uint32_t* __restrict__ keys, uint32_t n,
                                                      const uint32_t* __restrict__ bmap,
